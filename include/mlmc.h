@@ -1,0 +1,240 @@
+/*
+ * mlmc.h - C ABI of the MI355X (gfx950) library for the per-sample spectral
+ * hot path of multilevel Monte Carlo on honeycomb materials with random
+ * vacancies (Plechac & von Schwerin, "Multi-level Monte Carlo acceleration
+ * of computations on multi-layer materials with random defects").
+ *
+ * Per sample and per Brillouin-zone point the library assembles the complex
+ * Hermitian Bloch Hamiltonian H(k) of an N x N supercell with vacancies,
+ * computes all its eigenvalues and accumulates the smoothed integrated
+ * density of states (IDoS) per unit area; on top of that it accumulates the
+ * per-level sums of the MC / MLMC estimators.
+ *
+ * Conventions shared by every entry point
+ *   - Every call returns an mlmc_status (0 = success, negative = error).  No
+ *     call throws, aborts or prints.  mlmc_status_string() names a status and
+ *     mlmc_last_error() gives a detail message for the calling thread.
+ *   - Arguments named d_* are device pointers owned by the caller; h_* and
+ *     plain pointers to structs are host pointers.  Arguments are validated
+ *     before anything is launched; a failed validation launches nothing.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL is the default
+ *     stream) and is asynchronous: outputs are valid once the stream has
+ *     synchronised.  The only calls that may block are mlmc_lattice_create
+ *     and mlmc_lattice_destroy.
+ *   - Hot-path calls allocate no device memory.  Scratch memory is a caller
+ *     workspace whose size the matching *_workspace call reports.
+ *   - Results are deterministic: fixed reduction orders and no floating-point
+ *     atomics.  Per-outcome results (masks, H(k), eigenvalues, IDoS) do not
+ *     depend on which other outcomes share a call; level sums are
+ *     bitwise reproducible for equal inputs and equal workspace size.
+ *   - Orbital numbering: orbital m of cell (i, j) (position i*a1 + j*a2 of the
+ *     N x N supercell) has index (i*N + j)*n_orb + m.  Present orbitals keep
+ *     this order and are renumbered 0..n-1.
+ */
+#ifndef MLMC_H
+#define MLMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void *mlmc_stream; /* a hipStream_t */
+
+typedef enum {
+    MLMC_OK = 0,
+    MLMC_ERR_INVALID_ARG = -1, /* an argument is out of range or inconsistent       */
+    MLMC_ERR_UNSUPPORTED = -2, /* valid request this build does not implement       */
+    MLMC_ERR_WORKSPACE = -3,   /* workspace pointer NULL or smaller than required    */
+    MLMC_ERR_HIP = -4          /* the HIP runtime reported an error (detail string)  */
+} mlmc_status;
+
+typedef enum {
+    MLMC_C128 = 0, /* complex double, interleaved (re, im) */
+    MLMC_C64 = 1   /* complex float, interleaved (re, im)  */
+} mlmc_dtype;
+
+typedef enum {
+    MLMC_PREC_FP64 = 0, /* every step in double precision                              */
+    MLMC_PREC_MIXED = 1 /* tridiagonal reduction in single precision; Sturm bisection,
+                           IDoS and level sums in double precision                     */
+} mlmc_precision;
+
+typedef enum {
+    MLMC_KGRID_MP = 0,   /* K x K Monkhorst-Pack: kappa = (2r - K + 1) / (2K)  */
+    MLMC_KGRID_GAMMA = 1 /* K x K Gamma-centred:  kappa = r / K                */
+} mlmc_kgrid_kind;
+
+typedef enum {
+    MLMC_SMOOTH_GAUSS = 0, /* g(x) = erfc(x / sqrt 2) / 2                               */
+    MLMC_SMOOTH_CUBIC = 1  /* g(x) = 1/2 - 9x/8 + 5x^3/8 on [-1, 1], 1 below, 0 above     */
+} mlmc_smoother;
+
+/* One row of a tight-binding hopping table (Section 3.1, eq. (tightbinding)).
+ * It adds h * exp(i k.(R + r_to - r_from)) to H[from, to] and the complex
+ * conjugate to H[to, from] for every cell; R = (R[0], R[1]) is the cell
+ * offset of the target orbital in units of a1, a2.  A row with R = 0 and
+ * from_orb == to_orb is an on-site energy and is added once (its imaginary
+ * part must be 0). */
+typedef struct {
+    int32_t R[2];
+    int32_t from_orb;
+    int32_t to_orb;
+    double re;
+    double im;
+} mlmc_hop;
+
+/* Host description of a honeycomb lattice model (Sections 3.1-3.2). */
+typedef struct {
+    uint32_t lattice_id;            /* selects the vacancy random stream (tag)          */
+    int32_t n_orb;                  /* orbitals per primitive cell (1..64)              */
+    int32_t n_groups;               /* vacancy groups per cell (1..16)                  */
+    int32_t n_hops;                 /* rows of `hops` (1..65536)                        */
+    double cell_area;               /* |F| of the primitive cell, Angstrom^2 (> 0)      */
+    const double *orb_frac;         /* [n_orb][2] positions in fractions of a1, a2      */
+    const int32_t *orb_group;       /* [n_orb] group of each orbital, 0..n_groups-1     */
+    const uint8_t *group_removable; /* [n_groups] 1: the group may be vacant            */
+    const mlmc_hop *hops;           /* [n_hops]                                         */
+} mlmc_lattice_desc;
+
+typedef struct mlmc_lattice_s *mlmc_lattice; /* opaque device-resident lattice */
+
+const char *mlmc_status_string(int status);
+const char *mlmc_last_error(void);
+
+/* Copy a lattice description to the current HIP device (setup, blocking,
+ * allocates device memory).  The handle is bound to that device; the host
+ * arrays of `desc` may be freed afterwards.  Validates ranges and that the
+ * on-site rows are real. */
+mlmc_status mlmc_lattice_create(const mlmc_lattice_desc *desc, mlmc_lattice *out);
+/* Release a handle (blocking; waits for the device).  NULL is accepted. */
+mlmc_status mlmc_lattice_destroy(mlmc_lattice lat);
+/* Orbitals of the pristine N x N supercell (= n_orb * N * N); the matrix
+ * side bound `ld` of every per-outcome array. */
+mlmc_status mlmc_lattice_max_orbitals(mlmc_lattice lat, int32_t N, int64_t *n_max);
+
+/* Vacancy outcomes (Section 3.2: every removable group of every cell is
+ * vacant independently with probability p).
+ * Philox4x64-10 (Salmon et al., SC'11) with key (seed, tag) and counter
+ * (first_sample + s, floor(g/4), 0, 0); group g = (i*N + j)*n_groups + local
+ * of sample s takes word g mod 4 and is vacant iff it is removable and
+ * (word >> 11) < floor(p * 2^53).  The MLMC level call uses
+ * tag = (lattice_id << 32) | N.
+ * d_mask: [n_samples][N][N][n_groups] uint8, 1 = vacant (written).
+ * Errors: N < 1, p outside [0, 1], n_samples < 0. */
+mlmc_status mlmc_sample_vacancies(mlmc_lattice lat, int32_t N, double p, uint64_t seed, uint64_t tag,
+                                  int64_t first_sample, int64_t n_samples, uint8_t *d_mask, mlmc_stream stream);
+
+/* Control-variate partition (Section 3.3, Figure "CV"): each outcome of an N
+ * x N supercell (N even) is cut into four quarters that keep their vacancies;
+ * quarter q = 2*qi + qj holds cells i in [qi*N/2, (qi+1)*N/2), j in
+ * [qj*N/2, (qj+1)*N/2), renumbered as an N/2 supercell that is then
+ * re-periodised.
+ * d_mask: [n_samples][N][N][G]; d_quarters: [n_samples][4][N/2][N/2][G]. */
+mlmc_status mlmc_partition_masks(mlmc_lattice lat, int32_t N, const uint8_t *d_mask, int64_t n_samples,
+                                 uint8_t *d_quarters, mlmc_stream stream);
+
+/* Brillouin-zone grid (Section 4.2; reading: a uniform K x K grid of the
+ * supercell zone with equal weights, the nearest-point rule of Section 4.3).
+ * d_kred: [K*K][2] reduced coordinates of point r1*K + r2 with respect to the
+ * supercell reciprocal vectors; d_kweight: [K*K], each 1/K^2. */
+mlmc_status mlmc_kgrid(mlmc_kgrid_kind kind, int32_t K, double *d_kred, double *d_kweight, mlmc_stream stream);
+
+/* Bloch Hamiltonians H(k) (Section 3.1, eq. (tightbinding), orthogonal form;
+ * vacant sites' rows and columns removed, Section 3.2).  For outcome s and
+ * k-point k, unit u = s*n_k + k receives the n_u x n_u Hermitian matrix in the
+ * leading block of d_H + u*ld*ld (column-major, leading dimension ld), with
+ * H[a, b] += h * exp(2 pi i (kappa1 d1 + kappa2 d2) / N), d = R + frac(to) -
+ * frac(from) the unwrapped atom-to-atom displacement (atom gauge).
+ * d_mask: [n_samples][N][N][G]; d_kred: [n_k][2]; d_n: [n_samples*n_k] out.
+ * dtype selects complex128 or complex64 storage.  Entries outside the n_u x
+ * n_u block are not written.  Errors: ld < n_orb*N*N, n_k < 1. */
+mlmc_status mlmc_build_hamiltonians(mlmc_lattice lat, int32_t N, const uint8_t *d_mask, int64_t n_samples,
+                                    const double *d_kred, int32_t n_k, mlmc_dtype dtype, void *d_H, int64_t ld,
+                                    int32_t *d_n, mlmc_stream stream);
+
+/* Workspace bytes of mlmc_batched_eigvalsh for `batch` matrices of bound ld. */
+mlmc_status mlmc_eigvalsh_workspace(mlmc_dtype dtype, mlmc_precision prec, int64_t ld, int64_t batch,
+                                    size_t *bytes);
+
+/* All eigenvalues of a batch of Hermitian matrices (the dense full
+ * eigensolve of each H(k), Section 4.2; E_n(k) is the n-th smallest
+ * eigenvalue, Section 4.3).  Householder reduction to real tridiagonal form
+ * (LDS-resident for ld <= 128 complex128 / 180 complex64, else in device
+ * memory), then Sturm-count bisection in double precision.
+ * d_H: [batch][ld][ld] column-major, only the lower triangle of the leading
+ * n_b x n_b block is read; it is overwritten.  d_n: [batch] sides, each in
+ * [0, ld] (a matrix with n_b outside that range gets NaN eigenvalues).
+ * d_w: [batch][ldw], ascending, entries >= n_b untouched.
+ * dtype/prec: (C128, FP64) or (C64, MIXED). */
+mlmc_status mlmc_batched_eigvalsh(mlmc_dtype dtype, mlmc_precision prec, void *d_H, int64_t ld,
+                                  const int32_t *d_n, int64_t batch, double *d_w, int64_t ldw, void *d_work,
+                                  size_t work_bytes, mlmc_stream stream);
+
+/* Smoothed IDoS per unit area of each outcome (eq. (IDoS) with the
+ * nearest-point band approximation and the smoothing of eq.
+ * (MLMC_smoothing), Section 4.3):
+ *   I_s(eps_j) = 1/area * sum_k w_k sum_{i < n_{s,k}} g((E_{s,k,i} - eps_j)/delta)
+ * d_w: [n_samples*n_k][ldw] ascending eigenvalues; d_n: [n_samples*n_k];
+ * d_kweight: [n_k]; area = N*N*|F|; d_eps: [n_eps]; d_idos: [n_samples][n_eps].
+ * The Gaussian is evaluated for |x| < 10 and taken as exactly 1 / 0 beyond
+ * (|error| < 1e-23 per state); the cubic has compact support [-1, 1]. */
+mlmc_status mlmc_idos(const double *d_w, int64_t ldw, const int32_t *d_n, int64_t n_samples, int32_t n_k,
+                      const double *d_kweight, double area, const double *d_eps, int32_t n_eps, double delta,
+                      mlmc_smoother smoother, double *d_idos, mlmc_stream stream);
+
+/* Per-level sums of eq. (MLMC) and of its variance (Section 2.2):
+ *   Y_s = Q_s (d_idos_quarters == NULL) or Q_s - (1/4) sum_q Q_{s,q};
+ *   d_stats[0][j] += sum_s Y_s(j), [1] += sum Y^2, [2] += sum Q_s(j),
+ *   [3] += sum Q_s^2, accumulated in sample order in double precision.
+ * d_idos_fine: [n_samples][n_eps]; d_idos_quarters: [n_samples][4][n_eps];
+ * d_stats: [4][n_eps] (caller initialises). */
+mlmc_status mlmc_level_stats(const double *d_idos_fine, const double *d_idos_quarters, int64_t n_samples,
+                             int32_t n_eps, double *d_stats, mlmc_stream stream);
+
+/* Workspace bytes for mlmc_level_estimate when it processes `chunk_samples`
+ * samples per pass (the call uses the largest chunk that fits the workspace
+ * it is given; chunk_samples >= 1). */
+mlmc_status mlmc_level_workspace(mlmc_lattice lat, int32_t N_fine, int32_t coupled, int32_t K_fine,
+                                 int32_t K_coarse, int64_t chunk_samples, mlmc_precision prec, int32_t n_eps,
+                                 size_t *bytes);
+
+/* One MLMC level over samples first_sample .. first_sample+M-1 (Sections 2.2
+ * and 3.3): sample outcomes on the N_fine supercell (tag (lattice_id << 32) |
+ * N_fine), compute Q_f = IDoS on the K_fine grid and, when coupled, the four
+ * quarter IDoS Q_q on the K_coarse grid of the N_fine/2 supercell, and add
+ * the sums of Y = Q_f [- (1/4) sum_q Q_q], Y^2, Q_f, Q_f^2 into d_stats
+ * ([4][n_eps], accumulated; the caller initialises it).
+ * Errors: N_fine < 1, coupled with odd N_fine, K < 1, p outside [0, 1],
+ * delta <= 0, workspace too small for one sample. */
+mlmc_status mlmc_level_estimate(mlmc_lattice lat, int32_t N_fine, int32_t coupled, double p, int32_t K_fine,
+                                int32_t K_coarse, mlmc_kgrid_kind kind, uint64_t seed, int64_t first_sample,
+                                int64_t M, const double *d_eps, int32_t n_eps, double delta, mlmc_smoother smoother,
+                                mlmc_precision prec, double *d_stats, void *d_work, size_t work_bytes,
+                                mlmc_stream stream);
+
+/* Sample allocation of eq. (opt_samples) (host, no device work):
+ *   M_l = (C_alpha / (theta tol))^2 sqrt(V_l / W_l) sum_k sqrt(W_k V_k)
+ * V, W, M_out: host arrays [L] (real-valued; the caller rounds up).
+ * Errors: L < 1, any V < 0 or W <= 0, theta or tol <= 0. */
+mlmc_status mlmc_optimal_samples(int32_t L, const double *V, const double *W, double C_alpha, double theta,
+                                 double tol, double *M_out);
+
+/* Diagnostics (off by default): per-kernel launch timing with HIP events.
+ * While enabled, each kernel launch of this library records a start/stop
+ * event pair on the stream it is launched on (creating two events per
+ * launch).  mlmc_timer_enable(1) discards earlier records; 0 stops recording. */
+mlmc_status mlmc_timer_enable(int32_t enable);
+/* Total event-measured duration (ms) and count of the recorded launches of
+ * kernel `name`: "sample_vacancies", "partition", "kgrid", "assemble",
+ * "small_fused", "tridiag_global", "bisect", "idos" or "level_stats".
+ * Blocks until those launches have completed. */
+mlmc_status mlmc_timer_read(const char *name, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MLMC_H */

@@ -1,0 +1,350 @@
+"""ctypes binding of ``include/mlmc.h`` (argument marshalling only).
+
+Every computation happens in ``libmlmc.so`` (HIP kernels for gfx950).  This
+module converts torch tensors to device pointers, picks the current HIP
+stream, checks status codes and allocates output tensors with torch.  It
+never computes any step of the method itself, and it raises if the library
+has not been built: there is no CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmlmc.so")
+
+MLMC_OK = 0
+MLMC_ERR_INVALID_ARG = -1
+MLMC_ERR_UNSUPPORTED = -2
+MLMC_ERR_WORKSPACE = -3
+MLMC_ERR_HIP = -4
+
+MLMC_C128 = 0
+MLMC_C64 = 1
+MLMC_PREC_FP64 = 0
+MLMC_PREC_MIXED = 1
+MLMC_KGRID_MP = 0
+MLMC_KGRID_GAMMA = 1
+MLMC_SMOOTH_GAUSS = 0
+MLMC_SMOOTH_CUBIC = 1
+
+# Largest matrix side of the LDS-resident fused path / of the device-memory path.
+SMALL_MAX = {MLMC_PREC_FP64: 128, MLMC_PREC_MIXED: 180}
+LARGE_MAX = {MLMC_PREC_FP64: 2048, MLMC_PREC_MIXED: 4096}
+
+
+class MLMCError(RuntimeError):
+    def __init__(self, status, where, detail):
+        super().__init__(f"{where}: {status_string(status)} ({status}): {detail}")
+        self.status = status
+
+
+class _Hop(C.Structure):
+    _fields_ = [("R", C.c_int32 * 2), ("from_orb", C.c_int32), ("to_orb", C.c_int32),
+                ("re", C.c_double), ("im", C.c_double)]
+
+
+class _LatticeDesc(C.Structure):
+    _fields_ = [("lattice_id", C.c_uint32), ("n_orb", C.c_int32), ("n_groups", C.c_int32), ("n_hops", C.c_int32),
+                ("cell_area", C.c_double), ("orb_frac", C.c_void_p), ("orb_group", C.c_void_p),
+                ("group_removable", C.c_void_p), ("hops", C.c_void_p)]
+
+
+_LIB = None
+P = C.c_void_p
+I32, I64, U64, DBL, SZ = C.c_int32, C.c_int64, C.c_uint64, C.c_double, C.c_size_t
+
+# name -> (restype, argtypes); mirrors include/mlmc.h
+SIGNATURES = {
+    "mlmc_status_string": (C.c_char_p, [C.c_int]),
+    "mlmc_last_error": (C.c_char_p, []),
+    "mlmc_lattice_create": (C.c_int, [P, P]),
+    "mlmc_lattice_destroy": (C.c_int, [P]),
+    "mlmc_lattice_max_orbitals": (C.c_int, [P, I32, P]),
+    "mlmc_sample_vacancies": (C.c_int, [P, I32, DBL, U64, U64, I64, I64, P, P]),
+    "mlmc_partition_masks": (C.c_int, [P, I32, P, I64, P, P]),
+    "mlmc_kgrid": (C.c_int, [C.c_int, I32, P, P, P]),
+    "mlmc_build_hamiltonians": (C.c_int, [P, I32, P, I64, P, I32, C.c_int, P, I64, P, P]),
+    "mlmc_eigvalsh_workspace": (C.c_int, [C.c_int, C.c_int, I64, I64, P]),
+    "mlmc_batched_eigvalsh": (C.c_int, [C.c_int, C.c_int, P, I64, P, I64, P, I64, P, SZ, P]),
+    "mlmc_idos": (C.c_int, [P, I64, P, I64, I32, P, DBL, P, I32, DBL, C.c_int, P, P]),
+    "mlmc_level_stats": (C.c_int, [P, P, I64, I32, P, P]),
+    "mlmc_level_workspace": (C.c_int, [P, I32, I32, I32, I32, I64, C.c_int, I32, P]),
+    "mlmc_level_estimate": (C.c_int, [P, I32, I32, DBL, I32, I32, C.c_int, U64, I64, I64, P, I32, DBL, C.c_int,
+                                      C.c_int, P, P, SZ, P]),
+    "mlmc_optimal_samples": (C.c_int, [I32, P, P, DBL, DBL, DBL, P]),
+    "mlmc_timer_enable": (C.c_int, [I32]),
+    "mlmc_timer_read": (C.c_int, [C.c_char_p, P, P]),
+}
+
+
+def lib() -> C.CDLL:
+    """Load libmlmc.so; raises if it has not been built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; "
+                               f"g.build()'` (there is no CPU fallback)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def status_string(st: int) -> str:
+    try:
+        return lib().mlmc_status_string(st).decode()
+    except Exception:  # pragma: no cover - only when the library itself is missing
+        return str(st)
+
+
+def _check(st: int, where: str):
+    if st != MLMC_OK:
+        raise MLMCError(st, where, lib().mlmc_last_error().decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, torch.Tensor):
+        if t.numel() == 0:
+            return None
+        if not t.is_contiguous():
+            raise ValueError("tensor arguments must be contiguous")
+        return C.c_void_p(t.data_ptr())
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data_as(C.c_void_p)
+    raise TypeError(type(t))
+
+
+def _dev(t: torch.Tensor, dtype, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def stream_tag(lattice_id: int, N: int) -> int:
+    """Vacancy-stream tag used by mlmc_level_estimate: (lattice_id << 32) | N."""
+    return (int(lattice_id) << 32) | int(N)
+
+
+class DeviceLattice:
+    """Device-resident lattice handle (mlmc_lattice_create / _destroy)."""
+
+    def __init__(self, lat, device=None):
+        self.lat = lat
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        hops = np.zeros(lat.n_hops, dtype=np.dtype([("R", np.int32, 2), ("from_orb", np.int32),
+                                                     ("to_orb", np.int32), ("re", np.float64), ("im", np.float64)]))
+        hops["R"][:, 0] = lat.hops["R1"]
+        hops["R"][:, 1] = lat.hops["R2"]
+        hops["from_orb"] = lat.hops["frm"]
+        hops["to_orb"] = lat.hops["to"]
+        hops["re"] = lat.hops["re"]
+        hops["im"] = lat.hops["im"]
+        frac = np.ascontiguousarray(lat.orb_frac, dtype=np.float64)
+        group = np.ascontiguousarray(lat.orb_group, dtype=np.int32)
+        rem = np.ascontiguousarray(lat.group_removable, dtype=np.uint8)
+        desc = _LatticeDesc(lat.lattice_id, lat.n_orb, lat.n_groups, lat.n_hops, lat.cell_area,
+                            _ptr(frac), _ptr(group), _ptr(rem), _ptr(hops))
+        handle = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().mlmc_lattice_create(C.byref(desc), C.byref(handle)), "mlmc_lattice_create")
+        self._h = handle
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("lattice handle already closed")
+        return self._h
+
+    def max_orbitals(self, N: int) -> int:
+        out = C.c_int64()
+        _check(lib().mlmc_lattice_max_orbitals(self.handle, N, C.byref(out)), "mlmc_lattice_max_orbitals")
+        return out.value
+
+    def tag(self, N: int) -> int:
+        return stream_tag(self.lat.lattice_id, N)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().mlmc_lattice_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# One wrapper per C entry point (same names).
+# ---------------------------------------------------------------------------
+
+def mlmc_sample_vacancies(dlat, N, p, seed, tag, first_sample, n_samples, out=None, stream=None):
+    if out is None:
+        out = torch.empty((n_samples, N, N, dlat.lat.n_groups), dtype=torch.uint8, device=dlat.device)
+    _dev(out, torch.uint8, "mask")
+    _check(lib().mlmc_sample_vacancies(dlat.handle, N, float(p), int(seed) & (2**64 - 1), int(tag) & (2**64 - 1),
+                                       first_sample, n_samples, _ptr(out), _stream(stream)), "mlmc_sample_vacancies")
+    return out
+
+
+def mlmc_partition_masks(dlat, N, mask, out=None, stream=None):
+    _dev(mask, torch.uint8, "mask")
+    ns = mask.shape[0]
+    h = N // 2
+    if out is None:
+        out = torch.empty((ns, 4, h, h, dlat.lat.n_groups), dtype=torch.uint8, device=mask.device)
+    _check(lib().mlmc_partition_masks(dlat.handle, N, _ptr(mask), ns, _ptr(out), _stream(stream)),
+           "mlmc_partition_masks")
+    return out
+
+
+def mlmc_kgrid(kind, K, device=None, stream=None):
+    dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+    kred = torch.empty((K * K, 2), dtype=torch.float64, device=dev)
+    kw = torch.empty((K * K,), dtype=torch.float64, device=dev)
+    _check(lib().mlmc_kgrid(kind, K, _ptr(kred), _ptr(kw), _stream(stream)), "mlmc_kgrid")
+    return kred, kw
+
+
+def mlmc_build_hamiltonians(dlat, N, mask, kred, dtype=MLMC_C128, ld=None, H=None, n_out=None, stream=None):
+    _dev(mask, torch.uint8, "mask")
+    _dev(kred, torch.float64, "kred")
+    ns = mask.shape[0]
+    nk = kred.shape[0]
+    ld = dlat.max_orbitals(N) if ld is None else ld
+    tdt = torch.complex128 if dtype == MLMC_C128 else torch.complex64
+    if H is None:
+        H = torch.empty((ns * nk, ld, ld), dtype=tdt, device=mask.device)
+    if n_out is None:
+        n_out = torch.empty((ns * nk,), dtype=torch.int32, device=mask.device)
+    _dev(H, tdt, "H")
+    _dev(n_out, torch.int32, "n")
+    _check(lib().mlmc_build_hamiltonians(dlat.handle, N, _ptr(mask), ns, _ptr(kred), nk, dtype, _ptr(H), ld,
+                                         _ptr(n_out), _stream(stream)), "mlmc_build_hamiltonians")
+    return H, n_out
+
+
+def mlmc_eigvalsh_workspace(dtype, prec, ld, batch) -> int:
+    out = C.c_size_t()
+    _check(lib().mlmc_eigvalsh_workspace(dtype, prec, ld, batch, C.byref(out)), "mlmc_eigvalsh_workspace")
+    return out.value
+
+
+def mlmc_batched_eigvalsh(H, n, prec=None, w=None, ldw=None, work=None, stream=None):
+    """H: [batch][ld][ld] column-major (torch stores [u][c][r]); overwritten."""
+    if H.dtype == torch.complex128:
+        dtype = MLMC_C128
+    elif H.dtype == torch.complex64:
+        dtype = MLMC_C64
+    else:
+        raise ValueError("H must be complex64 or complex128")
+    if prec is None:
+        prec = MLMC_PREC_FP64 if dtype == MLMC_C128 else MLMC_PREC_MIXED
+    _dev(H, None, "H")
+    _dev(n, torch.int32, "n")
+    batch, ld = H.shape[0], H.shape[1]
+    ldw = ld if ldw is None else ldw
+    if w is None:
+        w = torch.zeros((batch, ldw), dtype=torch.float64, device=H.device)
+    _dev(w, torch.float64, "w")
+    need = mlmc_eigvalsh_workspace(dtype, prec, ld, batch)
+    if work is None and need > 0:
+        work = torch.empty((need,), dtype=torch.uint8, device=H.device)
+    wb = 0 if work is None else work.numel() * work.element_size()
+    _check(lib().mlmc_batched_eigvalsh(dtype, prec, _ptr(H), ld, _ptr(n), batch, _ptr(w), ldw, _ptr(work), wb,
+                                       _stream(stream)), "mlmc_batched_eigvalsh")
+    return w
+
+
+def mlmc_idos(w, n, n_k, kweight, area, eps, delta, smoother=MLMC_SMOOTH_GAUSS, out=None, stream=None):
+    _dev(w, torch.float64, "w")
+    _dev(n, torch.int32, "n")
+    _dev(kweight, torch.float64, "kweight")
+    _dev(eps, torch.float64, "eps")
+    ns = w.shape[0] // n_k
+    if out is None:
+        out = torch.empty((ns, eps.shape[0]), dtype=torch.float64, device=w.device)
+    _check(lib().mlmc_idos(_ptr(w), w.shape[1], _ptr(n), ns, n_k, _ptr(kweight), float(area), _ptr(eps),
+                           eps.shape[0], float(delta), smoother, _ptr(out), _stream(stream)), "mlmc_idos")
+    return out
+
+
+def mlmc_level_stats(idos_fine, idos_quarters=None, stats=None, stream=None):
+    _dev(idos_fine, torch.float64, "idos_fine")
+    ns, ne = idos_fine.shape
+    if idos_quarters is not None:
+        _dev(idos_quarters, torch.float64, "idos_quarters")
+    if stats is None:
+        stats = torch.zeros((4, ne), dtype=torch.float64, device=idos_fine.device)
+    _check(lib().mlmc_level_stats(_ptr(idos_fine), _ptr(idos_quarters), ns, ne, _ptr(stats), _stream(stream)),
+           "mlmc_level_stats")
+    return stats
+
+
+def mlmc_level_workspace(dlat, N, coupled, K_fine, K_coarse, chunk_samples, prec, n_eps) -> int:
+    out = C.c_size_t()
+    _check(lib().mlmc_level_workspace(dlat.handle, N, int(coupled), K_fine, K_coarse, chunk_samples, prec, n_eps,
+                                      C.byref(out)), "mlmc_level_workspace")
+    return out.value
+
+
+def mlmc_level_estimate(dlat, N, coupled, p, K_fine, K_coarse, kind, seed, first_sample, M, eps, delta,
+                        smoother=MLMC_SMOOTH_GAUSS, prec=MLMC_PREC_FP64, stats=None, work=None, chunk_samples=None,
+                        stream=None):
+    _dev(eps, torch.float64, "eps")
+    ne = eps.shape[0]
+    if stats is None:
+        stats = torch.zeros((4, ne), dtype=torch.float64, device=eps.device)
+    _dev(stats, torch.float64, "stats")
+    if work is None:
+        chunk = max(1, min(M, 64) if chunk_samples is None else chunk_samples)
+        need = mlmc_level_workspace(dlat, N, coupled, K_fine, K_coarse, chunk, prec, ne)
+        work = torch.empty((need,), dtype=torch.uint8, device=eps.device)
+    _check(lib().mlmc_level_estimate(dlat.handle, N, int(coupled), float(p), K_fine, K_coarse, kind,
+                                     int(seed) & (2**64 - 1), first_sample, M, _ptr(eps), ne, float(delta), smoother,
+                                     prec, _ptr(stats), _ptr(work), work.numel(), _stream(stream)),
+           "mlmc_level_estimate")
+    return stats
+
+
+def mlmc_optimal_samples(V, W, C_alpha, theta, tol) -> np.ndarray:
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    out = np.zeros_like(V)
+    _check(lib().mlmc_optimal_samples(V.shape[0], _ptr(V), _ptr(W), float(C_alpha), float(theta), float(tol),
+                                      _ptr(out)), "mlmc_optimal_samples")
+    return out
+
+
+def mlmc_timer_enable(enable: bool = True):
+    _check(lib().mlmc_timer_enable(1 if enable else 0), "mlmc_timer_enable")
+
+
+def mlmc_timer_read(name: str):
+    """(total milliseconds, launches) recorded for kernel `name` since the last enable."""
+    ms = C.c_double()
+    count = C.c_int64()
+    _check(lib().mlmc_timer_read(name.encode(), C.byref(ms), C.byref(count)), "mlmc_timer_read")
+    return ms.value, count.value

@@ -1,0 +1,539 @@
+// extern "C" entry points of include/mlmc.h: argument validation, workspace
+// layout and dispatch to the gfx950 kernels.
+#include <atomic>
+#include <cmath>
+#include <mutex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+using namespace mlmc;
+
+struct mlmc_lattice_s {
+    int device = -1;
+    DevLattice dev{};
+    void *d_buf = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+mlmc_status fail(mlmc_status st, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+mlmc_status fail(mlmc_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+mlmc_status hip_fail(hipError_t err, const char *where) {
+    return fail(MLMC_ERR_HIP, "%s: %s (%s)", where, hipGetErrorName(err), hipGetErrorString(err));
+}
+
+#define HIP_TRY(expr, where)                          \
+    do {                                              \
+        hipError_t e_ = (expr);                       \
+        if (e_ != hipSuccess) return hip_fail(e_, where); \
+    } while (0)
+
+// Opt-in launch timing (mlmc_timer_enable / mlmc_timer_read): a start/stop
+// event pair recorded on the launch stream around each kernel launch.
+struct TimerRec {
+    const char *name;
+    hipEvent_t start, stop;
+};
+std::mutex g_timer_mu;
+std::atomic<bool> g_timing{false};
+std::vector<TimerRec> g_timer_recs;
+
+void timer_clear_locked() {
+    for (auto &r : g_timer_recs) {
+        (void)hipEventDestroy(r.start);
+        (void)hipEventDestroy(r.stop);
+    }
+    g_timer_recs.clear();
+}
+
+template <typename F>
+hipError_t timed(const char *name, hipStream_t s, F &&launch) {
+    if (!g_timing.load(std::memory_order_relaxed)) return launch();
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t err = hipEventCreate(&a);
+    if (err == hipSuccess) err = hipEventCreate(&b);
+    if (err == hipSuccess) err = hipEventRecord(a, s);
+    if (err != hipSuccess) return err;
+    err = launch();
+    const hipError_t e2 = hipEventRecord(b, s);
+    {
+        std::lock_guard<std::mutex> lk(g_timer_mu);
+        g_timer_recs.push_back({name, a, b});
+    }
+    return err != hipSuccess ? err : e2;
+}
+
+#define LAUNCH(name, stream, expr) HIP_TRY(timed(name, stream, [&]() { return (expr); }), name)
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Sequential carving of one workspace; `base == nullptr` only measures.
+struct Carver {
+    char *base;
+    size_t used = 0;
+    template <typename P>
+    P *take(size_t bytes) {
+        const size_t at = used;
+        used += align_up(bytes);
+        return base ? reinterpret_cast<P *>(base + at) : nullptr;
+    }
+};
+
+bool valid_lattice(mlmc_lattice lat) { return lat != nullptr && lat->d_buf != nullptr; }
+
+int small_cap(mlmc_precision prec) { return prec == MLMC_PREC_FP64 ? kSmallMaxF64 : kSmallMaxF32; }
+int large_cap(mlmc_precision prec) { return prec == MLMC_PREC_FP64 ? kLargeMaxF64 : kLargeMaxF32; }
+size_t cplx_bytes(mlmc_precision prec) { return prec == MLMC_PREC_FP64 ? 16 : 8; }
+
+// Buffers of the device-memory eigen path for `units` matrices of side bound ld.
+struct EigBuffers {
+    void *H = nullptr;
+    double *d = nullptr, *e = nullptr;
+    void *partial = nullptr;
+};
+
+void carve_large(Carver &cv, mlmc_precision prec, int64_t ld, int64_t units, bool with_H, EigBuffers &b) {
+    if (with_H) b.H = cv.take<void>(cplx_bytes(prec) * (size_t)ld * (size_t)ld * (size_t)units);
+    b.d = cv.take<double>(sizeof(double) * (size_t)ld * (size_t)units);
+    b.e = cv.take<double>(sizeof(double) * (size_t)ld * (size_t)units);
+    const size_t pe = prec == MLMC_PREC_FP64 ? tridiag_global_partial_elems<double>(ld)
+                                             : tridiag_global_partial_elems<float>(ld);
+    b.partial = cv.take<void>(cplx_bytes(prec) * pe * (size_t)units);
+}
+
+// Eigenvalues of `units` matrices already in b.H (ld > small cap).
+mlmc_status run_large(mlmc_precision prec, void *H, int64_t ld, const int32_t *n, int64_t units, double *w, int64_t ldw,
+                      const EigBuffers &b, hipStream_t s) {
+    if (prec == MLMC_PREC_FP64)
+        LAUNCH("tridiag_global", s, launch_tridiag_global<double>(static_cast<cpx<double> *>(H), ld, n, units, b.d, b.e, ld,
+                                              static_cast<cpx<double> *>(b.partial), s));
+    else
+        LAUNCH("tridiag_global", s, launch_tridiag_global<float>(static_cast<cpx<float> *>(H), ld, n, units, b.d, b.e, ld,
+                                             static_cast<cpx<float> *>(b.partial), s));
+    LAUNCH("bisect", s, launch_bisect(b.d, b.e, ld, n, units, ld, w, ldw, s));
+    return MLMC_OK;
+}
+
+// Layout of mlmc_level_estimate's workspace for a chunk of `mc` samples.
+struct LevelLayout {
+    double *kf = nullptr, *kwf = nullptr, *kc = nullptr, *kwc = nullptr;
+    uint8_t *mask = nullptr, *quarters = nullptr;
+    int32_t *nf = nullptr, *nc = nullptr;
+    double *wf = nullptr, *wc = nullptr;
+    double *If = nullptr, *Ic = nullptr;
+    EigBuffers bf, bc;
+    size_t bytes = 0;
+};
+
+LevelLayout level_layout(const mlmc_lattice_s *lat, int N, bool coupled, int Kf, int Kc, int64_t mc,
+                         mlmc_precision prec, int n_eps, char *base) {
+    LevelLayout L;
+    Carver cv{base};
+    const int G = lat->dev.n_groups, no = lat->dev.n_orb;
+    const int64_t nkf = (int64_t)Kf * Kf, nkc = (int64_t)Kc * Kc;
+    const int64_t ldf = (int64_t)no * N * N;
+    L.kf = cv.take<double>(sizeof(double) * 2 * nkf);
+    L.kwf = cv.take<double>(sizeof(double) * nkf);
+    L.mask = cv.take<uint8_t>((size_t)mc * N * N * G);
+    L.nf = cv.take<int32_t>(sizeof(int32_t) * (size_t)(mc * nkf));
+    L.wf = cv.take<double>(sizeof(double) * (size_t)(mc * nkf * ldf));
+    L.If = cv.take<double>(sizeof(double) * (size_t)mc * n_eps);
+    if (ldf > small_cap(prec)) carve_large(cv, prec, ldf, mc * nkf, true, L.bf);
+    if (coupled) {
+        const int h = N / 2;
+        const int64_t ldc = (int64_t)no * h * h;
+        L.kc = cv.take<double>(sizeof(double) * 2 * nkc);
+        L.kwc = cv.take<double>(sizeof(double) * nkc);
+        L.quarters = cv.take<uint8_t>((size_t)mc * 4 * h * h * G);
+        L.nc = cv.take<int32_t>(sizeof(int32_t) * (size_t)(mc * 4 * nkc));
+        L.wc = cv.take<double>(sizeof(double) * (size_t)(mc * 4 * nkc * ldc));
+        L.Ic = cv.take<double>(sizeof(double) * (size_t)mc * 4 * n_eps);
+        if (ldc > small_cap(prec)) carve_large(cv, prec, ldc, mc * 4 * nkc, true, L.bc);
+    }
+    L.bytes = cv.used;
+    return L;
+}
+
+// Eigenvalues of every (outcome, k) unit of `ns` outcomes of side N.
+mlmc_status outcome_spectra(const mlmc_lattice_s *lat, int N, const uint8_t *mask, int64_t ns, const double *kred,
+                            int nk, mlmc_precision prec, double *w, int32_t *n_out, const EigBuffers &b,
+                            hipStream_t s) {
+    const int64_t ld = (int64_t)lat->dev.n_orb * N * N;
+    const int64_t units = ns * nk;
+    if (ld <= small_cap(prec)) {
+        if (prec == MLMC_PREC_FP64)
+            LAUNCH("small_fused", s, launch_small_from_lattice<double>(lat->dev, N, mask, ns, kred, nk, w, ld, n_out, s));
+        else
+            LAUNCH("small_fused", s, launch_small_from_lattice<float>(lat->dev, N, mask, ns, kred, nk, w, ld, n_out, s));
+        return MLMC_OK;
+    }
+    if (prec == MLMC_PREC_FP64)
+        LAUNCH("assemble", s, launch_assemble<double>(lat->dev, N, mask, ns, kred, nk, static_cast<cpx<double> *>(b.H), ld, n_out, s));
+    else
+        LAUNCH("assemble", s, launch_assemble<float>(lat->dev, N, mask, ns, kred, nk, static_cast<cpx<float> *>(b.H), ld, n_out, s));
+    return run_large(prec, b.H, ld, n_out, units, w, ld, b, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *mlmc_status_string(int status) {
+    switch (status) {
+        case MLMC_OK: return "MLMC_OK";
+        case MLMC_ERR_INVALID_ARG: return "MLMC_ERR_INVALID_ARG";
+        case MLMC_ERR_UNSUPPORTED: return "MLMC_ERR_UNSUPPORTED";
+        case MLMC_ERR_WORKSPACE: return "MLMC_ERR_WORKSPACE";
+        case MLMC_ERR_HIP: return "MLMC_ERR_HIP";
+        default: return "MLMC_ERR_UNKNOWN";
+    }
+}
+
+const char *mlmc_last_error(void) { return g_last_error.c_str(); }
+
+mlmc_status mlmc_lattice_create(const mlmc_lattice_desc *desc, mlmc_lattice *out) {
+    if (!desc || !out) return fail(MLMC_ERR_INVALID_ARG, "lattice_create: NULL argument");
+    *out = nullptr;
+    if (desc->n_orb < 1 || desc->n_orb > 64) return fail(MLMC_ERR_INVALID_ARG, "n_orb out of range: %d", desc->n_orb);
+    if (desc->n_groups < 1 || desc->n_groups > 16)
+        return fail(MLMC_ERR_INVALID_ARG, "n_groups out of range: %d", desc->n_groups);
+    if (desc->n_hops < 1 || desc->n_hops > 65536)
+        return fail(MLMC_ERR_INVALID_ARG, "n_hops out of range: %d", desc->n_hops);
+    if (!(desc->cell_area > 0.0)) return fail(MLMC_ERR_INVALID_ARG, "cell_area must be > 0");
+    if (!desc->orb_frac || !desc->orb_group || !desc->group_removable || !desc->hops)
+        return fail(MLMC_ERR_INVALID_ARG, "lattice_create: NULL array");
+    for (int m = 0; m < desc->n_orb; ++m)
+        if (desc->orb_group[m] < 0 || desc->orb_group[m] >= desc->n_groups)
+            return fail(MLMC_ERR_INVALID_ARG, "orb_group[%d] out of range", m);
+    std::vector<int4> hi(desc->n_hops);
+    std::vector<double4> hf(desc->n_hops);
+    for (int h = 0; h < desc->n_hops; ++h) {
+        const mlmc_hop &r = desc->hops[h];
+        if (r.from_orb < 0 || r.from_orb >= desc->n_orb || r.to_orb < 0 || r.to_orb >= desc->n_orb)
+            return fail(MLMC_ERR_INVALID_ARG, "hop %d: orbital out of range", h);
+        if (!std::isfinite(r.re) || !std::isfinite(r.im))
+            return fail(MLMC_ERR_INVALID_ARG, "hop %d: non-finite amplitude", h);
+        const bool onsite = r.R[0] == 0 && r.R[1] == 0 && r.from_orb == r.to_orb;
+        if (onsite && r.im != 0.0) return fail(MLMC_ERR_INVALID_ARG, "hop %d: on-site energy must be real", h);
+        hi[h] = make_int4(r.R[0], r.R[1], r.from_orb, r.to_orb);
+        const double d1 = r.R[0] + desc->orb_frac[2 * r.to_orb] - desc->orb_frac[2 * r.from_orb];
+        const double d2 = r.R[1] + desc->orb_frac[2 * r.to_orb + 1] - desc->orb_frac[2 * r.from_orb + 1];
+        hf[h] = make_double4(r.re, r.im, d1, d2);
+    }
+    auto *lat = new mlmc_lattice_s();
+    HIP_TRY(hipGetDevice(&lat->device), "hipGetDevice");
+    const size_t bi = align_up(sizeof(int4) * desc->n_hops), bf = align_up(sizeof(double4) * desc->n_hops);
+    const size_t bg = align_up(sizeof(int32_t) * desc->n_orb), br = align_up(desc->n_groups);
+    hipError_t err = hipMalloc(&lat->d_buf, bi + bf + bg + br);
+    if (err != hipSuccess) {
+        delete lat;
+        return hip_fail(err, "hipMalloc(lattice)");
+    }
+    char *p = static_cast<char *>(lat->d_buf);
+    err = hipMemcpy(p, hi.data(), sizeof(int4) * desc->n_hops, hipMemcpyHostToDevice);
+    if (err == hipSuccess) err = hipMemcpy(p + bi, hf.data(), sizeof(double4) * desc->n_hops, hipMemcpyHostToDevice);
+    if (err == hipSuccess) err = hipMemcpy(p + bi + bf, desc->orb_group, sizeof(int32_t) * desc->n_orb, hipMemcpyHostToDevice);
+    if (err == hipSuccess) err = hipMemcpy(p + bi + bf + bg, desc->group_removable, desc->n_groups, hipMemcpyHostToDevice);
+    if (err != hipSuccess) {
+        (void)hipFree(lat->d_buf);
+        delete lat;
+        return hip_fail(err, "hipMemcpy(lattice)");
+    }
+    lat->dev.hop_i = reinterpret_cast<const int4 *>(p);
+    lat->dev.hop_f = reinterpret_cast<const double4 *>(p + bi);
+    lat->dev.orb_group = reinterpret_cast<const int32_t *>(p + bi + bf);
+    lat->dev.removable = reinterpret_cast<const uint8_t *>(p + bi + bf + bg);
+    lat->dev.n_orb = desc->n_orb;
+    lat->dev.n_groups = desc->n_groups;
+    lat->dev.n_hops = desc->n_hops;
+    lat->dev.lattice_id = desc->lattice_id;
+    lat->dev.cell_area = desc->cell_area;
+    *out = lat;
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_lattice_destroy(mlmc_lattice lat) {
+    if (!lat) return MLMC_OK;
+    hipError_t err = hipSuccess;
+    if (lat->d_buf) {
+        err = hipDeviceSynchronize();
+        const hipError_t e2 = hipFree(lat->d_buf);
+        if (err == hipSuccess) err = e2;
+    }
+    delete lat;
+    if (err != hipSuccess) return hip_fail(err, "lattice_destroy");
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_lattice_max_orbitals(mlmc_lattice lat, int32_t N, int64_t *n_max) {
+    if (!valid_lattice(lat) || !n_max || N < 1) return fail(MLMC_ERR_INVALID_ARG, "lattice_max_orbitals: bad argument");
+    *n_max = (int64_t)lat->dev.n_orb * N * N;
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_sample_vacancies(mlmc_lattice lat, int32_t N, double p, uint64_t seed, uint64_t tag,
+                                  int64_t first_sample, int64_t n_samples, uint8_t *d_mask, mlmc_stream stream) {
+    if (!valid_lattice(lat)) return fail(MLMC_ERR_INVALID_ARG, "sample_vacancies: NULL lattice");
+    if (N < 1 || N > 4096) return fail(MLMC_ERR_INVALID_ARG, "sample_vacancies: N = %d", N);
+    if (!(p >= 0.0 && p <= 1.0)) return fail(MLMC_ERR_INVALID_ARG, "sample_vacancies: p = %g", p);
+    if (n_samples < 0 || first_sample < 0) return fail(MLMC_ERR_INVALID_ARG, "sample_vacancies: negative count");
+    if (n_samples > 0 && !d_mask) return fail(MLMC_ERR_INVALID_ARG, "sample_vacancies: NULL mask");
+    const uint64_t thr = (uint64_t)std::floor(p * 9007199254740992.0);
+    LAUNCH("sample_vacancies", static_cast<hipStream_t>(stream), launch_sample_vacancies(lat->dev, N, thr, seed, tag, first_sample, n_samples, d_mask,
+                                    static_cast<hipStream_t>(stream)));
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_partition_masks(mlmc_lattice lat, int32_t N, const uint8_t *d_mask, int64_t n_samples,
+                                 uint8_t *d_quarters, mlmc_stream stream) {
+    if (!valid_lattice(lat)) return fail(MLMC_ERR_INVALID_ARG, "partition_masks: NULL lattice");
+    if (N < 2 || N % 2 != 0) return fail(MLMC_ERR_INVALID_ARG, "partition_masks: N = %d must be even", N);
+    if (n_samples < 0) return fail(MLMC_ERR_INVALID_ARG, "partition_masks: negative count");
+    if (n_samples > 0 && (!d_mask || !d_quarters)) return fail(MLMC_ERR_INVALID_ARG, "partition_masks: NULL buffer");
+    LAUNCH("partition", static_cast<hipStream_t>(stream), launch_partition(N, lat->dev.n_groups, d_mask, n_samples, d_quarters, static_cast<hipStream_t>(stream)));
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_kgrid(mlmc_kgrid_kind kind, int32_t K, double *d_kred, double *d_kweight, mlmc_stream stream) {
+    if (kind != MLMC_KGRID_MP && kind != MLMC_KGRID_GAMMA) return fail(MLMC_ERR_INVALID_ARG, "kgrid: bad kind");
+    if (K < 1 || K > 4096) return fail(MLMC_ERR_INVALID_ARG, "kgrid: K = %d", K);
+    if (!d_kred || !d_kweight) return fail(MLMC_ERR_INVALID_ARG, "kgrid: NULL buffer");
+    LAUNCH("kgrid", static_cast<hipStream_t>(stream), launch_kgrid(kind, K, d_kred, d_kweight, static_cast<hipStream_t>(stream)));
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_build_hamiltonians(mlmc_lattice lat, int32_t N, const uint8_t *d_mask, int64_t n_samples,
+                                    const double *d_kred, int32_t n_k, mlmc_dtype dtype, void *d_H, int64_t ld,
+                                    int32_t *d_n, mlmc_stream stream) {
+    if (!valid_lattice(lat)) return fail(MLMC_ERR_INVALID_ARG, "build_hamiltonians: NULL lattice");
+    if (N < 1 || N > 4096 || n_k < 1 || n_samples < 0)
+        return fail(MLMC_ERR_INVALID_ARG, "build_hamiltonians: N = %d, n_k = %d", N, n_k);
+    if (dtype != MLMC_C128 && dtype != MLMC_C64) return fail(MLMC_ERR_INVALID_ARG, "build_hamiltonians: bad dtype");
+    const int64_t nmax = (int64_t)lat->dev.n_orb * N * N;
+    if (ld < nmax) return fail(MLMC_ERR_INVALID_ARG, "build_hamiltonians: ld %lld < %lld", (long long)ld, (long long)nmax);
+    if (nmax > 16384) return fail(MLMC_ERR_UNSUPPORTED, "build_hamiltonians: %lld orbitals exceed 16384", (long long)nmax);
+    if (n_samples > 0 && (!d_mask || !d_kred || !d_H || !d_n))
+        return fail(MLMC_ERR_INVALID_ARG, "build_hamiltonians: NULL buffer");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (dtype == MLMC_C128)
+        LAUNCH("assemble", s, launch_assemble<double>(lat->dev, N, d_mask, n_samples, d_kred, n_k, static_cast<cpx<double> *>(d_H), ld,
+                                        d_n, s));
+    else
+        LAUNCH("assemble", s, launch_assemble<float>(lat->dev, N, d_mask, n_samples, d_kred, n_k, static_cast<cpx<float> *>(d_H), ld,
+                                       d_n, s));
+    return MLMC_OK;
+}
+
+static mlmc_status check_dtype_prec(mlmc_dtype dtype, mlmc_precision prec) {
+    if (dtype == MLMC_C128 && prec == MLMC_PREC_FP64) return MLMC_OK;
+    if (dtype == MLMC_C64 && prec == MLMC_PREC_MIXED) return MLMC_OK;
+    return fail(MLMC_ERR_UNSUPPORTED, "dtype %d with precision %d is not supported", (int)dtype, (int)prec);
+}
+
+mlmc_status mlmc_eigvalsh_workspace(mlmc_dtype dtype, mlmc_precision prec, int64_t ld, int64_t batch, size_t *bytes) {
+    if (!bytes || ld < 0 || batch < 0) return fail(MLMC_ERR_INVALID_ARG, "eigvalsh_workspace: bad argument");
+    const mlmc_status st = check_dtype_prec(dtype, prec);
+    if (st != MLMC_OK) return st;
+    if (ld > large_cap(prec)) return fail(MLMC_ERR_UNSUPPORTED, "eigvalsh: ld %lld exceeds %d", (long long)ld, large_cap(prec));
+    *bytes = 0;
+    if (ld > small_cap(prec)) {
+        Carver cv{nullptr};
+        EigBuffers b;
+        carve_large(cv, prec, ld, batch, false, b);
+        *bytes = cv.used;
+    }
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_batched_eigvalsh(mlmc_dtype dtype, mlmc_precision prec, void *d_H, int64_t ld, const int32_t *d_n,
+                                  int64_t batch, double *d_w, int64_t ldw, void *d_work, size_t work_bytes,
+                                  mlmc_stream stream) {
+    size_t need = 0;
+    const mlmc_status st = mlmc_eigvalsh_workspace(dtype, prec, ld, batch, &need);
+    if (st != MLMC_OK) return st;
+    if (ldw < ld) return fail(MLMC_ERR_INVALID_ARG, "batched_eigvalsh: ldw %lld < ld %lld", (long long)ldw, (long long)ld);
+    if (batch > 0 && (!d_H || !d_n || !d_w)) return fail(MLMC_ERR_INVALID_ARG, "batched_eigvalsh: NULL buffer");
+    if (need > 0 && (!d_work || work_bytes < need))
+        return fail(MLMC_ERR_WORKSPACE, "batched_eigvalsh: workspace %zu < %zu bytes", work_bytes, need);
+    if (batch == 0 || ld == 0) return MLMC_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (ld <= small_cap(prec)) {
+        if (prec == MLMC_PREC_FP64)
+            LAUNCH("small_fused", s, launch_small_from_matrix<double>(static_cast<const cpx<double> *>(d_H), ld, d_n, batch, d_w, ldw, s));
+        else
+            LAUNCH("small_fused", s, launch_small_from_matrix<float>(static_cast<const cpx<float> *>(d_H), ld, d_n, batch, d_w, ldw, s));
+        return MLMC_OK;
+    }
+    Carver cv{static_cast<char *>(d_work)};
+    EigBuffers b;
+    carve_large(cv, prec, ld, batch, false, b);
+    return run_large(prec, d_H, ld, d_n, batch, d_w, ldw, b, s);
+}
+
+mlmc_status mlmc_idos(const double *d_w, int64_t ldw, const int32_t *d_n, int64_t n_samples, int32_t n_k,
+                      const double *d_kweight, double area, const double *d_eps, int32_t n_eps, double delta,
+                      mlmc_smoother smoother, double *d_idos, mlmc_stream stream) {
+    if (n_samples < 0 || n_k < 1 || n_eps < 0 || ldw < 0)
+        return fail(MLMC_ERR_INVALID_ARG, "idos: bad sizes (n_samples %lld, n_k %d, n_eps %d)", (long long)n_samples, n_k,
+                    n_eps);
+    if (!(delta > 0.0) || !std::isfinite(delta)) return fail(MLMC_ERR_INVALID_ARG, "idos: delta = %g", delta);
+    if (!(area > 0.0) || !std::isfinite(area)) return fail(MLMC_ERR_INVALID_ARG, "idos: area = %g", area);
+    if (smoother != MLMC_SMOOTH_GAUSS && smoother != MLMC_SMOOTH_CUBIC)
+        return fail(MLMC_ERR_INVALID_ARG, "idos: bad smoother");
+    if (n_samples > 0 && n_eps > 0 && (!d_w || !d_n || !d_kweight || !d_eps || !d_idos))
+        return fail(MLMC_ERR_INVALID_ARG, "idos: NULL buffer");
+    LAUNCH("idos", static_cast<hipStream_t>(stream), launch_idos(d_w, ldw, d_n, n_samples, n_k, d_kweight, 1.0 / area, d_eps, n_eps, delta, (int)smoother, d_idos,
+                        static_cast<hipStream_t>(stream)));
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_level_stats(const double *d_idos_fine, const double *d_idos_quarters, int64_t n_samples,
+                             int32_t n_eps, double *d_stats, mlmc_stream stream) {
+    if (n_samples < 0 || n_eps < 0) return fail(MLMC_ERR_INVALID_ARG, "level_stats: negative size");
+    if (n_samples > 0 && n_eps > 0 && (!d_idos_fine || !d_stats))
+        return fail(MLMC_ERR_INVALID_ARG, "level_stats: NULL buffer");
+    LAUNCH("level_stats", static_cast<hipStream_t>(stream), launch_level_stats(d_idos_fine, d_idos_quarters, n_samples, n_eps, d_stats, static_cast<hipStream_t>(stream)));
+    return MLMC_OK;
+}
+
+static mlmc_status check_level_args(mlmc_lattice lat, int32_t N, int32_t coupled, int32_t Kf, int32_t Kc,
+                                    mlmc_precision prec, int32_t n_eps) {
+    if (!valid_lattice(lat)) return fail(MLMC_ERR_INVALID_ARG, "level: NULL lattice");
+    if (N < 1 || N > 4096) return fail(MLMC_ERR_INVALID_ARG, "level: N = %d", N);
+    if (coupled != 0 && coupled != 1) return fail(MLMC_ERR_INVALID_ARG, "level: coupled must be 0 or 1");
+    if (coupled && N % 2 != 0) return fail(MLMC_ERR_INVALID_ARG, "level: coupled level needs even N, got %d", N);
+    if (Kf < 1 || Kf > 4096 || (coupled && (Kc < 1 || Kc > 4096)))
+        return fail(MLMC_ERR_INVALID_ARG, "level: K_fine = %d, K_coarse = %d", Kf, Kc);
+    if (n_eps < 1) return fail(MLMC_ERR_INVALID_ARG, "level: n_eps = %d", n_eps);
+    if (prec != MLMC_PREC_FP64 && prec != MLMC_PREC_MIXED) return fail(MLMC_ERR_INVALID_ARG, "level: bad precision");
+    const int64_t nmax = (int64_t)lat->dev.n_orb * N * N;
+    if (nmax > large_cap(prec))
+        return fail(MLMC_ERR_UNSUPPORTED, "level: %lld orbitals exceed the %d supported by this build", (long long)nmax,
+                    large_cap(prec));
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_level_workspace(mlmc_lattice lat, int32_t N_fine, int32_t coupled, int32_t K_fine, int32_t K_coarse,
+                                 int64_t chunk_samples, mlmc_precision prec, int32_t n_eps, size_t *bytes) {
+    const mlmc_status st = check_level_args(lat, N_fine, coupled, K_fine, K_coarse, prec, n_eps);
+    if (st != MLMC_OK) return st;
+    if (!bytes || chunk_samples < 1) return fail(MLMC_ERR_INVALID_ARG, "level_workspace: chunk_samples must be >= 1");
+    *bytes = level_layout(lat, N_fine, coupled != 0, K_fine, K_coarse, chunk_samples, prec, n_eps, nullptr).bytes;
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_level_estimate(mlmc_lattice lat, int32_t N, int32_t coupled, double p, int32_t Kf, int32_t Kc,
+                                mlmc_kgrid_kind kind, uint64_t seed, int64_t first_sample, int64_t M,
+                                const double *d_eps, int32_t n_eps, double delta, mlmc_smoother smoother,
+                                mlmc_precision prec, double *d_stats, void *d_work, size_t work_bytes,
+                                mlmc_stream stream) {
+    mlmc_status st = check_level_args(lat, N, coupled, Kf, Kc, prec, n_eps);
+    if (st != MLMC_OK) return st;
+    if (!(p >= 0.0 && p <= 1.0)) return fail(MLMC_ERR_INVALID_ARG, "level: p = %g", p);
+    if (!(delta > 0.0) || !std::isfinite(delta)) return fail(MLMC_ERR_INVALID_ARG, "level: delta = %g", delta);
+    if (kind != MLMC_KGRID_MP && kind != MLMC_KGRID_GAMMA) return fail(MLMC_ERR_INVALID_ARG, "level: bad k-grid");
+    if (smoother != MLMC_SMOOTH_GAUSS && smoother != MLMC_SMOOTH_CUBIC)
+        return fail(MLMC_ERR_INVALID_ARG, "level: bad smoother");
+    if (M < 0 || first_sample < 0) return fail(MLMC_ERR_INVALID_ARG, "level: negative sample range");
+    if (M == 0) return MLMC_OK;
+    if (!d_eps || !d_stats) return fail(MLMC_ERR_INVALID_ARG, "level: NULL buffer");
+    const bool cpl = coupled != 0;
+    const size_t one = level_layout(lat, N, cpl, Kf, Kc, 1, prec, n_eps, nullptr).bytes;
+    if (!d_work || work_bytes < one)
+        return fail(MLMC_ERR_WORKSPACE, "level: workspace %zu < %zu bytes needed for one sample", work_bytes, one);
+    const size_t two = level_layout(lat, N, cpl, Kf, Kc, 2, prec, n_eps, nullptr).bytes;
+    const size_t per = two - one, fixed = one - per;
+    int64_t mc = (int64_t)((work_bytes - fixed) / per);
+    if (mc > M) mc = M;
+    if (mc < 1) mc = 1;
+    while (mc > 1 && level_layout(lat, N, cpl, Kf, Kc, mc, prec, n_eps, nullptr).bytes > work_bytes) --mc;
+    const LevelLayout L = level_layout(lat, N, cpl, Kf, Kc, mc, prec, n_eps, static_cast<char *>(d_work));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int G = lat->dev.n_groups, h = N / 2;
+    const uint64_t tag = ((uint64_t)lat->dev.lattice_id << 32) | (uint64_t)(uint32_t)N;
+    const uint64_t thr = (uint64_t)std::floor(p * 9007199254740992.0);
+    const double inv_area_f = 1.0 / ((double)N * N * lat->dev.cell_area);
+    const double inv_area_c = cpl ? 1.0 / ((double)h * h * lat->dev.cell_area) : 0.0;
+    const int nkf = Kf * Kf, nkc = cpl ? Kc * Kc : 0;
+    LAUNCH("kgrid", s, launch_kgrid(kind, Kf, L.kf, L.kwf, s));
+    if (cpl) LAUNCH("kgrid", s, launch_kgrid(kind, Kc, L.kc, L.kwc, s));
+    for (int64_t done = 0; done < M; done += mc) {
+        const int64_t ns = (M - done < mc) ? (M - done) : mc;
+        LAUNCH("sample_vacancies", s, launch_sample_vacancies(lat->dev, N, thr, seed, tag, first_sample + done, ns, L.mask, s));
+        st = outcome_spectra(lat, N, L.mask, ns, L.kf, nkf, prec, L.wf, L.nf, L.bf, s);
+        if (st != MLMC_OK) return st;
+        LAUNCH("idos", s, launch_idos(L.wf, (int64_t)lat->dev.n_orb * N * N, L.nf, ns, nkf, L.kwf, inv_area_f, d_eps, n_eps, delta,
+                            (int)smoother, L.If, s));
+        if (cpl) {
+            LAUNCH("partition", s, launch_partition(N, G, L.mask, ns, L.quarters, s));
+            st = outcome_spectra(lat, h, L.quarters, ns * 4, L.kc, nkc, prec, L.wc, L.nc, L.bc, s);
+            if (st != MLMC_OK) return st;
+            LAUNCH("idos", s, launch_idos(L.wc, (int64_t)lat->dev.n_orb * h * h, L.nc, ns * 4, nkc, L.kwc, inv_area_c, d_eps, n_eps,
+                                delta, (int)smoother, L.Ic, s));
+        }
+        LAUNCH("level_stats", s, launch_level_stats(L.If, cpl ? L.Ic : nullptr, ns, n_eps, d_stats, s));
+    }
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_optimal_samples(int32_t L, const double *V, const double *W, double C_alpha, double theta, double tol,
+                                 double *M_out) {
+    if (L < 1 || !V || !W || !M_out) return fail(MLMC_ERR_INVALID_ARG, "optimal_samples: bad argument");
+    if (!(theta > 0.0) || !(tol > 0.0) || !(C_alpha > 0.0))
+        return fail(MLMC_ERR_INVALID_ARG, "optimal_samples: theta, tol and C_alpha must be > 0");
+    double total = 0.0;
+    for (int l = 0; l < L; ++l) {
+        if (!(V[l] >= 0.0) || !(W[l] > 0.0)) return fail(MLMC_ERR_INVALID_ARG, "optimal_samples: V[%d], W[%d]", l, l);
+        total += std::sqrt(W[l] * V[l]);
+    }
+    const double scale = (C_alpha / (theta * tol)) * (C_alpha / (theta * tol));
+    for (int l = 0; l < L; ++l) M_out[l] = scale * std::sqrt(V[l] / W[l]) * total;
+    return MLMC_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+mlmc_status mlmc_timer_enable(int32_t enable) {
+    std::lock_guard<std::mutex> lk(g_timer_mu);
+    if (enable) timer_clear_locked();
+    g_timing.store(enable != 0);
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_timer_read(const char *name, double *total_ms, int64_t *launches) {
+    if (!name || !total_ms || !launches) return fail(MLMC_ERR_INVALID_ARG, "timer_read: NULL argument");
+    std::lock_guard<std::mutex> lk(g_timer_mu);
+    double total = 0.0;
+    int64_t count = 0;
+    for (auto &r : g_timer_recs) {
+        if (std::strcmp(r.name, name) != 0) continue;
+        HIP_TRY(hipEventSynchronize(r.stop), "timer_read");
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, r.start, r.stop), "timer_read");
+        total += ms;
+        ++count;
+    }
+    *total_ms = total;
+    *launches = count;
+    return MLMC_OK;
+}
+
+}  // extern "C"

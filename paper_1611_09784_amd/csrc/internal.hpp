@@ -1,0 +1,164 @@
+// Internal declarations of the gfx950 library behind include/mlmc.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "mlmc.h"
+
+namespace mlmc {
+
+// ---------------------------------------------------------------------------
+// Complex arithmetic on interleaved (re, im) pairs.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct alignas(2 * sizeof(T)) cpx {
+    T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cpx<T> c_add(cpx<T> a, cpx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> c_sub(cpx<T> a, cpx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> c_mul(cpx<T> a, cpx<T> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// a * conj(b)
+template <typename T>
+__device__ __forceinline__ cpx<T> c_mulc(cpx<T> a, cpx<T> b) {
+    return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
+}
+// conj(a) * b
+template <typename T>
+__device__ __forceinline__ cpx<T> c_cmul(cpx<T> a, cpx<T> b) {
+    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> c_conj(cpx<T> a) { return {a.re, -a.im}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> c_scale(T s, cpx<T> a) { return {s * a.re, s * a.im}; }
+template <typename T>
+__device__ __forceinline__ T c_abs2(cpx<T> a) { return a.re * a.re + a.im * a.im; }
+
+// ---------------------------------------------------------------------------
+// Device copy of a lattice (built once by mlmc_lattice_create).
+// hop_i[h] = (R1, R2, from, to); hop_f[h] = (re, im, d1, d2) with
+// d = R + frac(to) - frac(from) the unwrapped displacement in units of a1, a2.
+// ---------------------------------------------------------------------------
+struct DevLattice {
+    const int4 *hop_i;
+    const double4 *hop_f;
+    const int32_t *orb_group;
+    const uint8_t *removable;
+    int n_orb;
+    int n_groups;
+    int n_hops;
+    uint32_t lattice_id;
+    double cell_area;
+};
+
+// Largest pristine matrix side handled by the LDS-resident fused kernel.
+constexpr int kSmallMaxF64 = 128;
+constexpr int kSmallMaxF32 = 180;
+// Largest matrix side of the device-memory reduction (LDS holds 3 vectors).
+constexpr int kLargeMaxF64 = 2048;
+constexpr int kLargeMaxF32 = 4096;
+// Gaussian smoothing is evaluated for |x| < kGaussCut and is exactly 0 / 1 beyond.
+constexpr double kGaussCut = 10.0;
+
+__host__ __device__ constexpr int64_t packed_size(int64_t n) { return n * (n + 1) / 2; }
+
+// ---------------------------------------------------------------------------
+// Launchers (each returns hipGetLastError() of its launch).
+// ---------------------------------------------------------------------------
+hipError_t launch_sample_vacancies(const DevLattice &lat, int N, uint64_t threshold, uint64_t seed, uint64_t tag,
+                                   int64_t first, int64_t n_samples, uint8_t *mask, hipStream_t s);
+hipError_t launch_partition(int N, int G, const uint8_t *mask, int64_t n_samples, uint8_t *quarters, hipStream_t s);
+hipError_t launch_kgrid(int kind, int K, double *kred, double *kweight, hipStream_t s);
+
+template <typename T>
+hipError_t launch_assemble(const DevLattice &lat, int N, const uint8_t *masks, int64_t n_samples, const double *kred,
+                           int n_k, cpx<T> *H, int64_t ld, int32_t *n_out, hipStream_t s);
+
+// Fused LDS kernel: (assemble or load) -> Householder -> bisection -> eigenvalues.
+template <typename T>
+hipError_t launch_small_from_lattice(const DevLattice &lat, int N, const uint8_t *masks, int64_t n_samples,
+                                     const double *kred, int n_k, double *w, int64_t ldw, int32_t *n_out,
+                                     hipStream_t s);
+template <typename T>
+hipError_t launch_small_from_matrix(const cpx<T> *H, int64_t ld, const int32_t *n_in, int64_t batch, double *w,
+                                    int64_t ldw, hipStream_t s);
+
+// Device-memory one-stage reduction (one workgroup per matrix) -> (d, e).
+template <typename T>
+hipError_t launch_tridiag_global(cpx<T> *H, int64_t ld, const int32_t *n_in, int64_t batch, double *d, double *e,
+                                 int64_t lde, cpx<T> *partial, hipStream_t s);
+template <typename T>
+size_t tridiag_global_partial_elems(int64_t ld);
+
+// Sturm-count bisection of (d, e) -> ascending eigenvalues.
+hipError_t launch_bisect(const double *d, const double *e, int64_t lde, const int32_t *n_in, int64_t batch,
+                         int64_t ld_max, double *w, int64_t ldw, hipStream_t s);
+
+hipError_t launch_idos(const double *w, int64_t ldw, const int32_t *n, int64_t n_samples, int n_k,
+                       const double *kweight, double inv_area, const double *eps, int n_eps, double delta,
+                       int smoother, double *out, hipStream_t s);
+hipError_t launch_level_stats(const double *fine, const double *quarters, int64_t n_samples, int n_eps,
+                              double *stats, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Deterministic block reductions (fixed butterfly order within a wave, then
+// waves summed in index order).  `scratch` holds >= 16 doubles in LDS.
+// All threads of the block must call them; every thread gets the result.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__device__ __forceinline__ double block_sum(double v, double *scratch) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane == 0) scratch[wid] = v;
+    __syncthreads();
+    double r = 0.0;
+    for (int i = 0; i < nw; ++i) r += scratch[i];
+    return r;
+}
+__device__ __forceinline__ double block_min(double v, double *scratch) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    v = wave_min(v);
+    __syncthreads();
+    if (lane == 0) scratch[wid] = v;
+    __syncthreads();
+    double r = scratch[0];
+    for (int i = 1; i < nw; ++i) r = fmin(r, scratch[i]);
+    return r;
+}
+__device__ __forceinline__ double block_max(double v, double *scratch) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    v = wave_max(v);
+    __syncthreads();
+    if (lane == 0) scratch[wid] = v;
+    __syncthreads();
+    double r = scratch[0];
+    for (int i = 1; i < nw; ++i) r = fmax(r, scratch[i]);
+    return r;
+}
+
+}  // namespace mlmc

@@ -1,0 +1,150 @@
+// Sturm bisection of tridiagonal matrices, smoothed IDoS and level sums.
+#include "device_common.hpp"
+
+namespace mlmc {
+
+// ---------------------------------------------------------------------------
+// Bisection: one workgroup per tridiagonal (d, e); d and e are staged in LDS
+// (e squared there), so the serial Sturm recurrences read broadcast LDS.
+// ---------------------------------------------------------------------------
+constexpr int kBisectThreads = 256;
+
+__global__ __launch_bounds__(kBisectThreads) void bisect_kernel(const double *__restrict__ dall,
+                                                                const double *__restrict__ eall, int64_t lde,
+                                                                const int32_t *__restrict__ n_in, int64_t ld_max,
+                                                                double *__restrict__ w, int64_t ldw) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    double *red = reinterpret_cast<double *>(smem);
+    int *cnt = reinterpret_cast<int *>(red + 32);
+    double *d = reinterpret_cast<double *>(cnt + kBisectThreads + 8);
+    double *e = d + ld_max;
+    const int64_t u = blockIdx.x;
+    const int n = n_in[u];
+    double *wu = w + u * ldw;
+    if (n < 0 || n > ld_max) {
+        for (int64_t i = threadIdx.x; i < ldw && i < ld_max; i += blockDim.x) wu[i] = NAN;
+        return;
+    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        d[i] = dall[u * lde + i];
+        e[i] = (i + 1 < n) ? eall[u * lde + i] : 0.0;
+    }
+    __syncthreads();
+    bisect_block(d, e, n, wu, red, cnt);
+}
+
+hipError_t launch_bisect(const double *d, const double *e, int64_t lde, const int32_t *n_in, int64_t batch,
+                         int64_t ld_max, double *w, int64_t ldw, hipStream_t s) {
+    if (batch == 0) return hipSuccess;
+    const size_t lds = 32 * sizeof(double) + (kBisectThreads + 8) * sizeof(int) + 2 * sizeof(double) * (size_t)ld_max;
+    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(bisect_kernel),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(bisect_kernel, dim3((unsigned)batch), dim3(kBisectThreads), lds, s, d, e, lde, n_in, ld_max, w,
+                       ldw);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Smoothed IDoS (eq. (IDoS), nearest-point rule, eq. (MLMC_smoothing)).
+// Thread = (outcome, energy).  For each k-point the ascending eigenvalues are
+// split by binary search into those with g = 1 exactly (counted), a window
+// where g is evaluated, and those with g = 0; k-points are summed in order.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int count_le(const double *E, int n, double x) {  // #{E_i <= x}
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (E[mid] <= x) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+__device__ __forceinline__ int count_lt(const double *E, int n, double x) {  // #{E_i < x}
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (E[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ double smooth_step(int smoother, double x) {
+    if (smoother == MLMC_SMOOTH_GAUSS) return 0.5 * erfc(x * 0.70710678118654752440);
+    if (x <= -1.0) return 1.0;
+    if (x >= 1.0) return 0.0;
+    return 0.5 - 1.125 * x + 0.625 * x * x * x;
+}
+
+__global__ __launch_bounds__(256) void idos_kernel(const double *__restrict__ w, int64_t ldw,
+                                                   const int32_t *__restrict__ n, int n_k,
+                                                   const double *__restrict__ kweight, double inv_area,
+                                                   const double *__restrict__ eps, int n_eps, double delta,
+                                                   int smoother, double *__restrict__ out) {
+    const int64_t s = blockIdx.x;
+    const int j = blockIdx.y * blockDim.x + threadIdx.x;
+    if (j >= n_eps) return;
+    const double ej = eps[j];
+    const double cut = (smoother == MLMC_SMOOTH_GAUSS) ? kGaussCut : 1.0;
+    const double lo_e = ej - cut * delta, hi_e = ej + cut * delta;
+    const double inv_delta = 1.0 / delta;
+    double acc = 0.0;
+    for (int k = 0; k < n_k; ++k) {
+        const int64_t unit = s * n_k + k;
+        const int nu = max(0, min(n[unit], (int)ldw));
+        const double *E = w + unit * ldw;
+        const int below = count_le(E, nu, lo_e);
+        const int upto = count_lt(E, nu, hi_e);
+        double sum = (double)below;
+        for (int i = below; i < upto; ++i) sum += smooth_step(smoother, (E[i] - ej) * inv_delta);
+        acc += kweight[k] * sum;
+    }
+    out[s * n_eps + j] = acc * inv_area;
+}
+
+hipError_t launch_idos(const double *w, int64_t ldw, const int32_t *n, int64_t n_samples, int n_k,
+                       const double *kweight, double inv_area, const double *eps, int n_eps, double delta,
+                       int smoother, double *out, hipStream_t s) {
+    if (n_samples == 0 || n_eps == 0) return hipSuccess;
+    const int threads = 256;
+    dim3 grid((unsigned)n_samples, (unsigned)((n_eps + threads - 1) / threads));
+    hipLaunchKernelGGL(idos_kernel, grid, dim3(threads), 0, s, w, ldw, n, n_k, kweight, inv_area, eps, n_eps, delta,
+                       smoother, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Level sums of eq. (MLMC): thread = energy, samples accumulated in order.
+// ---------------------------------------------------------------------------
+__global__ void level_stats_kernel(const double *__restrict__ fine, const double *__restrict__ quarters,
+                                   int64_t n_samples, int n_eps, double *__restrict__ stats) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n_eps) return;
+    double sy = 0.0, syy = 0.0, sq = 0.0, sqq = 0.0;
+    for (int64_t s = 0; s < n_samples; ++s) {
+        const double qf = fine[s * n_eps + j];
+        double y = qf;
+        if (quarters) {
+            const double *q = quarters + s * 4 * (int64_t)n_eps;
+            y = qf - 0.25 * (q[j] + q[n_eps + j] + q[2 * n_eps + j] + q[3 * n_eps + j]);
+        }
+        sy += y;
+        syy += y * y;
+        sq += qf;
+        sqq += qf * qf;
+    }
+    stats[j] += sy;
+    stats[n_eps + j] += syy;
+    stats[2 * n_eps + j] += sq;
+    stats[3 * n_eps + j] += sqq;
+}
+
+hipError_t launch_level_stats(const double *fine, const double *quarters, int64_t n_samples, int n_eps,
+                              double *stats, hipStream_t s) {
+    if (n_eps == 0 || n_samples == 0) return hipSuccess;
+    const int threads = 128;
+    hipLaunchKernelGGL(level_stats_kernel, dim3((n_eps + threads - 1) / threads), dim3(threads), 0, s, fine, quarters,
+                       n_samples, n_eps, stats);
+    return hipGetLastError();
+}
+
+}  // namespace mlmc

@@ -1,0 +1,90 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function
+declared in include/mlmc.h, and host-only entry points and argument
+validation behave as documented (no device work is started here)."""
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mlmc.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mlmc_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1611_09784_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.fail("libmlmc.so is not built (run __graft_entry__.build())")
+    binding.lib()
+    return binding
+
+
+def test_header_declares_the_four_core_calls():
+    names = declared_functions()
+    for core in ("mlmc_build_hamiltonians", "mlmc_batched_eigvalsh", "mlmc_idos", "mlmc_level_estimate"):
+        assert core in names
+
+
+def test_library_exports_every_declared_symbol(B):
+    names = declared_functions()
+    lib = C.CDLL(B.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(names) == set(B.SIGNATURES), "binding signatures must mirror the header"
+
+
+def test_status_strings(B):
+    assert B.status_string(0) == "MLMC_OK"
+    assert B.status_string(-3) == "MLMC_ERR_WORKSPACE"
+    assert B.status_string(-99) == "MLMC_ERR_UNKNOWN"
+
+
+def test_optimal_samples_matches_oracle(B):
+    from oracle import mlmc as omlmc
+    V = [3e-4, 5e-5, 1e-5, 2e-6]
+    W = [0.002, 0.01, 0.08, 0.6]
+    got = B.mlmc_optimal_samples(V, W, 2.0, 0.5, 1e-3)
+    want = omlmc.optimal_samples(V, W, 2.0, 0.5, 1e-3)
+    assert np.allclose(got, want, rtol=1e-14, atol=0)
+
+
+def test_validation_without_device(B):
+    lib = B.lib()
+    out = C.c_size_t()
+    # unsupported dtype / precision pairs and oversize matrices are rejected up front
+    assert lib.mlmc_eigvalsh_workspace(B.MLMC_C128, B.MLMC_PREC_MIXED, 64, 1, C.byref(out)) == B.MLMC_ERR_UNSUPPORTED
+    assert lib.mlmc_eigvalsh_workspace(B.MLMC_C128, B.MLMC_PREC_FP64, 4096, 1, C.byref(out)) == B.MLMC_ERR_UNSUPPORTED
+    assert lib.mlmc_eigvalsh_workspace(B.MLMC_C128, B.MLMC_PREC_FP64, 64, 10, C.byref(out)) == B.MLMC_OK
+    assert out.value == 0  # fused LDS path needs no workspace
+    assert lib.mlmc_eigvalsh_workspace(B.MLMC_C128, B.MLMC_PREC_FP64, 512, 10, C.byref(out)) == B.MLMC_OK
+    assert out.value > 0
+    # bad arguments return errors before any launch
+    assert lib.mlmc_kgrid(0, 0, None, None, None) == B.MLMC_ERR_INVALID_ARG
+    assert lib.mlmc_kgrid(7, 4, None, None, None) == B.MLMC_ERR_INVALID_ARG
+    assert lib.mlmc_idos(None, 8, None, 1, 1, None, 1.0, None, 5, 0.0, 0, None, None) == B.MLMC_ERR_INVALID_ARG
+    assert lib.mlmc_idos(None, 8, None, 1, 1, None, -1.0, None, 5, 0.1, 0, None, None) == B.MLMC_ERR_INVALID_ARG
+    assert lib.mlmc_sample_vacancies(None, 4, 0.1, 0, 0, 0, 1, None, None) == B.MLMC_ERR_INVALID_ARG
+    assert lib.mlmc_level_estimate(None, 4, 0, 0.1, 1, 1, 0, 0, 0, 1, None, 1, 0.1, 0, 0, None, None, 0,
+                                   None) == B.MLMC_ERR_INVALID_ARG
+    assert lib.mlmc_lattice_create(None, None) == B.MLMC_ERR_INVALID_ARG
+    assert b"NULL" in lib.mlmc_last_error()
+    assert lib.mlmc_lattice_destroy(None) == B.MLMC_OK
+    V = (C.c_double * 2)(1.0, -1.0)
+    W = (C.c_double * 2)(1.0, 1.0)
+    M = (C.c_double * 2)()
+    assert lib.mlmc_optimal_samples(2, V, W, 2.0, 0.5, 1e-3, M) == B.MLMC_ERR_INVALID_ARG
+
+
+def test_lattice_descriptor_layout(B):
+    # the binding's ctypes structs match the C layout (8-byte aligned doubles)
+    assert C.sizeof(B._Hop) == 32
+    assert C.sizeof(B._LatticeDesc) == 56

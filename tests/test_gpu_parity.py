@@ -1,0 +1,337 @@
+"""GPU parity: every C-ABI entry point against the FP64 oracle on the same
+seeded inputs.
+
+Tolerances (stated per output):
+  * integer / byte results (vacancy masks, partitions, matrix sides): bit-exact;
+  * H(k) entries: 1e-14 * max|H| (complex128; both sides evaluate the same
+    phases with different sin/cos implementations);
+  * eigenvalues: max_i |E_i - E_i^oracle| <= 1e-9 * max_i |E_i^oracle|
+    (FP64 path); mixed path: 2e-5 * max|E| (single-precision reduction);
+  * IDoS per unit area: 1e-10 (FP64 path), 1e-5 (mixed path);
+  * level sums: the IDoS bound scaled by the number of samples.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from mlmc_inputs import energy_grid, graphene, mos2_shaped  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1611_09784_amd import binding
+    binding.lib()
+    return binding
+
+
+@pytest.fixture(scope="module")
+def glat():
+    return graphene()
+
+
+@pytest.fixture(scope="module")
+def mlat():
+    return mos2_shaped()
+
+
+@pytest.fixture(scope="module")
+def gdev(B, glat):
+    d = B.DeviceLattice(glat, 0)
+    yield d
+    d.close()
+
+
+@pytest.fixture(scope="module")
+def mdev(B, mlat):
+    d = B.DeviceLattice(mlat, 0)
+    yield d
+    d.close()
+
+
+def pick(dev_name, gdev, mdev):
+    return gdev if dev_name == "graphene" else mdev
+
+
+# ---------------------------------------------------------------------------
+# a1 / a2 / a3: vacancy outcomes, partition, k-grid (bit-exact)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name,N,p,seed,first,ns", [
+    ("graphene", 4, 0.05, 101, 0, 100),
+    ("graphene", 16, 0.05, 202, 1990, 10),
+    ("graphene", 3, 0.5, 7, 123456789, 5),
+    ("graphene", 5, 0.0, 1, 0, 4),
+    ("graphene", 5, 1.0, 1, 0, 4),
+    ("mos2", 8, 0.02, 404, 3, 7),
+    ("mos2", 2, 1.0, 9, 0, 2),
+])
+def test_sample_vacancies_bit_exact(B, gdev, mdev, name, N, p, seed, first, ns):
+    say(f"[sample_vacancies] {name} N={N} p={p} seed={seed} first={first} ns={ns}")
+    dl = pick(name, gdev, mdev)
+    tag = dl.tag(N)
+    got = B.mlmc_sample_vacancies(dl, N, p, seed, tag, first, ns).cpu().numpy()
+    want = oracle.sample_vacancies(dl.lat, N, p, seed, tag, first, ns)
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("name,N", [("graphene", 2), ("graphene", 8), ("mos2", 6)])
+def test_partition_bit_exact(B, gdev, mdev, name, N):
+    say(f"[partition] {name} N={N}")
+    dl = pick(name, gdev, mdev)
+    mask = B.mlmc_sample_vacancies(dl, N, 0.4, 3, dl.tag(N), 0, 5)
+    got = B.mlmc_partition_masks(dl, N, mask).cpu().numpy()
+    m = mask.cpu().numpy()
+    for s in range(5):
+        assert np.array_equal(got[s], oracle.partition_masks(m[s]))
+
+
+@pytest.mark.parametrize("kind,K", [(0, 1), (0, 4), (0, 8), (1, 1), (1, 6), (0, 7)])
+def test_kgrid(B, kind, K):
+    say(f"[kgrid] kind={kind} K={K}")
+    kred, kw = B.mlmc_kgrid(kind, K)
+    okred, okw = oracle.kgrid(kind, K)
+    assert np.array_equal(kred.cpu().numpy(), okred)
+    assert np.array_equal(kw.cpu().numpy(), okw)
+
+
+# ---------------------------------------------------------------------------
+# a4: H(k) assembly
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name,N,p", [("graphene", 1, 0.0), ("graphene", 2, 0.3), ("graphene", 5, 0.2),
+                                      ("mos2", 1, 0.0), ("mos2", 2, 0.4), ("mos2", 3, 0.3), ("graphene", 3, 1.0)])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_build_hamiltonians(B, gdev, mdev, name, N, p, dtype):
+    say(f"[build_hamiltonians] {name} N={N} p={p} {dtype}")
+    dl = pick(name, gdev, mdev)
+    ns = 3
+    mask = B.mlmc_sample_vacancies(dl, N, p, 5, dl.tag(N), 0, ns)
+    kred, _ = B.mlmc_kgrid(0, 3)
+    code = B.MLMC_C128 if dtype == "c128" else B.MLMC_C64
+    H, n = B.mlmc_build_hamiltonians(dl, N, mask, kred, code)
+    H = H.cpu().numpy()
+    n = n.cpu().numpy()
+    m = mask.cpu().numpy()
+    kr = kred.cpu().numpy()
+    tol = 1e-14 if dtype == "c128" else 2e-7
+    for s in range(ns):
+        for k in range(kr.shape[0]):
+            u = s * kr.shape[0] + k
+            Ho = oracle.build_hamiltonian(dl.lat, N, m[s], kr[k])
+            assert n[u] == Ho.shape[0]
+            Hg = H[u][: n[u], : n[u]].T  # column-major storage
+            scale = max(1.0, np.abs(Ho).max()) if Ho.size else 1.0
+            assert np.abs(Hg - Ho).max(initial=0.0) <= tol * scale
+
+
+# ---------------------------------------------------------------------------
+# a5 + a6: batched eigensolver (both paths, both precisions)
+# ---------------------------------------------------------------------------
+
+def oracle_eigs(Hcm, n):
+    out = []
+    for u in range(Hcm.shape[0]):
+        A = Hcm[u][: n[u], : n[u]].T
+        out.append(oracle.eigvalsh(A) if n[u] > 0 else np.zeros(0))
+    return out
+
+
+def check_eigs(w, ref, n, rel):
+    for u, r in enumerate(ref):
+        if n[u] == 0:
+            continue
+        scale = max(1.0, np.abs(r).max())
+        err = np.abs(w[u, : n[u]] - r).max()
+        assert err <= rel * scale, f"unit {u}: n={n[u]} err={err:.3e}"
+
+
+@pytest.mark.parametrize("name,N,p,K", [("graphene", 4, 0.05, 4), ("graphene", 8, 0.05, 2), ("mos2", 3, 0.2, 2),
+                                        ("graphene", 12, 0.05, 1), ("mos2", 4, 0.1, 1), ("graphene", 16, 0.05, 1)])
+def test_batched_eigvalsh_fp64(B, gdev, mdev, name, N, p, K):
+    say(f"[eigvalsh fp64] {name} N={N} p={p} K={K}")
+    dl = pick(name, gdev, mdev)
+    ns = 2
+    mask = B.mlmc_sample_vacancies(dl, N, p, 17, dl.tag(N), 0, ns)
+    kred, _ = B.mlmc_kgrid(0, K)
+    H, n = B.mlmc_build_hamiltonians(dl, N, mask, kred, B.MLMC_C128)
+    Hc = H.cpu().numpy()
+    nc = n.cpu().numpy()
+    w = B.mlmc_batched_eigvalsh(H, n).cpu().numpy()
+    check_eigs(w, oracle_eigs(Hc, nc), nc, 1e-9)
+
+
+@pytest.mark.parametrize("ld,sizes", [(64, [0, 1, 2, 3, 17, 64]), (128, [128, 127, 5]), (200, [200, 199, 1, 2, 130]),
+                                      (300, [3, 300, 257])])
+def test_batched_eigvalsh_random_ragged(B, ld, sizes):
+    say(f"[eigvalsh random] ld={ld} sizes={sizes}")
+    rng = np.random.default_rng(ld)
+    batch = len(sizes)
+    Hs = np.zeros((batch, ld, ld), np.complex128)
+    for u, m in enumerate(sizes):
+        A = rng.normal(size=(m, m)) + 1j * rng.normal(size=(m, m))
+        A = A + A.conj().T
+        if u == 1 and m > 4:   # a matrix with a degenerate cluster and exact zeros
+            A[:, :] = 0.0
+            A[np.arange(m), np.arange(m)] = np.repeat([1.0, -2.0, 0.0, 3.0], (m + 3) // 4)[:m]
+        Hs[u, :m, :m] = A.T   # column-major storage of A
+    H = torch.as_tensor(Hs, device=DEV)
+    n = torch.as_tensor(np.array(sizes, np.int32), device=DEV)
+    w = B.mlmc_batched_eigvalsh(H, n).cpu().numpy()
+    ref = [np.linalg.eigvalsh(Hs[u, :m, :m].T) if m else np.zeros(0) for u, m in enumerate(sizes)]
+    check_eigs(w, ref, sizes, 1e-9)
+
+
+@pytest.mark.parametrize("name,N,K", [("graphene", 4, 2), ("mos2", 4, 1), ("graphene", 12, 1), ("graphene", 16, 1)])
+def test_batched_eigvalsh_mixed(B, gdev, mdev, name, N, K):
+    say(f"[eigvalsh mixed] {name} N={N} K={K}")
+    dl = pick(name, gdev, mdev)
+    mask = B.mlmc_sample_vacancies(dl, N, 0.05, 23, dl.tag(N), 0, 2)
+    kred, _ = B.mlmc_kgrid(0, K)
+    H64, n = B.mlmc_build_hamiltonians(dl, N, mask, kred, B.MLMC_C64)
+    H128, _ = B.mlmc_build_hamiltonians(dl, N, mask, kred, B.MLMC_C128)
+    nc = n.cpu().numpy()
+    ref = oracle_eigs(H128.cpu().numpy(), nc)
+    w = B.mlmc_batched_eigvalsh(H64, n).cpu().numpy()
+    check_eigs(w, ref, nc, 2e-5)
+
+
+def test_invalid_side_gives_nan(B):
+    say("[eigvalsh invalid n]")
+    H = torch.zeros((2, 8, 8), dtype=torch.complex128, device=DEV)
+    H[0, 0, 0] = 1.0
+    n = torch.tensor([1, 9], dtype=torch.int32, device=DEV)
+    w = B.mlmc_batched_eigvalsh(H, n).cpu().numpy()
+    assert w[0, 0] == 1.0
+    assert np.isnan(w[1]).all()
+
+
+# ---------------------------------------------------------------------------
+# a7 / a8: IDoS and level sums
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("smoother", [0, 1])
+def test_idos_parity(B, gdev, glat, smoother):
+    say(f"[idos] smoother={smoother}")
+    N, K, ns = 6, 3, 4
+    mask = B.mlmc_sample_vacancies(gdev, N, 0.1, 5, gdev.tag(N), 0, ns)
+    kred, kw = B.mlmc_kgrid(0, K)
+    H, n = B.mlmc_build_hamiltonians(gdev, N, mask, kred, B.MLMC_C128)
+    w = B.mlmc_batched_eigvalsh(H, n)
+    eps = energy_grid(-9.0, 9.0, 201)
+    delta = 0.1 if smoother == 0 else 0.3
+    got = B.mlmc_idos(w, n, K * K, kw, N * N * glat.cell_area, torch.as_tensor(eps, device=DEV), delta,
+                      smoother).cpu().numpy()
+    wc, nc, kwc = w.cpu().numpy(), n.cpu().numpy(), kw.cpu().numpy()
+    for s in range(ns):
+        sl = slice(s * K * K, (s + 1) * K * K)
+        want = oracle.idos(wc[sl], nc[sl], kwc, N * N * glat.cell_area, eps, delta, smoother)
+        assert np.abs(got[s] - want).max() <= 1e-12
+
+
+def test_level_stats(B):
+    say("[level_stats]")
+    rng = np.random.default_rng(3)
+    f = rng.random((9, 33))
+    q = rng.random((9, 4, 33))
+    st = B.mlmc_level_stats(torch.as_tensor(f, device=DEV), torch.as_tensor(q, device=DEV)).cpu().numpy()
+    y = f - 0.25 * q.sum(axis=1)
+    want = np.stack([y.sum(0), (y * y).sum(0), f.sum(0), (f * f).sum(0)])
+    assert np.abs(st - want).max() < 1e-13
+    st2 = B.mlmc_level_stats(torch.as_tensor(f, device=DEV)).cpu().numpy()
+    want2 = np.stack([f.sum(0), (f * f).sum(0), f.sum(0), (f * f).sum(0)])
+    assert np.abs(st2 - want2).max() < 1e-13
+
+
+def compare_stats(got, want, M, tol):
+    ymax = max(1.0, np.abs(want[0]).max() / M, np.abs(want[2]).max() / M)
+    assert np.abs(got[0] - want[0]).max() <= M * tol
+    assert np.abs(got[2] - want[2]).max() <= M * tol
+    assert np.abs(got[1] - want[1]).max() <= M * 2.5 * ymax * tol
+    assert np.abs(got[3] - want[3]).max() <= M * 2.5 * ymax * tol
+
+
+@pytest.mark.parametrize("name,N,coupled,K,Kc,kind,M,prec", [
+    ("graphene", 4, False, 4, 4, 0, 20, 0),     # plain MC, graphene N=4, MP 4x4
+    ("graphene", 8, True, 2, 4, 1, 6, 0),       # coupled, both sides on the fused path
+    ("graphene", 16, True, 1, 2, 1, 2, 0),      # coupled, fine side on the device-memory path
+    ("mos2", 4, True, 2, 4, 1, 3, 0),           # MoS2-shaped fine n=176 (device-memory path)
+    ("graphene", 8, True, 2, 4, 1, 6, 1),       # mixed precision, fused path
+    ("mos2", 4, False, 2, 2, 0, 3, 1),          # mixed precision, fused path at n=176
+    ("graphene", 16, False, 1, 1, 0, 2, 1),     # mixed precision, device-memory path
+])
+def test_level_estimate_parity(B, gdev, mdev, name, N, coupled, K, Kc, kind, M, prec):
+    say(f"[level_estimate] {name} N={N} coupled={coupled} K={K} Kc={Kc} kind={kind} M={M} prec={prec}")
+    dl = pick(name, gdev, mdev)
+    if name == "graphene":
+        eps = energy_grid(-9.0, 9.0, 201)
+    else:
+        b = dl.lat.hop_magnitude_bound() + 1.0
+        eps = energy_grid(-b, b, 201)
+    delta, p, seed = 0.1, 0.1, 404
+    got = B.mlmc_level_estimate(dl, N, coupled, p, K, Kc, kind, seed, 5, M, torch.as_tensor(eps, device=DEV), delta,
+                                prec=prec).cpu().numpy()
+    want = oracle.level_estimate(dl.lat, N, coupled, p, K, Kc, kind, seed, 5, M, eps, delta, 0, n_threads=8)
+    compare_stats(got, want, M, 1e-10 if prec == 0 else 1e-5)
+
+
+def test_level_estimate_full_size_sample(B, gdev, glat):
+    """Graphene N=16, MP 8x8, 401 energies, delta 0.05 (the 128k-eigensolve
+    plain-MC workload) in the launch configuration of the benchmark, checked
+    on one sampled outcome that the oracle recomputes on its own."""
+    say("[level_estimate full-size sampled outcome]")
+    N, K, p, seed, delta = 16, 8, 0.05, 202, 0.05
+    eps = energy_grid(-9.0, 9.0, 401)
+    d_eps = torch.as_tensor(eps, device=DEV)
+    chunk = 16
+    need = B.mlmc_level_workspace(gdev, N, False, K, K, chunk, B.MLMC_PREC_FP64, eps.size)
+    work = torch.empty((need,), dtype=torch.uint8, device=DEV)
+    first = 1234
+    got = B.mlmc_level_estimate(gdev, N, False, p, K, K, 0, seed, first, 1, d_eps, delta, work=work).cpu().numpy()
+    want = oracle.level_estimate(glat, N, False, p, K, K, 0, seed, first, 1, eps, delta, 0)
+    compare_stats(got, want, 1, 1e-10)
+
+
+def test_determinism_and_batch_independence(B, gdev, glat):
+    say("[determinism]")
+    eps = torch.as_tensor(energy_grid(-9.0, 9.0, 101), device=DEV)
+    a = B.mlmc_level_estimate(gdev, 8, True, 0.1, 2, 4, 1, 9, 0, 10, eps, 0.1).cpu().numpy()
+    b = B.mlmc_level_estimate(gdev, 8, True, 0.1, 2, 4, 1, 9, 0, 10, eps, 0.1).cpu().numpy()
+    assert np.array_equal(a, b)
+    # eigenvalues of a unit do not depend on the other matrices of the batch
+    N = 12
+    mask = B.mlmc_sample_vacancies(gdev, N, 0.05, 1, gdev.tag(N), 0, 3)
+    kred, _ = B.mlmc_kgrid(0, 1)
+    H, n = B.mlmc_build_hamiltonians(gdev, N, mask, kred)
+    H2 = H[1:2].clone()
+    w = B.mlmc_batched_eigvalsh(H, n).cpu().numpy()
+    w2 = B.mlmc_batched_eigvalsh(H2, n[1:2].clone()).cpu().numpy()
+    assert np.array_equal(w[1], w2[0])
+
+
+def test_error_codes(B, gdev):
+    say("[error codes]")
+    eps = torch.as_tensor(energy_grid(-9.0, 9.0, 11), device=DEV)
+    with pytest.raises(B.MLMCError) as e:
+        B.mlmc_level_estimate(gdev, 5, True, 0.1, 1, 2, 1, 0, 0, 1, eps, 0.1)
+    assert e.value.status == B.MLMC_ERR_INVALID_ARG
+    small = torch.empty((16,), dtype=torch.uint8, device=DEV)
+    with pytest.raises(B.MLMCError) as e:
+        B.mlmc_level_estimate(gdev, 4, False, 0.1, 1, 1, 1, 0, 0, 1, eps, 0.1, work=small)
+    assert e.value.status == B.MLMC_ERR_WORKSPACE
+    with pytest.raises(B.MLMCError) as e:
+        B.mlmc_level_estimate(gdev, 64, False, 0.1, 1, 1, 1, 0, 0, 1, eps, 0.1)
+    assert e.value.status == B.MLMC_ERR_UNSUPPORTED
