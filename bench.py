@@ -123,7 +123,7 @@ def main():
     elapsed = time.perf_counter() - t0
     B.mlmc_timer_enable(False)
     kernels = {}
-    for name in ("sample_vacancies", "kgrid", "assemble", "small_fused", "tridiag_global", "bisect", "idos",
+    for name in ("sample_vacancies", "kgrid", "assemble", "small_fused", "tridiag", "bisect", "idos",
                  "level_stats"):
         ms, cnt = B.mlmc_timer_read(name)
         if cnt:
@@ -139,8 +139,8 @@ def main():
     flops = float(nk * np.sum(16.0 / 3.0 * n_per_sample.astype(np.float64) ** 3))
     dom = max(kernels, key=lambda k: kernels[k]["ms"]) if kernels else None
     roofline = None
-    if "tridiag_global" in kernels or "small_fused" in kernels:
-        kname = "tridiag_global" if "tridiag_global" in kernels else "small_fused"
+    if "tridiag" in kernels or "small_fused" in kernels:
+        kname = "tridiag" if "tridiag" in kernels else "small_fused"
         kms = kernels[kname]["ms"]
         achieved = flops / (kms * 1e-3) / 1e12
         peak = FP64_PEAK_TFLOPS if prec == B.MLMC_PREC_FP64 else FP32_PEAK_TFLOPS

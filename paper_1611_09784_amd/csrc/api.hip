@@ -112,8 +112,8 @@ void carve_large(Carver &cv, mlmc_precision prec, int64_t ld, int64_t units, boo
     if (with_H) b.H = cv.take<void>(cplx_bytes(prec) * (size_t)ld * (size_t)ld * (size_t)units);
     b.d = cv.take<double>(sizeof(double) * (size_t)ld * (size_t)units);
     b.e = cv.take<double>(sizeof(double) * (size_t)ld * (size_t)units);
-    const size_t pe = prec == MLMC_PREC_FP64 ? tridiag_global_partial_elems<double>(ld)
-                                             : tridiag_global_partial_elems<float>(ld);
+    const size_t pe = prec == MLMC_PREC_FP64 ? tridiag_batched_work_elems<double>(ld)
+                                             : tridiag_batched_work_elems<float>(ld);
     b.partial = cv.take<void>(cplx_bytes(prec) * pe * (size_t)units);
 }
 
@@ -121,11 +121,11 @@ void carve_large(Carver &cv, mlmc_precision prec, int64_t ld, int64_t units, boo
 mlmc_status run_large(mlmc_precision prec, void *H, int64_t ld, const int32_t *n, int64_t units, double *w, int64_t ldw,
                       const EigBuffers &b, hipStream_t s) {
     if (prec == MLMC_PREC_FP64)
-        LAUNCH("tridiag_global", s, launch_tridiag_global<double>(static_cast<cpx<double> *>(H), ld, n, units, b.d, b.e, ld,
-                                              static_cast<cpx<double> *>(b.partial), s));
+        LAUNCH("tridiag", s, launch_tridiag_batched<double>(static_cast<cpx<double> *>(H), ld, n, units, b.d, b.e, ld,
+                                                     static_cast<cpx<double> *>(b.partial), s));
     else
-        LAUNCH("tridiag_global", s, launch_tridiag_global<float>(static_cast<cpx<float> *>(H), ld, n, units, b.d, b.e, ld,
-                                             static_cast<cpx<float> *>(b.partial), s));
+        LAUNCH("tridiag", s, launch_tridiag_batched<float>(static_cast<cpx<float> *>(H), ld, n, units, b.d, b.e, ld,
+                                                    static_cast<cpx<float> *>(b.partial), s));
     LAUNCH("bisect", s, launch_bisect(b.d, b.e, ld, n, units, ld, w, ldw, s));
     return MLMC_OK;
 }
@@ -459,7 +459,7 @@ mlmc_status mlmc_level_estimate(mlmc_lattice lat, int32_t N, int32_t coupled, do
         return fail(MLMC_ERR_WORKSPACE, "level: workspace %zu < %zu bytes needed for one sample", work_bytes, one);
     const size_t two = level_layout(lat, N, cpl, Kf, Kc, 2, prec, n_eps, nullptr).bytes;
     const size_t per = two - one, fixed = one - per;
-    int64_t mc = (int64_t)((work_bytes - fixed) / per);
+    int64_t mc = (int64_t)((work_bytes - fixed) / per) + 2;  // padding makes the estimate approximate
     if (mc > M) mc = M;
     if (mc < 1) mc = 1;
     while (mc > 1 && level_layout(lat, N, cpl, Kf, Kc, mc, prec, n_eps, nullptr).bytes > work_bytes) --mc;

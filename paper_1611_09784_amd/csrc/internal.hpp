@@ -63,7 +63,7 @@ struct DevLattice {
 // Largest pristine matrix side handled by the LDS-resident fused kernel.
 constexpr int kSmallMaxF64 = 128;
 constexpr int kSmallMaxF32 = 180;
-// Largest matrix side of the device-memory reduction (LDS holds 3 vectors).
+// Largest matrix side of the device-memory reduction.
 constexpr int kLargeMaxF64 = 2048;
 constexpr int kLargeMaxF32 = 4096;
 // Gaussian smoothing is evaluated for |x| < kGaussCut and is exactly 0 / 1 beyond.
@@ -92,12 +92,13 @@ template <typename T>
 hipError_t launch_small_from_matrix(const cpx<T> *H, int64_t ld, const int32_t *n_in, int64_t batch, double *w,
                                     int64_t ldw, hipStream_t s);
 
-// Device-memory one-stage reduction (one workgroup per matrix) -> (d, e).
+// Batched blocked Householder reduction in device memory (lower triangle
+// only; all matrices advance column by column together) -> (d, e).
 template <typename T>
-hipError_t launch_tridiag_global(cpx<T> *H, int64_t ld, const int32_t *n_in, int64_t batch, double *d, double *e,
-                                 int64_t lde, cpx<T> *partial, hipStream_t s);
+hipError_t launch_tridiag_batched(cpx<T> *H, int64_t ld, const int32_t *n_in, int64_t batch, double *d, double *e,
+                                  int64_t lde, cpx<T> *work, hipStream_t s);
 template <typename T>
-size_t tridiag_global_partial_elems(int64_t ld);
+size_t tridiag_batched_work_elems(int64_t ld);
 
 // Sturm-count bisection of (d, e) -> ascending eigenvalues.
 hipError_t launch_bisect(const double *d, const double *e, int64_t lde, const int32_t *n_in, int64_t batch,
