@@ -154,9 +154,10 @@ __global__ __launch_bounds__(kMvWaves * 64) void matvec_kernel(const cpx<T> *__r
         colacc[t] = {T(0), T(0)};
     }
     cpx<T> *rp = w.rowpart + (int64_t)S * ld;
-    for (int I = (S * kStripCols) / kTileRows; I < nI; ++I) {
+    // Tiles are software-pipelined: the loads of tile I+1 are issued before
+    // tile I is reduced, so every wavefront keeps a tile in flight.
+    auto load_tile = [&](int I, cpx<T> (&a)[4][4], cpx<T> (&vr)[4]) {
         const int rbase = b0 + I * kTileRows;
-        cpx<T> a[4][4], vr[4], rowacc[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             const int c = cbase + lc + 4 * t;
@@ -170,8 +171,18 @@ __global__ __launch_bounds__(kMvWaves * 64) void matvec_kernel(const cpx<T> *__r
         for (int q = 0; q < 4; ++q) {
             const int r = rbase + lr + 16 * q;
             vr[q] = r < n ? v[r] : cpx<T>{T(0), T(0)};
-            rowacc[q] = {T(0), T(0)};
         }
+    };
+    int I = (S * kStripCols) / kTileRows;
+    cpx<T> a[4][4], vr[4];
+    load_tile(I, a, vr);
+    for (; I < nI; ++I) {
+        cpx<T> an[4][4], vrn[4];
+        if (I + 1 < nI) load_tile(I + 1, an, vrn);
+        const int rbase = b0 + I * kTileRows;
+        cpx<T> rowacc[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) rowacc[q] = {T(0), T(0)};
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             const int c = cbase + lc + 4 * t;
@@ -195,6 +206,12 @@ __global__ __launch_bounds__(kMvWaves * 64) void matvec_kernel(const cpx<T> *__r
                 const int r = rbase + lr + 16 * q;
                 if (r < n) rp[r] = rowacc[q];
             }
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            vr[t] = vrn[t];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) a[t][q] = an[t][q];
         }
     }
 #pragma unroll
@@ -246,6 +263,7 @@ __global__ __launch_bounds__(kSerThreads) void finish_kernel(const cpx<T> *__res
     for (int r = b0 + t; r < n; r += kSerThreads) {
         cpx<T> s = w.ycol[r];
         const int smax = (r - b0) / kStripCols;
+#pragma unroll 8
         for (int S = 0; S <= smax; ++S) s = c_add(s, w.rowpart[(int64_t)S * ld + r]);
 #pragma unroll 4
         for (int k = 0; k < i; ++k)
