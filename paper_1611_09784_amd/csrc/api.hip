@@ -112,8 +112,8 @@ void carve_large(Carver &cv, mlmc_precision prec, int64_t ld, int64_t units, boo
     if (with_H) b.H = cv.take<void>(cplx_bytes(prec) * (size_t)ld * (size_t)ld * (size_t)units);
     b.d = cv.take<double>(sizeof(double) * (size_t)ld * (size_t)units);
     b.e = cv.take<double>(sizeof(double) * (size_t)ld * (size_t)units);
-    const size_t pe = prec == MLMC_PREC_FP64 ? tridiag_batched_work_elems<double>(ld)
-                                             : tridiag_batched_work_elems<float>(ld);
+    const size_t pe = prec == MLMC_PREC_FP64 ? tridiag_twostage_work_elems<double>(ld)
+                                             : tridiag_twostage_work_elems<float>(ld);
     b.partial = cv.take<void>(cplx_bytes(prec) * pe * (size_t)units);
 }
 
@@ -121,10 +121,10 @@ void carve_large(Carver &cv, mlmc_precision prec, int64_t ld, int64_t units, boo
 mlmc_status run_large(mlmc_precision prec, void *H, int64_t ld, const int32_t *n, int64_t units, double *w, int64_t ldw,
                       const EigBuffers &b, hipStream_t s) {
     if (prec == MLMC_PREC_FP64)
-        LAUNCH("tridiag", s, launch_tridiag_batched<double>(static_cast<cpx<double> *>(H), ld, n, units, b.d, b.e, ld,
+        LAUNCH("tridiag", s, launch_tridiag_twostage<double>(static_cast<cpx<double> *>(H), ld, n, units, b.d, b.e, ld,
                                                      static_cast<cpx<double> *>(b.partial), s));
     else
-        LAUNCH("tridiag", s, launch_tridiag_batched<float>(static_cast<cpx<float> *>(H), ld, n, units, b.d, b.e, ld,
+        LAUNCH("tridiag", s, launch_tridiag_twostage<float>(static_cast<cpx<float> *>(H), ld, n, units, b.d, b.e, ld,
                                                     static_cast<cpx<float> *>(b.partial), s));
     LAUNCH("bisect", s, launch_bisect(b.d, b.e, ld, n, units, ld, w, ldw, s));
     return MLMC_OK;

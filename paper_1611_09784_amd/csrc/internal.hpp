@@ -100,6 +100,13 @@ hipError_t launch_tridiag_batched(cpx<T> *H, int64_t ld, const int32_t *n_in, in
 template <typename T>
 size_t tridiag_batched_work_elems(int64_t ld);
 
+// Two-stage reduction (dense -> band of half-width 16 -> tridiagonal) -> (d, e).
+template <typename T>
+hipError_t launch_tridiag_twostage(cpx<T> *H, int64_t ld, const int32_t *n_in, int64_t batch, double *d, double *e,
+                                   int64_t lde, cpx<T> *work, hipStream_t s);
+template <typename T>
+size_t tridiag_twostage_work_elems(int64_t ld);
+
 // Sturm-count bisection of (d, e) -> ascending eigenvalues.
 hipError_t launch_bisect(const double *d, const double *e, int64_t lde, const int32_t *n_in, int64_t batch,
                          int64_t ld_max, double *w, int64_t ldw, hipStream_t s);
