@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=250, help="samples per step")
-    ap.add_argument("--chunk", type=int, default=16, help="samples per internal pass (workspace size)")
+    ap.add_argument("--chunk", type=int, default=32, help="samples per internal pass (workspace size)")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--workload", default="graphene_n16_mc")
     ap.add_argument("--cpu-baseline", dest="cpu_baseline", action="store_true", default=True)

@@ -32,15 +32,16 @@ constexpr int kB = 16;                 // band half-width = panel width
 constexpr int kBandLd = 2 * kB + 1;    // stored sub-diagonals per column (incl. diagonal)
 constexpr int kQrThreads = 256;
 constexpr int kHemmRows = 64;
-constexpr int kHemmChunk = 64;
 constexpr int kWThreads = 256;
 constexpr int kUpdBlk = 64;
 
 // Per-matrix workspace (complex elements): V [kB][ld], X [kB][ld], W [kB][ld],
-// T [kB][kB], band [ld][kBandLd].
+// T [kB][kB], band [ld + 1][kBandLd].  The band's last column is a discard
+// slot: lanes with nothing to store write there, so that every store of a
+// block is issued unconditionally.
 template <typename T>
 size_t tridiag_twostage_work_elems(int64_t ld) {
-    return (size_t)(3 * kB) * (size_t)ld + (size_t)kB * kB + (size_t)kBandLd * (size_t)ld;
+    return (size_t)(3 * kB) * (size_t)ld + (size_t)kB * kB + (size_t)kBandLd * (size_t)(ld + 1);
 }
 
 template <typename T>
@@ -60,9 +61,129 @@ template <typename T>
 __device__ __forceinline__ cpx<T> shfl_c(cpx<T> a, int src) {
     return {__shfl(a.re, src, 64), __shfl(a.im, src, 64)};
 }
+
+// Cross-lane moves without the LDS crossbar.  A wavefront is four rows of 16
+// lanes.  Within a row: DPP quad permutations and the half-row / row mirrors.
+// Across rows: the permlane swaps, which exchange odd with even 16-lane rows
+// (16) or the upper with the lower 32 lanes (32) of two registers; swapping a
+// register with itself leaves each lane with its own word and its partner's.
+// Each op is applied to the 32-bit words of a float or double.
+template <int CTRL>
+__device__ __forceinline__ int dpp_word(int v) {
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x) {
+    return __int_as_float(dpp_word<CTRL>(__float_as_int(x)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = dpp_word<CTRL>((int)b), hi = dpp_word<CTRL>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+// Returns (own, partner) ordered as the swap leaves them in its two registers.
+template <bool ROWS32>
+__device__ __forceinline__ void swap_word(int v, int &a, int &b) {
+    if constexpr (ROWS32) {
+        const auto q = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        a = (int)q[0];
+        b = (int)q[1];
+    } else {
+        const auto q = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        a = (int)q[0];
+        b = (int)q[1];
+    }
+}
+template <bool ROWS32>
+__device__ __forceinline__ void swap_pair(float x, float &a, float &b) {
+    int ia, ib;
+    swap_word<ROWS32>(__float_as_int(x), ia, ib);
+    a = __int_as_float(ia);
+    b = __int_as_float(ib);
+}
+template <bool ROWS32>
+__device__ __forceinline__ void swap_pair(double x, double &a, double &b) {
+    const long long w = __double_as_longlong(x);
+    int alo, blo, ahi, bhi;
+    swap_word<ROWS32>((int)w, alo, blo);
+    swap_word<ROWS32>((int)(w >> 32), ahi, bhi);
+    a = __longlong_as_double(((long long)ahi << 32) | (unsigned)alo);
+    b = __longlong_as_double(((long long)bhi << 32) | (unsigned)blo);
+}
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141; // lane i <- 7 - i within each 8
+constexpr int kDppMirror = 0x140;     // lane i <- 15 - i within each 16
+
+// Sum over the 16 lanes of each row; every lane of the row gets the same bits
+// (each step adds a lane's value and its partner's, which are equal pairwise).
 template <typename T>
-__device__ __forceinline__ cpx<T> shfl_xor2(cpx<T> a, int m) {
-    return {__shfl_xor(a.re, m, 64), __shfl_xor(a.im, m, 64)};
+__device__ __forceinline__ T row_sum(T x) {
+    x += dpp<kDppXor1>(x);
+    x += dpp<kDppXor2>(x);
+    x += dpp<kDppHalfMirror>(x);
+    return x + dpp<kDppMirror>(x);
+}
+// Sum over the four rows at each lane position.
+template <typename T>
+__device__ __forceinline__ T col_sum(T x) {
+    T a, b;
+    swap_pair<false>(x, a, b);
+    x = a + b;
+    swap_pair<true>(x, a, b);
+    return a + b;
+}
+// Row 0's value at each lane position, in every row.
+template <typename T>
+__device__ __forceinline__ T from_row0(T x) {
+    T a, b;
+    swap_pair<false>(x, a, b);  // a: rows (0, 0, 2, 2)
+    swap_pair<true>(a, x, b);   // x: rows (0, 0, 0, 0)
+    return x;
+}
+template <typename T>
+__device__ __forceinline__ T lane0(T x);
+template <>
+__device__ __forceinline__ float lane0(float x) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 0));
+}
+template <>
+__device__ __forceinline__ double lane0(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)b, 0), hi = __builtin_amdgcn_readlane((int)(b >> 32), 0);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Matrix-core 16x16x4 products (D += A B, A 16x4, B 4x16).  Lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16]; slot v of lane l receives D[row][l % 16]
+// with row = 4v + l/16 for the f64 instruction and 4(l/16) + v for the f32 one.
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 mma(double a, double b, v4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int v) { return 4 * v + (lane >> 4); }
+};
+template <>
+struct Mfma<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 mma(float a, float b, v4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+// Complex accumulate D += a b on real matrix cores (four real products).
+template <typename T>
+__device__ __forceinline__ void cmma(cpx<T> a, cpx<T> b, typename Mfma<T>::v4 &dre, typename Mfma<T>::v4 &dim) {
+    dre = Mfma<T>::mma(a.re, b.re, dre);
+    dre = Mfma<T>::mma(-a.im, b.im, dre);
+    dim = Mfma<T>::mma(a.re, b.im, dim);
+    dim = Mfma<T>::mma(a.im, b.re, dim);
 }
 
 // Reflector of x (norm^2 nrm2, first entry x0): v0 = x0 - alpha with
@@ -143,8 +264,7 @@ __global__ __launch_bounds__(kQrThreads) void qr_panel_kernel(cpx<T> *__restrict
         }
 #pragma unroll
         for (int c = 0; c < kB; ++c) {
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) acc[c] = c_add(acc[c], shfl_xor2(acc[c], off));
+            acc[c] = {col_sum(row_sum(acc[c].re)), col_sum(row_sum(acc[c].im))};
             if (lane == 0) part[wid][c] = acc[c];
         }
         __syncthreads();
@@ -183,47 +303,63 @@ __global__ __launch_bounds__(kQrThreads) void qr_panel_kernel(cpx<T> *__restrict
 // Stage 1: X = A22 V.  One wavefront per 64 output rows; lane = row.
 // ---------------------------------------------------------------------------
 template <typename T>
+__device__ __forceinline__ cpx<T> herm_lower(const cpx<T> *A, int64_t ld, int r, int c) {  // A[r,c] from the lower triangle
+    if (c < r) return A[r + (int64_t)c * ld];
+    if (c > r) return c_conj(A[c + (int64_t)r * ld]);
+    return {A[r + (int64_t)r * ld].re, T(0)};
+}
+
+// X = A22 V on the matrix cores: one wavefront per 64 output rows (four
+// 16-row tiles) x 16 reflectors; each step consumes 4 columns of A22.
+template <typename T>
 __global__ __launch_bounds__(64) void hemm_kernel(const cpx<T> *__restrict__ Hall, int64_t ld,
-                                                  const int32_t *__restrict__ n_in, cpx<T> *__restrict__ wall,
-                                                  int64_t stride, int p) {
-    __shared__ cpx<T> sV[kHemmChunk][kB];
+                                                  const int32_t *__restrict__ n_in, const cpx<T> *__restrict__ Vall,
+                                                  cpx<T> *__restrict__ Xall, int64_t stride, int p) {
+    using v4 = typename Mfma<T>::v4;
     const int64_t u = blockIdx.x;
     const int n = n_in[u];
     const int s = p + kB, m = n - s;
     if (n < 0 || n > ld || m < 2) return;
     const int rb = s + blockIdx.y * kHemmRows;
     if (rb >= n) return;
-    const int lane = threadIdx.x;
-    const TwoView<T> w(wall, stride, ld, u);
+    const int lane = threadIdx.x, ii = lane & 15, kk = lane >> 4;
     const cpx<T> *A = Hall + u * ld * ld;
-    const int r = rb + lane;
-    const bool rowok = r < n;
-    cpx<T> acc[kB];
+    const cpx<T> *V = Vall + u * stride;
+    const cpx<T> zero = {T(0), T(0)};
+    v4 dre[4], dim[4];
 #pragma unroll
-    for (int k = 0; k < kB; ++k) acc[k] = {T(0), T(0)};
-    for (int cb = s; cb < n; cb += kHemmChunk) {
-        const int cn = min(kHemmChunk, n - cb);
-        __syncthreads();
-        for (int idx = lane; idx < kHemmChunk * kB; idx += 64) {
-            const int c = idx % kHemmChunk, k = idx / kHemmChunk;
-            sV[c][k] = c < cn ? w.V[(int64_t)k * ld + cb + c] : cpx<T>{T(0), T(0)};
-        }
-        __syncthreads();
-        if (!rowok) continue;
-        for (int cc = 0; cc < cn; ++cc) {
-            const int c = cb + cc;
-            cpx<T> a;
-            if (c < r) a = A[r + (int64_t)c * ld];            // stored lower part of row r
-            else if (c > r) a = c_conj(A[c + (int64_t)r * ld]);  // column r below the diagonal
-            else a = {A[r + (int64_t)r * ld].re, T(0)};
-#pragma unroll
-            for (int k = 0; k < kB; ++k) acc[k] = c_add(acc[k], c_mul(a, sV[cc][k]));
-        }
+    for (int t = 0; t < 4; ++t) {
+        dre[t] = v4{T(0), T(0), T(0), T(0)};
+        dim[t] = v4{T(0), T(0), T(0), T(0)};
     }
-    if (rowok) {
+    auto fetch = [&](int c0, cpx<T> (&a)[4], cpx<T> &vb) {
+        const int c = c0 + kk;
+        vb = c < n ? V[(int64_t)ii * ld + c] : zero;
 #pragma unroll
-        for (int k = 0; k < kB; ++k) w.X[(int64_t)k * ld + r] = acc[k];
+        for (int t = 0; t < 4; ++t) {
+            const int r = rb + 16 * t + ii;
+            a[t] = (r < n && c < n) ? herm_lower(A, ld, r, c) : zero;
+        }
+    };
+    cpx<T> a[4], vb;
+    fetch(s, a, vb);
+    for (int c0 = s; c0 < n; c0 += 4) {
+        cpx<T> an[4], vbn;
+        if (c0 + 4 < n) fetch(c0 + 4, an, vbn);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) cmma<T>(a[t], vb, dre[t], dim[t]);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) a[t] = an[t];
+        vb = vbn;
     }
+    cpx<T> *X = Xall + u * stride;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = rb + 16 * t + Mfma<T>::row(lane, v);
+            if (r < n) X[(int64_t)ii * ld + r] = {dre[t][v], dim[t][v]};
+        }
 }
 
 // ---------------------------------------------------------------------------
@@ -335,40 +471,38 @@ __global__ __launch_bounds__(256) void band_update_kernel(cpx<T> *__restrict__ H
     __syncthreads();
     const int cs = cb + wid * 16;
     if (cs >= n || cs > rb + kUpdBlk - 1) return;
-    const int lr = lane & 15, lc = lane >> 4;
-    cpx<T> acc[4][4];
+    // (V W^H + W V^H)[r, c] = sum_k P[r, k] conj(Q[c, k]) with P = [V W], Q = [W V]
+    // (k < 2 kB).  The matrix cores compute the transposed tile
+    // D[c][r] = sum_k conj(Q[c, k]) P[r, k] so that the lane-fast index of the
+    // result is the row r of A (coalesced column-major read-modify-write).
+    using v4 = typename Mfma<T>::v4;
+    const int ii = lane & 15, kk = lane >> 4;
+    v4 dre[4], dim[4];
 #pragma unroll
-    for (int tt = 0; tt < 4; ++tt)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[tt][q] = {T(0), T(0)};
-    for (int k = 0; k < kB; ++k) {
-        cpx<T> vr[4], wr[4], vc[4], wc[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            vr[q] = sVr[k][lr + 16 * q];
-            wr[q] = sWr[k][lr + 16 * q];
-        }
+    for (int tt = 0; tt < 4; ++tt) {
+        dre[tt] = v4{T(0), T(0), T(0), T(0)};
+        dim[tt] = v4{T(0), T(0), T(0), T(0)};
+    }
+#pragma unroll 2
+    for (int k0 = 0; k0 < 2 * kB; k0 += 4) {
+        const int k = k0 + kk;
+        const cpx<T> a = c_conj((k < kB) ? sWc[k][wid * 16 + ii] : sVc[k - kB][wid * 16 + ii]);
 #pragma unroll
         for (int tt = 0; tt < 4; ++tt) {
-            vc[tt] = sVc[k][wid * 16 + lc + 4 * tt];
-            wc[tt] = sWc[k][wid * 16 + lc + 4 * tt];
+            const cpx<T> b = (k < kB) ? sVr[k][16 * tt + ii] : sWr[k - kB][16 * tt + ii];
+            cmma<T>(a, b, dre[tt], dim[tt]);
         }
-#pragma unroll
-        for (int tt = 0; tt < 4; ++tt)
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                acc[tt][q] = c_add(acc[tt][q], c_add(c_mulc(vr[q], wc[tt]), c_mulc(wr[q], vc[tt])));
     }
     cpx<T> *A = Hall + u * ld * ld;
 #pragma unroll
     for (int tt = 0; tt < 4; ++tt) {
-        const int c = cs + lc + 4 * tt;
+        const int r = rb + 16 * tt + ii;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int r = rb + lr + 16 * q;
+        for (int v = 0; v < 4; ++v) {
+            const int c = cs + Mfma<T>::row(lane, v);
             if (r < n && c < n && r >= c) {
-                cpx<T> &a = A[r + (int64_t)c * ld];
-                a = c_sub(a, acc[tt][q]);
+                cpx<T> &x = A[r + (int64_t)c * ld];
+                x = c_sub(x, cpx<T>{dre[tt][v], dim[tt][v]});
             }
         }
     }
@@ -388,44 +522,65 @@ __device__ __forceinline__ cpx<T> band_get(const cpx<T> *band, int row, int col)
     return band[(int64_t)col * kBandLd + (row - col)];
 }
 
-// Load A[r0 + r, c0 + c] (r < nrow, c < ncol) where every such element lies
+// Block loads are split into a raw load (every lane loads from a valid
+// address, masked lanes from element 0) and a fix-up (mask, conjugation)
+// applied where the block is first used, so that a prefetch stays in flight
+// across the current step's arithmetic instead of being waited for at once.
+// Raw load of A[r0 + r, c0 + c] (r < nrow, c < ncol); every such element lies
 // on or below the diagonal and within the stored band.
 template <typename T>
-__device__ __forceinline__ void load_blk(const cpx<T> *band, int r0, int c0, int nrow, int ncol, Blk<T> &b) {
+__device__ __forceinline__ void load_blk_raw(const cpx<T> *band, int r0, int c0, int nrow, int ncol, Blk<T> &b) {
     const int lane = threadIdx.x, r = lane & 15, g = lane >> 4;
 #pragma unroll
     for (int tt = 0; tt < 4; ++tt) {
         const int c = g + 4 * tt;
-        b.e[tt] = (r < nrow && c < ncol) ? band_get(band, r0 + r, c0 + c) : cpx<T>{T(0), T(0)};
+        const bool ok = r < nrow && c < ncol;
+        const int64_t idx = ok ? (int64_t)(c0 + c) * kBandLd + (r0 + r - c0 - c) : 0;
+        b.e[tt] = band[idx];
     }
 }
-// Hermitian diagonal block A[r0.., r0..] of size L from its lower part.
 template <typename T>
-__device__ __forceinline__ void load_diag(const cpx<T> *band, int r0, int L, Blk<T> &b) {
+__device__ __forceinline__ void fix_blk(int nrow, int ncol, Blk<T> &b) {
+    const int lane = threadIdx.x, r = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt) {
+        const bool ok = r < nrow && g + 4 * tt < ncol;
+        if (!ok) b.e[tt] = {T(0), T(0)};
+    }
+}
+// Raw load of the Hermitian diagonal block A[r0.., r0..] of size L: every
+// lane loads the stored (lower) element of its mirrored position.
+template <typename T>
+__device__ __forceinline__ void load_diag_raw(const cpx<T> *band, int r0, int L, Blk<T> &b) {
     const int lane = threadIdx.x, r = lane & 15, g = lane >> 4;
 #pragma unroll
     for (int tt = 0; tt < 4; ++tt) {
         const int c = g + 4 * tt;
-        cpx<T> x = {T(0), T(0)};
-        if (r < L && c < L) {
-            if (r > c) x = band_get(band, r0 + r, r0 + c);
-            else if (r < c) x = c_conj(band_get(band, r0 + c, r0 + r));
-            else x = {band_get(band, r0 + r, r0 + r).re, T(0)};
-        }
-        b.e[tt] = x;
+        const bool ok = r < L && c < L;
+        const int hi = r > c ? r : c, lo = r > c ? c : r;
+        const int64_t idx = ok ? (int64_t)(r0 + lo) * kBandLd + (hi - lo) : 0;
+        b.e[tt] = band[idx];
+    }
+}
+template <typename T>
+__device__ __forceinline__ void fix_diag(int L, Blk<T> &b) {
+    const int lane = threadIdx.x, r = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt) {
+        const int c = g + 4 * tt;
+        const cpx<T> x = b.e[tt];
+        const T im = (r == c) ? T(0) : ((r < c) ? -x.im : x.im);
+        b.e[tt] = (r < L && c < L) ? cpx<T>{x.re, im} : cpx<T>{T(0), T(0)};
     }
 }
 
 template <typename T>
 __device__ __forceinline__ cpx<T> sum16(cpx<T> x) {  // over the 16 row lanes of a column group
-#pragma unroll
-    for (int off = 1; off < 16; off <<= 1) x = c_add(x, shfl_xor2(x, off));
-    return x;
+    return {row_sum(x.re), row_sum(x.im)};
 }
 template <typename T>
 __device__ __forceinline__ cpx<T> sum4g(cpx<T> x) {  // over the 4 column groups of a row
-    x = c_add(x, shfl_xor2(x, 16));
-    return c_add(x, shfl_xor2(x, 32));
+    return {col_sum(x.re), col_sum(x.im)};
 }
 
 template <typename T>
@@ -445,6 +600,7 @@ __global__ __launch_bounds__(64) void chase_kernel(const cpx<T> *__restrict__ Ha
     const TwoView<T> w(wall, stride, ld, u);
     cpx<T> *band = w.band;
     const cpx<T> *A = Hall + u * ld * ld;
+    const int64_t discard = ld * kBandLd;
     for (int64_t q = lane; q < (int64_t)n * kBandLd; q += 64) {
         const int c = (int)(q / kBandLd), o = (int)(q % kBandLd);
         band[q] = (o <= kB && c + o < n) ? A[(c + o) + (int64_t)c * ld] : cpx<T>{T(0), T(0)};
@@ -456,33 +612,34 @@ __global__ __launch_bounds__(64) void chase_kernel(const cpx<T> *__restrict__ Ha
         if (L < 2) continue;
         // Step 0: the "previous block" is column j itself: B = A[lo..hi, j].
         Blk<T> B, D, E;
-        load_blk(band, lo, j, L, 1, B);
+        int lo1 = hi + 1, hi1 = min(hi + kB, n - 1), L1 = hi1 - lo1 + 1;
+        load_blk_raw(band, lo, j, L, 1, B);
+        load_diag_raw(band, lo, L, D);
+        load_blk_raw(band, lo1, lo, L1, L, E);
+        fix_blk(L, 1, B);
+        fix_diag(L, D);
+        fix_blk(L1, L, E);
         int col0 = j;  // first column of the block B
         int Lprev = 1;
-        D = {};
-        E = {};
-        load_diag(band, lo, L, D);
-        int lo1 = hi + 1, hi1 = min(hi + kB, n - 1), L1 = hi1 - lo1 + 1;
-        if (L1 > 0) load_blk(band, lo1, lo, L1, L, E);
         while (true) {
             // reflector from the first column of B (held by column group 0, tt = 0)
-            const cpx<T> xr = (g == 0 && r < L) ? B.e[0] : cpx<T>{T(0), T(0)};
-            const double nrm2 = (double)sum16(cpx<T>{c_abs2(xr), T(0)}).re;
-            const double nrm2_all = __shfl((double)nrm2, 0, 64);
-            const cpx<T> x0 = shfl_c(B.e[0], 0);
+            const cpx<T> xr = (r < L) ? B.e[0] : cpx<T>{T(0), T(0)};
+            const double nrm2 = (double)lane0(row_sum(c_abs2(xr)));
+            const cpx<T> x0 = {lane0(B.e[0].re), lane0(B.e[0].im)};
             T tau;
             cpx<T> v0, alpha;
-            make_reflector<T>(nrm2_all, x0, tau, v0, alpha);
-            const cpx<T> xsrc = shfl_c(B.e[0], r);  // every lane takes row r of B's first column
+            make_reflector<T>(nrm2, x0, tau, v0, alpha);
+            // every lane takes row r of B's first column (held by row group 0)
+            const cpx<T> xsrc = {from_row0(B.e[0].re), from_row0(B.e[0].im)};
             const cpx<T> vr = (r == 0) ? v0 : ((r < L) ? xsrc : cpx<T>{T(0), T(0)});
             cpx<T> vcol[4];
 #pragma unroll
             for (int tt = 0; tt < 4; ++tt) vcol[tt] = shfl_c(vr, g + 4 * tt);  // v at this lane's columns
             // prefetch the next step's diagonal block and block below (disjoint from this step's writes)
             const int lo2 = hi1 + 1, hi2 = min(hi1 + kB, n - 1), L2 = hi2 - lo2 + 1;
-            Blk<T> Dn = {}, En = {};
-            if (L1 > 0) load_diag(band, lo1, L1, Dn);
-            if (L1 > 0 && L2 > 0) load_blk(band, lo2, lo1, L2, L1, En);
+            Blk<T> Dn, En;
+            load_diag_raw(band, lo1, L1, Dn);
+            load_blk_raw(band, lo2, lo1, L2, L1, En);
             // B <- H B
 #pragma unroll
             for (int tt = 0; tt < 4; ++tt) {
@@ -517,8 +674,9 @@ __global__ __launch_bounds__(64) void chase_kernel(const cpx<T> *__restrict__ Ha
 #pragma unroll
             for (int tt = 0; tt < 4; ++tt) {
                 const int c = g + 4 * tt;
-                if (r < L && c < Lprev) band[(int64_t)(col0 + c) * kBandLd + (lo + r - col0 - c)] = B.e[tt];
-                if (r < L && c < L && r >= c) band[(int64_t)(lo + c) * kBandLd + (r - c)] = D.e[tt];
+                const bool okb = r < L && c < Lprev, okd = r < L && c < L && r >= c;
+                band[okb ? (int64_t)(col0 + c) * kBandLd + (lo + r - col0 - c) : discard] = B.e[tt];
+                band[okd ? (int64_t)(lo + c) * kBandLd + (r - c) : discard] = D.e[tt];
             }
             if (L1 < 2) {  // nothing left to chase (a 1-row block needs no annihilation)
                 if (L1 == 1) {
@@ -534,6 +692,8 @@ __global__ __launch_bounds__(64) void chase_kernel(const cpx<T> *__restrict__ Ha
             B = E;
             D = Dn;
             E = En;
+            fix_diag(L1, D);
+            fix_blk(L2, L1, E);
             col0 = lo;
             Lprev = L;
             lo = lo1;
@@ -562,7 +722,7 @@ hipError_t launch_tridiag_twostage(cpx<T> *H, int64_t ld, const int32_t *n_in, i
         const int64_t mmax = ld - p - kB;
         hipLaunchKernelGGL(qr_panel_kernel<T>, dim3(B), dim3(kQrThreads), 0, s, H, ld, n_in, work, stride, p);
         hipLaunchKernelGGL(hemm_kernel<T>, dim3(B, (unsigned)((mmax + kHemmRows - 1) / kHemmRows)), dim3(64), 0, s, H,
-                           ld, n_in, work, stride, p);
+                           ld, n_in, work, work + (int64_t)kB * ld, stride, p);
         hipLaunchKernelGGL(wfactor_kernel<T>, dim3(B), dim3(kWThreads), 0, s, n_in, ld, work, stride, p);
         const unsigned nblk = (unsigned)((mmax + kUpdBlk - 1) / kUpdBlk);
         hipLaunchKernelGGL(band_update_kernel<T>, dim3(B, nblk, nblk), dim3(256), 0, s, H, ld, n_in, work, stride, p);
