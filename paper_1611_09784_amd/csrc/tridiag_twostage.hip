@@ -57,6 +57,21 @@ struct TwoView {
     }
 };
 
+// Workgroups are dispatched round-robin over the chip's 8 XCDs (each with its
+// own L2).  Kernels with several workgroups per matrix take their (matrix,
+// tile) from the linear workgroup id so that all tiles of a matrix run on one
+// XCD back to back and share its V / W panels in that L2:
+// XCD x = w % 8 processes matrices x, x + 8, ... tile by tile.
+constexpr int kXcds = 8;
+__device__ __forceinline__ void xcd_tile(int64_t w, int64_t tiles, int64_t &u, int64_t &tile) {
+    const int64_t x = w % kXcds, k = w / kXcds;
+    u = x + kXcds * (k / tiles);
+    tile = k % tiles;
+}
+inline unsigned xcd_grid(int64_t batch, int64_t tiles) {
+    return (unsigned)(kXcds * ((batch + kXcds - 1) / kXcds) * tiles);
+}
+
 template <typename T>
 __device__ __forceinline__ cpx<T> shfl_c(cpx<T> a, int src) {
     return {__shfl(a.re, src, 64), __shfl(a.im, src, 64)};
@@ -309,18 +324,51 @@ __device__ __forceinline__ cpx<T> herm_lower(const cpx<T> *A, int64_t ld, int r,
     return {A[r + (int64_t)r * ld].re, T(0)};
 }
 
+// Raw operand loads of one hemm step (columns c0 .. c0 + 3) and their fix-up.
+// Offsets are 32-bit (ld * ld fits) and selects are per real component, so
+// that the loads are straight-line code.
+template <typename T>
+__device__ __forceinline__ void hemm_fetch(const cpx<T> *A, const cpx<T> *V, int ld, int n, int rb, int c0,
+                                           cpx<T> (&a)[4], cpx<T> &vb) {
+    const int lane = threadIdx.x, ii = lane & 15, c = c0 + (lane >> 4);
+    vb = V[c < n ? ii * ld + c : 0];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int r = rb + 16 * t + ii;
+        const int hi = r > c ? r : c, lo = r > c ? c : r;
+        a[t] = A[(r < n && c < n) ? hi + lo * ld : 0];
+    }
+}
+template <typename T>
+__device__ __forceinline__ void hemm_fix(int n, int rb, int c0, cpx<T> (&a)[4], cpx<T> &vb) {
+    const int lane = threadIdx.x, ii = lane & 15, c = c0 + (lane >> 4);
+    vb.re = c < n ? vb.re : T(0);
+    vb.im = c < n ? vb.im : T(0);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int r = rb + 16 * t + ii;
+        const bool ok = r < n && c < n;
+        const T re = a[t].re, im = a[t].im;
+        a[t].re = ok ? re : T(0);
+        a[t].im = (ok && c != r) ? (c > r ? -im : im) : T(0);
+    }
+}
+
 // X = A22 V on the matrix cores: one wavefront per 64 output rows (four
 // 16-row tiles) x 16 reflectors; each step consumes 4 columns of A22.
 template <typename T>
 __global__ __launch_bounds__(64) void hemm_kernel(const cpx<T> *__restrict__ Hall, int64_t ld,
                                                   const int32_t *__restrict__ n_in, const cpx<T> *__restrict__ Vall,
-                                                  cpx<T> *__restrict__ Xall, int64_t stride, int p) {
+                                                  cpx<T> *__restrict__ Xall, int64_t stride, int p,
+                                                  int64_t batch, int64_t tiles) {
     using v4 = typename Mfma<T>::v4;
-    const int64_t u = blockIdx.x;
+    int64_t u, tile;
+    xcd_tile(blockIdx.x, tiles, u, tile);
+    if (u >= batch) return;
     const int n = n_in[u];
     const int s = p + kB, m = n - s;
     if (n < 0 || n > ld || m < 2) return;
-    const int rb = s + blockIdx.y * kHemmRows;
+    const int rb = s + (int)tile * kHemmRows;
     if (rb >= n) return;
     const int lane = threadIdx.x, ii = lane & 15, kk = lane >> 4;
     const cpx<T> *A = Hall + u * ld * ld;
@@ -332,25 +380,28 @@ __global__ __launch_bounds__(64) void hemm_kernel(const cpx<T> *__restrict__ Hal
         dre[t] = v4{T(0), T(0), T(0), T(0)};
         dim[t] = v4{T(0), T(0), T(0), T(0)};
     }
-    auto fetch = [&](int c0, cpx<T> (&a)[4], cpx<T> &vb) {
-        const int c = c0 + kk;
-        vb = c < n ? V[(int64_t)ii * ld + c] : zero;
+    // Raw loads (every lane loads from a valid address: the stored lower
+    // element of its position, element 0 when outside the matrix) are issued
+    // one step ahead; the fix-up (mask, conjugation of mirrored elements,
+    // real diagonal) happens at use, so no load is waited for early.
+    // Two register sets in ping-pong.  The empty asm with a memory clobber
+    // after each prefetch keeps the compiler from turning the loop-carried
+    // loaded values into loop-carried addresses (which would move the loads
+    // down to their use).
+    cpx<T> a0[4], a1[4], b0, b1;
+    const int ldi = (int)ld;
+    hemm_fetch(A, V, ldi, n, rb, s, a0, b0);
+    for (int c0 = s; c0 < n; c0 += 8) {
+        hemm_fetch(A, V, ldi, n, rb, c0 + 4, a1, b1);
+        asm volatile("" ::: "memory");
+        hemm_fix(n, rb, c0, a0, b0);
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int r = rb + 16 * t + ii;
-            a[t] = (r < n && c < n) ? herm_lower(A, ld, r, c) : zero;
-        }
-    };
-    cpx<T> a[4], vb;
-    fetch(s, a, vb);
-    for (int c0 = s; c0 < n; c0 += 4) {
-        cpx<T> an[4], vbn;
-        if (c0 + 4 < n) fetch(c0 + 4, an, vbn);
+        for (int t = 0; t < 4; ++t) cmma<T>(a0[t], b0, dre[t], dim[t]);
+        hemm_fetch(A, V, ldi, n, rb, c0 + 8, a0, b0);
+        asm volatile("" ::: "memory");
+        hemm_fix(n, rb, c0 + 4, a1, b1);
 #pragma unroll
-        for (int t = 0; t < 4; ++t) cmma<T>(a[t], vb, dre[t], dim[t]);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) a[t] = an[t];
-        vb = vbn;
+        for (int t = 0; t < 4; ++t) cmma<T>(a1[t], b1, dre[t], dim[t]);
     }
     cpx<T> *X = Xall + u * stride;
 #pragma unroll
@@ -449,34 +500,69 @@ __global__ __launch_bounds__(kWThreads) void wfactor_kernel(const int32_t *__res
 template <typename T>
 __global__ __launch_bounds__(256) void band_update_kernel(cpx<T> *__restrict__ Hall, int64_t ld,
                                                           const int32_t *__restrict__ n_in, cpx<T> *__restrict__ wall,
-                                                          int64_t stride, int p) {
+                                                          int64_t stride, int p, int64_t batch, int64_t tiles) {
     __shared__ cpx<T> sVr[kB][kUpdBlk], sWr[kB][kUpdBlk], sVc[kB][kUpdBlk], sWc[kB][kUpdBlk];
-    const int64_t u = blockIdx.x;
+    int64_t u, tile;
+    xcd_tile(blockIdx.x, tiles, u, tile);
+    if (u >= batch) return;
     const int n = n_in[u];
     const int s = p + kB;
     if (n < 0 || n > ld || n - s < 2) return;
-    const int rb = s + blockIdx.y * kUpdBlk, cb = s + blockIdx.z * kUpdBlk;
+    // lower-triangle tile (bi, bj), bj <= bi, from tile = bi (bi + 1) / 2 + bj
+    int bi = (int)((sqrt(8.0 * (double)tile + 1.0) - 1.0) * 0.5);
+    while ((int64_t)bi * (bi + 1) / 2 > tile) --bi;
+    while ((int64_t)(bi + 1) * (bi + 2) / 2 <= tile) ++bi;
+    const int bj = (int)(tile - (int64_t)bi * (bi + 1) / 2);
+    const int rb = s + bi * kUpdBlk, cb = s + bj * kUpdBlk;
     if (rb >= n || cb > rb + kUpdBlk - 1) return;
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+    const int ii = lane & 15, kk = lane >> 4;
     const TwoView<T> w(wall, stride, ld, u);
-    for (int idx = t; idx < kB * kUpdBlk; idx += 256) {
-        const int k = idx / kUpdBlk, l = idx % kUpdBlk;
+    const int ldi = (int)ld;
+    // Stage the V, W strips of the tile's rows and columns (straight-line
+    // loads, out-of-range entries read element 0 and are zeroed at the store).
+    constexpr int kFill = kB * kUpdBlk / 256;
+    cpx<T> fv[kFill][4];
+#pragma unroll
+    for (int q = 0; q < kFill; ++q) {
+        const int idx = t + 256 * q, k = idx / kUpdBlk, l = idx % kUpdBlk;
         const int r = rb + l, c = cb + l;
-        const cpx<T> zero = {T(0), T(0)};
-        sVr[k][l] = r < n ? w.V[(int64_t)k * ld + r] : zero;
-        sWr[k][l] = r < n ? w.W[(int64_t)k * ld + r] : zero;
-        sVc[k][l] = c < n ? w.V[(int64_t)k * ld + c] : zero;
-        sWc[k][l] = c < n ? w.W[(int64_t)k * ld + c] : zero;
+        fv[q][0] = w.V[r < n ? k * ldi + r : 0];
+        fv[q][1] = w.W[r < n ? k * ldi + r : 0];
+        fv[q][2] = w.V[c < n ? k * ldi + c : 0];
+        fv[q][3] = w.W[c < n ? k * ldi + c : 0];
+    }
+    // This wave's part of the tile: rows rb + 16 tt + ii, columns cs + row(lane, v),
+    // loaded now so that the loads are in flight during the products.
+    const int cs = cb + wid * 16;
+    cpx<T> *A = Hall + u * ld * ld;
+    cpx<T> x[4][4];
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt) {
+        const int r = rb + 16 * tt + ii;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int c = cs + Mfma<T>::row(lane, v);
+            x[tt][v] = A[(r < n && c < n && r >= c) ? r + c * ldi : 0];
+        }
+    }
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int q = 0; q < kFill; ++q) {
+        const int idx = t + 256 * q, k = idx / kUpdBlk, l = idx % kUpdBlk;
+        const bool okr = rb + l < n, okc = cb + l < n;
+        sVr[k][l] = {okr ? fv[q][0].re : T(0), okr ? fv[q][0].im : T(0)};
+        sWr[k][l] = {okr ? fv[q][1].re : T(0), okr ? fv[q][1].im : T(0)};
+        sVc[k][l] = {okc ? fv[q][2].re : T(0), okc ? fv[q][2].im : T(0)};
+        sWc[k][l] = {okc ? fv[q][3].re : T(0), okc ? fv[q][3].im : T(0)};
     }
     __syncthreads();
-    const int cs = cb + wid * 16;
     if (cs >= n || cs > rb + kUpdBlk - 1) return;
     // (V W^H + W V^H)[r, c] = sum_k P[r, k] conj(Q[c, k]) with P = [V W], Q = [W V]
     // (k < 2 kB).  The matrix cores compute the transposed tile
     // D[c][r] = sum_k conj(Q[c, k]) P[r, k] so that the lane-fast index of the
     // result is the row r of A (coalesced column-major read-modify-write).
     using v4 = typename Mfma<T>::v4;
-    const int ii = lane & 15, kk = lane >> 4;
     v4 dre[4], dim[4];
 #pragma unroll
     for (int tt = 0; tt < 4; ++tt) {
@@ -493,17 +579,13 @@ __global__ __launch_bounds__(256) void band_update_kernel(cpx<T> *__restrict__ H
             cmma<T>(a, b, dre[tt], dim[tt]);
         }
     }
-    cpx<T> *A = Hall + u * ld * ld;
 #pragma unroll
     for (int tt = 0; tt < 4; ++tt) {
         const int r = rb + 16 * tt + ii;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int c = cs + Mfma<T>::row(lane, v);
-            if (r < n && c < n && r >= c) {
-                cpx<T> &x = A[r + (int64_t)c * ld];
-                x = c_sub(x, cpx<T>{dre[tt][v], dim[tt][v]});
-            }
+            if (r < n && c < n && r >= c) A[r + c * ldi] = c_sub(x[tt][v], cpx<T>{dre[tt][v], dim[tt][v]});
         }
     }
 }
@@ -721,11 +803,13 @@ hipError_t launch_tridiag_twostage(cpx<T> *H, int64_t ld, const int32_t *n_in, i
     for (int p = 0; p + kB + 1 < ld; p += kB) {
         const int64_t mmax = ld - p - kB;
         hipLaunchKernelGGL(qr_panel_kernel<T>, dim3(B), dim3(kQrThreads), 0, s, H, ld, n_in, work, stride, p);
-        hipLaunchKernelGGL(hemm_kernel<T>, dim3(B, (unsigned)((mmax + kHemmRows - 1) / kHemmRows)), dim3(64), 0, s, H,
-                           ld, n_in, work, work + (int64_t)kB * ld, stride, p);
+        const int64_t hrows = (mmax + kHemmRows - 1) / kHemmRows;
+        hipLaunchKernelGGL(hemm_kernel<T>, dim3(xcd_grid(batch, hrows)), dim3(64), 0, s, H, ld, n_in, work,
+                           work + (int64_t)kB * ld, stride, p, batch, hrows);
         hipLaunchKernelGGL(wfactor_kernel<T>, dim3(B), dim3(kWThreads), 0, s, n_in, ld, work, stride, p);
-        const unsigned nblk = (unsigned)((mmax + kUpdBlk - 1) / kUpdBlk);
-        hipLaunchKernelGGL(band_update_kernel<T>, dim3(B, nblk, nblk), dim3(256), 0, s, H, ld, n_in, work, stride, p);
+        const int64_t nblk = (mmax + kUpdBlk - 1) / kUpdBlk, ntile = nblk * (nblk + 1) / 2;
+        hipLaunchKernelGGL(band_update_kernel<T>, dim3(xcd_grid(batch, ntile)), dim3(256), 0, s, H, ld, n_in, work,
+                           stride, p, batch, ntile);
         const hipError_t err = hipGetLastError();
         if (err != hipSuccess) return err;
     }
