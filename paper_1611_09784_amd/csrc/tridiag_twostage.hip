@@ -24,6 +24,8 @@
 // so on down the band (bulge chasing).  Each 16 x 16 block lives in registers
 // (16 row lanes x 4 column lanes, 4 columns per lane); the next step's blocks
 // are prefetched while the current one is processed.
+#include <utility>
+
 #include "device_common.hpp"
 
 namespace mlmc {
@@ -70,6 +72,13 @@ __device__ __forceinline__ void xcd_tile(int64_t w, int64_t tiles, int64_t &u, i
 }
 inline unsigned xcd_grid(int64_t batch, int64_t tiles) {
     return (unsigned)(kXcds * ((batch + kXcds - 1) / kXcds) * tiles);
+}
+
+// Componentwise select (a select of whole structs can become a select of
+// their addresses, which forces register arrays into scratch memory).
+template <typename T>
+__device__ __forceinline__ cpx<T> csel(bool c, cpx<T> a, cpx<T> b) {
+    return {c ? a.re : b.re, c ? a.im : b.im};
 }
 
 template <typename T>
@@ -168,6 +177,69 @@ __device__ __forceinline__ double lane0(double x) {
     const long long b = __double_as_longlong(x);
     const int lo = __builtin_amdgcn_readlane((int)b, 0), hi = __builtin_amdgcn_readlane((int)(b >> 32), 0);
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Two-register permlane swap: returns (vdst, src0) after the swap of a
+// (as vdst) and b (as src0); their sum leaves a reduced over the lane pair in
+// the even rows (lower half) and b in the odd rows (upper half).
+template <bool ROWS32>
+__device__ __forceinline__ void swap2_word(int a, int b, int &oa, int &ob) {
+    if constexpr (ROWS32) {
+        const auto q = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+        oa = (int)q[0];
+        ob = (int)q[1];
+    } else {
+        const auto q = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+        oa = (int)q[0];
+        ob = (int)q[1];
+    }
+}
+template <bool ROWS32>
+__device__ __forceinline__ float swap_sum(float a, float b) {
+    int oa, ob;
+    swap2_word<ROWS32>(__float_as_int(a), __float_as_int(b), oa, ob);
+    return __int_as_float(oa) + __int_as_float(ob);
+}
+template <bool ROWS32>
+__device__ __forceinline__ double swap_sum(double a, double b) {
+    const long long wa = __double_as_longlong(a), wb = __double_as_longlong(b);
+    int alo, blo, ahi, bhi;
+    swap2_word<ROWS32>((int)wa, (int)wb, alo, blo);
+    swap2_word<ROWS32>((int)(wa >> 32), (int)(wb >> 32), ahi, bhi);
+    return __longlong_as_double(((long long)ahi << 32) | (unsigned)alo) +
+           __longlong_as_double(((long long)bhi << 32) | (unsigned)blo);
+}
+// One halving step of a reduce-scatter within rows: lanes with bit B clear
+// keep element j, the others element j + H; each adds its partner's copy
+// (the partner lane is given by the DPP pattern, whose pairs differ in bit B).
+template <int CTRL, int B, typename T>
+__device__ __forceinline__ T keep_send_sum(T lo, T hi) {
+    const bool upper = (threadIdx.x >> B) & 1;
+    const T keep = upper ? hi : lo, send = upper ? lo : hi;
+    return keep + dpp<CTRL>(send);
+}
+// Reduce-scatter of 32 values over the 64 lanes of a wavefront: afterwards
+// lane l holds the sum over all lanes of element
+// e(l) = 16 b5 + 8 b4 + 4 b3 + 2 b2 + b1 (b_k = bit k of l).  The pairing of
+// each step is fixed, so every run and both lanes holding an element get the
+// same bits.
+__device__ __forceinline__ int scatter_elem(int lane) {
+    return 16 * ((lane >> 5) & 1) + 8 * ((lane >> 4) & 1) + 4 * ((lane >> 3) & 1) + 2 * ((lane >> 2) & 1) +
+           ((lane >> 1) & 1);
+}
+template <typename T>
+__device__ __forceinline__ T wave_reduce_scatter32(const T (&x)[32]) {
+    T y[16], z[8], q[4], h[2];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) y[j] = swap_sum<true>(x[j], x[j + 16]);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) z[j] = swap_sum<false>(y[j], y[j + 8]);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) q[j] = keep_send_sum<kDppMirror, 3>(z[j], z[j + 4]);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) h[j] = keep_send_sum<kDppHalfMirror, 2>(q[j], q[j + 2]);
+    const T o = keep_send_sum<kDppXor2, 1>(h[0], h[1]);
+    return o + dpp<kDppXor1>(o);
 }
 
 // Matrix-core 16x16x4 products (D += A B, A 16x4, B 4x16).  Lane l supplies
@@ -322,6 +394,130 @@ __device__ __forceinline__ cpx<T> herm_lower(const cpx<T> *A, int64_t ld, int r,
     if (c < r) return A[r + (int64_t)c * ld];
     if (c > r) return c_conj(A[c + (int64_t)r * ld]);
     return {A[r + (int64_t)r * ld].re, T(0)};
+}
+
+// Panel QR with the panel in registers: one workgroup of NT >= m threads per
+// matrix, thread t holds row s + t of the 16 panel columns.  Per reflector two
+// workgroup reductions (column norm with the pivot, then the 16 products with
+// the other columns, reduce-scattered within each wavefront); the panel is
+// read and written once.  Column i keeps its reflector v below the band
+// (v0 at the pivot row) until the write-back.  The reflector index is a
+// template parameter so that every register index is static.
+template <typename T, int NT>
+struct QrShared {
+    double part[NT / 64][32];
+    double dotf[2 * kB];
+    double nred[NT / 64];
+    cpx<T> x0s;
+    cpx<T> Ts[kB][kB];
+    cpx<T> alphas[kB];
+};
+
+template <typename T, int NT, int I>
+__device__ __forceinline__ void qr_reflect(QrShared<T, NT> &sh, cpx<T> (&P)[kB], int s, int n, int nr) {
+    constexpr int NW = NT / 64;
+    if (I >= nr) return;  // uniform over the workgroup
+    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+    const int r = s + t, r0 = s + I;
+    const bool own = r < n;
+    const cpx<T> zero = {T(0), T(0)};
+    // norm of column I from the pivot row down, and the pivot
+    double ws = (own && r >= r0) ? (double)c_abs2(P[I]) : 0.0;
+    ws = col_sum(row_sum(ws));
+    if (lane == 0) sh.nred[wid] = ws;
+    if (r == r0) {
+        sh.x0s.re = P[I].re;
+        sh.x0s.im = P[I].im;
+    }
+    __syncthreads();
+    double nrm2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) nrm2 += sh.nred[q];
+    T tau;
+    cpx<T> v0, alpha;
+    make_reflector<T>(nrm2, cpx<T>{sh.x0s.re, sh.x0s.im}, tau, v0, alpha);
+    const cpx<T> v = csel(r == r0, v0, csel(own && r > r0, P[I], zero));
+    // v^H P[:, c] for c > I and V[:, c]^H v for c < I
+    T x[32];
+#pragma unroll
+    for (int c = 0; c < kB; ++c) {
+        const cpx<T> term = c > I ? c_cmul(v, P[c]) : (c < I ? c_cmul(P[c], v) : zero);  // c is static
+        x[2 * c] = term.re;
+        x[2 * c + 1] = term.im;
+    }
+    const T red = wave_reduce_scatter32(x);
+    if ((lane & 1) == 0) sh.part[wid][scatter_elem(lane)] = (double)red;
+    __syncthreads();
+    if (t < 2 * kB) {
+        double sum = 0.0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) sum += sh.part[q][t];
+        sh.dotf[t] = sum;
+    }
+    __syncthreads();
+    // apply the reflector to the columns right of I
+#pragma unroll
+    for (int c = I + 1; c < kB; ++c) {
+        const cpx<T> dc = {(T)sh.dotf[2 * c], (T)sh.dotf[2 * c + 1]};
+        P[c] = c_sub(P[c], c_scale(tau, c_mul(v, dc)));
+    }
+    P[I] = csel(r == r0, v0, P[I]);
+    // T[:I, I] = -tau T[:I, :I] (V^H v_I)[:I], T[I, I] = tau
+    if (t < I) {
+        cpx<T> sum = zero;
+        for (int q = t; q < I; ++q)
+            sum = c_add(sum, c_mul(sh.Ts[t][q], cpx<T>{(T)sh.dotf[2 * q], (T)sh.dotf[2 * q + 1]}));
+        sh.Ts[t][I] = c_scale(-tau, sum);
+    }
+    if (t == I) {
+        sh.Ts[I][I] = {tau, T(0)};
+        sh.alphas[I].re = alpha.re;
+        sh.alphas[I].im = alpha.im;
+    }
+}
+template <typename T, int NT, int... Is>
+__device__ __forceinline__ void qr_reflect_all(QrShared<T, NT> &sh, cpx<T> (&P)[kB], int s, int n, int nr,
+                                               std::integer_sequence<int, Is...>) {
+    (qr_reflect<T, NT, Is>(sh, P, s, n, nr), ...);
+}
+
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void qr_panel_reg_kernel(cpx<T> *__restrict__ Hall, int64_t ld,
+                                                          const int32_t *__restrict__ n_in,
+                                                          cpx<T> *__restrict__ wall, int64_t stride, int p) {
+    __shared__ QrShared<T, NT> sh;
+    const int64_t u = blockIdx.x;
+    const int n = n_in[u];
+    const int s = p + kB, m = n - s;
+    if (n < 0 || n > ld || m < 2 || m > NT) return;
+    const int t = threadIdx.x;
+    const int r = s + t;
+    const bool own = r < n;
+    const int ldi = (int)ld;
+    const TwoView<T> w(wall, stride, ld, u);
+    cpx<T> *A = Hall + u * ld * ld;
+    const cpx<T> zero = {T(0), T(0)};
+    cpx<T> P[kB];
+#pragma unroll
+    for (int c = 0; c < kB; ++c) {
+        const cpx<T> a = A[own ? r + (p + c) * ldi : 0];
+        P[c] = csel(own, a, zero);
+    }
+    for (int idx = t; idx < kB * kB; idx += NT) sh.Ts[idx / kB][idx % kB] = zero;
+    const int nr = min(m - 1, kB);
+    qr_reflect_all<T, NT>(sh, P, s, n, nr, std::make_integer_sequence<int, kB>{});
+    __syncthreads();
+    if (own) {
+#pragma unroll
+        for (int c = 0; c < kB; ++c) {
+            const int r0c = s + c;
+            const bool refl = c < nr;
+            const cpx<T> al = {sh.alphas[c].re, sh.alphas[c].im};
+            w.V[c * ldi + r] = csel(refl && r >= r0c, P[c], zero);
+            A[r + (p + c) * ldi] = csel(!refl || r < r0c, P[c], csel(r == r0c, al, zero));
+        }
+    }
+    for (int idx = t; idx < kB * kB; idx += NT) w.Tm[idx] = sh.Ts[idx / kB][idx % kB];
 }
 
 // Raw operand loads of one hemm step (columns c0 .. c0 + 3) and their fix-up.
@@ -802,7 +998,16 @@ hipError_t launch_tridiag_twostage(cpx<T> *H, int64_t ld, const int32_t *n_in, i
     const unsigned B = (unsigned)batch;
     for (int p = 0; p + kB + 1 < ld; p += kB) {
         const int64_t mmax = ld - p - kB;
-        hipLaunchKernelGGL(qr_panel_kernel<T>, dim3(B), dim3(kQrThreads), 0, s, H, ld, n_in, work, stride, p);
+        if (mmax <= 64)
+            hipLaunchKernelGGL((qr_panel_reg_kernel<T, 64>), dim3(B), dim3(64), 0, s, H, ld, n_in, work, stride, p);
+        else if (mmax <= 128)
+            hipLaunchKernelGGL((qr_panel_reg_kernel<T, 128>), dim3(B), dim3(128), 0, s, H, ld, n_in, work, stride, p);
+        else if (mmax <= 256)
+            hipLaunchKernelGGL((qr_panel_reg_kernel<T, 256>), dim3(B), dim3(256), 0, s, H, ld, n_in, work, stride, p);
+        else if (mmax <= 512)
+            hipLaunchKernelGGL((qr_panel_reg_kernel<T, 512>), dim3(B), dim3(512), 0, s, H, ld, n_in, work, stride, p);
+        else
+            hipLaunchKernelGGL(qr_panel_kernel<T>, dim3(B), dim3(kQrThreads), 0, s, H, ld, n_in, work, stride, p);
         const int64_t hrows = (mmax + kHemmRows - 1) / kHemmRows;
         hipLaunchKernelGGL(hemm_kernel<T>, dim3(xcd_grid(batch, hrows)), dim3(64), 0, s, H, ld, n_in, work,
                            work + (int64_t)kB * ld, stride, p, batch, hrows);

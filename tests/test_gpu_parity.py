@@ -175,7 +175,7 @@ def test_batched_eigvalsh_fp64(B, gdev, mdev, name, N, p, K):
 
 
 @pytest.mark.parametrize("ld,sizes", [(64, [0, 1, 2, 3, 17, 64]), (128, [128, 127, 5]), (200, [200, 199, 1, 2, 130]),
-                                      (300, [3, 300, 257])])
+                                      (300, [3, 300, 257]), (700, [700, 531, 2, 650])])
 def test_batched_eigvalsh_random_ragged(B, ld, sizes):
     say(f"[eigvalsh random] ld={ld} sizes={sizes}")
     rng = np.random.default_rng(ld)
