@@ -175,12 +175,26 @@ __device__ void tridiag_packed(cpx<T> *L, int n, int cap, cpx<T> *v, cpx<T> *pw,
 // Number of eigenvalues of the symmetric tridiagonal (d, e) below x: the
 // count of negative pivots of T - x I (Sturm sequence), with tiny pivots
 // replaced by -pivmin.  e2 holds the squared sub-diagonal.
+// 1/q for |q| >= pivmin (a normal number) and |q| finite: the hardware
+// reciprocal estimate refined by two Newton steps (within about an ulp).
+__device__ __forceinline__ double sturm_recip(double q) {
+    double r = __builtin_amdgcn_rcp(q);
+    double h = fma(-q, r, 1.0);
+    r = fma(r, h, r);
+    h = fma(-q, r, 1.0);
+    return fma(r, h, r);
+}
+
+// Number of eigenvalues of the symmetric tridiagonal (d, e) below x, from
+// the signs of the pivots of T - x I = L D L^T (e2 = e^2).  Pivots are kept
+// at least pivmin in magnitude, so every pivot and quotient stays finite.
 __device__ __forceinline__ int sturm_count(const double *d, const double *e2, int n, double x, double pivmin) {
     double q = d[0] - x;
     if (fabs(q) < pivmin) q = -pivmin;
     int c = q < 0.0 ? 1 : 0;
+#pragma unroll 4
     for (int i = 1; i < n; ++i) {
-        q = (d[i] - x) - e2[i - 1] / q;
+        q = fma(-e2[i - 1], sturm_recip(q), d[i] - x);
         if (fabs(q) < pivmin) q = -pivmin;
         c += q < 0.0 ? 1 : 0;
     }
