@@ -13,11 +13,16 @@ workspace already resident.  The default 8 steps x 250 samples cover exactly
 the 2000 samples of the workload.
 
 Prints one JSON line.  ``value`` is eigensolves per second of the whole job.
-``roofline`` reports the dominant kernel (timed with HIP events on the
-library's stream during the timed region) against the FP64 peak, using the
-algorithmic 16/3 n^3 real flops of a Hermitian tridiagonal reduction per
-eigensolve.  ``cpu_baseline`` times the FP64 C oracle (unchanged) on a bounded
-number of samples of the same workload on the host cores.
+``roofline`` reports the single kernel with the largest share, the
+band-to-tridiagonal chase, timed with HIP events on the library's stream
+during the timed region, against the HBM peak: algorithmic bytes per launch
+(``chase_bytes``) over the average launch duration; ``traffic`` is the HBM
+bytes per launch measured with rocprofv3 counters (recorded in profiles/ with
+the hash of the kernel source, null if the source has changed since).
+``time_to_tol`` runs the MLMC estimator of the graphene level hierarchy to
+TOL = 1e-3 with the FP64 and the mixed path.  ``cpu_baseline`` times the FP64 C
+oracle (unchanged) on a bounded number of samples of the same workload on the
+host cores.
 """
 
 from __future__ import annotations
@@ -39,6 +44,63 @@ if ROOT not in sys.path:
 METRIC = "H(k) eigensolves/sec + MLMC IDoS time-to-TOL, mixed/served vs plain FP64 path"
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
+HBM_PEAK_GBS = 8000.0
+BAND = 16  # half-bandwidth of the two-stage reduction
+CHASE_SOURCE = os.path.join(ROOT, "paper_1611_09784_amd", "csrc", "tridiag_twostage.hip")
+CHASE_PROFILE = os.path.join(ROOT, "profiles", "chase_kernel_graphene_n16_fp64.md")
+
+
+def chase_bytes(n: int, esize: int) -> int:
+    """Algorithmic HBM bytes of the band-to-tridiagonal chase for one matrix
+    of side n (esize bytes per complex element): copy of the lower band of
+    H into the band array (17 diagonals read, 33 written), then per step of
+    every sweep the unique elements read (lower part of the diagonal block and
+    the block below it) and written (the block left of the diagonal block and
+    the lower part of the diagonal block), and finally d and e."""
+    if n < 3:
+        return n * (BAND + 1 + 2 * BAND + 1) * esize + 3 * n * 8
+    tri = lambda L: L * (L + 1) // 2
+    elems = n * (BAND + 1) + n * (2 * BAND + 1)
+    for j in range(n - 2):
+        lo, hi = j + 1, min(j + BAND, n - 1)
+        L = hi - lo + 1
+        lo1, hi1 = hi + 1, min(hi + BAND, n - 1)
+        L1 = hi1 - lo1 + 1
+        Lprev = 1
+        elems += L + tri(L) + max(L1, 0) * L
+        while True:
+            elems += L * Lprev + tri(L)
+            lo2, hi2 = hi1 + 1, min(hi1 + BAND, n - 1)
+            L2 = hi2 - lo2 + 1
+            if L1 < 2:
+                if L1 == 1:
+                    elems += L
+                break
+            elems += tri(L1) + max(L2, 0) * L1
+            Lprev, lo, hi, L, lo1, hi1, L1 = L, lo1, hi1, L1, lo2, hi2, L2
+    return elems * esize + (2 * n - 1) * esize + 2 * n * 8
+
+
+def chase_traffic_per_solve():
+    """HBM bytes per eigensolve of the chase kernel measured with rocprofv3
+    counters, if the recorded source hash matches the current kernel source."""
+    import hashlib
+    try:
+        text = open(CHASE_PROFILE).read()
+        src = hashlib.sha256(open(CHASE_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    rec = {}
+    for line in text.splitlines():
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            rec[k.strip()] = v.strip().strip("`")
+    if rec.get("source_sha256") != src:
+        return None
+    try:
+        return float(rec["hbm_bytes_per_solve"])
+    except (KeyError, ValueError):
+        return None
 
 
 def parse():
@@ -53,7 +115,69 @@ def parse():
     ap.add_argument("--cpu-baseline", dest="cpu_baseline", action="store_true", default=True)
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--cpu-samples", type=int, default=0, help="oracle samples (0: one per host thread)")
+    ap.add_argument("--mlmc", dest="mlmc", action="store_true", default=True,
+                    help="also time the MLMC estimator to TOL (graphene levels N = 4..32), FP64 and mixed")
+    ap.add_argument("--no-mlmc", dest="mlmc", action="store_false")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device-to-device copy three times (reference for the "
+                         "FETCH_SIZE / WRITE_SIZE counter scale) and exit")
     return ap.parse_args()
+
+
+def copy_calibration():
+    import torch
+    n = 256 * 1024 * 1024
+    a = torch.ones(n // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n, "copies": 3}), flush=True)
+
+
+def time_to_tol(B, dev):
+    """MLMC IDoS estimator of the graphene level hierarchy N = 4, 8, 16, 32
+    (Gamma-centred K = 32 / N, p = 0.02, seed 303) run to TOL = 1e-3 relative,
+    once with the FP64 path and once with the mixed path (FP32 reduction, FP64
+    bisection and sums).  Beside each time: the per-level samples, the final
+    statistical error, and for the mixed path the largest IDoS difference from
+    the FP64 path on the same 8 coupled samples of every level."""
+    import torch
+    from mlmc_inputs import WORKLOADS
+    from mlmc_inputs.configs import workload_eps
+    from paper_1611_09784_amd import driver as D
+
+    wl = WORKLOADS["graphene_mlmc"]
+    lat = wl.make_lattice()
+    eps = workload_eps(wl)
+    dlat = B.DeviceLattice(lat, 0)
+    Ks = [wl.NK // N for N in wl.levels]
+    out = {"workload": wl.name, "levels": list(wl.levels), "K": Ks, "tol_rel": wl.tol}
+    for name, prec in (("fp64", B.MLMC_PREC_FP64), ("mixed", B.MLMC_PREC_MIXED)):
+        est = D.Estimator(dlat, eps, wl.delta, wl.p, wl.kgrid, wl.seed, wl.smoother, prec, chunk_samples=32)
+        for st in D.make_levels(wl.levels, Ks):  # warm-up: workspaces and first launches
+            est.add_samples(st, 2)
+        torch.cuda.synchronize(dev)
+        r = D.run_mlmc(est, wl.levels, Ks, wl.tol)
+        out[name] = {"seconds": round(r.seconds, 3), "M": [st.M for st in r.levels], "error": r.error,
+                     "tol_abs": r.tol_abs, "rounds": len(r.rounds),
+                     "seconds_per_level": [round(st.seconds, 3) for st in r.levels]}
+        print(f"[bench] time-to-TOL {name}: {r.seconds:.2f} s, M = {[st.M for st in r.levels]}", file=sys.stderr,
+              flush=True)
+    # precision error of the mixed path: same samples, both precisions
+    errs = []
+    for l, st in enumerate(D.make_levels(wl.levels, Ks)):
+        q = {}
+        for name, prec in (("fp64", B.MLMC_PREC_FP64), ("mixed", B.MLMC_PREC_MIXED)):
+            est = D.Estimator(dlat, eps, wl.delta, wl.p, wl.kgrid, wl.seed, wl.smoother, prec, chunk_samples=8)
+            lv = D.make_levels(wl.levels, Ks)[l]
+            est.add_samples(lv, 8)
+            q[name] = lv.stats[[0, 2]] / lv.M  # mean Y and mean Q_f
+        errs.append(float(np.max(np.abs(q["mixed"] - q["fp64"]))))
+    out["mixed_idos_err_per_level"] = errs
+    out["speedup_mixed_vs_fp64"] = round(out["fp64"]["seconds"] / out["mixed"]["seconds"], 3)
+    dlat.close()
+    return out
 
 
 def host_threads() -> int:
@@ -77,6 +201,9 @@ def cpu_model() -> str:
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; --gpus must be 1 "
@@ -123,7 +250,7 @@ def main():
     elapsed = time.perf_counter() - t0
     B.mlmc_timer_enable(False)
     kernels = {}
-    for name in ("sample_vacancies", "kgrid", "assemble", "small_fused", "tridiag", "bisect", "idos",
+    for name in ("sample_vacancies", "kgrid", "assemble", "small_fused", "band_reduce", "chase", "bisect", "idos",
                  "level_stats"):
         ms, cnt = B.mlmc_timer_read(name)
         if cnt:
@@ -131,23 +258,41 @@ def main():
     solves = args.steps * args.batch * nk
     value = solves / elapsed
 
-    # Algorithmic work of the timed eigensolves: 16/3 n^3 real flops per H(k).
+    # Sizes of the timed eigensolves (from the same vacancy masks the GPU drew).
     masks = B.mlmc_sample_vacancies(dlat, N, wl.p, wl.seed, dlat.tag(N), 0, args.steps * args.batch).cpu().numpy()
     orb_per_group = np.bincount(lat.orb_group, minlength=lat.n_groups)
     vac_orbs = (masks.reshape(masks.shape[0], -1, lat.n_groups) * orb_per_group).sum(axis=(1, 2))
-    n_per_sample = lat.n_orb * N * N - vac_orbs
+    n_per_sample = (lat.n_orb * N * N - vac_orbs).astype(np.int64)
     flops = float(nk * np.sum(16.0 / 3.0 * n_per_sample.astype(np.float64) ** 3))
     dom = max(kernels, key=lambda k: kernels[k]["ms"]) if kernels else None
     roofline = None
-    if "tridiag" in kernels or "small_fused" in kernels:
-        kname = "tridiag" if "tridiag" in kernels else "small_fused"
-        kms = kernels[kname]["ms"]
+    esize = 16 if prec == B.MLMC_PREC_FP64 else 8
+    if "chase" in kernels:
+        # The single kernel with the largest share: the band-to-tridiagonal chase,
+        # bound by HBM traffic.  Algorithmic bytes per launch / event-timed duration.
+        sizes, counts = np.unique(n_per_sample, return_counts=True)
+        total_bytes = float(nk * sum(int(c) * chase_bytes(int(v), esize) for v, c in zip(sizes, counts)))
+        launches = kernels["chase"]["launches"]
+        kms = kernels["chase"]["ms"]
+        achieved = total_bytes / (kms * 1e-3) / 1e9
+        per_solve = chase_traffic_per_solve() if prec == B.MLMC_PREC_FP64 and wl.name == "graphene_n16_mc" else None
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": None if per_solve is None else round(per_solve * solves / launches),
+                    "kernel": "chase_kernel", "avg_launch_ms": round(kms / launches, 3),
+                    "bytes_per_launch": round(total_bytes / launches),
+                    "tridiag_flops_per_s": round(flops / ((kms + kernels.get("band_reduce", {"ms": 0})["ms"]) * 1e-3)
+                                                 / 1e12, 3)}
+    elif "small_fused" in kernels:
+        kms = kernels["small_fused"]["ms"]
         achieved = flops / (kms * 1e-3) / 1e12
         peak = FP64_PEAK_TFLOPS if prec == B.MLMC_PREC_FP64 else FP32_PEAK_TFLOPS
         roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                    "frac": round(achieved / peak, 4), "traffic": None, "kernel": kname,
-                    "avg_launch_ms": round(kms / kernels[kname]["launches"], 3),
-                    "flops_per_launch": flops / kernels[kname]["launches"]}
+                    "frac": round(achieved / peak, 4), "traffic": None, "kernel": "small_eig_kernel",
+                    "avg_launch_ms": round(kms / kernels["small_fused"]["launches"], 3),
+                    "flops_per_launch": flops / kernels["small_fused"]["launches"]}
+
+    ttt = time_to_tol(B, dev) if args.mlmc else None
 
     cpu = None
     if args.cpu_baseline:
@@ -182,8 +327,9 @@ def main():
                    "precision": args.precision},
         "samples_per_s": round(args.steps * args.batch / elapsed, 3),
         "kernels_ms": kernels,
-        "dominant_kernel": dom,
+        "dominant_kernel": roofline["kernel"] if roofline else dom,
         "roofline": roofline,
+        "time_to_tol": ttt,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

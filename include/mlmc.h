@@ -229,7 +229,9 @@ mlmc_status mlmc_optimal_samples(int32_t L, const double *V, const double *W, do
 mlmc_status mlmc_timer_enable(int32_t enable);
 /* Total event-measured duration (ms) and count of the recorded launches of
  * kernel `name`: "sample_vacancies", "partition", "kgrid", "assemble",
- * "small_fused", "tridiag", "bisect", "idos" or "level_stats".
+ * "small_fused", "band_reduce" (dense to band, several kernels per launch),
+ * "chase" (band to tridiagonal, one kernel), "bisect", "idos" or
+ * "level_stats".
  * Blocks until those launches have completed. */
 mlmc_status mlmc_timer_read(const char *name, double *total_ms, int64_t *launches);
 

@@ -120,12 +120,15 @@ void carve_large(Carver &cv, mlmc_precision prec, int64_t ld, int64_t units, boo
 // Eigenvalues of `units` matrices already in b.H (ld > small cap).
 mlmc_status run_large(mlmc_precision prec, void *H, int64_t ld, const int32_t *n, int64_t units, double *w, int64_t ldw,
                       const EigBuffers &b, hipStream_t s) {
-    if (prec == MLMC_PREC_FP64)
-        LAUNCH("tridiag", s, launch_tridiag_twostage<double>(static_cast<cpx<double> *>(H), ld, n, units, b.d, b.e, ld,
-                                                     static_cast<cpx<double> *>(b.partial), s));
-    else
-        LAUNCH("tridiag", s, launch_tridiag_twostage<float>(static_cast<cpx<float> *>(H), ld, n, units, b.d, b.e, ld,
-                                                    static_cast<cpx<float> *>(b.partial), s));
+    if (prec == MLMC_PREC_FP64) {
+        cpx<double> *Hc = static_cast<cpx<double> *>(H), *wk = static_cast<cpx<double> *>(b.partial);
+        LAUNCH("band_reduce", s, launch_band_reduce<double>(Hc, ld, n, units, wk, s));
+        LAUNCH("chase", s, launch_band_chase<double>(Hc, ld, n, units, b.d, b.e, ld, wk, s));
+    } else {
+        cpx<float> *Hc = static_cast<cpx<float> *>(H), *wk = static_cast<cpx<float> *>(b.partial);
+        LAUNCH("band_reduce", s, launch_band_reduce<float>(Hc, ld, n, units, wk, s));
+        LAUNCH("chase", s, launch_band_chase<float>(Hc, ld, n, units, b.d, b.e, ld, wk, s));
+    }
     LAUNCH("bisect", s, launch_bisect(b.d, b.e, ld, n, units, ld, w, ldw, s));
     return MLMC_OK;
 }

@@ -92,18 +92,16 @@ template <typename T>
 hipError_t launch_small_from_matrix(const cpx<T> *H, int64_t ld, const int32_t *n_in, int64_t batch, double *w,
                                     int64_t ldw, hipStream_t s);
 
-// Batched blocked Householder reduction in device memory (lower triangle
-// only; all matrices advance column by column together) -> (d, e).
+// Two-stage reduction to tridiagonal form.  Stage 1 (launch_band_reduce):
+// dense -> band of half-width 16, in place in H (lower triangle).  Stage 2
+// (launch_band_chase): band -> tridiagonal (d, e) by bulge chasing.  Both use
+// the per-matrix workspace of tridiag_twostage_work_elems complex elements.
 template <typename T>
-hipError_t launch_tridiag_batched(cpx<T> *H, int64_t ld, const int32_t *n_in, int64_t batch, double *d, double *e,
-                                  int64_t lde, cpx<T> *work, hipStream_t s);
+hipError_t launch_band_reduce(cpx<T> *H, int64_t ld, const int32_t *n_in, int64_t batch, cpx<T> *work,
+                              hipStream_t s);
 template <typename T>
-size_t tridiag_batched_work_elems(int64_t ld);
-
-// Two-stage reduction (dense -> band of half-width 16 -> tridiagonal) -> (d, e).
-template <typename T>
-hipError_t launch_tridiag_twostage(cpx<T> *H, int64_t ld, const int32_t *n_in, int64_t batch, double *d, double *e,
-                                   int64_t lde, cpx<T> *work, hipStream_t s);
+hipError_t launch_band_chase(const cpx<T> *H, int64_t ld, const int32_t *n_in, int64_t batch, double *d, double *e,
+                             int64_t lde, cpx<T> *work, hipStream_t s);
 template <typename T>
 size_t tridiag_twostage_work_elems(int64_t ld);
 
