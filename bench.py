@@ -46,7 +46,8 @@ FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
 BAND = 16  # half-bandwidth of the two-stage reduction
-CHASE_SOURCE = os.path.join(ROOT, "paper_1611_09784_amd", "csrc", "tridiag_twostage.hip")
+CHASE_SOURCES = [os.path.join(ROOT, "paper_1611_09784_amd", "csrc", f)
+                 for f in ("band_chase.hip", "twostage_common.hpp", "device_common.hpp", "internal.hpp")]
 CHASE_PROFILE = os.path.join(ROOT, "profiles", "chase_kernel_graphene_n16_fp64.md")
 
 
@@ -87,7 +88,10 @@ def chase_traffic_per_solve():
     import hashlib
     try:
         text = open(CHASE_PROFILE).read()
-        src = hashlib.sha256(open(CHASE_SOURCE, "rb").read()).hexdigest()
+        h = hashlib.sha256()
+        for f in CHASE_SOURCES:
+            h.update(open(f, "rb").read())
+        src = h.hexdigest()
     except OSError:
         return None
     rec = {}
