@@ -228,8 +228,8 @@ def main():
     dlat = B.DeviceLattice(lat, 0)
     d_eps = torch.as_tensor(eps, device=dev)
     N, K = wl.N, wl.K
-    nk = K * K
-    need = B.mlmc_level_workspace(dlat, N, False, K, K, args.chunk, prec, eps.size)
+    nk = B.mlmc_kgrid_points(wl.kgrid, K)
+    need = B.mlmc_level_workspace(dlat, N, False, K, K, wl.kgrid, args.chunk, prec, eps.size)
     work = torch.empty((need,), dtype=torch.uint8, device=dev)
     stats = torch.zeros((4, eps.size), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()

@@ -63,8 +63,9 @@ typedef enum {
 } mlmc_precision;
 
 typedef enum {
-    MLMC_KGRID_MP = 0,   /* K x K Monkhorst-Pack: kappa = (2r - K + 1) / (2K)  */
-    MLMC_KGRID_GAMMA = 1 /* K x K Gamma-centred:  kappa = r / K                */
+    MLMC_KGRID_MP = 0,     /* K x K Monkhorst-Pack: kappa = (2r - K + 1) / (2K)           */
+    MLMC_KGRID_GAMMA = 1,  /* K x K Gamma-centred:  kappa = r / K                         */
+    MLMC_KGRID_RHOMBI = 2  /* the three-rhombus lattice of Section 4.2: 3 K^2 points       */
 } mlmc_kgrid_kind;
 
 typedef enum {
@@ -136,10 +137,22 @@ mlmc_status mlmc_sample_vacancies(mlmc_lattice lat, int32_t N, double p, uint64_
 mlmc_status mlmc_partition_masks(mlmc_lattice lat, int32_t N, const uint8_t *d_mask, int64_t n_samples,
                                  uint8_t *d_quarters, mlmc_stream stream);
 
-/* Brillouin-zone grid (Section 4.2; reading: a uniform K x K grid of the
- * supercell zone with equal weights, the nearest-point rule of Section 4.3).
- * d_kred: [K*K][2] reduced coordinates of point r1*K + r2 with respect to the
- * supercell reciprocal vectors; d_kweight: [K*K], each 1/K^2. */
+/* Number of points of a Brillouin-zone grid: K^2 (MLMC_KGRID_MP,
+ * MLMC_KGRID_GAMMA) or 3 K^2 (MLMC_KGRID_RHOMBI).  Host only.
+ * Errors: bad kind, K < 1 or K > 4096, NULL n_k. */
+mlmc_status mlmc_kgrid_points(mlmc_kgrid_kind kind, int32_t K, int32_t *n_k);
+
+/* Brillouin-zone grid in reduced coordinates of the supercell reciprocal
+ * lattice, with the weights of the nearest-point rule (Section 4.3).
+ *   MP, GAMMA: a uniform K x K grid of the supercell zone with equal weights
+ *     (the reading used by the main workloads); point r1*K + r2, weight 1/K^2.
+ *   RHOMBI: Section 4.2's lattice: the hexagonal zone as three rhombi with
+ *     the common corner Gamma, each cut into K x K rhombi whose corners are
+ *     the k-points; corners shared by two rhombi or equal modulo a reciprocal
+ *     lattice vector count once.  These are the 3 K^2 points
+ *     (a, b) / (3K) with a + b divisible by 3, listed in increasing (a, b),
+ *     each of weight 1 / (3 K^2).
+ * d_kred: [n_k][2], d_kweight: [n_k] with n_k from mlmc_kgrid_points. */
 mlmc_status mlmc_kgrid(mlmc_kgrid_kind kind, int32_t K, double *d_kred, double *d_kweight, mlmc_stream stream);
 
 /* Bloch Hamiltonians H(k) (Section 3.1, eq. (tightbinding), orthogonal form;
@@ -194,12 +207,13 @@ mlmc_status mlmc_idos(const double *d_w, int64_t ldw, const int32_t *d_n, int64_
 mlmc_status mlmc_level_stats(const double *d_idos_fine, const double *d_idos_quarters, int64_t n_samples,
                              int32_t n_eps, double *d_stats, mlmc_stream stream);
 
-/* Workspace bytes for mlmc_level_estimate when it processes `chunk_samples`
- * samples per pass (the call uses the largest chunk that fits the workspace
- * it is given; chunk_samples >= 1). */
+/* Workspace bytes for mlmc_level_estimate with the same lattice, sizes and
+ * k-grid kind when it processes `chunk_samples` samples per pass (the call
+ * uses the largest chunk that fits the workspace it is given;
+ * chunk_samples >= 1). */
 mlmc_status mlmc_level_workspace(mlmc_lattice lat, int32_t N_fine, int32_t coupled, int32_t K_fine,
-                                 int32_t K_coarse, int64_t chunk_samples, mlmc_precision prec, int32_t n_eps,
-                                 size_t *bytes);
+                                 int32_t K_coarse, mlmc_kgrid_kind kind, int64_t chunk_samples,
+                                 mlmc_precision prec, int32_t n_eps, size_t *bytes);
 
 /* One MLMC level over samples first_sample .. first_sample+M-1 (Sections 2.2
  * and 3.3): sample outcomes on the N_fine supercell (tag (lattice_id << 32) |

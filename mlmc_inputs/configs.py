@@ -20,6 +20,7 @@ from .lattices import Lattice, graphene, mos2_shaped
 
 KGRID_MP = 0      # Monkhorst-Pack K x K grid
 KGRID_GAMMA = 1   # Gamma-centred K x K grid
+KGRID_RHOMBI = 2  # three-rhombus lattice of the hexagonal zone, 3 K^2 points
 SMOOTH_GAUSS = 0  # g(x) = erfc(x / sqrt 2) / 2
 SMOOTH_CUBIC = 1  # compactly supported cubic meeting the q = 0, 1 moment conditions
 

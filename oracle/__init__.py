@@ -54,6 +54,8 @@ def lib():
                                            C.c_int64, P]
         L.ora_partition_masks.argtypes = [C.c_int32, C.c_int32, P, P]
         L.ora_kgrid.argtypes = [C.c_int32, C.c_int32, P, P]
+        L.ora_kgrid_points.argtypes = [C.c_int32, C.c_int32]
+        L.ora_kgrid_points.restype = C.c_int32
         L.ora_build_hamiltonian.argtypes = [P, C.c_int32, P, C.c_double, C.c_double, P, C.c_int64, P]
         L.ora_tridiagonalize.argtypes = [C.c_int32, P, C.c_int64, P, P]
         L.ora_tridiag_eigvals.argtypes = [C.c_int32, P, P, P]
@@ -145,9 +147,17 @@ def partition_masks(mask: np.ndarray) -> np.ndarray:
     return out
 
 
+def kgrid_points(kind: int, K: int) -> int:
+    n = lib().ora_kgrid_points(kind, K)
+    if n < 0:
+        raise ValueError(f"kgrid_points: kind {kind}, K {K}")
+    return n
+
+
 def kgrid(kind: int, K: int):
-    kred = np.zeros((K * K, 2))
-    kw = np.zeros(K * K)
+    nk = kgrid_points(kind, K)
+    kred = np.zeros((nk, 2))
+    kw = np.zeros(nk)
     _check(lib().ora_kgrid(kind, K, _ptr(kred), _ptr(kw)), "kgrid")
     return kred, kw
 

@@ -138,24 +138,87 @@ int ora_partition_masks(int32_t N, int32_t G, const uint8_t *mask, uint8_t *quar
     return ORA_OK;
 }
 
-/* K x K Brillouin-zone grid in reduced coordinates of the supercell          */
-/* reciprocal lattice, equal weights.  kind 0: Monkhorst-Pack offsets         */
-/* (2r - K + 1)/(2K); kind 1: Gamma-centred r/K.  Point index r1*K + r2.      */
+/* Number of k-points of a grid: K x K for the Monkhorst-Pack (0) and
+ * Gamma-centred (1) grids, 3 K^2 for the three-rhombus lattice (2). */
+int ora_kgrid_points(int32_t kind, int32_t K)
+{
+    if (K < 1) return -1;
+    if (kind == 0 || kind == 1) return K * K;
+    if (kind == 2) return 3 * K * K;
+    return -1;
+}
+
+static int imod(int a, int m)
+{
+    int r = a % m;
+    return r < 0 ? r + m : r;
+}
+
+/* Brillouin-zone grids in reduced coordinates of the supercell reciprocal
+ * lattice, with weights.
+ *   kind 0, 1: a uniform K x K grid (Monkhorst-Pack or Gamma-centred), equal
+ *              weights (the reading of Sections 4.2-4.3 used by the main
+ *              workloads).
+ *   kind 2:    the three-rhombus lattice of Section 4.2.  The hexagonal zone
+ *              is the union of three rhombi with the common corner Gamma,
+ *              each spanned by two zone corners 120 degrees apart; in reduced
+ *              coordinates the corners used are c1 = (2/3, 1/3),
+ *              c3 = (-1/3, 1/3) and c5 = (-1/3, -2/3), and the rhombi are
+ *              (c1, c3), (c3, c5), (c5, c1).  Each rhombus is cut into K x K
+ *              equal rhombi and the k-points are their corners,
+ *              (m/K) u + (n/K) v for 0 <= m, n <= K.  Corners shared by two
+ *              rhombi, and corners that differ by a reciprocal lattice vector
+ *              (the same point of the periodic band structure), are kept once.
+ *              The kept points form a uniform lattice, so every one has the
+ *              same nearest-point cell (Section 4.3): weight 1 / (number of
+ *              points).  Points are listed in increasing (3K kappa1, 3K kappa2).
+ */
 int ora_kgrid(int32_t kind, int32_t K, double *kred, double *kweight)
 {
-    if (K < 1 || (kind != 0 && kind != 1)) return ORA_ERR_ARG;
-    for (int r1 = 0; r1 < K; ++r1)
-        for (int r2 = 0; r2 < K; ++r2) {
-            int idx = r1 * K + r2;
-            if (kind == 0) {
-                kred[2 * idx + 0] = (2.0 * r1 - K + 1.0) / (2.0 * K);
-                kred[2 * idx + 1] = (2.0 * r2 - K + 1.0) / (2.0 * K);
-            } else {
-                kred[2 * idx + 0] = (double)r1 / K;
-                kred[2 * idx + 1] = (double)r2 / K;
+    const int nk = ora_kgrid_points(kind, K);
+    if (nk < 0) return ORA_ERR_ARG;
+    if (kind == 0 || kind == 1) {
+        for (int r1 = 0; r1 < K; ++r1)
+            for (int r2 = 0; r2 < K; ++r2) {
+                int idx = r1 * K + r2;
+                if (kind == 0) {
+                    kred[2 * idx + 0] = (2.0 * r1 - K + 1.0) / (2.0 * K);
+                    kred[2 * idx + 1] = (2.0 * r2 - K + 1.0) / (2.0 * K);
+                } else {
+                    kred[2 * idx + 0] = (double)r1 / K;
+                    kred[2 * idx + 1] = (double)r2 / K;
+                }
+                kweight[idx] = 1.0 / ((double)K * K);
             }
-            kweight[idx] = 1.0 / ((double)K * K);
-        }
+        return ORA_OK;
+    }
+    /* zone corners times 3 (integer numerators over 3) */
+    const int corner[3][2] = {{2, 1}, {-1, 1}, {-1, -2}};
+    const int M3 = 3 * K;
+    unsigned char *seen = (unsigned char *)calloc((size_t)M3 * M3, 1);
+    if (!seen) return ORA_ERR_NOMEM;
+    for (int r = 0; r < 3; ++r) {
+        const int *u = corner[r], *v = corner[(r + 1) % 3];
+        for (int m = 0; m <= K; ++m)
+            for (int n = 0; n <= K; ++n) {
+                /* (m/K) u/3 + (n/K) v/3 = (m u + n v) / (3K) */
+                const int a = imod(m * u[0] + n * v[0], M3), b = imod(m * u[1] + n * v[1], M3);
+                seen[(size_t)a * M3 + b] = 1;
+            }
+    }
+    int count = 0;
+    for (int a = 0; a < M3; ++a)
+        for (int b = 0; b < M3; ++b)
+            if (seen[(size_t)a * M3 + b]) {
+                if (count < nk) {
+                    kred[2 * count + 0] = (double)a / (double)M3;
+                    kred[2 * count + 1] = (double)b / (double)M3;
+                }
+                ++count;
+            }
+    free(seen);
+    if (count != nk) return ORA_ERR_ARG;
+    for (int i = 0; i < nk; ++i) kweight[i] = 1.0 / (double)nk;
     return ORA_OK;
 }
 
@@ -419,7 +482,8 @@ int ora_idos(const double *w, int64_t ldw, const int32_t *n, int32_t n_k, const 
 static int outcome_idos(const ora_lattice *L, int32_t N, const uint8_t *mask, int32_t kind, int32_t K,
                         const double *eps, int32_t n_eps, double delta, int32_t smoother, double *out)
 {
-    const int nk = K * K;
+    const int nk = ora_kgrid_points(kind, K);
+    if (nk < 0) return ORA_ERR_ARG;
     const int nmax = N * N * L->n_orb;
     double *kred = (double *)malloc(sizeof(double) * 2 * (size_t)nk);
     double *kw = (double *)malloc(sizeof(double) * (size_t)nk);

@@ -30,6 +30,7 @@ MLMC_PREC_FP64 = 0
 MLMC_PREC_MIXED = 1
 MLMC_KGRID_MP = 0
 MLMC_KGRID_GAMMA = 1
+MLMC_KGRID_RHOMBI = 2
 MLMC_SMOOTH_GAUSS = 0
 MLMC_SMOOTH_CUBIC = 1
 
@@ -68,13 +69,14 @@ SIGNATURES = {
     "mlmc_lattice_max_orbitals": (C.c_int, [P, I32, P]),
     "mlmc_sample_vacancies": (C.c_int, [P, I32, DBL, U64, U64, I64, I64, P, P]),
     "mlmc_partition_masks": (C.c_int, [P, I32, P, I64, P, P]),
+    "mlmc_kgrid_points": (C.c_int, [C.c_int, I32, P]),
     "mlmc_kgrid": (C.c_int, [C.c_int, I32, P, P, P]),
     "mlmc_build_hamiltonians": (C.c_int, [P, I32, P, I64, P, I32, C.c_int, P, I64, P, P]),
     "mlmc_eigvalsh_workspace": (C.c_int, [C.c_int, C.c_int, I64, I64, P]),
     "mlmc_batched_eigvalsh": (C.c_int, [C.c_int, C.c_int, P, I64, P, I64, P, I64, P, SZ, P]),
     "mlmc_idos": (C.c_int, [P, I64, P, I64, I32, P, DBL, P, I32, DBL, C.c_int, P, P]),
     "mlmc_level_stats": (C.c_int, [P, P, I64, I32, P, P]),
-    "mlmc_level_workspace": (C.c_int, [P, I32, I32, I32, I32, I64, C.c_int, I32, P]),
+    "mlmc_level_workspace": (C.c_int, [P, I32, I32, I32, I32, C.c_int, I64, C.c_int, I32, P]),
     "mlmc_level_estimate": (C.c_int, [P, I32, I32, DBL, I32, I32, C.c_int, U64, I64, I64, P, I32, DBL, C.c_int,
                                       C.c_int, P, P, SZ, P]),
     "mlmc_optimal_samples": (C.c_int, [I32, P, P, DBL, DBL, DBL, P]),
@@ -220,10 +222,17 @@ def mlmc_partition_masks(dlat, N, mask, out=None, stream=None):
     return out
 
 
+def mlmc_kgrid_points(kind, K) -> int:
+    out = C.c_int32()
+    _check(lib().mlmc_kgrid_points(kind, K, C.byref(out)), "mlmc_kgrid_points")
+    return out.value
+
+
 def mlmc_kgrid(kind, K, device=None, stream=None):
     dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
-    kred = torch.empty((K * K, 2), dtype=torch.float64, device=dev)
-    kw = torch.empty((K * K,), dtype=torch.float64, device=dev)
+    nk = mlmc_kgrid_points(kind, K)
+    kred = torch.empty((nk, 2), dtype=torch.float64, device=dev)
+    kw = torch.empty((nk,), dtype=torch.float64, device=dev)
     _check(lib().mlmc_kgrid(kind, K, _ptr(kred), _ptr(kw), _stream(stream)), "mlmc_kgrid")
     return kred, kw
 
@@ -303,10 +312,10 @@ def mlmc_level_stats(idos_fine, idos_quarters=None, stats=None, stream=None):
     return stats
 
 
-def mlmc_level_workspace(dlat, N, coupled, K_fine, K_coarse, chunk_samples, prec, n_eps) -> int:
+def mlmc_level_workspace(dlat, N, coupled, K_fine, K_coarse, kind, chunk_samples, prec, n_eps) -> int:
     out = C.c_size_t()
-    _check(lib().mlmc_level_workspace(dlat.handle, N, int(coupled), K_fine, K_coarse, chunk_samples, prec, n_eps,
-                                      C.byref(out)), "mlmc_level_workspace")
+    _check(lib().mlmc_level_workspace(dlat.handle, N, int(coupled), K_fine, K_coarse, kind, chunk_samples, prec,
+                                      n_eps, C.byref(out)), "mlmc_level_workspace")
     return out.value
 
 
@@ -320,7 +329,7 @@ def mlmc_level_estimate(dlat, N, coupled, p, K_fine, K_coarse, kind, seed, first
     _dev(stats, torch.float64, "stats")
     if work is None:
         chunk = max(1, min(M, 64) if chunk_samples is None else chunk_samples)
-        need = mlmc_level_workspace(dlat, N, coupled, K_fine, K_coarse, chunk, prec, ne)
+        need = mlmc_level_workspace(dlat, N, coupled, K_fine, K_coarse, kind, chunk, prec, ne)
         work = torch.empty((need,), dtype=torch.uint8, device=eps.device)
     _check(lib().mlmc_level_estimate(dlat.handle, N, int(coupled), float(p), K_fine, K_coarse, kind,
                                      int(seed) & (2**64 - 1), first_sample, M, _ptr(eps), ne, float(delta), smoother,

@@ -144,12 +144,16 @@ struct LevelLayout {
     size_t bytes = 0;
 };
 
-LevelLayout level_layout(const mlmc_lattice_s *lat, int N, bool coupled, int Kf, int Kc, int64_t mc,
+static bool valid_kgrid_kind(int kind) {
+    return kind == MLMC_KGRID_MP || kind == MLMC_KGRID_GAMMA || kind == MLMC_KGRID_RHOMBI;
+}
+
+LevelLayout level_layout(const mlmc_lattice_s *lat, int N, bool coupled, int Kf, int Kc, int kind, int64_t mc,
                          mlmc_precision prec, int n_eps, char *base) {
     LevelLayout L;
     Carver cv{base};
     const int G = lat->dev.n_groups, no = lat->dev.n_orb;
-    const int64_t nkf = (int64_t)Kf * Kf, nkc = (int64_t)Kc * Kc;
+    const int64_t nkf = kgrid_count(kind, Kf), nkc = kgrid_count(kind, Kc);
     const int64_t ldf = (int64_t)no * N * N;
     L.kf = cv.take<double>(sizeof(double) * 2 * nkf);
     L.kwf = cv.take<double>(sizeof(double) * nkf);
@@ -313,8 +317,16 @@ mlmc_status mlmc_partition_masks(mlmc_lattice lat, int32_t N, const uint8_t *d_m
     return MLMC_OK;
 }
 
+mlmc_status mlmc_kgrid_points(mlmc_kgrid_kind kind, int32_t K, int32_t *n_k) {
+    if (!valid_kgrid_kind(kind)) return fail(MLMC_ERR_INVALID_ARG, "kgrid_points: bad kind");
+    if (K < 1 || K > 4096) return fail(MLMC_ERR_INVALID_ARG, "kgrid_points: K = %d", K);
+    if (!n_k) return fail(MLMC_ERR_INVALID_ARG, "kgrid_points: NULL n_k");
+    *n_k = kgrid_count(kind, K);
+    return MLMC_OK;
+}
+
 mlmc_status mlmc_kgrid(mlmc_kgrid_kind kind, int32_t K, double *d_kred, double *d_kweight, mlmc_stream stream) {
-    if (kind != MLMC_KGRID_MP && kind != MLMC_KGRID_GAMMA) return fail(MLMC_ERR_INVALID_ARG, "kgrid: bad kind");
+    if (!valid_kgrid_kind(kind)) return fail(MLMC_ERR_INVALID_ARG, "kgrid: bad kind");
     if (K < 1 || K > 4096) return fail(MLMC_ERR_INVALID_ARG, "kgrid: K = %d", K);
     if (!d_kred || !d_kweight) return fail(MLMC_ERR_INVALID_ARG, "kgrid: NULL buffer");
     LAUNCH("kgrid", static_cast<hipStream_t>(stream), launch_kgrid(kind, K, d_kred, d_kweight, static_cast<hipStream_t>(stream)));
@@ -433,11 +445,13 @@ static mlmc_status check_level_args(mlmc_lattice lat, int32_t N, int32_t coupled
 }
 
 mlmc_status mlmc_level_workspace(mlmc_lattice lat, int32_t N_fine, int32_t coupled, int32_t K_fine, int32_t K_coarse,
-                                 int64_t chunk_samples, mlmc_precision prec, int32_t n_eps, size_t *bytes) {
+                                 mlmc_kgrid_kind kind, int64_t chunk_samples, mlmc_precision prec, int32_t n_eps,
+                                 size_t *bytes) {
     const mlmc_status st = check_level_args(lat, N_fine, coupled, K_fine, K_coarse, prec, n_eps);
     if (st != MLMC_OK) return st;
+    if (!valid_kgrid_kind(kind)) return fail(MLMC_ERR_INVALID_ARG, "level_workspace: bad k-grid");
     if (!bytes || chunk_samples < 1) return fail(MLMC_ERR_INVALID_ARG, "level_workspace: chunk_samples must be >= 1");
-    *bytes = level_layout(lat, N_fine, coupled != 0, K_fine, K_coarse, chunk_samples, prec, n_eps, nullptr).bytes;
+    *bytes = level_layout(lat, N_fine, coupled != 0, K_fine, K_coarse, kind, chunk_samples, prec, n_eps, nullptr).bytes;
     return MLMC_OK;
 }
 
@@ -450,30 +464,30 @@ mlmc_status mlmc_level_estimate(mlmc_lattice lat, int32_t N, int32_t coupled, do
     if (st != MLMC_OK) return st;
     if (!(p >= 0.0 && p <= 1.0)) return fail(MLMC_ERR_INVALID_ARG, "level: p = %g", p);
     if (!(delta > 0.0) || !std::isfinite(delta)) return fail(MLMC_ERR_INVALID_ARG, "level: delta = %g", delta);
-    if (kind != MLMC_KGRID_MP && kind != MLMC_KGRID_GAMMA) return fail(MLMC_ERR_INVALID_ARG, "level: bad k-grid");
+    if (!valid_kgrid_kind(kind)) return fail(MLMC_ERR_INVALID_ARG, "level: bad k-grid");
     if (smoother != MLMC_SMOOTH_GAUSS && smoother != MLMC_SMOOTH_CUBIC)
         return fail(MLMC_ERR_INVALID_ARG, "level: bad smoother");
     if (M < 0 || first_sample < 0) return fail(MLMC_ERR_INVALID_ARG, "level: negative sample range");
     if (M == 0) return MLMC_OK;
     if (!d_eps || !d_stats) return fail(MLMC_ERR_INVALID_ARG, "level: NULL buffer");
     const bool cpl = coupled != 0;
-    const size_t one = level_layout(lat, N, cpl, Kf, Kc, 1, prec, n_eps, nullptr).bytes;
+    const size_t one = level_layout(lat, N, cpl, Kf, Kc, kind, 1, prec, n_eps, nullptr).bytes;
     if (!d_work || work_bytes < one)
         return fail(MLMC_ERR_WORKSPACE, "level: workspace %zu < %zu bytes needed for one sample", work_bytes, one);
-    const size_t two = level_layout(lat, N, cpl, Kf, Kc, 2, prec, n_eps, nullptr).bytes;
+    const size_t two = level_layout(lat, N, cpl, Kf, Kc, kind, 2, prec, n_eps, nullptr).bytes;
     const size_t per = two - one, fixed = one - per;
     int64_t mc = (int64_t)((work_bytes - fixed) / per) + 2;  // padding makes the estimate approximate
     if (mc > M) mc = M;
     if (mc < 1) mc = 1;
-    while (mc > 1 && level_layout(lat, N, cpl, Kf, Kc, mc, prec, n_eps, nullptr).bytes > work_bytes) --mc;
-    const LevelLayout L = level_layout(lat, N, cpl, Kf, Kc, mc, prec, n_eps, static_cast<char *>(d_work));
+    while (mc > 1 && level_layout(lat, N, cpl, Kf, Kc, kind, mc, prec, n_eps, nullptr).bytes > work_bytes) --mc;
+    const LevelLayout L = level_layout(lat, N, cpl, Kf, Kc, kind, mc, prec, n_eps, static_cast<char *>(d_work));
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int G = lat->dev.n_groups, h = N / 2;
     const uint64_t tag = ((uint64_t)lat->dev.lattice_id << 32) | (uint64_t)(uint32_t)N;
     const uint64_t thr = (uint64_t)std::floor(p * 9007199254740992.0);
     const double inv_area_f = 1.0 / ((double)N * N * lat->dev.cell_area);
     const double inv_area_c = cpl ? 1.0 / ((double)h * h * lat->dev.cell_area) : 0.0;
-    const int nkf = Kf * Kf, nkc = cpl ? Kc * Kc : 0;
+    const int nkf = kgrid_count(kind, Kf), nkc = cpl ? kgrid_count(kind, Kc) : 0;
     LAUNCH("kgrid", s, launch_kgrid(kind, Kf, L.kf, L.kwf, s));
     if (cpl) LAUNCH("kgrid", s, launch_kgrid(kind, Kc, L.kc, L.kwc, s));
     for (int64_t done = 0; done < M; done += mc) {

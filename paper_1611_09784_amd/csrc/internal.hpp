@@ -78,6 +78,8 @@ hipError_t launch_sample_vacancies(const DevLattice &lat, int N, uint64_t thresh
                                    int64_t first, int64_t n_samples, uint8_t *mask, hipStream_t s);
 hipError_t launch_partition(int N, int G, const uint8_t *mask, int64_t n_samples, uint8_t *quarters, hipStream_t s);
 hipError_t launch_kgrid(int kind, int K, double *kred, double *kweight, hipStream_t s);
+// Number of points of a grid kind (K^2, or 3 K^2 for the three-rhombus lattice).
+int kgrid_count(int kind, int K);
 
 template <typename T>
 hipError_t launch_assemble(const DevLattice &lat, int N, const uint8_t *masks, int64_t n_samples, const double *kred,

@@ -87,6 +87,17 @@ hipError_t launch_partition(int N, int G, const uint8_t *mask, int64_t n_samples
 
 __global__ void kgrid_kernel(int kind, int K, double *__restrict__ kred, double *__restrict__ kweight) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (kind == MLMC_KGRID_RHOMBI) {
+        // point t = a*K + j: a in [0, 3K), b = (-a mod 3) + 3j, kappa = (a, b) / (3K)
+        const int M3 = 3 * K;
+        if (t >= M3 * K) return;
+        const int a = t / K, j = t % K;
+        const int b = (3 - a % 3) % 3 + 3 * j;
+        kred[2 * t] = (double)a / (double)M3;
+        kred[2 * t + 1] = (double)b / (double)M3;
+        kweight[t] = 1.0 / ((double)M3 * (double)K);
+        return;
+    }
     if (t >= K * K) return;
     const int r1 = t / K, r2 = t % K;
     if (kind == MLMC_KGRID_MP) {
@@ -99,9 +110,11 @@ __global__ void kgrid_kernel(int kind, int K, double *__restrict__ kred, double 
     kweight[t] = 1.0 / ((double)K * (double)K);
 }
 
+int kgrid_count(int kind, int K) { return kind == MLMC_KGRID_RHOMBI ? 3 * K * K : K * K; }
+
 hipError_t launch_kgrid(int kind, int K, double *kred, double *kweight, hipStream_t s) {
     const int threads = 256;
-    const int blocks = (K * K + threads - 1) / threads;
+    const int blocks = (kgrid_count(kind, K) + threads - 1) / threads;
     hipLaunchKernelGGL(kgrid_kernel, dim3(blocks), dim3(threads), 0, s, kind, K, kred, kweight);
     return hipGetLastError();
 }

@@ -69,8 +69,8 @@ class Estimator:
     def _workspace(self, lvl: LevelState):
         key = (lvl.N, lvl.coupled, lvl.K, lvl.K_coarse)
         if key not in self._work:
-            need = B.mlmc_level_workspace(self.dlat, lvl.N, lvl.coupled, lvl.K, lvl.K_coarse, self.chunk, self.prec,
-                                          self.eps.shape[0])
+            need = B.mlmc_level_workspace(self.dlat, lvl.N, lvl.coupled, lvl.K, lvl.K_coarse, self.kind, self.chunk,
+                                          self.prec, self.eps.shape[0])
             self._work[key] = torch.empty((need,), dtype=torch.uint8, device=self.dlat.device)
         return self._work[key]
 

@@ -88,3 +88,14 @@ def test_lattice_descriptor_layout(B):
     # the binding's ctypes structs match the C layout (8-byte aligned doubles)
     assert C.sizeof(B._Hop) == 32
     assert C.sizeof(B._LatticeDesc) == 56
+
+
+def test_kgrid_points_host_only(B):
+    from oracle import kgrid_points
+    for kind in (B.MLMC_KGRID_MP, B.MLMC_KGRID_GAMMA, B.MLMC_KGRID_RHOMBI):
+        for K in (1, 2, 7):
+            assert B.mlmc_kgrid_points(kind, K) == kgrid_points(kind, K)
+    out = C.c_int32()
+    assert B.lib().mlmc_kgrid_points(3, 4, C.byref(out)) == B.MLMC_ERR_INVALID_ARG
+    assert B.lib().mlmc_kgrid_points(2, 0, C.byref(out)) == B.MLMC_ERR_INVALID_ARG
+    assert B.lib().mlmc_kgrid_points(2, 4, None) == B.MLMC_ERR_INVALID_ARG

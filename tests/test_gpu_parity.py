@@ -99,7 +99,7 @@ def test_partition_bit_exact(B, gdev, mdev, name, N):
         assert np.array_equal(got[s], oracle.partition_masks(m[s]))
 
 
-@pytest.mark.parametrize("kind,K", [(0, 1), (0, 4), (0, 8), (1, 1), (1, 6), (0, 7)])
+@pytest.mark.parametrize("kind,K", [(0, 1), (0, 4), (0, 8), (1, 1), (1, 6), (0, 7), (2, 1), (2, 2), (2, 5), (2, 8)])
 def test_kgrid(B, kind, K):
     say(f"[kgrid] kind={kind} K={K}")
     kred, kw = B.mlmc_kgrid(kind, K)
@@ -271,6 +271,8 @@ def compare_stats(got, want, M, tol):
     ("mos2", 4, True, 2, 4, 1, 3, 0),           # MoS2-shaped fine n=176 (device-memory path)
     ("graphene", 8, True, 2, 4, 1, 6, 1),       # mixed precision, fused path
     ("mos2", 4, False, 2, 2, 0, 3, 1),          # mixed precision, fused path at n=176
+    ("graphene", 8, True, 1, 2, 2, 4, 0),       # three-rhombus k-lattice (3 K^2 points), coupled
+    ("graphene", 4, False, 2, 2, 2, 6, 1),      # three-rhombus k-lattice, mixed precision
     ("graphene", 16, False, 1, 1, 0, 2, 1),     # mixed precision, device-memory path
 ])
 def test_level_estimate_parity(B, gdev, mdev, name, N, coupled, K, Kc, kind, M, prec):
@@ -297,7 +299,7 @@ def test_level_estimate_full_size_sample(B, gdev, glat):
     eps = energy_grid(-9.0, 9.0, 401)
     d_eps = torch.as_tensor(eps, device=DEV)
     chunk = 16
-    need = B.mlmc_level_workspace(gdev, N, False, K, K, chunk, B.MLMC_PREC_FP64, eps.size)
+    need = B.mlmc_level_workspace(gdev, N, False, K, K, B.MLMC_KGRID_MP, chunk, B.MLMC_PREC_FP64, eps.size)
     work = torch.empty((need,), dtype=torch.uint8, device=DEV)
     first = 1234
     got = B.mlmc_level_estimate(gdev, N, False, p, K, K, 0, seed, first, 1, d_eps, delta, work=work).cpu().numpy()
