@@ -26,7 +26,8 @@ Two lattices are provided:
   top-S p x3 and bottom-S p x3 on site B).  Its parameters are random
   (iid uniform on [-1.5, 1.5] eV), drawn once from ``param_seed`` in the fixed
   order documented in :func:`mos2_shaped`.  Mo is never removed; each S site
-  is its own 3-orbital removable group.
+  is its own 3-orbital removable group, or (``s_pairs``) the two S of a cell
+  are removed together as one 6-orbital group.
 """
 
 from __future__ import annotations
@@ -118,8 +119,13 @@ NN_DIRS = [(0, 0), (-1, 0), (0, -1)]          # A -> B nearest-neighbour cells
 SAME_SUBLATTICE_DIRS = [(1, 0), (0, 1), (-1, 1)]  # a1, a2, a2 - a1
 
 
-def mos2_shaped(param_seed: int = 4040, a: float = 3.19, scale: float = 1.5) -> Lattice:
+def mos2_shaped(param_seed: int = 4040, a: float = 3.19, scale: float = 1.5, s_pairs: bool = False) -> Lattice:
     """MoS2-shaped 11-orbital honeycomb model with random real parameters.
+
+    Vacancy groups: Mo (never removed) and, by default, each S site on its
+    own (3 orbitals).  With ``s_pairs`` the top and bottom S of a cell form one
+    6-orbital group removed together (the S-pair vacancies of Section 3.2);
+    that lattice has its own id, so its vacancy stream is independent.
 
     Draw order (one ``Generator(Philox(param_seed)).uniform(-scale, scale)``
     stream, consumed in this order):
@@ -153,16 +159,21 @@ def mos2_shaped(param_seed: int = 4040, a: float = 3.19, scale: float = 1.5) -> 
                 for mp in block:
                     rows.append((R1, R2, m, mp, u(), 0.0))
     frac = np.array([[0.0, 0.0]] * 5 + [[1.0 / 3.0, 1.0 / 3.0]] * 6)
-    group = np.array([0] * 5 + [1] * 3 + [2] * 3, dtype=np.int32)
+    if s_pairs:
+        group = np.array([0] * 5 + [1] * 6, dtype=np.int32)
+        removable = np.array([0, 1], dtype=np.uint8)
+    else:
+        group = np.array([0] * 5 + [1] * 3 + [2] * 3, dtype=np.int32)
+        removable = np.array([0, 1, 1], dtype=np.uint8)
     return Lattice(
-        name="mos2_shaped",
-        lattice_id=2,
+        name="mos2_shaped_spairs" if s_pairs else "mos2_shaped",
+        lattice_id=3 if s_pairs else 2,
         a1=(a, 0.0),
         a2=(0.5 * a, 0.5 * math.sqrt(3.0) * a),
         cell_area=0.5 * math.sqrt(3.0) * a * a,
         orb_frac=frac,
         orb_group=group,
-        group_removable=np.array([0, 1, 1], dtype=np.uint8),
+        group_removable=removable,
         hops=_hops(rows),
     )
 
@@ -172,4 +183,6 @@ def lattice_by_name(name: str) -> Lattice:
         return graphene()
     if name in ("mos2_shaped", "mos2"):
         return mos2_shaped()
+    if name in ("mos2_shaped_spairs", "mos2_spairs"):
+        return mos2_shaped(s_pairs=True)
     raise ValueError(f"unknown lattice {name!r}")

@@ -22,3 +22,9 @@ def glat():
 def mlat():
     from mlmc_inputs import mos2_shaped
     return mos2_shaped()
+
+
+@pytest.fixture(scope="session")
+def plat():
+    from mlmc_inputs import mos2_shaped
+    return mos2_shaped(s_pairs=True)

@@ -337,3 +337,30 @@ def test_error_codes(B, gdev):
     with pytest.raises(B.MLMCError) as e:
         B.mlmc_level_estimate(gdev, 64, False, 0.1, 1, 1, 1, 0, 0, 1, eps, 0.1)
     assert e.value.status == B.MLMC_ERR_UNSUPPORTED
+
+
+# ---------------------------------------------------------------------------
+# S-pair vacancies (MoS2-shaped lattice with 6-orbital S-pair groups)
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def pdev(B):
+    d = B.DeviceLattice(mos2_shaped(s_pairs=True), 0)
+    yield d
+    d.close()
+
+
+@pytest.mark.parametrize("coupled,K,Kc,prec", [(True, 2, 4, 0), (False, 2, 2, 1), (False, 1, 1, 0)])
+def test_spairs_level_parity(B, pdev, coupled, K, Kc, prec):
+    say(f"[S pairs] coupled={coupled} K={K} Kc={Kc} prec={prec}")
+    N = 4
+    tag = pdev.tag(N)
+    got = B.mlmc_sample_vacancies(pdev, N, 0.3, 21, tag, 5, 9).cpu().numpy()
+    assert np.array_equal(got, oracle.sample_vacancies(pdev.lat, N, 0.3, 21, tag, 5, 9))
+    b = pdev.lat.hop_magnitude_bound() + 1.0
+    eps = energy_grid(-b, b, 201)
+    M = 3
+    got = B.mlmc_level_estimate(pdev, N, coupled, 0.1, K, Kc, 1, 404, 5, M, torch.as_tensor(eps, device=DEV), 0.1,
+                                prec=prec).cpu().numpy()
+    want = oracle.level_estimate(pdev.lat, N, coupled, 0.1, K, Kc, 1, 404, 5, M, eps, 0.1, 0, n_threads=8)
+    compare_stats(got, want, M, 1e-10 if prec == 0 else 1e-5)
