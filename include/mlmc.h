@@ -236,6 +236,14 @@ mlmc_status mlmc_level_estimate(mlmc_lattice lat, int32_t N_fine, int32_t couple
 mlmc_status mlmc_optimal_samples(int32_t L, const double *V, const double *W, double C_alpha, double theta,
                                  double tol, double *M_out);
 
+/* Density of states from the integrated density of states by numerical
+ * differentiation (Section 4.3): on the increasing energy grid eps[0..n_eps)
+ * dos[j] approximates dI/deps at eps[j] with the second-order three-point
+ * formula, centred at interior points (unequal spacings allowed) and
+ * one-sided at the two ends.  Host arrays; no device work.
+ * Errors: n_eps < 3, NULL pointer, eps not strictly increasing. */
+mlmc_status mlmc_dos(int32_t n_eps, const double *eps, const double *idos, double *dos);
+
 /* Diagnostics (off by default): per-kernel launch timing with HIP events.
  * While enabled, each kernel launch of this library records a start/stop
  * event pair on the stream it is launched on (creating two events per

@@ -77,6 +77,13 @@ def exhaustive_expectation(lat, N, p, K, kind, eps, delta, smoother):
     return acc
 
 
+def dos_from_idos(eps, idos):
+    """Density of states as the derivative of the IDoS on the energy grid
+    (Section 4.3, numerical differentiation): second-order differences,
+    centred inside and one-sided at the ends (numpy.gradient, edge_order 2)."""
+    return np.gradient(np.asarray(idos, dtype=np.float64), np.asarray(eps, dtype=np.float64), edge_order=2)
+
+
 def run_mlmc(lat, levels, Ks, p, kind, seed, eps, delta, smoother, tol_rel, C_alpha=2.0, theta=0.5,
              pilot=16, max_rounds=8, n_threads=1, max_samples=None):
     """Adaptive-sample MLMC driver over fixed levels (eq. (MLMC) + eq. (opt_samples)).

@@ -80,6 +80,7 @@ SIGNATURES = {
     "mlmc_level_estimate": (C.c_int, [P, I32, I32, DBL, I32, I32, C.c_int, U64, I64, I64, P, I32, DBL, C.c_int,
                                       C.c_int, P, P, SZ, P]),
     "mlmc_optimal_samples": (C.c_int, [I32, P, P, DBL, DBL, DBL, P]),
+    "mlmc_dos": (C.c_int, [I32, P, P, P]),
     "mlmc_timer_enable": (C.c_int, [I32]),
     "mlmc_timer_read": (C.c_int, [C.c_char_p, P, P]),
 }
@@ -344,6 +345,17 @@ def mlmc_optimal_samples(V, W, C_alpha, theta, tol) -> np.ndarray:
     out = np.zeros_like(V)
     _check(lib().mlmc_optimal_samples(V.shape[0], _ptr(V), _ptr(W), float(C_alpha), float(theta), float(tol),
                                       _ptr(out)), "mlmc_optimal_samples")
+    return out
+
+
+def mlmc_dos(eps, idos) -> np.ndarray:
+    """Density of states from an IDoS on an increasing energy grid (host arrays)."""
+    eps = np.ascontiguousarray(eps, dtype=np.float64)
+    idos = np.ascontiguousarray(idos, dtype=np.float64)
+    if eps.shape != idos.shape or eps.ndim != 1:
+        raise ValueError("mlmc_dos: eps and idos must be 1-d arrays of one length")
+    out = np.zeros_like(idos)
+    _check(lib().mlmc_dos(eps.shape[0], _ptr(eps), _ptr(idos), _ptr(out)), "mlmc_dos")
     return out
 
 

@@ -509,6 +509,27 @@ mlmc_status mlmc_level_estimate(mlmc_lattice lat, int32_t N, int32_t coupled, do
     return MLMC_OK;
 }
 
+mlmc_status mlmc_dos(int32_t n_eps, const double *eps, const double *idos, double *dos) {
+    if (n_eps < 3 || !eps || !idos || !dos) return fail(MLMC_ERR_INVALID_ARG, "dos: need n_eps >= 3 and buffers");
+    for (int j = 1; j < n_eps; ++j)
+        if (!(eps[j] > eps[j - 1])) return fail(MLMC_ERR_INVALID_ARG, "dos: eps not increasing at %d", j);
+    // f'(x1) from f(x0), f(x1), f(x2) with a = x1 - x0, b = x2 - x1: exact for quadratics
+    for (int j = 1; j + 1 < n_eps; ++j) {
+        const double a = eps[j] - eps[j - 1], b = eps[j + 1] - eps[j];
+        dos[j] = (-b / (a * (a + b))) * idos[j - 1] + ((b - a) / (a * b)) * idos[j] + (a / (b * (a + b))) * idos[j + 1];
+    }
+    {
+        const double a = eps[1] - eps[0], b = eps[2] - eps[1];
+        dos[0] = (-(2.0 * a + b) / (a * (a + b))) * idos[0] + ((a + b) / (a * b)) * idos[1] - (a / (b * (a + b))) * idos[2];
+    }
+    {
+        const int k = n_eps - 1;
+        const double a = eps[k - 1] - eps[k - 2], b = eps[k] - eps[k - 1];
+        dos[k] = (b / (a * (a + b))) * idos[k - 2] - ((a + b) / (a * b)) * idos[k - 1] + ((2.0 * b + a) / (b * (a + b))) * idos[k];
+    }
+    return MLMC_OK;
+}
+
 mlmc_status mlmc_optimal_samples(int32_t L, const double *V, const double *W, double C_alpha, double theta, double tol,
                                  double *M_out) {
     if (L < 1 || !V || !W || !M_out) return fail(MLMC_ERR_INVALID_ARG, "optimal_samples: bad argument");

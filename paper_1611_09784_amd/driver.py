@@ -58,13 +58,17 @@ class Estimator:
 
     def __init__(self, dlat: B.DeviceLattice, eps: np.ndarray, delta: float, p: float, kind: int, seed: int,
                  smoother: int = B.MLMC_SMOOTH_GAUSS, prec: int = B.MLMC_PREC_FP64, chunk_samples: int = 64,
-                 stream=None):
+                 stream=None, dedup_max_orbitals: int = 0):
         self.dlat = dlat
         self.eps = torch.as_tensor(np.asarray(eps, dtype=np.float64), device=dlat.device)
         self.delta, self.p, self.kind, self.seed = float(delta), float(p), int(kind), int(seed)
         self.smoother, self.prec, self.chunk = int(smoother), int(prec), int(chunk_samples)
         self.stream = stream
         self._work = {}
+        # levels whose matrices have at most this many orbitals solve each
+        # distinct outcome once (0: off)
+        self.dedup_max_orbitals = int(dedup_max_orbitals)
+        self.unique_solved = 0
 
     def _workspace(self, lvl: LevelState):
         key = (lvl.N, lvl.coupled, lvl.K, lvl.K_coarse)
@@ -80,13 +84,111 @@ class Estimator:
         stats = torch.zeros((4, self.eps.shape[0]), dtype=torch.float64, device=self.dlat.device)
         torch.cuda.synchronize(self.dlat.device)
         t0 = time.perf_counter()
-        B.mlmc_level_estimate(self.dlat, lvl.N, lvl.coupled, self.p, lvl.K, lvl.K_coarse, self.kind, self.seed,
-                              lvl.M, count, self.eps, self.delta, self.smoother, self.prec, stats=stats,
-                              work=self._workspace(lvl), stream=self.stream)
+        if self.dedup_max_orbitals and self.dlat.max_orbitals(lvl.N) <= self.dedup_max_orbitals:
+            self._add_deduplicated(lvl, count, stats)
+        else:
+            B.mlmc_level_estimate(self.dlat, lvl.N, lvl.coupled, self.p, lvl.K, lvl.K_coarse, self.kind, self.seed,
+                                  lvl.M, count, self.eps, self.delta, self.smoother, self.prec, stats=stats,
+                                  work=self._workspace(lvl), stream=self.stream)
         host = stats.cpu().numpy()
         lvl.seconds += time.perf_counter() - t0
         lvl.stats = host if lvl.stats is None else lvl.stats + host
         lvl.M += count
+
+    # -- explicit outcomes (steps a3-a7 through the C ABI) -------------------
+    def outcome_idos(self, N: int, masks: torch.Tensor, K: int, budget_bytes: int = 1 << 30) -> torch.Tensor:
+        """IDoS [ns][n_eps] of the given vacancy outcomes masks [ns][N][N][G]
+        (device, uint8) on the K grid of the N x N supercell."""
+        dev = self.dlat.device
+        ns = masks.shape[0]
+        kred, kw = B.mlmc_kgrid(self.kind, K, device=dev.index, stream=self.stream)
+        nk = kred.shape[0]
+        ld = self.dlat.max_orbitals(N)
+        esize = 16 if self.prec == B.MLMC_PREC_FP64 else 8
+        chunk = max(1, budget_bytes // max(1, nk * ld * ld * esize))
+        out = torch.empty((ns, self.eps.shape[0]), dtype=torch.float64, device=dev)
+        dtype = B.MLMC_C128 if self.prec == B.MLMC_PREC_FP64 else B.MLMC_C64
+        area = N * N * self.dlat.lat.cell_area
+        for a in range(0, ns, chunk):
+            b = min(ns, a + chunk)
+            H, n = B.mlmc_build_hamiltonians(self.dlat, N, masks[a:b].contiguous(), kred, dtype, stream=self.stream)
+            w = B.mlmc_batched_eigvalsh(H, n, prec=self.prec, stream=self.stream)
+            B.mlmc_idos(w, n, nk, kw, area, self.eps, self.delta, self.smoother, out=out[a:b], stream=self.stream)
+            del H
+        return out
+
+    def _add_deduplicated(self, lvl: LevelState, count: int, stats: torch.Tensor):
+        """Samples lvl.M .. lvl.M + count - 1 with each distinct outcome solved
+        once (Section 4.4: identical outcomes are identified beforehand and not
+        recomputed).  Uncoupled levels identify outcomes up to a translation of
+        the supercell (which leaves every H(k) spectrum unchanged); coupled
+        levels identify equal outcomes only, since the quarters depend on the
+        position of the vacancies."""
+        N = lvl.N
+        masks = B.mlmc_sample_vacancies(self.dlat, N, self.p, self.seed, self.dlat.tag(N), lvl.M, count,
+                                        stream=self.stream)
+        keys = outcome_keys(masks.cpu().numpy(), self.dlat.lat.group_removable, translations=not lvl.coupled)
+        _, first, inverse = np.unique(keys, return_index=True, return_inverse=True)
+        rep = masks[torch.as_tensor(first, device=masks.device)]
+        inv = torch.as_tensor(inverse.reshape(-1), device=masks.device)
+        Qf = self.outcome_idos(N, rep, lvl.K)[inv].contiguous()
+        Qq = None
+        if lvl.coupled:
+            h = N // 2
+            quarters = B.mlmc_partition_masks(self.dlat, N, rep, stream=self.stream)
+            G = self.dlat.lat.n_groups
+            Qq_rep = self.outcome_idos(h, quarters.reshape(-1, h, h, G), lvl.K_coarse)
+            Qq = Qq_rep.reshape(rep.shape[0], 4, -1)[inv].contiguous()
+        B.mlmc_level_stats(Qf, Qq, stats=stats, stream=self.stream)
+        self.unique_solved += int(first.size)
+
+    def exhaustive_expectation(self, N: int, K: int) -> np.ndarray:
+        """E[Q_N] over every vacancy outcome of the N x N supercell, each with
+        probability p^v (1-p)^(r-v) (Sections 1 and 4.4); outcomes equal up to
+        a translation of the supercell are solved once and weighted by the
+        size of their class."""
+        lat = self.dlat.lat
+        G = lat.n_groups
+        slots = [g for g in range(N * N * G) if lat.group_removable[g % G]]
+        r = len(slots)
+        if r > 24:
+            raise ValueError(f"exhaustive enumeration of 2^{r} outcomes is not supported")
+        codes = np.arange(1 << r, dtype=np.int64)
+        masks = np.zeros((codes.size, N * N * G), dtype=np.uint8)
+        for i, g in enumerate(slots):
+            masks[:, g] = (codes >> i) & 1
+        masks = masks.reshape(-1, N, N, G)
+        keys = outcome_keys(masks, lat.group_removable, translations=True)
+        _, first, inverse = np.unique(keys, return_index=True, return_inverse=True)
+        v = masks.reshape(codes.size, -1).sum(axis=1)
+        prob = (self.p ** v) * ((1.0 - self.p) ** (r - v))
+        weight = np.bincount(inverse.reshape(-1), weights=prob, minlength=first.size)
+        rep = torch.as_tensor(masks[first], device=self.dlat.device)
+        Q = self.outcome_idos(N, rep, K).cpu().numpy()
+        self.unique_solved += int(first.size)
+        return weight @ Q
+
+
+def outcome_keys(masks: np.ndarray, removable: np.ndarray, translations: bool) -> np.ndarray:
+    """One key per outcome ([n][N][N][G] uint8): equal keys for equal outcomes,
+    or, with ``translations``, for outcomes equal up to a translation of the
+    supercell (the smallest code over the N^2 cyclic shifts)."""
+    n, N, _, G = masks.shape
+    rem = np.flatnonzero(np.asarray(removable, dtype=bool))
+    bits = masks[..., rem]                      # [n][N][N][R]
+    nbits = N * N * rem.size
+    if translations and nbits <= 62:
+        weights = (np.int64(1) << np.arange(nbits, dtype=np.int64))
+        best = None
+        for a in range(N):
+            for b in range(N):
+                code = np.roll(bits, (a, b), axis=(1, 2)).reshape(n, -1).astype(np.int64) @ weights
+                best = code if best is None else np.minimum(best, code)
+        return best
+    if translations:
+        raise ValueError("translation classes need at most 62 removable sites")
+    packed = np.packbits(bits.reshape(n, -1), axis=1)
+    return np.ascontiguousarray(packed).view(np.dtype((np.void, packed.shape[1]))).reshape(-1)
 
 
 def make_levels(levels, Ks):
@@ -99,36 +201,64 @@ def make_levels(levels, Ks):
 
 
 def run_mlmc(est: Estimator, levels, Ks, tol_rel: float, C_alpha: float = 2.0, theta: float = 0.5, pilot: int = 16,
-             max_rounds: int = 10, max_samples: int = 1_000_000) -> MLMCResult:
-    """Adaptive-sample MLMC over fixed levels (eq. (MLMC), eq. (opt_samples))."""
+             max_rounds: int = 10, max_samples: int = 1_000_000, exact_first: bool = False,
+             tol_sequence=None) -> MLMCResult:
+    """Adaptive-sample MLMC over fixed levels (eq. (MLMC), eq. (opt_samples)).
+
+    exact_first: level 1 is the exhaustive expectation over every outcome of
+    its (small) supercell instead of a sample mean (Section 4.4); it then adds
+    no variance and takes no part in the allocation.
+    tol_sequence: relative tolerances worked through in order before tol_rel
+    (continuation: each stage re-estimates V_l and W_l from all samples so far
+    and allocates for its own tolerance; samples are kept from stage to stage).
+    """
     lv = make_levels(levels, Ks)
     t0 = time.perf_counter()
-    target = [pilot] * len(lv)
+    exact = None
+    if exact_first:
+        t1 = time.perf_counter()
+        exact = est.exhaustive_expectation(lv[0].N, lv[0].K)
+        lv[0].seconds = time.perf_counter() - t1
+    sampled = lv[1:] if exact_first else lv
+    target = [pilot] * len(sampled)
     rounds = []
     err = tol_abs = float("inf")
     estimate = None
-    for _ in range(max_rounds):
-        for l, st in enumerate(lv):
-            est.add_samples(st, min(target[l], max_samples) - st.M)
+    stages = list(tol_sequence or []) + [tol_rel]
+    stage = 0
+    for _ in range(max_rounds * len(stages)):
+        for t, st in zip(target, sampled):
+            est.add_samples(st, min(t, max_samples) - st.M)
         means, V = [], []
-        for st in lv:
+        for st in sampled:
             m, v = st.mean_var()
             means.append(m)
             V.append(max(float(v.max()), 1e-300))
-        W = [st.seconds / st.M for st in lv]
-        estimate = np.sum(means, axis=0)
+        W = [st.seconds / st.M for st in sampled]
+        estimate = np.sum(means, axis=0) + (exact if exact is not None else 0.0)
         tol_abs = tol_rel * float(np.max(np.abs(estimate)))
-        M = [st.M for st in lv]
+        stage_tol = stages[stage] * float(np.max(np.abs(estimate)))
+        M = [st.M for st in sampled]
         err = C_alpha * math.sqrt(sum(v / m for v, m in zip(V, M)))
-        rounds.append({"M": M, "V": V, "W": W, "error": err, "tol_abs": tol_abs})
+        rounds.append({"M": M, "V": V, "W": W, "error": err, "tol_abs": tol_abs, "stage_tol_rel": stages[stage],
+                       "stage_tol_abs": stage_tol})
         if err <= theta * tol_abs:
             break
-        Mopt = B.mlmc_optimal_samples(V, W, C_alpha, theta, tol_abs)
-        target = [max(st.M, int(math.ceil(m))) for st, m in zip(lv, Mopt)]
-        if all(st.M >= max_samples for st in lv):
+        while stage + 1 < len(stages) and err <= theta * stage_tol:
+            stage += 1
+            stage_tol = stages[stage] * float(np.max(np.abs(estimate)))
+        Mopt = B.mlmc_optimal_samples(V, W, C_alpha, theta, stage_tol)
+        target = [max(st.M, int(math.ceil(m))) for st, m in zip(sampled, Mopt)]
+        if all(st.M >= max_samples for st in sampled):
             break
     return MLMCResult(estimate=estimate, levels=lv, error=err, tol_abs=tol_abs, seconds=time.perf_counter() - t0,
                       rounds=rounds)
+
+
+def continuation_tolerances(tol_rel: float, stages: int = 3, ratio: float = 2.0):
+    """Relative tolerances ratio^s * tol_rel for s = stages .. 1 (largest first),
+    the sequence a continuation MLMC works through before tol_rel."""
+    return [tol_rel * ratio ** s for s in range(stages, 0, -1)]
 
 
 def run_mc(est: Estimator, N: int, K: int, M: int) -> LevelState:
