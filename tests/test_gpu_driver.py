@@ -91,7 +91,8 @@ def test_mlmc_with_exact_first_level_and_continuation(B):
     try:
         est = D.Estimator(dl, eps, 0.1, 0.05, KGRID_GAMMA, 303, SMOOTH_GAUSS, B.MLMC_PREC_FP64,
                           dedup_max_orbitals=128)
-        res = D.run_mlmc(est, [2, 4, 8], [8, 4, 2], 5e-3, tol_sequence=D.continuation_tolerances(5e-3, 2))
+        res = D.run_mlmc(est, [2, 4, 8], [8, 4, 2], 5e-3, exact_first=True,
+                         tol_sequence=D.continuation_tolerances(5e-3, 2))
     finally:
         dl.close()
     assert res.levels[0].M == 0
