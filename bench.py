@@ -141,11 +141,13 @@ def copy_calibration():
 
 def time_to_tol(B, dev):
     """MLMC IDoS estimator of the graphene level hierarchy N = 4, 8, 16, 32
-    (Gamma-centred K = 32 / N, p = 0.02, seed 303) run to TOL = 1e-3 relative,
-    once with the FP64 path and once with the mixed path (FP32 reduction, FP64
-    bisection and sums).  Beside each time: the per-level samples, the final
-    statistical error, and for the mixed path the largest IDoS difference from
-    the FP64 path on the same 8 coupled samples of every level."""
+    (Gamma-centred K = 32 / N, p = 0.02, seed 303) run to TOL = 1e-3 relative
+    with the FP64 path, the mixed path (FP32 reduction, FP64 bisection and
+    sums), and the mixed path that solves each distinct outcome of the two
+    smallest supercells once (identical outcomes identified beforehand).
+    Beside each time: the per-level samples, the final statistical error, and
+    for the mixed path the largest IDoS difference from the FP64 path on the
+    same 8 coupled samples of every level."""
     import torch
     from mlmc_inputs import WORKLOADS
     from mlmc_inputs.configs import workload_eps
@@ -157,8 +159,10 @@ def time_to_tol(B, dev):
     dlat = B.DeviceLattice(lat, 0)
     Ks = [wl.NK // N for N in wl.levels]
     out = {"workload": wl.name, "levels": list(wl.levels), "K": Ks, "tol_rel": wl.tol}
-    for name, prec in (("fp64", B.MLMC_PREC_FP64), ("mixed", B.MLMC_PREC_MIXED)):
-        est = D.Estimator(dlat, eps, wl.delta, wl.p, wl.kgrid, wl.seed, wl.smoother, prec, chunk_samples=32)
+    for name, prec, dedup in (("fp64", B.MLMC_PREC_FP64, 0), ("mixed", B.MLMC_PREC_MIXED, 0),
+                              ("mixed_reuse", B.MLMC_PREC_MIXED, 128)):
+        est = D.Estimator(dlat, eps, wl.delta, wl.p, wl.kgrid, wl.seed, wl.smoother, prec, chunk_samples=32,
+                          dedup_max_orbitals=dedup)
         for st in D.make_levels(wl.levels, Ks):  # warm-up: workspaces and first launches
             est.add_samples(st, 2)
         torch.cuda.synchronize(dev)
@@ -166,6 +170,8 @@ def time_to_tol(B, dev):
         out[name] = {"seconds": round(r.seconds, 3), "M": [st.M for st in r.levels], "error": r.error,
                      "tol_abs": r.tol_abs, "rounds": len(r.rounds),
                      "seconds_per_level": [round(st.seconds, 3) for st in r.levels]}
+        if dedup:
+            out[name]["distinct_outcomes_solved"] = est.unique_solved
         print(f"[bench] time-to-TOL {name}: {r.seconds:.2f} s, M = {[st.M for st in r.levels]}", file=sys.stderr,
               flush=True)
     # precision error of the mixed path: same samples, both precisions
@@ -180,6 +186,7 @@ def time_to_tol(B, dev):
         errs.append(float(np.max(np.abs(q["mixed"] - q["fp64"]))))
     out["mixed_idos_err_per_level"] = errs
     out["speedup_mixed_vs_fp64"] = round(out["fp64"]["seconds"] / out["mixed"]["seconds"], 3)
+    out["speedup_mixed_reuse_vs_fp64"] = round(out["fp64"]["seconds"] / out["mixed_reuse"]["seconds"], 3)
     dlat.close()
     return out
 
