@@ -8,5 +8,5 @@ estimators), so that the oracle and the GPU path can both consume it
 without sharing any computation.
 """
 
-from .lattices import Lattice, graphene, mos2_shaped, lattice_by_name  # noqa: F401
+from .lattices import Lattice, graphene, graphene_overlap, mos2_shaped, lattice_by_name  # noqa: F401
 from .configs import WORKLOADS, energy_grid, Workload  # noqa: F401

@@ -54,6 +54,9 @@ class Lattice:
     orb_group: np.ndarray      # [n_orb] int32
     group_removable: np.ndarray  # [n_groups] uint8
     hops: np.ndarray           # [n_hops] HOP_DTYPE
+    # Non-orthogonal basis: S(k) = I + Bloch sum of this table (HOP_DTYPE), or
+    # None for an orthogonal basis (S = I).
+    overlap: np.ndarray = None
 
     @property
     def n_orb(self) -> int:
@@ -66,6 +69,10 @@ class Lattice:
     @property
     def n_hops(self) -> int:
         return int(self.hops.shape[0])
+
+    @property
+    def has_overlap(self) -> bool:
+        return self.overlap is not None
 
     def max_orbitals(self, N: int) -> int:
         """Matrix side of the pristine N x N supercell."""
@@ -110,6 +117,30 @@ def graphene(t: float = -2.7, a: float = 2.46) -> Lattice:
         orb_group=np.array([0, 1], dtype=np.int32),
         group_removable=np.array([1, 1], dtype=np.uint8),
         hops=_hops(rows),
+    )
+
+
+def graphene_overlap(t: float = -3.033, s: float = 0.129, eps_2p: float = 0.0, a: float = 2.46) -> Lattice:
+    """Graphene in the non-orthogonal nearest-neighbour model of Section 3.1:
+    hopping t and overlap s on the three A-B bonds, on-site energy eps_2p and
+    unit on-site overlap, i.e. the generalised problem H c = E S c with
+    S = I + s (bond Bloch sum).  Groups and geometry as in ``graphene``; its
+    own lattice id, so its vacancy stream is independent."""
+    rows = [(0, 0, 0, 1, t, 0.0), (-1, 0, 0, 1, t, 0.0), (0, -1, 0, 1, t, 0.0)]
+    if eps_2p != 0.0:
+        rows += [(0, 0, 0, 0, eps_2p, 0.0), (0, 0, 1, 1, eps_2p, 0.0)]
+    ovl = [(0, 0, 0, 1, s, 0.0), (-1, 0, 0, 1, s, 0.0), (0, -1, 0, 1, s, 0.0)]
+    return Lattice(
+        name="graphene_overlap",
+        lattice_id=4,
+        a1=(a, 0.0),
+        a2=(0.5 * a, 0.5 * math.sqrt(3.0) * a),
+        cell_area=0.5 * math.sqrt(3.0) * a * a,
+        orb_frac=np.array([[0.0, 0.0], [1.0 / 3.0, 1.0 / 3.0]]),
+        orb_group=np.array([0, 1], dtype=np.int32),
+        group_removable=np.array([1, 1], dtype=np.uint8),
+        hops=_hops(rows),
+        overlap=_hops(ovl),
     )
 
 
@@ -185,4 +216,6 @@ def lattice_by_name(name: str) -> Lattice:
         return mos2_shaped()
     if name in ("mos2_shaped_spairs", "mos2_spairs"):
         return mos2_shaped(s_pairs=True)
+    if name == "graphene_overlap":
+        return graphene_overlap()
     raise ValueError(f"unknown lattice {name!r}")

@@ -39,6 +39,9 @@ class _OraLattice(C.Structure):
         ("orb_frac", C.c_void_p), ("orb_group", C.c_void_p), ("removable", C.c_void_p),
         ("hop_R", C.c_void_p), ("hop_from", C.c_void_p), ("hop_to", C.c_void_p),
         ("hop_re", C.c_void_p), ("hop_im", C.c_void_p),
+        ("has_overlap", C.c_int32), ("n_ovl", C.c_int32),
+        ("ovl_R", C.c_void_p), ("ovl_from", C.c_void_p), ("ovl_to", C.c_void_p),
+        ("ovl_re", C.c_void_p), ("ovl_im", C.c_void_p),
     ]
 
 
@@ -54,6 +57,9 @@ def lib():
                                            C.c_int64, P]
         L.ora_partition_masks.argtypes = [C.c_int32, C.c_int32, P, P]
         L.ora_kgrid.argtypes = [C.c_int32, C.c_int32, P, P]
+        L.ora_build_overlap.argtypes = [P, C.c_int32, P, C.c_double, C.c_double, P, C.c_int64, P]
+        L.ora_cholesky.argtypes = [C.c_int32, P, C.c_int64]
+        L.ora_eigvalsh_generalized.argtypes = [C.c_int32, P, P, C.c_int64, P]
         L.ora_kgrid_points.argtypes = [C.c_int32, C.c_int32]
         L.ora_kgrid_points.restype = C.c_int32
         L.ora_build_hamiltonian.argtypes = [P, C.c_int32, P, C.c_double, C.c_double, P, C.c_int64, P]
@@ -96,10 +102,19 @@ class OracleLattice:
         self.to = np.ascontiguousarray(h["to"], dtype=np.int32)
         self.re = np.ascontiguousarray(h["re"], dtype=np.float64)
         self.im = np.ascontiguousarray(h["im"], dtype=np.float64)
+        o = lat.overlap if lat.overlap is not None else np.zeros(0, dtype=h.dtype)
+        self.oR = np.ascontiguousarray(np.stack([o["R1"], o["R2"]], axis=1).reshape(-1, 2), dtype=np.int32)
+        self.ofrm = np.ascontiguousarray(o["frm"], dtype=np.int32)
+        self.oto = np.ascontiguousarray(o["to"], dtype=np.int32)
+        self.ore = np.ascontiguousarray(o["re"], dtype=np.float64)
+        self.oim = np.ascontiguousarray(o["im"], dtype=np.float64)
         self.s = _OraLattice(lat.lattice_id, lat.n_orb, lat.n_groups, lat.n_hops, lat.cell_area,
                              _ptr(self.frac).value, _ptr(self.group).value, _ptr(self.removable).value,
                              _ptr(self.R).value, _ptr(self.frm).value, _ptr(self.to).value,
-                             _ptr(self.re).value, _ptr(self.im).value)
+                             _ptr(self.re).value, _ptr(self.im).value,
+                             1 if lat.overlap is not None else 0, int(o.shape[0]),
+                             _ptr(self.oR).value, _ptr(self.ofrm).value, _ptr(self.oto).value,
+                             _ptr(self.ore).value, _ptr(self.oim).value)
 
     @property
     def ref(self):
@@ -171,6 +186,36 @@ def build_hamiltonian(lat, N, mask, kappa) -> np.ndarray:
     _check(lib().ora_build_hamiltonian(_olat(lat).ref, N, _ptr(mask), float(kappa[0]), float(kappa[1]),
                                        _ptr(H), nmax, C.byref(n)), "build_hamiltonian")
     return np.array(H[: n.value, : n.value])
+
+
+def build_overlap(lat, N, mask, kappa) -> np.ndarray:
+    """Overlap matrix S(k) of one outcome (unit matrix plus the Bloch sum of the
+    overlap table); n x n complex128."""
+    mask = np.ascontiguousarray(mask, dtype=np.uint8).reshape(-1)
+    nmax = lat.n_orb * N * N
+    S = np.zeros((nmax, nmax), dtype=np.complex128, order="F")
+    n = C.c_int32(0)
+    _check(lib().ora_build_overlap(_olat(lat).ref, N, _ptr(mask), float(kappa[0]), float(kappa[1]),
+                                   _ptr(S), nmax, C.byref(n)), "build_overlap")
+    return np.array(S[: n.value, : n.value])
+
+
+def cholesky(S: np.ndarray) -> np.ndarray:
+    """Lower Cholesky factor of a Hermitian positive definite matrix."""
+    A = np.array(S, dtype=np.complex128, order="F")
+    n = A.shape[0]
+    _check(lib().ora_cholesky(n, _ptr(A), max(n, 1)), "cholesky")
+    return np.tril(A)
+
+
+def eigvalsh_generalized(H: np.ndarray, S: np.ndarray) -> np.ndarray:
+    """Eigenvalues of the Hermitian-definite pencil (H, S), ascending."""
+    A = np.array(H, dtype=np.complex128, order="F")
+    Bm = np.array(S, dtype=np.complex128, order="F")
+    n = A.shape[0]
+    w = np.zeros(n)
+    _check(lib().ora_eigvalsh_generalized(n, _ptr(A), _ptr(Bm), max(n, 1), _ptr(w)), "eigvalsh_generalized")
+    return w
 
 
 def tridiagonalize(A: np.ndarray):

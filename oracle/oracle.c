@@ -19,6 +19,10 @@
  *     removed (Section 3.2);
  *   - the control-variate partition into four re-periodised quarters follows
  *     Section 3.3 (Figure "CV");
+ *   - for a non-orthogonal basis (overlap matrix S, Section 3.1) the
+ *     generalised problem H c = E S c is reduced to C = L^{-1} H L^{-H} with
+ *     the Cholesky factor S = L L^H (Golub & Van Loan, Alg. 4.2.1 and
+ *     Sec. 8.7.2) before the Hermitian eigensolver;
  *   - eigenvalues: unblocked Householder reduction of the Hermitian matrix to
  *     real symmetric tridiagonal form (Golub & Van Loan, Matrix Computations,
  *     Sec. 8.3.1, Hermitian form) followed by the implicit symmetric QR
@@ -60,6 +64,15 @@ typedef struct {
     const int32_t *hop_to;     /* [n_hops]                                 */
     const double *hop_re;      /* [n_hops]                                 */
     const double *hop_im;      /* [n_hops]                                 */
+    /* Non-orthogonal basis (Section 3.1, generalised problem H c = E S c):  */
+    /* has_overlap = 1 adds an overlap table; S = I + its Bloch sum.         */
+    int32_t has_overlap;
+    int32_t n_ovl;
+    const int32_t *ovl_R;      /* [n_ovl][2] */
+    const int32_t *ovl_from;   /* [n_ovl]    */
+    const int32_t *ovl_to;     /* [n_ovl]    */
+    const double *ovl_re;      /* [n_ovl]    */
+    const double *ovl_im;      /* [n_ovl]    */
 } ora_lattice;
 
 /* ------------------------------------------------------------------------ */
@@ -239,8 +252,12 @@ static int wrap(int a, int N)
 /* a1, a2 (the atom-to-atom vector of eq. (tightbinding)).  On-site rows     */
 /* (R = 0, from == to) are added once.  H is written column-major with       */
 /* leading dimension ld; *n_out receives n.                                   */
-int ora_build_hamiltonian(const ora_lattice *L, int32_t N, const uint8_t *mask, double k1, double k2,
-                          cplx *H, int64_t ld, int32_t *n_out)
+/* Bloch sum of one hopping table over the present orbitals of an outcome   */
+/* (Section 3.1, eq. (tightbinding); vacant rows and columns removed,         */
+/* Section 3.2), with the unit matrix added first when unit_diag is set.      */
+static int assemble_table(const ora_lattice *L, int32_t N, const uint8_t *mask, double k1, double k2, int n_tab,
+                          const int32_t *tR, const int32_t *tfrom, const int32_t *tto, const double *tre,
+                          const double *tim, int unit_diag, cplx *H, int64_t ld, int32_t *n_out)
 {
     const int n_orb = L->n_orb, G = L->n_groups;
     const int total = N * N * n_orb;
@@ -255,11 +272,11 @@ int ora_build_hamiltonian(const ora_lattice *L, int32_t N, const uint8_t *mask, 
         return ORA_ERR_ARG;
     }
     for (int64_t col = 0; col < n; ++col)
-        for (int64_t row = 0; row < n; ++row) H[row + col * ld] = 0.0;
-    for (int h = 0; h < L->n_hops; ++h) {
-        const int R1 = L->hop_R[2 * h], R2 = L->hop_R[2 * h + 1];
-        const int from = L->hop_from[h], to = L->hop_to[h];
-        const cplx amp = L->hop_re[h] + I * L->hop_im[h];
+        for (int64_t row = 0; row < n; ++row) H[row + col * ld] = (unit_diag && row == col) ? 1.0 : 0.0;
+    for (int h = 0; h < n_tab; ++h) {
+        const int R1 = tR[2 * h], R2 = tR[2 * h + 1];
+        const int from = tfrom[h], to = tto[h];
+        const cplx amp = tre[h] + I * tim[h];
         const double d1 = R1 + L->orb_frac[2 * to] - L->orb_frac[2 * from];
         const double d2 = R2 + L->orb_frac[2 * to + 1] - L->orb_frac[2 * from + 1];
         double x = (k1 * d1 + k2 * d2) / N;
@@ -282,6 +299,79 @@ int ora_build_hamiltonian(const ora_lattice *L, int32_t N, const uint8_t *mask, 
     free(index);
     *n_out = n;
     return ORA_OK;
+}
+
+int ora_build_hamiltonian(const ora_lattice *L, int32_t N, const uint8_t *mask, double k1, double k2,
+                          cplx *H, int64_t ld, int32_t *n_out)
+{
+    return assemble_table(L, N, mask, k1, k2, L->n_hops, L->hop_R, L->hop_from, L->hop_to, L->hop_re, L->hop_im, 0,
+                          H, ld, n_out);
+}
+
+/* Overlap matrix S(k) of a non-orthogonal basis: the unit matrix plus the  */
+/* Bloch sum of the overlap table (same phase convention as H(k)).          */
+int ora_build_overlap(const ora_lattice *L, int32_t N, const uint8_t *mask, double k1, double k2,
+                      cplx *S, int64_t ld, int32_t *n_out)
+{
+    if (!L->has_overlap) return ORA_ERR_ARG;
+    return assemble_table(L, N, mask, k1, k2, L->n_ovl, L->ovl_R, L->ovl_from, L->ovl_to, L->ovl_re, L->ovl_im, 1,
+                          S, ld, n_out);
+}
+
+/* Cholesky factorisation S = L L^H of a Hermitian positive definite matrix  */
+/* (Golub & Van Loan, Alg. 4.2.1, column by column); L overwrites the lower  */
+/* triangle.  Returns ORA_ERR_ARG when a pivot is not positive.              */
+int ora_cholesky(int32_t n, cplx *S, int64_t ld)
+{
+    for (int j = 0; j < n; ++j) {
+        double djj = creal(S[j + (int64_t)j * ld]);
+        for (int k = 0; k < j; ++k) djj -= creal(S[j + (int64_t)k * ld] * conj(S[j + (int64_t)k * ld]));
+        if (!(djj > 0.0)) return ORA_ERR_ARG;
+        const double ljj = sqrt(djj);
+        S[j + (int64_t)j * ld] = ljj;
+        for (int i = j + 1; i < n; ++i) {
+            cplx sij = S[i + (int64_t)j * ld];
+            for (int k = 0; k < j; ++k) sij -= S[i + (int64_t)k * ld] * conj(S[j + (int64_t)k * ld]);
+            S[i + (int64_t)j * ld] = sij / ljj;
+        }
+    }
+    return ORA_OK;
+}
+
+int ora_eigvalsh(int32_t n, cplx *A, int64_t ld, double *w);
+
+/* Eigenvalues of the Hermitian-definite pencil (H, S): with S = L L^H the  */
+/* pencil has the eigenvalues of the Hermitian C = L^{-1} H L^{-H}.  Y =     */
+/* L^{-1} H by forward substitution, then C = L^{-1} Y^H (= Y L^{-H}, as C   */
+/* is Hermitian), then the Hermitian eigensolver.  H and S are overwritten.  */
+int ora_eigvalsh_generalized(int32_t n, cplx *H, cplx *S, int64_t ld, double *w)
+{
+    if (n < 0) return ORA_ERR_ARG;
+    if (n == 0) return ORA_OK;
+    int st = ora_cholesky(n, S, ld);
+    if (st != ORA_OK) return st;
+    cplx *Y = (cplx *)malloc(sizeof(cplx) * (size_t)n * (size_t)n);
+    if (!Y) return ORA_ERR_NOMEM;
+    for (int c = 0; c < n; ++c)            /* Y[:, c] = L^{-1} H[:, c] */
+        for (int i = 0; i < n; ++i) {
+            cplx v = H[i + (int64_t)c * ld];
+            for (int k = 0; k < i; ++k) v -= S[i + (int64_t)k * ld] * Y[k + (size_t)c * n];
+            Y[i + (size_t)c * n] = v / creal(S[i + (int64_t)i * ld]);
+        }
+    for (int c = 0; c < n; ++c)            /* C[:, c] = L^{-1} (Y^H)[:, c] */
+        for (int i = 0; i < n; ++i) {
+            cplx v = conj(Y[c + (size_t)i * n]);
+            for (int k = 0; k < i; ++k) v -= S[i + (int64_t)k * ld] * H[k + (int64_t)c * ld];
+            H[i + (int64_t)c * ld] = v / creal(S[i + (int64_t)i * ld]);
+        }
+    free(Y);
+    for (int c = 0; c < n; ++c)            /* the Hermitian part of the computed C */
+        for (int i = c; i < n; ++i) {
+            const cplx m = 0.5 * (H[i + (int64_t)c * ld] + conj(H[c + (int64_t)i * ld]));
+            H[i + (int64_t)c * ld] = m;
+            H[c + (int64_t)i * ld] = conj(m);
+        }
+    return ora_eigvalsh(n, H, ld, w);
 }
 
 /* Householder reduction of a Hermitian matrix (full storage, column-major)  */
@@ -490,16 +580,25 @@ static int outcome_idos(const ora_lattice *L, int32_t N, const uint8_t *mask, in
     double *w = (double *)malloc(sizeof(double) * (size_t)nk * (size_t)(nmax > 0 ? nmax : 1));
     int32_t *nn = (int32_t *)malloc(sizeof(int32_t) * (size_t)nk);
     cplx *H = (cplx *)malloc(sizeof(cplx) * (size_t)(nmax > 0 ? nmax : 1) * (size_t)(nmax > 0 ? nmax : 1));
+    cplx *S = L->has_overlap
+                  ? (cplx *)malloc(sizeof(cplx) * (size_t)(nmax > 0 ? nmax : 1) * (size_t)(nmax > 0 ? nmax : 1))
+                  : NULL;
     int st = ORA_OK;
-    if (!kred || !kw || !w || !nn || !H) st = ORA_ERR_NOMEM;
+    if (!kred || !kw || !w || !nn || !H || (L->has_overlap && !S)) st = ORA_ERR_NOMEM;
     if (st == ORA_OK) st = ora_kgrid(kind, K, kred, kw);
     for (int k = 0; st == ORA_OK && k < nk; ++k) {
         st = ora_build_hamiltonian(L, N, mask, kred[2 * k], kred[2 * k + 1], H, nmax, &nn[k]);
-        if (st == ORA_OK) st = ora_eigvalsh(nn[k], H, nmax, &w[(size_t)k * nmax]);
+        if (st == ORA_OK && L->has_overlap) {
+            int32_t ns = 0;
+            st = ora_build_overlap(L, N, mask, kred[2 * k], kred[2 * k + 1], S, nmax, &ns);
+            if (st == ORA_OK) st = ora_eigvalsh_generalized(nn[k], H, S, nmax, &w[(size_t)k * nmax]);
+        } else if (st == ORA_OK) {
+            st = ora_eigvalsh(nn[k], H, nmax, &w[(size_t)k * nmax]);
+        }
     }
     if (st == ORA_OK)
         st = ora_idos(w, nmax, nn, nk, kw, (double)N * N * L->cell_area, eps, n_eps, delta, smoother, out);
-    free(kred); free(kw); free(w); free(nn); free(H);
+    free(kred); free(kw); free(w); free(nn); free(H); free(S);
     return st;
 }
 
