@@ -69,7 +69,7 @@ def test_against_lapack_generalized_solver():
 def test_overlap_idos_counts_states():
     lat = graphene_overlap()
     N = 3
-    eps = energy_grid(-12.0, 12.0, 41)
+    eps = energy_grid(-9.0, 18.0, 41)   # bands span about [-6.6, 14.9] eV
     mask = oracle.sample_vacancies(lat, N, 0.2, 2, oracle.stream_tag(lat, N), 0, 1)[0]
     n = 2 * N * N - int(mask.sum())
     Q = oracle.sample_qoi(lat, N, mask, False, 2, 2, KGRID_GAMMA, eps, 0.05, SMOOTH_GAUSS)
