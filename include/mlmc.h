@@ -98,6 +98,12 @@ typedef struct {
     const int32_t *orb_group;       /* [n_orb] group of each orbital, 0..n_groups-1     */
     const uint8_t *group_removable; /* [n_groups] 1: the group may be vacant            */
     const mlmc_hop *hops;           /* [n_hops]                                         */
+    /* Non-orthogonal basis (Section 3.1, generalised problem H c = E S c):
+     * n_overlap > 0 rows of an overlap table, S(k) = I + its Bloch sum with
+     * the conventions of `hops`; n_overlap = 0 and overlap = NULL for an
+     * orthogonal basis (S = I). */
+    int32_t n_overlap;              /* 0..65536                                         */
+    const mlmc_hop *overlap;        /* [n_overlap]                                      */
 } mlmc_lattice_desc;
 
 typedef struct mlmc_lattice_s *mlmc_lattice; /* opaque device-resident lattice */
@@ -168,6 +174,15 @@ mlmc_status mlmc_build_hamiltonians(mlmc_lattice lat, int32_t N, const uint8_t *
                                     const double *d_kred, int32_t n_k, mlmc_dtype dtype, void *d_H, int64_t ld,
                                     int32_t *d_n, mlmc_stream stream);
 
+/* Overlap matrices S(k) of a lattice with a non-orthogonal basis (Section
+ * 3.1): the unit matrix plus the Bloch sum of the lattice's overlap table,
+ * with the layout, phases and removed rows and columns of
+ * mlmc_build_hamiltonians for the same outcomes and k-points.
+ * Errors: the lattice has no overlap table, ld < n_orb*N*N, n_k < 1. */
+mlmc_status mlmc_build_overlaps(mlmc_lattice lat, int32_t N, const uint8_t *d_mask, int64_t n_samples,
+                                const double *d_kred, int32_t n_k, mlmc_dtype dtype, void *d_S, int64_t ld,
+                                int32_t *d_n, mlmc_stream stream);
+
 /* Workspace bytes of mlmc_batched_eigvalsh for `batch` matrices of bound ld. */
 mlmc_status mlmc_eigvalsh_workspace(mlmc_dtype dtype, mlmc_precision prec, int64_t ld, int64_t batch,
                                     size_t *bytes);
@@ -185,6 +200,22 @@ mlmc_status mlmc_eigvalsh_workspace(mlmc_dtype dtype, mlmc_precision prec, int64
 mlmc_status mlmc_batched_eigvalsh(mlmc_dtype dtype, mlmc_precision prec, void *d_H, int64_t ld,
                                   const int32_t *d_n, int64_t batch, double *d_w, int64_t ldw, void *d_work,
                                   size_t work_bytes, mlmc_stream stream);
+
+/* Workspace bytes of mlmc_batched_eigvalsh_generalized (ld <= 1024). */
+mlmc_status mlmc_generalized_workspace(mlmc_dtype dtype, mlmc_precision prec, int64_t ld, int64_t batch,
+                                       size_t *bytes);
+
+/* All eigenvalues of a batch of Hermitian-definite pencils (H, S) (the
+ * generalised problem H c = E S c of a non-orthogonal basis, Section 3.1):
+ * S = L L^H (Cholesky) and C = L^{-1} H L^{-H}, both blocked on the GPU,
+ * then the eigenvalues of C as in mlmc_batched_eigvalsh.  d_H, d_S: lower
+ * triangles of the leading n_b x n_b blocks are read and both are
+ * overwritten (S by L).  S must be positive definite (otherwise the
+ * eigenvalues come out NaN).  Other arguments as mlmc_batched_eigvalsh.
+ * Errors: ld > 1024 (MLMC_ERR_UNSUPPORTED), workspace too small. */
+mlmc_status mlmc_batched_eigvalsh_generalized(mlmc_dtype dtype, mlmc_precision prec, void *d_H, void *d_S,
+                                              int64_t ld, const int32_t *d_n, int64_t batch, double *d_w,
+                                              int64_t ldw, void *d_work, size_t work_bytes, mlmc_stream stream);
 
 /* Smoothed IDoS per unit area of each outcome (eq. (IDoS) with the
  * nearest-point band approximation and the smoothing of eq.
@@ -252,7 +283,8 @@ mlmc_status mlmc_timer_enable(int32_t enable);
 /* Total event-measured duration (ms) and count of the recorded launches of
  * kernel `name`: "sample_vacancies", "partition", "kgrid", "assemble",
  * "small_fused", "band_reduce" (dense to band, several kernels per launch),
- * "chase" (band to tridiagonal, one kernel), "bisect", "idos" or
+ * "chase" (band to tridiagonal, one kernel), "overlap_reduce" (Cholesky and
+ * reduction of a generalised problem, several kernels), "bisect", "idos" or
  * "level_stats".
  * Blocks until those launches have completed. */
 mlmc_status mlmc_timer_read(const char *name, double *total_ms, int64_t *launches);

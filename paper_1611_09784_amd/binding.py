@@ -53,7 +53,8 @@ class _Hop(C.Structure):
 class _LatticeDesc(C.Structure):
     _fields_ = [("lattice_id", C.c_uint32), ("n_orb", C.c_int32), ("n_groups", C.c_int32), ("n_hops", C.c_int32),
                 ("cell_area", C.c_double), ("orb_frac", C.c_void_p), ("orb_group", C.c_void_p),
-                ("group_removable", C.c_void_p), ("hops", C.c_void_p)]
+                ("group_removable", C.c_void_p), ("hops", C.c_void_p),
+                ("n_overlap", C.c_int32), ("overlap", C.c_void_p)]
 
 
 _LIB = None
@@ -74,6 +75,9 @@ SIGNATURES = {
     "mlmc_build_hamiltonians": (C.c_int, [P, I32, P, I64, P, I32, C.c_int, P, I64, P, P]),
     "mlmc_eigvalsh_workspace": (C.c_int, [C.c_int, C.c_int, I64, I64, P]),
     "mlmc_batched_eigvalsh": (C.c_int, [C.c_int, C.c_int, P, I64, P, I64, P, I64, P, SZ, P]),
+    "mlmc_build_overlaps": (C.c_int, [P, I32, P, I64, P, I32, C.c_int, P, I64, P, P]),
+    "mlmc_generalized_workspace": (C.c_int, [C.c_int, C.c_int, I64, I64, P]),
+    "mlmc_batched_eigvalsh_generalized": (C.c_int, [C.c_int, C.c_int, P, P, I64, P, I64, P, I64, P, SZ, P]),
     "mlmc_idos": (C.c_int, [P, I64, P, I64, I32, P, DBL, P, I32, DBL, C.c_int, P, P]),
     "mlmc_level_stats": (C.c_int, [P, P, I64, I32, P, P]),
     "mlmc_level_workspace": (C.c_int, [P, I32, I32, I32, I32, C.c_int, I64, C.c_int, I32, P]),
@@ -149,25 +153,32 @@ def stream_tag(lattice_id: int, N: int) -> int:
     return (int(lattice_id) << 32) | int(N)
 
 
+def _hop_rows(table):
+    rows = np.zeros(table.shape[0], dtype=np.dtype([("R", np.int32, 2), ("from_orb", np.int32),
+                                                    ("to_orb", np.int32), ("re", np.float64), ("im", np.float64)]))
+    rows["R"][:, 0] = table["R1"]
+    rows["R"][:, 1] = table["R2"]
+    rows["from_orb"] = table["frm"]
+    rows["to_orb"] = table["to"]
+    rows["re"] = table["re"]
+    rows["im"] = table["im"]
+    return rows
+
+
 class DeviceLattice:
     """Device-resident lattice handle (mlmc_lattice_create / _destroy)."""
 
     def __init__(self, lat, device=None):
         self.lat = lat
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
-        hops = np.zeros(lat.n_hops, dtype=np.dtype([("R", np.int32, 2), ("from_orb", np.int32),
-                                                     ("to_orb", np.int32), ("re", np.float64), ("im", np.float64)]))
-        hops["R"][:, 0] = lat.hops["R1"]
-        hops["R"][:, 1] = lat.hops["R2"]
-        hops["from_orb"] = lat.hops["frm"]
-        hops["to_orb"] = lat.hops["to"]
-        hops["re"] = lat.hops["re"]
-        hops["im"] = lat.hops["im"]
+        hops = _hop_rows(lat.hops)
+        ovl = _hop_rows(lat.overlap) if getattr(lat, "overlap", None) is not None else None
         frac = np.ascontiguousarray(lat.orb_frac, dtype=np.float64)
         group = np.ascontiguousarray(lat.orb_group, dtype=np.int32)
         rem = np.ascontiguousarray(lat.group_removable, dtype=np.uint8)
         desc = _LatticeDesc(lat.lattice_id, lat.n_orb, lat.n_groups, lat.n_hops, lat.cell_area,
-                            _ptr(frac), _ptr(group), _ptr(rem), _ptr(hops))
+                            _ptr(frac), _ptr(group), _ptr(rem), _ptr(hops),
+                            0 if ovl is None else ovl.shape[0], None if ovl is None else _ptr(ovl))
         handle = C.c_void_p()
         with torch.cuda.device(self.device):
             _check(lib().mlmc_lattice_create(C.byref(desc), C.byref(handle)), "mlmc_lattice_create")
@@ -254,6 +265,55 @@ def mlmc_build_hamiltonians(dlat, N, mask, kred, dtype=MLMC_C128, ld=None, H=Non
     _check(lib().mlmc_build_hamiltonians(dlat.handle, N, _ptr(mask), ns, _ptr(kred), nk, dtype, _ptr(H), ld,
                                          _ptr(n_out), _stream(stream)), "mlmc_build_hamiltonians")
     return H, n_out
+
+
+def mlmc_build_overlaps(dlat, N, mask, kred, dtype=MLMC_C128, ld=None, S=None, n_out=None, stream=None):
+    _dev(mask, torch.uint8, "mask")
+    _dev(kred, torch.float64, "kred")
+    ns = mask.shape[0]
+    nk = kred.shape[0]
+    ld = dlat.max_orbitals(N) if ld is None else ld
+    tdt = torch.complex128 if dtype == MLMC_C128 else torch.complex64
+    if S is None:
+        S = torch.empty((ns * nk, ld, ld), dtype=tdt, device=mask.device)
+    if n_out is None:
+        n_out = torch.empty((ns * nk,), dtype=torch.int32, device=mask.device)
+    _dev(S, tdt, "S")
+    _dev(n_out, torch.int32, "n")
+    _check(lib().mlmc_build_overlaps(dlat.handle, N, _ptr(mask), ns, _ptr(kred), nk, dtype, _ptr(S), ld,
+                                     _ptr(n_out), _stream(stream)), "mlmc_build_overlaps")
+    return S, n_out
+
+
+def mlmc_generalized_workspace(dtype, prec, ld, batch) -> int:
+    out = C.c_size_t()
+    _check(lib().mlmc_generalized_workspace(dtype, prec, ld, batch, C.byref(out)), "mlmc_generalized_workspace")
+    return out.value
+
+
+def mlmc_batched_eigvalsh_generalized(H, S, n, prec=None, w=None, ldw=None, work=None, stream=None):
+    """Eigenvalues of the pencils (H, S); H and S are overwritten."""
+    dtype = MLMC_C128 if H.dtype == torch.complex128 else MLMC_C64
+    if prec is None:
+        prec = MLMC_PREC_FP64 if dtype == MLMC_C128 else MLMC_PREC_MIXED
+    _dev(H, None, "H")
+    _dev(S, H.dtype, "S")
+    _dev(n, torch.int32, "n")
+    batch, ld = H.shape[0], H.shape[1]
+    if S.shape != H.shape:
+        raise ValueError("H and S must have the same shape")
+    ldw = ld if ldw is None else ldw
+    if w is None:
+        w = torch.zeros((batch, ldw), dtype=torch.float64, device=H.device)
+    _dev(w, torch.float64, "w")
+    need = mlmc_generalized_workspace(dtype, prec, ld, batch)
+    if work is None and need > 0:
+        work = torch.empty((need,), dtype=torch.uint8, device=H.device)
+    wb = 0 if work is None else work.numel() * work.element_size()
+    _check(lib().mlmc_batched_eigvalsh_generalized(dtype, prec, _ptr(H), _ptr(S), ld, _ptr(n), batch, _ptr(w), ldw,
+                                                   _ptr(work), wb, _stream(stream)),
+           "mlmc_batched_eigvalsh_generalized")
+    return w
 
 
 def mlmc_eigvalsh_workspace(dtype, prec, ld, batch) -> int:

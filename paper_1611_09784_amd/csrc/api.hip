@@ -104,6 +104,7 @@ size_t cplx_bytes(mlmc_precision prec) { return prec == MLMC_PREC_FP64 ? 16 : 8;
 // Buffers of the device-memory eigen path for `units` matrices of side bound ld.
 struct EigBuffers {
     void *H = nullptr;
+    void *S = nullptr;  // overlap matrices (non-orthogonal basis only)
     double *d = nullptr, *e = nullptr;
     void *partial = nullptr;
 };
@@ -114,6 +115,20 @@ void carve_large(Carver &cv, mlmc_precision prec, int64_t ld, int64_t units, boo
     b.e = cv.take<double>(sizeof(double) * (size_t)ld * (size_t)units);
     const size_t pe = prec == MLMC_PREC_FP64 ? tridiag_twostage_work_elems<double>(ld)
                                              : tridiag_twostage_work_elems<float>(ld);
+    b.partial = cv.take<void>(cplx_bytes(prec) * pe * (size_t)units);
+}
+
+// Buffers of the generalised path (any ld <= kGenMax): H and S when asked for,
+// d, e, and the per-matrix workspace of the Cholesky / two-sided reduction,
+// which the two-stage reduction reuses afterwards.
+void carve_generalized(Carver &cv, mlmc_precision prec, int64_t ld, int64_t units, bool with_HS, EigBuffers &b) {
+    if (with_HS) {
+        b.H = cv.take<void>(cplx_bytes(prec) * (size_t)ld * (size_t)ld * (size_t)units);
+        b.S = cv.take<void>(cplx_bytes(prec) * (size_t)ld * (size_t)ld * (size_t)units);
+    }
+    b.d = cv.take<double>(sizeof(double) * (size_t)ld * (size_t)units);
+    b.e = cv.take<double>(sizeof(double) * (size_t)ld * (size_t)units);
+    const size_t pe = prec == MLMC_PREC_FP64 ? generalized_work_elems<double>(ld) : generalized_work_elems<float>(ld);
     b.partial = cv.take<void>(cplx_bytes(prec) * pe * (size_t)units);
 }
 
@@ -161,7 +176,9 @@ LevelLayout level_layout(const mlmc_lattice_s *lat, int N, bool coupled, int Kf,
     L.nf = cv.take<int32_t>(sizeof(int32_t) * (size_t)(mc * nkf));
     L.wf = cv.take<double>(sizeof(double) * (size_t)(mc * nkf * ldf));
     L.If = cv.take<double>(sizeof(double) * (size_t)mc * n_eps);
-    if (ldf > small_cap(prec)) carve_large(cv, prec, ldf, mc * nkf, true, L.bf);
+    const bool gen = lat->dev.n_ovl > 0;
+    if (gen) carve_generalized(cv, prec, ldf, mc * nkf, true, L.bf);
+    else if (ldf > small_cap(prec)) carve_large(cv, prec, ldf, mc * nkf, true, L.bf);
     if (coupled) {
         const int h = N / 2;
         const int64_t ldc = (int64_t)no * h * h;
@@ -171,18 +188,49 @@ LevelLayout level_layout(const mlmc_lattice_s *lat, int N, bool coupled, int Kf,
         L.nc = cv.take<int32_t>(sizeof(int32_t) * (size_t)(mc * 4 * nkc));
         L.wc = cv.take<double>(sizeof(double) * (size_t)(mc * 4 * nkc * ldc));
         L.Ic = cv.take<double>(sizeof(double) * (size_t)mc * 4 * n_eps);
-        if (ldc > small_cap(prec)) carve_large(cv, prec, ldc, mc * 4 * nkc, true, L.bc);
+        if (gen) carve_generalized(cv, prec, ldc, mc * 4 * nkc, true, L.bc);
+        else if (ldc > small_cap(prec)) carve_large(cv, prec, ldc, mc * 4 * nkc, true, L.bc);
     }
     L.bytes = cv.used;
     return L;
 }
 
 // Eigenvalues of every (outcome, k) unit of `ns` outcomes of side N.
+// Pencils (H, S) already in b.H, b.S -> eigenvalues (reduction to C = L^{-1}
+// H L^{-H}, then the standard path on C).
+mlmc_status run_generalized(mlmc_precision prec, void *H, void *S, int64_t ld, const int32_t *n, int64_t units,
+                            double *w, int64_t ldw, const EigBuffers &b, hipStream_t s) {
+    if (prec == MLMC_PREC_FP64)
+        LAUNCH("overlap_reduce", s, launch_cholesky_reduce<double>(static_cast<cpx<double> *>(H), static_cast<cpx<double> *>(S), ld, n, units,
+                                                            static_cast<cpx<double> *>(b.partial), s));
+    else
+        LAUNCH("overlap_reduce", s, launch_cholesky_reduce<float>(static_cast<cpx<float> *>(H), static_cast<cpx<float> *>(S), ld, n, units,
+                                                           static_cast<cpx<float> *>(b.partial), s));
+    if (ld <= small_cap(prec)) {
+        if (prec == MLMC_PREC_FP64)
+            LAUNCH("small_fused", s, launch_small_from_matrix<double>(static_cast<const cpx<double> *>(H), ld, n, units, w, ldw, s));
+        else
+            LAUNCH("small_fused", s, launch_small_from_matrix<float>(static_cast<const cpx<float> *>(H), ld, n, units, w, ldw, s));
+        return MLMC_OK;
+    }
+    return run_large(prec, H, ld, n, units, w, ldw, b, s);
+}
+
 mlmc_status outcome_spectra(const mlmc_lattice_s *lat, int N, const uint8_t *mask, int64_t ns, const double *kred,
                             int nk, mlmc_precision prec, double *w, int32_t *n_out, const EigBuffers &b,
                             hipStream_t s) {
     const int64_t ld = (int64_t)lat->dev.n_orb * N * N;
     const int64_t units = ns * nk;
+    if (lat->dev.n_ovl > 0) {  // non-orthogonal basis: assemble H and S, generalised path
+        if (prec == MLMC_PREC_FP64) {
+            LAUNCH("assemble", s, launch_assemble<double>(lat->dev, N, mask, ns, kred, nk, static_cast<cpx<double> *>(b.H), ld, n_out, s));
+            LAUNCH("assemble", s, launch_assemble<double>(lat->dev, N, mask, ns, kred, nk, static_cast<cpx<double> *>(b.S), ld, n_out, s, true));
+        } else {
+            LAUNCH("assemble", s, launch_assemble<float>(lat->dev, N, mask, ns, kred, nk, static_cast<cpx<float> *>(b.H), ld, n_out, s));
+            LAUNCH("assemble", s, launch_assemble<float>(lat->dev, N, mask, ns, kred, nk, static_cast<cpx<float> *>(b.S), ld, n_out, s, true));
+        }
+        return run_generalized(prec, b.H, b.S, ld, n_out, units, w, ld, b, s);
+    }
     if (ld <= small_cap(prec)) {
         if (prec == MLMC_PREC_FP64)
             LAUNCH("small_fused", s, launch_small_from_lattice<double>(lat->dev, N, mask, ns, kred, nk, w, ld, n_out, s));
@@ -195,6 +243,26 @@ mlmc_status outcome_spectra(const mlmc_lattice_s *lat, int N, const uint8_t *mas
     else
         LAUNCH("assemble", s, launch_assemble<float>(lat->dev, N, mask, ns, kred, nk, static_cast<cpx<float> *>(b.H), ld, n_out, s));
     return run_large(prec, b.H, ld, n_out, units, w, ld, b, s);
+}
+
+mlmc_status convert_hops(const mlmc_lattice_desc *desc, const mlmc_hop *rows, int count, const char *what,
+                         std::vector<int4> &hi, std::vector<double4> &hf) {
+    hi.resize(count);
+    hf.resize(count);
+    for (int h = 0; h < count; ++h) {
+        const mlmc_hop &r = rows[h];
+        if (r.from_orb < 0 || r.from_orb >= desc->n_orb || r.to_orb < 0 || r.to_orb >= desc->n_orb)
+            return fail(MLMC_ERR_INVALID_ARG, "%s %d: orbital out of range", what, h);
+        if (!std::isfinite(r.re) || !std::isfinite(r.im))
+            return fail(MLMC_ERR_INVALID_ARG, "%s %d: non-finite amplitude", what, h);
+        const bool onsite = r.R[0] == 0 && r.R[1] == 0 && r.from_orb == r.to_orb;
+        if (onsite && r.im != 0.0) return fail(MLMC_ERR_INVALID_ARG, "%s %d: on-site entry must be real", what, h);
+        hi[h] = make_int4(r.R[0], r.R[1], r.from_orb, r.to_orb);
+        const double d1 = r.R[0] + desc->orb_frac[2 * r.to_orb] - desc->orb_frac[2 * r.from_orb];
+        const double d2 = r.R[1] + desc->orb_frac[2 * r.to_orb + 1] - desc->orb_frac[2 * r.from_orb + 1];
+        hf[h] = make_double4(r.re, r.im, d1, d2);
+    }
+    return MLMC_OK;
 }
 
 }  // namespace
@@ -228,35 +296,33 @@ mlmc_status mlmc_lattice_create(const mlmc_lattice_desc *desc, mlmc_lattice *out
     for (int m = 0; m < desc->n_orb; ++m)
         if (desc->orb_group[m] < 0 || desc->orb_group[m] >= desc->n_groups)
             return fail(MLMC_ERR_INVALID_ARG, "orb_group[%d] out of range", m);
-    std::vector<int4> hi(desc->n_hops);
-    std::vector<double4> hf(desc->n_hops);
-    for (int h = 0; h < desc->n_hops; ++h) {
-        const mlmc_hop &r = desc->hops[h];
-        if (r.from_orb < 0 || r.from_orb >= desc->n_orb || r.to_orb < 0 || r.to_orb >= desc->n_orb)
-            return fail(MLMC_ERR_INVALID_ARG, "hop %d: orbital out of range", h);
-        if (!std::isfinite(r.re) || !std::isfinite(r.im))
-            return fail(MLMC_ERR_INVALID_ARG, "hop %d: non-finite amplitude", h);
-        const bool onsite = r.R[0] == 0 && r.R[1] == 0 && r.from_orb == r.to_orb;
-        if (onsite && r.im != 0.0) return fail(MLMC_ERR_INVALID_ARG, "hop %d: on-site energy must be real", h);
-        hi[h] = make_int4(r.R[0], r.R[1], r.from_orb, r.to_orb);
-        const double d1 = r.R[0] + desc->orb_frac[2 * r.to_orb] - desc->orb_frac[2 * r.from_orb];
-        const double d2 = r.R[1] + desc->orb_frac[2 * r.to_orb + 1] - desc->orb_frac[2 * r.from_orb + 1];
-        hf[h] = make_double4(r.re, r.im, d1, d2);
-    }
+    if (desc->n_overlap < 0 || desc->n_overlap > 65536 || (desc->n_overlap > 0 && !desc->overlap))
+        return fail(MLMC_ERR_INVALID_ARG, "n_overlap out of range or NULL overlap table");
+    std::vector<int4> hi, oi;
+    std::vector<double4> hf, of;
+    mlmc_status st = convert_hops(desc, desc->hops, desc->n_hops, "hop", hi, hf);
+    if (st != MLMC_OK) return st;
+    st = convert_hops(desc, desc->overlap, desc->n_overlap, "overlap", oi, of);
+    if (st != MLMC_OK) return st;
     auto *lat = new mlmc_lattice_s();
     HIP_TRY(hipGetDevice(&lat->device), "hipGetDevice");
+    const int no = desc->n_overlap;
     const size_t bi = align_up(sizeof(int4) * desc->n_hops), bf = align_up(sizeof(double4) * desc->n_hops);
     const size_t bg = align_up(sizeof(int32_t) * desc->n_orb), br = align_up(desc->n_groups);
-    hipError_t err = hipMalloc(&lat->d_buf, bi + bf + bg + br);
+    const size_t boi = align_up(sizeof(int4) * no), bof = align_up(sizeof(double4) * no);
+    hipError_t err = hipMalloc(&lat->d_buf, bi + bf + bg + br + boi + bof);
     if (err != hipSuccess) {
         delete lat;
         return hip_fail(err, "hipMalloc(lattice)");
     }
     char *p = static_cast<char *>(lat->d_buf);
+    char *po = p + bi + bf + bg + br;
     err = hipMemcpy(p, hi.data(), sizeof(int4) * desc->n_hops, hipMemcpyHostToDevice);
     if (err == hipSuccess) err = hipMemcpy(p + bi, hf.data(), sizeof(double4) * desc->n_hops, hipMemcpyHostToDevice);
     if (err == hipSuccess) err = hipMemcpy(p + bi + bf, desc->orb_group, sizeof(int32_t) * desc->n_orb, hipMemcpyHostToDevice);
     if (err == hipSuccess) err = hipMemcpy(p + bi + bf + bg, desc->group_removable, desc->n_groups, hipMemcpyHostToDevice);
+    if (err == hipSuccess && no > 0) err = hipMemcpy(po, oi.data(), sizeof(int4) * no, hipMemcpyHostToDevice);
+    if (err == hipSuccess && no > 0) err = hipMemcpy(po + boi, of.data(), sizeof(double4) * no, hipMemcpyHostToDevice);
     if (err != hipSuccess) {
         (void)hipFree(lat->d_buf);
         delete lat;
@@ -266,6 +332,9 @@ mlmc_status mlmc_lattice_create(const mlmc_lattice_desc *desc, mlmc_lattice *out
     lat->dev.hop_f = reinterpret_cast<const double4 *>(p + bi);
     lat->dev.orb_group = reinterpret_cast<const int32_t *>(p + bi + bf);
     lat->dev.removable = reinterpret_cast<const uint8_t *>(p + bi + bf + bg);
+    lat->dev.ovl_i = no > 0 ? reinterpret_cast<const int4 *>(po) : nullptr;
+    lat->dev.ovl_f = no > 0 ? reinterpret_cast<const double4 *>(po + boi) : nullptr;
+    lat->dev.n_ovl = no;
     lat->dev.n_orb = desc->n_orb;
     lat->dev.n_groups = desc->n_groups;
     lat->dev.n_hops = desc->n_hops;
@@ -355,6 +424,29 @@ mlmc_status mlmc_build_hamiltonians(mlmc_lattice lat, int32_t N, const uint8_t *
     return MLMC_OK;
 }
 
+mlmc_status mlmc_build_overlaps(mlmc_lattice lat, int32_t N, const uint8_t *d_mask, int64_t n_samples,
+                                const double *d_kred, int32_t n_k, mlmc_dtype dtype, void *d_S, int64_t ld,
+                                int32_t *d_n, mlmc_stream stream) {
+    if (!valid_lattice(lat)) return fail(MLMC_ERR_INVALID_ARG, "build_overlaps: NULL lattice");
+    if (lat->dev.n_ovl < 1) return fail(MLMC_ERR_INVALID_ARG, "build_overlaps: the lattice has no overlap table");
+    if (N < 1 || N > 4096 || n_k < 1 || n_samples < 0)
+        return fail(MLMC_ERR_INVALID_ARG, "build_overlaps: N = %d, n_k = %d", N, n_k);
+    if (dtype != MLMC_C128 && dtype != MLMC_C64) return fail(MLMC_ERR_INVALID_ARG, "build_overlaps: bad dtype");
+    const int64_t nmax = (int64_t)lat->dev.n_orb * N * N;
+    if (ld < nmax) return fail(MLMC_ERR_INVALID_ARG, "build_overlaps: ld %lld < %lld", (long long)ld, (long long)nmax);
+    if (nmax > 16384) return fail(MLMC_ERR_UNSUPPORTED, "build_overlaps: %lld orbitals exceed 16384", (long long)nmax);
+    if (n_samples > 0 && (!d_mask || !d_kred || !d_S || !d_n))
+        return fail(MLMC_ERR_INVALID_ARG, "build_overlaps: NULL buffer");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (dtype == MLMC_C128)
+        LAUNCH("assemble", s, launch_assemble<double>(lat->dev, N, d_mask, n_samples, d_kred, n_k,
+                                                      static_cast<cpx<double> *>(d_S), ld, d_n, s, true));
+    else
+        LAUNCH("assemble", s, launch_assemble<float>(lat->dev, N, d_mask, n_samples, d_kred, n_k,
+                                                     static_cast<cpx<float> *>(d_S), ld, d_n, s, true));
+    return MLMC_OK;
+}
+
 static mlmc_status check_dtype_prec(mlmc_dtype dtype, mlmc_precision prec) {
     if (dtype == MLMC_C128 && prec == MLMC_PREC_FP64) return MLMC_OK;
     if (dtype == MLMC_C64 && prec == MLMC_PREC_MIXED) return MLMC_OK;
@@ -401,6 +493,37 @@ mlmc_status mlmc_batched_eigvalsh(mlmc_dtype dtype, mlmc_precision prec, void *d
     return run_large(prec, d_H, ld, d_n, batch, d_w, ldw, b, s);
 }
 
+mlmc_status mlmc_generalized_workspace(mlmc_dtype dtype, mlmc_precision prec, int64_t ld, int64_t batch,
+                                       size_t *bytes) {
+    if (!bytes || ld < 0 || batch < 0) return fail(MLMC_ERR_INVALID_ARG, "generalized_workspace: bad argument");
+    const mlmc_status st = check_dtype_prec(dtype, prec);
+    if (st != MLMC_OK) return st;
+    if (ld > kGenMax)
+        return fail(MLMC_ERR_UNSUPPORTED, "generalized eigvalsh: ld %lld exceeds %d", (long long)ld, kGenMax);
+    Carver cv{nullptr};
+    EigBuffers b;
+    carve_generalized(cv, prec, ld, batch, false, b);
+    *bytes = cv.used;
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_batched_eigvalsh_generalized(mlmc_dtype dtype, mlmc_precision prec, void *d_H, void *d_S,
+                                              int64_t ld, const int32_t *d_n, int64_t batch, double *d_w,
+                                              int64_t ldw, void *d_work, size_t work_bytes, mlmc_stream stream) {
+    size_t need = 0;
+    const mlmc_status st = mlmc_generalized_workspace(dtype, prec, ld, batch, &need);
+    if (st != MLMC_OK) return st;
+    if (ldw < ld) return fail(MLMC_ERR_INVALID_ARG, "eigvalsh_generalized: ldw %lld < ld %lld", (long long)ldw, (long long)ld);
+    if (batch > 0 && (!d_H || !d_S || !d_n || !d_w)) return fail(MLMC_ERR_INVALID_ARG, "eigvalsh_generalized: NULL buffer");
+    if (need > 0 && (!d_work || work_bytes < need))
+        return fail(MLMC_ERR_WORKSPACE, "eigvalsh_generalized: workspace %zu < %zu bytes", work_bytes, need);
+    if (batch == 0 || ld == 0) return MLMC_OK;
+    Carver cv{static_cast<char *>(d_work)};
+    EigBuffers b;
+    carve_generalized(cv, prec, ld, batch, false, b);
+    return run_generalized(prec, d_H, d_S, ld, d_n, batch, d_w, ldw, b, static_cast<hipStream_t>(stream));
+}
+
 mlmc_status mlmc_idos(const double *d_w, int64_t ldw, const int32_t *d_n, int64_t n_samples, int32_t n_k,
                       const double *d_kweight, double area, const double *d_eps, int32_t n_eps, double delta,
                       mlmc_smoother smoother, double *d_idos, mlmc_stream stream) {
@@ -441,6 +564,8 @@ static mlmc_status check_level_args(mlmc_lattice lat, int32_t N, int32_t coupled
     if (nmax > large_cap(prec))
         return fail(MLMC_ERR_UNSUPPORTED, "level: %lld orbitals exceed the %d supported by this build", (long long)nmax,
                     large_cap(prec));
+    if (lat->dev.n_ovl > 0 && nmax > kGenMax)
+        return fail(MLMC_ERR_UNSUPPORTED, "level: the overlap (generalised) path supports at most %d orbitals", kGenMax);
     return MLMC_OK;
 }
 

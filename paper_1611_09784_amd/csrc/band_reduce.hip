@@ -528,14 +528,15 @@ __global__ __launch_bounds__(kWThreads) void wfactor_kernel(const int32_t *__res
 template <typename T>
 __global__ __launch_bounds__(256) void band_update_kernel(cpx<T> *__restrict__ Hall, int64_t ld,
                                                           const int32_t *__restrict__ n_in, cpx<T> *__restrict__ wall,
-                                                          int64_t stride, int p, int64_t batch, int64_t tiles) {
+                                                          int64_t stride, int p, int64_t batch, int64_t tiles,
+                                                          int min_m) {
     __shared__ cpx<T> sVr[kB][kUpdBlk], sWr[kB][kUpdBlk], sVc[kB][kUpdBlk], sWc[kB][kUpdBlk];
     int64_t u, tile;
     xcd_tile(blockIdx.x, tiles, u, tile);
     if (u >= batch) return;
     const int n = n_in[u];
     const int s = p + kB;
-    if (n < 0 || n > ld || n - s < 2) return;
+    if (n < 0 || n > ld || n - s < min_m) return;
     // lower-triangle tile (bi, bj), bj <= bi, from tile = bi (bi + 1) / 2 + bj
     int bi = (int)((sqrt(8.0 * (double)tile + 1.0) - 1.0) * 0.5);
     while ((int64_t)bi * (bi + 1) / 2 > tile) --bi;
@@ -642,13 +643,32 @@ hipError_t launch_band_reduce(cpx<T> *H, int64_t ld, const int32_t *n_in, int64_
         hipLaunchKernelGGL(wfactor_kernel<T>, dim3(B), dim3(kWThreads), 0, s, n_in, ld, work, stride, p);
         const int64_t nblk = (mmax + kUpdBlk - 1) / kUpdBlk, ntile = nblk * (nblk + 1) / 2;
         hipLaunchKernelGGL(band_update_kernel<T>, dim3(xcd_grid(batch, ntile)), dim3(256), 0, s, H, ld, n_in, work,
-                           stride, p, batch, ntile);
+                           stride, p, batch, ntile, 2);
         const hipError_t err = hipGetLastError();
         if (err != hipSuccess) return err;
     }
     return hipSuccess;
 }
 
+// A22 <- A22 - V W^H - W V^H on the lower triangle of the trailing matrix
+// below panel p (rows and columns p + 16 .. n - 1), V and W from the
+// per-matrix workspace (stride elements apart); skipped when fewer than
+// min_m trailing rows remain.
+template <typename T>
+hipError_t launch_rank2k_update(cpx<T> *H, int64_t ld, const int32_t *n_in, int64_t batch, cpx<T> *work,
+                                int64_t stride, int p, int min_m, hipStream_t s) {
+    if (batch == 0 || p + kB >= ld) return hipSuccess;
+    const int64_t mmax = ld - p - kB;
+    const int64_t nblk = (mmax + kUpdBlk - 1) / kUpdBlk, ntile = nblk * (nblk + 1) / 2;
+    hipLaunchKernelGGL(band_update_kernel<T>, dim3(xcd_grid(batch, ntile)), dim3(256), 0, s, H, ld, n_in, work, stride,
+                       p, batch, ntile, min_m);
+    return hipGetLastError();
+}
+
+template hipError_t launch_rank2k_update<double>(cpx<double> *, int64_t, const int32_t *, int64_t, cpx<double> *,
+                                                 int64_t, int, int, hipStream_t);
+template hipError_t launch_rank2k_update<float>(cpx<float> *, int64_t, const int32_t *, int64_t, cpx<float> *,
+                                                int64_t, int, int, hipStream_t);
 template size_t tridiag_twostage_work_elems<double>(int64_t);
 template size_t tridiag_twostage_work_elems<float>(int64_t);
 template hipError_t launch_band_reduce<double>(cpx<double> *, int64_t, const int32_t *, int64_t, cpx<double> *,

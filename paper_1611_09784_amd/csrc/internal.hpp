@@ -58,6 +58,10 @@ struct DevLattice {
     int n_hops;
     uint32_t lattice_id;
     double cell_area;
+    // overlap table of a non-orthogonal basis (n_ovl == 0: orthogonal)
+    const int4 *ovl_i;
+    const double4 *ovl_f;
+    int n_ovl;
 };
 
 // Largest pristine matrix side handled by the LDS-resident fused kernel.
@@ -83,7 +87,7 @@ int kgrid_count(int kind, int K);
 
 template <typename T>
 hipError_t launch_assemble(const DevLattice &lat, int N, const uint8_t *masks, int64_t n_samples, const double *kred,
-                           int n_k, cpx<T> *H, int64_t ld, int32_t *n_out, hipStream_t s);
+                           int n_k, cpx<T> *H, int64_t ld, int32_t *n_out, hipStream_t s, bool overlap = false);
 
 // Fused LDS kernel: (assemble or load) -> Householder -> bisection -> eigenvalues.
 template <typename T>
@@ -106,6 +110,21 @@ hipError_t launch_band_chase(const cpx<T> *H, int64_t ld, const int32_t *n_in, i
                              int64_t lde, cpx<T> *work, hipStream_t s);
 template <typename T>
 size_t tridiag_twostage_work_elems(int64_t ld);
+// Rank-2k update A22 -= V W^H + W V^H below panel p (see band_reduce.hip).
+template <typename T>
+hipError_t launch_rank2k_update(cpx<T> *H, int64_t ld, const int32_t *n_in, int64_t batch, cpx<T> *work,
+                                int64_t stride, int p, int min_m, hipStream_t s);
+
+// Generalised problem H c = E S c (generalized.hip): S = L L^H in place in S
+// (lower), H <- L^{-1} H L^{-H} in place (lower triangle).  Workspace per
+// matrix: generalized_work_elems complex elements.  Supported for
+// ld <= kGenMax.
+constexpr int kGenMax = 1024;
+template <typename T>
+size_t generalized_work_elems(int64_t ld);
+template <typename T>
+hipError_t launch_cholesky_reduce(cpx<T> *H, cpx<T> *S, int64_t ld, const int32_t *n_in, int64_t batch, cpx<T> *work,
+                                  hipStream_t s);
 
 // Sturm-count bisection of (d, e) -> ascending eigenvalues.
 hipError_t launch_bisect(const double *d, const double *e, int64_t lde, const int32_t *n_in, int64_t batch,

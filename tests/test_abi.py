@@ -87,7 +87,7 @@ def test_validation_without_device(B):
 def test_lattice_descriptor_layout(B):
     # the binding's ctypes structs match the C layout (8-byte aligned doubles)
     assert C.sizeof(B._Hop) == 32
-    assert C.sizeof(B._LatticeDesc) == 56
+    assert C.sizeof(B._LatticeDesc) == 72
 
 
 def test_kgrid_points_host_only(B):
@@ -99,3 +99,14 @@ def test_kgrid_points_host_only(B):
     assert B.lib().mlmc_kgrid_points(3, 4, C.byref(out)) == B.MLMC_ERR_INVALID_ARG
     assert B.lib().mlmc_kgrid_points(2, 0, C.byref(out)) == B.MLMC_ERR_INVALID_ARG
     assert B.lib().mlmc_kgrid_points(2, 4, None) == B.MLMC_ERR_INVALID_ARG
+
+
+def test_generalized_workspace_limits(B):
+    out = C.c_size_t()
+    lib = B.lib()
+    assert lib.mlmc_generalized_workspace(B.MLMC_C128, B.MLMC_PREC_FP64, 1025, 1, C.byref(out)) == \
+        B.MLMC_ERR_UNSUPPORTED
+    assert lib.mlmc_generalized_workspace(B.MLMC_C128, B.MLMC_PREC_FP64, 64, 3, C.byref(out)) == B.MLMC_OK
+    assert out.value > 0                    # the generalised path always needs its workspace
+    assert lib.mlmc_generalized_workspace(B.MLMC_C64, B.MLMC_PREC_FP64, 64, 3, C.byref(out)) == \
+        B.MLMC_ERR_UNSUPPORTED

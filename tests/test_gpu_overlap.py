@@ -1,0 +1,124 @@
+"""GPU parity of the non-orthogonal (overlap) path: S(k) assembly, the
+batched generalised eigensolver (Cholesky + two-sided reduction on the GPU)
+and a level call on the graphene overlap model of Section 3.1, against the
+FP64 oracle and LAPACK."""
+
+import sys
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from mlmc_inputs import energy_grid, graphene, graphene_overlap  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1611_09784_amd import binding
+    binding.lib()
+    return binding
+
+
+@pytest.fixture(scope="module")
+def odev(B):
+    d = B.DeviceLattice(graphene_overlap(eps_2p=0.3), 0)
+    yield d
+    d.close()
+
+
+def check_eigs(got, want_list, sizes, rel):
+    for u, m in enumerate(sizes):
+        if m == 0:
+            continue
+        want = want_list[u]
+        assert np.abs(got[u, :m] - want).max() <= rel * max(1.0, np.abs(want).max()), (u, m)
+
+
+@pytest.mark.parametrize("N,p", [(3, 0.3), (1, 0.0), (5, 0.2)])
+def test_build_overlaps(B, odev, N, p):
+    say(f"[overlap build] N={N} p={p}")
+    mask = B.mlmc_sample_vacancies(odev, N, p, 5, odev.tag(N), 0, 3)
+    kred, _ = B.mlmc_kgrid(0, 2)
+    S, n = B.mlmc_build_overlaps(odev, N, mask, kred)
+    Sc, nc, m = S.cpu().numpy(), n.cpu().numpy(), mask.cpu().numpy()
+    kr = kred.cpu().numpy()
+    for u in range(Sc.shape[0]):
+        s, k = divmod(u, kr.shape[0])
+        want = oracle.build_overlap(odev.lat, N, m[s], kr[k])
+        got = Sc[u].T[: nc[u], : nc[u]]
+        assert want.shape[0] == nc[u]
+        assert np.abs(got - want).max() < 1e-14
+
+
+@pytest.mark.parametrize("N,K", [(4, 2), (12, 1)])
+def test_generalized_eigvalsh_lattice(B, odev, N, K):
+    say(f"[generalized lattice] N={N} K={K}")
+    mask = B.mlmc_sample_vacancies(odev, N, 0.1, 9, odev.tag(N), 0, 2)
+    kred, _ = B.mlmc_kgrid(1, K)
+    H, n = B.mlmc_build_hamiltonians(odev, N, mask, kred)
+    S, _ = B.mlmc_build_overlaps(odev, N, mask, kred)
+    Hc, Sc, nc = H.cpu().numpy(), S.cpu().numpy(), n.cpu().numpy()
+    w = B.mlmc_batched_eigvalsh_generalized(H, S, n).cpu().numpy()
+    want = [oracle.eigvalsh_generalized(Hc[u].T[: nc[u], : nc[u]], Sc[u].T[: nc[u], : nc[u]]) for u in range(len(nc))]
+    check_eigs(w, want, nc, 1e-9)
+
+
+@pytest.mark.parametrize("ld,sizes", [(40, [40, 17, 1, 0]), (200, [200, 199, 33, 2]), (700, [700, 531, 640])])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_generalized_eigvalsh_random_pencils(B, ld, sizes, prec):
+    say(f"[generalized random] ld={ld} sizes={sizes} prec={prec}")
+    rng = np.random.default_rng(ld + 7 * prec)
+    batch = len(sizes)
+    Hs = np.zeros((batch, ld, ld), np.complex128)
+    Ss = np.zeros((batch, ld, ld), np.complex128)
+    want = []
+    for u, m in enumerate(sizes):
+        A = rng.normal(size=(m, m)) + 1j * rng.normal(size=(m, m))
+        A = (A + A.conj().T) / 2
+        E = rng.normal(size=(m, m)) + 1j * rng.normal(size=(m, m))
+        Sm = np.eye(m) + 0.3 * (E @ E.conj().T) / max(m, 1)        # well-conditioned, positive definite
+        Hs[u, :m, :m] = A.T
+        Ss[u, :m, :m] = Sm.T
+        want.append(scipy.linalg.eigh(A, Sm, eigvals_only=True) if m else np.zeros(0))
+    tdt = torch.complex128 if prec == 0 else torch.complex64
+    H = torch.as_tensor(Hs, device=DEV).to(tdt)
+    S = torch.as_tensor(Ss, device=DEV).to(tdt)
+    n = torch.as_tensor(np.array(sizes, np.int32), device=DEV)
+    w = B.mlmc_batched_eigvalsh_generalized(H, S, n).cpu().numpy()
+    check_eigs(w, want, sizes, 1e-9 if prec == 0 else 5e-5)
+
+
+@pytest.mark.parametrize("N,coupled,K,Kc,kind,prec", [(4, False, 2, 2, 0, 0), (8, True, 2, 4, 1, 0),
+                                                      (4, False, 2, 2, 0, 1), (16, False, 1, 1, 1, 0)])
+def test_overlap_level_parity(B, odev, N, coupled, K, Kc, kind, prec):
+    say(f"[overlap level] N={N} coupled={coupled} prec={prec}")
+    eps = energy_grid(-9.0, 18.0, 201)
+    M = 3
+    got = B.mlmc_level_estimate(odev, N, coupled, 0.1, K, Kc, kind, 77, 2, M, torch.as_tensor(eps, device=DEV), 0.1,
+                                prec=prec).cpu().numpy()
+    want = oracle.level_estimate(odev.lat, N, coupled, 0.1, K, Kc, kind, 77, 2, M, eps, 0.1, 0, n_threads=8)
+    tol = 1e-10 if prec == 0 else 1e-5
+    assert np.abs(got[0] - want[0]).max() <= M * tol
+    assert np.abs(got[2] - want[2]).max() <= M * tol
+
+
+def test_overlap_errors(B):
+    d = B.DeviceLattice(graphene(), 0)
+    try:
+        mask = B.mlmc_sample_vacancies(d, 2, 0.0, 1, d.tag(2), 0, 1)
+        kred, _ = B.mlmc_kgrid(0, 1)
+        with pytest.raises(B.MLMCError):
+            B.mlmc_build_overlaps(d, 2, mask, kred)
+    finally:
+        d.close()
