@@ -261,7 +261,7 @@ def main():
     elapsed = time.perf_counter() - t0
     B.mlmc_timer_enable(False)
     kernels = {}
-    for name in ("sample_vacancies", "kgrid", "assemble", "small_fused", "band_reduce", "chase", "bisect", "idos",
+    for name in ("sample_vacancies", "kgrid", "assemble", "small_fused", "overlap_reduce", "band_reduce", "chase", "bisect", "idos",
                  "level_stats"):
         ms, cnt = B.mlmc_timer_read(name)
         if cnt:

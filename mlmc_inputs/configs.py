@@ -16,7 +16,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from .lattices import Lattice, graphene, mos2_shaped
+from .lattices import Lattice, graphene, lattice_by_name, mos2_shaped
 
 KGRID_MP = 0      # Monkhorst-Pack K x K grid
 KGRID_GAMMA = 1   # Gamma-centred K x K grid
@@ -60,7 +60,7 @@ class Workload:
     tol: float = 0.0                               # MLMC: relative tolerance
 
     def make_lattice(self) -> Lattice:
-        return graphene() if self.lattice == "graphene" else mos2_shaped()
+        return lattice_by_name(self.lattice)
 
     def eps(self) -> np.ndarray:
         return energy_grid(self.eps_lo, self.eps_hi, self.n_eps)
@@ -80,6 +80,11 @@ WORKLOADS = {
                               kgrid=KGRID_GAMMA, M=16, seed=303, n_eps=401,
                               eps_lo=-9.0, eps_hi=9.0, delta=0.05,
                               levels=(4, 8, 16, 32), NK=32, tol=1e-3),
+    # The graphene N=16 plain-MC workload in the non-orthogonal model of
+    # Section 3.1 (t = -3.033 eV, s = 0.129, eps_2p = 0): generalised problems.
+    "graphene_n16_overlap_mc": Workload("graphene_n16_overlap_mc", "graphene_overlap", N=16, p=0.05, K=8,
+                                        kgrid=KGRID_MP, M=2000, seed=202, n_eps=401,
+                                        eps_lo=-8.0, eps_hi=16.0, delta=0.05),
     # MoS2-shaped, N = 4, 8, 16 with a 6x6 grid at every N.
     "mos2_mlmc": Workload("mos2_mlmc", "mos2_shaped", N=16, p=0.02, K=6,
                           kgrid=KGRID_GAMMA, M=16, seed=404, n_eps=401,
@@ -89,7 +94,7 @@ WORKLOADS = {
 
 
 def workload_eps(w: Workload) -> np.ndarray:
-    if w.lattice == "graphene":
+    if w.lattice in ("graphene", "graphene_overlap"):
         return w.eps()
     lo, hi = mos2_energy_window(mos2_shaped())
     return energy_grid(lo, hi, w.n_eps)
