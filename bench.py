@@ -15,8 +15,9 @@ the 2000 samples of the workload.
 Prints one JSON line.  ``value`` is eigensolves per second of the whole job.
 ``roofline`` reports the single kernel with the largest share, the
 band-to-tridiagonal chase, timed with HIP events on the library's stream
-during the timed region, against the HBM peak: algorithmic bytes per launch
-(``chase_bytes``) over the average launch duration; ``traffic`` is the HBM
+during the timed region, against the vector ALU peak: algorithmic flops per
+launch (``chase_flops``) over the average launch duration, with its
+algorithmic HBM bytes (``chase_bytes``) alongside; ``traffic`` is the HBM
 bytes per launch measured with rocprofv3 counters (recorded in profiles/ with
 the hash of the kernel source, null if the source has changed since).
 ``time_to_tol`` runs the MLMC estimator of the graphene level hierarchy to
@@ -51,35 +52,54 @@ CHASE_SOURCES = [os.path.join(ROOT, "paper_1611_09784_amd", "csrc", f)
 CHASE_PROFILE = os.path.join(ROOT, "profiles", "chase_kernel_graphene_n16_fp64.md")
 
 
+# Shape of the chase: S sweeps in flight per matrix through a ring of WC band
+# columns in LDS (FP64: 4 and 256, FP32: 8 and 512), 2 BAND sub-diagonals per column.
+CHASE_SHAPE = {16: (4, 256), 8: (8, 512)}
+
+
+def _sweep_blocks(n: int, j: int):
+    """(L, L1, Lprev) of every step of sweep j on a band of side n."""
+    lo, hi = j + 1, min(j + BAND, n - 1)
+    L = hi - lo + 1
+    lo1, hi1 = hi + 1, min(hi + BAND, n - 1)
+    L1 = hi1 - lo1 + 1
+    Lprev = 1
+    while True:
+        yield L, L1, Lprev
+        if L1 < 2:
+            return
+        lo2, hi2 = hi1 + 1, min(hi1 + BAND, n - 1)
+        Lprev, L, L1, hi1 = L, L1, hi2 - lo2 + 1, hi2
+
+
+def chase_flops(n: int) -> float:
+    """Floating-point operations of the band-to-tridiagonal chase for one
+    matrix of side n (8 per complex multiply-add): per step, v^H B and the
+    update of B (L x Lprev), D v, v^H D v and the rank-2 update of the L x L
+    diagonal block, E v and the update of E (L1 x L)."""
+    f = 0.0
+    for j in range(max(n - 2, 0)):
+        for L, L1, Lp in _sweep_blocks(n, j):
+            f += 8.0 * (2 * L * Lp + 3 * L * L + 2 * L + 2 * max(L1, 0) * L)
+    return f
+
+
 def chase_bytes(n: int, esize: int) -> int:
-    """Algorithmic HBM bytes of the band-to-tridiagonal chase for one matrix
-    of side n (esize bytes per complex element): copy of the lower band of
-    H into the band array (17 diagonals read, 33 written), then per step of
-    every sweep the unique elements read (lower part of the diagonal block and
-    the block below it) and written (the block left of the diagonal block and
-    the lower part of the diagonal block), and finally d and e."""
-    if n < 3:
-        return n * (BAND + 1 + 2 * BAND + 1) * esize + 3 * n * 8
-    tri = lambda L: L * (L + 1) // 2
-    elems = n * (BAND + 1) + n * (2 * BAND + 1)
-    for j in range(n - 2):
-        lo, hi = j + 1, min(j + BAND, n - 1)
-        L = hi - lo + 1
-        lo1, hi1 = hi + 1, min(hi + BAND, n - 1)
-        L1 = hi1 - lo1 + 1
-        Lprev = 1
-        elems += L + tri(L) + max(L1, 0) * L
-        while True:
-            elems += L * Lprev + tri(L)
-            lo2, hi2 = hi1 + 1, min(hi1 + BAND, n - 1)
-            L2 = hi2 - lo2 + 1
-            if L1 < 2:
-                if L1 == 1:
-                    elems += L
-                break
-            elems += tri(L1) + max(L2, 0) * L1
-            Lprev, lo, hi, L, lo1, hi1, L1 = L, lo1, hi1, L1, lo2, hi2, L2
-    return elems * esize + (2 * n - 1) * esize + 2 * n * 8
+    """Algorithmic HBM bytes of the chase for one matrix of side n (esize
+    bytes per complex element).  S sweeps at a time run through the LDS ring;
+    while the rest of the band is wider than the ring, each batch of S sweeps
+    reads the remaining columns (2 BAND sub-diagonals each; the first batch
+    reads BAND + 1 of them from the matrix) and writes back those after its
+    own S columns; once the rest fits, it is read once and stays.  Plus d and e."""
+    S, WC = CHASE_SHAPE[esize]
+    nsw = max(n - 2, 0)
+    col = 2 * BAND * esize
+    total, j0 = 0, 0
+    while j0 < nsw and n - j0 > WC:
+        total += (n - j0) * ((BAND + 1) * esize if j0 == 0 else col) + (n - j0 - S) * col
+        j0 += S
+    total += (n - j0) * ((BAND + 1) * esize if j0 == 0 else col)
+    return total + max(2 * n - 1, 0) * 8
 
 
 def chase_traffic_per_solve():
@@ -279,19 +299,26 @@ def main():
     roofline = None
     esize = 16 if prec == B.MLMC_PREC_FP64 else 8
     if "chase" in kernels:
-        # The single kernel with the largest share: the band-to-tridiagonal chase,
-        # bound by HBM traffic.  Algorithmic bytes per launch / event-timed duration.
+        # The single kernel with the largest share: the band-to-tridiagonal
+        # chase.  With the band staged through LDS it moves little HBM traffic;
+        # its bound is the vector ALU (one wavefront per SIMD in FP64), so the
+        # roofline is its algorithmic flops per launch over the event-timed
+        # duration against the vector peak, with the HBM side alongside.
         sizes, counts = np.unique(n_per_sample, return_counts=True)
+        total_flops = float(nk * sum(int(c) * chase_flops(int(v)) for v, c in zip(sizes, counts)))
         total_bytes = float(nk * sum(int(c) * chase_bytes(int(v), esize) for v, c in zip(sizes, counts)))
         launches = kernels["chase"]["launches"]
         kms = kernels["chase"]["ms"]
-        achieved = total_bytes / (kms * 1e-3) / 1e9
+        peak = FP64_PEAK_TFLOPS if prec == B.MLMC_PREC_FP64 else FP32_PEAK_TFLOPS
+        achieved = total_flops / (kms * 1e-3) / 1e12
         per_solve = chase_traffic_per_solve() if prec == B.MLMC_PREC_FP64 and wl.name == "graphene_n16_mc" else None
-        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4),
+        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                    "frac": round(achieved / peak, 4),
                     "traffic": None if per_solve is None else round(per_solve * solves / launches),
                     "kernel": "chase_kernel", "avg_launch_ms": round(kms / launches, 3),
-                    "bytes_per_launch": round(total_bytes / launches),
+                    "flops_per_launch": round(total_flops / launches),
+                    "hbm_bytes_per_launch": round(total_bytes / launches),
+                    "hbm_gbs": round(total_bytes / (kms * 1e-3) / 1e9, 1),
                     "tridiag_flops_per_s": round(flops / ((kms + kernels.get("band_reduce", {"ms": 0})["ms"]) * 1e-3)
                                                  / 1e12, 3)}
     elif "small_fused" in kernels:
