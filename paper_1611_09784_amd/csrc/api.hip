@@ -106,13 +106,33 @@ struct EigBuffers {
     void *H = nullptr;
     void *S = nullptr;  // overlap matrices (non-orthogonal basis only)
     double *d = nullptr, *e = nullptr;
+    double *d2 = nullptr, *e2 = nullptr;  // second tridiagonal set (pipelined level estimates)
     void *partial = nullptr;
+
+    // The view whose d, e are tridiagonal set `parity` (0 or 1).
+    EigBuffers set(int parity) const {
+        EigBuffers v = *this;
+        if (parity) {
+            v.d = d2;
+            v.e = e2;
+        }
+        return v;
+    }
 };
 
-void carve_large(Carver &cv, mlmc_precision prec, int64_t ld, int64_t units, bool with_H, EigBuffers &b) {
-    if (with_H) b.H = cv.take<void>(cplx_bytes(prec) * (size_t)ld * (size_t)ld * (size_t)units);
+void carve_tridiagonal(Carver &cv, int64_t ld, int64_t units, bool twin, EigBuffers &b) {
     b.d = cv.take<double>(sizeof(double) * (size_t)ld * (size_t)units);
     b.e = cv.take<double>(sizeof(double) * (size_t)ld * (size_t)units);
+    if (twin) {
+        b.d2 = cv.take<double>(sizeof(double) * (size_t)ld * (size_t)units);
+        b.e2 = cv.take<double>(sizeof(double) * (size_t)ld * (size_t)units);
+    }
+}
+
+void carve_large(Carver &cv, mlmc_precision prec, int64_t ld, int64_t units, bool with_H, EigBuffers &b,
+                 bool twin = false) {
+    if (with_H) b.H = cv.take<void>(cplx_bytes(prec) * (size_t)ld * (size_t)ld * (size_t)units);
+    carve_tridiagonal(cv, ld, units, twin, b);
     const size_t pe = prec == MLMC_PREC_FP64 ? tridiag_twostage_work_elems<double>(ld)
                                              : tridiag_twostage_work_elems<float>(ld);
     b.partial = cv.take<void>(cplx_bytes(prec) * pe * (size_t)units);
@@ -121,20 +141,28 @@ void carve_large(Carver &cv, mlmc_precision prec, int64_t ld, int64_t units, boo
 // Buffers of the generalised path (any ld <= kGenMax): H and S when asked for,
 // d, e, and the per-matrix workspace of the Cholesky / two-sided reduction,
 // which the two-stage reduction reuses afterwards.
-void carve_generalized(Carver &cv, mlmc_precision prec, int64_t ld, int64_t units, bool with_HS, EigBuffers &b) {
+void carve_generalized(Carver &cv, mlmc_precision prec, int64_t ld, int64_t units, bool with_HS, EigBuffers &b,
+                       bool twin = false) {
     if (with_HS) {
         b.H = cv.take<void>(cplx_bytes(prec) * (size_t)ld * (size_t)ld * (size_t)units);
         b.S = cv.take<void>(cplx_bytes(prec) * (size_t)ld * (size_t)ld * (size_t)units);
     }
-    b.d = cv.take<double>(sizeof(double) * (size_t)ld * (size_t)units);
-    b.e = cv.take<double>(sizeof(double) * (size_t)ld * (size_t)units);
+    carve_tridiagonal(cv, ld, units, twin, b);
     const size_t pe = prec == MLMC_PREC_FP64 ? generalized_work_elems<double>(ld) : generalized_work_elems<float>(ld);
     b.partial = cv.take<void>(cplx_bytes(prec) * pe * (size_t)units);
 }
 
-// Eigenvalues of `units` matrices already in b.H (ld > small cap).
+// Eigenvalues of `units` matrices already in b.H (ld > small cap).  With
+// defer_bisect the tridiagonal matrices are left in b.d, b.e and the caller
+// runs the bisection (run_bisect) itself.
+mlmc_status run_bisect(const int32_t *n, int64_t ld, int64_t units, double *w, int64_t ldw, const EigBuffers &b,
+                       hipStream_t s, int64_t max_blocks = 0) {
+    LAUNCH("bisect", s, launch_bisect(b.d, b.e, ld, n, units, ld, w, ldw, s, max_blocks));
+    return MLMC_OK;
+}
+
 mlmc_status run_large(mlmc_precision prec, void *H, int64_t ld, const int32_t *n, int64_t units, double *w, int64_t ldw,
-                      const EigBuffers &b, hipStream_t s) {
+                      const EigBuffers &b, hipStream_t s, bool defer_bisect = false) {
     if (prec == MLMC_PREC_FP64) {
         cpx<double> *Hc = static_cast<cpx<double> *>(H), *wk = static_cast<cpx<double> *>(b.partial);
         LAUNCH("band_reduce", s, launch_band_reduce<double>(Hc, ld, n, units, wk, s));
@@ -144,16 +172,19 @@ mlmc_status run_large(mlmc_precision prec, void *H, int64_t ld, const int32_t *n
         LAUNCH("band_reduce", s, launch_band_reduce<float>(Hc, ld, n, units, wk, s));
         LAUNCH("chase", s, launch_band_chase<float>(Hc, ld, n, units, b.d, b.e, ld, wk, s));
     }
-    LAUNCH("bisect", s, launch_bisect(b.d, b.e, ld, n, units, ld, w, ldw, s));
-    return MLMC_OK;
+    if (defer_bisect) return MLMC_OK;
+    return run_bisect(n, ld, units, w, ldw, b, s);
 }
 
-// Layout of mlmc_level_estimate's workspace for a chunk of `mc` samples.
+// Layout of mlmc_level_estimate's workspace for a chunk of `mc` samples.  The
+// matrix sizes, tridiagonal matrices and eigenvalues come in two sets, one per
+// chunk parity, so that one chunk's bisection and IDoS overlap the next
+// chunk's reduction.
 struct LevelLayout {
     double *kf = nullptr, *kwf = nullptr, *kc = nullptr, *kwc = nullptr;
     uint8_t *mask = nullptr, *quarters = nullptr;
-    int32_t *nf = nullptr, *nc = nullptr;
-    double *wf = nullptr, *wc = nullptr;
+    int32_t *nf[2] = {}, *nc[2] = {};
+    double *wf[2] = {}, *wc[2] = {};
     double *If = nullptr, *Ic = nullptr;
     EigBuffers bf, bc;
     size_t bytes = 0;
@@ -173,33 +204,36 @@ LevelLayout level_layout(const mlmc_lattice_s *lat, int N, bool coupled, int Kf,
     L.kf = cv.take<double>(sizeof(double) * 2 * nkf);
     L.kwf = cv.take<double>(sizeof(double) * nkf);
     L.mask = cv.take<uint8_t>((size_t)mc * N * N * G);
-    L.nf = cv.take<int32_t>(sizeof(int32_t) * (size_t)(mc * nkf));
-    L.wf = cv.take<double>(sizeof(double) * (size_t)(mc * nkf * ldf));
+    for (int q = 0; q < 2; ++q) {
+        L.nf[q] = cv.take<int32_t>(sizeof(int32_t) * (size_t)(mc * nkf));
+        L.wf[q] = cv.take<double>(sizeof(double) * (size_t)(mc * nkf * ldf));
+    }
     L.If = cv.take<double>(sizeof(double) * (size_t)mc * n_eps);
     const bool gen = lat->dev.n_ovl > 0;
-    if (gen) carve_generalized(cv, prec, ldf, mc * nkf, true, L.bf);
-    else if (ldf > small_cap(prec)) carve_large(cv, prec, ldf, mc * nkf, true, L.bf);
+    if (gen) carve_generalized(cv, prec, ldf, mc * nkf, true, L.bf, true);
+    else if (ldf > small_cap(prec)) carve_large(cv, prec, ldf, mc * nkf, true, L.bf, true);
     if (coupled) {
         const int h = N / 2;
         const int64_t ldc = (int64_t)no * h * h;
         L.kc = cv.take<double>(sizeof(double) * 2 * nkc);
         L.kwc = cv.take<double>(sizeof(double) * nkc);
         L.quarters = cv.take<uint8_t>((size_t)mc * 4 * h * h * G);
-        L.nc = cv.take<int32_t>(sizeof(int32_t) * (size_t)(mc * 4 * nkc));
-        L.wc = cv.take<double>(sizeof(double) * (size_t)(mc * 4 * nkc * ldc));
+        for (int q = 0; q < 2; ++q) {
+            L.nc[q] = cv.take<int32_t>(sizeof(int32_t) * (size_t)(mc * 4 * nkc));
+            L.wc[q] = cv.take<double>(sizeof(double) * (size_t)(mc * 4 * nkc * ldc));
+        }
         L.Ic = cv.take<double>(sizeof(double) * (size_t)mc * 4 * n_eps);
-        if (gen) carve_generalized(cv, prec, ldc, mc * 4 * nkc, true, L.bc);
-        else if (ldc > small_cap(prec)) carve_large(cv, prec, ldc, mc * 4 * nkc, true, L.bc);
+        if (gen) carve_generalized(cv, prec, ldc, mc * 4 * nkc, true, L.bc, true);
+        else if (ldc > small_cap(prec)) carve_large(cv, prec, ldc, mc * 4 * nkc, true, L.bc, true);
     }
     L.bytes = cv.used;
     return L;
 }
 
-// Eigenvalues of every (outcome, k) unit of `ns` outcomes of side N.
 // Pencils (H, S) already in b.H, b.S -> eigenvalues (reduction to C = L^{-1}
 // H L^{-H}, then the standard path on C).
 mlmc_status run_generalized(mlmc_precision prec, void *H, void *S, int64_t ld, const int32_t *n, int64_t units,
-                            double *w, int64_t ldw, const EigBuffers &b, hipStream_t s) {
+                            double *w, int64_t ldw, const EigBuffers &b, hipStream_t s, bool *bisect_pending = nullptr) {
     if (prec == MLMC_PREC_FP64)
         LAUNCH("overlap_reduce", s, launch_cholesky_reduce<double>(static_cast<cpx<double> *>(H), static_cast<cpx<double> *>(S), ld, n, units,
                                                             static_cast<cpx<double> *>(b.partial), s));
@@ -213,14 +247,19 @@ mlmc_status run_generalized(mlmc_precision prec, void *H, void *S, int64_t ld, c
             LAUNCH("small_fused", s, launch_small_from_matrix<float>(static_cast<const cpx<float> *>(H), ld, n, units, w, ldw, s));
         return MLMC_OK;
     }
-    return run_large(prec, H, ld, n, units, w, ldw, b, s);
+    if (bisect_pending) *bisect_pending = true;
+    return run_large(prec, H, ld, n, units, w, ldw, b, s, bisect_pending != nullptr);
 }
 
+// Eigenvalues of every (outcome, k) unit of `ns` outcomes of side N.  With
+// bisect_pending, a path that ends in a bisection stops before it and says so
+// (the caller then calls run_bisect on the same buffers).
 mlmc_status outcome_spectra(const mlmc_lattice_s *lat, int N, const uint8_t *mask, int64_t ns, const double *kred,
                             int nk, mlmc_precision prec, double *w, int32_t *n_out, const EigBuffers &b,
-                            hipStream_t s) {
+                            hipStream_t s, bool *bisect_pending = nullptr) {
     const int64_t ld = (int64_t)lat->dev.n_orb * N * N;
     const int64_t units = ns * nk;
+    if (bisect_pending) *bisect_pending = false;
     if (lat->dev.n_ovl > 0) {  // non-orthogonal basis: assemble H and S, generalised path
         if (prec == MLMC_PREC_FP64) {
             LAUNCH("assemble", s, launch_assemble<double>(lat->dev, N, mask, ns, kred, nk, static_cast<cpx<double> *>(b.H), ld, n_out, s));
@@ -229,7 +268,7 @@ mlmc_status outcome_spectra(const mlmc_lattice_s *lat, int N, const uint8_t *mas
             LAUNCH("assemble", s, launch_assemble<float>(lat->dev, N, mask, ns, kred, nk, static_cast<cpx<float> *>(b.H), ld, n_out, s));
             LAUNCH("assemble", s, launch_assemble<float>(lat->dev, N, mask, ns, kred, nk, static_cast<cpx<float> *>(b.S), ld, n_out, s, true));
         }
-        return run_generalized(prec, b.H, b.S, ld, n_out, units, w, ld, b, s);
+        return run_generalized(prec, b.H, b.S, ld, n_out, units, w, ld, b, s, bisect_pending);
     }
     if (ld <= small_cap(prec)) {
         if (prec == MLMC_PREC_FP64)
@@ -242,7 +281,46 @@ mlmc_status outcome_spectra(const mlmc_lattice_s *lat, int N, const uint8_t *mas
         LAUNCH("assemble", s, launch_assemble<double>(lat->dev, N, mask, ns, kred, nk, static_cast<cpx<double> *>(b.H), ld, n_out, s));
     else
         LAUNCH("assemble", s, launch_assemble<float>(lat->dev, N, mask, ns, kred, nk, static_cast<cpx<float> *>(b.H), ld, n_out, s));
-    return run_large(prec, b.H, ld, n_out, units, w, ld, b, s);
+    if (bisect_pending) *bisect_pending = true;
+    return run_large(prec, b.H, ld, n_out, units, w, ld, b, s, bisect_pending != nullptr);
+}
+
+// The library's second stream on the current device, with the events that
+// order it against the caller's stream in mlmc_level_estimate.  Created on
+// first use, default priority; kept until the process ends.
+struct BackStream {
+    hipStream_t s = nullptr;
+    int64_t bisect_blocks = 0;    // workgroups of a bisection on this stream: one per CU
+    hipEvent_t begin = nullptr;   // caller's stream -> back stream
+    hipEvent_t ready = nullptr;   // front (caller's stream) -> back: a chunk's tridiagonals are complete
+    hipEvent_t freed[2] = {};     // back -> front: set q of the sizes / tridiagonals / eigenvalues is free
+    hipEvent_t end = nullptr;     // back -> caller's stream
+};
+constexpr int kMaxDevices = 64;
+std::mutex g_back_mu;  // held while a level estimate enqueues its work
+BackStream g_back[kMaxDevices];
+
+hipError_t back_stream(BackStream **out) {
+    int dev = 0;
+    hipError_t err = hipGetDevice(&dev);
+    if (err != hipSuccess) return err;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    BackStream &b = g_back[dev];
+    if (!b.s) {
+        // One bisection workgroup per CU leaves the rest of each CU to the
+        // next chunk's reduction on the caller's stream (measured best among
+        // 1/4 to 8 per CU on the graphene N = 16 workload).
+        int cus = 0;
+        err = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (err != hipSuccess) return err;
+        b.bisect_blocks = cus > 0 ? cus : 1;
+        err = hipStreamCreateWithFlags(&b.s, hipStreamNonBlocking);
+        hipEvent_t *evs[5] = {&b.begin, &b.ready, &b.freed[0], &b.freed[1], &b.end};
+        for (int i = 0; i < 5 && err == hipSuccess; ++i) err = hipEventCreateWithFlags(evs[i], hipEventDisableTiming);
+        if (err != hipSuccess) return err;
+    }
+    *out = &b;
+    return hipSuccess;
 }
 
 mlmc_status convert_hops(const mlmc_lattice_desc *desc, const mlmc_hop *rows, int count, const char *what,
@@ -613,24 +691,57 @@ mlmc_status mlmc_level_estimate(mlmc_lattice lat, int32_t N, int32_t coupled, do
     const double inv_area_f = 1.0 / ((double)N * N * lat->dev.cell_area);
     const double inv_area_c = cpl ? 1.0 / ((double)h * h * lat->dev.cell_area) : 0.0;
     const int nkf = kgrid_count(kind, Kf), nkc = cpl ? kgrid_count(kind, Kc) : 0;
+    const int64_t ldf = (int64_t)lat->dev.n_orb * N * N, ldc = (int64_t)lat->dev.n_orb * h * h;
+    // Two streams: the caller's (front) samples, assembles and reduces chunk
+    // c; the back stream runs chunk c's bisection, IDoS and level sums while
+    // the front goes on with chunk c + 1.  Sizes, tridiagonals and eigenvalues
+    // alternate between two sets; the front waits until the back has released
+    // a set before refilling it.
+    std::lock_guard<std::mutex> lk(g_back_mu);
+    BackStream *bk = nullptr;
+    HIP_TRY(back_stream(&bk), "level: back stream");
+    hipStream_t sb = bk->s;
+    HIP_TRY(hipEventRecord(bk->begin, s), "level: event");
+    HIP_TRY(hipStreamWaitEvent(sb, bk->begin, 0), "level: wait");
+    for (int q = 0; q < 2; ++q) HIP_TRY(hipEventRecord(bk->freed[q], sb), "level: event");
     LAUNCH("kgrid", s, launch_kgrid(kind, Kf, L.kf, L.kwf, s));
     if (cpl) LAUNCH("kgrid", s, launch_kgrid(kind, Kc, L.kc, L.kwc, s));
-    for (int64_t done = 0; done < M; done += mc) {
+    int64_t chunk = 0;
+    for (int64_t done = 0; done < M; done += mc, ++chunk) {
         const int64_t ns = (M - done < mc) ? (M - done) : mc;
+        const int q = (int)(chunk & 1);
+        HIP_TRY(hipStreamWaitEvent(s, bk->freed[q], 0), "level: wait");
         LAUNCH("sample_vacancies", s, launch_sample_vacancies(lat->dev, N, thr, seed, tag, first_sample + done, ns, L.mask, s));
-        st = outcome_spectra(lat, N, L.mask, ns, L.kf, nkf, prec, L.wf, L.nf, L.bf, s);
+        bool pend_f = false, pend_c = false;
+        const EigBuffers bf = L.bf.set(q), bc = L.bc.set(q);
+        st = outcome_spectra(lat, N, L.mask, ns, L.kf, nkf, prec, L.wf[q], L.nf[q], bf, s, &pend_f);
         if (st != MLMC_OK) return st;
-        LAUNCH("idos", s, launch_idos(L.wf, (int64_t)lat->dev.n_orb * N * N, L.nf, ns, nkf, L.kwf, inv_area_f, d_eps, n_eps, delta,
-                            (int)smoother, L.If, s));
         if (cpl) {
             LAUNCH("partition", s, launch_partition(N, G, L.mask, ns, L.quarters, s));
-            st = outcome_spectra(lat, h, L.quarters, ns * 4, L.kc, nkc, prec, L.wc, L.nc, L.bc, s);
+            st = outcome_spectra(lat, h, L.quarters, ns * 4, L.kc, nkc, prec, L.wc[q], L.nc[q], bc, s, &pend_c);
             if (st != MLMC_OK) return st;
-            LAUNCH("idos", s, launch_idos(L.wc, (int64_t)lat->dev.n_orb * h * h, L.nc, ns * 4, nkc, L.kwc, inv_area_c, d_eps, n_eps,
-                                delta, (int)smoother, L.Ic, s));
         }
-        LAUNCH("level_stats", s, launch_level_stats(L.If, cpl ? L.Ic : nullptr, ns, n_eps, d_stats, s));
+        HIP_TRY(hipEventRecord(bk->ready, s), "level: event");
+        HIP_TRY(hipStreamWaitEvent(sb, bk->ready, 0), "level: wait");
+        if (pend_f) {
+            st = run_bisect(L.nf[q], ldf, ns * nkf, L.wf[q], ldf, bf, sb, bk->bisect_blocks);
+            if (st != MLMC_OK) return st;
+        }
+        LAUNCH("idos", sb, launch_idos(L.wf[q], ldf, L.nf[q], ns, nkf, L.kwf, inv_area_f, d_eps, n_eps, delta,
+                             (int)smoother, L.If, sb));
+        if (cpl) {
+            if (pend_c) {
+                st = run_bisect(L.nc[q], ldc, ns * 4 * nkc, L.wc[q], ldc, bc, sb, bk->bisect_blocks);
+                if (st != MLMC_OK) return st;
+            }
+            LAUNCH("idos", sb, launch_idos(L.wc[q], ldc, L.nc[q], ns * 4, nkc, L.kwc, inv_area_c, d_eps, n_eps, delta,
+                                 (int)smoother, L.Ic, sb));
+        }
+        LAUNCH("level_stats", sb, launch_level_stats(L.If, cpl ? L.Ic : nullptr, ns, n_eps, d_stats, sb));
+        HIP_TRY(hipEventRecord(bk->freed[q], sb), "level: event");
     }
+    HIP_TRY(hipEventRecord(bk->end, sb), "level: event");
+    HIP_TRY(hipStreamWaitEvent(s, bk->end, 0), "level: wait");
     return MLMC_OK;
 }
 

@@ -75,38 +75,42 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// A[r0 + r, c0 + c] for r < nrow, c < ncol, zero elsewhere.
-template <typename T, int WC>
+// A[r0 + r, c0 + c] for r < nrow, c < ncol, zero elsewhere (FULL: the block
+// is known to be whole, nrow = ncol = kB).
+template <typename T, int WC, bool FULL>
 __device__ __forceinline__ void ring_blk(const cpx<T> *win, int r0, int c0, int nrow, int ncol, Blk<T> &b) {
     const int lane = lane_id(), r = lane & 15, g = lane >> 4;
 #pragma unroll
     for (int tt = 0; tt < 4; ++tt) {
         const int c = g + 4 * tt;
-        b.e[tt] = win[opaque((r < nrow && c < ncol) ? Ring<WC>::at(r0 + r, c0 + c) : Ring<WC>::kZero)];
+        const bool ok = FULL || (r < nrow && c < ncol);
+        b.e[tt] = win[opaque(ok ? Ring<WC>::at(r0 + r, c0 + c) : Ring<WC>::kZero)];
     }
 }
 
 // Transposed: lane (c = lane & 15, g = lane >> 4) holds A[r0 + g + 4t, c0 + c].
-template <typename T, int WC>
+template <typename T, int WC, bool FULL>
 __device__ __forceinline__ void ring_blk_t(const cpx<T> *win, int r0, int c0, int nrow, int ncol, Blk<T> &b) {
     const int lane = lane_id(), c = lane & 15, g = lane >> 4;
 #pragma unroll
     for (int tt = 0; tt < 4; ++tt) {
         const int r = g + 4 * tt;
-        b.e[tt] = win[opaque((r < nrow && c < ncol) ? Ring<WC>::at(r0 + r, c0 + c) : Ring<WC>::kZero)];
+        const bool ok = FULL || (r < nrow && c < ncol);
+        b.e[tt] = win[opaque(ok ? Ring<WC>::at(r0 + r, c0 + c) : Ring<WC>::kZero)];
     }
 }
 
 // The Hermitian diagonal block A[r0.., r0..] of size L from its stored lower
 // triangle: lanes above the diagonal take the conjugate of their mirror.
-template <typename T, int WC>
+template <typename T, int WC, bool FULL>
 __device__ __forceinline__ void ring_diag(const cpx<T> *win, int r0, int L, Blk<T> &b) {
     const int lane = lane_id(), r = lane & 15, g = lane >> 4;
 #pragma unroll
     for (int tt = 0; tt < 4; ++tt) {
         const int c = g + 4 * tt;
         const int hi = r > c ? r : c, lo = r > c ? c : r;
-        const cpx<T> x = win[opaque((r < L && c < L) ? Ring<WC>::at(r0 + hi, r0 + lo) : Ring<WC>::kZero)];
+        const bool ok = FULL || (r < L && c < L);
+        const cpx<T> x = win[opaque(ok ? Ring<WC>::at(r0 + hi, r0 + lo) : Ring<WC>::kZero)];
         const T im = keep(x.im);
         b.e[tt] = {x.re, (r == c) ? T(0) : ((r < c) ? -im : im)};
     }
@@ -212,26 +216,28 @@ __device__ __forceinline__ void sweep_begin(int n, int j, Sweep &S) {
 
 // One step: load B (transposed), the diagonal block D and the block below E,
 // reflect, store B (final for this sweep), the lower triangle of D and E
-// (the next step's B).  Returns true when the sweep has ended.
-template <typename T, int WC>
-__device__ __forceinline__ bool sweep_advance(cpx<T> *win, int vb, int n, Sweep &S) {
+// (the next step's B).  Returns true when the sweep has ended.  FULL: an
+// interior step, all three blocks whole (L = L1 = Lprev = kB), no masks.
+template <typename T, int WC, bool FULL>
+__device__ __forceinline__ bool sweep_step(cpx<T> *win, int vb, int n, Sweep &S) {
     const int lane = lane_id(), r = lane & 15, g = lane >> 4;
     const int sink = Ring<WC>::kSink + lane;
+    const int L = FULL ? kB : S.L, L1 = FULL ? kB : S.L1, Lprev = FULL ? kB : S.Lprev;
     Blk<T> B, D, E;
-    ring_blk_t<T, WC>(win, S.lo, S.col0, S.L, S.Lprev, B);
-    ring_diag<T, WC>(win, S.lo, S.L, D);
-    ring_blk<T, WC>(win, S.lo1, S.lo, S.L1, S.L, E);
-    const int L = S.L;
+    ring_blk_t<T, WC, FULL>(win, S.lo, S.col0, L, Lprev, B);
+    ring_diag<T, WC, FULL>(win, S.lo, L, D);
+    ring_blk<T, WC, FULL>(win, S.lo1, S.lo, L1, L, E);
     chase_reflect<T>(win, vb, sink, L, B, D, E);
 #pragma unroll
     for (int tt = 0; tt < 4; ++tt) {
         const int i = g + 4 * tt;  // row of B held at tt; column of D and E held at tt
-        const bool okb = i < L && r < S.Lprev, okd = r < L && i < L && r >= i, oke = r < S.L1 && i < L;
+        const bool okb = FULL || (i < L && r < Lprev), okd = (FULL || (r < L && i < L)) && r >= i,
+                   oke = FULL || (r < L1 && i < L);
         win[opaque(okb ? Ring<WC>::at(S.lo + i, S.col0 + r) : sink)] = B.e[tt];
         win[opaque(okd ? Ring<WC>::at(S.lo + r, S.lo + i) : sink)] = D.e[tt];
         win[opaque(oke ? Ring<WC>::at(S.lo1 + r, S.lo + i) : sink)] = E.e[tt];
     }
-    if (S.L1 < 2) return true;  // nothing left to chase (a 1-row block needs no annihilation)
+    if (!FULL && S.L1 < 2) return true;  // nothing left to chase (a 1-row block needs no annihilation)
     S.col0 = S.lo;
     S.Lprev = L;
     S.lo = S.lo1;
@@ -241,6 +247,12 @@ __device__ __forceinline__ bool sweep_advance(cpx<T> *win, int vb, int n, Sweep 
     S.hi1 = min(S.hi1 + kB, n - 1);
     S.L1 = S.hi1 - S.lo1 + 1;
     return false;
+}
+
+template <typename T, int WC>
+__device__ __forceinline__ bool sweep_advance(cpx<T> *win, int vb, int n, Sweep &S) {
+    if (S.L == kB && S.L1 == kB && S.Lprev == kB) return sweep_step<T, WC, true>(win, vb, n, S);
+    return sweep_step<T, WC, false>(win, vb, n, S);
 }
 
 // ---------------------------------------------------------------------------

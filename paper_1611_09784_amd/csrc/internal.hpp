@@ -126,9 +126,10 @@ template <typename T>
 hipError_t launch_cholesky_reduce(cpx<T> *H, cpx<T> *S, int64_t ld, const int32_t *n_in, int64_t batch, cpx<T> *work,
                                   hipStream_t s);
 
-// Sturm-count bisection of (d, e) -> ascending eigenvalues.
+// Sturm-count bisection of (d, e) -> ascending eigenvalues; at most
+// max_blocks workgroups (0: one per matrix).
 hipError_t launch_bisect(const double *d, const double *e, int64_t lde, const int32_t *n_in, int64_t batch,
-                         int64_t ld_max, double *w, int64_t ldw, hipStream_t s);
+                         int64_t ld_max, double *w, int64_t ldw, hipStream_t s, int64_t max_blocks = 0);
 
 hipError_t launch_idos(const double *w, int64_t ldw, const int32_t *n, int64_t n_samples, int n_k,
                        const double *kweight, double inv_area, const double *eps, int n_eps, double delta,

@@ -4,44 +4,49 @@
 namespace mlmc {
 
 // ---------------------------------------------------------------------------
-// Bisection: one workgroup per tridiagonal (d, e); d and e are staged in LDS
-// (e squared there), so the serial Sturm recurrences read broadcast LDS.
+// Bisection: one workgroup per tridiagonal (d, e) at a time; d and e are
+// staged in LDS (e squared there), so the serial Sturm recurrences read
+// broadcast LDS.  A grid smaller than the batch walks it with a stride
+// (a bisection running beside other kernels keeps to a few workgroups per CU).
 // ---------------------------------------------------------------------------
 constexpr int kBisectThreads = 256;
 
 __global__ __launch_bounds__(kBisectThreads) void bisect_kernel(const double *__restrict__ dall,
                                                                 const double *__restrict__ eall, int64_t lde,
-                                                                const int32_t *__restrict__ n_in, int64_t ld_max,
-                                                                double *__restrict__ w, int64_t ldw) {
+                                                                const int32_t *__restrict__ n_in, int64_t batch,
+                                                                int64_t ld_max, double *__restrict__ w, int64_t ldw) {
     extern __shared__ __align__(16) unsigned char smem[];
     double *red = reinterpret_cast<double *>(smem);
     int *cnt = reinterpret_cast<int *>(red + 32);
     double *d = reinterpret_cast<double *>(cnt + kBisectThreads + 8);
     double *e = d + ld_max;
-    const int64_t u = blockIdx.x;
-    const int n = n_in[u];
-    double *wu = w + u * ldw;
-    if (n < 0 || n > ld_max) {
-        for (int64_t i = threadIdx.x; i < ldw && i < ld_max; i += blockDim.x) wu[i] = NAN;
-        return;
+    for (int64_t u = blockIdx.x; u < batch; u += gridDim.x) {
+        const int n = n_in[u];
+        double *wu = w + u * ldw;
+        if (n < 0 || n > ld_max) {
+            for (int64_t i = threadIdx.x; i < ldw && i < ld_max; i += blockDim.x) wu[i] = NAN;
+            continue;
+        }
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            d[i] = dall[u * lde + i];
+            e[i] = (i + 1 < n) ? eall[u * lde + i] : 0.0;
+        }
+        __syncthreads();
+        bisect_block(d, e, n, wu, red, cnt);
+        __syncthreads();  // d, e are read to the end before the next matrix replaces them
     }
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        d[i] = dall[u * lde + i];
-        e[i] = (i + 1 < n) ? eall[u * lde + i] : 0.0;
-    }
-    __syncthreads();
-    bisect_block(d, e, n, wu, red, cnt);
 }
 
 hipError_t launch_bisect(const double *d, const double *e, int64_t lde, const int32_t *n_in, int64_t batch,
-                         int64_t ld_max, double *w, int64_t ldw, hipStream_t s) {
+                         int64_t ld_max, double *w, int64_t ldw, hipStream_t s, int64_t max_blocks) {
     if (batch == 0) return hipSuccess;
     const size_t lds = 32 * sizeof(double) + (kBisectThreads + 8) * sizeof(int) + 2 * sizeof(double) * (size_t)ld_max;
     hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(bisect_kernel),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(bisect_kernel, dim3((unsigned)batch), dim3(kBisectThreads), lds, s, d, e, lde, n_in, ld_max, w,
-                       ldw);
+    const int64_t blocks = (max_blocks > 0 && max_blocks < batch) ? max_blocks : batch;
+    hipLaunchKernelGGL(bisect_kernel, dim3((unsigned)blocks), dim3(kBisectThreads), lds, s, d, e, lde, n_in, batch,
+                       ld_max, w, ldw);
     return hipGetLastError();
 }
 

@@ -140,22 +140,52 @@ __device__ __forceinline__ double lane0(double x) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
+// 1/x and 1/sqrt(x) for x >= kRefinedMin: the hardware estimates refined by
+// two Newton steps each (quadratic convergence to within about an ulp).
+constexpr double kRefinedMin = 1e-290;
+__device__ __forceinline__ double rcp_refined(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double h = fma(-x, r, 1.0);
+    r = fma(r, h, r);
+    h = fma(-x, r, 1.0);
+    return fma(r, h, r);
+}
+__device__ __forceinline__ double rsq_refined(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double h = fma(-x * y, y, 1.0);  // 1 - x y^2
+        y = fma(0.5 * y, h, y);
+    }
+    return y;
+}
+
 // Reflector of x (norm^2 nrm2, first entry x0): v0 = x0 - alpha with
-// alpha = -e^{i arg x0} |x|, tau = 2 / |v|^2 (0 when x = 0).
+// alpha = -e^{i arg x0} |x|, tau = 2 / |v|^2 = 1 / (|x| (|x| + |x0|)) (0 when
+// x = 0).  Square roots and quotients come from the refined reciprocal
+// estimates; inputs below kRefinedMin take the exact operations.
 template <typename T>
 __device__ __forceinline__ void make_reflector(double nrm2, cpx<T> x0, T &tau, cpx<T> &v0, cpx<T> &alpha) {
-    const double xnorm = sqrt(nrm2);
     tau = T(0);
     v0 = x0;
     alpha = x0;
-    if (xnorm > 0.0) {
-        const double ax0 = sqrt((double)c_abs2(x0));
-        const double pr = ax0 > 0.0 ? (double)x0.re / ax0 : 1.0;
-        const double pi = ax0 > 0.0 ? (double)x0.im / ax0 : 0.0;
-        const double v0r = (double)x0.re + pr * xnorm, v0i = (double)x0.im + pi * xnorm;
-        const double vn2 = nrm2 - ax0 * ax0 + v0r * v0r + v0i * v0i;
-        tau = (T)(2.0 / vn2);
-        v0 = {(T)v0r, (T)v0i};
+    if (nrm2 > 0.0) {
+        const double xr = (double)x0.re, xi = (double)x0.im, ax2 = xr * xr + xi * xi;
+        const double xnorm = nrm2 >= kRefinedMin ? nrm2 * rsq_refined(nrm2) : sqrt(nrm2);
+        double pr = 1.0, pi = 0.0, ax0 = 0.0;
+        if (ax2 >= kRefinedMin) {
+            const double inv = rsq_refined(ax2);
+            ax0 = ax2 * inv;
+            pr = xr * inv;
+            pi = xi * inv;
+        } else if (ax2 > 0.0) {
+            ax0 = sqrt(ax2);
+            pr = xr / ax0;
+            pi = xi / ax0;
+        }
+        const double vh = xnorm * (xnorm + ax0);  // |v|^2 / 2
+        tau = (T)(vh >= kRefinedMin ? rcp_refined(vh) : 1.0 / vh);
+        v0 = {(T)(xr + pr * xnorm), (T)(xi + pi * xnorm)};
         alpha = {(T)(-pr * xnorm), (T)(-pi * xnorm)};
     }
 }

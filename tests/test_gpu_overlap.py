@@ -99,14 +99,15 @@ def test_generalized_eigvalsh_random_pencils(B, ld, sizes, prec):
     check_eigs(w, want, sizes, 1e-9 if prec == 0 else 5e-5)
 
 
-@pytest.mark.parametrize("N,coupled,K,Kc,kind,prec", [(4, False, 2, 2, 0, 0), (8, True, 2, 4, 1, 0),
-                                                      (4, False, 2, 2, 0, 1), (16, False, 1, 1, 1, 0)])
-def test_overlap_level_parity(B, odev, N, coupled, K, Kc, kind, prec):
-    say(f"[overlap level] N={N} coupled={coupled} prec={prec}")
+@pytest.mark.parametrize("N,coupled,K,Kc,kind,prec,chunk", [(4, False, 2, 2, 0, 0, None), (8, True, 2, 4, 1, 0, None),
+                                                            (4, False, 2, 2, 0, 1, None), (16, False, 1, 1, 1, 0, None),
+                                                            (16, True, 1, 2, 1, 0, 1)])
+def test_overlap_level_parity(B, odev, N, coupled, K, Kc, kind, prec, chunk):
+    say(f"[overlap level] N={N} coupled={coupled} prec={prec} chunk={chunk}")
     eps = energy_grid(-9.0, 18.0, 201)
     M = 3
     got = B.mlmc_level_estimate(odev, N, coupled, 0.1, K, Kc, kind, 77, 2, M, torch.as_tensor(eps, device=DEV), 0.1,
-                                prec=prec).cpu().numpy()
+                                prec=prec, chunk_samples=chunk).cpu().numpy()
     want = oracle.level_estimate(odev.lat, N, coupled, 0.1, K, Kc, kind, 77, 2, M, eps, 0.1, 0, n_threads=8)
     tol = 1e-10 if prec == 0 else 1e-5
     assert np.abs(got[0] - want[0]).max() <= M * tol

@@ -290,6 +290,30 @@ def test_level_estimate_parity(B, gdev, mdev, name, N, coupled, K, Kc, kind, M, 
     compare_stats(got, want, M, 1e-10 if prec == 0 else 1e-5)
 
 
+@pytest.mark.parametrize("name,N,coupled,K,Kc,kind,M,chunk,prec", [
+    ("graphene", 16, False, 1, 1, 0, 5, 1, 0),   # device-memory path, five one-sample chunks
+    ("graphene", 16, True, 1, 2, 1, 3, 1, 1),    # mixed, coupled: fine side device-memory, coarse side fused
+    ("graphene", 8, True, 2, 4, 1, 7, 2, 0),     # fused paths, a ragged last chunk
+    ("mos2", 4, True, 1, 2, 1, 4, 1, 0),         # MoS2-shaped fine n=176 on the device-memory path
+])
+def test_level_estimate_pipelined_chunks(B, gdev, mdev, name, N, coupled, K, Kc, kind, M, chunk, prec):
+    """Several chunks in one call: each chunk's bisection, IDoS and level sums
+    run on the library's second stream while the next chunk is reduced, with
+    sizes, tridiagonals and eigenvalues alternating between two sets."""
+    say(f"[level_estimate pipelined] {name} N={N} coupled={coupled} M={M} chunk={chunk} prec={prec}")
+    dl = pick(name, gdev, mdev)
+    if name == "graphene":
+        eps = energy_grid(-9.0, 9.0, 201)
+    else:
+        b = dl.lat.hop_magnitude_bound() + 1.0
+        eps = energy_grid(-b, b, 201)
+    delta, p, seed = 0.1, 0.1, 818
+    got = B.mlmc_level_estimate(dl, N, coupled, p, K, Kc, kind, seed, 3, M, torch.as_tensor(eps, device=DEV), delta,
+                                prec=prec, chunk_samples=chunk).cpu().numpy()
+    want = oracle.level_estimate(dl.lat, N, coupled, p, K, Kc, kind, seed, 3, M, eps, delta, 0, n_threads=8)
+    compare_stats(got, want, M, 1e-10 if prec == 0 else 1e-5)
+
+
 def test_level_estimate_full_size_sample(B, gdev, glat):
     """Graphene N=16, MP 8x8, 401 energies, delta 0.05 (the 128k-eigensolve
     plain-MC workload) in the launch configuration of the benchmark, checked
