@@ -252,6 +252,14 @@ mlmc_status mlmc_level_workspace(mlmc_lattice lat, int32_t N_fine, int32_t coupl
  * quarter IDoS Q_q on the K_coarse grid of the N_fine/2 supercell, and add
  * the sums of Y = Q_f [- (1/4) sum_q Q_q], Y^2, Q_f, Q_f^2 into d_stats
  * ([4][n_eps], accumulated; the caller initialises it).
+ * Samples are processed in chunks that fit the workspace.  Each chunk's
+ * bisection, IDoS and level sums run on a second stream owned by the library
+ * (one per device, default priority, created on the first call and kept until
+ * the process ends) while the caller's stream goes on with the next chunk;
+ * the work is ordered by events, `stream` waits for the second stream before
+ * the call returns, and the sums are added in sample order as on one stream.
+ * Calls on one device enqueue one at a time (a process-wide lock) and share
+ * that second stream, so their bisections run one after another.
  * Errors: N_fine < 1, coupled with odd N_fine, K < 1, p outside [0, 1],
  * delta <= 0, workspace too small for one sample. */
 mlmc_status mlmc_level_estimate(mlmc_lattice lat, int32_t N_fine, int32_t coupled, double p, int32_t K_fine,
