@@ -6,10 +6,12 @@
 //                    Householder QR of the kB-column panel below the band,
 //                    A[s:n, p:p+kB] = Q R (s = p + kB), Q = I - V T V^H
 //                    (compact WY; reflectors of unit phase alpha = -e^{i arg x0}|x|)
-//   hemm_kernel      X = A22 V with A22 = A[s:n, s:n] read from its stored
-//                    lower triangle, one wavefront per 64 output rows, on the
-//                    matrix cores, no partial sums
-//   wfactor_kernel   W = X T - 1/2 V (T^H V^H X T)
+//                    (and V T, the Hermitian product's operand)
+//   hemm_kernel      X T = A22 (V T) with A22 = A[s:n, s:n] read from its
+//                    stored lower triangle, one wavefront per 64 output rows,
+//                    on the matrix cores; each wavefront also forms
+//                    V_rows^H (X T)_rows for its rows
+//   wfactor_kernel   W = X T - 1/2 V Y, Y = T^H sum over row blocks of those
 //   band_update_kernel  A22 <- Q^H A22 Q = A22 - V W^H - W V^H (lower triangle)
 // Per panel the trailing matrix is read about three times, instead of once
 // per column as in a one-stage reduction.
@@ -131,6 +133,36 @@ __device__ __forceinline__ void cmma(cpx<T> a, cpx<T> b, typename Mfma<T>::v4 &d
     dim = Mfma<T>::mma(a.im, b.re, dim);
 }
 
+// V T (rows s..n-1, T upper triangular in LDS) into the W slot, where the
+// Hermitian product takes it as its operand (the W factor overwrites it).
+template <typename T>
+__device__ __forceinline__ void vt_row(const cpx<T> (&v)[kB], const cpx<T> (&Ts)[kB][kB], cpx<T> (&out)[kB]) {
+#pragma unroll
+    for (int l = 0; l < kB; ++l) {
+        cpx<T> sum = {T(0), T(0)};
+#pragma unroll
+        for (int q = 0; q <= l; ++q) sum = c_add(sum, c_mul(v[q], Ts[q][l]));
+        out[l] = sum;
+    }
+}
+template <typename T>
+__device__ __noinline__ void store_vt(const TwoView<T> &w, int64_t ld, int s, int n, int t, int nt,
+                                      const cpx<T> (&Ts)[kB][kB]) {
+#pragma unroll 1
+    for (int r = s + t; r < n; r += nt) {
+        cpx<T> v[kB];
+#pragma unroll
+        for (int q = 0; q < kB; ++q) v[q] = w.V[(int64_t)q * ld + r];
+#pragma unroll
+        for (int l = 0; l < kB; ++l) {
+            cpx<T> sum = {T(0), T(0)};
+#pragma unroll
+            for (int q = 0; q <= l; ++q) sum = c_add(sum, c_mul(v[q], Ts[q][l]));
+            w.W[(int64_t)l * ld + r] = sum;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Stage 1: panel QR.  One workgroup per matrix.
 // ---------------------------------------------------------------------------
@@ -222,6 +254,7 @@ __global__ __launch_bounds__(kQrThreads) void qr_panel_kernel(cpx<T> *__restrict
         __syncthreads();
     }
     for (int idx = t; idx < kB * kB; idx += kQrThreads) w.Tm[idx] = Ts[idx / kB][idx % kB];
+    store_vt<T>(w, ld, s, n, t, kQrThreads, Ts);
 }
 
 // ---------------------------------------------------------------------------
@@ -340,14 +373,19 @@ __global__ __launch_bounds__(NT) void qr_panel_reg_kernel(cpx<T> *__restrict__ H
     qr_reflect_all<T, NT>(sh, P, s, n, nr, std::make_integer_sequence<int, kB>{});
     __syncthreads();
     if (own) {
+        cpx<T> v[kB], vt[kB];
 #pragma unroll
         for (int c = 0; c < kB; ++c) {
             const int r0c = s + c;
             const bool refl = c < nr;
             const cpx<T> al = {sh.alphas[c].re, sh.alphas[c].im};
-            w.V[c * ldi + r] = csel(refl && r >= r0c, P[c], zero);
+            v[c] = csel(refl && r >= r0c, P[c], zero);
+            w.V[c * ldi + r] = v[c];
             A[r + (p + c) * ldi] = csel(!refl || r < r0c, P[c], csel(r == r0c, al, zero));
         }
+        vt_row<T>(v, sh.Ts, vt);
+#pragma unroll
+        for (int l = 0; l < kB; ++l) w.W[l * ldi + r] = vt[l];
     }
     for (int idx = t; idx < kB * kB; idx += NT) w.Tm[idx] = sh.Ts[idx / kB][idx % kB];
 }
@@ -382,13 +420,17 @@ __device__ __forceinline__ void hemm_fix(int n, int rb, int c0, cpx<T> (&a)[4], 
     }
 }
 
-// X = A22 V on the matrix cores: one wavefront per 64 output rows (four
-// 16-row tiles) x 16 reflectors; each step consumes 4 columns of A22.
+// X T = A22 (V T) on the matrix cores: one wavefront per 64 output rows
+// (four 16-row tiles) x 16 columns; each step consumes 4 columns of A22.
+// Then Z_b = V_rows^H (X T)_rows for the wavefront's row block b, on the
+// matrix cores as well (the accumulators are already laid out as the B
+// operand of a 4-row step), into Zall[b][16][16] for the W factor.
 template <typename T>
 __global__ __launch_bounds__(64) void hemm_kernel(const cpx<T> *__restrict__ Hall, int64_t ld,
-                                                  const int32_t *__restrict__ n_in, const cpx<T> *__restrict__ Vall,
-                                                  cpx<T> *__restrict__ Xall, int64_t stride, int p,
-                                                  int64_t batch, int64_t tiles) {
+                                                  const int32_t *__restrict__ n_in, const cpx<T> *__restrict__ VTall,
+                                                  const cpx<T> *__restrict__ Vall, cpx<T> *__restrict__ Xall,
+                                                  cpx<T> *__restrict__ Zall, int64_t stride, int p, int64_t batch,
+                                                  int64_t tiles) {
     using v4 = typename Mfma<T>::v4;
     int64_t u, tile;
     xcd_tile(blockIdx.x, tiles, u, tile);
@@ -400,7 +442,7 @@ __global__ __launch_bounds__(64) void hemm_kernel(const cpx<T> *__restrict__ Hal
     if (rb >= n) return;
     const int lane = threadIdx.x, ii = lane & 15, kk = lane >> 4;
     const cpx<T> *A = Hall + u * ld * ld;
-    const cpx<T> *V = Vall + u * stride;
+    const cpx<T> *V = VTall + u * stride;
     const cpx<T> zero = {T(0), T(0)};
     v4 dre[4], dim[4];
 #pragma unroll
@@ -418,6 +460,17 @@ __global__ __launch_bounds__(64) void hemm_kernel(const cpx<T> *__restrict__ Hal
     // down to their use).
     cpx<T> a0[4], a1[4], b0, b1;
     const int ldi = (int)ld;
+    // The V rows of the block product below, loaded first so that they arrive
+    // during the main loop.
+    const cpx<T> *Vo = Vall + u * stride;
+    cpx<T> vz[4][4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = rb + 16 * t + Mfma<T>::row(lane, v);
+            vz[t][v] = Vo[r < n ? ii * ldi + r : 0];
+        }
     hemm_fetch(A, V, ldi, n, rb, s, a0, b0);
     for (int c0 = s; c0 < n; c0 += 8) {
         hemm_fetch(A, V, ldi, n, rb, c0 + 4, a1, b1);
@@ -439,83 +492,61 @@ __global__ __launch_bounds__(64) void hemm_kernel(const cpx<T> *__restrict__ Hal
             const int r = rb + 16 * t + Mfma<T>::row(lane, v);
             if (r < n) X[(int64_t)ii * ld + r] = {dre[t][v], dim[t][v]};
         }
+    // Z_b[i][l] = sum_r conj(V[r][i]) (X T)[r][l]: step (t, v) takes the rows
+    // rb + 16 t + row(lane, v), lane supplying A[ii][kk] = conj(V[r][ii]) and
+    // B[kk][ii] = (X T)[r][ii] (its own accumulator entry).
+    v4 zre = v4{T(0), T(0), T(0), T(0)}, zim = v4{T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = rb + 16 * t + Mfma<T>::row(lane, v);
+            const cpx<T> vr = vz[t][v];
+            const cpx<T> a = {r < n ? vr.re : T(0), r < n ? -vr.im : T(0)};
+            cmma<T>(a, cpx<T>{dre[t][v], dim[t][v]}, zre, zim);
+        }
+    cpx<T> *Z = Zall + u * stride + (int64_t)tile * kB * kB;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Z[Mfma<T>::row(lane, v) * kB + ii] = {zre[v], zim[v]};
 }
 
 // ---------------------------------------------------------------------------
-// Stage 1: W = X T - 1/2 V Y, Y = T^H (V^H X T).  One workgroup per matrix.
+// Stage 1: W = X T - 1/2 V Y, Y = T^H Z, Z = sum over the Hermitian product's
+// row blocks of V_rows^H (X T)_rows.  One workgroup per matrix.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kWThreads) void wfactor_kernel(const int32_t *__restrict__ n_in, int64_t ld,
                                                             cpx<T> *__restrict__ wall, int64_t stride, int p) {
-    __shared__ cpx<T> Ts[kB][kB];
-    constexpr int kZGroups = 8;
-    __shared__ cpx<T> Zp[kZGroups][kB][kB];  // [row group][k][l]
-    __shared__ cpx<T> Y[kB][kB];
+    __shared__ cpx<T> Ts[kB][kB], Zs[kB][kB], Y[kB][kB];
+    static_assert(kWThreads == kB * kB, "one thread per entry of the 16 x 16 factors");
     const int64_t u = blockIdx.x;
     const int n = n_in[u];
     const int s = p + kB, m = n - s;
     if (n < 0 || n > ld || m < 2) return;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, k = t / kB, l = t % kB;
     const TwoView<T> w(wall, stride, ld, u);
-    for (int idx = t; idx < kB * kB; idx += kWThreads) Ts[idx / kB][idx % kB] = w.Tm[idx];
+    const cpx<T> *Zp = hemm_partials(w, ld);
+    const int blocks = (m + kHemmRows - 1) / kHemmRows;
+    Ts[k][l] = w.Tm[t];
+    cpx<T> z = {T(0), T(0)};
+    for (int b = 0; b < blocks; ++b) z = c_add(z, Zp[(int64_t)b * kB * kB + t]);
+    Zs[k][l] = z;
     __syncthreads();
-    // X <- X T (per row)
-#pragma unroll 1
-    for (int r = s + t; r < n; r += kWThreads) {
-        cpx<T> x[kB];
-#pragma unroll
-        for (int q = 0; q < kB; ++q) x[q] = w.X[(int64_t)q * ld + r];
-        // `zr` is 0 but depends on r, so the 16 x 16 table stays in LDS instead
-        // of being hoisted out of the row loop into (spilled) registers.
-        const int zr = r >> 30;
-        for (int l = 0; l < kB; ++l) {  // T is upper triangular: column l uses rows q <= l
-            cpx<T> sum = {T(0), T(0)};
-#pragma unroll
-            for (int q = 0; q < kB; ++q)
-                if (q <= l) sum = c_add(sum, c_mul(x[q], Ts[q + zr][l]));
-            w.X[(int64_t)l * ld + r] = sum;
-        }
-    }
-    __syncthreads();
-    // Z = V^H (X T): thread (row group g, k) accumulates Z[k][:] over rows r = s + g, s + g + G, ...
-    if (t < kZGroups * kB) {
-        const int k = t % kB, g = t / kB;
-        constexpr int G = kZGroups;
-        cpx<T> z[kB];
-#pragma unroll
-        for (int l = 0; l < kB; ++l) z[l] = {T(0), T(0)};
-#pragma unroll 1
-        for (int r = s + g; r < n; r += G) {
-            const cpx<T> vk = w.V[(int64_t)k * ld + r];
-#pragma unroll
-            for (int l = 0; l < kB; ++l) z[l] = c_add(z[l], c_cmul(vk, w.X[(int64_t)l * ld + r]));
-        }
-#pragma unroll
-        for (int l = 0; l < kB; ++l) Zp[g][k][l] = z[l];
-    }
-    __syncthreads();
-    {
-        const int k = t / kB, l = t % kB;  // Y = T^H Z, T upper triangular
-        cpx<T> y = {T(0), T(0)};
-        for (int q = 0; q <= k; ++q) {
-            cpx<T> zql = {T(0), T(0)};
-            for (int g = 0; g < kZGroups; ++g) zql = c_add(zql, Zp[g][q][l]);
-            y = c_add(y, c_cmul(Ts[q][k], zql));
-        }
-        Y[k][l] = y;
-    }
+    cpx<T> y = {T(0), T(0)};  // Y = T^H Z, T upper triangular
+    for (int q = 0; q <= k; ++q) y = c_add(y, c_cmul(Ts[q][k], Zs[q][l]));
+    Y[k][l] = y;
     __syncthreads();
 #pragma unroll 1
     for (int r = s + t; r < n; r += kWThreads) {
         cpx<T> v[kB];
 #pragma unroll
-        for (int k = 0; k < kB; ++k) v[k] = w.V[(int64_t)k * ld + r];
-        const int zr = r >> 30;  // see above
-        for (int l = 0; l < kB; ++l) {
+        for (int q = 0; q < kB; ++q) v[q] = w.V[(int64_t)q * ld + r];
+        const int zr = r >> 30;  // 0, but keeps the 16 x 16 table in LDS rather than in (spilled) registers
+        for (int c = 0; c < kB; ++c) {
             cpx<T> sum = {T(0), T(0)};
 #pragma unroll
-            for (int k = 0; k < kB; ++k) sum = c_add(sum, c_mul(v[k], Y[k + zr][l]));
-            w.W[(int64_t)l * ld + r] = c_sub(w.X[(int64_t)l * ld + r], c_scale(T(0.5), sum));
+            for (int q = 0; q < kB; ++q) sum = c_add(sum, c_mul(v[q], Y[q + zr][c]));
+            w.W[(int64_t)c * ld + r] = c_sub(w.X[(int64_t)c * ld + r], c_scale(T(0.5), sum));
         }
     }
 }
@@ -638,8 +669,9 @@ hipError_t launch_band_reduce(cpx<T> *H, int64_t ld, const int32_t *n_in, int64_
         else
             hipLaunchKernelGGL(qr_panel_kernel<T>, dim3(B), dim3(kQrThreads), 0, s, H, ld, n_in, work, stride, p);
         const int64_t hrows = (mmax + kHemmRows - 1) / kHemmRows;
-        hipLaunchKernelGGL(hemm_kernel<T>, dim3(xcd_grid(batch, hrows)), dim3(64), 0, s, H, ld, n_in, work,
-                           work + (int64_t)kB * ld, stride, p, batch, hrows);
+        hipLaunchKernelGGL(hemm_kernel<T>, dim3(xcd_grid(batch, hrows)), dim3(64), 0, s, H, ld, n_in,
+                           work + 2 * (int64_t)kB * ld, work, work + (int64_t)kB * ld,
+                           work + 3 * (int64_t)kB * ld + kB * kB, stride, p, batch, hrows);
         hipLaunchKernelGGL(wfactor_kernel<T>, dim3(B), dim3(kWThreads), 0, s, n_in, ld, work, stride, p);
         const int64_t nblk = (mmax + kUpdBlk - 1) / kUpdBlk, ntile = nblk * (nblk + 1) / 2;
         hipLaunchKernelGGL(band_update_kernel<T>, dim3(xcd_grid(batch, ntile)), dim3(256), 0, s, H, ld, n_in, work,

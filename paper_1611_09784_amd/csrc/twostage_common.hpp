@@ -16,7 +16,9 @@ constexpr int kBandLd = 2 * kB + 1;    // stored sub-diagonals per column (incl.
 // Per-matrix workspace (complex elements): V [kB][ld], X [kB][ld], W [kB][ld],
 // T [kB][kB], band [ld + 1][kBandLd].  The band's last column is a discard
 // slot: lanes with nothing to store write there, so that every store of a
-// block is issued unconditionally.
+// block is issued unconditionally.  During stage 1 the band area holds the
+// Hermitian product's per-row-block partial products [ceil(ld / 64)][kB][kB]
+// (the chase fills it only afterwards).
 template <typename T>
 size_t tridiag_twostage_work_elems(int64_t ld) {
     return (size_t)(3 * kB) * (size_t)ld + (size_t)kB * kB + (size_t)kBandLd * (size_t)(ld + 1);
@@ -34,6 +36,11 @@ struct TwoView {
         band = Tm + kB * kB;
     }
 };
+
+template <typename T>
+__device__ __forceinline__ cpx<T> *hemm_partials(const TwoView<T> &w, int64_t) {
+    return w.band;
+}
 
 // Componentwise select (a select of whole structs can become a select of
 // their addresses, which forces register arrays into scratch memory).
