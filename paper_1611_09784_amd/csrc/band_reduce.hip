@@ -629,12 +629,19 @@ __global__ __launch_bounds__(256) void band_update_kernel(cpx<T> *__restrict__ H
         dre[tt] = v4{T(0), T(0), T(0), T(0)};
         dim[tt] = v4{T(0), T(0), T(0), T(0)};
     }
+    // In a diagonal tile, row blocks above this wavefront's 16 columns lie in
+    // the upper triangle (never stored): in FP64 their products are skipped
+    // (in FP32 the branches cost the kernel a wavefront per SIMD, more than
+    // the skipped products save).
+    constexpr bool kSkipUpper = sizeof(T) == 8;
+    const int tt0 = (kSkipUpper && rb == cb) ? __builtin_amdgcn_readfirstlane(wid) : 0;
 #pragma unroll 2
     for (int k0 = 0; k0 < 2 * kB; k0 += 4) {
         const int k = k0 + kk;
         const cpx<T> a = c_conj((k < kB) ? sWc[k][wid * 16 + ii] : sVc[k - kB][wid * 16 + ii]);
 #pragma unroll
         for (int tt = 0; tt < 4; ++tt) {
+            if (tt < tt0) continue;
             const cpx<T> b = (k < kB) ? sVr[k][16 * tt + ii] : sWr[k - kB][16 * tt + ii];
             cmma<T>(a, b, dre[tt], dim[tt]);
         }
