@@ -201,10 +201,16 @@ __device__ __forceinline__ int sturm_count(const double *d, const double *e2, in
     return c;
 }
 
+// Absolute width at which an eigenvalue's bracket is final (eV): far below
+// what the smoothed IDoS resolves (a shift dE of one eigenvalue moves I by at
+// most dE g'_max / (delta N^2 |F|)).
+constexpr double kBisectAbsTol = 1e-12;
+
 // All eigenvalues of (d, e) by bisection on Sturm counts, in double
 // precision.  The Gershgorin interval is first cut at blockDim.x points
 // (one count per thread); each eigenvalue index i then bisects its own
-// sub-interval until its width reaches a few ulps of the spectral radius.
+// sub-interval until its width reaches kBisectAbsTol (or a few ulps of the
+// spectral radius, if that is larger).
 // e is squared in place.  w[i] = i-th smallest eigenvalue.
 // cnt holds blockDim.x + 1 ints of LDS.
 __device__ inline void bisect_block(const double *d, double *e, int n, double *w, double *red, int *cnt) {
@@ -226,7 +232,7 @@ __device__ inline void bisect_block(const double *d, double *e, int n, double *w
     const double margin = 2.0 * DBL_EPSILON * bnorm * (double)n + 2.0 * pivmin;
     gl -= margin;
     gu += margin;
-    const double atol = 2.0 * DBL_EPSILON * bnorm;
+    const double atol = fmax(kBisectAbsTol, 2.0 * DBL_EPSILON * bnorm);
     __syncthreads();
     const double step = (gu - gl) / nt;
     cnt[t + 1] = (t + 1 == nt) ? n : sturm_count(d, e, n, gl + step * (t + 1), pivmin);
