@@ -133,6 +133,26 @@ __device__ __forceinline__ void cmma(cpx<T> a, cpx<T> b, typename Mfma<T>::v4 &d
     dim = Mfma<T>::mma(a.im, b.re, dim);
 }
 
+// Complex accumulate with three real products per complex one (Gauss's
+// form): P += Re a Re b, Q += Im a Im b, R += (Re a + Im a)(Re b + Im b), so
+// that the complex sum is (P - Q) + i (R - P - Q).  as, bs: Re + Im of a, b.
+// The error of the imaginary part stays within a small multiple of the
+// product of the operands' norms, as for the four-product form.
+template <typename T>
+struct CAcc3 {
+    typename Mfma<T>::v4 p, q, r;
+    __device__ __forceinline__ void zero() {
+        p = q = r = typename Mfma<T>::v4{T(0), T(0), T(0), T(0)};
+    }
+    __device__ __forceinline__ void mma(cpx<T> a, T as, cpx<T> b, T bs) {
+        p = Mfma<T>::mma(a.re, b.re, p);
+        q = Mfma<T>::mma(a.im, b.im, q);
+        r = Mfma<T>::mma(as, bs, r);
+    }
+    __device__ __forceinline__ typename Mfma<T>::v4 re() const { return p - q; }
+    __device__ __forceinline__ typename Mfma<T>::v4 im() const { return r - p - q; }
+};
+
 // V T (rows s..n-1, T upper triangular in LDS) into the W slot, where the
 // Hermitian product takes it as its operand (the W factor overwrites it).
 template <typename T>
@@ -426,7 +446,7 @@ __device__ __forceinline__ void hemm_fix(int n, int rb, int c0, cpx<T> (&a)[4], 
 // matrix cores as well (the accumulators are already laid out as the B
 // operand of a 4-row step), into Zall[b][16][16] for the W factor.
 template <typename T>
-__global__ __launch_bounds__(64) void hemm_kernel(const cpx<T> *__restrict__ Hall, int64_t ld,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void hemm_kernel(const cpx<T> *__restrict__ Hall, int64_t ld,
                                                   const int32_t *__restrict__ n_in, const cpx<T> *__restrict__ VTall,
                                                   const cpx<T> *__restrict__ Vall, cpx<T> *__restrict__ Xall,
                                                   cpx<T> *__restrict__ Zall, int64_t stride, int p, int64_t batch,
@@ -444,12 +464,9 @@ __global__ __launch_bounds__(64) void hemm_kernel(const cpx<T> *__restrict__ Hal
     const cpx<T> *A = Hall + u * ld * ld;
     const cpx<T> *V = VTall + u * stride;
     const cpx<T> zero = {T(0), T(0)};
-    v4 dre[4], dim[4];
+    CAcc3<T> acc[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        dre[t] = v4{T(0), T(0), T(0), T(0)};
-        dim[t] = v4{T(0), T(0), T(0), T(0)};
-    }
+    for (int t = 0; t < 4; ++t) acc[t].zero();
     // Raw loads (every lane loads from a valid address: the stored lower
     // element of its position, element 0 when outside the matrix) are issued
     // one step ahead; the fix-up (mask, conjugation of mirrored elements,
@@ -477,12 +494,18 @@ __global__ __launch_bounds__(64) void hemm_kernel(const cpx<T> *__restrict__ Hal
         asm volatile("" ::: "memory");
         hemm_fix(n, rb, c0, a0, b0);
 #pragma unroll
-        for (int t = 0; t < 4; ++t) cmma<T>(a0[t], b0, dre[t], dim[t]);
+        for (int t = 0; t < 4; ++t) acc[t].mma(a0[t], a0[t].re + a0[t].im, b0, b0.re + b0.im);
         hemm_fetch(A, V, ldi, n, rb, c0 + 8, a0, b0);
         asm volatile("" ::: "memory");
         hemm_fix(n, rb, c0 + 4, a1, b1);
 #pragma unroll
-        for (int t = 0; t < 4; ++t) cmma<T>(a1[t], b1, dre[t], dim[t]);
+        for (int t = 0; t < 4; ++t) acc[t].mma(a1[t], a1[t].re + a1[t].im, b1, b1.re + b1.im);
+    }
+    v4 dre[4], dim[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        dre[t] = acc[t].re();
+        dim[t] = acc[t].im();
     }
     cpx<T> *X = Xall + u * stride;
 #pragma unroll
@@ -557,7 +580,7 @@ __global__ __launch_bounds__(kWThreads) void wfactor_kernel(const int32_t *__res
 // accumulates a 4 x 4 micro-tile.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void band_update_kernel(cpx<T> *__restrict__ Hall, int64_t ld,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void band_update_kernel(cpx<T> *__restrict__ Hall, int64_t ld,
                                                           const int32_t *__restrict__ n_in, cpx<T> *__restrict__ wall,
                                                           int64_t stride, int p, int64_t batch, int64_t tiles,
                                                           int min_m) {
@@ -622,13 +645,9 @@ __global__ __launch_bounds__(256) void band_update_kernel(cpx<T> *__restrict__ H
     // (k < 2 kB).  The matrix cores compute the transposed tile
     // D[c][r] = sum_k conj(Q[c, k]) P[r, k] so that the lane-fast index of the
     // result is the row r of A (coalesced column-major read-modify-write).
-    using v4 = typename Mfma<T>::v4;
-    v4 dre[4], dim[4];
+    CAcc3<T> acc[4];
 #pragma unroll
-    for (int tt = 0; tt < 4; ++tt) {
-        dre[tt] = v4{T(0), T(0), T(0), T(0)};
-        dim[tt] = v4{T(0), T(0), T(0), T(0)};
-    }
+    for (int tt = 0; tt < 4; ++tt) acc[tt].zero();
     // In a diagonal tile, row blocks above this wavefront's 16 columns lie in
     // the upper triangle (never stored): in FP64 their products are skipped
     // (in FP32 the branches cost the kernel a wavefront per SIMD, more than
@@ -639,20 +658,22 @@ __global__ __launch_bounds__(256) void band_update_kernel(cpx<T> *__restrict__ H
     for (int k0 = 0; k0 < 2 * kB; k0 += 4) {
         const int k = k0 + kk;
         const cpx<T> a = c_conj((k < kB) ? sWc[k][wid * 16 + ii] : sVc[k - kB][wid * 16 + ii]);
+        const T as = a.re + a.im;
 #pragma unroll
         for (int tt = 0; tt < 4; ++tt) {
             if (tt < tt0) continue;
             const cpx<T> b = (k < kB) ? sVr[k][16 * tt + ii] : sWr[k - kB][16 * tt + ii];
-            cmma<T>(a, b, dre[tt], dim[tt]);
+            acc[tt].mma(a, as, b, b.re + b.im);
         }
     }
 #pragma unroll
     for (int tt = 0; tt < 4; ++tt) {
         const int r = rb + 16 * tt + ii;
+        const typename Mfma<T>::v4 dre = acc[tt].re(), dim = acc[tt].im();
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int c = cs + Mfma<T>::row(lane, v);
-            if (r < n && c < n && r >= c) A[r + c * ldi] = c_sub(x[tt][v], cpx<T>{dre[tt][v], dim[tt][v]});
+            if (r < n && c < n && r >= c) A[r + c * ldi] = c_sub(x[tt][v], cpx<T>{dre[v], dim[v]});
         }
     }
 }
