@@ -21,6 +21,7 @@ namespace mlmc {
 
 constexpr int kQrThreads = 256;
 constexpr int kHemmRows = 64;
+constexpr int kHemmDepth = 2;  // Hermitian product: register sets of its load pipeline
 constexpr int kWThreads = 256;
 constexpr int kUpdBlk = 64;
 
@@ -401,7 +402,10 @@ __global__ __launch_bounds__(NT) void qr_panel_reg_kernel(cpx<T> *__restrict__ H
             const cpx<T> al = {sh.alphas[c].re, sh.alphas[c].im};
             v[c] = csel(refl && r >= r0c, P[c], zero);
             w.V[c * ldi + r] = v[c];
-            A[r + (p + c) * ldi] = csel(!refl || r < r0c, P[c], csel(r == r0c, al, zero));
+            // Rows s .. s + c of column p + c are the band's (R above the
+            // pivot, alpha at it); the zeros below lie outside the band and
+            // are never read again.
+            if (t <= c) A[r + (p + c) * ldi] = csel(!refl || r < r0c, P[c], csel(r == r0c, al, zero));
         }
         vt_row<T>(v, sh.Ts, vt);
 #pragma unroll
@@ -440,46 +444,15 @@ __device__ __forceinline__ void hemm_fix(int n, int rb, int c0, cpx<T> (&a)[4], 
     }
 }
 
-// X T = A22 (V T) on the matrix cores: one wavefront per 64 output rows
-// (four 16-row tiles) x 16 columns; each step consumes 4 columns of A22.
-// Then Z_b = V_rows^H (X T)_rows for the wavefront's row block b, on the
-// matrix cores as well (the accumulators are already laid out as the B
-// operand of a 4-row step), into Zall[b][16][16] for the W factor.
-template <typename T>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void hemm_kernel(const cpx<T> *__restrict__ Hall, int64_t ld,
-                                                  const int32_t *__restrict__ n_in, const cpx<T> *__restrict__ VTall,
-                                                  const cpx<T> *__restrict__ Vall, cpx<T> *__restrict__ Xall,
-                                                  cpx<T> *__restrict__ Zall, int64_t stride, int p, int64_t batch,
-                                                  int64_t tiles) {
+// After the Hermitian product of a wavefront's 64-row block (rows rb ..):
+// its rows of X T, and Z_b = V_rows^H (X T)_rows for the block b, on the
+// matrix cores (the accumulators are already laid out as the B operand of a
+// 4-row step), into Zall[b][16][16] for the W factor.
+template <typename T, typename Acc>
+__device__ __forceinline__ void hemm_finish(const Acc (&acc)[4], const cpx<T> *Vo, cpx<T> *X, cpx<T> *Z,
+                                            int ldi, int n, int rb) {
     using v4 = typename Mfma<T>::v4;
-    int64_t u, tile;
-    xcd_tile(blockIdx.x, tiles, u, tile);
-    if (u >= batch) return;
-    const int n = n_in[u];
-    const int s = p + kB, m = n - s;
-    if (n < 0 || n > ld || m < 2) return;
-    const int rb = s + (int)tile * kHemmRows;
-    if (rb >= n) return;
-    const int lane = threadIdx.x, ii = lane & 15, kk = lane >> 4;
-    const cpx<T> *A = Hall + u * ld * ld;
-    const cpx<T> *V = VTall + u * stride;
-    const cpx<T> zero = {T(0), T(0)};
-    CAcc3<T> acc[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t].zero();
-    // Raw loads (every lane loads from a valid address: the stored lower
-    // element of its position, element 0 when outside the matrix) are issued
-    // one step ahead; the fix-up (mask, conjugation of mirrored elements,
-    // real diagonal) happens at use, so no load is waited for early.
-    // Two register sets in ping-pong.  The empty asm with a memory clobber
-    // after each prefetch keeps the compiler from turning the loop-carried
-    // loaded values into loop-carried addresses (which would move the loads
-    // down to their use).
-    cpx<T> a0[4], a1[4], b0, b1;
-    const int ldi = (int)ld;
-    // The V rows of the block product below, loaded first so that they arrive
-    // during the main loop.
-    const cpx<T> *Vo = Vall + u * stride;
+    const int lane = (int)threadIdx.x & 63, ii = lane & 15;
     cpx<T> vz[4][4];
 #pragma unroll
     for (int t = 0; t < 4; ++t)
@@ -488,32 +461,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void he
             const int r = rb + 16 * t + Mfma<T>::row(lane, v);
             vz[t][v] = Vo[r < n ? ii * ldi + r : 0];
         }
-    hemm_fetch(A, V, ldi, n, rb, s, a0, b0);
-    for (int c0 = s; c0 < n; c0 += 8) {
-        hemm_fetch(A, V, ldi, n, rb, c0 + 4, a1, b1);
-        asm volatile("" ::: "memory");
-        hemm_fix(n, rb, c0, a0, b0);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) acc[t].mma(a0[t], a0[t].re + a0[t].im, b0, b0.re + b0.im);
-        hemm_fetch(A, V, ldi, n, rb, c0 + 8, a0, b0);
-        asm volatile("" ::: "memory");
-        hemm_fix(n, rb, c0 + 4, a1, b1);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) acc[t].mma(a1[t], a1[t].re + a1[t].im, b1, b1.re + b1.im);
-    }
     v4 dre[4], dim[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         dre[t] = acc[t].re();
         dim[t] = acc[t].im();
     }
-    cpx<T> *X = Xall + u * stride;
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int r = rb + 16 * t + Mfma<T>::row(lane, v);
-            if (r < n) X[(int64_t)ii * ld + r] = {dre[t][v], dim[t][v]};
+            if (r < n) X[ii * ldi + r] = {dre[t][v], dim[t][v]};
         }
     // Z_b[i][l] = sum_r conj(V[r][i]) (X T)[r][l]: step (t, v) takes the rows
     // rb + 16 t + row(lane, v), lane supplying A[ii][kk] = conj(V[r][ii]) and
@@ -528,9 +487,71 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void he
             const cpx<T> a = {r < n ? vr.re : T(0), r < n ? -vr.im : T(0)};
             cmma<T>(a, cpx<T>{dre[t][v], dim[t][v]}, zre, zim);
         }
-    cpx<T> *Z = Zall + u * stride + (int64_t)tile * kB * kB;
 #pragma unroll
     for (int v = 0; v < 4; ++v) Z[Mfma<T>::row(lane, v) * kB + ii] = {zre[v], zim[v]};
+}
+
+// X T = A22 (V T) on the matrix cores: one wavefront per 64 output rows
+// (four 16-row tiles) x 16 columns; each step consumes 4 columns of A22.
+template <typename T>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void hemm_kernel(
+    const cpx<T> *__restrict__ Hall, int64_t ld, const int32_t *__restrict__ n_in, const cpx<T> *__restrict__ VTall,
+    const cpx<T> *__restrict__ Vall, cpx<T> *__restrict__ Xall, cpx<T> *__restrict__ Zall, int64_t stride, int p,
+    int64_t batch, int64_t tiles) {
+    int64_t u, tile;
+    xcd_tile(blockIdx.x, tiles, u, tile);
+    if (u >= batch) return;
+    const int n = n_in[u];
+    const int s = p + kB, m = n - s;
+    if (n < 0 || n > ld || m < 2) return;
+    const int rb = s + (int)tile * kHemmRows;
+    if (rb >= n) return;
+    const cpx<T> *A = Hall + u * ld * ld;
+    const cpx<T> *V = VTall + u * stride;
+    CAcc3<T> acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t].zero();
+    // Raw loads (every lane loads from a valid address: the stored lower
+    // element of its position, element 0 when outside the matrix) are issued
+    // kHemmDepth - 1 steps ahead into a ring of register sets; the fix-up
+    // (mask, conjugation of mirrored elements, real diagonal) happens at
+    // use, so no load is waited for early.  The empty asm with a memory
+    // clobber after each prefetch keeps the compiler from turning the
+    // loop-carried loaded values into loop-carried addresses (which would
+    // move the loads down to their use).
+    //
+    // Column order: the wavefront of row block I starts at column offset
+    // -64 I (mod m, in steps of 4 columns) and wraps around, so that the
+    // wavefronts of a matrix do not all stream the same columns at the same
+    // time (about 9 % faster than all starting at column s).  Steps past
+    // the last one (the step count is padded to a multiple of kHemmDepth)
+    // read column n, which is masked to zero.
+    constexpr int D = kHemmDepth;
+    cpx<T> a[D][4], b[D];
+    int cs[D];
+    const int ldi = (int)ld;
+    const int m4 = (m + 3) & ~3, nst = m4 / 4;
+    int of = (m4 - (kHemmRows * (int)tile) % m4) % m4, fetched = 0;
+    auto fetch_next = [&](int slot) {
+        cs[slot] = fetched < nst ? s + of : n;
+        hemm_fetch(A, V, ldi, n, rb, cs[slot], a[slot], b[slot]);
+        of = of + 4 >= m4 ? 0 : of + 4;
+        ++fetched;
+    };
+#pragma unroll
+    for (int i = 0; i < D - 1; ++i) fetch_next(i);
+    for (int q = 0; q < nst; q += D) {
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            fetch_next((i + D - 1) % D);
+            asm volatile("" ::: "memory");
+            hemm_fix(n, rb, cs[i], a[i], b[i]);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc[t].mma(a[i][t], a[i][t].re + a[i][t].im, b[i], b[i].re + b[i].im);
+        }
+    }
+    hemm_finish<T>(acc, Vall + u * stride, Xall + u * stride, Zall + u * stride + (int64_t)tile * kB * kB, ldi, n,
+                   rb);
 }
 
 // ---------------------------------------------------------------------------
