@@ -260,13 +260,14 @@ mlmc_status outcome_spectra(const mlmc_lattice_s *lat, int N, const uint8_t *mas
     const int64_t ld = (int64_t)lat->dev.n_orb * N * N;
     const int64_t units = ns * nk;
     if (bisect_pending) *bisect_pending = false;
+    // The eigensolvers read lower triangles only, so only those are assembled.
     if (lat->dev.n_ovl > 0) {  // non-orthogonal basis: assemble H and S, generalised path
         if (prec == MLMC_PREC_FP64) {
-            LAUNCH("assemble", s, launch_assemble<double>(lat->dev, N, mask, ns, kred, nk, static_cast<cpx<double> *>(b.H), ld, n_out, s));
-            LAUNCH("assemble", s, launch_assemble<double>(lat->dev, N, mask, ns, kred, nk, static_cast<cpx<double> *>(b.S), ld, n_out, s, true));
+            LAUNCH("assemble", s, launch_assemble<double>(lat->dev, N, mask, ns, kred, nk, static_cast<cpx<double> *>(b.H), ld, n_out, s, false, true));
+            LAUNCH("assemble", s, launch_assemble<double>(lat->dev, N, mask, ns, kred, nk, static_cast<cpx<double> *>(b.S), ld, n_out, s, true, true));
         } else {
-            LAUNCH("assemble", s, launch_assemble<float>(lat->dev, N, mask, ns, kred, nk, static_cast<cpx<float> *>(b.H), ld, n_out, s));
-            LAUNCH("assemble", s, launch_assemble<float>(lat->dev, N, mask, ns, kred, nk, static_cast<cpx<float> *>(b.S), ld, n_out, s, true));
+            LAUNCH("assemble", s, launch_assemble<float>(lat->dev, N, mask, ns, kred, nk, static_cast<cpx<float> *>(b.H), ld, n_out, s, false, true));
+            LAUNCH("assemble", s, launch_assemble<float>(lat->dev, N, mask, ns, kred, nk, static_cast<cpx<float> *>(b.S), ld, n_out, s, true, true));
         }
         return run_generalized(prec, b.H, b.S, ld, n_out, units, w, ld, b, s, bisect_pending);
     }
@@ -278,9 +279,9 @@ mlmc_status outcome_spectra(const mlmc_lattice_s *lat, int N, const uint8_t *mas
         return MLMC_OK;
     }
     if (prec == MLMC_PREC_FP64)
-        LAUNCH("assemble", s, launch_assemble<double>(lat->dev, N, mask, ns, kred, nk, static_cast<cpx<double> *>(b.H), ld, n_out, s));
+        LAUNCH("assemble", s, launch_assemble<double>(lat->dev, N, mask, ns, kred, nk, static_cast<cpx<double> *>(b.H), ld, n_out, s, false, true));
     else
-        LAUNCH("assemble", s, launch_assemble<float>(lat->dev, N, mask, ns, kred, nk, static_cast<cpx<float> *>(b.H), ld, n_out, s));
+        LAUNCH("assemble", s, launch_assemble<float>(lat->dev, N, mask, ns, kred, nk, static_cast<cpx<float> *>(b.H), ld, n_out, s, false, true));
     if (bisect_pending) *bisect_pending = true;
     return run_large(prec, b.H, ld, n_out, units, w, ld, b, s, bisect_pending != nullptr);
 }

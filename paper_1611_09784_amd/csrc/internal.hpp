@@ -87,7 +87,8 @@ int kgrid_count(int kind, int K);
 
 template <typename T>
 hipError_t launch_assemble(const DevLattice &lat, int N, const uint8_t *masks, int64_t n_samples, const double *kred,
-                           int n_k, cpx<T> *H, int64_t ld, int32_t *n_out, hipStream_t s, bool overlap = false);
+                           int n_k, cpx<T> *H, int64_t ld, int32_t *n_out, hipStream_t s, bool overlap = false,
+                           bool lower = false);
 
 // Fused LDS kernel: (assemble or load) -> Householder -> bisection -> eigenvalues.
 template <typename T>
