@@ -254,12 +254,15 @@ mlmc_status mlmc_level_workspace(mlmc_lattice lat, int32_t N_fine, int32_t coupl
  * ([4][n_eps], accumulated; the caller initialises it).
  * Samples are processed in chunks that fit the workspace.  Each chunk's
  * bisection, IDoS and level sums run on a second stream owned by the library
- * (one per device, default priority, created on the first call and kept until
- * the process ends) while the caller's stream goes on with the next chunk;
- * the work is ordered by events, `stream` waits for the second stream before
- * the call returns, and the sums are added in sample order as on one stream.
- * Calls on one device enqueue one at a time (a process-wide lock) and share
- * that second stream, so their bisections run one after another.
+ * while the caller's stream goes on with the next chunk; in FP64 the
+ * two-stage path's band-to-tridiagonal chase runs on a third such stream, on
+ * the number of CUs mlmc_chase_cus reports, beside the next chunk's dense-to-
+ * band stage on the caller's stream (these streams: one pair per device,
+ * default priority, created on the first call and kept until the process
+ * ends).  The work is ordered by events, `stream` waits for the library's
+ * streams before the call returns, and the sums are added in sample order as
+ * on one stream.  Calls on one device enqueue one at a time (a process-wide
+ * lock) and share those streams, so their bisections run one after another.
  * Errors: N_fine < 1, coupled with odd N_fine, K < 1, p outside [0, 1],
  * delta <= 0, workspace too small for one sample. */
 mlmc_status mlmc_level_estimate(mlmc_lattice lat, int32_t N_fine, int32_t coupled, double p, int32_t K_fine,
@@ -267,6 +270,13 @@ mlmc_status mlmc_level_estimate(mlmc_lattice lat, int32_t N_fine, int32_t couple
                                 int64_t M, const double *d_eps, int32_t n_eps, double delta, mlmc_smoother smoother,
                                 mlmc_precision prec, double *d_stats, void *d_work, size_t work_bytes,
                                 mlmc_stream stream);
+
+/* Workgroups (one per CU) that mlmc_level_estimate's chase occupies on the
+ * current device with precision prec: 3/4 of the CUs in FP64 (the chase
+ * runs beside the next chunk's dense-to-band stage), all of them in mixed
+ * precision (where it runs on the caller's stream, one workgroup per matrix
+ * up to the CU count at a time).  Errors: no device, bad prec. */
+mlmc_status mlmc_chase_cus(mlmc_precision prec, int64_t *cus);
 
 /* Sample allocation of eq. (opt_samples) (host, no device work):
  *   M_l = (C_alpha / (theta tol))^2 sqrt(V_l / W_l) sum_k sqrt(W_k V_k)

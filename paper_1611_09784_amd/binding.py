@@ -85,6 +85,7 @@ SIGNATURES = {
                                       C.c_int, P, P, SZ, P]),
     "mlmc_optimal_samples": (C.c_int, [I32, P, P, DBL, DBL, DBL, P]),
     "mlmc_dos": (C.c_int, [I32, P, P, P]),
+    "mlmc_chase_cus": (C.c_int, [C.c_int, P]),
     "mlmc_timer_enable": (C.c_int, [I32]),
     "mlmc_timer_read": (C.c_int, [C.c_char_p, P, P]),
 }
@@ -417,6 +418,13 @@ def mlmc_dos(eps, idos) -> np.ndarray:
     out = np.zeros_like(idos)
     _check(lib().mlmc_dos(eps.shape[0], _ptr(eps), _ptr(idos), _ptr(out)), "mlmc_dos")
     return out
+
+
+def mlmc_chase_cus(prec) -> int:
+    """CUs (one chase workgroup each) that a level estimate's chase occupies on the current device."""
+    out = C.c_int64()
+    _check(lib().mlmc_chase_cus(prec, C.byref(out)), "mlmc_chase_cus")
+    return out.value
 
 
 def mlmc_timer_enable(enable: bool = True):

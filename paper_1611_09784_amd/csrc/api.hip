@@ -106,13 +106,18 @@ struct EigBuffers {
     void *H = nullptr;
     void *S = nullptr;  // overlap matrices (non-orthogonal basis only)
     double *d = nullptr, *e = nullptr;
-    double *d2 = nullptr, *e2 = nullptr;  // second tridiagonal set (pipelined level estimates)
+    // Second sets for pipelined level estimates: tridiagonal matrices, and on
+    // the two-stage path the matrices themselves (their chase runs beside the
+    // next chunk's stage 1).
+    void *H2 = nullptr;
+    double *d2 = nullptr, *e2 = nullptr;
     void *partial = nullptr;
 
-    // The view whose d, e are tridiagonal set `parity` (0 or 1).
+    // The view whose H (when it has two), d, e are set `parity` (0 or 1).
     EigBuffers set(int parity) const {
         EigBuffers v = *this;
         if (parity) {
+            if (H2) v.H = H2;
             v.d = d2;
             v.e = e2;
         }
@@ -132,6 +137,7 @@ void carve_tridiagonal(Carver &cv, int64_t ld, int64_t units, bool twin, EigBuff
 void carve_large(Carver &cv, mlmc_precision prec, int64_t ld, int64_t units, bool with_H, EigBuffers &b,
                  bool twin = false) {
     if (with_H) b.H = cv.take<void>(cplx_bytes(prec) * (size_t)ld * (size_t)ld * (size_t)units);
+    if (with_H && twin) b.H2 = cv.take<void>(cplx_bytes(prec) * (size_t)ld * (size_t)ld * (size_t)units);
     carve_tridiagonal(cv, ld, units, twin, b);
     const size_t pe = prec == MLMC_PREC_FP64 ? tridiag_twostage_work_elems<double>(ld)
                                              : tridiag_twostage_work_elems<float>(ld);
@@ -161,18 +167,32 @@ mlmc_status run_bisect(const int32_t *n, int64_t ld, int64_t units, double *w, i
     return MLMC_OK;
 }
 
+// Band -> tridiagonal (b.d, b.e) of matrices that stage 1 left in H, on at
+// most max_blocks workgroups (0: one per matrix).
+mlmc_status run_chase(mlmc_precision prec, const void *H, int64_t ld, const int32_t *n, int64_t units,
+                      const EigBuffers &b, hipStream_t s, int64_t max_blocks = 0) {
+    if (prec == MLMC_PREC_FP64)
+        LAUNCH("chase", s, launch_band_chase<double>(static_cast<const cpx<double> *>(H), ld, n, units, b.d, b.e, ld,
+                                                     static_cast<cpx<double> *>(b.partial), s, max_blocks));
+    else
+        LAUNCH("chase", s, launch_band_chase<float>(static_cast<const cpx<float> *>(H), ld, n, units, b.d, b.e, ld,
+                                                    static_cast<cpx<float> *>(b.partial), s, max_blocks));
+    return MLMC_OK;
+}
+
+// With defer_chase only stage 1 runs here (the caller runs run_chase and
+// run_bisect, possibly on other streams).
 mlmc_status run_large(mlmc_precision prec, void *H, int64_t ld, const int32_t *n, int64_t units, double *w, int64_t ldw,
-                      const EigBuffers &b, hipStream_t s, bool defer_bisect = false) {
-    if (prec == MLMC_PREC_FP64) {
-        cpx<double> *Hc = static_cast<cpx<double> *>(H), *wk = static_cast<cpx<double> *>(b.partial);
-        LAUNCH("band_reduce", s, launch_band_reduce<double>(Hc, ld, n, units, wk, s));
-        LAUNCH("chase", s, launch_band_chase<double>(Hc, ld, n, units, b.d, b.e, ld, wk, s));
-    } else {
-        cpx<float> *Hc = static_cast<cpx<float> *>(H), *wk = static_cast<cpx<float> *>(b.partial);
-        LAUNCH("band_reduce", s, launch_band_reduce<float>(Hc, ld, n, units, wk, s));
-        LAUNCH("chase", s, launch_band_chase<float>(Hc, ld, n, units, b.d, b.e, ld, wk, s));
-    }
-    if (defer_bisect) return MLMC_OK;
+                      const EigBuffers &b, hipStream_t s, bool defer_bisect = false, bool defer_chase = false) {
+    if (prec == MLMC_PREC_FP64)
+        LAUNCH("band_reduce", s, launch_band_reduce<double>(static_cast<cpx<double> *>(H), ld, n, units,
+                                                            static_cast<cpx<double> *>(b.partial), s));
+    else
+        LAUNCH("band_reduce", s, launch_band_reduce<float>(static_cast<cpx<float> *>(H), ld, n, units,
+                                                           static_cast<cpx<float> *>(b.partial), s));
+    if (defer_chase) return MLMC_OK;
+    const mlmc_status st = run_chase(prec, H, ld, n, units, b, s);
+    if (st != MLMC_OK || defer_bisect) return st;
     return run_bisect(n, ld, units, w, ldw, b, s);
 }
 
@@ -253,13 +273,16 @@ mlmc_status run_generalized(mlmc_precision prec, void *H, void *S, int64_t ld, c
 
 // Eigenvalues of every (outcome, k) unit of `ns` outcomes of side N.  With
 // bisect_pending, a path that ends in a bisection stops before it and says so
-// (the caller then calls run_bisect on the same buffers).
+// (the caller then calls run_bisect on the same buffers); with chase_pending
+// as well, the two-stage path stops after stage 1 (the caller then calls
+// run_chase first).
 mlmc_status outcome_spectra(const mlmc_lattice_s *lat, int N, const uint8_t *mask, int64_t ns, const double *kred,
                             int nk, mlmc_precision prec, double *w, int32_t *n_out, const EigBuffers &b,
-                            hipStream_t s, bool *bisect_pending = nullptr) {
+                            hipStream_t s, bool *bisect_pending = nullptr, bool *chase_pending = nullptr) {
     const int64_t ld = (int64_t)lat->dev.n_orb * N * N;
     const int64_t units = ns * nk;
     if (bisect_pending) *bisect_pending = false;
+    if (chase_pending) *chase_pending = false;
     // The eigensolvers read lower triangles only, so only those are assembled.
     if (lat->dev.n_ovl > 0) {  // non-orthogonal basis: assemble H and S, generalised path
         if (prec == MLMC_PREC_FP64) {
@@ -283,7 +306,9 @@ mlmc_status outcome_spectra(const mlmc_lattice_s *lat, int N, const uint8_t *mas
     else
         LAUNCH("assemble", s, launch_assemble<float>(lat->dev, N, mask, ns, kred, nk, static_cast<cpx<float> *>(b.H), ld, n_out, s, false, true));
     if (bisect_pending) *bisect_pending = true;
-    return run_large(prec, b.H, ld, n_out, units, w, ld, b, s, bisect_pending != nullptr);
+    if (bisect_pending && chase_pending) *chase_pending = true;
+    return run_large(prec, b.H, ld, n_out, units, w, ld, b, s, bisect_pending != nullptr,
+                     bisect_pending != nullptr && chase_pending != nullptr);
 }
 
 // The library's second stream on the current device, with the events that
@@ -291,14 +316,26 @@ mlmc_status outcome_spectra(const mlmc_lattice_s *lat, int N, const uint8_t *mas
 // first use, default priority; kept until the process ends.
 struct BackStream {
     hipStream_t s = nullptr;
-    int64_t bisect_blocks = 0;    // workgroups of a bisection on this stream: one per CU
+    hipStream_t sc = nullptr;     // the chase stream
+    int64_t bisect_blocks = 0;    // workgroups of a bisection on the back stream: one per CU
+    int64_t chase_blocks = 0;     // workgroups of a chase on the chase stream
     hipEvent_t begin = nullptr;   // caller's stream -> back stream
-    hipEvent_t ready = nullptr;   // front (caller's stream) -> back: a chunk's tridiagonals are complete
-    hipEvent_t freed[2] = {};     // back -> front: set q of the sizes / tridiagonals / eigenvalues is free
+    hipEvent_t ready = nullptr;   // front (caller's stream) -> chase and back: a chunk's front part is complete
+    hipEvent_t chased = nullptr;  // chase -> back: a chunk's tridiagonals are complete
+    hipEvent_t freed[2] = {};     // back -> front: set q of the matrices / sizes / tridiagonals / eigenvalues is free
     hipEvent_t end = nullptr;     // back -> caller's stream
 };
 constexpr int kMaxDevices = 64;
 std::mutex g_back_mu;  // held while a level estimate enqueues its work
+
+// Workgroups (one per CU) of a chase on the chase stream: the quarter of the
+// CUs it leaves free runs the next chunk's stage 1 (measured on the graphene
+// N = 16 workload, FP64: 3/4 of the CUs 22.3k eigensolves/s, 1/2 20.3k, all
+// 21.3k; with the chase on the front stream 21.3k).
+int64_t chase_cus(int cus) {
+    const int64_t v = (int64_t)cus * 3 / 4;
+    return v > 0 ? v : 1;
+}
 BackStream g_back[kMaxDevices];
 
 hipError_t back_stream(BackStream **out) {
@@ -315,9 +352,11 @@ hipError_t back_stream(BackStream **out) {
         err = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (err != hipSuccess) return err;
         b.bisect_blocks = cus > 0 ? cus : 1;
+        b.chase_blocks = chase_cus(cus);
         err = hipStreamCreateWithFlags(&b.s, hipStreamNonBlocking);
-        hipEvent_t *evs[5] = {&b.begin, &b.ready, &b.freed[0], &b.freed[1], &b.end};
-        for (int i = 0; i < 5 && err == hipSuccess; ++i) err = hipEventCreateWithFlags(evs[i], hipEventDisableTiming);
+        if (err == hipSuccess) err = hipStreamCreateWithFlags(&b.sc, hipStreamNonBlocking);
+        hipEvent_t *evs[6] = {&b.begin, &b.ready, &b.chased, &b.freed[0], &b.freed[1], &b.end};
+        for (int i = 0; i < 6 && err == hipSuccess; ++i) err = hipEventCreateWithFlags(evs[i], hipEventDisableTiming);
         if (err != hipSuccess) return err;
     }
     *out = &b;
@@ -693,15 +732,17 @@ mlmc_status mlmc_level_estimate(mlmc_lattice lat, int32_t N, int32_t coupled, do
     const double inv_area_c = cpl ? 1.0 / ((double)h * h * lat->dev.cell_area) : 0.0;
     const int nkf = kgrid_count(kind, Kf), nkc = cpl ? kgrid_count(kind, Kc) : 0;
     const int64_t ldf = (int64_t)lat->dev.n_orb * N * N, ldc = (int64_t)lat->dev.n_orb * h * h;
-    // Two streams: the caller's (front) samples, assembles and reduces chunk
-    // c; the back stream runs chunk c's bisection, IDoS and level sums while
-    // the front goes on with chunk c + 1.  Sizes, tridiagonals and eigenvalues
-    // alternate between two sets; the front waits until the back has released
-    // a set before refilling it.
+    // Three streams: the caller's (front) samples, assembles and reduces
+    // chunk c (on the two-stage path in FP64: stage 1 only); the chase stream
+    // chases chunk c's bands on 3/4 of the CUs while the front goes on with
+    // chunk c + 1; the back stream runs chunk c's bisection, IDoS and level
+    // sums.  Matrices (two-stage path), sizes, tridiagonals and
+    // eigenvalues alternate between two sets; the front waits until the back
+    // has released a set before refilling it.
     std::lock_guard<std::mutex> lk(g_back_mu);
     BackStream *bk = nullptr;
     HIP_TRY(back_stream(&bk), "level: back stream");
-    hipStream_t sb = bk->s;
+    hipStream_t sb = bk->s, sc = bk->sc;
     HIP_TRY(hipEventRecord(bk->begin, s), "level: event");
     HIP_TRY(hipStreamWaitEvent(sb, bk->begin, 0), "level: wait");
     for (int q = 0; q < 2; ++q) HIP_TRY(hipEventRecord(bk->freed[q], sb), "level: event");
@@ -713,17 +754,36 @@ mlmc_status mlmc_level_estimate(mlmc_lattice lat, int32_t N, int32_t coupled, do
         const int q = (int)(chunk & 1);
         HIP_TRY(hipStreamWaitEvent(s, bk->freed[q], 0), "level: wait");
         LAUNCH("sample_vacancies", s, launch_sample_vacancies(lat->dev, N, thr, seed, tag, first_sample + done, ns, L.mask, s));
-        bool pend_f = false, pend_c = false;
+        // In FP64 the two-stage chase moves to the chase stream; in mixed
+        // precision it stays on the front (its chase is short, and a third
+        // stream slowed the whole from 35.7k to 31.9k eigensolves/s at best).
+        bool pend_f = false, pend_c = false, chase_f = false, chase_c = false;
+        const bool split = prec == MLMC_PREC_FP64;
         const EigBuffers bf = L.bf.set(q), bc = L.bc.set(q);
-        st = outcome_spectra(lat, N, L.mask, ns, L.kf, nkf, prec, L.wf[q], L.nf[q], bf, s, &pend_f);
+        st = outcome_spectra(lat, N, L.mask, ns, L.kf, nkf, prec, L.wf[q], L.nf[q], bf, s, &pend_f,
+                             split ? &chase_f : nullptr);
         if (st != MLMC_OK) return st;
         if (cpl) {
             LAUNCH("partition", s, launch_partition(N, G, L.mask, ns, L.quarters, s));
-            st = outcome_spectra(lat, h, L.quarters, ns * 4, L.kc, nkc, prec, L.wc[q], L.nc[q], bc, s, &pend_c);
+            st = outcome_spectra(lat, h, L.quarters, ns * 4, L.kc, nkc, prec, L.wc[q], L.nc[q], bc, s, &pend_c,
+                                 split ? &chase_c : nullptr);
             if (st != MLMC_OK) return st;
         }
         HIP_TRY(hipEventRecord(bk->ready, s), "level: event");
         HIP_TRY(hipStreamWaitEvent(sb, bk->ready, 0), "level: wait");
+        if (chase_f || chase_c) {
+            HIP_TRY(hipStreamWaitEvent(sc, bk->ready, 0), "level: wait");
+            if (chase_f) {
+                st = run_chase(prec, bf.H, ldf, L.nf[q], ns * nkf, bf, sc, bk->chase_blocks);
+                if (st != MLMC_OK) return st;
+            }
+            if (chase_c) {
+                st = run_chase(prec, bc.H, ldc, L.nc[q], ns * 4 * nkc, bc, sc, bk->chase_blocks);
+                if (st != MLMC_OK) return st;
+            }
+            HIP_TRY(hipEventRecord(bk->chased, sc), "level: event");
+            HIP_TRY(hipStreamWaitEvent(sb, bk->chased, 0), "level: wait");
+        }
         if (pend_f) {
             st = run_bisect(L.nf[q], ldf, ns * nkf, L.wf[q], ldf, bf, sb, bk->bisect_blocks);
             if (st != MLMC_OK) return st;
@@ -743,6 +803,16 @@ mlmc_status mlmc_level_estimate(mlmc_lattice lat, int32_t N, int32_t coupled, do
     }
     HIP_TRY(hipEventRecord(bk->end, sb), "level: event");
     HIP_TRY(hipStreamWaitEvent(s, bk->end, 0), "level: wait");
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_chase_cus(mlmc_precision prec, int64_t *cus) {
+    if (!cus) return fail(MLMC_ERR_INVALID_ARG, "chase_cus: NULL argument");
+    if (prec != MLMC_PREC_FP64 && prec != MLMC_PREC_MIXED) return fail(MLMC_ERR_INVALID_ARG, "chase_cus: bad prec");
+    int dev = 0, n = 0;
+    HIP_TRY(hipGetDevice(&dev), "chase_cus: device");
+    HIP_TRY(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev), "chase_cus: attribute");
+    *cus = prec == MLMC_PREC_FP64 ? chase_cus(n) : (int64_t)n;
     return MLMC_OK;
 }
 

@@ -720,7 +720,7 @@ hipError_t launch_band_reduce(cpx<T> *H, int64_t ld, const int32_t *n_in, int64_
         const int64_t hrows = (mmax + kHemmRows - 1) / kHemmRows;
         hipLaunchKernelGGL(hemm_kernel<T>, dim3(xcd_grid(batch, hrows)), dim3(64), 0, s, H, ld, n_in,
                            work + 2 * (int64_t)kB * ld, work, work + (int64_t)kB * ld,
-                           work + 3 * (int64_t)kB * ld + kB * kB, stride, p, batch, hrows);
+                           work + hemm_partials_offset(ld), stride, p, batch, hrows);
         hipLaunchKernelGGL(wfactor_kernel<T>, dim3(B), dim3(kWThreads), 0, s, n_in, ld, work, stride, p);
         const int64_t nblk = (mmax + kUpdBlk - 1) / kUpdBlk, ntile = nblk * (nblk + 1) / 2;
         hipLaunchKernelGGL(band_update_kernel<T>, dim3(xcd_grid(batch, ntile)), dim3(256), 0, s, H, ld, n_in, work,

@@ -25,8 +25,10 @@ size_t generalized_work_elems(int64_t ld) {
 }
 
 template <typename T>
-__device__ __forceinline__ cpx<T> *linv_blocks(const TwoView<T> &w, int64_t ld) {
-    return w.band + (ld + 1) * kBandLd;
+__device__ __forceinline__ cpx<T> *linv_blocks(const TwoView<T> &w, int64_t) {
+    // The Hermitian product's partial products start here too; they are
+    // written only by the standard reduction of C, after the last use of L^-1.
+    return w.zp;
 }
 
 // Panel p of the Cholesky factorisation; S22 -= L21 L21^H follows as a

@@ -14,19 +14,22 @@ constexpr int kB = 16;                 // band half-width = panel width
 constexpr int kBandLd = 2 * kB + 1;    // stored sub-diagonals per column (incl. diagonal)
 
 // Per-matrix workspace (complex elements): V [kB][ld], X [kB][ld], W [kB][ld],
-// T [kB][kB], band [ld + 1][kBandLd].  The band's last column is a discard
-// slot: lanes with nothing to store write there, so that every store of a
-// block is issued unconditionally.  During stage 1 the band area holds the
-// Hermitian product's per-row-block partial products [ceil(ld / 64)][kB][kB]
-// (the chase fills it only afterwards).
+// T [kB][kB], band [ld + 1][kBandLd], then the Hermitian product's
+// per-row-block partial products [ceil(ld / 64)][kB][kB].  The band's last
+// column is a discard slot: lanes with nothing to store write there, so that
+// every store of a block is issued unconditionally.  Stage 1 never touches
+// the band and the chase touches nothing else.
 template <typename T>
 size_t tridiag_twostage_work_elems(int64_t ld) {
-    return (size_t)(3 * kB) * (size_t)ld + (size_t)kB * kB + (size_t)kBandLd * (size_t)(ld + 1);
+    return (size_t)(3 * kB) * (size_t)ld + (size_t)kB * kB + (size_t)kBandLd * (size_t)(ld + 1) +
+           (size_t)((ld + 63) / 64) * kB * kB;
 }
+// Offset of the partial products within a matrix's workspace.
+inline int64_t hemm_partials_offset(int64_t ld) { return 3 * kB * ld + kB * kB + kBandLd * (ld + 1); }
 
 template <typename T>
 struct TwoView {
-    cpx<T> *V, *X, *W, *Tm, *band;
+    cpx<T> *V, *X, *W, *Tm, *band, *zp;
     __device__ TwoView(cpx<T> *wall, int64_t stride, int64_t ld, int64_t u) {
         cpx<T> *b = wall + u * stride;
         V = b;
@@ -34,12 +37,13 @@ struct TwoView {
         W = X + (int64_t)kB * ld;
         Tm = W + (int64_t)kB * ld;
         band = Tm + kB * kB;
+        zp = band + kBandLd * (ld + 1);
     }
 };
 
 template <typename T>
 __device__ __forceinline__ cpx<T> *hemm_partials(const TwoView<T> &w, int64_t) {
-    return w.band;
+    return w.zp;
 }
 
 // Componentwise select (a select of whole structs can become a select of

@@ -295,6 +295,8 @@ def test_level_estimate_parity(B, gdev, mdev, name, N, coupled, K, Kc, kind, M, 
     ("graphene", 16, True, 1, 2, 1, 3, 1, 1),    # mixed, coupled: fine side device-memory, coarse side fused
     ("graphene", 8, True, 2, 4, 1, 7, 2, 0),     # fused paths, a ragged last chunk
     ("mos2", 4, True, 1, 2, 1, 4, 1, 0),         # MoS2-shaped fine n=176 on the device-memory path
+    ("mos2", 4, False, 4, 4, 0, 16, 16, 0),      # 256 matrices of n=176 per chunk: FP64 chase workgroups
+                                                 # (3/4 of the CUs) each take one or two matrices
 ])
 def test_level_estimate_pipelined_chunks(B, gdev, mdev, name, N, coupled, K, Kc, kind, M, chunk, prec):
     """Several chunks in one call: each chunk's bisection, IDoS and level sums
@@ -312,6 +314,15 @@ def test_level_estimate_pipelined_chunks(B, gdev, mdev, name, N, coupled, K, Kc,
                                 prec=prec, chunk_samples=chunk).cpu().numpy()
     want = oracle.level_estimate(dl.lat, N, coupled, p, K, Kc, kind, seed, 3, M, eps, delta, 0, n_threads=8)
     compare_stats(got, want, M, 1e-10 if prec == 0 else 1e-5)
+
+
+def test_chase_cus(B):
+    """The chase of an FP64 level estimate occupies 3/4 of the CUs, the mixed one all of them."""
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    assert B.mlmc_chase_cus(B.MLMC_PREC_FP64) == max(cus * 3 // 4, 1)
+    assert B.mlmc_chase_cus(B.MLMC_PREC_MIXED) == cus
+    with pytest.raises(B.MLMCError):
+        B.mlmc_chase_cus(7)
 
 
 def test_level_estimate_full_size_sample(B, gdev, glat):
