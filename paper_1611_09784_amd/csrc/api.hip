@@ -101,44 +101,51 @@ int small_cap(mlmc_precision prec) { return prec == MLMC_PREC_FP64 ? kSmallMaxF6
 int large_cap(mlmc_precision prec) { return prec == MLMC_PREC_FP64 ? kLargeMaxF64 : kLargeMaxF32; }
 size_t cplx_bytes(mlmc_precision prec) { return prec == MLMC_PREC_FP64 ? 16 : 8; }
 
+// Buffer sets of a pipelined level estimate: chunk c uses set c % kLevelSets,
+// so that the caller's stream can start chunk c + 2 while chunk c is still
+// being chased and bisected (graphene N = 16, FP64: 22.83k eigensolves/s
+// against 22.73k with two sets; one more set of matrices, 8.6 GB there).
+constexpr int kLevelSets = 3;
+
 // Buffers of the device-memory eigen path for `units` matrices of side bound ld.
 struct EigBuffers {
     void *H = nullptr;
     void *S = nullptr;  // overlap matrices (non-orthogonal basis only)
     double *d = nullptr, *e = nullptr;
-    // Second sets for pipelined level estimates: tridiagonal matrices, and on
-    // the two-stage path the matrices themselves (their chase runs beside the
-    // next chunk's stage 1).
-    void *H2 = nullptr;
-    double *d2 = nullptr, *e2 = nullptr;
+    // Further sets 1 .. kLevelSets - 1 for pipelined level estimates (set 0
+    // is H, d, e): tridiagonal matrices, and on the two-stage path the
+    // matrices themselves (a chunk's chase runs beside the next chunk's stage 1).
+    void *Hq[kLevelSets] = {};
+    double *dq[kLevelSets] = {}, *eq[kLevelSets] = {};
     void *partial = nullptr;
 
-    // The view whose H (when it has two), d, e are set `parity` (0 or 1).
-    EigBuffers set(int parity) const {
+    // The view whose H (when it has sets), d, e are set q.
+    EigBuffers set(int q) const {
         EigBuffers v = *this;
-        if (parity) {
-            if (H2) v.H = H2;
-            v.d = d2;
-            v.e = e2;
+        if (q > 0) {
+            if (Hq[q]) v.H = Hq[q];
+            v.d = dq[q];
+            v.e = eq[q];
         }
         return v;
     }
 };
 
-void carve_tridiagonal(Carver &cv, int64_t ld, int64_t units, bool twin, EigBuffers &b) {
+void carve_tridiagonal(Carver &cv, int64_t ld, int64_t units, int sets, EigBuffers &b) {
     b.d = cv.take<double>(sizeof(double) * (size_t)ld * (size_t)units);
     b.e = cv.take<double>(sizeof(double) * (size_t)ld * (size_t)units);
-    if (twin) {
-        b.d2 = cv.take<double>(sizeof(double) * (size_t)ld * (size_t)units);
-        b.e2 = cv.take<double>(sizeof(double) * (size_t)ld * (size_t)units);
+    for (int q = 1; q < sets; ++q) {
+        b.dq[q] = cv.take<double>(sizeof(double) * (size_t)ld * (size_t)units);
+        b.eq[q] = cv.take<double>(sizeof(double) * (size_t)ld * (size_t)units);
     }
 }
 
 void carve_large(Carver &cv, mlmc_precision prec, int64_t ld, int64_t units, bool with_H, EigBuffers &b,
-                 bool twin = false) {
+                 int sets = 1) {
     if (with_H) b.H = cv.take<void>(cplx_bytes(prec) * (size_t)ld * (size_t)ld * (size_t)units);
-    if (with_H && twin) b.H2 = cv.take<void>(cplx_bytes(prec) * (size_t)ld * (size_t)ld * (size_t)units);
-    carve_tridiagonal(cv, ld, units, twin, b);
+    for (int q = 1; with_H && q < sets; ++q)
+        b.Hq[q] = cv.take<void>(cplx_bytes(prec) * (size_t)ld * (size_t)ld * (size_t)units);
+    carve_tridiagonal(cv, ld, units, sets, b);
     const size_t pe = prec == MLMC_PREC_FP64 ? tridiag_twostage_work_elems<double>(ld)
                                              : tridiag_twostage_work_elems<float>(ld);
     b.partial = cv.take<void>(cplx_bytes(prec) * pe * (size_t)units);
@@ -148,12 +155,12 @@ void carve_large(Carver &cv, mlmc_precision prec, int64_t ld, int64_t units, boo
 // d, e, and the per-matrix workspace of the Cholesky / two-sided reduction,
 // which the two-stage reduction reuses afterwards.
 void carve_generalized(Carver &cv, mlmc_precision prec, int64_t ld, int64_t units, bool with_HS, EigBuffers &b,
-                       bool twin = false) {
+                       int sets = 1) {
     if (with_HS) {
         b.H = cv.take<void>(cplx_bytes(prec) * (size_t)ld * (size_t)ld * (size_t)units);
         b.S = cv.take<void>(cplx_bytes(prec) * (size_t)ld * (size_t)ld * (size_t)units);
     }
-    carve_tridiagonal(cv, ld, units, twin, b);
+    carve_tridiagonal(cv, ld, units, sets, b);
     const size_t pe = prec == MLMC_PREC_FP64 ? generalized_work_elems<double>(ld) : generalized_work_elems<float>(ld);
     b.partial = cv.take<void>(cplx_bytes(prec) * pe * (size_t)units);
 }
@@ -197,14 +204,14 @@ mlmc_status run_large(mlmc_precision prec, void *H, int64_t ld, const int32_t *n
 }
 
 // Layout of mlmc_level_estimate's workspace for a chunk of `mc` samples.  The
-// matrix sizes, tridiagonal matrices and eigenvalues come in two sets, one per
-// chunk parity, so that one chunk's bisection and IDoS overlap the next
-// chunk's reduction.
+// matrices (two-stage path), matrix sizes, tridiagonal matrices and
+// eigenvalues come in kLevelSets sets, used by chunks in turn, so that one
+// chunk's chase, bisection and IDoS overlap the reduction of the next ones.
 struct LevelLayout {
     double *kf = nullptr, *kwf = nullptr, *kc = nullptr, *kwc = nullptr;
     uint8_t *mask = nullptr, *quarters = nullptr;
-    int32_t *nf[2] = {}, *nc[2] = {};
-    double *wf[2] = {}, *wc[2] = {};
+    int32_t *nf[kLevelSets] = {}, *nc[kLevelSets] = {};
+    double *wf[kLevelSets] = {}, *wc[kLevelSets] = {};
     double *If = nullptr, *Ic = nullptr;
     EigBuffers bf, bc;
     size_t bytes = 0;
@@ -224,27 +231,27 @@ LevelLayout level_layout(const mlmc_lattice_s *lat, int N, bool coupled, int Kf,
     L.kf = cv.take<double>(sizeof(double) * 2 * nkf);
     L.kwf = cv.take<double>(sizeof(double) * nkf);
     L.mask = cv.take<uint8_t>((size_t)mc * N * N * G);
-    for (int q = 0; q < 2; ++q) {
+    for (int q = 0; q < kLevelSets; ++q) {
         L.nf[q] = cv.take<int32_t>(sizeof(int32_t) * (size_t)(mc * nkf));
         L.wf[q] = cv.take<double>(sizeof(double) * (size_t)(mc * nkf * ldf));
     }
     L.If = cv.take<double>(sizeof(double) * (size_t)mc * n_eps);
     const bool gen = lat->dev.n_ovl > 0;
-    if (gen) carve_generalized(cv, prec, ldf, mc * nkf, true, L.bf, true);
-    else if (ldf > small_cap(prec)) carve_large(cv, prec, ldf, mc * nkf, true, L.bf, true);
+    if (gen) carve_generalized(cv, prec, ldf, mc * nkf, true, L.bf, kLevelSets);
+    else if (ldf > small_cap(prec)) carve_large(cv, prec, ldf, mc * nkf, true, L.bf, kLevelSets);
     if (coupled) {
         const int h = N / 2;
         const int64_t ldc = (int64_t)no * h * h;
         L.kc = cv.take<double>(sizeof(double) * 2 * nkc);
         L.kwc = cv.take<double>(sizeof(double) * nkc);
         L.quarters = cv.take<uint8_t>((size_t)mc * 4 * h * h * G);
-        for (int q = 0; q < 2; ++q) {
+        for (int q = 0; q < kLevelSets; ++q) {
             L.nc[q] = cv.take<int32_t>(sizeof(int32_t) * (size_t)(mc * 4 * nkc));
             L.wc[q] = cv.take<double>(sizeof(double) * (size_t)(mc * 4 * nkc * ldc));
         }
         L.Ic = cv.take<double>(sizeof(double) * (size_t)mc * 4 * n_eps);
-        if (gen) carve_generalized(cv, prec, ldc, mc * 4 * nkc, true, L.bc, true);
-        else if (ldc > small_cap(prec)) carve_large(cv, prec, ldc, mc * 4 * nkc, true, L.bc, true);
+        if (gen) carve_generalized(cv, prec, ldc, mc * 4 * nkc, true, L.bc, kLevelSets);
+        else if (ldc > small_cap(prec)) carve_large(cv, prec, ldc, mc * 4 * nkc, true, L.bc, kLevelSets);
     }
     L.bytes = cv.used;
     return L;
@@ -322,7 +329,8 @@ struct BackStream {
     hipEvent_t begin = nullptr;   // caller's stream -> back stream
     hipEvent_t ready = nullptr;   // front (caller's stream) -> chase and back: a chunk's front part is complete
     hipEvent_t chased = nullptr;  // chase -> back: a chunk's tridiagonals are complete
-    hipEvent_t freed[2] = {};     // back -> front: set q of the matrices / sizes / tridiagonals / eigenvalues is free
+    hipEvent_t freed[kLevelSets] = {};  // back -> front: set q of the matrices / sizes / tridiagonals /
+                                        // eigenvalues is free
     hipEvent_t end = nullptr;     // back -> caller's stream
 };
 constexpr int kMaxDevices = 64;
@@ -355,8 +363,10 @@ hipError_t back_stream(BackStream **out) {
         b.chase_blocks = chase_cus(cus);
         err = hipStreamCreateWithFlags(&b.s, hipStreamNonBlocking);
         if (err == hipSuccess) err = hipStreamCreateWithFlags(&b.sc, hipStreamNonBlocking);
-        hipEvent_t *evs[6] = {&b.begin, &b.ready, &b.chased, &b.freed[0], &b.freed[1], &b.end};
-        for (int i = 0; i < 6 && err == hipSuccess; ++i) err = hipEventCreateWithFlags(evs[i], hipEventDisableTiming);
+        hipEvent_t *evs[4] = {&b.begin, &b.ready, &b.chased, &b.end};
+        for (int i = 0; i < 4 && err == hipSuccess; ++i) err = hipEventCreateWithFlags(evs[i], hipEventDisableTiming);
+        for (int q = 0; q < kLevelSets && err == hipSuccess; ++q)
+            err = hipEventCreateWithFlags(&b.freed[q], hipEventDisableTiming);
         if (err != hipSuccess) return err;
     }
     *out = &b;
@@ -736,8 +746,8 @@ mlmc_status mlmc_level_estimate(mlmc_lattice lat, int32_t N, int32_t coupled, do
     // chunk c (on the two-stage path in FP64: stage 1 only); the chase stream
     // chases chunk c's bands on 3/4 of the CUs while the front goes on with
     // chunk c + 1; the back stream runs chunk c's bisection, IDoS and level
-    // sums.  Matrices (two-stage path), sizes, tridiagonals and
-    // eigenvalues alternate between two sets; the front waits until the back
+    // sums.  Matrices (two-stage path), sizes, tridiagonals and eigenvalues
+    // come in kLevelSets sets used in turn; the front waits until the back
     // has released a set before refilling it.
     std::lock_guard<std::mutex> lk(g_back_mu);
     BackStream *bk = nullptr;
@@ -745,13 +755,13 @@ mlmc_status mlmc_level_estimate(mlmc_lattice lat, int32_t N, int32_t coupled, do
     hipStream_t sb = bk->s, sc = bk->sc;
     HIP_TRY(hipEventRecord(bk->begin, s), "level: event");
     HIP_TRY(hipStreamWaitEvent(sb, bk->begin, 0), "level: wait");
-    for (int q = 0; q < 2; ++q) HIP_TRY(hipEventRecord(bk->freed[q], sb), "level: event");
+    for (int q = 0; q < kLevelSets; ++q) HIP_TRY(hipEventRecord(bk->freed[q], sb), "level: event");
     LAUNCH("kgrid", s, launch_kgrid(kind, Kf, L.kf, L.kwf, s));
     if (cpl) LAUNCH("kgrid", s, launch_kgrid(kind, Kc, L.kc, L.kwc, s));
     int64_t chunk = 0;
     for (int64_t done = 0; done < M; done += mc, ++chunk) {
         const int64_t ns = (M - done < mc) ? (M - done) : mc;
-        const int q = (int)(chunk & 1);
+        const int q = (int)(chunk % kLevelSets);
         HIP_TRY(hipStreamWaitEvent(s, bk->freed[q], 0), "level: wait");
         LAUNCH("sample_vacancies", s, launch_sample_vacancies(lat->dev, N, thr, seed, tag, first_sample + done, ns, L.mask, s));
         // In FP64 the two-stage chase moves to the chase stream; in mixed
@@ -771,28 +781,32 @@ mlmc_status mlmc_level_estimate(mlmc_lattice lat, int32_t N, int32_t coupled, do
         }
         HIP_TRY(hipEventRecord(bk->ready, s), "level: event");
         HIP_TRY(hipStreamWaitEvent(sb, bk->ready, 0), "level: wait");
+        // The last chunk's chase and bisection have nothing left to run
+        // beside: they take the whole device (one workgroup per matrix).
+        const bool last = done + ns >= M;
+        const int64_t chase_blocks = last ? 0 : bk->chase_blocks, bisect_blocks = last ? 0 : bk->bisect_blocks;
         if (chase_f || chase_c) {
             HIP_TRY(hipStreamWaitEvent(sc, bk->ready, 0), "level: wait");
             if (chase_f) {
-                st = run_chase(prec, bf.H, ldf, L.nf[q], ns * nkf, bf, sc, bk->chase_blocks);
+                st = run_chase(prec, bf.H, ldf, L.nf[q], ns * nkf, bf, sc, chase_blocks);
                 if (st != MLMC_OK) return st;
             }
             if (chase_c) {
-                st = run_chase(prec, bc.H, ldc, L.nc[q], ns * 4 * nkc, bc, sc, bk->chase_blocks);
+                st = run_chase(prec, bc.H, ldc, L.nc[q], ns * 4 * nkc, bc, sc, chase_blocks);
                 if (st != MLMC_OK) return st;
             }
             HIP_TRY(hipEventRecord(bk->chased, sc), "level: event");
             HIP_TRY(hipStreamWaitEvent(sb, bk->chased, 0), "level: wait");
         }
         if (pend_f) {
-            st = run_bisect(L.nf[q], ldf, ns * nkf, L.wf[q], ldf, bf, sb, bk->bisect_blocks);
+            st = run_bisect(L.nf[q], ldf, ns * nkf, L.wf[q], ldf, bf, sb, bisect_blocks);
             if (st != MLMC_OK) return st;
         }
         LAUNCH("idos", sb, launch_idos(L.wf[q], ldf, L.nf[q], ns, nkf, L.kwf, inv_area_f, d_eps, n_eps, delta,
                              (int)smoother, L.If, sb));
         if (cpl) {
             if (pend_c) {
-                st = run_bisect(L.nc[q], ldc, ns * 4 * nkc, L.wc[q], ldc, bc, sb, bk->bisect_blocks);
+                st = run_bisect(L.nc[q], ldc, ns * 4 * nkc, L.wc[q], ldc, bc, sb, bisect_blocks);
                 if (st != MLMC_OK) return st;
             }
             LAUNCH("idos", sb, launch_idos(L.wc[q], ldc, L.nc[q], ns * 4, nkc, L.kwc, inv_area_c, d_eps, n_eps, delta,
