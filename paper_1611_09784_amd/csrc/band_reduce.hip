@@ -24,6 +24,7 @@ constexpr int kHemmRows = 64;
 constexpr int kHemmDepth = 2;  // Hermitian product: register sets of its load pipeline
 constexpr int kWThreads = 256;
 constexpr int kUpdBlk = 64;
+constexpr bool kUpdate32 = true;
 
 // Workgroups are dispatched round-robin over the chip's 8 XCDs (each with its
 // own L2).  Kernels with several workgroups per matrix take their (matrix,
@@ -699,6 +700,107 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
     }
 }
 
+// The same update with 32 x 64 tiles (32 rows, 64 columns) and 16 KiB of LDS:
+// only the rows' V, W strips are staged; each wavefront loads the V, W
+// entries of its own 16 columns (the A operand) from L2 into registers.  Its
+// workgroups fit beside a chase workgroup on one CU, which the 64 x 64 tiles
+// (64 KiB) do not.  Lower tiles (bi, bj) have bj <= bi / 2; with a = bi / 2
+// rows 2a and 2a + 1 hold a + 1 tiles each, so tile t lies in rows 2a or
+// 2a + 1 for a (a + 1) <= t < (a + 1) (a + 2).
+template <typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void band_update32_kernel(
+    cpx<T> *__restrict__ Hall, int64_t ld, const int32_t *__restrict__ n_in, cpx<T> *__restrict__ wall,
+    int64_t stride, int p, int64_t batch, int64_t tiles, int min_m) {
+    constexpr int R = kUpdBlk / 2;  // rows per tile
+    __shared__ cpx<T> sVr[kB][R], sWr[kB][R];
+    int64_t u, tile;
+    xcd_tile(blockIdx.x, tiles, u, tile);
+    if (u >= batch) return;
+    const int n = n_in[u];
+    const int s = p + kB;
+    if (n < 0 || n > ld || n - s < min_m) return;
+    int a = (int)((sqrt(4.0 * (double)tile + 1.0) - 1.0) * 0.5);
+    while ((int64_t)a * (a + 1) > tile) --a;
+    while ((int64_t)(a + 1) * (a + 2) <= tile) ++a;
+    const int64_t t0 = tile - (int64_t)a * (a + 1);
+    const int bi = t0 < a + 1 ? 2 * a : 2 * a + 1;
+    const int bj = (int)(t0 < a + 1 ? t0 : t0 - (a + 1));
+    const int rb = s + bi * R, cb = s + bj * kUpdBlk;
+    if (rb >= n || cb > rb + R - 1) return;
+    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+    const int ii = lane & 15, kk = lane >> 4;
+    const TwoView<T> w(wall, stride, ld, u);
+    const int ldi = (int)ld;
+    // Row strips (16 x 32 of V and of W: two entries per thread).
+    cpx<T> fv[2][2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int idx = t + 256 * q, k = idx / R, l = idx % R, r = rb + l;
+        fv[q][0] = w.V[r < n ? k * ldi + r : 0];
+        fv[q][1] = w.W[r < n ? k * ldi + r : 0];
+    }
+    // This wavefront's columns cs + ii: the A operand of step k0 is
+    // conj(Q[c, k0 + kk]) with Q = [W V] (k < 2 kB); and its part of the tile,
+    // rows rb + 16 tt + ii, columns cs + row(lane, v).
+    const int cs = cb + wid * 16, c = cs + ii;
+    cpx<T> af[2 * kB / 4];
+#pragma unroll
+    for (int q = 0; q < 2 * kB / 4; ++q) {
+        const int k = 4 * q + kk;
+        af[q] = (k < kB ? w.W : w.V)[c < n ? (k & (kB - 1)) * ldi + c : 0];
+    }
+    cpx<T> *A = Hall + u * ld * ld;
+    cpx<T> x[2][4];
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt) {
+        const int r = rb + 16 * tt + ii;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int cc = cs + Mfma<T>::row(lane, v);
+            x[tt][v] = A[(r < n && cc < n && r >= cc) ? r + cc * ldi : 0];
+        }
+    }
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int idx = t + 256 * q, k = idx / R, l = idx % R;
+        const bool ok = rb + l < n;
+        sVr[k][l] = {ok ? fv[q][0].re : T(0), ok ? fv[q][0].im : T(0)};
+        sWr[k][l] = {ok ? fv[q][1].re : T(0), ok ? fv[q][1].im : T(0)};
+    }
+    __syncthreads();
+    if (cs >= n || cs > rb + R - 1) return;
+    CAcc3<T> acc[2];
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt) acc[tt].zero();
+    // Row tiles wholly above this wavefront's columns lie in the upper
+    // triangle (never stored) and are skipped.
+    const int tt0 = __builtin_amdgcn_readfirstlane(rb + 15 < cs ? 1 : 0);
+#pragma unroll
+    for (int q = 0; q < 2 * kB / 4; ++q) {
+        const int k = 4 * q + kk;
+        const bool ok = c < n;
+        const cpx<T> ac = {ok ? af[q].re : T(0), ok ? -af[q].im : T(0)};
+        const T as = ac.re + ac.im;
+#pragma unroll
+        for (int tt = 0; tt < 2; ++tt) {
+            if (tt < tt0) continue;
+            const cpx<T> b = (k < kB) ? sVr[k][16 * tt + ii] : sWr[k - kB][16 * tt + ii];
+            acc[tt].mma(ac, as, b, b.re + b.im);
+        }
+    }
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt) {
+        const int r = rb + 16 * tt + ii;
+        const typename Mfma<T>::v4 dre = acc[tt].re(), dim = acc[tt].im();
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int cc = cs + Mfma<T>::row(lane, v);
+            if (r < n && cc < n && r >= cc) A[r + cc * ldi] = c_sub(x[tt][v], cpx<T>{dre[v], dim[v]});
+        }
+    }
+}
+
 template <typename T>
 hipError_t launch_band_reduce(cpx<T> *H, int64_t ld, const int32_t *n_in, int64_t batch, cpx<T> *work,
                               hipStream_t s) {
@@ -722,9 +824,17 @@ hipError_t launch_band_reduce(cpx<T> *H, int64_t ld, const int32_t *n_in, int64_
                            work + 2 * (int64_t)kB * ld, work, work + (int64_t)kB * ld,
                            work + hemm_partials_offset(ld), stride, p, batch, hrows);
         hipLaunchKernelGGL(wfactor_kernel<T>, dim3(B), dim3(kWThreads), 0, s, n_in, ld, work, stride, p);
-        const int64_t nblk = (mmax + kUpdBlk - 1) / kUpdBlk, ntile = nblk * (nblk + 1) / 2;
-        hipLaunchKernelGGL(band_update_kernel<T>, dim3(xcd_grid(batch, ntile)), dim3(256), 0, s, H, ld, n_in, work,
-                           stride, p, batch, ntile, 2);
+        if (kUpdate32) {
+            const int64_t nb32 = (mmax + kUpdBlk / 2 - 1) / (kUpdBlk / 2), ha = (nb32 - 1) / 2;
+            // tiles of rows 0 .. nb32 - 1: pairs of rows (2a, 2a + 1) hold 2 (a + 1) tiles
+            const int64_t ntile = (nb32 % 2 == 0) ? (ha + 1) * (ha + 2) : (ha + 1) * (ha + 1);
+            hipLaunchKernelGGL(band_update32_kernel<T>, dim3(xcd_grid(batch, ntile)), dim3(256), 0, s, H, ld, n_in,
+                               work, stride, p, batch, ntile, 2);
+        } else {
+            const int64_t nblk = (mmax + kUpdBlk - 1) / kUpdBlk, ntile = nblk * (nblk + 1) / 2;
+            hipLaunchKernelGGL(band_update_kernel<T>, dim3(xcd_grid(batch, ntile)), dim3(256), 0, s, H, ld, n_in,
+                               work, stride, p, batch, ntile, 2);
+        }
         const hipError_t err = hipGetLastError();
         if (err != hipSuccess) return err;
     }
