@@ -17,8 +17,8 @@ Prints one JSON line.  ``value`` is eigensolves per second of the whole job.
 band-to-tridiagonal chase, timed with HIP events on the library's stream
 during the timed region, against the vector ALU peak: algorithmic flops per
 launch (``chase_flops``) over the average launch duration, with its
-algorithmic HBM bytes (``chase_bytes``) alongside.  In FP64 the chase runs on
-3/4 of the CUs beside the next chunk's dense-to-band stage (``cus``,
+algorithmic HBM bytes (``chase_bytes``) alongside.  The chase runs on 3/4 of
+the CUs beside the next chunk's dense-to-band stage (``cus``,
 ``frac_of_its_cus``: the fraction of the peak of the CUs it occupies), which
 lengthens each launch but shortens the whole job; ``traffic`` is the HBM
 bytes per launch measured with rocprofv3 counters (recorded in profiles/ with
@@ -315,8 +315,8 @@ def main():
         peak = FP64_PEAK_TFLOPS if prec == B.MLMC_PREC_FP64 else FP32_PEAK_TFLOPS
         achieved = total_flops / (kms * 1e-3) / 1e12
         per_solve = chase_traffic_per_solve() if prec == B.MLMC_PREC_FP64 and wl.name == "graphene_n16_mc" else None
-        # In FP64 the level pipeline gives the chase part of the CUs (the rest
-        # run the next chunk's dense-to-band stage meanwhile): frac is against
+        # The level pipeline gives the chase part of the CUs (beside it the
+        # next chunk's dense-to-band stage runs meanwhile): frac is against
         # the whole chip, frac_of_its_cus against the CUs it occupies.
         cus = B.mlmc_chase_cus(prec)
         cus_total = torch.cuda.get_device_properties(0).multi_processor_count

@@ -254,9 +254,9 @@ mlmc_status mlmc_level_workspace(mlmc_lattice lat, int32_t N_fine, int32_t coupl
  * ([4][n_eps], accumulated; the caller initialises it).
  * Samples are processed in chunks that fit the workspace.  Each chunk's
  * bisection, IDoS and level sums run on a second stream owned by the library
- * while the caller's stream goes on with the next chunk; in FP64 the
- * two-stage path's band-to-tridiagonal chase runs on a third such stream, on
- * the number of CUs mlmc_chase_cus reports, beside the next chunk's dense-to-
+ * while the caller's stream goes on with the next chunk; the two-stage
+ * path's band-to-tridiagonal chase runs on a third such stream, on the
+ * number of CUs mlmc_chase_cus reports, beside the next chunk's dense-to-
  * band stage on the caller's stream (these streams: one pair per device,
  * default priority, created on the first call and kept until the process
  * ends).  The work is ordered by events, `stream` waits for the library's
@@ -272,10 +272,9 @@ mlmc_status mlmc_level_estimate(mlmc_lattice lat, int32_t N_fine, int32_t couple
                                 mlmc_stream stream);
 
 /* Workgroups (one per CU) that mlmc_level_estimate's chase occupies on the
- * current device with precision prec: 3/4 of the CUs in FP64 (the chase
- * runs beside the next chunk's dense-to-band stage), all of them in mixed
- * precision (where it runs on the caller's stream, one workgroup per matrix
- * up to the CU count at a time).  Errors: no device, bad prec. */
+ * current device with precision prec: 3/4 of the CUs (the chase runs beside
+ * the next chunk's dense-to-band stage; the last chunk of a call is chased on
+ * the whole device).  Errors: no device, bad prec. */
 mlmc_status mlmc_chase_cus(mlmc_precision prec, int64_t *cus);
 
 /* Sample allocation of eq. (opt_samples) (host, no device work):

@@ -336,10 +336,11 @@ struct BackStream {
 constexpr int kMaxDevices = 64;
 std::mutex g_back_mu;  // held while a level estimate enqueues its work
 
-// Workgroups (one per CU) of a chase on the chase stream: the quarter of the
-// CUs it leaves free runs the next chunk's stage 1 (measured on the graphene
-// N = 16 workload, FP64: 3/4 of the CUs 22.3k eigensolves/s, 1/2 20.3k, all
-// 21.3k; with the chase on the front stream 21.3k).
+// Workgroups (one per CU) of a chase on the chase stream: the next chunk's
+// stage 1 runs on the quarter of the CUs it leaves free and, with the 32-row
+// rank-2k update, beside it on the others (measured on the graphene N = 16
+// workload: FP64 3/4 of the CUs 24.7k eigensolves/s, 5/8 22.9k, 7/8 24.1k,
+// all 21.9k; mixed 40.3k, 37.6k, 38.8k, 30.1k).
 int64_t chase_cus(int cus) {
     const int64_t v = (int64_t)cus * 3 / 4;
     return v > 0 ? v : 1;
@@ -743,10 +744,9 @@ mlmc_status mlmc_level_estimate(mlmc_lattice lat, int32_t N, int32_t coupled, do
     const int nkf = kgrid_count(kind, Kf), nkc = cpl ? kgrid_count(kind, Kc) : 0;
     const int64_t ldf = (int64_t)lat->dev.n_orb * N * N, ldc = (int64_t)lat->dev.n_orb * h * h;
     // Three streams: the caller's (front) samples, assembles and reduces
-    // chunk c (on the two-stage path in FP64: stage 1 only); the chase stream
-    // chases chunk c's bands on 3/4 of the CUs while the front goes on with
-    // chunk c + 1; the back stream runs chunk c's bisection, IDoS and level
-    // sums.  Matrices (two-stage path), sizes, tridiagonals and eigenvalues
+    // chunk c (on the two-stage path: stage 1 only); the chase stream chases
+    // chunk c's bands on 3/4 of the CUs while the front goes on with chunk
+    // c + 1; the back stream runs chunk c's bisection, IDoS and level sums.  Matrices (two-stage path), sizes, tridiagonals and eigenvalues
     // come in kLevelSets sets used in turn; the front waits until the back
     // has released a set before refilling it.
     std::lock_guard<std::mutex> lk(g_back_mu);
@@ -764,19 +764,14 @@ mlmc_status mlmc_level_estimate(mlmc_lattice lat, int32_t N, int32_t coupled, do
         const int q = (int)(chunk % kLevelSets);
         HIP_TRY(hipStreamWaitEvent(s, bk->freed[q], 0), "level: wait");
         LAUNCH("sample_vacancies", s, launch_sample_vacancies(lat->dev, N, thr, seed, tag, first_sample + done, ns, L.mask, s));
-        // In FP64 the two-stage chase moves to the chase stream; in mixed
-        // precision it stays on the front (its chase is short, and a third
-        // stream slowed the whole from 35.7k to 31.9k eigensolves/s at best).
         bool pend_f = false, pend_c = false, chase_f = false, chase_c = false;
-        const bool split = prec == MLMC_PREC_FP64;
         const EigBuffers bf = L.bf.set(q), bc = L.bc.set(q);
-        st = outcome_spectra(lat, N, L.mask, ns, L.kf, nkf, prec, L.wf[q], L.nf[q], bf, s, &pend_f,
-                             split ? &chase_f : nullptr);
+        st = outcome_spectra(lat, N, L.mask, ns, L.kf, nkf, prec, L.wf[q], L.nf[q], bf, s, &pend_f, &chase_f);
         if (st != MLMC_OK) return st;
         if (cpl) {
             LAUNCH("partition", s, launch_partition(N, G, L.mask, ns, L.quarters, s));
             st = outcome_spectra(lat, h, L.quarters, ns * 4, L.kc, nkc, prec, L.wc[q], L.nc[q], bc, s, &pend_c,
-                                 split ? &chase_c : nullptr);
+                                 &chase_c);
             if (st != MLMC_OK) return st;
         }
         HIP_TRY(hipEventRecord(bk->ready, s), "level: event");
@@ -826,7 +821,7 @@ mlmc_status mlmc_chase_cus(mlmc_precision prec, int64_t *cus) {
     int dev = 0, n = 0;
     HIP_TRY(hipGetDevice(&dev), "chase_cus: device");
     HIP_TRY(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev), "chase_cus: attribute");
-    *cus = prec == MLMC_PREC_FP64 ? chase_cus(n) : (int64_t)n;
+    *cus = chase_cus(n);
     return MLMC_OK;
 }
 

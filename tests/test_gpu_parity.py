@@ -317,10 +317,10 @@ def test_level_estimate_pipelined_chunks(B, gdev, mdev, name, N, coupled, K, Kc,
 
 
 def test_chase_cus(B):
-    """The chase of an FP64 level estimate occupies 3/4 of the CUs, the mixed one all of them."""
+    """The chase of a level estimate occupies 3/4 of the CUs in either precision."""
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     assert B.mlmc_chase_cus(B.MLMC_PREC_FP64) == max(cus * 3 // 4, 1)
-    assert B.mlmc_chase_cus(B.MLMC_PREC_MIXED) == cus
+    assert B.mlmc_chase_cus(B.MLMC_PREC_MIXED) == max(cus * 3 // 4, 1)
     with pytest.raises(B.MLMCError):
         B.mlmc_chase_cus(7)
 
