@@ -318,9 +318,10 @@ mlmc_status outcome_spectra(const mlmc_lattice_s *lat, int N, const uint8_t *mas
                      bisect_pending != nullptr && chase_pending != nullptr);
 }
 
-// The library's second stream on the current device, with the events that
-// order it against the caller's stream in mlmc_level_estimate.  Created on
-// first use, default priority; kept until the process ends.
+// The library's two streams on the current device (back: bisection, IDoS,
+// level sums; chase), with the events that order them against the caller's
+// stream in mlmc_level_estimate.  Created on first use, default priority;
+// kept until the process ends.
 struct BackStream {
     hipStream_t s = nullptr;
     hipStream_t sc = nullptr;     // the chase stream

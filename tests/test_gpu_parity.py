@@ -299,9 +299,10 @@ def test_level_estimate_parity(B, gdev, mdev, name, N, coupled, K, Kc, kind, M, 
                                                  # (3/4 of the CUs) each take one or two matrices
 ])
 def test_level_estimate_pipelined_chunks(B, gdev, mdev, name, N, coupled, K, Kc, kind, M, chunk, prec):
-    """Several chunks in one call: each chunk's bisection, IDoS and level sums
-    run on the library's second stream while the next chunk is reduced, with
-    sizes, tridiagonals and eigenvalues alternating between two sets."""
+    """Several chunks in one call: each chunk's chase (two-stage path) and its
+    bisection, IDoS and level sums run on the library's streams while the next
+    chunks are reduced, with matrices, sizes, tridiagonals and eigenvalues
+    taken from three sets in turn."""
     say(f"[level_estimate pipelined] {name} N={N} coupled={coupled} M={M} chunk={chunk} prec={prec}")
     dl = pick(name, gdev, mdev)
     if name == "graphene":
