@@ -343,6 +343,25 @@ def test_level_estimate_full_size_sample(B, gdev, glat):
     compare_stats(got, want, 1, 1e-10)
 
 
+def test_level_estimate_full_size_bench_launches(B, gdev, glat):
+    """The benchmark's launch configuration at full size: graphene N=16, MP
+    8x8, 401 energies, 32-sample chunks; 33 samples make two chunks, so the
+    first chunk's 2048 bands are chased by the persistent workgroups on 3/4 of
+    the CUs (several matrices each) beside the second chunk's dense-to-band
+    stage, and the second (last) chunk on the full grid.  Level sums against
+    the oracle over all 33 samples."""
+    say("[level_estimate full-size, benchmark launches]")
+    N, K, p, seed, delta, M, chunk = 16, 8, 0.05, 202, 0.05, 33, 32
+    eps = energy_grid(-9.0, 9.0, 401)
+    d_eps = torch.as_tensor(eps, device=DEV)
+    need = B.mlmc_level_workspace(gdev, N, False, K, K, B.MLMC_KGRID_MP, chunk, B.MLMC_PREC_FP64, eps.size)
+    work = torch.empty((need,), dtype=torch.uint8, device=DEV)
+    first = 500
+    got = B.mlmc_level_estimate(gdev, N, False, p, K, K, 0, seed, first, M, d_eps, delta, work=work).cpu().numpy()
+    want = oracle.level_estimate(glat, N, False, p, K, K, 0, seed, first, M, eps, delta, 0, n_threads=16)
+    compare_stats(got, want, M, 1e-10)
+
+
 def test_determinism_and_batch_independence(B, gdev, glat):
     say("[determinism]")
     eps = torch.as_tensor(energy_grid(-9.0, 9.0, 101), device=DEV)
