@@ -26,7 +26,9 @@ the hash of the kernel source, null if the source has changed since).
 ``time_to_tol`` runs the MLMC estimator of the graphene level hierarchy to
 TOL = 1e-3 with the FP64 and the mixed path.  ``cpu_baseline`` times the FP64 C
 oracle (unchanged) on a bounded number of samples of the same workload on the
-host cores.
+host cores, with two context lines: the oracle on one core and one sample,
+and LAPACK's Hermitian eigenvalues (scipy, threaded BLAS) on the 64 matrices
+of sample 0.
 """
 
 from __future__ import annotations
@@ -355,6 +357,26 @@ def main():
         cpu = {"value": round(ns * nk / ct, 3), "unit": "eigensolves/s", "cores": threads, "kind": "oracle",
                "sample": f"{ns} samples x {nk} k-points of {wl.name} (samples 0..{ns - 1}), {ct:.1f} s",
                "cpu_model": cpu_model()}
+        # Context: the oracle on one core (the paper's one-sample-per-core
+        # regime), and LAPACK's Hermitian eigenvalues (scipy, threaded BLAS)
+        # on the oracle-built matrices of sample 0, eigenvalues only.
+        t1 = time.perf_counter()
+        oracle.level_estimate(lat, N, False, wl.p, K, K, wl.kgrid, wl.seed, 0, 1, eps, wl.delta, wl.smoother,
+                              n_threads=1)
+        c1 = time.perf_counter() - t1
+        cpu["one_core"] = {"value": round(nk / c1, 3), "unit": "eigensolves/s",
+                           "sample": f"1 sample x {nk} k-points, {c1:.1f} s"}
+        import scipy.linalg
+        mask0 = oracle.sample_vacancies(lat, N, wl.p, wl.seed, oracle.stream_tag(lat, N), 0, 1)[0]
+        kred, _ = oracle.kgrid(wl.kgrid, K)
+        Hs = [oracle.build_hamiltonian(lat, N, mask0, kred[k]) for k in range(nk)]
+        t1 = time.perf_counter()
+        for H in Hs:
+            scipy.linalg.eigvalsh(H, check_finite=False)
+        cl = time.perf_counter() - t1
+        cpu["lapack_eigvalsh"] = {"value": round(nk / cl, 3), "unit": "eigensolves/s",
+                                  "sample": f"sample 0 x {nk} k-points (assembly not timed), {cl:.1f} s",
+                                  "kind": "scipy.linalg.eigvalsh, threaded BLAS"}
 
     out = {
         "metric": METRIC,
