@@ -118,6 +118,7 @@ struct EigBuffers {
     void *Hq[kLevelSets] = {};
     double *dq[kLevelSets] = {}, *eq[kLevelSets] = {};
     void *partial = nullptr;
+    int64_t stride = 0;  // complex elements per matrix in `partial` (0: the two-stage layout's size)
 
     // The view whose H (when it has sets), d, e are set q.
     EigBuffers set(int q) const {
@@ -160,9 +161,12 @@ void carve_generalized(Carver &cv, mlmc_precision prec, int64_t ld, int64_t unit
         b.H = cv.take<void>(cplx_bytes(prec) * (size_t)ld * (size_t)ld * (size_t)units);
         b.S = cv.take<void>(cplx_bytes(prec) * (size_t)ld * (size_t)ld * (size_t)units);
     }
+    for (int q = 1; with_HS && q < sets; ++q)  // C = L^-1 H L^-H stays in H, which the chase reads
+        b.Hq[q] = cv.take<void>(cplx_bytes(prec) * (size_t)ld * (size_t)ld * (size_t)units);
     carve_tridiagonal(cv, ld, units, sets, b);
     const size_t pe = prec == MLMC_PREC_FP64 ? generalized_work_elems<double>(ld) : generalized_work_elems<float>(ld);
     b.partial = cv.take<void>(cplx_bytes(prec) * pe * (size_t)units);
+    b.stride = (int64_t)pe;  // the two-stage kernels use the same per-matrix spacing as the Cholesky ones
 }
 
 // Eigenvalues of `units` matrices already in b.H (ld > small cap).  With
@@ -180,10 +184,10 @@ mlmc_status run_chase(mlmc_precision prec, const void *H, int64_t ld, const int3
                       const EigBuffers &b, hipStream_t s, int64_t max_blocks = 0) {
     if (prec == MLMC_PREC_FP64)
         LAUNCH("chase", s, launch_band_chase<double>(static_cast<const cpx<double> *>(H), ld, n, units, b.d, b.e, ld,
-                                                     static_cast<cpx<double> *>(b.partial), s, max_blocks));
+                                                     static_cast<cpx<double> *>(b.partial), s, max_blocks, b.stride));
     else
         LAUNCH("chase", s, launch_band_chase<float>(static_cast<const cpx<float> *>(H), ld, n, units, b.d, b.e, ld,
-                                                    static_cast<cpx<float> *>(b.partial), s, max_blocks));
+                                                    static_cast<cpx<float> *>(b.partial), s, max_blocks, b.stride));
     return MLMC_OK;
 }
 
@@ -193,10 +197,10 @@ mlmc_status run_large(mlmc_precision prec, void *H, int64_t ld, const int32_t *n
                       const EigBuffers &b, hipStream_t s, bool defer_bisect = false, bool defer_chase = false) {
     if (prec == MLMC_PREC_FP64)
         LAUNCH("band_reduce", s, launch_band_reduce<double>(static_cast<cpx<double> *>(H), ld, n, units,
-                                                            static_cast<cpx<double> *>(b.partial), s));
+                                                            static_cast<cpx<double> *>(b.partial), s, b.stride));
     else
         LAUNCH("band_reduce", s, launch_band_reduce<float>(static_cast<cpx<float> *>(H), ld, n, units,
-                                                           static_cast<cpx<float> *>(b.partial), s));
+                                                           static_cast<cpx<float> *>(b.partial), s, b.stride));
     if (defer_chase) return MLMC_OK;
     const mlmc_status st = run_chase(prec, H, ld, n, units, b, s);
     if (st != MLMC_OK || defer_bisect) return st;
@@ -260,7 +264,8 @@ LevelLayout level_layout(const mlmc_lattice_s *lat, int N, bool coupled, int Kf,
 // Pencils (H, S) already in b.H, b.S -> eigenvalues (reduction to C = L^{-1}
 // H L^{-H}, then the standard path on C).
 mlmc_status run_generalized(mlmc_precision prec, void *H, void *S, int64_t ld, const int32_t *n, int64_t units,
-                            double *w, int64_t ldw, const EigBuffers &b, hipStream_t s, bool *bisect_pending = nullptr) {
+                            double *w, int64_t ldw, const EigBuffers &b, hipStream_t s, bool *bisect_pending = nullptr,
+                            bool *chase_pending = nullptr) {
     if (prec == MLMC_PREC_FP64)
         LAUNCH("overlap_reduce", s, launch_cholesky_reduce<double>(static_cast<cpx<double> *>(H), static_cast<cpx<double> *>(S), ld, n, units,
                                                             static_cast<cpx<double> *>(b.partial), s));
@@ -275,7 +280,9 @@ mlmc_status run_generalized(mlmc_precision prec, void *H, void *S, int64_t ld, c
         return MLMC_OK;
     }
     if (bisect_pending) *bisect_pending = true;
-    return run_large(prec, H, ld, n, units, w, ldw, b, s, bisect_pending != nullptr);
+    if (bisect_pending && chase_pending) *chase_pending = true;
+    return run_large(prec, H, ld, n, units, w, ldw, b, s, bisect_pending != nullptr,
+                     bisect_pending != nullptr && chase_pending != nullptr);
 }
 
 // Eigenvalues of every (outcome, k) unit of `ns` outcomes of side N.  With
@@ -299,7 +306,7 @@ mlmc_status outcome_spectra(const mlmc_lattice_s *lat, int N, const uint8_t *mas
             LAUNCH("assemble", s, launch_assemble<float>(lat->dev, N, mask, ns, kred, nk, static_cast<cpx<float> *>(b.H), ld, n_out, s, false, true));
             LAUNCH("assemble", s, launch_assemble<float>(lat->dev, N, mask, ns, kred, nk, static_cast<cpx<float> *>(b.S), ld, n_out, s, true, true));
         }
-        return run_generalized(prec, b.H, b.S, ld, n_out, units, w, ld, b, s, bisect_pending);
+        return run_generalized(prec, b.H, b.S, ld, n_out, units, w, ld, b, s, bisect_pending, chase_pending);
     }
     if (ld <= small_cap(prec)) {
         if (prec == MLMC_PREC_FP64)

@@ -483,11 +483,12 @@ struct ChaseShape<float> {
 
 template <typename T>
 hipError_t launch_band_chase(const cpx<T> *H, int64_t ld, const int32_t *n_in, int64_t batch, double *d, double *e,
-                             int64_t lde, cpx<T> *work, hipStream_t s, int64_t max_blocks) {
+                             int64_t lde, cpx<T> *work, hipStream_t s, int64_t max_blocks, int64_t stride) {
     if (batch == 0) return hipSuccess;
     if (ld > 46340) return hipErrorInvalidValue;  // element offsets into H are 32-bit
     constexpr int S = ChaseShape<T>::S, WC = ChaseShape<T>::WC;
-    const int64_t stride = (int64_t)tridiag_twostage_work_elems<T>(ld);
+    if (stride == 0) stride = (int64_t)tridiag_twostage_work_elems<T>(ld);
+    if (stride < (int64_t)tridiag_twostage_work_elems<T>(ld)) return hipErrorInvalidValue;
     const int64_t grid = (max_blocks > 0 && max_blocks < batch) ? max_blocks : batch;
     hipLaunchKernelGGL((chase_kernel<T, S, WC>), dim3((unsigned)grid), dim3(64 * S), 0, s, H, ld, n_in, batch, d, e,
                        lde, work, stride);
@@ -495,8 +496,8 @@ hipError_t launch_band_chase(const cpx<T> *H, int64_t ld, const int32_t *n_in, i
 }
 
 template hipError_t launch_band_chase<double>(const cpx<double> *, int64_t, const int32_t *, int64_t, double *,
-                                              double *, int64_t, cpx<double> *, hipStream_t, int64_t);
+                                              double *, int64_t, cpx<double> *, hipStream_t, int64_t, int64_t);
 template hipError_t launch_band_chase<float>(const cpx<float> *, int64_t, const int32_t *, int64_t, double *,
-                                             double *, int64_t, cpx<float> *, hipStream_t, int64_t);
+                                             double *, int64_t, cpx<float> *, hipStream_t, int64_t, int64_t);
 
 }  // namespace mlmc

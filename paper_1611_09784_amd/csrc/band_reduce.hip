@@ -803,9 +803,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
 
 template <typename T>
 hipError_t launch_band_reduce(cpx<T> *H, int64_t ld, const int32_t *n_in, int64_t batch, cpx<T> *work,
-                              hipStream_t s) {
+                              hipStream_t s, int64_t stride) {
     if (batch == 0) return hipSuccess;
-    const int64_t stride = (int64_t)tridiag_twostage_work_elems<T>(ld);
+    if (stride == 0) stride = (int64_t)tridiag_twostage_work_elems<T>(ld);
+    if (stride < (int64_t)tridiag_twostage_work_elems<T>(ld)) return hipErrorInvalidValue;
     const unsigned B = (unsigned)batch;
     for (int p = 0; p + kB + 1 < ld; p += kB) {
         const int64_t mmax = ld - p - kB;
@@ -863,8 +864,8 @@ template hipError_t launch_rank2k_update<float>(cpx<float> *, int64_t, const int
 template size_t tridiag_twostage_work_elems<double>(int64_t);
 template size_t tridiag_twostage_work_elems<float>(int64_t);
 template hipError_t launch_band_reduce<double>(cpx<double> *, int64_t, const int32_t *, int64_t, cpx<double> *,
-                                               hipStream_t);
+                                               hipStream_t, int64_t);
 template hipError_t launch_band_reduce<float>(cpx<float> *, int64_t, const int32_t *, int64_t, cpx<float> *,
-                                              hipStream_t);
+                                              hipStream_t, int64_t);
 
 }  // namespace mlmc

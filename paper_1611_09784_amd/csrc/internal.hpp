@@ -106,13 +106,16 @@ hipError_t launch_small_from_matrix(const cpx<T> *H, int64_t ld, const int32_t *
 // in disjoint parts (stage 1: V, X, W, T and the Hermitian product's
 // partials; the chase: the band), so that the chase of one batch may run
 // beside stage 1 of another batch on the same workspace.  The chase runs on
-// at most max_blocks workgroups (one per CU; 0: one per matrix).
+// at most max_blocks workgroups (one per CU; 0: one per matrix).  stride:
+// elements between consecutive matrices' workspaces (0: the two-stage
+// layout's own size; a caller whose other kernels use a larger per-matrix
+// workspace passes that, so that their parts stay disjoint).
 template <typename T>
 hipError_t launch_band_reduce(cpx<T> *H, int64_t ld, const int32_t *n_in, int64_t batch, cpx<T> *work,
-                              hipStream_t s);
+                              hipStream_t s, int64_t stride = 0);
 template <typename T>
 hipError_t launch_band_chase(const cpx<T> *H, int64_t ld, const int32_t *n_in, int64_t batch, double *d, double *e,
-                             int64_t lde, cpx<T> *work, hipStream_t s, int64_t max_blocks = 0);
+                             int64_t lde, cpx<T> *work, hipStream_t s, int64_t max_blocks = 0, int64_t stride = 0);
 template <typename T>
 size_t tridiag_twostage_work_elems(int64_t ld);
 // Rank-2k update A22 -= V W^H + W V^H below panel p (see band_reduce.hip).
