@@ -12,9 +12,12 @@
 //                    on the matrix cores; each wavefront also forms
 //                    V_rows^H (X T)_rows for its rows
 //   wfactor_kernel   W = X T - 1/2 V Y, Y = T^H sum over row blocks of those
-//   band_update_kernel  A22 <- Q^H A22 Q = A22 - V W^H - W V^H (lower triangle)
-// Per panel the trailing matrix is read about three times, instead of once
-// per column as in a one-stage reduction.
+//   band_update32_kernel  A22 <- Q^H A22 Q = A22 - V W^H - W V^H (lower
+//                    triangle, 32 x 64 tiles; band_update_kernel, 64 x 64
+//                    tiles, serves the generalised path's Cholesky updates)
+// Complex products on the matrix cores take three real products each.  Per
+// panel the trailing matrix is read about three times, instead of once per
+// column as in a one-stage reduction.
 #include "twostage_common.hpp"
 
 namespace mlmc {
@@ -24,7 +27,6 @@ constexpr int kHemmRows = 64;
 constexpr int kHemmDepth = 2;  // Hermitian product: register sets of its load pipeline
 constexpr int kWThreads = 256;
 constexpr int kUpdBlk = 64;
-constexpr bool kUpdate32 = true;
 
 // Workgroups are dispatched round-robin over the chip's 8 XCDs (each with its
 // own L2).  Kernels with several workgroups per matrix take their (matrix,
@@ -825,17 +827,13 @@ hipError_t launch_band_reduce(cpx<T> *H, int64_t ld, const int32_t *n_in, int64_
                            work + 2 * (int64_t)kB * ld, work, work + (int64_t)kB * ld,
                            work + hemm_partials_offset(ld), stride, p, batch, hrows);
         hipLaunchKernelGGL(wfactor_kernel<T>, dim3(B), dim3(kWThreads), 0, s, n_in, ld, work, stride, p);
-        if (kUpdate32) {
-            const int64_t nb32 = (mmax + kUpdBlk / 2 - 1) / (kUpdBlk / 2), ha = (nb32 - 1) / 2;
-            // tiles of rows 0 .. nb32 - 1: pairs of rows (2a, 2a + 1) hold 2 (a + 1) tiles
-            const int64_t ntile = (nb32 % 2 == 0) ? (ha + 1) * (ha + 2) : (ha + 1) * (ha + 1);
-            hipLaunchKernelGGL(band_update32_kernel<T>, dim3(xcd_grid(batch, ntile)), dim3(256), 0, s, H, ld, n_in,
-                               work, stride, p, batch, ntile, 2);
-        } else {
-            const int64_t nblk = (mmax + kUpdBlk - 1) / kUpdBlk, ntile = nblk * (nblk + 1) / 2;
-            hipLaunchKernelGGL(band_update_kernel<T>, dim3(xcd_grid(batch, ntile)), dim3(256), 0, s, H, ld, n_in,
-                               work, stride, p, batch, ntile, 2);
-        }
+        // The rank-2k update in 32 x 64 tiles (small enough to share a CU with
+        // a chase workgroup).  Lower tiles of row blocks 0 .. nb32 - 1: pairs of
+        // row blocks (2a, 2a + 1) hold 2 (a + 1) tiles.
+        const int64_t nb32 = (mmax + kUpdBlk / 2 - 1) / (kUpdBlk / 2), ha = (nb32 - 1) / 2;
+        const int64_t ntile = (nb32 % 2 == 0) ? (ha + 1) * (ha + 2) : (ha + 1) * (ha + 1);
+        hipLaunchKernelGGL(band_update32_kernel<T>, dim3(xcd_grid(batch, ntile)), dim3(256), 0, s, H, ld, n_in, work,
+                           stride, p, batch, ntile, 2);
         const hipError_t err = hipGetLastError();
         if (err != hipSuccess) return err;
     }
