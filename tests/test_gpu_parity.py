@@ -174,6 +174,23 @@ def test_batched_eigvalsh_fp64(B, gdev, mdev, name, N, p, K):
     check_eigs(w, oracle_eigs(Hc, nc), nc, 1e-9)
 
 
+@pytest.mark.parametrize("name,N,ns", [("graphene", 32, 1), ("mos2", 8, 2)])
+def test_batched_eigvalsh_large_n(B, gdev, mdev, name, N, ns):
+    """The largest matrices of the MLMC hierarchies (graphene N = 32, n ~ 2000,
+    the finest level of the graphene workload; MoS2-shaped N = 8, n ~ 700):
+    panels of more than 512 rows go through the global-memory panel QR, and
+    the chase streams the band through its ring for hundreds of batches."""
+    say(f"[eigvalsh large n] {name} N={N}")
+    dl = pick(name, gdev, mdev)
+    mask = B.mlmc_sample_vacancies(dl, N, 0.02, 17, dl.tag(N), 0, ns)
+    kred, _ = B.mlmc_kgrid(1, 1)
+    H, n = B.mlmc_build_hamiltonians(dl, N, mask, kred, B.MLMC_C128)
+    Hc = H.cpu().numpy()
+    nc = n.cpu().numpy()
+    w = B.mlmc_batched_eigvalsh(H, n).cpu().numpy()
+    check_eigs(w, oracle_eigs(Hc, nc), nc, 1e-9)
+
+
 @pytest.mark.parametrize("ld,sizes", [(64, [0, 1, 2, 3, 17, 64]), (128, [128, 127, 5]), (200, [200, 199, 1, 2, 130]),
                                       (300, [3, 300, 257]), (700, [700, 531, 2, 650])])
 def test_batched_eigvalsh_random_ragged(B, ld, sizes):
@@ -195,7 +212,8 @@ def test_batched_eigvalsh_random_ragged(B, ld, sizes):
     check_eigs(w, ref, sizes, 1e-9)
 
 
-@pytest.mark.parametrize("name,N,K", [("graphene", 4, 2), ("mos2", 4, 1), ("graphene", 12, 1), ("graphene", 16, 1)])
+@pytest.mark.parametrize("name,N,K", [("graphene", 4, 2), ("mos2", 4, 1), ("graphene", 12, 1), ("graphene", 16, 1),
+                                      ("graphene", 32, 1)])   # n ~ 2000: the FP32 chase leaves its ring
 def test_batched_eigvalsh_mixed(B, gdev, mdev, name, N, K):
     say(f"[eigvalsh mixed] {name} N={N} K={K}")
     dl = pick(name, gdev, mdev)
