@@ -10,7 +10,10 @@ One step = one call of ``mlmc_level_estimate`` over a batch of samples: vacancy
 sampling, k-grid, H(k) assembly, Householder tridiagonalisation, Sturm
 bisection, smoothed IDoS and the level sums, all on the GPU with inputs and
 workspace already resident.  The default 8 steps x 250 samples cover exactly
-the 2000 samples of the workload.
+the 2000 samples of the workload.  Consecutive steps alternate between two
+caller streams (``--streams 1``: one), so that a step's first chunk is reduced
+while the previous step's last chunk is chased and bisected; every step's work
+is inside the timed region.
 
 Prints one JSON line.  ``value`` is eigensolves per second of the whole job.
 ``roofline`` reports the single kernel with the largest share, the
@@ -139,6 +142,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=250, help="samples per step")
     ap.add_argument("--chunk", type=int, default=32, help="samples per internal pass (workspace size)")
+    ap.add_argument("--streams", type=int, default=2, choices=[1, 2],
+                    help="caller streams the steps alternate over (2: a step starts beside the previous "
+                         "step's last chase and bisection)")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--workload", default="graphene_n16_mc")
     ap.add_argument("--cpu-baseline", dest="cpu_baseline", action="store_true", default=True)
@@ -264,9 +270,16 @@ def main():
     need = B.mlmc_level_workspace(dlat, N, False, K, K, wl.kgrid, args.chunk, prec, eps.size)
     work = torch.empty((need,), dtype=torch.uint8, device=dev)
     stats = torch.zeros((4, eps.size), dtype=torch.float64, device=dev)
-    stream = torch.cuda.current_stream()
+    # Consecutive steps are consecutive level-estimate calls on one workspace;
+    # on alternating streams the library lets a call's front part start while
+    # the previous call's last chunk is still chased and bisected (the sums
+    # are still added in call order).
+    streams = [torch.cuda.current_stream()] + [torch.cuda.Stream(dev) for _ in range(args.streams - 1)]
+    calls = [0]
 
     def step(first):
+        stream = streams[calls[0] % len(streams)]
+        calls[0] += 1
         B.mlmc_level_estimate(dlat, N, False, wl.p, K, K, wl.kgrid, wl.seed, first, args.batch, d_eps, wl.delta,
                               wl.smoother, prec, stats=stats, work=work, stream=stream)
 
@@ -394,7 +407,7 @@ def main():
         "config": {"workload": wl.name, "lattice": wl.lattice, "N": N, "p": wl.p, "K": K,
                    "kgrid": "monkhorst-pack" if wl.kgrid == 0 else "gamma", "n_eps": int(eps.size),
                    "delta": wl.delta, "samples_per_step": args.batch, "eigensolves_per_step": args.batch * nk,
-                   "precision": args.precision},
+                   "precision": args.precision, "caller_streams": args.streams},
         "samples_per_s": round(args.steps * args.batch / elapsed, 3),
         "kernels_ms": kernels,
         "dominant_kernel": roofline["kernel"] if roofline else dom,

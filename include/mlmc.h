@@ -262,7 +262,17 @@ mlmc_status mlmc_level_workspace(mlmc_lattice lat, int32_t N_fine, int32_t coupl
  * ends).  The work is ordered by events, `stream` waits for the library's
  * streams before the call returns, and the sums are added in sample order as
  * on one stream.  Calls on one device enqueue one at a time (a process-wide
- * lock) and share those streams, so their bisections run one after another.
+ * lock) and share those streams, so their bisections run one after another
+ * and their sums are added in the order of the calls.  The workspace may be
+ * handed from one call to the next on another stream without synchronising:
+ * a call starts after the previous call's front part, and reuses a buffer
+ * set only after the previous call has released it, so consecutive calls on
+ * alternating streams with the same workspace, lattice, sizes, precision and
+ * chunk overlap (one call's last chase and bisection beside the next call's
+ * first reduction; a call on another stream than the previous one with the
+ * same layout also leaves its last chunk's chase on the mlmc_chase_cus share
+ * instead of the whole device); with any other layout a call waits for all
+ * earlier calls' work.  Other work that uses the workspace is the caller's to order.
  * Errors: N_fine < 1, coupled with odd N_fine, K < 1, p outside [0, 1],
  * delta <= 0, workspace too small for one sample. */
 mlmc_status mlmc_level_estimate(mlmc_lattice lat, int32_t N_fine, int32_t coupled, double p, int32_t K_fine,

@@ -212,7 +212,10 @@ mlmc_status run_large(mlmc_precision prec, void *H, int64_t ld, const int32_t *n
 // eigenvalues come in kLevelSets sets, used by chunks in turn, so that one
 // chunk's chase, bisection and IDoS overlap the reduction of the next ones.
 struct LevelLayout {
-    double *kf = nullptr, *kwf = nullptr, *kc = nullptr, *kwc = nullptr;
+    // k-points and weights per set: a chunk rewrites its set's copy only after
+    // the back stream has released the set, so a following call with the same
+    // layout never writes a k-grid that an earlier chunk's IDoS still reads.
+    double *kf[kLevelSets] = {}, *kwf[kLevelSets] = {}, *kc[kLevelSets] = {}, *kwc[kLevelSets] = {};
     uint8_t *mask = nullptr, *quarters = nullptr;
     int32_t *nf[kLevelSets] = {}, *nc[kLevelSets] = {};
     double *wf[kLevelSets] = {}, *wc[kLevelSets] = {};
@@ -232,8 +235,10 @@ LevelLayout level_layout(const mlmc_lattice_s *lat, int N, bool coupled, int Kf,
     const int G = lat->dev.n_groups, no = lat->dev.n_orb;
     const int64_t nkf = kgrid_count(kind, Kf), nkc = kgrid_count(kind, Kc);
     const int64_t ldf = (int64_t)no * N * N;
-    L.kf = cv.take<double>(sizeof(double) * 2 * nkf);
-    L.kwf = cv.take<double>(sizeof(double) * nkf);
+    for (int q = 0; q < kLevelSets; ++q) {
+        L.kf[q] = cv.take<double>(sizeof(double) * 2 * nkf);
+        L.kwf[q] = cv.take<double>(sizeof(double) * nkf);
+    }
     L.mask = cv.take<uint8_t>((size_t)mc * N * N * G);
     for (int q = 0; q < kLevelSets; ++q) {
         L.nf[q] = cv.take<int32_t>(sizeof(int32_t) * (size_t)(mc * nkf));
@@ -246,8 +251,10 @@ LevelLayout level_layout(const mlmc_lattice_s *lat, int N, bool coupled, int Kf,
     if (coupled) {
         const int h = N / 2;
         const int64_t ldc = (int64_t)no * h * h;
-        L.kc = cv.take<double>(sizeof(double) * 2 * nkc);
-        L.kwc = cv.take<double>(sizeof(double) * nkc);
+        for (int q = 0; q < kLevelSets; ++q) {
+            L.kc[q] = cv.take<double>(sizeof(double) * 2 * nkc);
+            L.kwc[q] = cv.take<double>(sizeof(double) * nkc);
+        }
         L.quarters = cv.take<uint8_t>((size_t)mc * 4 * h * h * G);
         for (int q = 0; q < kLevelSets; ++q) {
             L.nc[q] = cv.take<int32_t>(sizeof(int32_t) * (size_t)(mc * 4 * nkc));
@@ -340,6 +347,25 @@ struct BackStream {
     hipEvent_t freed[kLevelSets] = {};  // back -> front: set q of the matrices / sizes / tridiagonals /
                                         // eigenvalues is free
     hipEvent_t end = nullptr;     // back -> caller's stream
+    bool created = false;         // streams and events all created
+    // The previous level estimate's workspace layout and the set its next
+    // chunk would use.  A call with the same layout continues the rotation:
+    // each of its chunks waits only for the release of its own set (and its
+    // first for the previous call's front part), so it may start while the
+    // previous call's last chunks are still chased and bisected.
+    struct LayoutKey {
+        const void *work = nullptr;
+        int64_t mc = 0, nkf = 0, nkc = 0;
+        int n_orb = 0, n_groups = 0, N = 0, n_eps = 0, prec = 0;
+        bool cpl = false, gen = false;
+        bool operator==(const LayoutKey &o) const {
+            return work == o.work && mc == o.mc && nkf == o.nkf && nkc == o.nkc && n_orb == o.n_orb &&
+                   n_groups == o.n_groups && N == o.N && n_eps == o.n_eps && prec == o.prec && cpl == o.cpl &&
+                   gen == o.gen;
+        }
+    } last;
+    int next_set = 0;
+    hipStream_t last_stream = nullptr;  // the previous call's stream
 };
 constexpr int kMaxDevices = 64;
 std::mutex g_back_mu;  // held while a level estimate enqueues its work
@@ -361,7 +387,7 @@ hipError_t back_stream(BackStream **out) {
     if (err != hipSuccess) return err;
     if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
     BackStream &b = g_back[dev];
-    if (!b.s) {
+    if (!b.created) {
         // One bisection workgroup per CU leaves the rest of each CU to the
         // next chunk's reduction on the caller's stream (measured best among
         // 1/4 to 8 per CU on the graphene N = 16 workload).
@@ -370,13 +396,18 @@ hipError_t back_stream(BackStream **out) {
         if (err != hipSuccess) return err;
         b.bisect_blocks = cus > 0 ? cus : 1;
         b.chase_blocks = chase_cus(cus);
-        err = hipStreamCreateWithFlags(&b.s, hipStreamNonBlocking);
-        if (err == hipSuccess) err = hipStreamCreateWithFlags(&b.sc, hipStreamNonBlocking);
-        hipEvent_t *evs[4] = {&b.begin, &b.ready, &b.chased, &b.end};
-        for (int i = 0; i < 4 && err == hipSuccess; ++i) err = hipEventCreateWithFlags(evs[i], hipEventDisableTiming);
-        for (int q = 0; q < kLevelSets && err == hipSuccess; ++q)
-            err = hipEventCreateWithFlags(&b.freed[q], hipEventDisableTiming);
+        // (What a failed attempt did create is kept and the rest tried again.)
+        if (!b.s) err = hipStreamCreateWithFlags(&b.s, hipStreamNonBlocking);
+        if (err == hipSuccess && !b.sc) err = hipStreamCreateWithFlags(&b.sc, hipStreamNonBlocking);
+        hipEvent_t *evs[4 + kLevelSets] = {&b.begin, &b.ready, &b.chased, &b.end};
+        for (int q = 0; q < kLevelSets; ++q) evs[4 + q] = &b.freed[q];
+        for (hipEvent_t *ev : evs)
+            if (err == hipSuccess && !*ev) err = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+        // Every event a level estimate waits for has been recorded at least once.
+        if (err == hipSuccess) err = hipEventRecord(b.ready, b.s);
+        if (err == hipSuccess) err = hipEventRecord(b.chased, b.s);
         if (err != hipSuccess) return err;
+        b.created = true;
     }
     *out = &b;
     return hipSuccess;
@@ -754,39 +785,85 @@ mlmc_status mlmc_level_estimate(mlmc_lattice lat, int32_t N, int32_t coupled, do
     // Three streams: the caller's (front) samples, assembles and reduces
     // chunk c (on the two-stage path: stage 1 only); the chase stream chases
     // chunk c's bands on 3/4 of the CUs while the front goes on with chunk
-    // c + 1; the back stream runs chunk c's bisection, IDoS and level sums.  Matrices (two-stage path), sizes, tridiagonals and eigenvalues
+    // c + 1; the back stream runs chunk c's bisection, IDoS and level sums.
+    // Matrices (two-stage path), k-grids, sizes, tridiagonals and eigenvalues
     // come in kLevelSets sets used in turn; the front waits until the back
-    // has released a set before refilling it.
+    // has released a set before refilling it.  The sample masks and the
+    // stage-1 workspace are the front's alone, the band workspace the chase
+    // stream's, the per-sample IDoS the back stream's.
     std::lock_guard<std::mutex> lk(g_back_mu);
     BackStream *bk = nullptr;
     HIP_TRY(back_stream(&bk), "level: back stream");
     hipStream_t sb = bk->s, sc = bk->sc;
-    HIP_TRY(hipEventRecord(bk->begin, s), "level: event");
-    HIP_TRY(hipStreamWaitEvent(sb, bk->begin, 0), "level: wait");
-    for (int q = 0; q < kLevelSets; ++q) HIP_TRY(hipEventRecord(bk->freed[q], sb), "level: event");
-    LAUNCH("kgrid", s, launch_kgrid(kind, Kf, L.kf, L.kwf, s));
-    if (cpl) LAUNCH("kgrid", s, launch_kgrid(kind, Kc, L.kc, L.kwc, s));
-    int64_t chunk = 0;
-    for (int64_t done = 0; done < M; done += mc, ++chunk) {
+    BackStream::LayoutKey key;
+    key.work = d_work;
+    key.mc = mc;
+    key.nkf = nkf;
+    key.nkc = nkc;
+    key.n_orb = lat->dev.n_orb;
+    key.n_groups = G;
+    key.N = N;
+    key.n_eps = n_eps;
+    key.prec = (int)prec;
+    key.cpl = cpl;
+    key.gen = lat->dev.n_ovl > 0;
+    // The previous call's front part (masks, stage-1 workspace, the last
+    // chunk's matrices) is complete before this call's front starts.
+    HIP_TRY(hipStreamWaitEvent(s, bk->ready, 0), "level: wait");
+    // Same layout on another stream than the previous call: the caller
+    // alternates streams, so the next call is likely to start beside this
+    // one's last chunk, which then keeps the chase stream's share of the CUs.
+    const bool overlapping = key == bk->last && s != bk->last_stream;
+    bk->last_stream = s;
+    if (!(key == bk->last)) {
+        // Another layout may overlap any of the previous call's buffers: all
+        // sets count as released only after everything enqueued so far.
+        bk->last = BackStream::LayoutKey{};
+        HIP_TRY(hipEventRecord(bk->begin, s), "level: event");
+        HIP_TRY(hipStreamWaitEvent(sb, bk->begin, 0), "level: wait");
+        for (int q = 0; q < kLevelSets; ++q) HIP_TRY(hipEventRecord(bk->freed[q], sb), "level: event");
+        bk->last = key;
+        bk->next_set = 0;
+    }
+    // A call that fails part-way makes the next one take the path above, with
+    // the front and chase work it did enqueue covered by `ready` and the back
+    // stream.
+    struct FailGuard {
+        BackStream *bk;
+        hipStream_t s;
+        bool ok = false;
+        ~FailGuard() {
+            if (ok) return;
+            bk->last = BackStream::LayoutKey{};
+            (void)hipEventRecord(bk->chased, bk->sc);
+            (void)hipStreamWaitEvent(bk->s, bk->chased, 0);
+            (void)hipEventRecord(bk->ready, s);
+        }
+    } guard{bk, s};
+    for (int64_t done = 0; done < M; done += mc) {
         const int64_t ns = (M - done < mc) ? (M - done) : mc;
-        const int q = (int)(chunk % kLevelSets);
+        const int q = bk->next_set;
+        bk->next_set = (q + 1) % kLevelSets;
         HIP_TRY(hipStreamWaitEvent(s, bk->freed[q], 0), "level: wait");
+        LAUNCH("kgrid", s, launch_kgrid(kind, Kf, L.kf[q], L.kwf[q], s));
+        if (cpl) LAUNCH("kgrid", s, launch_kgrid(kind, Kc, L.kc[q], L.kwc[q], s));
         LAUNCH("sample_vacancies", s, launch_sample_vacancies(lat->dev, N, thr, seed, tag, first_sample + done, ns, L.mask, s));
         bool pend_f = false, pend_c = false, chase_f = false, chase_c = false;
         const EigBuffers bf = L.bf.set(q), bc = L.bc.set(q);
-        st = outcome_spectra(lat, N, L.mask, ns, L.kf, nkf, prec, L.wf[q], L.nf[q], bf, s, &pend_f, &chase_f);
+        st = outcome_spectra(lat, N, L.mask, ns, L.kf[q], nkf, prec, L.wf[q], L.nf[q], bf, s, &pend_f, &chase_f);
         if (st != MLMC_OK) return st;
         if (cpl) {
             LAUNCH("partition", s, launch_partition(N, G, L.mask, ns, L.quarters, s));
-            st = outcome_spectra(lat, h, L.quarters, ns * 4, L.kc, nkc, prec, L.wc[q], L.nc[q], bc, s, &pend_c,
+            st = outcome_spectra(lat, h, L.quarters, ns * 4, L.kc[q], nkc, prec, L.wc[q], L.nc[q], bc, s, &pend_c,
                                  &chase_c);
             if (st != MLMC_OK) return st;
         }
         HIP_TRY(hipEventRecord(bk->ready, s), "level: event");
         HIP_TRY(hipStreamWaitEvent(sb, bk->ready, 0), "level: wait");
         // The last chunk's chase and bisection have nothing left to run
-        // beside: they take the whole device (one workgroup per matrix).
-        const bool last = done + ns >= M;
+        // beside (unless the calls overlap): they take the whole device (one
+        // workgroup per matrix).
+        const bool last = !overlapping && done + ns >= M;
         const int64_t chase_blocks = last ? 0 : bk->chase_blocks, bisect_blocks = last ? 0 : bk->bisect_blocks;
         if (chase_f || chase_c) {
             HIP_TRY(hipStreamWaitEvent(sc, bk->ready, 0), "level: wait");
@@ -805,19 +882,20 @@ mlmc_status mlmc_level_estimate(mlmc_lattice lat, int32_t N, int32_t coupled, do
             st = run_bisect(L.nf[q], ldf, ns * nkf, L.wf[q], ldf, bf, sb, bisect_blocks);
             if (st != MLMC_OK) return st;
         }
-        LAUNCH("idos", sb, launch_idos(L.wf[q], ldf, L.nf[q], ns, nkf, L.kwf, inv_area_f, d_eps, n_eps, delta,
+        LAUNCH("idos", sb, launch_idos(L.wf[q], ldf, L.nf[q], ns, nkf, L.kwf[q], inv_area_f, d_eps, n_eps, delta,
                              (int)smoother, L.If, sb));
         if (cpl) {
             if (pend_c) {
                 st = run_bisect(L.nc[q], ldc, ns * 4 * nkc, L.wc[q], ldc, bc, sb, bisect_blocks);
                 if (st != MLMC_OK) return st;
             }
-            LAUNCH("idos", sb, launch_idos(L.wc[q], ldc, L.nc[q], ns * 4, nkc, L.kwc, inv_area_c, d_eps, n_eps, delta,
+            LAUNCH("idos", sb, launch_idos(L.wc[q], ldc, L.nc[q], ns * 4, nkc, L.kwc[q], inv_area_c, d_eps, n_eps, delta,
                                  (int)smoother, L.Ic, sb));
         }
         LAUNCH("level_stats", sb, launch_level_stats(L.If, cpl ? L.Ic : nullptr, ns, n_eps, d_stats, sb));
         HIP_TRY(hipEventRecord(bk->freed[q], sb), "level: event");
     }
+    guard.ok = true;
     HIP_TRY(hipEventRecord(bk->end, sb), "level: event");
     HIP_TRY(hipStreamWaitEvent(s, bk->end, 0), "level: wait");
     return MLMC_OK;

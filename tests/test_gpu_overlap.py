@@ -114,6 +114,36 @@ def test_overlap_level_parity(B, odev, N, coupled, K, Kc, kind, prec, chunk):
     assert np.abs(got[2] - want[2]).max() <= M * tol
 
 
+def test_overlap_level_alternating_streams(B, odev):
+    """Consecutive level calls of the overlap model on one workspace,
+    alternating between two streams (the Cholesky-reduction workspace shared
+    by the chunks of both calls): bit-identical to the same calls on one
+    stream, and the oracle's sums over all samples."""
+    say("[overlap level, alternating streams]")
+    eps = energy_grid(-9.0, 18.0, 201)
+    N, K, kind, prec = 16, 1, 1, 0
+    d_eps = torch.as_tensor(eps, device=DEV)
+    need = B.mlmc_level_workspace(odev, N, False, K, K, kind, 1, prec, eps.size)
+    work = torch.empty((need,), dtype=torch.uint8, device=DEV)
+    calls = [(0, 2), (2, 2), (4, 1)]
+
+    def run(streams):
+        stats = torch.zeros((4, eps.size), dtype=torch.float64, device=DEV)
+        torch.cuda.synchronize()
+        for i, (first, M) in enumerate(calls):
+            B.mlmc_level_estimate(odev, N, False, 0.1, K, K, kind, 31, first, M, d_eps, 0.1, prec=prec, stats=stats,
+                                  work=work, stream=streams[i % len(streams)])
+        torch.cuda.synchronize()
+        return stats.cpu().numpy()
+
+    one = run([torch.cuda.current_stream()])
+    two = run([torch.cuda.current_stream(), torch.cuda.Stream(DEV)])
+    assert np.array_equal(one, two)
+    want = oracle.level_estimate(odev.lat, N, False, 0.1, K, K, kind, 31, 0, 5, eps, 0.1, 0, n_threads=8)
+    assert np.abs(two[0] - want[0]).max() <= 5 * 1e-10
+    assert np.abs(two[2] - want[2]).max() <= 5 * 1e-10
+
+
 def test_overlap_errors(B):
     d = B.DeviceLattice(graphene(), 0)
     try:

@@ -335,6 +335,52 @@ def test_level_estimate_pipelined_chunks(B, gdev, mdev, name, N, coupled, K, Kc,
     compare_stats(got, want, M, 1e-10 if prec == 0 else 1e-5)
 
 
+# (first sample, M) of consecutive calls with 2-sample chunks: a ragged
+# three-chunk call, calls continuing the set rotation, a one-sample call (a
+# smaller chunk: another layout of the same workspace), and calls after it.
+STREAM_CALLS = [(0, 5), (5, 3), (8, 4), (12, 1), (13, 5), (18, 2)]
+
+
+def run_level_calls(B, dl, N, coupled, K, Kc, kind, prec, eps, streams, work, calls=STREAM_CALLS, seed=929):
+    d_eps = torch.as_tensor(eps, device=DEV)
+    stats = torch.zeros((4, eps.size), dtype=torch.float64, device=DEV)
+    torch.cuda.synchronize()
+    for i, (first, M) in enumerate(calls):
+        B.mlmc_level_estimate(dl, N, coupled, 0.1, K, Kc, kind, seed, first, M, d_eps, 0.1, prec=prec, stats=stats,
+                              work=work, stream=streams[i % len(streams)])
+    torch.cuda.synchronize()
+    return stats.cpu().numpy()
+
+
+@pytest.mark.parametrize("name,N,coupled,K,Kc,kind,prec", [
+    ("graphene", 16, False, 1, 1, 0, 0),   # two-stage path: chase, bisection on the library's streams
+    ("graphene", 16, True, 1, 2, 1, 1),    # mixed precision, coupled (coarse side fused)
+    ("mos2", 4, True, 1, 2, 1, 0),         # MoS2-shaped fine n=176 on the two-stage path
+])
+def test_level_estimate_calls_on_alternating_streams(B, gdev, mdev, name, N, coupled, K, Kc, kind, prec):
+    """Consecutive calls on one workspace, alternating between two streams
+    with no synchronisation between them, so that a call may start beside the
+    previous call's last chase and bisection.  The sums equal bit for bit
+    those of the same calls on one stream (both add them in call order), and
+    the oracle's over all samples."""
+    say(f"[level_estimate alternating streams] {name} N={N} coupled={coupled} prec={prec}")
+    dl = pick(name, gdev, mdev)
+    if name == "graphene":
+        eps = energy_grid(-9.0, 9.0, 201)
+    else:
+        b = dl.lat.hop_magnitude_bound() + 1.0
+        eps = energy_grid(-b, b, 201)
+    need = B.mlmc_level_workspace(dl, N, coupled, K, Kc, kind, 2, prec, eps.size)
+    work = torch.empty((need,), dtype=torch.uint8, device=DEV)
+    one = run_level_calls(B, dl, N, coupled, K, Kc, kind, prec, eps, [torch.cuda.current_stream()], work)
+    two = run_level_calls(B, dl, N, coupled, K, Kc, kind, prec, eps, [torch.cuda.current_stream(),
+                                                                      torch.cuda.Stream(DEV)], work)
+    assert np.array_equal(one, two)
+    M = sum(m for _, m in STREAM_CALLS)
+    want = oracle.level_estimate(dl.lat, N, coupled, 0.1, K, Kc, kind, 929, 0, M, eps, 0.1, 0, n_threads=8)
+    compare_stats(two, want, M, 1e-10 if prec == 0 else 1e-5)
+
+
 def test_chase_cus(B):
     """The chase of a level estimate occupies 3/4 of the CUs in either precision."""
     cus = torch.cuda.get_device_properties(0).multi_processor_count
