@@ -101,9 +101,9 @@ int small_cap(mlmc_precision prec) { return prec == MLMC_PREC_FP64 ? kSmallMaxF6
 int large_cap(mlmc_precision prec) { return prec == MLMC_PREC_FP64 ? kLargeMaxF64 : kLargeMaxF32; }
 size_t cplx_bytes(mlmc_precision prec) { return prec == MLMC_PREC_FP64 ? 16 : 8; }
 
-// Buffer sets of a pipelined level estimate: chunk c uses set c % kLevelSets,
-// so that the caller's stream can start chunk c + 2 while chunk c is still
-// being chased and bisected (graphene N = 16, FP64: 22.83k eigensolves/s
+// Buffer sets of a pipelined level estimate: chunks take the sets in turn
+// (continuing across calls with one layout), so that the caller's stream can
+// start chunk c + 2 while chunk c is still being chased and bisected (graphene N = 16, FP64: 22.83k eigensolves/s
 // against 22.73k with two sets; one more set of matrices, 8.6 GB there).
 constexpr int kLevelSets = 3;
 

@@ -201,6 +201,29 @@ __device__ __forceinline__ int sturm_count(const double *d, const double *e2, in
     return c;
 }
 
+// The count of sturm_count and, in dx, the Newton correction -f/f' at x for
+// f(x) = det(T - x I) = prod q_i: f'/f = sum q_i'/q_i with q_i' = -1 +
+// e2_{i-1} q_{i-1}' / q_{i-1}^2, carried along the same pivots.
+__device__ __forceinline__ int sturm_count_newton(const double *d, const double *e2, int n, double x, double pivmin,
+                                                  double *dx) {
+    double q = d[0] - x;
+    if (fabs(q) < pivmin) q = -pivmin;
+    int c = q < 0.0 ? 1 : 0;
+    double r = sturm_recip(q), dq = -1.0, s = -r;
+#pragma unroll 4
+    for (int i = 1; i < n; ++i) {
+        const double t = e2[i - 1] * r;
+        dq = fma(t * r, dq, -1.0);
+        q = fma(-e2[i - 1], r, d[i] - x);
+        if (fabs(q) < pivmin) q = -pivmin;
+        c += q < 0.0 ? 1 : 0;
+        r = sturm_recip(q);
+        s = fma(dq, r, s);
+    }
+    *dx = -1.0 / s;
+    return c;
+}
+
 // Absolute width at which an eigenvalue's bracket is final (eV): far below
 // what the smoothed IDoS resolves (a shift dE of one eigenvalue moves I by at
 // most dE g'_max / (delta N^2 |F|)).
@@ -208,9 +231,21 @@ constexpr double kBisectAbsTol = 1e-12;
 
 // All eigenvalues of (d, e) by bisection on Sturm counts, in double
 // precision.  The Gershgorin interval is first cut at blockDim.x points
-// (one count per thread); each eigenvalue index i then bisects its own
-// sub-interval until its width reaches kBisectAbsTol (or a few ulps of the
-// spectral radius, if that is larger).
+// (one count per thread).  Thread t then takes eigenvalues t, t + blockDim.x,
+// ... in turn, narrowing a bracket [lo, hi] with count(lo) <= i < count(hi)
+// until its width reaches kBisectAbsTol (or a few ulps of the spectral
+// radius, if that is larger).  Each count also gives the Newton correction
+// of det(T - x I), scaled by the number m of eigenvalues in the bracket (the
+// step to an m-fold root, also right for a tight cluster).  The next point
+// is the Newton iterate while it lies inside the bracket and each correction
+// at least halves the previous one, the midpoint otherwise; a correction
+// below 0.45 of the final width is followed by counts at the iterate -/+
+// that much, which close the bracket around it.  Every point only moves a
+// side of a bracket that the counts certify, so the result has the bound of
+// plain bisection; on the honeycomb tridiagonals the slowest thread makes
+// about a third of the counts.  One count per loop turn, at whatever point
+// each thread chose, keeps the threads of a wavefront in step; a thread
+// moves on to its next eigenvalue as soon as one is done.
 // e is squared in place.  w[i] = i-th smallest eigenvalue.
 // cnt holds blockDim.x + 1 ints of LDS.
 __device__ inline void bisect_block(const double *d, double *e, int n, double *w, double *red, int *cnt) {
@@ -238,21 +273,74 @@ __device__ inline void bisect_block(const double *d, double *e, int n, double *w
     cnt[t + 1] = (t + 1 == nt) ? n : sturm_count(d, e, n, gl + step * (t + 1), pivmin);
     if (t == 0) cnt[0] = 0;
     __syncthreads();
-    for (int i = t; i < n; i += nt) {
+    int i = t;
+    double lo = 0.0, hi = 0.0, xn = NAN, dxprev = INFINITY, xc = 0.0, h = 0.0;
+    int clo = 0, chi = 0, mode = 0, its = 0;  // mode 1 / 2: count at xc - h / xc + h next
+    auto start = [&]() {
         int a = 0, b = nt;  // find g with cnt[g] <= i < cnt[g + 1]
         while (b - a > 1) {
             const int mid = (a + b) >> 1;
             if (cnt[mid] <= i) a = mid; else b = mid;
         }
-        double lo = gl + step * a, hi = (a + 1 == nt) ? gu : gl + step * (a + 1);
-        for (int it = 0; it < 128; ++it) {
-            const double width = hi - lo;
-            if (width <= fmax(atol, 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)))) break;
-            const double mid = lo + 0.5 * width;
-            if (mid <= lo || mid >= hi) break;
-            if (sturm_count(d, e, n, mid, pivmin) > i) hi = mid; else lo = mid;
+        lo = gl + step * a;
+        hi = (a + 1 == nt) ? gu : gl + step * (a + 1);
+        clo = cnt[a];
+        chi = cnt[a + 1];
+        xn = NAN;
+        dxprev = INFINITY;
+        mode = 0;
+        its = 0;
+    };
+    if (i < n) start();
+    while (i < n) {
+        const double width = hi - lo;
+        const double tolw = fmax(atol, 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)));
+        const double mid = lo + 0.5 * width;
+        bool done = width <= tolw || its >= 128;
+        double x = mid;
+        int kind = 0;  // 0 midpoint, 1 Newton iterate, 2 / 3 closing counts
+        if (!done) {
+            if (mode == 1) {
+                if (xc - h > lo && xc - h < hi) { x = xc - h; kind = 2; } else mode = 2;
+            }
+            if (mode == 2 && kind == 0) {
+                if (xc + h > lo && xc + h < hi) { x = xc + h; kind = 3; } else mode = 0;
+            }
+            if (mode == 0 && kind == 0) {
+                if (xn > lo && xn < hi) { x = xn; kind = 1; }
+                else if (mid <= lo || mid >= hi) done = true;
+            }
         }
-        w[i] = lo + 0.5 * (hi - lo);
+        if (done) {
+            w[i] = lo + 0.5 * (hi - lo);
+            i += nt;
+            if (i < n) start();
+            continue;
+        }
+        double dx;
+        const int c = sturm_count_newton(d, e, n, x, pivmin, &dx);
+        ++its;
+        if (c > i) { hi = x; chi = c; } else { lo = x; clo = c; }
+        const double st = (double)(chi - clo) * dx;
+        if (kind == 2) {
+            mode = 2;
+        } else if (kind == 3) {
+            mode = 0;
+            xn = NAN;
+        } else if (kind == 1) {
+            xn = (fabs(st) <= 0.5 * dxprev) ? x + st : NAN;
+            dxprev = fabs(st);
+            const double h0 = 0.45 * tolw;
+            if (fabs(st) <= h0) {
+                xc = x + st;
+                h = h0;
+                mode = 1;
+                xn = NAN;
+            }
+        } else {
+            xn = x + st;
+            dxprev = INFINITY;
+        }
     }
 }
 
