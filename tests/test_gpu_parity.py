@@ -212,6 +212,44 @@ def test_batched_eigvalsh_random_ragged(B, ld, sizes):
     check_eigs(w, ref, sizes, 1e-9)
 
 
+def clustered_spectrum(m, rng):
+    """m eigenvalues with the structures a bisection with Newton steps has to
+    get right: exact multiplicities (four-fold levels, a three-fold zero), a
+    cluster 1e-13 wide, a pair 1e-9 apart, and simple random values."""
+    lam = [0.0, 0.0, 0.0, 1.0, 1.0 + 1e-13, 1.0 + 2e-13, 2.5, 2.5 + 1e-9]
+    levels = [-3.2, -1.1, 0.7, 4.4]
+    for v in levels:
+        lam += [v] * 4
+    lam += list(rng.uniform(-6.0, 6.0, size=max(0, m - len(lam))))
+    return np.sort(np.array(lam[:m]))
+
+
+@pytest.mark.parametrize("ld,sizes,prec", [(128, [96, 40], 0), (400, [333, 128, 250], 0), (400, [333, 250], 1)])
+def test_batched_eigvalsh_clustered_spectra(B, ld, sizes, prec):
+    """H = U diag(lam) U^H with a random unitary U and a spectrum lam known by
+    construction (clustered_spectrum): the fused path (n <= 128) and the
+    two-stage path, FP64 and mixed, against lam itself."""
+    say(f"[eigvalsh clustered] ld={ld} sizes={sizes} prec={prec}")
+    rng = np.random.default_rng(ld + len(sizes))
+    Hs = np.zeros((len(sizes), ld, ld), np.complex128)
+    want = []
+    for u, m in enumerate(sizes):
+        lam = clustered_spectrum(m, rng)
+        Q, _ = np.linalg.qr(rng.normal(size=(m, m)) + 1j * rng.normal(size=(m, m)))
+        A = (Q * lam) @ Q.conj().T
+        A = 0.5 * (A + A.conj().T)
+        Hs[u, :m, :m] = A.T
+        want.append(lam)
+    n = torch.as_tensor(np.array(sizes, np.int32), device=DEV)
+    if prec == 0:
+        w = B.mlmc_batched_eigvalsh(torch.as_tensor(Hs, device=DEV), n).cpu().numpy()
+        check_eigs(w, want, sizes, 1e-11)
+    else:
+        H = torch.as_tensor(Hs, device=DEV).to(torch.complex64)
+        w = B.mlmc_batched_eigvalsh(H, n, prec=B.MLMC_PREC_MIXED).cpu().numpy()
+        check_eigs(w, want, sizes, 2e-5)
+
+
 @pytest.mark.parametrize("name,N,K", [("graphene", 4, 2), ("mos2", 4, 1), ("graphene", 12, 1), ("graphene", 16, 1),
                                       ("graphene", 32, 1)])   # n ~ 2000: the FP32 chase leaves its ring
 def test_batched_eigvalsh_mixed(B, gdev, mdev, name, N, K):
