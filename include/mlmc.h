@@ -191,7 +191,9 @@ mlmc_status mlmc_eigvalsh_workspace(mlmc_dtype dtype, mlmc_precision prec, int64
  * eigensolve of each H(k), Section 4.2; E_n(k) is the n-th smallest
  * eigenvalue, Section 4.3).  Householder reduction to real tridiagonal form
  * (LDS-resident for ld <= 128 complex128 / 180 complex64, else in device
- * memory), then Sturm-count bisection in double precision.
+ * memory), then Sturm-count bisection in double precision (Newton points
+ * inside the certified brackets; each eigenvalue within 1e-12 eV, or a few
+ * ulps of the spectral radius if that is larger).
  * d_H: [batch][ld][ld] column-major, only the lower triangle of the leading
  * n_b x n_b block is read; it is overwritten.  d_n: [batch] sides, each in
  * [0, ld] (a matrix with n_b outside that range gets NaN eigenvalues).
