@@ -103,8 +103,9 @@ size_t cplx_bytes(mlmc_precision prec) { return prec == MLMC_PREC_FP64 ? 16 : 8;
 
 // Buffer sets of a pipelined level estimate: chunks take the sets in turn
 // (continuing across calls with one layout), so that the caller's stream can
-// start chunk c + 2 while chunk c is still being chased and bisected (graphene N = 16, FP64: 22.83k eigensolves/s
-// against 22.73k with two sets; one more set of matrices, 8.6 GB there).
+// start chunk c + 2 while chunk c is still being chased and bisected
+// (graphene N = 16, FP64: 22.83k eigensolves/s against 22.73k with two sets;
+// one more set of matrices, 8.6 GB there).
 constexpr int kLevelSets = 3;
 
 // Buffers of the device-memory eigen path for `units` matrices of side bound ld.
