@@ -46,7 +46,7 @@ typedef void *mlmc_stream; /* a hipStream_t */
 typedef enum {
     MLMC_OK = 0,
     MLMC_ERR_INVALID_ARG = -1, /* an argument is out of range or inconsistent       */
-    MLMC_ERR_UNSUPPORTED = -2, /* valid request this build does not implement       */
+    MLMC_ERR_UNSUPPORTED = -2, /* valid request the library does not implement      */
     MLMC_ERR_WORKSPACE = -3,   /* workspace pointer NULL or smaller than required    */
     MLMC_ERR_HIP = -4          /* the HIP runtime reported an error (detail string)  */
 } mlmc_status;

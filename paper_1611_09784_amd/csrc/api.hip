@@ -731,7 +731,7 @@ static mlmc_status check_level_args(mlmc_lattice lat, int32_t N, int32_t coupled
     if (prec != MLMC_PREC_FP64 && prec != MLMC_PREC_MIXED) return fail(MLMC_ERR_INVALID_ARG, "level: bad precision");
     const int64_t nmax = (int64_t)lat->dev.n_orb * N * N;
     if (nmax > large_cap(prec))
-        return fail(MLMC_ERR_UNSUPPORTED, "level: %lld orbitals exceed the %d supported by this build", (long long)nmax,
+        return fail(MLMC_ERR_UNSUPPORTED, "level: %lld orbitals exceed the %d the library supports", (long long)nmax,
                     large_cap(prec));
     if (lat->dev.n_ovl > 0 && nmax > kGenMax)
         return fail(MLMC_ERR_UNSUPPORTED, "level: the overlap (generalised) path supports at most %d orbitals", kGenMax);
