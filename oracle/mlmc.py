@@ -40,6 +40,9 @@ def optimal_samples(V, W, C_alpha: float, theta: float, tol: float) -> np.ndarra
 
 
 def statistical_error(V, M, C_alpha: float) -> float:
+    """C_alpha times the standard deviation of the MLMC estimator, sqrt(sum_l
+    V_l / M_l), for independent levels with variances V_l and M_l samples
+    (Section 2.2)."""
     V = np.asarray(V, dtype=np.float64)
     M = np.asarray(M, dtype=np.float64)
     return C_alpha * math.sqrt(float(np.sum(V / M)))
@@ -85,13 +88,22 @@ def dos_from_idos(eps, idos):
 
 
 def run_mlmc(lat, levels, Ks, p, kind, seed, eps, delta, smoother, tol_rel, C_alpha=2.0, theta=0.5,
-             pilot=16, max_rounds=8, n_threads=1, max_samples=None):
+             pilot=16, max_rounds=8, n_threads=1, max_samples=None, level_fn=None, cost_fn=None):
     """Adaptive-sample MLMC driver over fixed levels (eq. (MLMC) + eq. (opt_samples)).
 
     Level 1 is the plain IDoS on the coarsest supercell; level l >= 2 couples
     the N_l supercell with the mean of its four quarters on the N_{l-1} grid.
-    Returns a dict with the estimate, per-level sums, sample counts and the
-    final statistical error."""
+    Each round adds samples up to the target counts, forms the sample means
+    and variances (V_l = largest variance over the energies), the estimate
+    (sum of the level means) and the statistical error C_alpha sqrt(sum V_l /
+    M_l); it stops once that error is at most theta * TOL_abs (TOL_abs = tol_rel
+    * max |estimate|), otherwise it allocates the next targets by eq.
+    (opt_samples) with the measured cost per sample W_l.
+
+    level_fn(l, first, count) -> [4][n_eps] sums replaces the oracle's own
+    level estimate (the default draws and solves the outcomes); cost_fn(l)
+    -> seconds per sample replaces the measured time.  Returns a dict with the
+    estimate, per-level sums, sample counts and the final statistical error."""
     L = len(levels)
     ne = len(eps)
     stats = [np.zeros((4, ne)) for _ in range(L)]
@@ -107,9 +119,12 @@ def run_mlmc(lat, levels, Ks, p, kind, seed, eps, delta, smoother, tol_rel, C_al
             if add <= 0:
                 continue
             t0 = time.perf_counter()
-            coupled = l > 0
-            st = level_estimate(lat, levels[l], coupled, p, Ks[l], Ks[l - 1] if coupled else Ks[l], kind,
-                                seed, M[l], add, eps, delta, smoother, n_threads=n_threads)
+            if level_fn is not None:
+                st = level_fn(l, M[l], add)
+            else:
+                coupled = l > 0
+                st = level_estimate(lat, levels[l], coupled, p, Ks[l], Ks[l - 1] if coupled else Ks[l], kind,
+                                    seed, M[l], add, eps, delta, smoother, n_threads=n_threads)
             secs[l] += time.perf_counter() - t0
             stats[l] += st
             M[l] += add
@@ -119,11 +134,11 @@ def run_mlmc(lat, levels, Ks, p, kind, seed, eps, delta, smoother, tol_rel, C_al
             mean, var = mean_and_var(stats[l], M[l])
             means.append(mean)
             V.append(max(float(var.max()), 1e-300))
-        W = [secs[l] / M[l] for l in range(L)]
+        W = [cost_fn(l) if cost_fn is not None else secs[l] / M[l] for l in range(L)]
         estimate = np.sum(means, axis=0)
         tol_abs = tol_rel * float(np.max(np.abs(estimate)))
         err = statistical_error(V, M, C_alpha)
-        history.append((list(M), err, tol_abs))
+        history.append({"M": list(M), "V": list(V), "W": list(W), "error": err, "tol_abs": tol_abs})
         if err <= theta * tol_abs:
             break
         Mopt = optimal_samples(V, W, C_alpha, theta, tol_abs)

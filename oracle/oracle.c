@@ -675,15 +675,34 @@ int ora_level_estimate(const ora_lattice *L, int32_t N, int32_t coupled, double 
         level_job *jobs = (level_job *)calloc((size_t)n_threads, sizeof(level_job));
         pthread_t *th = (pthread_t *)calloc((size_t)n_threads, sizeof(pthread_t));
         if (!jobs || !th) st = ORA_ERR_NOMEM;
+        /* Thread t takes samples t, t + n_threads, ... */
+        int started = 0;
         for (int t = 0; st == ORA_OK && t < n_threads; ++t) {
             level_job j = {L, N, coupled, K_fine, K_coarse, kind, n_eps, smoother, delta, eps, masks,
                            M, groups, t, n_threads, Qf, Qq, ORA_OK};
             jobs[t] = j;
-            pthread_create(&th[t], NULL, level_worker, &jobs[t]);
         }
         for (int t = 0; st == ORA_OK && t < n_threads; ++t) {
-            pthread_join(th[t], NULL);
-            if (jobs[t].status != ORA_OK) st = jobs[t].status;
+            if (pthread_create(&th[t], NULL, level_worker, &jobs[t]) != 0) break;
+            ++started;
+        }
+        if (st == ORA_OK && started < n_threads) {
+            /* Not every thread started: join those that did, then run every
+             * sample again on this thread alone (the results do not depend
+             * on the split). */
+            for (int t = 0; t < started; ++t) pthread_join(th[t], NULL);
+            started = 0;
+            level_job j = {L, N, coupled, K_fine, K_coarse, kind, n_eps, smoother, delta, eps, masks,
+                           M, groups, 0, 1, Qf, Qq, ORA_OK};
+            jobs[0] = j;
+            level_worker(&jobs[0]);
+            st = jobs[0].status;
+        } else {
+            /* Join every started thread before reading any status or freeing
+             * the buffers they use. */
+            for (int t = 0; t < started; ++t) pthread_join(th[t], NULL);
+            for (int t = 0; st == ORA_OK && t < started; ++t)
+                if (jobs[t].status != ORA_OK) st = jobs[t].status;
         }
         free(jobs); free(th);
     }
