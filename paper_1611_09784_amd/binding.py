@@ -36,7 +36,7 @@ MLMC_SMOOTH_CUBIC = 1
 
 # Largest matrix side of the LDS-resident fused path / of the device-memory path.
 SMALL_MAX = {MLMC_PREC_FP64: 128, MLMC_PREC_MIXED: 180}
-LARGE_MAX = {MLMC_PREC_FP64: 2048, MLMC_PREC_MIXED: 4096}
+LARGE_MAX = {MLMC_PREC_FP64: 16384, MLMC_PREC_MIXED: 16384}
 
 
 class MLMCError(RuntimeError):

@@ -156,10 +156,13 @@ __global__ __launch_bounds__(kGenThreads) void hegst_a_kernel(cpx<T> *__restrict
 }
 
 // Second half of panel p: A21 <- A21 - 1/2 L21 C11, then C21 = L22^{-1} A21.
-// Thread t holds rows s + t + kTrsmThreads i (i < RPT) of the panel in
-// registers; the substitution runs over 16-row blocks q of L22: the block's
-// rows are multiplied by the block's inverse, then every row below subtracts
-// L[r, q..q+15] times the block's solution.
+// The rows below the panel are taken in segments of RPT * kTrsmThreads rows:
+// thread t holds rows g + t + kTrsmThreads i (i < RPT) of segment g in
+// registers.  The substitution runs over 16-row blocks q of L22: rows of
+// earlier segments are already solved and stored in H, so their block of the
+// solution is read back from H; a block inside the segment is first
+// multiplied by the inverse of its diagonal block; then every row of the
+// segment below the block subtracts L[r, q..q+15] times the block's solution.
 template <typename T, int RPT>
 __global__ __launch_bounds__(kTrsmThreads) void hegst_b_kernel(cpx<T> *__restrict__ Hall,
                                                                 const cpx<T> *__restrict__ Sall, int64_t ld,
@@ -169,7 +172,7 @@ __global__ __launch_bounds__(kTrsmThreads) void hegst_b_kernel(cpx<T> *__restric
     const int64_t u = blockIdx.x;
     const int n = n_in[u];
     const int s = p + kB;
-    if (n < 0 || n > ld || s >= n || n - s > RPT * kTrsmThreads) return;
+    if (n < 0 || n > ld || s >= n) return;
     const int t = threadIdx.x;
     const cpx<T> zero = {T(0), T(0)};
     cpx<T> *H = Hall + u * ld * ld;
@@ -182,80 +185,94 @@ __global__ __launch_bounds__(kTrsmThreads) void hegst_b_kernel(cpx<T> *__restric
         X[r0][c0] = zero;
     }
     __syncthreads();
-    cpx<T> a[RPT][kB];
-#pragma unroll
-    for (int i = 0; i < RPT; ++i) {
-        const int r = s + t + kTrsmThreads * i;
-        const bool own = r < n;
-        cpx<T> l[kB];
-#pragma unroll
-        for (int k = 0; k < kB; ++k) {
-            a[i][k] = own ? H[r + (int64_t)(p + k) * ld] : zero;
-            l[k] = own ? S[r + (int64_t)(p + k) * ld] : zero;
-        }
-#pragma unroll
-        for (int j = 0; j < kB; ++j) {
-            cpx<T> q = zero;
-#pragma unroll
-            for (int k = 0; k < kB; ++k) q = c_add(q, c_mul(l[k], C11[k][j]));
-            a[i][j] = c_sub(a[i][j], c_scale(T(0.5), q));
-        }
-    }
-    for (int q0 = s; q0 < n; q0 += kB) {
-        const int qb = min(kB, n - q0);
-        if (t < kB * kB) LiB[t % kB][t / kB] = Lblk[(int64_t)(q0 / kB) * kB * kB + (t % kB) * kB + t / kB];
+    constexpr int kSeg = RPT * kTrsmThreads;
+    for (int g = s; g < n; g += kSeg) {
+        cpx<T> a[RPT][kB];
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
-            const int r = s + t + kTrsmThreads * i;
-            if (r >= q0 && r < q0 + qb) {
+            const int r = g + t + kTrsmThreads * i;
+            const bool own = r < n;
+            cpx<T> l[kB];
 #pragma unroll
-                for (int j = 0; j < kB; ++j) X[r - q0][j] = a[i][j];
+            for (int k = 0; k < kB; ++k) {
+                a[i][k] = own ? H[r + (int64_t)(p + k) * ld] : zero;
+                l[k] = own ? S[r + (int64_t)(p + k) * ld] : zero;
+            }
+#pragma unroll
+            for (int j = 0; j < kB; ++j) {
+                cpx<T> q = zero;
+#pragma unroll
+                for (int k = 0; k < kB; ++k) q = c_add(q, c_mul(l[k], C11[k][j]));
+                a[i][j] = c_sub(a[i][j], c_scale(T(0.5), q));
             }
         }
-        __syncthreads();
+        for (int q0 = s; q0 < n; q0 += kB) {
+            const int qb = min(kB, n - q0);
+            if (q0 < g) {
+                // a block solved in an earlier segment: its solution is in H
+                if (t < kB * kB) {
+                    const int r0 = t % kB, c0 = t / kB;
+                    X[r0][c0] = (r0 < qb) ? H[(q0 + r0) + (int64_t)(p + c0) * ld] : zero;
+                }
+                __syncthreads();
+            } else {
+                if (t < kB * kB) LiB[t % kB][t / kB] = Lblk[(int64_t)(q0 / kB) * kB * kB + (t % kB) * kB + t / kB];
 #pragma unroll
-        for (int i = 0; i < RPT; ++i) {
-            const int r = s + t + kTrsmThreads * i;
-            if (r >= q0 && r < q0 + qb) {
+                for (int i = 0; i < RPT; ++i) {
+                    const int r = g + t + kTrsmThreads * i;
+                    if (r >= q0 && r < q0 + qb) {
 #pragma unroll
-                for (int j = 0; j < kB; ++j) {
-                    cpx<T> x = zero;
+                        for (int j = 0; j < kB; ++j) X[r - q0][j] = a[i][j];
+                    }
+                }
+                __syncthreads();
 #pragma unroll
-                    for (int k = 0; k < kB; ++k) x = c_add(x, c_mul(LiB[r - q0][k], X[k][j]));
-                    a[i][j] = x;
+                for (int i = 0; i < RPT; ++i) {
+                    const int r = g + t + kTrsmThreads * i;
+                    if (r >= q0 && r < q0 + qb) {
+#pragma unroll
+                        for (int j = 0; j < kB; ++j) {
+                            cpx<T> x = zero;
+#pragma unroll
+                            for (int k = 0; k < kB; ++k) x = c_add(x, c_mul(LiB[r - q0][k], X[k][j]));
+                            a[i][j] = x;
+                        }
+                    }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int i = 0; i < RPT; ++i) {
+                    const int r = g + t + kTrsmThreads * i;
+                    if (r >= q0 && r < q0 + qb) {
+#pragma unroll
+                        for (int j = 0; j < kB; ++j) X[r - q0][j] = a[i][j];
+                    }
+                }
+                __syncthreads();
+            }
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                const int r = g + t + kTrsmThreads * i;
+                if (r >= q0 + qb && r < n) {
+                    for (int k = 0; k < qb; ++k) {
+                        const cpx<T> lk = S[r + (int64_t)(q0 + k) * ld];
+#pragma unroll
+                        for (int j = 0; j < kB; ++j) a[i][j] = c_sub(a[i][j], c_mul(lk, X[k][j]));
+                    }
                 }
             }
+            __syncthreads();
+            if (q0 + qb >= g + kSeg) break;  // the rest of the rows belong to later segments
         }
-        __syncthreads();
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
-            const int r = s + t + kTrsmThreads * i;
-            if (r >= q0 && r < q0 + qb) {
+            const int r = g + t + kTrsmThreads * i;
+            if (r < n) {
 #pragma unroll
-                for (int j = 0; j < kB; ++j) X[r - q0][j] = a[i][j];
+                for (int j = 0; j < kB; ++j) H[r + (int64_t)(p + j) * ld] = a[i][j];
             }
         }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < RPT; ++i) {
-            const int r = s + t + kTrsmThreads * i;
-            if (r >= q0 + qb && r < n) {
-                for (int k = 0; k < qb; ++k) {
-                    const cpx<T> lk = S[r + (int64_t)(q0 + k) * ld];
-#pragma unroll
-                    for (int j = 0; j < kB; ++j) a[i][j] = c_sub(a[i][j], c_mul(lk, X[k][j]));
-                }
-            }
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int i = 0; i < RPT; ++i) {
-        const int r = s + t + kTrsmThreads * i;
-        if (r < n) {
-#pragma unroll
-            for (int j = 0; j < kB; ++j) H[r + (int64_t)(p + j) * ld] = a[i][j];
-        }
+        __syncthreads();  // this segment's solution is in H before the next segment reads it
     }
 }
 

@@ -67,9 +67,10 @@ struct DevLattice {
 // Largest pristine matrix side handled by the LDS-resident fused kernel.
 constexpr int kSmallMaxF64 = 128;
 constexpr int kSmallMaxF32 = 180;
-// Largest matrix side of the device-memory reduction.
-constexpr int kLargeMaxF64 = 2048;
-constexpr int kLargeMaxF32 = 4096;
+// Largest matrix side of the device-memory reduction (the largest pristine
+// supercell the assembly accepts).
+constexpr int kLargeMaxF64 = 16384;
+constexpr int kLargeMaxF32 = 16384;
 // Gaussian smoothing is evaluated for |x| < kGaussCut and is exactly 0 / 1 beyond.
 constexpr double kGaussCut = 10.0;
 
@@ -127,7 +128,7 @@ hipError_t launch_rank2k_update(cpx<T> *H, int64_t ld, const int32_t *n_in, int6
 // (lower), H <- L^{-1} H L^{-H} in place (lower triangle).  Workspace per
 // matrix: generalized_work_elems complex elements.  Supported for
 // ld <= kGenMax.
-constexpr int kGenMax = 1024;
+constexpr int kGenMax = 2048;
 template <typename T>
 size_t generalized_work_elems(int64_t ld);
 template <typename T>
@@ -135,8 +136,9 @@ hipError_t launch_cholesky_reduce(cpx<T> *H, cpx<T> *S, int64_t ld, const int32_
                                   hipStream_t s);
 
 // Sturm-count bisection of (d, e) -> ascending eigenvalues; at most
-// max_blocks workgroups (0: one per matrix).
-hipError_t launch_bisect(const double *d, const double *e, int64_t lde, const int32_t *n_in, int64_t batch,
+// max_blocks workgroups (0: one per matrix).  e is overwritten when ld_max
+// exceeds the LDS staging limit (it is squared in place).
+hipError_t launch_bisect(const double *d, double *e, int64_t lde, const int32_t *n_in, int64_t batch,
                          int64_t ld_max, double *w, int64_t ldw, hipStream_t s, int64_t max_blocks = 0);
 
 hipError_t launch_idos(const double *w, int64_t ldw, const int32_t *n, int64_t n_samples, int n_k,

@@ -10,16 +10,21 @@ namespace mlmc {
 // (a bisection running beside other kernels keeps to a few workgroups per CU).
 // ---------------------------------------------------------------------------
 constexpr int kBisectThreads = 256;
+// Largest matrix side whose d and e^2 are staged in LDS (16 bytes per row);
+// larger tridiagonals are read from device memory where they lie (e is
+// squared in place there).
+constexpr int64_t kBisectLdsMaxLd = 8192;
 
+template <bool GLOBAL>
 __global__ __launch_bounds__(kBisectThreads) void bisect_kernel(const double *__restrict__ dall,
-                                                                const double *__restrict__ eall, int64_t lde,
+                                                                double *__restrict__ eall, int64_t lde,
                                                                 const int32_t *__restrict__ n_in, int64_t batch,
                                                                 int64_t ld_max, double *__restrict__ w, int64_t ldw) {
     extern __shared__ __align__(16) unsigned char smem[];
     double *red = reinterpret_cast<double *>(smem);
     int *cnt = reinterpret_cast<int *>(red + 32);
-    double *d = reinterpret_cast<double *>(cnt + kBisectThreads + 8);
-    double *e = d + ld_max;
+    double *dl = reinterpret_cast<double *>(cnt + kBisectThreads + 8);
+    double *el = dl + ld_max;
     for (int64_t u = blockIdx.x; u < batch; u += gridDim.x) {
         const int n = n_in[u];
         double *wu = w + u * ldw;
@@ -27,9 +32,16 @@ __global__ __launch_bounds__(kBisectThreads) void bisect_kernel(const double *__
             for (int64_t i = threadIdx.x; i < ldw && i < ld_max; i += blockDim.x) wu[i] = NAN;
             continue;
         }
-        for (int i = threadIdx.x; i < n; i += blockDim.x) {
-            d[i] = dall[u * lde + i];
-            e[i] = (i + 1 < n) ? eall[u * lde + i] : 0.0;
+        const double *d = dl;
+        double *e = el;
+        if constexpr (GLOBAL) {
+            d = dall + u * lde;
+            e = eall + u * lde;
+        } else {
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                dl[i] = dall[u * lde + i];
+                el[i] = (i + 1 < n) ? eall[u * lde + i] : 0.0;
+            }
         }
         __syncthreads();
         bisect_block(d, e, n, wu, red, cnt);
@@ -37,16 +49,23 @@ __global__ __launch_bounds__(kBisectThreads) void bisect_kernel(const double *__
     }
 }
 
-hipError_t launch_bisect(const double *d, const double *e, int64_t lde, const int32_t *n_in, int64_t batch,
+hipError_t launch_bisect(const double *d, double *e, int64_t lde, const int32_t *n_in, int64_t batch,
                          int64_t ld_max, double *w, int64_t ldw, hipStream_t s, int64_t max_blocks) {
     if (batch == 0) return hipSuccess;
-    const size_t lds = 32 * sizeof(double) + (kBisectThreads + 8) * sizeof(int) + 2 * sizeof(double) * (size_t)ld_max;
-    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(bisect_kernel),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const bool global = ld_max > kBisectLdsMaxLd;
+    const size_t lds = 32 * sizeof(double) + (kBisectThreads + 8) * sizeof(int) +
+                       (global ? 0 : 2 * sizeof(double) * (size_t)ld_max);
+    const void *fn = global ? reinterpret_cast<const void *>(bisect_kernel<true>)
+                            : reinterpret_cast<const void *>(bisect_kernel<false>);
+    hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (err != hipSuccess) return err;
     const int64_t blocks = (max_blocks > 0 && max_blocks < batch) ? max_blocks : batch;
-    hipLaunchKernelGGL(bisect_kernel, dim3((unsigned)blocks), dim3(kBisectThreads), lds, s, d, e, lde, n_in, batch,
-                       ld_max, w, ldw);
+    if (global)
+        hipLaunchKernelGGL(bisect_kernel<true>, dim3((unsigned)blocks), dim3(kBisectThreads), lds, s, d, e, lde, n_in,
+                           batch, ld_max, w, ldw);
+    else
+        hipLaunchKernelGGL(bisect_kernel<false>, dim3((unsigned)blocks), dim3(kBisectThreads), lds, s, d, e, lde, n_in,
+                           batch, ld_max, w, ldw);
     return hipGetLastError();
 }
 

@@ -62,7 +62,7 @@ def test_validation_without_device(B):
     out = C.c_size_t()
     # unsupported dtype / precision pairs and oversize matrices are rejected up front
     assert lib.mlmc_eigvalsh_workspace(B.MLMC_C128, B.MLMC_PREC_MIXED, 64, 1, C.byref(out)) == B.MLMC_ERR_UNSUPPORTED
-    assert lib.mlmc_eigvalsh_workspace(B.MLMC_C128, B.MLMC_PREC_FP64, 4096, 1, C.byref(out)) == B.MLMC_ERR_UNSUPPORTED
+    assert lib.mlmc_eigvalsh_workspace(B.MLMC_C128, B.MLMC_PREC_FP64, 16385, 1, C.byref(out)) == B.MLMC_ERR_UNSUPPORTED
     assert lib.mlmc_eigvalsh_workspace(B.MLMC_C128, B.MLMC_PREC_FP64, 64, 10, C.byref(out)) == B.MLMC_OK
     assert out.value == 0  # fused LDS path needs no workspace
     assert lib.mlmc_eigvalsh_workspace(B.MLMC_C128, B.MLMC_PREC_FP64, 512, 10, C.byref(out)) == B.MLMC_OK
@@ -104,7 +104,7 @@ def test_kgrid_points_host_only(B):
 def test_generalized_workspace_limits(B):
     out = C.c_size_t()
     lib = B.lib()
-    assert lib.mlmc_generalized_workspace(B.MLMC_C128, B.MLMC_PREC_FP64, 1025, 1, C.byref(out)) == \
+    assert lib.mlmc_generalized_workspace(B.MLMC_C128, B.MLMC_PREC_FP64, 2049, 1, C.byref(out)) == \
         B.MLMC_ERR_UNSUPPORTED
     assert lib.mlmc_generalized_workspace(B.MLMC_C128, B.MLMC_PREC_FP64, 64, 3, C.byref(out)) == B.MLMC_OK
     assert out.value > 0                    # the generalised path always needs its workspace

@@ -153,3 +153,48 @@ def test_overlap_errors(B):
             B.mlmc_build_overlaps(d, 2, mask, kred)
     finally:
         d.close()
+
+
+@pytest.mark.timeout(900)
+def test_generalized_eigvalsh_n32_overlap_model(B, odev):
+    """The overlap model at the size of the paper's bi-level graphene run
+    (32 x 32 supercell, ld = 2048): the panel substitution of the reduction to
+    standard form runs in two 1024-row segments.  One outcome, one k-point,
+    against the oracle (Cholesky + Householder + QR)."""
+    N = 32
+    say("[generalized N=32 overlap model, ld=2048]")
+    mask = B.mlmc_sample_vacancies(odev, N, 0.02, 13, odev.tag(N), 0, 1)
+    kred = torch.as_tensor(np.array([[0.0, 0.0]]), device=DEV)
+    H, n = B.mlmc_build_hamiltonians(odev, N, mask, kred)
+    S, _ = B.mlmc_build_overlaps(odev, N, mask, kred)
+    nc = n.cpu().numpy()
+    Hc, Sc = H.cpu().numpy()[0].T[: nc[0], : nc[0]], S.cpu().numpy()[0].T[: nc[0], : nc[0]]
+    w = B.mlmc_batched_eigvalsh_generalized(H, S, n).cpu().numpy()
+    want = oracle.eigvalsh_generalized(np.ascontiguousarray(Hc), np.ascontiguousarray(Sc))
+    check_eigs(w, [want], nc, 1e-9)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_generalized_eigvalsh_random_pencils_two_segments(B, prec):
+    """Random pencils above 1024 rows (ld 1500): the substitution's second
+    segment reads the first segment's solution back from H."""
+    ld, sizes = 1500, [1500, 1100]
+    say(f"[generalized random two segments] ld={ld} prec={prec}")
+    rng = np.random.default_rng(99 + prec)
+    Hs = np.zeros((len(sizes), ld, ld), np.complex128)
+    Ss = np.zeros((len(sizes), ld, ld), np.complex128)
+    want = []
+    for u, m in enumerate(sizes):
+        A = rng.normal(size=(m, m)) + 1j * rng.normal(size=(m, m))
+        A = (A + A.conj().T) / 2
+        E = rng.normal(size=(m, m)) + 1j * rng.normal(size=(m, m))
+        Sm = np.eye(m) + 0.3 * (E @ E.conj().T) / m
+        Hs[u, :m, :m] = A.T
+        Ss[u, :m, :m] = Sm.T
+        want.append(scipy.linalg.eigh(A, Sm, eigvals_only=True))
+    tdt = torch.complex128 if prec == 0 else torch.complex64
+    H = torch.as_tensor(Hs, device=DEV).to(tdt)
+    S = torch.as_tensor(Ss, device=DEV).to(tdt)
+    n = torch.as_tensor(np.array(sizes, np.int32), device=DEV)
+    w = B.mlmc_batched_eigvalsh_generalized(H, S, n).cpu().numpy()
+    check_eigs(w, want, sizes, 1e-9 if prec == 0 else 5e-5)

@@ -491,8 +491,8 @@ def test_error_codes(B, gdev):
     with pytest.raises(B.MLMCError) as e:
         B.mlmc_level_estimate(gdev, 4, False, 0.1, 1, 1, 1, 0, 0, 1, eps, 0.1, work=small)
     assert e.value.status == B.MLMC_ERR_WORKSPACE
-    with pytest.raises(B.MLMCError) as e:
-        B.mlmc_level_estimate(gdev, 64, False, 0.1, 1, 1, 1, 0, 0, 1, eps, 0.1)
+    with pytest.raises(B.MLMCError) as e:  # 2 * 128^2 orbitals: above the 16384 the library supports
+        B.mlmc_level_workspace(gdev, 128, False, 1, 1, 1, 1, B.MLMC_PREC_FP64, 11)
     assert e.value.status == B.MLMC_ERR_UNSUPPORTED
 
 
