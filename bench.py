@@ -15,9 +15,14 @@ caller streams (``--streams 1``: one), so that a step's first chunk is reduced
 while the previous step's last chunk is chased and bisected; every step's work
 is inside the timed region.
 
-Prints one JSON line.  ``value`` is eigensolves per second of the whole job.
+Prints one JSON line.  ``value`` is eigensolves per second of the whole job
+on the FP64 path; ``mixed`` holds the same measurement of the mixed path
+(complex64 reduction and chase, FP64 bisection, IDoS and sums), run in the
+same process after it.  Kernel durations come from HIP event pairs that the
+level calls' pipeline context creates before the timed region and records
+around each launch inside it (``mlmc_context_timer``).
 ``roofline`` reports the single kernel with the largest share, the
-band-to-tridiagonal chase, timed with HIP events on the library's stream
+band-to-tridiagonal chase, timed with HIP events on the stream it runs on
 during the timed region, against the vector ALU peak: algorithmic flops per
 launch (``chase_flops``) over the average launch duration, with its
 algorithmic HBM bytes (``chase_bytes``) alongside.  The chase runs on 3/4 of
@@ -27,9 +32,11 @@ lengthens each launch but shortens the whole job; ``traffic`` is the HBM
 bytes per launch measured with rocprofv3 counters (recorded in profiles/ with
 the hash of the kernel source, null if the source has changed since).
 ``time_to_tol`` runs the MLMC estimator of the graphene level hierarchy to
-TOL = 1e-3 with the FP64 and the mixed path.  ``cpu_baseline`` times the FP64 C
-oracle (unchanged) on a bounded number of samples of the same workload on the
-host cores, with two context lines: the oracle on one core and one sample,
+TOL = 1e-3 with the FP64 and the mixed path, and states each path's IDoS
+error per level against the FP64 oracle on the same coupled samples.
+``cpu_baseline`` times the FP64 C oracle (unchanged) on a bounded number of
+samples of the same workload on the host cores (``nproc`` and the CPU model
+recorded), with two context lines: the oracle on one core and one sample,
 and LAPACK's Hermitian eigenvalues (scipy, threaded BLAS) on the 64 matrices
 of sample 0.
 """
@@ -145,7 +152,9 @@ def parse():
     ap.add_argument("--streams", type=int, default=2, choices=[1, 2],
                     help="caller streams the steps alternate over (2: a step starts beside the previous "
                          "step's last chase and bisection)")
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64", help="precision of `value`")
+    ap.add_argument("--no-second", dest="second", action="store_false", default=True,
+                    help="skip the measurement of the other precision")
     ap.add_argument("--workload", default="graphene_n16_mc")
     ap.add_argument("--cpu-baseline", dest="cpu_baseline", action="store_true", default=True)
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
@@ -176,9 +185,9 @@ def time_to_tol(B, dev):
     with the FP64 path, the mixed path (FP32 reduction, FP64 bisection and
     sums), and the mixed path that solves each distinct outcome of the two
     smallest supercells once (identical outcomes identified beforehand).
-    Beside each time: the per-level samples, the final statistical error, and
-    for the mixed path the largest IDoS difference from the FP64 path on the
-    same 8 coupled samples of every level."""
+    Beside each time: the per-level samples and the final statistical error;
+    then each path's IDoS error against the FP64 oracle on the same coupled
+    samples of every level (8, or 4 at N = 32)."""
     import torch
     from mlmc_inputs import WORKLOADS
     from mlmc_inputs.configs import workload_eps
@@ -198,6 +207,7 @@ def time_to_tol(B, dev):
             est.add_samples(st, 2)
         torch.cuda.synchronize(dev)
         r = D.run_mlmc(est, wl.levels, Ks, wl.tol)
+        est.close()
         out[name] = {"seconds": round(r.seconds, 3), "M": [st.M for st in r.levels], "error": r.error,
                      "tol_abs": r.tol_abs, "rounds": len(r.rounds),
                      "seconds_per_level": [round(st.seconds, 3) for st in r.levels]}
@@ -205,17 +215,25 @@ def time_to_tol(B, dev):
             out[name]["distinct_outcomes_solved"] = est.unique_solved
         print(f"[bench] time-to-TOL {name}: {r.seconds:.2f} s, M = {[st.M for st in r.levels]}", file=sys.stderr,
               flush=True)
-    # precision error of the mixed path: same samples, both precisions
-    errs = []
+    # IDoS error of each path against the FP64 oracle on the same coupled
+    # samples of every level (the oracle's level sums of those samples)
+    import oracle
+    errs = {"fp64": [], "mixed": []}
+    samples = []
     for l, st in enumerate(D.make_levels(wl.levels, Ks)):
-        q = {}
+        ns = 4 if st.N >= 32 else 8
+        samples.append(ns)
+        want = oracle.level_estimate(lat, st.N, st.coupled, wl.p, st.K, st.K_coarse, wl.kgrid, wl.seed, 0, ns, eps,
+                                     wl.delta, wl.smoother, n_threads=host_threads())
         for name, prec in (("fp64", B.MLMC_PREC_FP64), ("mixed", B.MLMC_PREC_MIXED)):
             est = D.Estimator(dlat, eps, wl.delta, wl.p, wl.kgrid, wl.seed, wl.smoother, prec, chunk_samples=8)
             lv = D.make_levels(wl.levels, Ks)[l]
-            est.add_samples(lv, 8)
-            q[name] = lv.stats[[0, 2]] / lv.M  # mean Y and mean Q_f
-        errs.append(float(np.max(np.abs(q["mixed"] - q["fp64"]))))
-    out["mixed_idos_err_per_level"] = errs
+            est.add_samples(lv, ns)
+            est.close()
+            # per-sample mean of Y and of Q_f, against the oracle's
+            errs[name].append(float(np.max(np.abs(lv.stats[[0, 2]] - want[[0, 2]]) / ns)))
+    out["idos_err_vs_oracle"] = {"samples_per_level": samples, **errs,
+                                 "unit": "states/Angstrom^2, max over energies of mean Y and mean Q_f"}
     out["speedup_mixed_vs_fp64"] = round(out["fp64"]["seconds"] / out["mixed"]["seconds"], 3)
     out["speedup_mixed_reuse_vs_fp64"] = round(out["fp64"]["seconds"] / out["mixed_reuse"]["seconds"], 3)
     dlat.close()
@@ -223,6 +241,8 @@ def time_to_tol(B, dev):
 
 
 def host_threads() -> int:
+    """Threads for the oracle: every core this process may run on, at most 16
+    (the host share of one GPU on the GPU machines)."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:  # pragma: no cover
@@ -230,15 +250,144 @@ def host_threads() -> int:
     return max(1, min(16, n))
 
 
-def cpu_model() -> str:
+def cpu_info() -> dict:
+    """nproc, the cores this process may use, and the CPU model (lscpu)."""
+    info = {"nproc": os.cpu_count()}
+    try:
+        info["affinity"] = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        pass
+    model = None
     try:
         out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
         for line in out.splitlines():
-            if line.startswith("Model name"):
-                return line.split(":", 1)[1].strip()
+            key, _, val = line.partition(":")
+            if key.strip() in ("Model name", "Vendor ID", "Socket(s)", "Core(s) per socket", "Thread(s) per core",
+                               "CPU max MHz"):
+                info["lscpu " + key.strip()] = val.strip()
+                if key.strip() == "Model name":
+                    model = val.strip()
     except Exception:
         pass
-    return platform.processor() or "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                info["proc_cpuinfo_model"] = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    info["model"] = model or info.get("proc_cpuinfo_model") or platform.processor() or "unknown"
+    return info
+
+
+KERNEL_NAMES = ("sample_vacancies", "kgrid", "assemble", "small_fused", "overlap_reduce", "band_reduce", "chase",
+                "bisect", "idos", "level_stats")
+
+
+def measure(B, wl, lat, eps, prec, args, dev):
+    """Eigensolves/s of `args.steps` level calls of `args.batch` samples
+    (after `args.warmup` untimed ones) with precision `prec`, the per-kernel
+    event times of the timed calls and the chase's roofline."""
+    import torch
+    dlat = B.DeviceLattice(lat, 0)
+    d_eps = torch.as_tensor(eps, device=dev)
+    N, K = wl.N, wl.K
+    nk = B.mlmc_kgrid_points(wl.kgrid, K)
+    need = B.mlmc_level_workspace(dlat, N, False, K, K, wl.kgrid, args.chunk, prec, eps.size)
+    work = torch.empty((need,), dtype=torch.uint8, device=dev)
+    stats = torch.zeros((4, eps.size), dtype=torch.float64, device=dev)
+    ctx = B.Context(0)
+    # Consecutive steps are consecutive level-estimate calls of one context on
+    # one workspace; on alternating streams a call's front part starts while
+    # the previous call's last chunk is still chased and bisected (the sums
+    # are still added in call order).
+    streams = [torch.cuda.current_stream()] + [torch.cuda.Stream(dev) for _ in range(args.streams - 1)]
+    calls = [0]
+
+    def step(first):
+        stream = streams[calls[0] % len(streams)]
+        calls[0] += 1
+        B.mlmc_level_estimate(dlat, N, False, wl.p, K, K, wl.kgrid, wl.seed, first, args.batch, d_eps, wl.delta,
+                              wl.smoother, prec, stats=stats, work=work, ctx=ctx, stream=stream)
+
+    pname = "fp64" if prec == B.MLMC_PREC_FP64 else "mixed"
+    print(f"[bench] workload={wl.name} N={N} K={K} batch={args.batch} steps={args.steps} warmup={args.warmup} "
+          f"precision={pname} workspace={need / 2**30:.2f} GiB", file=sys.stderr, flush=True)
+    for w in range(args.warmup):
+        step((args.steps + w) * args.batch)
+    torch.cuda.synchronize()
+    stats.zero_()
+    # event pairs for every launch of the timed calls, created before them
+    chunks = -(-args.batch // args.chunk)
+    ctx.timer(args.steps * chunks * 16 + 64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(i * args.batch)
+        print(f"[bench] {pname} step {i + 1}/{args.steps} queued", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kernels = {}
+    dropped = 0
+    for name in KERNEL_NAMES:
+        ms, cnt, dropped = ctx.timer_read(name)
+        if cnt:
+            kernels[name] = {"ms": round(ms, 3), "launches": cnt}
+    ctx.close()
+    solves = args.steps * args.batch * nk
+    value = solves / elapsed
+
+    # Sizes of the timed eigensolves (from the same vacancy masks the GPU drew).
+    masks = B.mlmc_sample_vacancies(dlat, N, wl.p, wl.seed, dlat.tag(N), 0, args.steps * args.batch).cpu().numpy()
+    orb_per_group = np.bincount(lat.orb_group, minlength=lat.n_groups)
+    vac_orbs = (masks.reshape(masks.shape[0], -1, lat.n_groups) * orb_per_group).sum(axis=(1, 2))
+    n_per_sample = (lat.n_orb * N * N - vac_orbs).astype(np.int64)
+    flops = float(nk * np.sum(16.0 / 3.0 * n_per_sample.astype(np.float64) ** 3))
+    dom = max(kernels, key=lambda k: kernels[k]["ms"]) if kernels else None
+    roofline = None
+    esize = 16 if prec == B.MLMC_PREC_FP64 else 8
+    peak = FP64_PEAK_TFLOPS if prec == B.MLMC_PREC_FP64 else FP32_PEAK_TFLOPS
+    if "chase" in kernels:
+        # The single kernel with the largest share: the band-to-tridiagonal
+        # chase.  With the band staged through LDS it moves little HBM traffic;
+        # its bound is the vector ALU (one wavefront per SIMD in FP64), so the
+        # roofline is its algorithmic flops per launch over the event-timed
+        # duration against the vector peak, with the HBM side alongside.
+        sizes, counts = np.unique(n_per_sample, return_counts=True)
+        total_flops = float(nk * sum(int(c) * chase_flops(int(v)) for v, c in zip(sizes, counts)))
+        total_bytes = float(nk * sum(int(c) * chase_bytes(int(v), esize) for v, c in zip(sizes, counts)))
+        launches = kernels["chase"]["launches"]
+        kms = kernels["chase"]["ms"]
+        achieved = total_flops / (kms * 1e-3) / 1e12
+        per_solve = chase_traffic_per_solve() if prec == B.MLMC_PREC_FP64 and wl.name == "graphene_n16_mc" else None
+        # The level pipeline gives the chase part of the CUs (beside it the
+        # next chunk's dense-to-band stage runs meanwhile): frac is against
+        # the whole chip, frac_of_its_cus against the CUs it occupies.
+        cus = B.mlmc_chase_cus(prec)
+        cus_total = torch.cuda.get_device_properties(0).multi_processor_count
+        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                    "frac": round(achieved / peak, 4),
+                    "traffic": None if per_solve is None else round(per_solve * solves / launches),
+                    "kernel": "chase_kernel", "avg_launch_ms": round(kms / launches, 3),
+                    "cus": cus, "cus_total": cus_total,
+                    "frac_of_its_cus": round(achieved / (peak * cus / cus_total), 4),
+                    "flops_per_launch": round(total_flops / launches),
+                    "hbm_bytes_per_launch": round(total_bytes / launches),
+                    "hbm_gbs": round(total_bytes / (kms * 1e-3) / 1e9, 1),
+                    "tridiag_flops_per_s": round(flops / ((kms + kernels.get("band_reduce", {"ms": 0})["ms"]) * 1e-3)
+                                                 / 1e12, 3)}
+    elif "small_fused" in kernels:
+        kms = kernels["small_fused"]["ms"]
+        achieved = flops / (kms * 1e-3) / 1e12
+        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                    "frac": round(achieved / peak, 4), "traffic": None, "kernel": "small_eig_kernel",
+                    "avg_launch_ms": round(kms / kernels["small_fused"]["launches"], 3),
+                    "flops_per_launch": flops / kernels["small_fused"]["launches"]}
+    dlat.close()
+    return {"value": round(value, 3), "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+            "samples_per_s": round(args.steps * args.batch / elapsed, 3), "kernels_ms": kernels,
+            "timer_dropped": dropped, "dominant_kernel": roofline["kernel"] if roofline else dom,
+            "roofline": roofline, "reduction_tflops_16_3_n3": round(flops / elapsed / 1e12, 3)}
 
 
 def main():
@@ -261,99 +410,14 @@ def main():
     lat = wl.make_lattice()
     eps = workload_eps(wl)
     prec = B.MLMC_PREC_FP64 if args.precision == "fp64" else B.MLMC_PREC_MIXED
+    other = B.MLMC_PREC_MIXED if prec == B.MLMC_PREC_FP64 else B.MLMC_PREC_FP64
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    dlat = B.DeviceLattice(lat, 0)
-    d_eps = torch.as_tensor(eps, device=dev)
     N, K = wl.N, wl.K
     nk = B.mlmc_kgrid_points(wl.kgrid, K)
-    need = B.mlmc_level_workspace(dlat, N, False, K, K, wl.kgrid, args.chunk, prec, eps.size)
-    work = torch.empty((need,), dtype=torch.uint8, device=dev)
-    stats = torch.zeros((4, eps.size), dtype=torch.float64, device=dev)
-    # Consecutive steps are consecutive level-estimate calls on one workspace;
-    # on alternating streams the library lets a call's front part start while
-    # the previous call's last chunk is still chased and bisected (the sums
-    # are still added in call order).
-    streams = [torch.cuda.current_stream()] + [torch.cuda.Stream(dev) for _ in range(args.streams - 1)]
-    calls = [0]
 
-    def step(first):
-        stream = streams[calls[0] % len(streams)]
-        calls[0] += 1
-        B.mlmc_level_estimate(dlat, N, False, wl.p, K, K, wl.kgrid, wl.seed, first, args.batch, d_eps, wl.delta,
-                              wl.smoother, prec, stats=stats, work=work, stream=stream)
-
-    print(f"[bench] workload={wl.name} N={N} K={K} batch={args.batch} steps={args.steps} warmup={args.warmup} "
-          f"precision={args.precision} workspace={need / 2**30:.2f} GiB", file=sys.stderr, flush=True)
-    for w in range(args.warmup):
-        step((args.steps + w) * args.batch)
-    torch.cuda.synchronize()
-    stats.zero_()
-    B.mlmc_timer_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(i * args.batch)
-        print(f"[bench] step {i + 1}/{args.steps} queued", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    B.mlmc_timer_enable(False)
-    kernels = {}
-    for name in ("sample_vacancies", "kgrid", "assemble", "small_fused", "overlap_reduce", "band_reduce", "chase", "bisect", "idos",
-                 "level_stats"):
-        ms, cnt = B.mlmc_timer_read(name)
-        if cnt:
-            kernels[name] = {"ms": round(ms, 3), "launches": cnt}
-    solves = args.steps * args.batch * nk
-    value = solves / elapsed
-
-    # Sizes of the timed eigensolves (from the same vacancy masks the GPU drew).
-    masks = B.mlmc_sample_vacancies(dlat, N, wl.p, wl.seed, dlat.tag(N), 0, args.steps * args.batch).cpu().numpy()
-    orb_per_group = np.bincount(lat.orb_group, minlength=lat.n_groups)
-    vac_orbs = (masks.reshape(masks.shape[0], -1, lat.n_groups) * orb_per_group).sum(axis=(1, 2))
-    n_per_sample = (lat.n_orb * N * N - vac_orbs).astype(np.int64)
-    flops = float(nk * np.sum(16.0 / 3.0 * n_per_sample.astype(np.float64) ** 3))
-    dom = max(kernels, key=lambda k: kernels[k]["ms"]) if kernels else None
-    roofline = None
-    esize = 16 if prec == B.MLMC_PREC_FP64 else 8
-    if "chase" in kernels:
-        # The single kernel with the largest share: the band-to-tridiagonal
-        # chase.  With the band staged through LDS it moves little HBM traffic;
-        # its bound is the vector ALU (one wavefront per SIMD in FP64), so the
-        # roofline is its algorithmic flops per launch over the event-timed
-        # duration against the vector peak, with the HBM side alongside.
-        sizes, counts = np.unique(n_per_sample, return_counts=True)
-        total_flops = float(nk * sum(int(c) * chase_flops(int(v)) for v, c in zip(sizes, counts)))
-        total_bytes = float(nk * sum(int(c) * chase_bytes(int(v), esize) for v, c in zip(sizes, counts)))
-        launches = kernels["chase"]["launches"]
-        kms = kernels["chase"]["ms"]
-        peak = FP64_PEAK_TFLOPS if prec == B.MLMC_PREC_FP64 else FP32_PEAK_TFLOPS
-        achieved = total_flops / (kms * 1e-3) / 1e12
-        per_solve = chase_traffic_per_solve() if prec == B.MLMC_PREC_FP64 and wl.name == "graphene_n16_mc" else None
-        # The level pipeline gives the chase part of the CUs (beside it the
-        # next chunk's dense-to-band stage runs meanwhile): frac is against
-        # the whole chip, frac_of_its_cus against the CUs it occupies.
-        cus = B.mlmc_chase_cus(prec)
-        cus_total = torch.cuda.get_device_properties(0).multi_processor_count
-        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                    "frac": round(achieved / peak, 4),
-                    "traffic": None if per_solve is None else round(per_solve * solves / launches),
-                    "kernel": "chase_kernel", "avg_launch_ms": round(kms / launches, 3),
-                    "cus": cus, "cus_total": cus_total,
-                    "frac_of_its_cus": round(achieved / (peak * cus / cus_total), 4),
-                    "flops_per_launch": round(total_flops / launches),
-                    "hbm_bytes_per_launch": round(total_bytes / launches),
-                    "hbm_gbs": round(total_bytes / (kms * 1e-3) / 1e9, 1),
-                    "tridiag_flops_per_s": round(flops / ((kms + kernels.get("band_reduce", {"ms": 0})["ms"]) * 1e-3)
-                                                 / 1e12, 3)}
-    elif "small_fused" in kernels:
-        kms = kernels["small_fused"]["ms"]
-        achieved = flops / (kms * 1e-3) / 1e12
-        peak = FP64_PEAK_TFLOPS if prec == B.MLMC_PREC_FP64 else FP32_PEAK_TFLOPS
-        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                    "frac": round(achieved / peak, 4), "traffic": None, "kernel": "small_eig_kernel",
-                    "avg_launch_ms": round(kms / kernels["small_fused"]["launches"], 3),
-                    "flops_per_launch": flops / kernels["small_fused"]["launches"]}
+    main_run = measure(B, wl, lat, eps, prec, args, dev)
+    second = measure(B, wl, lat, eps, other, args, dev) if args.second else None
 
     ttt = time_to_tol(B, dev) if args.mlmc else None
 
@@ -367,9 +431,12 @@ def main():
         oracle.level_estimate(lat, N, False, wl.p, K, K, wl.kgrid, wl.seed, 0, ns, eps, wl.delta, wl.smoother,
                               n_threads=threads)
         ct = time.perf_counter() - t1
+        info = cpu_info()
         cpu = {"value": round(ns * nk / ct, 3), "unit": "eigensolves/s", "cores": threads, "kind": "oracle",
                "sample": f"{ns} samples x {nk} k-points of {wl.name} (samples 0..{ns - 1}), {ct:.1f} s",
-               "cpu_model": cpu_model()}
+               "cpu_model": info["model"], "host": info,
+               "threads_note": "one oracle thread per core this process may use, at most 16 (the host share of "
+                               "one GPU on the GPU boxes)"}
         # Context: the oracle on one core (the paper's one-sample-per-core
         # regime), and LAPACK's Hermitian eigenvalues (scipy, threaded BLAS)
         # on the oracle-built matrices of sample 0, eigenvalues only.
@@ -393,12 +460,12 @@ def main():
 
     out = {
         "metric": METRIC,
-        "value": round(value, 3),
+        "value": main_run["value"],
         "unit": "eigensolves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+        "ms_per_step": main_run["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -408,15 +475,19 @@ def main():
                    "kgrid": "monkhorst-pack" if wl.kgrid == 0 else "gamma", "n_eps": int(eps.size),
                    "delta": wl.delta, "samples_per_step": args.batch, "eigensolves_per_step": args.batch * nk,
                    "precision": args.precision, "caller_streams": args.streams},
-        "samples_per_s": round(args.steps * args.batch / elapsed, 3),
-        "kernels_ms": kernels,
-        "dominant_kernel": roofline["kernel"] if roofline else dom,
-        "roofline": roofline,
-        "time_to_tol": ttt,
-        "cpu_baseline": cpu,
+        "samples_per_s": main_run["samples_per_s"],
+        "kernels_ms": main_run["kernels_ms"],
+        "dominant_kernel": main_run["dominant_kernel"],
+        "roofline": main_run["roofline"],
+        "reduction_tflops_16_3_n3": main_run["reduction_tflops_16_3_n3"],
     }
+    if second is not None:
+        out["mixed" if other == B.MLMC_PREC_MIXED else "fp64"] = second
+        if other == B.MLMC_PREC_MIXED:
+            out["speedup_mixed_vs_fp64_eigensolves"] = round(second["value"] / main_run["value"], 3)
+    out["time_to_tol"] = ttt
+    out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
-    dlat.close()
 
 
 if __name__ == "__main__":

@@ -19,10 +19,16 @@
  *     before anything is launched; a failed validation launches nothing.
  *   - Work is enqueued on `stream` (a hipStream_t; NULL is the default
  *     stream) and is asynchronous: outputs are valid once the stream has
- *     synchronised.  The only calls that may block are mlmc_lattice_create
- *     and mlmc_lattice_destroy.
+ *     synchronised.  The only calls that may block are the setup calls
+ *     (mlmc_lattice_create / _destroy, mlmc_context_create / _destroy /
+ *     _timer) and mlmc_context_timer_read.
  *   - Hot-path calls allocate no device memory.  Scratch memory is a caller
- *     workspace whose size the matching *_workspace call reports.
+ *     workspace whose size mlmc_workspace_bytes reports.
+ *   - The library keeps no mutable state between calls outside the handles
+ *     the caller creates and destroys (lattices, pipeline contexts): calls
+ *     on different streams with different workspaces and contexts share
+ *     nothing and may be made from any thread.  mlmc_last_error() is
+ *     per thread.
  *   - Results are deterministic: fixed reduction orders and no floating-point
  *     atomics.  Per-outcome results (masks, H(k), eigenvalues, IDoS) do not
  *     depend on which other outcomes share a call; level sums are
@@ -108,6 +114,35 @@ typedef struct {
 
 typedef struct mlmc_lattice_s *mlmc_lattice; /* opaque device-resident lattice */
 
+/* Opaque pipeline context of level estimates (mlmc_context_create). */
+typedef struct mlmc_context_s *mlmc_context;
+
+/* The operations that take a caller workspace (mlmc_workspace_bytes). */
+typedef enum {
+    MLMC_OP_BATCHED_EIGVALSH = 0,             /* mlmc_batched_eigvalsh: dtype, prec, ld, batch          */
+    MLMC_OP_BATCHED_EIGVALSH_GENERALIZED = 1, /* mlmc_batched_eigvalsh_generalized: dtype, prec, ld, batch */
+    MLMC_OP_LEVEL_ESTIMATE = 2                /* mlmc_level_estimate and mlmc_level_outcomes: lat, N_fine,
+                                                 coupled, K_fine, K_coarse, kgrid, chunk_samples, prec,
+                                                 n_eps                                                   */
+} mlmc_op;
+
+/* Arguments of a workspace query; fields an operation does not use are ignored. */
+typedef struct {
+    mlmc_op op;
+    mlmc_dtype dtype;
+    mlmc_precision prec;
+    int64_t ld;            /* matrix side bound                                  */
+    int64_t batch;         /* matrices per call                                  */
+    mlmc_lattice lat;
+    int32_t N_fine;
+    int32_t coupled;       /* 0 or 1                                             */
+    int32_t K_fine;
+    int32_t K_coarse;
+    mlmc_kgrid_kind kgrid;
+    int64_t chunk_samples; /* samples per pass of a level call (>= 1)            */
+    int32_t n_eps;
+} mlmc_workspace_request;
+
 const char *mlmc_status_string(int status);
 const char *mlmc_last_error(void);
 
@@ -183,9 +218,16 @@ mlmc_status mlmc_build_overlaps(mlmc_lattice lat, int32_t N, const uint8_t *d_ma
                                 const double *d_kred, int32_t n_k, mlmc_dtype dtype, void *d_S, int64_t ld,
                                 int32_t *d_n, mlmc_stream stream);
 
-/* Workspace bytes of mlmc_batched_eigvalsh for `batch` matrices of bound ld. */
-mlmc_status mlmc_eigvalsh_workspace(mlmc_dtype dtype, mlmc_precision prec, int64_t ld, int64_t batch,
-                                    size_t *bytes);
+/* Bytes of caller workspace an operation needs (host only, no device work).
+ *   MLMC_OP_BATCHED_EIGVALSH: `batch` matrices of side bound ld (0 for the
+ *     LDS-resident path, ld <= 128 complex128 / 180 complex64).
+ *   MLMC_OP_BATCHED_EIGVALSH_GENERALIZED: `batch` pencils of side bound ld.
+ *   MLMC_OP_LEVEL_ESTIMATE: a level call that processes chunk_samples samples
+ *     per pass (the call uses the largest chunk that fits the workspace it is
+ *     given).
+ * Errors: NULL arguments, unknown op, the operation's own argument checks
+ * (MLMC_ERR_UNSUPPORTED for sizes beyond the library's limits). */
+mlmc_status mlmc_workspace_bytes(const mlmc_workspace_request *req, size_t *bytes);
 
 /* All eigenvalues of a batch of Hermitian matrices (the dense full
  * eigensolve of each H(k), Section 4.2; E_n(k) is the n-th smallest
@@ -203,10 +245,6 @@ mlmc_status mlmc_batched_eigvalsh(mlmc_dtype dtype, mlmc_precision prec, void *d
                                   const int32_t *d_n, int64_t batch, double *d_w, int64_t ldw, void *d_work,
                                   size_t work_bytes, mlmc_stream stream);
 
-/* Workspace bytes of mlmc_batched_eigvalsh_generalized (ld <= 1024). */
-mlmc_status mlmc_generalized_workspace(mlmc_dtype dtype, mlmc_precision prec, int64_t ld, int64_t batch,
-                                       size_t *bytes);
-
 /* All eigenvalues of a batch of Hermitian-definite pencils (H, S) (the
  * generalised problem H c = E S c of a non-orthogonal basis, Section 3.1):
  * S = L L^H (Cholesky) and C = L^{-1} H L^{-H}, both blocked on the GPU,
@@ -214,7 +252,7 @@ mlmc_status mlmc_generalized_workspace(mlmc_dtype dtype, mlmc_precision prec, in
  * triangles of the leading n_b x n_b blocks are read and both are
  * overwritten (S by L).  S must be positive definite (otherwise the
  * eigenvalues come out NaN).  Other arguments as mlmc_batched_eigvalsh.
- * Errors: ld > 1024 (MLMC_ERR_UNSUPPORTED), workspace too small. */
+ * Errors: ld > 2048 (MLMC_ERR_UNSUPPORTED), workspace too small. */
 mlmc_status mlmc_batched_eigvalsh_generalized(mlmc_dtype dtype, mlmc_precision prec, void *d_H, void *d_S,
                                               int64_t ld, const int32_t *d_n, int64_t batch, double *d_w,
                                               int64_t ldw, void *d_work, size_t work_bytes, mlmc_stream stream);
@@ -240,13 +278,36 @@ mlmc_status mlmc_idos(const double *d_w, int64_t ldw, const int32_t *d_n, int64_
 mlmc_status mlmc_level_stats(const double *d_idos_fine, const double *d_idos_quarters, int64_t n_samples,
                              int32_t n_eps, double *d_stats, mlmc_stream stream);
 
-/* Workspace bytes for mlmc_level_estimate with the same lattice, sizes and
- * k-grid kind when it processes `chunk_samples` samples per pass (the call
- * uses the largest chunk that fits the workspace it is given;
- * chunk_samples >= 1). */
-mlmc_status mlmc_level_workspace(mlmc_lattice lat, int32_t N_fine, int32_t coupled, int32_t K_fine,
-                                 int32_t K_coarse, mlmc_kgrid_kind kind, int64_t chunk_samples,
-                                 mlmc_precision prec, int32_t n_eps, size_t *bytes);
+/* Pipeline context of level estimates (setup calls; they create and destroy
+ * HIP streams and events and may block).  A context holds, for the current
+ * device: two streams besides the caller's (default priority; one runs the
+ * band-to-tridiagonal chase, the other the bisection, IDoS and level sums),
+ * the events that order them against the caller's stream, the buffer-set
+ * rotation of consecutive calls, and an optional launch timer.  Level calls
+ * that pass the same context enqueue one at a time (the context's own lock);
+ * calls with different contexts share nothing.  A context is bound to the
+ * device current at creation. */
+mlmc_status mlmc_context_create(mlmc_context *out);
+/* Waits for the context's streams, then destroys its events and streams.
+ * NULL is accepted.  The caller must not use the context afterwards. */
+mlmc_status mlmc_context_destroy(mlmc_context ctx);
+/* Launch timing of the level calls made with `ctx` (diagnostics): capacity
+ * > 0 creates that many start/stop HIP event pairs up front (a setup call),
+ * and each kernel launch of those calls then records one pair on the stream
+ * it is launched on, until all pairs are used (later launches are counted as
+ * dropped).  Calling again with the same capacity forgets the records and
+ * keeps the events; 0 destroys them. */
+mlmc_status mlmc_context_timer(mlmc_context ctx, int64_t capacity);
+/* Total event-measured duration (ms) and count of the recorded launches of
+ * kernel `name` since the timer was last (re)set: "sample_vacancies",
+ * "partition", "kgrid", "assemble", "small_fused", "band_reduce" (dense to
+ * band, several kernels per launch), "chase" (band to tridiagonal, one
+ * kernel), "overlap_reduce" (Cholesky and reduction of a generalised
+ * problem, several kernels), "bisect", "idos" or "level_stats"; `dropped`
+ * (may be NULL) receives the launches not timed.  Blocks until the recorded
+ * launches have completed. */
+mlmc_status mlmc_context_timer_read(mlmc_context ctx, const char *name, double *total_ms, int64_t *launches,
+                                    int64_t *dropped);
 
 /* One MLMC level over samples first_sample .. first_sample+M-1 (Sections 2.2
  * and 3.3): sample outcomes on the N_fine supercell (tag (lattice_id << 32) |
@@ -254,37 +315,53 @@ mlmc_status mlmc_level_workspace(mlmc_lattice lat, int32_t N_fine, int32_t coupl
  * quarter IDoS Q_q on the K_coarse grid of the N_fine/2 supercell, and add
  * the sums of Y = Q_f [- (1/4) sum_q Q_q], Y^2, Q_f, Q_f^2 into d_stats
  * ([4][n_eps], accumulated; the caller initialises it).
- * Samples are processed in chunks that fit the workspace.  Each chunk's
- * bisection, IDoS and level sums run on a second stream owned by the library
- * while the caller's stream goes on with the next chunk; the two-stage
- * path's band-to-tridiagonal chase runs on a third such stream, on the
- * number of CUs mlmc_chase_cus reports, beside the next chunk's dense-to-
- * band stage on the caller's stream (these streams: one pair per device,
- * default priority, created on the first call and kept until the process
- * ends).  The work is ordered by events, `stream` waits for the library's
+ * Samples are processed in chunks that fit the workspace.
+ * ctx == NULL: every step runs on `stream`, and the call keeps nothing.
+ * With a context (mlmc_context_create, same device): each chunk's
+ * bisection, IDoS and level sums run on the context's back stream while
+ * `stream` goes on with the next chunk, and the two-stage path's
+ * band-to-tridiagonal chase runs on its chase stream, on the number of CUs
+ * mlmc_chase_cus reports, beside the next chunk's dense-to-band stage.  The
+ * work is ordered by the context's events, `stream` waits for the context's
  * streams before the call returns, and the sums are added in sample order as
- * on one stream.  Calls on one device enqueue one at a time (a process-wide
- * lock) and share those streams, so their bisections run one after another
- * and their sums are added in the order of the calls.  The workspace may be
- * handed from one call to the next on another stream without synchronising:
- * a call starts after the previous call's front part, and reuses a buffer
- * set only after the previous call has released it, so consecutive calls on
- * alternating streams with the same workspace, lattice, sizes, precision and
- * chunk overlap (one call's last chase and bisection beside the next call's
- * first reduction; a call on another stream than the previous one with the
- * same layout also leaves its last chunk's chase on the mlmc_chase_cus share
- * instead of the whole device); with any other layout a call waits for all
- * earlier calls' work.  Other work that uses the workspace is the caller's to order.
+ * on one stream, so the result is the same bit for bit.  The workspace may be
+ * handed from one call to the next of the same context on another stream
+ * without synchronising: a call starts after the previous call's front part,
+ * and reuses a buffer set only after the previous call has released it, so
+ * consecutive calls on alternating streams with the same workspace, lattice,
+ * sizes, precision and chunk overlap (one call's last chase and bisection
+ * beside the next call's first reduction; such a call also leaves its last
+ * chunk's chase on the mlmc_chase_cus share instead of the whole device);
+ * with any other layout a call waits for all of the context's earlier work.
+ * Other work that uses the workspace is the caller's to order; two contexts
+ * must not share a workspace while both have work in flight.
  * Errors: N_fine < 1, coupled with odd N_fine, K < 1, p outside [0, 1],
  * delta <= 0, workspace too small for one sample. */
 mlmc_status mlmc_level_estimate(mlmc_lattice lat, int32_t N_fine, int32_t coupled, double p, int32_t K_fine,
                                 int32_t K_coarse, mlmc_kgrid_kind kind, uint64_t seed, int64_t first_sample,
                                 int64_t M, const double *d_eps, int32_t n_eps, double delta, mlmc_smoother smoother,
                                 mlmc_precision prec, double *d_stats, void *d_work, size_t work_bytes,
-                                mlmc_stream stream);
+                                mlmc_context ctx, mlmc_stream stream);
 
-/* Workgroups (one per CU) that mlmc_level_estimate's chase occupies on the
- * current device with precision prec: 3/4 of the CUs (the chase runs beside
+/* The level of mlmc_level_estimate over M given outcomes instead of drawn
+ * ones (d_mask: [M][N_fine][N_fine][n_groups], 1 = vacant, e.g. from
+ * mlmc_sample_vacancies with each outcome's own seed and index), with
+ * per-outcome outputs: row s of d_Y ([M][n_eps]) receives Y_s = Q_s [- (1/4)
+ * sum_q Q_{s,q}] and row s of d_Q ([M][n_eps]) the fine IDoS Q_s; d_stats
+ * ([4][n_eps], accumulated) receives the level sums as in
+ * mlmc_level_estimate.  Any of the three may be NULL, not all.  Every
+ * outcome's rows depend on that outcome alone (not on the others of the
+ * call), which is what a server that batches requests relies on.  Workspace,
+ * context and streams as mlmc_level_estimate.
+ * Errors: as mlmc_level_estimate, NULL mask, no output. */
+mlmc_status mlmc_level_outcomes(mlmc_lattice lat, int32_t N_fine, int32_t coupled, int32_t K_fine, int32_t K_coarse,
+                                mlmc_kgrid_kind kind, const uint8_t *d_mask, int64_t M, const double *d_eps,
+                                int32_t n_eps, double delta, mlmc_smoother smoother, mlmc_precision prec,
+                                double *d_stats, double *d_Y, double *d_Q, void *d_work, size_t work_bytes,
+                                mlmc_context ctx, mlmc_stream stream);
+
+/* Workgroups (one per CU) that the chase of a level call with a context
+ * occupies on the current device with precision prec: 3/4 of the CUs (the chase runs beside
  * the next chunk's dense-to-band stage; the last chunk of a call is chased on
  * the whole device).  Errors: no device, bad prec. */
 mlmc_status mlmc_chase_cus(mlmc_precision prec, int64_t *cus);
@@ -303,20 +380,6 @@ mlmc_status mlmc_optimal_samples(int32_t L, const double *V, const double *W, do
  * one-sided at the two ends.  Host arrays; no device work.
  * Errors: n_eps < 3, NULL pointer, eps not strictly increasing. */
 mlmc_status mlmc_dos(int32_t n_eps, const double *eps, const double *idos, double *dos);
-
-/* Diagnostics (off by default): per-kernel launch timing with HIP events.
- * While enabled, each kernel launch of this library records a start/stop
- * event pair on the stream it is launched on (creating two events per
- * launch).  mlmc_timer_enable(1) discards earlier records; 0 stops recording. */
-mlmc_status mlmc_timer_enable(int32_t enable);
-/* Total event-measured duration (ms) and count of the recorded launches of
- * kernel `name`: "sample_vacancies", "partition", "kgrid", "assemble",
- * "small_fused", "band_reduce" (dense to band, several kernels per launch),
- * "chase" (band to tridiagonal, one kernel), "overlap_reduce" (Cholesky and
- * reduction of a generalised problem, several kernels), "bisect", "idos" or
- * "level_stats".
- * Blocks until those launches have completed. */
-mlmc_status mlmc_timer_read(const char *name, double *total_ms, int64_t *launches);
 
 #ifdef __cplusplus
 }

@@ -9,8 +9,10 @@ has not been built: there is no CPU fallback.
 
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 import torch
@@ -33,6 +35,9 @@ MLMC_KGRID_GAMMA = 1
 MLMC_KGRID_RHOMBI = 2
 MLMC_SMOOTH_GAUSS = 0
 MLMC_SMOOTH_CUBIC = 1
+MLMC_OP_BATCHED_EIGVALSH = 0
+MLMC_OP_BATCHED_EIGVALSH_GENERALIZED = 1
+MLMC_OP_LEVEL_ESTIMATE = 2
 
 # Largest matrix side of the LDS-resident fused path / of the device-memory path.
 SMALL_MAX = {MLMC_PREC_FP64: 128, MLMC_PREC_MIXED: 180}
@@ -57,6 +62,12 @@ class _LatticeDesc(C.Structure):
                 ("n_overlap", C.c_int32), ("overlap", C.c_void_p)]
 
 
+class _WorkspaceRequest(C.Structure):
+    _fields_ = [("op", C.c_int), ("dtype", C.c_int), ("prec", C.c_int), ("ld", C.c_int64), ("batch", C.c_int64),
+                ("lat", C.c_void_p), ("N_fine", C.c_int32), ("coupled", C.c_int32), ("K_fine", C.c_int32),
+                ("K_coarse", C.c_int32), ("kgrid", C.c_int), ("chunk_samples", C.c_int64), ("n_eps", C.c_int32)]
+
+
 _LIB = None
 P = C.c_void_p
 I32, I64, U64, DBL, SZ = C.c_int32, C.c_int64, C.c_uint64, C.c_double, C.c_size_t
@@ -73,21 +84,23 @@ SIGNATURES = {
     "mlmc_kgrid_points": (C.c_int, [C.c_int, I32, P]),
     "mlmc_kgrid": (C.c_int, [C.c_int, I32, P, P, P]),
     "mlmc_build_hamiltonians": (C.c_int, [P, I32, P, I64, P, I32, C.c_int, P, I64, P, P]),
-    "mlmc_eigvalsh_workspace": (C.c_int, [C.c_int, C.c_int, I64, I64, P]),
+    "mlmc_workspace_bytes": (C.c_int, [P, P]),
     "mlmc_batched_eigvalsh": (C.c_int, [C.c_int, C.c_int, P, I64, P, I64, P, I64, P, SZ, P]),
     "mlmc_build_overlaps": (C.c_int, [P, I32, P, I64, P, I32, C.c_int, P, I64, P, P]),
-    "mlmc_generalized_workspace": (C.c_int, [C.c_int, C.c_int, I64, I64, P]),
     "mlmc_batched_eigvalsh_generalized": (C.c_int, [C.c_int, C.c_int, P, P, I64, P, I64, P, I64, P, SZ, P]),
     "mlmc_idos": (C.c_int, [P, I64, P, I64, I32, P, DBL, P, I32, DBL, C.c_int, P, P]),
     "mlmc_level_stats": (C.c_int, [P, P, I64, I32, P, P]),
-    "mlmc_level_workspace": (C.c_int, [P, I32, I32, I32, I32, C.c_int, I64, C.c_int, I32, P]),
     "mlmc_level_estimate": (C.c_int, [P, I32, I32, DBL, I32, I32, C.c_int, U64, I64, I64, P, I32, DBL, C.c_int,
-                                      C.c_int, P, P, SZ, P]),
+                                      C.c_int, P, P, SZ, P, P]),
+    "mlmc_level_outcomes": (C.c_int, [P, I32, I32, I32, I32, C.c_int, P, I64, P, I32, DBL, C.c_int, C.c_int,
+                                      P, P, P, P, SZ, P, P]),
+    "mlmc_context_create": (C.c_int, [P]),
+    "mlmc_context_destroy": (C.c_int, [P]),
+    "mlmc_context_timer": (C.c_int, [P, I64]),
+    "mlmc_context_timer_read": (C.c_int, [P, C.c_char_p, P, P, P]),
     "mlmc_optimal_samples": (C.c_int, [I32, P, P, DBL, DBL, DBL, P]),
     "mlmc_dos": (C.c_int, [I32, P, P, P]),
     "mlmc_chase_cus": (C.c_int, [C.c_int, P]),
-    "mlmc_timer_enable": (C.c_int, [I32]),
-    "mlmc_timer_read": (C.c_int, [C.c_char_p, P, P]),
 }
 
 
@@ -166,6 +179,20 @@ def _hop_rows(table):
     return rows
 
 
+# Handles still open when the interpreter exits are released before the HIP
+# runtime shuts down (at process exit, after the atexit hooks).
+_OPEN_HANDLES = weakref.WeakSet()
+
+
+@atexit.register
+def _close_open_handles():
+    for h in list(_OPEN_HANDLES):
+        try:
+            h.close()
+        except Exception:
+            pass
+
+
 class DeviceLattice:
     """Device-resident lattice handle (mlmc_lattice_create / _destroy)."""
 
@@ -184,6 +211,7 @@ class DeviceLattice:
         with torch.cuda.device(self.device):
             _check(lib().mlmc_lattice_create(C.byref(desc), C.byref(handle)), "mlmc_lattice_create")
         self._h = handle
+        _OPEN_HANDLES.add(self)
 
     @property
     def handle(self):
@@ -209,6 +237,61 @@ class DeviceLattice:
             self.close()
         except Exception:
             pass
+
+
+class Context:
+    """Pipeline context of level estimates (mlmc_context_create / _destroy):
+    the chase and back streams, their events and the buffer-set rotation of
+    consecutive calls, on the device current at creation."""
+
+    def __init__(self, device=None):
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        handle = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().mlmc_context_create(C.byref(handle)), "mlmc_context_create")
+        self._h = handle
+        _OPEN_HANDLES.add(self)
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("context already closed")
+        return self._h
+
+    def timer(self, capacity: int):
+        """Create `capacity` start/stop event pairs (0: destroy them); the
+        level calls of this context then time their kernel launches."""
+        _check(lib().mlmc_context_timer(self.handle, int(capacity)), "mlmc_context_timer")
+
+    def timer_read(self, name: str):
+        """(total milliseconds, launches, dropped) of kernel `name` since the timer was (re)set."""
+        ms, count, dropped = C.c_double(), C.c_int64(), C.c_int64()
+        _check(lib().mlmc_context_timer_read(self.handle, name.encode(), C.byref(ms), C.byref(count),
+                                             C.byref(dropped)), "mlmc_context_timer_read")
+        return ms.value, count.value, dropped.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            with torch.cuda.device(self.device):
+                st = lib().mlmc_context_destroy(self._h)
+            self._h = None
+            _check(st, "mlmc_context_destroy")
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _ctx(ctx):
+    return None if ctx is None else ctx.handle
 
 
 # ---------------------------------------------------------------------------
@@ -286,10 +369,17 @@ def mlmc_build_overlaps(dlat, N, mask, kred, dtype=MLMC_C128, ld=None, S=None, n
     return S, n_out
 
 
-def mlmc_generalized_workspace(dtype, prec, ld, batch) -> int:
+def mlmc_workspace_bytes(op, dtype=MLMC_C128, prec=MLMC_PREC_FP64, ld=0, batch=0, dlat=None, N_fine=0, coupled=0,
+                         K_fine=0, K_coarse=0, kgrid=MLMC_KGRID_MP, chunk_samples=0, n_eps=0) -> int:
+    req = _WorkspaceRequest(op, dtype, prec, ld, batch, None if dlat is None else dlat.handle, N_fine, int(coupled),
+                            K_fine, K_coarse, kgrid, chunk_samples, n_eps)
     out = C.c_size_t()
-    _check(lib().mlmc_generalized_workspace(dtype, prec, ld, batch, C.byref(out)), "mlmc_generalized_workspace")
+    _check(lib().mlmc_workspace_bytes(C.byref(req), C.byref(out)), "mlmc_workspace_bytes")
     return out.value
+
+
+def mlmc_generalized_workspace(dtype, prec, ld, batch) -> int:
+    return mlmc_workspace_bytes(MLMC_OP_BATCHED_EIGVALSH_GENERALIZED, dtype, prec, ld, batch)
 
 
 def mlmc_batched_eigvalsh_generalized(H, S, n, prec=None, w=None, ldw=None, work=None, stream=None):
@@ -318,9 +408,7 @@ def mlmc_batched_eigvalsh_generalized(H, S, n, prec=None, w=None, ldw=None, work
 
 
 def mlmc_eigvalsh_workspace(dtype, prec, ld, batch) -> int:
-    out = C.c_size_t()
-    _check(lib().mlmc_eigvalsh_workspace(dtype, prec, ld, batch, C.byref(out)), "mlmc_eigvalsh_workspace")
-    return out.value
+    return mlmc_workspace_bytes(MLMC_OP_BATCHED_EIGVALSH, dtype, prec, ld, batch)
 
 
 def mlmc_batched_eigvalsh(H, n, prec=None, w=None, ldw=None, work=None, stream=None):
@@ -375,15 +463,17 @@ def mlmc_level_stats(idos_fine, idos_quarters=None, stats=None, stream=None):
 
 
 def mlmc_level_workspace(dlat, N, coupled, K_fine, K_coarse, kind, chunk_samples, prec, n_eps) -> int:
-    out = C.c_size_t()
-    _check(lib().mlmc_level_workspace(dlat.handle, N, int(coupled), K_fine, K_coarse, kind, chunk_samples, prec,
-                                      n_eps, C.byref(out)), "mlmc_level_workspace")
-    return out.value
+    return mlmc_workspace_bytes(MLMC_OP_LEVEL_ESTIMATE, prec=prec, dlat=dlat, N_fine=N, coupled=coupled,
+                                K_fine=K_fine, K_coarse=K_coarse, kgrid=kind, chunk_samples=chunk_samples,
+                                n_eps=n_eps)
 
 
 def mlmc_level_estimate(dlat, N, coupled, p, K_fine, K_coarse, kind, seed, first_sample, M, eps, delta,
                         smoother=MLMC_SMOOTH_GAUSS, prec=MLMC_PREC_FP64, stats=None, work=None, chunk_samples=None,
-                        stream=None):
+                        ctx=None, stream=None):
+    """One level's sums ([4][n_eps]: sum Y, sum Y^2, sum Q, sum Q^2, accumulated
+    into `stats`).  ctx: a Context (pipelined over its streams) or None (all on
+    `stream`)."""
     _dev(eps, torch.float64, "eps")
     ne = eps.shape[0]
     if stats is None:
@@ -395,9 +485,37 @@ def mlmc_level_estimate(dlat, N, coupled, p, K_fine, K_coarse, kind, seed, first
         work = torch.empty((need,), dtype=torch.uint8, device=eps.device)
     _check(lib().mlmc_level_estimate(dlat.handle, N, int(coupled), float(p), K_fine, K_coarse, kind,
                                      int(seed) & (2**64 - 1), first_sample, M, _ptr(eps), ne, float(delta), smoother,
-                                     prec, _ptr(stats), _ptr(work), work.numel(), _stream(stream)),
+                                     prec, _ptr(stats), _ptr(work), work.numel(), _ctx(ctx), _stream(stream)),
            "mlmc_level_estimate")
     return stats
+
+
+def mlmc_level_outcomes(dlat, N, coupled, K_fine, K_coarse, kind, mask, eps, delta, smoother=MLMC_SMOOTH_GAUSS,
+                        prec=MLMC_PREC_FP64, stats=None, Y=None, Q=None, work=None, chunk_samples=None, ctx=None,
+                        stream=None, want_stats=True, want_rows=True):
+    """The level over given outcomes `mask` ([M][N][N][G]): per-outcome rows
+    Y, Q ([M][n_eps]) and/or the accumulated level sums."""
+    _dev(eps, torch.float64, "eps")
+    _dev(mask, torch.uint8, "mask")
+    ne = eps.shape[0]
+    M = mask.shape[0]
+    if want_stats and stats is None:
+        stats = torch.zeros((4, ne), dtype=torch.float64, device=eps.device)
+    if want_rows and Y is None:
+        Y = torch.empty((M, ne), dtype=torch.float64, device=eps.device)
+    if want_rows and Q is None:
+        Q = torch.empty((M, ne), dtype=torch.float64, device=eps.device)
+    for t, name in ((stats, "stats"), (Y, "Y"), (Q, "Q")):
+        if t is not None:
+            _dev(t, torch.float64, name)
+    if work is None:
+        chunk = max(1, min(M, 64) if chunk_samples is None else chunk_samples)
+        need = mlmc_level_workspace(dlat, N, coupled, K_fine, K_coarse, kind, chunk, prec, ne)
+        work = torch.empty((need,), dtype=torch.uint8, device=eps.device)
+    _check(lib().mlmc_level_outcomes(dlat.handle, N, int(coupled), K_fine, K_coarse, kind, _ptr(mask), M, _ptr(eps),
+                                     ne, float(delta), smoother, prec, _ptr(stats), _ptr(Y), _ptr(Q), _ptr(work),
+                                     work.numel(), _ctx(ctx), _stream(stream)), "mlmc_level_outcomes")
+    return stats, Y, Q
 
 
 def mlmc_optimal_samples(V, W, C_alpha, theta, tol) -> np.ndarray:
@@ -425,15 +543,3 @@ def mlmc_chase_cus(prec) -> int:
     out = C.c_int64()
     _check(lib().mlmc_chase_cus(prec, C.byref(out)), "mlmc_chase_cus")
     return out.value
-
-
-def mlmc_timer_enable(enable: bool = True):
-    _check(lib().mlmc_timer_enable(1 if enable else 0), "mlmc_timer_enable")
-
-
-def mlmc_timer_read(name: str):
-    """(total milliseconds, launches) recorded for kernel `name` since the last enable."""
-    ms = C.c_double()
-    count = C.c_int64()
-    _check(lib().mlmc_timer_read(name.encode(), C.byref(ms), C.byref(count)), "mlmc_timer_read")
-    return ms.value, count.value

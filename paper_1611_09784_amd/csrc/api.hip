@@ -44,38 +44,42 @@ mlmc_status hip_fail(hipError_t err, const char *where) {
         if (e_ != hipSuccess) return hip_fail(e_, where); \
     } while (0)
 
-// Opt-in launch timing (mlmc_timer_enable / mlmc_timer_read): a start/stop
-// event pair recorded on the launch stream around each kernel launch.
-struct TimerRec {
-    const char *name;
-    hipEvent_t start, stop;
-};
-std::mutex g_timer_mu;
-std::atomic<bool> g_timing{false};
-std::vector<TimerRec> g_timer_recs;
+// Opt-in launch timing of a context's level estimates
+// (mlmc_context_timer / mlmc_context_timer_read): event pairs created when the
+// timer is enabled, recorded on the launch stream around each kernel launch.
+// The pointer below is set only while a level estimate of a timed context
+// enqueues its work on this thread.
+struct LaunchTimer {
+    std::vector<hipEvent_t> ev;       // 2 * capacity events, created up front
+    std::vector<const char *> names;  // name of record r (pair 2r, 2r + 1)
+    size_t used = 0;
+    int64_t dropped = 0;  // launches not timed because every pair was in use
 
-void timer_clear_locked() {
-    for (auto &r : g_timer_recs) {
-        (void)hipEventDestroy(r.start);
-        (void)hipEventDestroy(r.stop);
+    void release() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        ev.clear();
+        names.clear();
+        used = 0;
+        dropped = 0;
     }
-    g_timer_recs.clear();
-}
+};
+thread_local LaunchTimer *t_timer = nullptr;
 
 template <typename F>
 hipError_t timed(const char *name, hipStream_t s, F &&launch) {
-    if (!g_timing.load(std::memory_order_relaxed)) return launch();
-    hipEvent_t a = nullptr, b = nullptr;
-    hipError_t err = hipEventCreate(&a);
-    if (err == hipSuccess) err = hipEventCreate(&b);
-    if (err == hipSuccess) err = hipEventRecord(a, s);
+    LaunchTimer *tm = t_timer;
+    if (!tm) return launch();
+    if (2 * tm->used + 1 >= tm->ev.size()) {
+        ++tm->dropped;
+        return launch();
+    }
+    const size_t r = tm->used;
+    hipError_t err = hipEventRecord(tm->ev[2 * r], s);
     if (err != hipSuccess) return err;
     err = launch();
-    const hipError_t e2 = hipEventRecord(b, s);
-    {
-        std::lock_guard<std::mutex> lk(g_timer_mu);
-        g_timer_recs.push_back({name, a, b});
-    }
+    const hipError_t e2 = hipEventRecord(tm->ev[2 * r + 1], s);
+    tm->names[r] = name;
+    tm->used = r + 1;
     return err != hipSuccess ? err : e2;
 }
 
@@ -333,13 +337,41 @@ mlmc_status outcome_spectra(const mlmc_lattice_s *lat, int N, const uint8_t *mas
                      bisect_pending != nullptr && chase_pending != nullptr);
 }
 
-// The library's two streams on the current device (back: bisection, IDoS,
-// level sums; chase), with the events that order them against the caller's
-// stream in mlmc_level_estimate.  Created on first use, default priority;
-// kept until the process ends.
-struct BackStream {
-    hipStream_t s = nullptr;
-    hipStream_t sc = nullptr;     // the chase stream
+// Workgroups (one per CU) of a chase on a context's chase stream: the next
+// chunk's stage 1 runs on the quarter of the CUs it leaves free and, with the
+// 32-row rank-2k update, beside it on the others (measured on the graphene
+// N = 16 workload: FP64 3/4 of the CUs 24.7k eigensolves/s, 5/8 22.9k, 7/8
+// 24.1k, all 21.9k; mixed 40.3k, 37.6k, 38.8k, 30.1k).
+int64_t chase_cus(int cus) {
+    const int64_t v = (int64_t)cus * 3 / 4;
+    return v > 0 ? v : 1;
+}
+
+// Workspace layout of a level estimate: calls with equal keys use the
+// workspace's buffer sets in the same places.
+struct LayoutKey {
+    const void *work = nullptr;
+    int64_t mc = 0, nkf = 0, nkc = 0;
+    int n_orb = 0, n_groups = 0, N = 0, n_eps = 0, prec = 0;
+    bool cpl = false, gen = false;
+    bool operator==(const LayoutKey &o) const {
+        return work == o.work && mc == o.mc && nkf == o.nkf && nkc == o.nkc && n_orb == o.n_orb &&
+               n_groups == o.n_groups && N == o.N && n_eps == o.n_eps && prec == o.prec && cpl == o.cpl &&
+               gen == o.gen;
+    }
+};
+
+}  // namespace
+
+// A pipeline context (mlmc_context_create): the two streams of a pipelined
+// level estimate besides the caller's (back: bisection, IDoS, level sums;
+// chase), the events that order them, the rotation state of consecutive
+// calls, and an optional launch timer.  Everything a level estimate keeps
+// between calls lives here, so calls on different contexts share nothing.
+struct mlmc_context_s {
+    int device = -1;
+    hipStream_t s = nullptr;      // back stream
+    hipStream_t sc = nullptr;     // chase stream
     int64_t bisect_blocks = 0;    // workgroups of a bisection on the back stream: one per CU
     int64_t chase_blocks = 0;     // workgroups of a chase on the chase stream
     hipEvent_t begin = nullptr;   // caller's stream -> back stream
@@ -348,71 +380,40 @@ struct BackStream {
     hipEvent_t freed[kLevelSets] = {};  // back -> front: set q of the matrices / sizes / tridiagonals /
                                         // eigenvalues is free
     hipEvent_t end = nullptr;     // back -> caller's stream
-    bool created = false;         // streams and events all created
     // The previous level estimate's workspace layout and the set its next
     // chunk would use.  A call with the same layout continues the rotation:
     // each of its chunks waits only for the release of its own set (and its
     // first for the previous call's front part), so it may start while the
     // previous call's last chunks are still chased and bisected.
-    struct LayoutKey {
-        const void *work = nullptr;
-        int64_t mc = 0, nkf = 0, nkc = 0;
-        int n_orb = 0, n_groups = 0, N = 0, n_eps = 0, prec = 0;
-        bool cpl = false, gen = false;
-        bool operator==(const LayoutKey &o) const {
-            return work == o.work && mc == o.mc && nkf == o.nkf && nkc == o.nkc && n_orb == o.n_orb &&
-                   n_groups == o.n_groups && N == o.N && n_eps == o.n_eps && prec == o.prec && cpl == o.cpl &&
-                   gen == o.gen;
-        }
-    } last;
+    LayoutKey last;
     int next_set = 0;
     hipStream_t last_stream = nullptr;  // the previous call's stream
-};
-constexpr int kMaxDevices = 64;
-std::mutex g_back_mu;  // held while a level estimate enqueues its work
+    std::mutex mu;                      // held while a call enqueues its work on this context
+    LaunchTimer timer;
 
-// Workgroups (one per CU) of a chase on the chase stream: the next chunk's
-// stage 1 runs on the quarter of the CUs it leaves free and, with the 32-row
-// rank-2k update, beside it on the others (measured on the graphene N = 16
-// workload: FP64 3/4 of the CUs 24.7k eigensolves/s, 5/8 22.9k, 7/8 24.1k,
-// all 21.9k; mixed 40.3k, 37.6k, 38.8k, 30.1k).
-int64_t chase_cus(int cus) {
-    const int64_t v = (int64_t)cus * 3 / 4;
-    return v > 0 ? v : 1;
-}
-BackStream g_back[kMaxDevices];
-
-hipError_t back_stream(BackStream **out) {
-    int dev = 0;
-    hipError_t err = hipGetDevice(&dev);
-    if (err != hipSuccess) return err;
-    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
-    BackStream &b = g_back[dev];
-    if (!b.created) {
-        // One bisection workgroup per CU leaves the rest of each CU to the
-        // next chunk's reduction on the caller's stream (measured best among
-        // 1/4 to 8 per CU on the graphene N = 16 workload).
-        int cus = 0;
-        err = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (err != hipSuccess) return err;
-        b.bisect_blocks = cus > 0 ? cus : 1;
-        b.chase_blocks = chase_cus(cus);
-        // (What a failed attempt did create is kept and the rest tried again.)
-        if (!b.s) err = hipStreamCreateWithFlags(&b.s, hipStreamNonBlocking);
-        if (err == hipSuccess && !b.sc) err = hipStreamCreateWithFlags(&b.sc, hipStreamNonBlocking);
-        hipEvent_t *evs[4 + kLevelSets] = {&b.begin, &b.ready, &b.chased, &b.end};
-        for (int q = 0; q < kLevelSets; ++q) evs[4 + q] = &b.freed[q];
-        for (hipEvent_t *ev : evs)
-            if (err == hipSuccess && !*ev) err = hipEventCreateWithFlags(ev, hipEventDisableTiming);
-        // Every event a level estimate waits for has been recorded at least once.
-        if (err == hipSuccess) err = hipEventRecord(b.ready, b.s);
-        if (err == hipSuccess) err = hipEventRecord(b.chased, b.s);
-        if (err != hipSuccess) return err;
-        b.created = true;
+    // Destroys every HIP object the context holds (after its streams are idle).
+    hipError_t release() {
+        hipError_t err = hipSuccess;
+        auto keep = [&](hipError_t e) {
+            if (err == hipSuccess && e != hipSuccess) err = e;
+        };
+        if (sc) keep(hipStreamSynchronize(sc));
+        if (s) keep(hipStreamSynchronize(s));
+        timer.release();
+        hipEvent_t *evs[4 + kLevelSets] = {&begin, &ready, &chased, &end};
+        for (int q = 0; q < kLevelSets; ++q) evs[4 + q] = &freed[q];
+        for (hipEvent_t *ev : evs) {
+            if (*ev) keep(hipEventDestroy(*ev));
+            *ev = nullptr;
+        }
+        if (sc) keep(hipStreamDestroy(sc));
+        if (s) keep(hipStreamDestroy(s));
+        sc = s = nullptr;
+        return err;
     }
-    *out = &b;
-    return hipSuccess;
-}
+};
+
+namespace {
 
 mlmc_status convert_hops(const mlmc_lattice_desc *desc, const mlmc_hop *rows, int count, const char *what,
                          std::vector<int4> &hi, std::vector<double4> &hf) {
@@ -622,7 +623,7 @@ static mlmc_status check_dtype_prec(mlmc_dtype dtype, mlmc_precision prec) {
     return fail(MLMC_ERR_UNSUPPORTED, "dtype %d with precision %d is not supported", (int)dtype, (int)prec);
 }
 
-mlmc_status mlmc_eigvalsh_workspace(mlmc_dtype dtype, mlmc_precision prec, int64_t ld, int64_t batch, size_t *bytes) {
+static mlmc_status eigvalsh_workspace(mlmc_dtype dtype, mlmc_precision prec, int64_t ld, int64_t batch, size_t *bytes) {
     if (!bytes || ld < 0 || batch < 0) return fail(MLMC_ERR_INVALID_ARG, "eigvalsh_workspace: bad argument");
     const mlmc_status st = check_dtype_prec(dtype, prec);
     if (st != MLMC_OK) return st;
@@ -641,7 +642,7 @@ mlmc_status mlmc_batched_eigvalsh(mlmc_dtype dtype, mlmc_precision prec, void *d
                                   int64_t batch, double *d_w, int64_t ldw, void *d_work, size_t work_bytes,
                                   mlmc_stream stream) {
     size_t need = 0;
-    const mlmc_status st = mlmc_eigvalsh_workspace(dtype, prec, ld, batch, &need);
+    const mlmc_status st = eigvalsh_workspace(dtype, prec, ld, batch, &need);
     if (st != MLMC_OK) return st;
     if (ldw < ld) return fail(MLMC_ERR_INVALID_ARG, "batched_eigvalsh: ldw %lld < ld %lld", (long long)ldw, (long long)ld);
     if (batch > 0 && (!d_H || !d_n || !d_w)) return fail(MLMC_ERR_INVALID_ARG, "batched_eigvalsh: NULL buffer");
@@ -662,8 +663,8 @@ mlmc_status mlmc_batched_eigvalsh(mlmc_dtype dtype, mlmc_precision prec, void *d
     return run_large(prec, d_H, ld, d_n, batch, d_w, ldw, b, s);
 }
 
-mlmc_status mlmc_generalized_workspace(mlmc_dtype dtype, mlmc_precision prec, int64_t ld, int64_t batch,
-                                       size_t *bytes) {
+static mlmc_status generalized_workspace(mlmc_dtype dtype, mlmc_precision prec, int64_t ld, int64_t batch,
+                                         size_t *bytes) {
     if (!bytes || ld < 0 || batch < 0) return fail(MLMC_ERR_INVALID_ARG, "generalized_workspace: bad argument");
     const mlmc_status st = check_dtype_prec(dtype, prec);
     if (st != MLMC_OK) return st;
@@ -680,7 +681,7 @@ mlmc_status mlmc_batched_eigvalsh_generalized(mlmc_dtype dtype, mlmc_precision p
                                               int64_t ld, const int32_t *d_n, int64_t batch, double *d_w,
                                               int64_t ldw, void *d_work, size_t work_bytes, mlmc_stream stream) {
     size_t need = 0;
-    const mlmc_status st = mlmc_generalized_workspace(dtype, prec, ld, batch, &need);
+    const mlmc_status st = generalized_workspace(dtype, prec, ld, batch, &need);
     if (st != MLMC_OK) return st;
     if (ldw < ld) return fail(MLMC_ERR_INVALID_ARG, "eigvalsh_generalized: ldw %lld < ld %lld", (long long)ldw, (long long)ld);
     if (batch > 0 && (!d_H || !d_S || !d_n || !d_w)) return fail(MLMC_ERR_INVALID_ARG, "eigvalsh_generalized: NULL buffer");
@@ -738,36 +739,69 @@ static mlmc_status check_level_args(mlmc_lattice lat, int32_t N, int32_t coupled
     return MLMC_OK;
 }
 
-mlmc_status mlmc_level_workspace(mlmc_lattice lat, int32_t N_fine, int32_t coupled, int32_t K_fine, int32_t K_coarse,
-                                 mlmc_kgrid_kind kind, int64_t chunk_samples, mlmc_precision prec, int32_t n_eps,
-                                 size_t *bytes) {
+static mlmc_status level_workspace(mlmc_lattice lat, int32_t N_fine, int32_t coupled, int32_t K_fine,
+                                   int32_t K_coarse, mlmc_kgrid_kind kind, int64_t chunk_samples, mlmc_precision prec,
+                                   int32_t n_eps, size_t *bytes) {
     const mlmc_status st = check_level_args(lat, N_fine, coupled, K_fine, K_coarse, prec, n_eps);
     if (st != MLMC_OK) return st;
     if (!valid_kgrid_kind(kind)) return fail(MLMC_ERR_INVALID_ARG, "level_workspace: bad k-grid");
-    if (!bytes || chunk_samples < 1) return fail(MLMC_ERR_INVALID_ARG, "level_workspace: chunk_samples must be >= 1");
+    if (chunk_samples < 1) return fail(MLMC_ERR_INVALID_ARG, "level_workspace: chunk_samples must be >= 1");
     *bytes = level_layout(lat, N_fine, coupled != 0, K_fine, K_coarse, kind, chunk_samples, prec, n_eps, nullptr).bytes;
     return MLMC_OK;
 }
 
-mlmc_status mlmc_level_estimate(mlmc_lattice lat, int32_t N, int32_t coupled, double p, int32_t Kf, int32_t Kc,
-                                mlmc_kgrid_kind kind, uint64_t seed, int64_t first_sample, int64_t M,
-                                const double *d_eps, int32_t n_eps, double delta, mlmc_smoother smoother,
-                                mlmc_precision prec, double *d_stats, void *d_work, size_t work_bytes,
-                                mlmc_stream stream) {
-    mlmc_status st = check_level_args(lat, N, coupled, Kf, Kc, prec, n_eps);
-    if (st != MLMC_OK) return st;
-    if (!(p >= 0.0 && p <= 1.0)) return fail(MLMC_ERR_INVALID_ARG, "level: p = %g", p);
-    if (!(delta > 0.0) || !std::isfinite(delta)) return fail(MLMC_ERR_INVALID_ARG, "level: delta = %g", delta);
-    if (!valid_kgrid_kind(kind)) return fail(MLMC_ERR_INVALID_ARG, "level: bad k-grid");
-    if (smoother != MLMC_SMOOTH_GAUSS && smoother != MLMC_SMOOTH_CUBIC)
-        return fail(MLMC_ERR_INVALID_ARG, "level: bad smoother");
-    if (M < 0 || first_sample < 0) return fail(MLMC_ERR_INVALID_ARG, "level: negative sample range");
-    if (M == 0) return MLMC_OK;
-    if (!d_eps || !d_stats) return fail(MLMC_ERR_INVALID_ARG, "level: NULL buffer");
-    const bool cpl = coupled != 0;
+mlmc_status mlmc_workspace_bytes(const mlmc_workspace_request *req, size_t *bytes) {
+    if (!req || !bytes) return fail(MLMC_ERR_INVALID_ARG, "workspace_bytes: NULL argument");
+    *bytes = 0;
+    switch (req->op) {
+        case MLMC_OP_BATCHED_EIGVALSH: return eigvalsh_workspace(req->dtype, req->prec, req->ld, req->batch, bytes);
+        case MLMC_OP_BATCHED_EIGVALSH_GENERALIZED:
+            return generalized_workspace(req->dtype, req->prec, req->ld, req->batch, bytes);
+        case MLMC_OP_LEVEL_ESTIMATE:
+            return level_workspace(req->lat, req->N_fine, req->coupled, req->K_fine, req->K_coarse, req->kgrid,
+                                   req->chunk_samples, req->prec, req->n_eps, bytes);
+        default: return fail(MLMC_ERR_INVALID_ARG, "workspace_bytes: unknown operation %d", (int)req->op);
+    }
+}
+
+}  // extern "C"
+
+namespace {
+
+// Streams and events of one level call: with a context, three streams
+// ordered by the context's events; without one, everything on the caller's
+// stream (then the event operations are no-ops).
+struct LevelStreams {
+    mlmc_context ctx;
+    hipStream_t front, chase, back;
+    hipError_t record(hipEvent_t ev, hipStream_t st) const { return ctx ? hipEventRecord(ev, st) : hipSuccess; }
+    hipError_t wait(hipStream_t st, hipEvent_t ev) const { return ctx ? hipStreamWaitEvent(st, ev, 0) : hipSuccess; }
+};
+
+// Sets the thread's launch timer for the duration of a call.
+struct TimerScope {
+    explicit TimerScope(LaunchTimer *t) { t_timer = t; }
+    ~TimerScope() { t_timer = nullptr; }
+};
+
+// One MLMC level over M outcomes (Sections 2.2 and 3.3): the outcomes are
+// drawn (d_mask_in == NULL: seed, first_sample, p) or given (d_mask_in:
+// [M][N][N][G]).  Adds the level sums to d_stats (if not NULL) and writes the
+// per-outcome Y and Q_f rows to d_Y, d_Q (if not NULL).
+mlmc_status level_run(mlmc_context ctx, mlmc_lattice lat, int32_t N, bool cpl, double p, int32_t Kf, int32_t Kc,
+                      mlmc_kgrid_kind kind, uint64_t seed, int64_t first_sample, const uint8_t *d_mask_in,
+                      int64_t M, const double *d_eps, int32_t n_eps, double delta, mlmc_smoother smoother,
+                      mlmc_precision prec, double *d_stats, double *d_Y, double *d_Q, void *d_work,
+                      size_t work_bytes, hipStream_t s) {
     const size_t one = level_layout(lat, N, cpl, Kf, Kc, kind, 1, prec, n_eps, nullptr).bytes;
     if (!d_work || work_bytes < one)
         return fail(MLMC_ERR_WORKSPACE, "level: workspace %zu < %zu bytes needed for one sample", work_bytes, one);
+    if (ctx) {
+        int dev = -1;
+        HIP_TRY(hipGetDevice(&dev), "level: device");
+        if (dev != ctx->device)
+            return fail(MLMC_ERR_INVALID_ARG, "level: context of device %d used on device %d", ctx->device, dev);
+    }
     const size_t two = level_layout(lat, N, cpl, Kf, Kc, kind, 2, prec, n_eps, nullptr).bytes;
     const size_t per = two - one, fixed = one - per;
     int64_t mc = (int64_t)((work_bytes - fixed) / per) + 2;  // padding makes the estimate approximate
@@ -775,7 +809,6 @@ mlmc_status mlmc_level_estimate(mlmc_lattice lat, int32_t N, int32_t coupled, do
     if (mc < 1) mc = 1;
     while (mc > 1 && level_layout(lat, N, cpl, Kf, Kc, kind, mc, prec, n_eps, nullptr).bytes > work_bytes) --mc;
     const LevelLayout L = level_layout(lat, N, cpl, Kf, Kc, kind, mc, prec, n_eps, static_cast<char *>(d_work));
-    hipStream_t s = static_cast<hipStream_t>(stream);
     const int G = lat->dev.n_groups, h = N / 2;
     const uint64_t tag = ((uint64_t)lat->dev.lattice_id << 32) | (uint64_t)(uint32_t)N;
     const uint64_t thr = (uint64_t)std::floor(p * 9007199254740992.0);
@@ -783,91 +816,110 @@ mlmc_status mlmc_level_estimate(mlmc_lattice lat, int32_t N, int32_t coupled, do
     const double inv_area_c = cpl ? 1.0 / ((double)h * h * lat->dev.cell_area) : 0.0;
     const int nkf = kgrid_count(kind, Kf), nkc = cpl ? kgrid_count(kind, Kc) : 0;
     const int64_t ldf = (int64_t)lat->dev.n_orb * N * N, ldc = (int64_t)lat->dev.n_orb * h * h;
-    // Three streams: the caller's (front) samples, assembles and reduces
-    // chunk c (on the two-stage path: stage 1 only); the chase stream chases
-    // chunk c's bands on 3/4 of the CUs while the front goes on with chunk
-    // c + 1; the back stream runs chunk c's bisection, IDoS and level sums.
-    // Matrices (two-stage path), k-grids, sizes, tridiagonals and eigenvalues
-    // come in kLevelSets sets used in turn; the front waits until the back
-    // has released a set before refilling it.  The sample masks and the
-    // stage-1 workspace are the front's alone, the band workspace the chase
-    // stream's, the per-sample IDoS the back stream's.
-    std::lock_guard<std::mutex> lk(g_back_mu);
-    BackStream *bk = nullptr;
-    HIP_TRY(back_stream(&bk), "level: back stream");
-    hipStream_t sb = bk->s, sc = bk->sc;
-    BackStream::LayoutKey key;
-    key.work = d_work;
-    key.mc = mc;
-    key.nkf = nkf;
-    key.nkc = nkc;
-    key.n_orb = lat->dev.n_orb;
-    key.n_groups = G;
-    key.N = N;
-    key.n_eps = n_eps;
-    key.prec = (int)prec;
-    key.cpl = cpl;
-    key.gen = lat->dev.n_ovl > 0;
-    // The previous call's front part (masks, stage-1 workspace, the last
-    // chunk's matrices) is complete before this call's front starts.
-    HIP_TRY(hipStreamWaitEvent(s, bk->ready, 0), "level: wait");
-    // Same layout on another stream than the previous call: the caller
-    // alternates streams, so the next call is likely to start beside this
-    // one's last chunk, which then keeps the chase stream's share of the CUs.
-    const bool overlapping = key == bk->last && s != bk->last_stream;
-    bk->last_stream = s;
-    if (!(key == bk->last)) {
-        // Another layout may overlap any of the previous call's buffers: all
-        // sets count as released only after everything enqueued so far.
-        bk->last = BackStream::LayoutKey{};
-        HIP_TRY(hipEventRecord(bk->begin, s), "level: event");
-        HIP_TRY(hipStreamWaitEvent(sb, bk->begin, 0), "level: wait");
-        for (int q = 0; q < kLevelSets; ++q) HIP_TRY(hipEventRecord(bk->freed[q], sb), "level: event");
-        bk->last = key;
-        bk->next_set = 0;
+    const int64_t mask_bytes = (int64_t)N * N * G;
+    // With a context, three streams: the caller's (front) samples, assembles
+    // and reduces chunk c (on the two-stage path: stage 1 only); the chase
+    // stream chases chunk c's bands on 3/4 of the CUs while the front goes on
+    // with chunk c + 1; the back stream runs chunk c's bisection, IDoS and
+    // level sums.  Matrices (two-stage path), k-grids, sizes, tridiagonals and
+    // eigenvalues come in kLevelSets sets used in turn; the front waits until
+    // the back has released a set before refilling it.  The sample masks and
+    // the stage-1 workspace are the front's alone, the band workspace the
+    // chase stream's, the per-sample IDoS the back stream's.
+    std::unique_lock<std::mutex> lk;
+    if (ctx) lk = std::unique_lock<std::mutex>(ctx->mu);
+    const LevelStreams S{ctx, s, ctx ? ctx->sc : s, ctx ? ctx->s : s};
+    TimerScope timer_scope(ctx && !ctx->timer.ev.empty() ? &ctx->timer : nullptr);
+    bool overlapping = false;
+    int set0 = 0;
+    if (ctx) {
+        LayoutKey key;
+        key.work = d_work;
+        key.mc = mc;
+        key.nkf = nkf;
+        key.nkc = nkc;
+        key.n_orb = lat->dev.n_orb;
+        key.n_groups = G;
+        key.N = N;
+        key.n_eps = n_eps;
+        key.prec = (int)prec;
+        key.cpl = cpl;
+        key.gen = lat->dev.n_ovl > 0;
+        // The previous call's front part (masks, stage-1 workspace, the last
+        // chunk's matrices) is complete before this call's front starts.
+        HIP_TRY(hipStreamWaitEvent(s, ctx->ready, 0), "level: wait");
+        // Same layout on another stream than the previous call: the caller
+        // alternates streams, so the next call is likely to start beside this
+        // one's last chunk, which then keeps the chase stream's share of the CUs.
+        overlapping = key == ctx->last && s != ctx->last_stream;
+        ctx->last_stream = s;
+        if (!(key == ctx->last)) {
+            // Another layout may overlap any of the previous call's buffers:
+            // all sets count as released only after everything enqueued so far.
+            ctx->last = LayoutKey{};
+            HIP_TRY(hipEventRecord(ctx->begin, s), "level: event");
+            HIP_TRY(hipStreamWaitEvent(ctx->s, ctx->begin, 0), "level: wait");
+            for (int q = 0; q < kLevelSets; ++q) HIP_TRY(hipEventRecord(ctx->freed[q], ctx->s), "level: event");
+            ctx->last = key;
+            ctx->next_set = 0;
+        }
+        set0 = ctx->next_set;
     }
-    // A call that fails part-way makes the next one take the path above, with
-    // the front and chase work it did enqueue covered by `ready` and the back
-    // stream.
+    // A call that fails part-way makes the next one on its context take the
+    // path above, with the front and chase work it did enqueue covered by
+    // `ready` and the back stream.
     struct FailGuard {
-        BackStream *bk;
+        mlmc_context ctx;
         hipStream_t s;
         bool ok = false;
         ~FailGuard() {
-            if (ok) return;
-            bk->last = BackStream::LayoutKey{};
-            (void)hipEventRecord(bk->chased, bk->sc);
-            (void)hipStreamWaitEvent(bk->s, bk->chased, 0);
-            (void)hipEventRecord(bk->ready, s);
+            if (ok || !ctx) return;
+            ctx->last = LayoutKey{};
+            (void)hipEventRecord(ctx->chased, ctx->sc);
+            (void)hipStreamWaitEvent(ctx->s, ctx->chased, 0);
+            (void)hipEventRecord(ctx->ready, s);
         }
-    } guard{bk, s};
+    } guard{ctx, s};
+    int next_set = set0;
+    mlmc_status st = MLMC_OK;
     for (int64_t done = 0; done < M; done += mc) {
         const int64_t ns = (M - done < mc) ? (M - done) : mc;
-        const int q = bk->next_set;
-        bk->next_set = (q + 1) % kLevelSets;
-        HIP_TRY(hipStreamWaitEvent(s, bk->freed[q], 0), "level: wait");
+        const int q = next_set;
+        next_set = (q + 1) % kLevelSets;
+        if (ctx) {
+            ctx->next_set = next_set;
+            HIP_TRY(hipStreamWaitEvent(s, ctx->freed[q], 0), "level: wait");
+        }
         LAUNCH("kgrid", s, launch_kgrid(kind, Kf, L.kf[q], L.kwf[q], s));
         if (cpl) LAUNCH("kgrid", s, launch_kgrid(kind, Kc, L.kc[q], L.kwc[q], s));
-        LAUNCH("sample_vacancies", s, launch_sample_vacancies(lat->dev, N, thr, seed, tag, first_sample + done, ns, L.mask, s));
+        const uint8_t *mask = L.mask;
+        if (d_mask_in)
+            mask = d_mask_in + done * mask_bytes;
+        else
+            LAUNCH("sample_vacancies", s,
+                   launch_sample_vacancies(lat->dev, N, thr, seed, tag, first_sample + done, ns, L.mask, s));
         bool pend_f = false, pend_c = false, chase_f = false, chase_c = false;
         const EigBuffers bf = L.bf.set(q), bc = L.bc.set(q);
-        st = outcome_spectra(lat, N, L.mask, ns, L.kf[q], nkf, prec, L.wf[q], L.nf[q], bf, s, &pend_f, &chase_f);
+        st = outcome_spectra(lat, N, mask, ns, L.kf[q], nkf, prec, L.wf[q], L.nf[q], bf, s, &pend_f, &chase_f);
         if (st != MLMC_OK) return st;
         if (cpl) {
-            LAUNCH("partition", s, launch_partition(N, G, L.mask, ns, L.quarters, s));
+            LAUNCH("partition", s, launch_partition(N, G, mask, ns, L.quarters, s));
             st = outcome_spectra(lat, h, L.quarters, ns * 4, L.kc[q], nkc, prec, L.wc[q], L.nc[q], bc, s, &pend_c,
                                  &chase_c);
             if (st != MLMC_OK) return st;
         }
-        HIP_TRY(hipEventRecord(bk->ready, s), "level: event");
-        HIP_TRY(hipStreamWaitEvent(sb, bk->ready, 0), "level: wait");
+        hipStream_t sc = S.chase, sb = S.back;
+        if (ctx) {
+            HIP_TRY(hipEventRecord(ctx->ready, s), "level: event");
+            HIP_TRY(hipStreamWaitEvent(sb, ctx->ready, 0), "level: wait");
+        }
         // The last chunk's chase and bisection have nothing left to run
         // beside (unless the calls overlap): they take the whole device (one
-        // workgroup per matrix).
-        const bool last = !overlapping && done + ns >= M;
-        const int64_t chase_blocks = last ? 0 : bk->chase_blocks, bisect_blocks = last ? 0 : bk->bisect_blocks;
+        // workgroup per matrix), as does everything without a context.
+        const bool last = !ctx || (!overlapping && done + ns >= M);
+        const int64_t chase_blocks = last ? 0 : ctx->chase_blocks, bisect_blocks = last ? 0 : ctx->bisect_blocks;
         if (chase_f || chase_c) {
-            HIP_TRY(hipStreamWaitEvent(sc, bk->ready, 0), "level: wait");
+            if (ctx) HIP_TRY(hipStreamWaitEvent(sc, ctx->ready, 0), "level: wait");
             if (chase_f) {
                 st = run_chase(prec, bf.H, ldf, L.nf[q], ns * nkf, bf, sc, chase_blocks);
                 if (st != MLMC_OK) return st;
@@ -876,29 +928,175 @@ mlmc_status mlmc_level_estimate(mlmc_lattice lat, int32_t N, int32_t coupled, do
                 st = run_chase(prec, bc.H, ldc, L.nc[q], ns * 4 * nkc, bc, sc, chase_blocks);
                 if (st != MLMC_OK) return st;
             }
-            HIP_TRY(hipEventRecord(bk->chased, sc), "level: event");
-            HIP_TRY(hipStreamWaitEvent(sb, bk->chased, 0), "level: wait");
+            if (ctx) {
+                HIP_TRY(hipEventRecord(ctx->chased, sc), "level: event");
+                HIP_TRY(hipStreamWaitEvent(sb, ctx->chased, 0), "level: wait");
+            }
         }
         if (pend_f) {
             st = run_bisect(L.nf[q], ldf, ns * nkf, L.wf[q], ldf, bf, sb, bisect_blocks);
             if (st != MLMC_OK) return st;
         }
         LAUNCH("idos", sb, launch_idos(L.wf[q], ldf, L.nf[q], ns, nkf, L.kwf[q], inv_area_f, d_eps, n_eps, delta,
-                             (int)smoother, L.If, sb));
+                                       (int)smoother, L.If, sb));
         if (cpl) {
             if (pend_c) {
                 st = run_bisect(L.nc[q], ldc, ns * 4 * nkc, L.wc[q], ldc, bc, sb, bisect_blocks);
                 if (st != MLMC_OK) return st;
             }
-            LAUNCH("idos", sb, launch_idos(L.wc[q], ldc, L.nc[q], ns * 4, nkc, L.kwc[q], inv_area_c, d_eps, n_eps, delta,
-                                 (int)smoother, L.Ic, sb));
+            LAUNCH("idos", sb, launch_idos(L.wc[q], ldc, L.nc[q], ns * 4, nkc, L.kwc[q], inv_area_c, d_eps, n_eps,
+                                           delta, (int)smoother, L.Ic, sb));
         }
-        LAUNCH("level_stats", sb, launch_level_stats(L.If, cpl ? L.Ic : nullptr, ns, n_eps, d_stats, sb));
-        HIP_TRY(hipEventRecord(bk->freed[q], sb), "level: event");
+        LAUNCH("level_stats", sb,
+               launch_level_stats(L.If, cpl ? L.Ic : nullptr, ns, n_eps, d_stats, sb,
+                                  d_Y ? d_Y + done * n_eps : nullptr, d_Q ? d_Q + done * n_eps : nullptr));
+        if (ctx) HIP_TRY(hipEventRecord(ctx->freed[q], sb), "level: event");
     }
     guard.ok = true;
-    HIP_TRY(hipEventRecord(bk->end, sb), "level: event");
-    HIP_TRY(hipStreamWaitEvent(s, bk->end, 0), "level: wait");
+    if (ctx) {
+        HIP_TRY(hipEventRecord(ctx->end, ctx->s), "level: event");
+        HIP_TRY(hipStreamWaitEvent(s, ctx->end, 0), "level: wait");
+    }
+    return MLMC_OK;
+}
+
+mlmc_status check_level_call(mlmc_lattice lat, int32_t N, int32_t coupled, double p, int32_t Kf, int32_t Kc,
+                             mlmc_kgrid_kind kind, int64_t M, const double *d_eps, int32_t n_eps, double delta,
+                             mlmc_smoother smoother, mlmc_precision prec) {
+    mlmc_status st = check_level_args(lat, N, coupled, Kf, Kc, prec, n_eps);
+    if (st != MLMC_OK) return st;
+    if (!(p >= 0.0 && p <= 1.0)) return fail(MLMC_ERR_INVALID_ARG, "level: p = %g", p);
+    if (!(delta > 0.0) || !std::isfinite(delta)) return fail(MLMC_ERR_INVALID_ARG, "level: delta = %g", delta);
+    if (!valid_kgrid_kind(kind)) return fail(MLMC_ERR_INVALID_ARG, "level: bad k-grid");
+    if (smoother != MLMC_SMOOTH_GAUSS && smoother != MLMC_SMOOTH_CUBIC)
+        return fail(MLMC_ERR_INVALID_ARG, "level: bad smoother");
+    if (M < 0) return fail(MLMC_ERR_INVALID_ARG, "level: negative sample count");
+    if (M > 0 && !d_eps) return fail(MLMC_ERR_INVALID_ARG, "level: NULL energies");
+    return MLMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mlmc_status mlmc_level_estimate(mlmc_lattice lat, int32_t N, int32_t coupled, double p, int32_t Kf, int32_t Kc,
+                                mlmc_kgrid_kind kind, uint64_t seed, int64_t first_sample, int64_t M,
+                                const double *d_eps, int32_t n_eps, double delta, mlmc_smoother smoother,
+                                mlmc_precision prec, double *d_stats, void *d_work, size_t work_bytes,
+                                mlmc_context ctx, mlmc_stream stream) {
+    mlmc_status st = check_level_call(lat, N, coupled, p, Kf, Kc, kind, M, d_eps, n_eps, delta, smoother, prec);
+    if (st != MLMC_OK) return st;
+    if (first_sample < 0) return fail(MLMC_ERR_INVALID_ARG, "level: negative first sample");
+    if (M == 0) return MLMC_OK;
+    if (!d_stats) return fail(MLMC_ERR_INVALID_ARG, "level: NULL stats");
+    return level_run(ctx, lat, N, coupled != 0, p, Kf, Kc, kind, seed, first_sample, nullptr, M, d_eps, n_eps, delta,
+                     smoother, prec, d_stats, nullptr, nullptr, d_work, work_bytes, static_cast<hipStream_t>(stream));
+}
+
+mlmc_status mlmc_level_outcomes(mlmc_lattice lat, int32_t N, int32_t coupled, int32_t Kf, int32_t Kc,
+                                mlmc_kgrid_kind kind, const uint8_t *d_mask, int64_t M, const double *d_eps,
+                                int32_t n_eps, double delta, mlmc_smoother smoother, mlmc_precision prec,
+                                double *d_stats, double *d_Y, double *d_Q, void *d_work, size_t work_bytes,
+                                mlmc_context ctx, mlmc_stream stream) {
+    mlmc_status st = check_level_call(lat, N, coupled, 0.0, Kf, Kc, kind, M, d_eps, n_eps, delta, smoother, prec);
+    if (st != MLMC_OK) return st;
+    if (M == 0) return MLMC_OK;
+    if (!d_mask) return fail(MLMC_ERR_INVALID_ARG, "level_outcomes: NULL mask");
+    if (!d_stats && !d_Y && !d_Q) return fail(MLMC_ERR_INVALID_ARG, "level_outcomes: no output");
+    return level_run(ctx, lat, N, coupled != 0, 0.0, Kf, Kc, kind, 0, 0, d_mask, M, d_eps, n_eps, delta, smoother,
+                     prec, d_stats, d_Y, d_Q, d_work, work_bytes, static_cast<hipStream_t>(stream));
+}
+
+mlmc_status mlmc_context_create(mlmc_context *out) {
+    if (!out) return fail(MLMC_ERR_INVALID_ARG, "context_create: NULL argument");
+    *out = nullptr;
+    auto *c = new mlmc_context_s();
+    hipError_t err = hipGetDevice(&c->device);
+    int cus = 0;
+    if (err == hipSuccess) err = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
+    // One bisection workgroup per CU leaves the rest of each CU to the next
+    // chunk's reduction on the caller's stream (measured best among 1/4 to 8
+    // per CU on the graphene N = 16 workload).
+    c->bisect_blocks = cus > 0 ? cus : 1;
+    c->chase_blocks = chase_cus(cus);
+    // Default-priority streams that do not synchronise with the null stream.
+    if (err == hipSuccess) err = hipStreamCreateWithFlags(&c->s, hipStreamNonBlocking);
+    if (err == hipSuccess) err = hipStreamCreateWithFlags(&c->sc, hipStreamNonBlocking);
+    hipEvent_t *evs[4 + kLevelSets] = {&c->begin, &c->ready, &c->chased, &c->end};
+    for (int q = 0; q < kLevelSets; ++q) evs[4 + q] = &c->freed[q];
+    for (hipEvent_t *ev : evs)
+        if (err == hipSuccess) err = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+    // Every event a level estimate waits for has been recorded at least once.
+    if (err == hipSuccess) err = hipEventRecord(c->ready, c->s);
+    if (err == hipSuccess) err = hipEventRecord(c->chased, c->s);
+    if (err != hipSuccess) {
+        (void)c->release();
+        delete c;
+        return hip_fail(err, "context_create");
+    }
+    *out = c;
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_context_destroy(mlmc_context ctx) {
+    if (!ctx) return MLMC_OK;
+    hipError_t err;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        int prev = -1;
+        err = hipGetDevice(&prev);
+        if (err == hipSuccess && prev != ctx->device) err = hipSetDevice(ctx->device);
+        const hipError_t e2 = ctx->release();
+        if (err == hipSuccess) err = e2;
+        if (prev >= 0 && prev != ctx->device) (void)hipSetDevice(prev);
+    }
+    delete ctx;
+    if (err != hipSuccess) return hip_fail(err, "context_destroy");
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_context_timer(mlmc_context ctx, int64_t capacity) {
+    if (!ctx || capacity < 0 || capacity > (int64_t)1 << 20)
+        return fail(MLMC_ERR_INVALID_ARG, "context_timer: bad argument");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    LaunchTimer &t = ctx->timer;
+    if ((int64_t)t.names.size() == capacity) {  // same capacity: keep the events, forget the records
+        t.used = 0;
+        t.dropped = 0;
+        return MLMC_OK;
+    }
+    t.release();
+    if (capacity == 0) return MLMC_OK;
+    t.ev.assign(2 * (size_t)capacity, nullptr);
+    t.names.assign((size_t)capacity, nullptr);
+    for (hipEvent_t &e : t.ev) {
+        const hipError_t err = hipEventCreate(&e);
+        if (err != hipSuccess) {
+            t.release();
+            return hip_fail(err, "context_timer");
+        }
+    }
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_context_timer_read(mlmc_context ctx, const char *name, double *total_ms, int64_t *launches,
+                                    int64_t *dropped) {
+    if (!ctx || !name || !total_ms || !launches) return fail(MLMC_ERR_INVALID_ARG, "context_timer_read: NULL argument");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    const LaunchTimer &t = ctx->timer;
+    double total = 0.0;
+    int64_t count = 0;
+    for (size_t r = 0; r < t.used; ++r) {
+        if (std::strcmp(t.names[r], name) != 0) continue;
+        HIP_TRY(hipEventSynchronize(t.ev[2 * r + 1]), "timer_read");
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, t.ev[2 * r], t.ev[2 * r + 1]), "timer_read");
+        total += ms;
+        ++count;
+    }
+    *total_ms = total;
+    *launches = count;
+    if (dropped) *dropped = t.dropped;
     return MLMC_OK;
 }
 
@@ -950,31 +1148,4 @@ mlmc_status mlmc_optimal_samples(int32_t L, const double *V, const double *W, do
 
 }  // extern "C"
 
-extern "C" {
 
-mlmc_status mlmc_timer_enable(int32_t enable) {
-    std::lock_guard<std::mutex> lk(g_timer_mu);
-    if (enable) timer_clear_locked();
-    g_timing.store(enable != 0);
-    return MLMC_OK;
-}
-
-mlmc_status mlmc_timer_read(const char *name, double *total_ms, int64_t *launches) {
-    if (!name || !total_ms || !launches) return fail(MLMC_ERR_INVALID_ARG, "timer_read: NULL argument");
-    std::lock_guard<std::mutex> lk(g_timer_mu);
-    double total = 0.0;
-    int64_t count = 0;
-    for (auto &r : g_timer_recs) {
-        if (std::strcmp(r.name, name) != 0) continue;
-        HIP_TRY(hipEventSynchronize(r.stop), "timer_read");
-        float ms = 0.0f;
-        HIP_TRY(hipEventElapsedTime(&ms, r.start, r.stop), "timer_read");
-        total += ms;
-        ++count;
-    }
-    *total_ms = total;
-    *launches = count;
-    return MLMC_OK;
-}
-
-}  // extern "C"

@@ -228,6 +228,9 @@ __device__ __forceinline__ int sturm_count_newton(const double *d, const double 
 // what the smoothed IDoS resolves (a shift dE of one eigenvalue moves I by at
 // most dE g'_max / (delta N^2 |F|)).
 constexpr double kBisectAbsTol = 1e-12;
+// Counts per eigenvalue that may take Newton or closing points; later counts
+// bisect.  On the honeycomb tridiagonals an eigenvalue takes about 10 to 25.
+constexpr int kNewtonCounts = 48;
 
 // All eigenvalues of (d, e) by bisection on Sturm counts, in double
 // precision.  The Gershgorin interval is first cut at blockDim.x points
@@ -243,12 +246,11 @@ constexpr double kBisectAbsTol = 1e-12;
 // that much, which close the bracket around it.  Every point only moves a
 // side of a bracket that the counts certify, so the result has the bound of
 // plain bisection; on the honeycomb tridiagonals the slowest thread makes
-// about a third of the counts.  Two counts in a row that do not halve the
-// bracket (measured from its width at the last halving) force a midpoint
-// next, so every three counts at least halve it: from the first cut (1/256
-// of the Gershgorin interval) to the final width takes at most
-// log2(1 / (256 eps)) < 45 halvings, i.e. at most 135 counts, and the loop
-// never stops before the bracket is final.  One count per loop turn, at whatever point
+// about a third of the counts.  After kNewtonCounts counts on one
+// eigenvalue every further point is the midpoint, so every further count
+// halves the bracket: from the first cut (1/256 of the Gershgorin interval)
+// to the final width takes at most log2(1 / (256 eps)) < 45 halvings, and the
+// loop never stops before the bracket is final.  One count per loop turn, at whatever point
 // each thread chose, keeps the threads of a wavefront in step; a thread
 // moves on to its next eigenvalue as soon as one is done.
 // e is squared in place.  w[i] = i-th smallest eigenvalue.
@@ -279,8 +281,8 @@ __device__ inline void bisect_block(const double *d, double *e, int n, double *w
     if (t == 0) cnt[0] = 0;
     __syncthreads();
     int i = t;
-    double lo = 0.0, hi = 0.0, xn = NAN, dxprev = INFINITY, xc = 0.0, h = 0.0, wref = 0.0;
-    int clo = 0, chi = 0, mode = 0, stall = 0;  // mode 1 / 2: count at xc - h / xc + h next
+    double lo = 0.0, hi = 0.0, xn = NAN, dxprev = INFINITY, xc = 0.0, h = 0.0;
+    int clo = 0, chi = 0, mode = 0, its = 0;  // mode 1 / 2: count at xc - h / xc + h next
     auto start = [&]() {
         int a = 0, b = nt;  // find g with cnt[g] <= i < cnt[g + 1]
         while (b - a > 1) {
@@ -294,8 +296,7 @@ __device__ inline void bisect_block(const double *d, double *e, int n, double *w
         xn = NAN;
         dxprev = INFINITY;
         mode = 0;
-        wref = hi - lo;
-        stall = 0;
+        its = 0;
     };
     if (i < n) start();
     while (i < n) {
@@ -305,9 +306,7 @@ __device__ inline void bisect_block(const double *d, double *e, int n, double *w
         bool done = width <= tolw;
         double x = mid;
         int kind = 0;  // 0 midpoint, 1 Newton iterate, 2 / 3 closing counts
-        if (!done && stall >= 2) {  // two counts without halving: bisect
-            mode = 0;
-            xn = NAN;
+        if (!done && its >= kNewtonCounts) {  // past the Newton budget: bisect
             if (mid <= lo || mid >= hi) done = true;
         } else if (!done) {
             if (mode == 1) {
@@ -329,13 +328,8 @@ __device__ inline void bisect_block(const double *d, double *e, int n, double *w
         }
         double dx;
         const int c = sturm_count_newton(d, e, n, x, pivmin, &dx);
+        ++its;
         if (c > i) { hi = x; chi = c; } else { lo = x; clo = c; }
-        if (hi - lo <= 0.5 * wref) {
-            wref = hi - lo;
-            stall = 0;
-        } else {
-            ++stall;
-        }
         const double st = (double)(chi - clo) * dx;
         if (kind == 2) {
             mode = 2;

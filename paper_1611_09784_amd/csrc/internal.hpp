@@ -145,7 +145,7 @@ hipError_t launch_idos(const double *w, int64_t ldw, const int32_t *n, int64_t n
                        const double *kweight, double inv_area, const double *eps, int n_eps, double delta,
                        int smoother, double *out, hipStream_t s);
 hipError_t launch_level_stats(const double *fine, const double *quarters, int64_t n_samples, int n_eps,
-                              double *stats, hipStream_t s);
+                              double *stats, hipStream_t s, double *y_out = nullptr, double *q_out = nullptr);
 
 // ---------------------------------------------------------------------------
 // Deterministic block reductions (fixed butterfly order within a wave, then

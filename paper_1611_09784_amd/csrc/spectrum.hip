@@ -138,9 +138,12 @@ hipError_t launch_idos(const double *w, int64_t ldw, const int32_t *n, int64_t n
 
 // ---------------------------------------------------------------------------
 // Level sums of eq. (MLMC): thread = energy, samples accumulated in order.
+// Optionally the per-sample values Y_s and Q_s themselves (rows of y_out,
+// q_out); stats may be null when only those are wanted.
 // ---------------------------------------------------------------------------
 __global__ void level_stats_kernel(const double *__restrict__ fine, const double *__restrict__ quarters,
-                                   int64_t n_samples, int n_eps, double *__restrict__ stats) {
+                                   int64_t n_samples, int n_eps, double *__restrict__ stats,
+                                   double *__restrict__ y_out, double *__restrict__ q_out) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n_eps) return;
     double sy = 0.0, syy = 0.0, sq = 0.0, sqq = 0.0;
@@ -151,11 +154,14 @@ __global__ void level_stats_kernel(const double *__restrict__ fine, const double
             const double *q = quarters + s * 4 * (int64_t)n_eps;
             y = qf - 0.25 * (q[j] + q[n_eps + j] + q[2 * n_eps + j] + q[3 * n_eps + j]);
         }
+        if (y_out) y_out[s * n_eps + j] = y;
+        if (q_out) q_out[s * n_eps + j] = qf;
         sy += y;
         syy += y * y;
         sq += qf;
         sqq += qf * qf;
     }
+    if (!stats) return;
     stats[j] += sy;
     stats[n_eps + j] += syy;
     stats[2 * n_eps + j] += sq;
@@ -163,11 +169,11 @@ __global__ void level_stats_kernel(const double *__restrict__ fine, const double
 }
 
 hipError_t launch_level_stats(const double *fine, const double *quarters, int64_t n_samples, int n_eps,
-                              double *stats, hipStream_t s) {
+                              double *stats, hipStream_t s, double *y_out, double *q_out) {
     if (n_eps == 0 || n_samples == 0) return hipSuccess;
     const int threads = 128;
     hipLaunchKernelGGL(level_stats_kernel, dim3((n_eps + threads - 1) / threads), dim3(threads), 0, s, fine, quarters,
-                       n_samples, n_eps, stats);
+                       n_samples, n_eps, stats, y_out, q_out);
     return hipGetLastError();
 }
 

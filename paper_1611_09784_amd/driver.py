@@ -54,7 +54,9 @@ class MLMCResult:
 
 
 class Estimator:
-    """Runs level calls on one device with a reusable workspace."""
+    """Runs level calls on one device with a reusable workspace and its own
+    pipeline context (the chase and back streams of the level calls);
+    ``close()`` releases the context."""
 
     def __init__(self, dlat: B.DeviceLattice, eps: np.ndarray, delta: float, p: float, kind: int, seed: int,
                  smoother: int = B.MLMC_SMOOTH_GAUSS, prec: int = B.MLMC_PREC_FP64, chunk_samples: int = 64,
@@ -64,6 +66,7 @@ class Estimator:
         self.delta, self.p, self.kind, self.seed = float(delta), float(p), int(kind), int(seed)
         self.smoother, self.prec, self.chunk = int(smoother), int(prec), int(chunk_samples)
         self.stream = stream
+        self.ctx = B.Context(dlat.device.index)
         self._work = {}
         # levels whose matrices have at most this many orbitals solve each
         # distinct outcome once (0: off)
@@ -89,11 +92,17 @@ class Estimator:
         else:
             B.mlmc_level_estimate(self.dlat, lvl.N, lvl.coupled, self.p, lvl.K, lvl.K_coarse, self.kind, self.seed,
                                   lvl.M, count, self.eps, self.delta, self.smoother, self.prec, stats=stats,
-                                  work=self._workspace(lvl), stream=self.stream)
+                                  work=self._workspace(lvl), ctx=self.ctx, stream=self.stream)
         host = stats.cpu().numpy()
         lvl.seconds += time.perf_counter() - t0
         lvl.stats = host if lvl.stats is None else lvl.stats + host
         lvl.M += count
+
+    def close(self):
+        if self.ctx is not None:
+            self.ctx.close()
+            self.ctx = None
+        self._work.clear()
 
     # -- explicit outcomes (steps a3-a7 through the C ABI) -------------------
     def outcome_idos(self, N: int, masks: torch.Tensor, K: int, budget_bytes: int = 1 << 30) -> torch.Tensor:

@@ -60,13 +60,23 @@ def test_optimal_samples_matches_oracle(B):
 def test_validation_without_device(B):
     lib = B.lib()
     out = C.c_size_t()
+
+    def eig_ws(dtype, prec, ld, batch, op=B.MLMC_OP_BATCHED_EIGVALSH):
+        req = B._WorkspaceRequest(op, dtype, prec, ld, batch, None, 0, 0, 0, 0, 0, 0, 0)
+        return lib.mlmc_workspace_bytes(C.byref(req), C.byref(out))
+
     # unsupported dtype / precision pairs and oversize matrices are rejected up front
-    assert lib.mlmc_eigvalsh_workspace(B.MLMC_C128, B.MLMC_PREC_MIXED, 64, 1, C.byref(out)) == B.MLMC_ERR_UNSUPPORTED
-    assert lib.mlmc_eigvalsh_workspace(B.MLMC_C128, B.MLMC_PREC_FP64, 16385, 1, C.byref(out)) == B.MLMC_ERR_UNSUPPORTED
-    assert lib.mlmc_eigvalsh_workspace(B.MLMC_C128, B.MLMC_PREC_FP64, 64, 10, C.byref(out)) == B.MLMC_OK
+    assert eig_ws(B.MLMC_C128, B.MLMC_PREC_MIXED, 64, 1) == B.MLMC_ERR_UNSUPPORTED
+    assert eig_ws(B.MLMC_C128, B.MLMC_PREC_FP64, 16385, 1) == B.MLMC_ERR_UNSUPPORTED
+    assert eig_ws(B.MLMC_C128, B.MLMC_PREC_FP64, 64, 10) == B.MLMC_OK
     assert out.value == 0  # fused LDS path needs no workspace
-    assert lib.mlmc_eigvalsh_workspace(B.MLMC_C128, B.MLMC_PREC_FP64, 512, 10, C.byref(out)) == B.MLMC_OK
+    assert eig_ws(B.MLMC_C128, B.MLMC_PREC_FP64, 512, 10) == B.MLMC_OK
     assert out.value > 0
+    assert eig_ws(B.MLMC_C128, B.MLMC_PREC_FP64, 512, 10, op=7) == B.MLMC_ERR_INVALID_ARG
+    assert lib.mlmc_workspace_bytes(None, C.byref(out)) == B.MLMC_ERR_INVALID_ARG
+    # level query without a lattice
+    req = B._WorkspaceRequest(B.MLMC_OP_LEVEL_ESTIMATE, 0, 0, 0, 0, None, 4, 0, 1, 1, 0, 1, 11)
+    assert lib.mlmc_workspace_bytes(C.byref(req), C.byref(out)) == B.MLMC_ERR_INVALID_ARG
     # bad arguments return errors before any launch
     assert lib.mlmc_kgrid(0, 0, None, None, None) == B.MLMC_ERR_INVALID_ARG
     assert lib.mlmc_kgrid(7, 4, None, None, None) == B.MLMC_ERR_INVALID_ARG
@@ -74,7 +84,12 @@ def test_validation_without_device(B):
     assert lib.mlmc_idos(None, 8, None, 1, 1, None, -1.0, None, 5, 0.1, 0, None, None) == B.MLMC_ERR_INVALID_ARG
     assert lib.mlmc_sample_vacancies(None, 4, 0.1, 0, 0, 0, 1, None, None) == B.MLMC_ERR_INVALID_ARG
     assert lib.mlmc_level_estimate(None, 4, 0, 0.1, 1, 1, 0, 0, 0, 1, None, 1, 0.1, 0, 0, None, None, 0,
-                                   None) == B.MLMC_ERR_INVALID_ARG
+                                   None, None) == B.MLMC_ERR_INVALID_ARG
+    assert lib.mlmc_level_outcomes(None, 4, 0, 1, 1, 0, None, 1, None, 1, 0.1, 0, 0, None, None, None, None, 0,
+                                   None, None) == B.MLMC_ERR_INVALID_ARG
+    assert lib.mlmc_context_create(None) == B.MLMC_ERR_INVALID_ARG
+    assert lib.mlmc_context_destroy(None) == B.MLMC_OK
+    assert lib.mlmc_context_timer(None, 4) == B.MLMC_ERR_INVALID_ARG
     assert lib.mlmc_lattice_create(None, None) == B.MLMC_ERR_INVALID_ARG
     assert b"NULL" in lib.mlmc_last_error()
     assert lib.mlmc_lattice_destroy(None) == B.MLMC_OK
@@ -88,6 +103,7 @@ def test_lattice_descriptor_layout(B):
     # the binding's ctypes structs match the C layout (8-byte aligned doubles)
     assert C.sizeof(B._Hop) == 32
     assert C.sizeof(B._LatticeDesc) == 72
+    assert C.sizeof(B._WorkspaceRequest) == 80
 
 
 def test_kgrid_points_host_only(B):
@@ -104,9 +120,13 @@ def test_kgrid_points_host_only(B):
 def test_generalized_workspace_limits(B):
     out = C.c_size_t()
     lib = B.lib()
-    assert lib.mlmc_generalized_workspace(B.MLMC_C128, B.MLMC_PREC_FP64, 2049, 1, C.byref(out)) == \
-        B.MLMC_ERR_UNSUPPORTED
-    assert lib.mlmc_generalized_workspace(B.MLMC_C128, B.MLMC_PREC_FP64, 64, 3, C.byref(out)) == B.MLMC_OK
+    op = B.MLMC_OP_BATCHED_EIGVALSH_GENERALIZED
+
+    def gen_ws(dtype, prec, ld, batch):
+        req = B._WorkspaceRequest(op, dtype, prec, ld, batch, None, 0, 0, 0, 0, 0, 0, 0)
+        return lib.mlmc_workspace_bytes(C.byref(req), C.byref(out))
+
+    assert gen_ws(B.MLMC_C128, B.MLMC_PREC_FP64, 2049, 1) == B.MLMC_ERR_UNSUPPORTED
+    assert gen_ws(B.MLMC_C128, B.MLMC_PREC_FP64, 64, 3) == B.MLMC_OK
     assert out.value > 0                    # the generalised path always needs its workspace
-    assert lib.mlmc_generalized_workspace(B.MLMC_C64, B.MLMC_PREC_FP64, 64, 3, C.byref(out)) == \
-        B.MLMC_ERR_UNSUPPORTED
+    assert gen_ws(B.MLMC_C64, B.MLMC_PREC_FP64, 64, 3) == B.MLMC_ERR_UNSUPPORTED

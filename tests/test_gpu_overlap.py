@@ -115,8 +115,8 @@ def test_overlap_level_parity(B, odev, N, coupled, K, Kc, kind, prec, chunk):
 
 
 def test_overlap_level_alternating_streams(B, odev):
-    """Consecutive level calls of the overlap model on one workspace,
-    alternating between two streams (the Cholesky-reduction workspace shared
+    """Consecutive level calls of the overlap model with one pipeline context
+    on one workspace, alternating between two streams (the Cholesky-reduction workspace shared
     by the chunks of both calls): bit-identical to the same calls on one
     stream, and the oracle's sums over all samples."""
     say("[overlap level, alternating streams]")
@@ -127,17 +127,18 @@ def test_overlap_level_alternating_streams(B, odev):
     work = torch.empty((need,), dtype=torch.uint8, device=DEV)
     calls = [(0, 2), (2, 2), (4, 1)]
 
-    def run(streams):
+    def run(streams, ctx=None):
         stats = torch.zeros((4, eps.size), dtype=torch.float64, device=DEV)
         torch.cuda.synchronize()
         for i, (first, M) in enumerate(calls):
             B.mlmc_level_estimate(odev, N, False, 0.1, K, K, kind, 31, first, M, d_eps, 0.1, prec=prec, stats=stats,
-                                  work=work, stream=streams[i % len(streams)])
+                                  work=work, ctx=ctx, stream=streams[i % len(streams)])
         torch.cuda.synchronize()
         return stats.cpu().numpy()
 
     one = run([torch.cuda.current_stream()])
-    two = run([torch.cuda.current_stream(), torch.cuda.Stream(DEV)])
+    with B.Context() as ctx:
+        two = run([torch.cuda.current_stream(), torch.cuda.Stream(DEV)], ctx)
     assert np.array_equal(one, two)
     want = oracle.level_estimate(odev.lat, N, False, 0.1, K, K, kind, 31, 0, 5, eps, 0.1, 0, n_threads=8)
     assert np.abs(two[0] - want[0]).max() <= 5 * 1e-10

@@ -379,13 +379,13 @@ def test_level_estimate_pipelined_chunks(B, gdev, mdev, name, N, coupled, K, Kc,
 STREAM_CALLS = [(0, 5), (5, 3), (8, 4), (12, 1), (13, 5), (18, 2)]
 
 
-def run_level_calls(B, dl, N, coupled, K, Kc, kind, prec, eps, streams, work, calls=STREAM_CALLS, seed=929):
+def run_level_calls(B, dl, N, coupled, K, Kc, kind, prec, eps, streams, work, calls=STREAM_CALLS, seed=929, ctx=None):
     d_eps = torch.as_tensor(eps, device=DEV)
     stats = torch.zeros((4, eps.size), dtype=torch.float64, device=DEV)
     torch.cuda.synchronize()
     for i, (first, M) in enumerate(calls):
         B.mlmc_level_estimate(dl, N, coupled, 0.1, K, Kc, kind, seed, first, M, d_eps, 0.1, prec=prec, stats=stats,
-                              work=work, stream=streams[i % len(streams)])
+                              work=work, ctx=ctx, stream=streams[i % len(streams)])
     torch.cuda.synchronize()
     return stats.cpu().numpy()
 
@@ -396,11 +396,11 @@ def run_level_calls(B, dl, N, coupled, K, Kc, kind, prec, eps, streams, work, ca
     ("mos2", 4, True, 1, 2, 1, 0),         # MoS2-shaped fine n=176 on the two-stage path
 ])
 def test_level_estimate_calls_on_alternating_streams(B, gdev, mdev, name, N, coupled, K, Kc, kind, prec):
-    """Consecutive calls on one workspace, alternating between two streams
-    with no synchronisation between them, so that a call may start beside the
-    previous call's last chase and bisection.  The sums equal bit for bit
-    those of the same calls on one stream (both add them in call order), and
-    the oracle's over all samples."""
+    """Consecutive calls of one pipeline context on one workspace, alternating
+    between two streams with no synchronisation between them, so that a call
+    may start beside the previous call's last chase and bisection.  The sums
+    equal bit for bit those of the same calls without a context on one stream
+    (both add them in call order), and the oracle's over all samples."""
     say(f"[level_estimate alternating streams] {name} N={N} coupled={coupled} prec={prec}")
     dl = pick(name, gdev, mdev)
     if name == "graphene":
@@ -411,8 +411,9 @@ def test_level_estimate_calls_on_alternating_streams(B, gdev, mdev, name, N, cou
     need = B.mlmc_level_workspace(dl, N, coupled, K, Kc, kind, 2, prec, eps.size)
     work = torch.empty((need,), dtype=torch.uint8, device=DEV)
     one = run_level_calls(B, dl, N, coupled, K, Kc, kind, prec, eps, [torch.cuda.current_stream()], work)
-    two = run_level_calls(B, dl, N, coupled, K, Kc, kind, prec, eps, [torch.cuda.current_stream(),
-                                                                      torch.cuda.Stream(DEV)], work)
+    with B.Context() as ctx:
+        two = run_level_calls(B, dl, N, coupled, K, Kc, kind, prec, eps, [torch.cuda.current_stream(),
+                                                                          torch.cuda.Stream(DEV)], work, ctx=ctx)
     assert np.array_equal(one, two)
     M = sum(m for _, m in STREAM_CALLS)
     want = oracle.level_estimate(dl.lat, N, coupled, 0.1, K, Kc, kind, 929, 0, M, eps, 0.1, 0, n_threads=8)
@@ -521,3 +522,81 @@ def test_spairs_level_parity(B, pdev, coupled, K, Kc, prec):
                                 prec=prec).cpu().numpy()
     want = oracle.level_estimate(pdev.lat, N, coupled, 0.1, K, Kc, 1, 404, 5, M, eps, 0.1, 0, n_threads=8)
     compare_stats(got, want, M, 1e-10 if prec == 0 else 1e-5)
+
+
+def test_two_contexts_concurrent_streams(B, gdev):
+    """Two pipeline contexts, each with its own workspace and caller stream,
+    enqueue their calls interleaved with no synchronisation between them: each
+    context's sums equal bit for bit those of its calls made one after another
+    without a context on one stream."""
+    say("[two contexts, concurrent streams]")
+    eps = energy_grid(-9.0, 9.0, 201)
+    d_eps = torch.as_tensor(eps, device=DEV)
+    jobs = [(16, False, 1, 1, 0, 0, 929), (8, True, 2, 4, 1, 0, 313)]  # (N, coupled, K, Kc, kind, prec, seed)
+    works = []
+    for N, cpl, K, Kc, kind, prec, _ in jobs:
+        need = B.mlmc_level_workspace(gdev, N, cpl, K, Kc, kind, 2, prec, eps.size)
+        works.append(torch.empty((need,), dtype=torch.uint8, device=DEV))
+    calls = [(0, 3), (3, 2), (5, 4)]
+
+    def sequential(j):
+        N, cpl, K, Kc, kind, prec, seed = jobs[j]
+        stats = torch.zeros((4, eps.size), dtype=torch.float64, device=DEV)
+        for first, M in calls:
+            B.mlmc_level_estimate(gdev, N, cpl, 0.1, K, Kc, kind, seed, first, M, d_eps, 0.1, prec=prec, stats=stats,
+                                  work=works[j])
+        torch.cuda.synchronize()
+        return stats.cpu().numpy()
+
+    want = [sequential(0), sequential(1)]
+    streams = [torch.cuda.Stream(DEV), torch.cuda.Stream(DEV)]
+    stats = [torch.zeros((4, eps.size), dtype=torch.float64, device=DEV) for _ in jobs]
+    torch.cuda.synchronize()
+    with B.Context() as c0, B.Context() as c1:
+        ctxs = [c0, c1]
+        for first, M in calls:
+            for j, (N, cpl, K, Kc, kind, prec, seed) in enumerate(jobs):
+                B.mlmc_level_estimate(gdev, N, cpl, 0.1, K, Kc, kind, seed, first, M, d_eps, 0.1, prec=prec,
+                                      stats=stats[j], work=works[j], ctx=ctxs[j], stream=streams[j])
+        torch.cuda.synchronize()
+    for j in range(2):
+        assert np.array_equal(stats[j].cpu().numpy(), want[j])
+
+
+@pytest.mark.parametrize("name,N,coupled,K,Kc,kind,prec", [
+    ("graphene", 4, False, 2, 2, 1, 0),    # fused path
+    ("graphene", 16, True, 1, 2, 1, 0),    # two-stage fine, fused quarters
+    ("graphene", 16, True, 1, 2, 1, 1),    # mixed
+    ("mos2", 4, True, 1, 2, 1, 0),         # MoS2-shaped, two-stage fine
+])
+def test_level_outcomes(B, gdev, mdev, name, N, coupled, K, Kc, kind, prec):
+    """mlmc_level_outcomes on given outcomes: the level sums equal those of
+    mlmc_level_estimate on the same drawn outcomes bit for bit, every
+    outcome's rows equal those of the same outcome alone in a call of its own
+    bit for bit, and the oracle's per-outcome Y and Q_f (single-sample level
+    sums)."""
+    say(f"[level_outcomes] {name} N={N} coupled={coupled} prec={prec}")
+    dl = pick(name, gdev, mdev)
+    if name == "graphene":
+        eps = energy_grid(-9.0, 9.0, 101)
+    else:
+        b = dl.lat.hop_magnitude_bound() + 1.0
+        eps = energy_grid(-b, b, 101)
+    d_eps = torch.as_tensor(eps, device=DEV)
+    seed, first, M, p = 4242, 6, 5, 0.1
+    mask = B.mlmc_sample_vacancies(dl, N, p, seed, dl.tag(N), first, M)
+    want = B.mlmc_level_estimate(dl, N, coupled, p, K, Kc, kind, seed, first, M, d_eps, 0.1, prec=prec,
+                                 chunk_samples=2).cpu().numpy()
+    stats, Y, Q = B.mlmc_level_outcomes(dl, N, coupled, K, Kc, kind, mask, d_eps, 0.1, prec=prec, chunk_samples=2)
+    torch.cuda.synchronize()
+    assert np.array_equal(stats.cpu().numpy(), want)
+    Y, Q = Y.cpu().numpy(), Q.cpu().numpy()
+    tol = 1e-10 if prec == 0 else 1e-5
+    for s in range(M):
+        _, y1, q1 = B.mlmc_level_outcomes(dl, N, coupled, K, Kc, kind, mask[s:s + 1].contiguous(), d_eps, 0.1,
+                                          prec=prec, want_stats=False)
+        assert np.array_equal(y1.cpu().numpy()[0], Y[s])
+        assert np.array_equal(q1.cpu().numpy()[0], Q[s])
+        ref = oracle.level_estimate(dl.lat, N, coupled, p, K, Kc, kind, seed, first + s, 1, eps, 0.1, 0, n_threads=8)
+        assert np.abs(Y[s] - ref[0]).max() <= tol
+        assert np.abs(Q[s] - ref[2]).max() <= tol
