@@ -245,6 +245,24 @@ mlmc_status mlmc_batched_eigvalsh(mlmc_dtype dtype, mlmc_precision prec, void *d
                                   const int32_t *d_n, int64_t batch, double *d_w, int64_t ldw, void *d_work,
                                   size_t work_bytes, mlmc_stream stream);
 
+/* mlmc_batched_eigvalsh for callers that cannot allocate device memory or
+ * bring a workspace (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, layout and results as
+ * mlmc_batched_eigvalsh (the same kernels), without d_work: the two-stage
+ * path's scratch is a static 64 MiB device array of the library, one per
+ * device, kept from the library's load until the process ends; batches whose
+ * workspace exceeds it run in consecutive chunks on `stream`.  The call
+ * allocates nothing.  Every call on one device shares that array and leaves
+ * its contents behind (nothing in it has to start at zero), so calls that
+ * overlap on one device - on different streams, or from different threads
+ * without ordering - race; calls on one stream are ordered.
+ * Errors: as mlmc_batched_eigvalsh; MLMC_ERR_UNSUPPORTED when one matrix of
+ * side ld needs more than the 64 MiB (not the case for any ld the library
+ * supports). */
+mlmc_status mlmc_batched_eigvalsh_noalloc(mlmc_dtype dtype, mlmc_precision prec, void *d_H, int64_t ld,
+                                          const int32_t *d_n, int64_t batch, double *d_w, int64_t ldw,
+                                          mlmc_stream stream);
+
 /* All eigenvalues of a batch of Hermitian-definite pencils (H, S) (the
  * generalised problem H c = E S c of a non-orthogonal basis, Section 3.1):
  * S = L L^H (Cholesky) and C = L^{-1} H L^{-H}, both blocked on the GPU,

@@ -86,6 +86,7 @@ SIGNATURES = {
     "mlmc_build_hamiltonians": (C.c_int, [P, I32, P, I64, P, I32, C.c_int, P, I64, P, P]),
     "mlmc_workspace_bytes": (C.c_int, [P, P]),
     "mlmc_batched_eigvalsh": (C.c_int, [C.c_int, C.c_int, P, I64, P, I64, P, I64, P, SZ, P]),
+    "mlmc_batched_eigvalsh_noalloc": (C.c_int, [C.c_int, C.c_int, P, I64, P, I64, P, I64, P]),
     "mlmc_build_overlaps": (C.c_int, [P, I32, P, I64, P, I32, C.c_int, P, I64, P, P]),
     "mlmc_batched_eigvalsh_generalized": (C.c_int, [C.c_int, C.c_int, P, P, I64, P, I64, P, I64, P, SZ, P]),
     "mlmc_idos": (C.c_int, [P, I64, P, I64, I32, P, DBL, P, I32, DBL, C.c_int, P, P]),
@@ -434,6 +435,29 @@ def mlmc_batched_eigvalsh(H, n, prec=None, w=None, ldw=None, work=None, stream=N
     wb = 0 if work is None else work.numel() * work.element_size()
     _check(lib().mlmc_batched_eigvalsh(dtype, prec, _ptr(H), ld, _ptr(n), batch, _ptr(w), ldw, _ptr(work), wb,
                                        _stream(stream)), "mlmc_batched_eigvalsh")
+    return w
+
+
+def mlmc_batched_eigvalsh_noalloc(H, n, prec=None, w=None, ldw=None, stream=None):
+    """mlmc_batched_eigvalsh on the library's static device scratch (no
+    workspace argument, no allocation in the library); H is overwritten."""
+    if H.dtype == torch.complex128:
+        dtype = MLMC_C128
+    elif H.dtype == torch.complex64:
+        dtype = MLMC_C64
+    else:
+        raise ValueError("H must be complex64 or complex128")
+    if prec is None:
+        prec = MLMC_PREC_FP64 if dtype == MLMC_C128 else MLMC_PREC_MIXED
+    _dev(H, None, "H")
+    _dev(n, torch.int32, "n")
+    batch, ld = H.shape[0], H.shape[1]
+    ldw = ld if ldw is None else ldw
+    if w is None:
+        w = torch.zeros((batch, ldw), dtype=torch.float64, device=H.device)
+    _dev(w, torch.float64, "w")
+    _check(lib().mlmc_batched_eigvalsh_noalloc(dtype, prec, _ptr(H), ld, _ptr(n), batch, _ptr(w), ldw,
+                                               _stream(stream)), "mlmc_batched_eigvalsh_noalloc")
     return w
 
 

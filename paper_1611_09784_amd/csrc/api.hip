@@ -19,6 +19,14 @@ struct mlmc_lattice_s {
     void *d_buf = nullptr;
 };
 
+// Device scratch of mlmc_batched_eigvalsh_noalloc: the two-stage
+// reduction's per-matrix workspace for as many matrices as fit, reused chunk
+// after chunk.  Each device holds its own copy from the library's load until
+// the process ends.  Host code never passes this name to a kernel; it uses
+// the device address that hipGetSymbolAddress gives for the current device.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -661,6 +669,89 @@ mlmc_status mlmc_batched_eigvalsh(mlmc_dtype dtype, mlmc_precision prec, void *d
     EigBuffers b;
     carve_large(cv, prec, ld, batch, false, b);
     return run_large(prec, d_H, ld, d_n, batch, d_w, ldw, b, s);
+}
+
+}  // extern "C"
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+
+// Device address of `scratch` on each device, looked up once per device with
+// that device current (the only per-process state of the library besides
+// the caller's handles; written once, then read only).
+struct ScratchAddress {
+    std::once_flag once;
+    void *ptr = nullptr;
+    hipError_t err = hipSuccess;
+};
+ScratchAddress g_scratch_addr[kMaxDevices];
+
+hipError_t scratch_address(void **out) {
+    int dev = 0;
+    hipError_t err = hipGetDevice(&dev);
+    if (err != hipSuccess) return err;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    ScratchAddress &a = g_scratch_addr[dev];
+    std::call_once(a.once, [&a]() { a.err = hipGetSymbolAddress(&a.ptr, HIP_SYMBOL(scratch)); });
+    if (a.err != hipSuccess) return a.err;
+    *out = a.ptr;
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+mlmc_status mlmc_batched_eigvalsh_noalloc(mlmc_dtype dtype, mlmc_precision prec, void *d_H, int64_t ld,
+                                          const int32_t *d_n, int64_t batch, double *d_w, int64_t ldw,
+                                          mlmc_stream stream) {
+    size_t one = 0;
+    mlmc_status st = eigvalsh_workspace(dtype, prec, ld, 1, &one);
+    if (st != MLMC_OK) return st;
+    if (batch < 0) return fail(MLMC_ERR_INVALID_ARG, "batched_eigvalsh_noalloc: batch %lld", (long long)batch);
+    if (ldw < ld)
+        return fail(MLMC_ERR_INVALID_ARG, "batched_eigvalsh_noalloc: ldw %lld < ld %lld", (long long)ldw, (long long)ld);
+    if (batch > 0 && (!d_H || !d_n || !d_w)) return fail(MLMC_ERR_INVALID_ARG, "batched_eigvalsh_noalloc: NULL buffer");
+    if (one > kNoAllocScratchBytes)
+        return fail(MLMC_ERR_UNSUPPORTED,
+                    "batched_eigvalsh_noalloc: one matrix of side %lld needs %zu bytes of scratch, more than the "
+                    "%zu bytes this entry point has", (long long)ld, one, kNoAllocScratchBytes);
+    if (batch == 0 || ld == 0) return MLMC_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (one == 0) {  // LDS-resident path: no scratch
+        if (prec == MLMC_PREC_FP64)
+            LAUNCH("small_fused", s, launch_small_from_matrix<double>(static_cast<const cpx<double> *>(d_H), ld, d_n, batch, d_w, ldw, s));
+        else
+            LAUNCH("small_fused", s, launch_small_from_matrix<float>(static_cast<const cpx<float> *>(d_H), ld, d_n, batch, d_w, ldw, s));
+        return MLMC_OK;
+    }
+    void *base = nullptr;
+    HIP_TRY(scratch_address(&base), "batched_eigvalsh_noalloc: scratch address");
+    // The largest number of matrices whose workspace fits the scratch.
+    int64_t chunk = (int64_t)(kNoAllocScratchBytes / one);
+    if (chunk > batch) chunk = batch;
+    for (;;) {
+        size_t need = 0;
+        st = eigvalsh_workspace(dtype, prec, ld, chunk, &need);
+        if (st != MLMC_OK) return st;
+        if (need <= kNoAllocScratchBytes || chunk == 1) break;
+        --chunk;
+    }
+    // Chunks run one after another on `stream`, so each reuses the scratch
+    // after the previous one is done with it.  Nothing in the workspace has
+    // to start at zero: every kernel writes what it later reads.
+    const size_t esize = cplx_bytes(prec);
+    for (int64_t u0 = 0; u0 < batch; u0 += chunk) {
+        const int64_t units = (batch - u0 < chunk) ? (batch - u0) : chunk;
+        Carver cv{static_cast<char *>(base)};
+        EigBuffers b;
+        carve_large(cv, prec, ld, units, false, b);
+        char *H = static_cast<char *>(d_H) + (size_t)u0 * (size_t)ld * (size_t)ld * esize;
+        st = run_large(prec, H, ld, d_n + u0, units, d_w + u0 * ldw, ldw, b, s);
+        if (st != MLMC_OK) return st;
+    }
+    return MLMC_OK;
 }
 
 static mlmc_status generalized_workspace(mlmc_dtype dtype, mlmc_precision prec, int64_t ld, int64_t batch,
