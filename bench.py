@@ -162,6 +162,9 @@ def parse():
     ap.add_argument("--mlmc", dest="mlmc", action="store_true", default=True,
                     help="also time the MLMC estimator to TOL (graphene levels N = 4..32), FP64 and mixed")
     ap.add_argument("--no-mlmc", dest="mlmc", action="store_false")
+    ap.add_argument("--serve-requests", type=int, default=160, help="requests per served run (--workload served)")
+    ap.add_argument("--serve-slots", type=int, default=4, help="batches in flight at once (--workload served)")
+    ap.add_argument("--serve-budget-gb", type=float, default=200.0, help="HBM budget of the server (GB)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy three times (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counter scale) and exit")
@@ -390,6 +393,51 @@ def measure(B, wl, lat, eps, prec, args, dev):
             "roofline": roofline, "reduction_tflops_16_3_n3": round(flops / elapsed / 1e12, 3)}
 
 
+def served(B, args, dev):
+    """The served stream: Poisson arrivals (seed 5050) of single-sample MLMC
+    requests, lattice uniform over {graphene, MoS2-shaped}, N in {4, 8, 16, 32}
+    with weights 0.55 / 0.30 / 0.12 / 0.03, K = 32 / N (levels above N = 4
+    coupled with their quarters), 401 energies, delta = 0.05, p = 0.02, served
+    by continuous batching under an HBM budget.  First the saturation rate of
+    each path (every request waiting at the start), then three offered loads,
+    0.5x, 0.8x and 1.2x the FP64 saturation rate, each path on the same
+    arrival stream; p50 / p99 latency and eigensolves/s per run."""
+    from mlmc_inputs import energy_grid, graphene, mos2_shaped
+    from mlmc_inputs.configs import mos2_energy_window
+    from paper_1611_09784_amd.serve import (BatchLimits, GpuExecutor, Request, Server, StreamSpec, poisson_requests,
+                                            summarize_classes)
+    lats = {"graphene": graphene(), "mos2_shaped": mos2_shaped()}
+    lo, hi = mos2_energy_window(lats["mos2_shaped"])
+    eps = {"graphene": energy_grid(-9.0, 9.0, 401), "mos2_shaped": energy_grid(lo, hi, 401)}
+    budget = int(args.serve_budget_gb * 1e9)
+    limits = BatchLimits()
+    R = args.serve_requests
+    out = {"requests_per_run": R, "slots": args.serve_slots, "budget_gb": args.serve_budget_gb,
+           "batch_limits": {"max_requests": limits.max_requests, "max_solves": limits.max_solves,
+                            "max_gb": round(limits.max_bytes / 1e9, 2)}}
+    base_rate = None
+    for name, prec in (("fp64", B.MLMC_PREC_FP64), ("mixed", B.MLMC_PREC_MIXED)):
+        ex = GpuExecutor(lats, eps, 0.05, 0.02, prec, slots=args.serve_slots, device=0)
+        srv = Server(ex, budget, slots=args.serve_slots, limits=limits)
+        warm = [Request(i, lat, N, seed=9999, index=0, arrival=0.0)
+                for i, (lat, N) in enumerate((l, n) for l in lats for n in (4, 8, 16, 32))]
+        srv.run(warm)
+        sat = srv.run(poisson_requests(StreamSpec(rate=0.0, count=R)))
+        rec = {"saturation": sat.summary()}
+        print(f"[bench] served {name} saturation: {rec['saturation']}", file=sys.stderr, flush=True)
+        if base_rate is None:
+            base_rate = len(sat.requests) / sat.seconds
+        for f in (0.5, 0.8, 1.2):
+            rep = srv.run(poisson_requests(StreamSpec(rate=f * base_rate, count=R)))
+            rec[f"load_{f}x"] = {"offered_requests_per_s": round(f * base_rate, 3), **rep.summary(),
+                                 "per_class": summarize_classes(rep.requests)}
+            print(f"[bench] served {name} load {f}x: {rep.summary()}", file=sys.stderr, flush=True)
+        out[name] = rec
+        ex.close()
+    out["fp64_saturation_requests_per_s"] = round(base_rate, 3)
+    return out
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -405,6 +453,23 @@ def main():
     from mlmc_inputs import WORKLOADS
     from mlmc_inputs.configs import workload_eps
     from paper_1611_09784_amd import binding as B
+
+    if args.workload == "served":
+        dev = torch.device("cuda", 0)
+        torch.cuda.set_device(dev)
+        rec = served(B, args, dev)
+        fp, mx = rec["fp64"]["saturation"], rec["mixed"]["saturation"]
+        print(json.dumps({
+            "metric": METRIC, "value": fp["eigensolves_per_s"], "unit": "eigensolves/s", "n_gpus": 1,
+            "steps": args.serve_requests, "warmup": 1, "ms_per_step": round(1e3 * fp["seconds"] / fp["requests"], 3),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "served", "lattices": ["graphene", "mos2_shaped"], "N": [4, 8, 16, 32],
+                       "N_weights": [0.55, 0.30, 0.12, 0.03], "K": "32/N", "p": 0.02, "n_eps": 401, "delta": 0.05,
+                       "arrival_seed": 5050, "step": "one request"},
+            "served": rec,
+            "speedup_mixed_vs_fp64_saturation": round(mx["eigensolves_per_s"] / fp["eigensolves_per_s"], 3),
+        }), flush=True)
+        return
 
     wl = WORKLOADS[args.workload]
     lat = wl.make_lattice()

@@ -121,9 +121,11 @@ typedef struct mlmc_context_s *mlmc_context;
 typedef enum {
     MLMC_OP_BATCHED_EIGVALSH = 0,             /* mlmc_batched_eigvalsh: dtype, prec, ld, batch          */
     MLMC_OP_BATCHED_EIGVALSH_GENERALIZED = 1, /* mlmc_batched_eigvalsh_generalized: dtype, prec, ld, batch */
-    MLMC_OP_LEVEL_ESTIMATE = 2                /* mlmc_level_estimate and mlmc_level_outcomes: lat, N_fine,
+    MLMC_OP_LEVEL_ESTIMATE = 2,               /* mlmc_level_estimate and mlmc_level_outcomes: lat, N_fine,
                                                  coupled, K_fine, K_coarse, kgrid, chunk_samples, prec,
                                                  n_eps                                                   */
+    MLMC_OP_LEVEL_OUTCOMES_SINGLE_PASS = 3    /* mlmc_level_outcomes taking chunk_samples outcomes in one
+                                                 pass (one buffer set): the fields of MLMC_OP_LEVEL_ESTIMATE */
 } mlmc_op;
 
 /* Arguments of a workspace query; fields an operation does not use are ignored. */
@@ -224,7 +226,10 @@ mlmc_status mlmc_build_overlaps(mlmc_lattice lat, int32_t N, const uint8_t *d_ma
  *   MLMC_OP_BATCHED_EIGVALSH_GENERALIZED: `batch` pencils of side bound ld.
  *   MLMC_OP_LEVEL_ESTIMATE: a level call that processes chunk_samples samples
  *     per pass (the call uses the largest chunk that fits the workspace it is
- *     given).
+ *     given), with three buffer sets that consecutive chunks take in turn.
+ *   MLMC_OP_LEVEL_OUTCOMES_SINGLE_PASS: mlmc_level_outcomes on up to
+ *     chunk_samples outcomes in a single pass with one buffer set (about a
+ *     third of the matrix memory of the pipelined layout).
  * Errors: NULL arguments, unknown op, the operation's own argument checks
  * (MLMC_ERR_UNSUPPORTED for sizes beyond the library's limits). */
 mlmc_status mlmc_workspace_bytes(const mlmc_workspace_request *req, size_t *bytes);
@@ -369,8 +374,11 @@ mlmc_status mlmc_level_estimate(mlmc_lattice lat, int32_t N_fine, int32_t couple
  * ([4][n_eps], accumulated) receives the level sums as in
  * mlmc_level_estimate.  Any of the three may be NULL, not all.  Every
  * outcome's rows depend on that outcome alone (not on the others of the
- * call), which is what a server that batches requests relies on.  Workspace,
- * context and streams as mlmc_level_estimate.
+ * call), which is what a server that batches requests relies on.  When the
+ * workspace holds all M outcomes in a single pass with one buffer set
+ * (MLMC_OP_LEVEL_OUTCOMES_SINGLE_PASS), the call takes that pass; otherwise
+ * it works in chunks like mlmc_level_estimate.  Context and streams as
+ * mlmc_level_estimate.
  * Errors: as mlmc_level_estimate, NULL mask, no output. */
 mlmc_status mlmc_level_outcomes(mlmc_lattice lat, int32_t N_fine, int32_t coupled, int32_t K_fine, int32_t K_coarse,
                                 mlmc_kgrid_kind kind, const uint8_t *d_mask, int64_t M, const double *d_eps,

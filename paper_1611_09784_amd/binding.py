@@ -38,6 +38,7 @@ MLMC_SMOOTH_CUBIC = 1
 MLMC_OP_BATCHED_EIGVALSH = 0
 MLMC_OP_BATCHED_EIGVALSH_GENERALIZED = 1
 MLMC_OP_LEVEL_ESTIMATE = 2
+MLMC_OP_LEVEL_OUTCOMES_SINGLE_PASS = 3
 
 # Largest matrix side of the LDS-resident fused path / of the device-memory path.
 SMALL_MAX = {MLMC_PREC_FP64: 128, MLMC_PREC_MIXED: 180}
@@ -492,6 +493,12 @@ def mlmc_level_workspace(dlat, N, coupled, K_fine, K_coarse, kind, chunk_samples
                                 n_eps=n_eps)
 
 
+def mlmc_level_outcomes_workspace(dlat, N, coupled, K_fine, K_coarse, kind, n_outcomes, prec, n_eps) -> int:
+    """Workspace bytes for mlmc_level_outcomes on n_outcomes outcomes in one pass."""
+    return mlmc_workspace_bytes(MLMC_OP_LEVEL_OUTCOMES_SINGLE_PASS, prec=prec, dlat=dlat, N_fine=N, coupled=coupled,
+                                K_fine=K_fine, K_coarse=K_coarse, kgrid=kind, chunk_samples=n_outcomes, n_eps=n_eps)
+
+
 def mlmc_level_estimate(dlat, N, coupled, p, K_fine, K_coarse, kind, seed, first_sample, M, eps, delta,
                         smoother=MLMC_SMOOTH_GAUSS, prec=MLMC_PREC_FP64, stats=None, work=None, chunk_samples=None,
                         ctx=None, stream=None):
@@ -533,8 +540,10 @@ def mlmc_level_outcomes(dlat, N, coupled, K_fine, K_coarse, kind, mask, eps, del
         if t is not None:
             _dev(t, torch.float64, name)
     if work is None:
-        chunk = max(1, min(M, 64) if chunk_samples is None else chunk_samples)
-        need = mlmc_level_workspace(dlat, N, coupled, K_fine, K_coarse, kind, chunk, prec, ne)
+        if chunk_samples is None:  # all outcomes in one pass
+            need = mlmc_level_outcomes_workspace(dlat, N, coupled, K_fine, K_coarse, kind, max(1, M), prec, ne)
+        else:
+            need = mlmc_level_workspace(dlat, N, coupled, K_fine, K_coarse, kind, chunk_samples, prec, ne)
         work = torch.empty((need,), dtype=torch.uint8, device=eps.device)
     _check(lib().mlmc_level_outcomes(dlat.handle, N, int(coupled), K_fine, K_coarse, kind, _ptr(mask), M, _ptr(eps),
                                      ne, float(delta), smoother, prec, _ptr(stats), _ptr(Y), _ptr(Q), _ptr(work),

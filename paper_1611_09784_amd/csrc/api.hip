@@ -234,6 +234,7 @@ struct LevelLayout {
     double *wf[kLevelSets] = {}, *wc[kLevelSets] = {};
     double *If = nullptr, *Ic = nullptr;
     EigBuffers bf, bc;
+    int sets = kLevelSets;  // buffer sets in use (1: a single pass)
     size_t bytes = 0;
 };
 
@@ -242,40 +243,41 @@ static bool valid_kgrid_kind(int kind) {
 }
 
 LevelLayout level_layout(const mlmc_lattice_s *lat, int N, bool coupled, int Kf, int Kc, int kind, int64_t mc,
-                         mlmc_precision prec, int n_eps, char *base) {
+                         mlmc_precision prec, int n_eps, char *base, int sets = kLevelSets) {
     LevelLayout L;
+    L.sets = sets;
     Carver cv{base};
     const int G = lat->dev.n_groups, no = lat->dev.n_orb;
     const int64_t nkf = kgrid_count(kind, Kf), nkc = kgrid_count(kind, Kc);
     const int64_t ldf = (int64_t)no * N * N;
-    for (int q = 0; q < kLevelSets; ++q) {
+    for (int q = 0; q < sets; ++q) {
         L.kf[q] = cv.take<double>(sizeof(double) * 2 * nkf);
         L.kwf[q] = cv.take<double>(sizeof(double) * nkf);
     }
     L.mask = cv.take<uint8_t>((size_t)mc * N * N * G);
-    for (int q = 0; q < kLevelSets; ++q) {
+    for (int q = 0; q < sets; ++q) {
         L.nf[q] = cv.take<int32_t>(sizeof(int32_t) * (size_t)(mc * nkf));
         L.wf[q] = cv.take<double>(sizeof(double) * (size_t)(mc * nkf * ldf));
     }
     L.If = cv.take<double>(sizeof(double) * (size_t)mc * n_eps);
     const bool gen = lat->dev.n_ovl > 0;
-    if (gen) carve_generalized(cv, prec, ldf, mc * nkf, true, L.bf, kLevelSets);
-    else if (ldf > small_cap(prec)) carve_large(cv, prec, ldf, mc * nkf, true, L.bf, kLevelSets);
+    if (gen) carve_generalized(cv, prec, ldf, mc * nkf, true, L.bf, sets);
+    else if (ldf > small_cap(prec)) carve_large(cv, prec, ldf, mc * nkf, true, L.bf, sets);
     if (coupled) {
         const int h = N / 2;
         const int64_t ldc = (int64_t)no * h * h;
-        for (int q = 0; q < kLevelSets; ++q) {
+        for (int q = 0; q < sets; ++q) {
             L.kc[q] = cv.take<double>(sizeof(double) * 2 * nkc);
             L.kwc[q] = cv.take<double>(sizeof(double) * nkc);
         }
         L.quarters = cv.take<uint8_t>((size_t)mc * 4 * h * h * G);
-        for (int q = 0; q < kLevelSets; ++q) {
+        for (int q = 0; q < sets; ++q) {
             L.nc[q] = cv.take<int32_t>(sizeof(int32_t) * (size_t)(mc * 4 * nkc));
             L.wc[q] = cv.take<double>(sizeof(double) * (size_t)(mc * 4 * nkc * ldc));
         }
         L.Ic = cv.take<double>(sizeof(double) * (size_t)mc * 4 * n_eps);
-        if (gen) carve_generalized(cv, prec, ldc, mc * 4 * nkc, true, L.bc, kLevelSets);
-        else if (ldc > small_cap(prec)) carve_large(cv, prec, ldc, mc * 4 * nkc, true, L.bc, kLevelSets);
+        if (gen) carve_generalized(cv, prec, ldc, mc * 4 * nkc, true, L.bc, sets);
+        else if (ldc > small_cap(prec)) carve_large(cv, prec, ldc, mc * 4 * nkc, true, L.bc, sets);
     }
     L.bytes = cv.used;
     return L;
@@ -360,12 +362,12 @@ int64_t chase_cus(int cus) {
 struct LayoutKey {
     const void *work = nullptr;
     int64_t mc = 0, nkf = 0, nkc = 0;
-    int n_orb = 0, n_groups = 0, N = 0, n_eps = 0, prec = 0;
+    int n_orb = 0, n_groups = 0, N = 0, n_eps = 0, prec = 0, sets = 0;
     bool cpl = false, gen = false;
     bool operator==(const LayoutKey &o) const {
         return work == o.work && mc == o.mc && nkf == o.nkf && nkc == o.nkc && n_orb == o.n_orb &&
-               n_groups == o.n_groups && N == o.N && n_eps == o.n_eps && prec == o.prec && cpl == o.cpl &&
-               gen == o.gen;
+               n_groups == o.n_groups && N == o.N && n_eps == o.n_eps && prec == o.prec && sets == o.sets &&
+               cpl == o.cpl && gen == o.gen;
     }
 };
 
@@ -832,12 +834,13 @@ static mlmc_status check_level_args(mlmc_lattice lat, int32_t N, int32_t coupled
 
 static mlmc_status level_workspace(mlmc_lattice lat, int32_t N_fine, int32_t coupled, int32_t K_fine,
                                    int32_t K_coarse, mlmc_kgrid_kind kind, int64_t chunk_samples, mlmc_precision prec,
-                                   int32_t n_eps, size_t *bytes) {
+                                   int32_t n_eps, size_t *bytes, int sets = kLevelSets) {
     const mlmc_status st = check_level_args(lat, N_fine, coupled, K_fine, K_coarse, prec, n_eps);
     if (st != MLMC_OK) return st;
     if (!valid_kgrid_kind(kind)) return fail(MLMC_ERR_INVALID_ARG, "level_workspace: bad k-grid");
     if (chunk_samples < 1) return fail(MLMC_ERR_INVALID_ARG, "level_workspace: chunk_samples must be >= 1");
-    *bytes = level_layout(lat, N_fine, coupled != 0, K_fine, K_coarse, kind, chunk_samples, prec, n_eps, nullptr).bytes;
+    *bytes = level_layout(lat, N_fine, coupled != 0, K_fine, K_coarse, kind, chunk_samples, prec, n_eps, nullptr, sets)
+                 .bytes;
     return MLMC_OK;
 }
 
@@ -851,6 +854,9 @@ mlmc_status mlmc_workspace_bytes(const mlmc_workspace_request *req, size_t *byte
         case MLMC_OP_LEVEL_ESTIMATE:
             return level_workspace(req->lat, req->N_fine, req->coupled, req->K_fine, req->K_coarse, req->kgrid,
                                    req->chunk_samples, req->prec, req->n_eps, bytes);
+        case MLMC_OP_LEVEL_OUTCOMES_SINGLE_PASS:
+            return level_workspace(req->lat, req->N_fine, req->coupled, req->K_fine, req->K_coarse, req->kgrid,
+                                   req->chunk_samples, req->prec, req->n_eps, bytes, 1);
         default: return fail(MLMC_ERR_INVALID_ARG, "workspace_bytes: unknown operation %d", (int)req->op);
     }
 }
@@ -883,8 +889,13 @@ mlmc_status level_run(mlmc_context ctx, mlmc_lattice lat, int32_t N, bool cpl, d
                       mlmc_kgrid_kind kind, uint64_t seed, int64_t first_sample, const uint8_t *d_mask_in,
                       int64_t M, const double *d_eps, int32_t n_eps, double delta, mlmc_smoother smoother,
                       mlmc_precision prec, double *d_stats, double *d_Y, double *d_Q, void *d_work,
-                      size_t work_bytes, hipStream_t s) {
-    const size_t one = level_layout(lat, N, cpl, Kf, Kc, kind, 1, prec, n_eps, nullptr).bytes;
+                      size_t work_bytes, hipStream_t s, bool single_pass_ok = false) {
+    // A call allowed a single pass takes all M outcomes at once with one
+    // buffer set when the workspace holds that; otherwise chunks in turn
+    // over kLevelSets sets.
+    const bool single = single_pass_ok && d_work &&
+                        level_layout(lat, N, cpl, Kf, Kc, kind, M, prec, n_eps, nullptr, 1).bytes <= work_bytes;
+    const size_t one = level_layout(lat, N, cpl, Kf, Kc, kind, 1, prec, n_eps, nullptr, single ? 1 : kLevelSets).bytes;
     if (!d_work || work_bytes < one)
         return fail(MLMC_ERR_WORKSPACE, "level: workspace %zu < %zu bytes needed for one sample", work_bytes, one);
     if (ctx) {
@@ -893,13 +904,17 @@ mlmc_status level_run(mlmc_context ctx, mlmc_lattice lat, int32_t N, bool cpl, d
         if (dev != ctx->device)
             return fail(MLMC_ERR_INVALID_ARG, "level: context of device %d used on device %d", ctx->device, dev);
     }
-    const size_t two = level_layout(lat, N, cpl, Kf, Kc, kind, 2, prec, n_eps, nullptr).bytes;
-    const size_t per = two - one, fixed = one - per;
-    int64_t mc = (int64_t)((work_bytes - fixed) / per) + 2;  // padding makes the estimate approximate
-    if (mc > M) mc = M;
-    if (mc < 1) mc = 1;
-    while (mc > 1 && level_layout(lat, N, cpl, Kf, Kc, kind, mc, prec, n_eps, nullptr).bytes > work_bytes) --mc;
-    const LevelLayout L = level_layout(lat, N, cpl, Kf, Kc, kind, mc, prec, n_eps, static_cast<char *>(d_work));
+    int64_t mc = M;
+    if (!single) {
+        const size_t two = level_layout(lat, N, cpl, Kf, Kc, kind, 2, prec, n_eps, nullptr).bytes;
+        const size_t per = two - one, fixed = one - per;
+        mc = (int64_t)((work_bytes - fixed) / per) + 2;  // padding makes the estimate approximate
+        if (mc > M) mc = M;
+        if (mc < 1) mc = 1;
+        while (mc > 1 && level_layout(lat, N, cpl, Kf, Kc, kind, mc, prec, n_eps, nullptr).bytes > work_bytes) --mc;
+    }
+    const int nsets = single ? 1 : kLevelSets;
+    const LevelLayout L = level_layout(lat, N, cpl, Kf, Kc, kind, mc, prec, n_eps, static_cast<char *>(d_work), nsets);
     const int G = lat->dev.n_groups, h = N / 2;
     const uint64_t tag = ((uint64_t)lat->dev.lattice_id << 32) | (uint64_t)(uint32_t)N;
     const uint64_t thr = (uint64_t)std::floor(p * 9007199254740992.0);
@@ -936,6 +951,7 @@ mlmc_status level_run(mlmc_context ctx, mlmc_lattice lat, int32_t N, bool cpl, d
         key.prec = (int)prec;
         key.cpl = cpl;
         key.gen = lat->dev.n_ovl > 0;
+        key.sets = nsets;
         // The previous call's front part (masks, stage-1 workspace, the last
         // chunk's matrices) is complete before this call's front starts.
         HIP_TRY(hipStreamWaitEvent(s, ctx->ready, 0), "level: wait");
@@ -954,7 +970,7 @@ mlmc_status level_run(mlmc_context ctx, mlmc_lattice lat, int32_t N, bool cpl, d
             ctx->last = key;
             ctx->next_set = 0;
         }
-        set0 = ctx->next_set;
+        set0 = ctx->next_set % nsets;
     }
     // A call that fails part-way makes the next one on its context take the
     // path above, with the front and chase work it did enqueue covered by
@@ -976,7 +992,7 @@ mlmc_status level_run(mlmc_context ctx, mlmc_lattice lat, int32_t N, bool cpl, d
     for (int64_t done = 0; done < M; done += mc) {
         const int64_t ns = (M - done < mc) ? (M - done) : mc;
         const int q = next_set;
-        next_set = (q + 1) % kLevelSets;
+        next_set = (q + 1) % nsets;
         if (ctx) {
             ctx->next_set = next_set;
             HIP_TRY(hipStreamWaitEvent(s, ctx->freed[q], 0), "level: wait");
@@ -1095,7 +1111,7 @@ mlmc_status mlmc_level_outcomes(mlmc_lattice lat, int32_t N, int32_t coupled, in
     if (!d_mask) return fail(MLMC_ERR_INVALID_ARG, "level_outcomes: NULL mask");
     if (!d_stats && !d_Y && !d_Q) return fail(MLMC_ERR_INVALID_ARG, "level_outcomes: no output");
     return level_run(ctx, lat, N, coupled != 0, 0.0, Kf, Kc, kind, 0, 0, d_mask, M, d_eps, n_eps, delta, smoother,
-                     prec, d_stats, d_Y, d_Q, d_work, work_bytes, static_cast<hipStream_t>(stream));
+                     prec, d_stats, d_Y, d_Q, d_work, work_bytes, static_cast<hipStream_t>(stream), true);
 }
 
 mlmc_status mlmc_context_create(mlmc_context *out) {

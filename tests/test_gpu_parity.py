@@ -571,7 +571,8 @@ def test_two_contexts_concurrent_streams(B, gdev):
 ])
 def test_level_outcomes(B, gdev, mdev, name, N, coupled, K, Kc, kind, prec):
     """mlmc_level_outcomes on given outcomes: the level sums equal those of
-    mlmc_level_estimate on the same drawn outcomes bit for bit, every
+    mlmc_level_estimate on the same drawn outcomes bit for bit (both in one
+    pass), the rows do not depend on the chunking, every
     outcome's rows equal those of the same outcome alone in a call of its own
     bit for bit, and the oracle's per-outcome Y and Q_f (single-sample level
     sums)."""
@@ -585,11 +586,19 @@ def test_level_outcomes(B, gdev, mdev, name, N, coupled, K, Kc, kind, prec):
     d_eps = torch.as_tensor(eps, device=DEV)
     seed, first, M, p = 4242, 6, 5, 0.1
     mask = B.mlmc_sample_vacancies(dl, N, p, seed, dl.tag(N), first, M)
+    # one pass each: the same summation order, the same sums bit for bit
     want = B.mlmc_level_estimate(dl, N, coupled, p, K, Kc, kind, seed, first, M, d_eps, 0.1, prec=prec,
-                                 chunk_samples=2).cpu().numpy()
-    stats, Y, Q = B.mlmc_level_outcomes(dl, N, coupled, K, Kc, kind, mask, d_eps, 0.1, prec=prec, chunk_samples=2)
+                                 chunk_samples=M).cpu().numpy()
+    stats, Y, Q = B.mlmc_level_outcomes(dl, N, coupled, K, Kc, kind, mask, d_eps, 0.1, prec=prec)
     torch.cuda.synchronize()
     assert np.array_equal(stats.cpu().numpy(), want)
+    # chunks of two (the sums grouped per chunk): the same rows bit for bit, sums to rounding
+    stats2, Y2, Q2 = B.mlmc_level_outcomes(dl, N, coupled, K, Kc, kind, mask, d_eps, 0.1, prec=prec,
+                                           chunk_samples=2)
+    torch.cuda.synchronize()
+    assert np.array_equal(Y2.cpu().numpy(), Y.cpu().numpy())
+    assert np.array_equal(Q2.cpu().numpy(), Q.cpu().numpy())
+    assert np.allclose(stats2.cpu().numpy(), want, rtol=1e-14, atol=1e-15)
     Y, Q = Y.cpu().numpy(), Q.cpu().numpy()
     tol = 1e-10 if prec == 0 else 1e-5
     for s in range(M):
