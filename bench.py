@@ -401,11 +401,14 @@ def served(B, args, dev):
     by continuous batching under an HBM budget.  First the saturation rate of
     each path (every request waiting at the start), then three offered loads,
     0.5x, 0.8x and 1.2x the FP64 saturation rate, each path on the same
-    arrival stream; p50 / p99 latency and eigensolves/s per run."""
+    arrival stream; p50 / p99 latency and eigensolves/s per run.  Then the
+    MLMC estimator of the graphene hierarchy runs to TOL = 1e-3 as one client
+    of the server beside background requests at 0.5x that rate."""
     from mlmc_inputs import energy_grid, graphene, mos2_shaped
     from mlmc_inputs.configs import mos2_energy_window
-    from paper_1611_09784_amd.serve import (BatchLimits, GpuExecutor, Request, Server, StreamSpec, poisson_requests,
-                                            summarize_classes)
+    from paper_1611_09784_amd import driver as D
+    from paper_1611_09784_amd.serve import (BatchLimits, GpuExecutor, Request, Server, ServedEstimator, StreamSpec,
+                                            poisson_requests, summarize_classes)
     lats = {"graphene": graphene(), "mos2_shaped": mos2_shaped()}
     lo, hi = mos2_energy_window(lats["mos2_shaped"])
     eps = {"graphene": energy_grid(-9.0, 9.0, 401), "mos2_shaped": energy_grid(lo, hi, 401)}
@@ -432,6 +435,24 @@ def served(B, args, dev):
             rec[f"load_{f}x"] = {"offered_requests_per_s": round(f * base_rate, 3), **rep.summary(),
                                  "per_class": summarize_classes(rep.requests)}
             print(f"[bench] served {name} load {f}x: {rep.summary()}", file=sys.stderr, flush=True)
+        # The MLMC estimator of the graphene hierarchy (N = 4..32, K = 32 / N,
+        # seed 303, TOL = 1e-3 relative) as one client of the server while
+        # background requests arrive at 0.5x the FP64 saturation rate.
+        bg_rate = 0.5 * base_rate
+        srv.open()
+        srv.submit(poisson_requests(StreamSpec(rate=bg_rate, count=int(bg_rate * 60) + 1, first_rid=1 << 30)))
+        est = ServedEstimator(srv, "graphene", 303)
+        r = D.run_mlmc(est, (4, 8, 16, 32), [8, 4, 2, 1], 1e-3)
+        bg_pending = srv.drop_pending()
+        while srv.busy():
+            srv.step()
+        bg = [q for q in srv.report().requests if (1 << 30) <= q.rid < (1 << 40)]  # the client's rids start at 2^40
+        rec["mlmc_client"] = {"seconds": round(r.seconds, 3), "M": [st.M for st in r.levels], "error": r.error,
+                              "tol_abs": r.tol_abs, "rounds": len(r.rounds),
+                              "background_rate": round(bg_rate, 3), "background_served": len(bg),
+                              "background_p50_ms": round(1e3 * float(np.percentile([q.latency for q in bg], 50)), 3)
+                              if bg else None}
+        print(f"[bench] served {name} MLMC client: {rec['mlmc_client']}", file=sys.stderr, flush=True)
         out[name] = rec
         ex.close()
     out["fp64_saturation_requests_per_s"] = round(base_rate, 3)
@@ -468,6 +489,8 @@ def main():
                        "arrival_seed": 5050, "step": "one request"},
             "served": rec,
             "speedup_mixed_vs_fp64_saturation": round(mx["eigensolves_per_s"] / fp["eigensolves_per_s"], 3),
+            "mlmc_client_time_to_tol_s": {"fp64": rec["fp64"]["mlmc_client"]["seconds"],
+                                          "mixed": rec["mixed"]["mlmc_client"]["seconds"]},
         }), flush=True)
         return
 

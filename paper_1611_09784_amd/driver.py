@@ -236,8 +236,11 @@ def run_mlmc(est: Estimator, levels, Ks, tol_rel: float, C_alpha: float = 2.0, t
     stages = list(tol_sequence or []) + [tol_rel]
     stage = 0
     for _ in range(max_rounds * len(stages)):
-        for t, st in zip(target, sampled):
-            est.add_samples(st, min(t, max_samples) - st.M)
+        if hasattr(est, "add_round"):  # a client of a server: the round's samples of all levels at once
+            est.add_round([(st, min(t, max_samples) - st.M) for t, st in zip(target, sampled)])
+        else:
+            for t, st in zip(target, sampled):
+                est.add_samples(st, min(t, max_samples) - st.M)
         means, V = [], []
         for st in sampled:
             m, v = st.mean_var()

@@ -165,88 +165,178 @@ class Server:
             return 0
         return b
 
-    def run(self, requests: list, on_complete=None) -> ServeReport:
-        """Serve `requests` (arrival times relative to the start of the run);
-        returns when all are complete.  on_complete(req) is called for each
-        request as its batch completes."""
+    # -- incremental use: open, submit, step / wait_for, report ---------------
+    def open(self, on_complete=None):
+        """Start a session: time 0 is now; requests submitted later carry
+        arrival times relative to it."""
+        self._pending = []          # not yet arrived, sorted by (arrival, rid)
+        self._queues = {}           # class -> arrived requests in arrival order
+        self._running = []
+        self._free = list(range(self.slots))
+        self._used = self._peak = self._max_in_flight = self._batches = self._solves = 0
+        self._served = []
+        self._on_complete = on_complete
+        self._t0 = self.clock()
+
+    def now(self) -> float:
+        return self.clock() - self._t0
+
+    def submit(self, requests: list):
         for r in requests:
             cls = request_class(r.lattice, r.N)
             if self.ex.bytes_for(cls, 1) > self.budget:
                 raise ValueError(f"request {r.rid} ({r.lattice}, N = {r.N}) needs more than the HBM budget")
-        pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
-        queues = {}                 # class -> list of arrived requests in arrival order
-        running = []
-        free_slots = list(range(self.slots))
-        used = 0
-        peak = 0
-        max_in_flight = 0
-        batches = 0
-        solves = 0
-        nxt = 0
-        t0 = self.clock()
-        while nxt < len(pending) or any(queues.values()) or running:
-            now = self.clock() - t0
-            while nxt < len(pending) and pending[nxt].arrival <= now:
-                r = pending[nxt]
-                queues.setdefault(request_class(r.lattice, r.N), []).append(r)
-                nxt += 1
-            progressed = False
-            # completions
-            still = []
-            for job in running:
-                if job.handle.done():
-                    t = self.clock() - t0
-                    Y, Q = job.handle.collect()
-                    for i, r in enumerate(job.reqs):
-                        r.done = t
-                        r.Y = Y[i]
-                        r.Q = Q[i]
-                        if on_complete is not None:
-                            on_complete(r)
-                    job.handle.release()
-                    used -= job.nbytes
-                    free_slots.append(job.slot)
-                    progressed = True
-                else:
-                    still.append(job)
-            running = still
-            # admissions: oldest waiting request's class first (heavy classes
-            # only while they hold fewer than heavy_slots slots)
-            while free_slots:
-                heavy_busy = sum(1 for job in running if self._heavy(job.cls))
-                heads = [(q[0].arrival, q[0].rid, c) for c, q in queues.items()
-                         if q and (heavy_busy < self.heavy_slots or not self._heavy(c))]
-                if not heads:
-                    break
-                _, _, cls = min(heads, key=lambda h: (h[0], h[1]))
-                q = queues[cls]
-                b = self._batch_size(cls, len(q), self.budget - used)
-                if b == 0:
-                    break  # wait for memory; no other class goes first
-                reqs, queues[cls] = q[:b], q[b:]
-                nbytes = self.ex.bytes_for(cls, b)
-                slot = free_slots.pop(0)
-                t = self.clock() - t0
-                for r in reqs:
-                    r.admitted = t
-                    r.batch = batches
-                handle = self.ex.launch(slot, cls, reqs)
-                running.append(_Running(slot, cls, reqs, handle, nbytes, t))
-                used += nbytes
-                peak = max(peak, used)
-                max_in_flight = max(max_in_flight, len(running))
-                batches += 1
-                solves += b * self.ex.solves_per_request(cls)
+        self._pending = sorted(self._pending + list(requests), key=lambda r: (r.arrival, r.rid))
+
+    def busy(self) -> bool:
+        return bool(self._pending) or any(self._queues.values()) or bool(self._running)
+
+    def drop_pending(self) -> int:
+        """Forget requests that have not arrived yet; returns how many."""
+        n = len(self._pending)
+        self._pending = []
+        return n
+
+    def step(self):
+        """One scheduler turn: arrivals, completions, admissions; sleeps
+        briefly when none of them happened."""
+        now = self.now()
+        k = 0
+        while k < len(self._pending) and self._pending[k].arrival <= now:
+            r = self._pending[k]
+            self._queues.setdefault(request_class(r.lattice, r.N), []).append(r)
+            k += 1
+        self._pending = self._pending[k:]
+        progressed = False
+        still = []
+        for job in self._running:
+            if job.handle.done():
+                t = self.now()
+                Y, Q = job.handle.collect()
+                for i, r in enumerate(job.reqs):
+                    r.done = t
+                    r.Y = Y[i]
+                    r.Q = Q[i]
+                    self._served.append(r)
+                    if self._on_complete is not None:
+                        self._on_complete(r)
+                job.handle.release()
+                self._used -= job.nbytes
+                self._free.append(job.slot)
                 progressed = True
-            if not progressed:
-                wait = self.idle_sleep
-                if nxt < len(pending) and not running and not any(queues.values()):
-                    wait = max(0.0, min(0.05, pending[nxt].arrival - now))
-                if wait > 0:
-                    self.sleep(wait)
-        seconds = max((r.done for r in requests), default=0.0)
-        return ServeReport(requests=requests, seconds=seconds, batches=batches, solves=solves, peak_bytes=peak,
-                           max_in_flight=max_in_flight, budget_bytes=self.budget)
+            else:
+                still.append(job)
+        self._running = still
+        # admissions: oldest waiting request's class first (heavy classes
+        # only while they hold fewer than heavy_slots slots)
+        while self._free:
+            heavy_busy = sum(1 for job in self._running if self._heavy(job.cls))
+            heads = [(q[0].arrival, q[0].rid, c) for c, q in self._queues.items()
+                     if q and (heavy_busy < self.heavy_slots or not self._heavy(c))]
+            if not heads:
+                break
+            _, _, cls = min(heads, key=lambda h: (h[0], h[1]))
+            q = self._queues[cls]
+            b = self._batch_size(cls, len(q), self.budget - self._used)
+            if b == 0:
+                break  # wait for memory; no other class goes first
+            reqs, self._queues[cls] = q[:b], q[b:]
+            nbytes = self.ex.bytes_for(cls, b)
+            slot = self._free.pop(0)
+            t = self.now()
+            for r in reqs:
+                r.admitted = t
+                r.batch = self._batches
+            handle = self.ex.launch(slot, cls, reqs)
+            self._running.append(_Running(slot, cls, reqs, handle, nbytes, t))
+            self._used += nbytes
+            self._peak = max(self._peak, self._used)
+            self._max_in_flight = max(self._max_in_flight, len(self._running))
+            self._batches += 1
+            self._solves += b * self.ex.solves_per_request(cls)
+            progressed = True
+        if not progressed:
+            wait = self.idle_sleep
+            if self._pending and not self._running and not any(self._queues.values()):
+                wait = max(0.0, min(0.05, self._pending[0].arrival - now))
+            if wait > 0:
+                self.sleep(wait)
+
+    def wait_for(self, requests: list):
+        """Step until every request in `requests` is complete."""
+        while any(math.isnan(r.done) for r in requests):
+            self.step()
+
+    def report(self) -> ServeReport:
+        reqs = self._served
+        seconds = max((r.done for r in reqs), default=0.0)
+        return ServeReport(requests=list(reqs), seconds=seconds, batches=self._batches, solves=self._solves,
+                           peak_bytes=self._peak, max_in_flight=self._max_in_flight, budget_bytes=self.budget)
+
+    def run(self, requests: list, on_complete=None) -> ServeReport:
+        """Serve `requests` (arrival times relative to the start of the run);
+        returns when all are complete.  on_complete(req) is called for each
+        request as its batch completes."""
+        self.open(on_complete)
+        self.submit(requests)
+        while self.busy():
+            self.step()
+        return self.report()
+
+
+class ServedEstimator:
+    """An MLMC client of a Server (the estimator of the MLMC driver): each
+    round submits the round's new samples of every level as requests of one
+    lattice and seed (outcome index = sample number of the level), waits for
+    them while the server goes on with whatever else arrives, and turns the
+    returned rows into level sums with the library's level-sum kernel.  A
+    level's cost per sample W is its requests' share of their batches'
+    service times."""
+
+    def __init__(self, server: Server, lattice: str, seed: int, device=0):
+        import torch
+        from . import binding as B
+        self.srv, self.lattice, self.seed = server, lattice, int(seed)
+        self.B, self.torch = B, torch
+        self.device = torch.device("cuda", device)
+        self._rid = 1 << 40
+        self.requests = []
+
+    def add_round(self, items):
+        """items: [(LevelState, count)]; adds `count` samples to each level."""
+        torch, B = self.torch, self.B
+        now = self.srv.now()
+        per_level = []
+        for lvl, count in items:
+            reqs = []
+            for i in range(max(0, count)):
+                reqs.append(Request(rid=self._rid, lattice=self.lattice, N=lvl.N, seed=self.seed, index=lvl.M + i,
+                                    arrival=now))
+                self._rid += 1
+            per_level.append((lvl, reqs))
+        allr = [r for _, reqs in per_level for r in reqs]
+        self.srv.submit(allr)
+        self.srv.wait_for(allr)
+        self.requests += allr
+        for lvl, reqs in per_level:
+            if not reqs:
+                continue
+            Y = torch.as_tensor(np.stack([r.Y for r in reqs]), device=self.device)
+            Q = torch.as_tensor(np.stack([r.Q for r in reqs]), device=self.device)
+            sy = B.mlmc_level_stats(Y).cpu().numpy()   # [sum Y, sum Y^2, ...]
+            sq = B.mlmc_level_stats(Q).cpu().numpy()   # [sum Q, sum Q^2, ...]
+            host = np.stack([sy[0], sy[1], sq[0], sq[1]])
+            sizes = {}
+            for r in self.srv._served:
+                if r.batch >= 0:
+                    sizes[r.batch] = sizes.get(r.batch, 0) + 1
+            cost = sum((r.done - r.admitted) / sizes.get(r.batch, 1) for r in reqs)
+            lvl.seconds += cost
+            lvl.stats = host if lvl.stats is None else lvl.stats + host
+            lvl.M += len(reqs)
+
+    def add_samples(self, lvl, count: int):
+        self.add_round([(lvl, count)])
 
 
 # ---------------------------------------------------------------------------

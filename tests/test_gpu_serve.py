@@ -84,3 +84,39 @@ def test_served_alone_equals_in_mix(setup, prec):
             assert np.abs(r.Q - want[2]).max() <= tol, f"request {r.rid}"
     finally:
         ex.close()
+
+
+@pytest.mark.timeout(600)
+def test_served_mlmc_client(setup):
+    """The MLMC driver as a client of the server beside background requests:
+    its level sums after one round equal the plain estimator's over the same
+    samples (to summation order), and the adaptive run reaches theta * TOL."""
+    import paper_1611_09784_amd.driver as D
+    from paper_1611_09784_amd.serve import BatchLimits, GpuExecutor, Server, ServedEstimator, StreamSpec, \
+        poisson_requests
+    B, lats, eps = setup
+    ex = GpuExecutor(lats, eps, DELTA, P, 0, slots=3)
+    try:
+        srv = Server(ex, 100 << 30, slots=3, limits=BatchLimits(max_requests=16))
+        srv.open()
+        bg = poisson_requests(StreamSpec(rate=40.0, count=60, Ns=(4, 8), weights=(0.6, 0.4), first_rid=1 << 30))
+        srv.submit(bg)
+        est = ServedEstimator(srv, "graphene", 303)
+        levels, Ks = (4, 8, 16), [8, 4, 2]
+        lv = D.make_levels(levels, Ks)
+        est.add_round([(st, 6) for st in lv])
+        ref = D.Estimator(B.DeviceLattice(lats["graphene"], 0), eps["graphene"], DELTA, P, B.MLMC_KGRID_GAMMA, 303)
+        for st in lv:
+            want = D.LevelState(N=st.N, K=st.K, coupled=st.coupled, K_coarse=st.K_coarse)
+            ref.add_samples(want, 6)
+            assert np.allclose(st.stats, want.stats, rtol=1e-12, atol=1e-14), f"level N = {st.N}"
+        ref.close()
+        r = D.run_mlmc(est, levels, Ks, 1e-2, pilot=8)
+        say(f"[served MLMC client] M = {[st.M for st in r.levels]}, error {r.error:.3e}, tol_abs {r.tol_abs:.3e}")
+        assert r.error <= 0.5 * r.tol_abs
+        srv.drop_pending()
+        while srv.busy():
+            srv.step()
+        assert sum(1 for q in srv.report().requests if (1 << 30) <= q.rid < (1 << 40)) > 0   # background beside
+    finally:
+        ex.close()
