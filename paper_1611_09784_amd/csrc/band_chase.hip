@@ -111,8 +111,8 @@ __device__ __forceinline__ void ring_diag(const cpx<T> *win, int r0, int L, Blk<
         const int hi = r > c ? r : c, lo = r > c ? c : r;
         const bool ok = FULL || (r < L && c < L);
         const cpx<T> x = win[opaque(ok ? Ring<WC>::at(r0 + hi, r0 + lo) : Ring<WC>::kZero)];
-        const T im = keep(x.im);
-        b.e[tt] = {x.re, (r == c) ? T(0) : ((r < c) ? -im : im)};
+        const T f = (r == c) ? T(0) : ((r < c) ? T(-1) : T(1));  // lane constant: conjugate above, real diagonal
+        b.e[tt] = {x.re, f * x.im};
     }
 }
 
@@ -125,10 +125,38 @@ __device__ __forceinline__ cpx<T> sum4g(cpx<T> x) {  // over the 4 column groups
     return {col_sum(x.re), col_sum(x.im)};
 }
 
+// Complex multiply-adds as two fused multiply-adds per real component.
+template <typename T>
+__device__ __forceinline__ T fmat(T a, T b, T c) {
+    return __builtin_fma(a, b, c);
+}
+template <>
+__device__ __forceinline__ float fmat<float>(float a, float b, float c) {
+    return __builtin_fmaf(a, b, c);
+}
+template <typename T>  // acc + a b
+__device__ __forceinline__ cpx<T> cfma(cpx<T> acc, cpx<T> a, cpx<T> b) {
+    return {fmat(a.re, b.re, fmat(-a.im, b.im, acc.re)), fmat(a.re, b.im, fmat(a.im, b.re, acc.im))};
+}
+template <typename T>  // acc + conj(a) b
+__device__ __forceinline__ cpx<T> cfma_ca(cpx<T> acc, cpx<T> a, cpx<T> b) {
+    return {fmat(a.re, b.re, fmat(a.im, b.im, acc.re)), fmat(a.re, b.im, fmat(-a.im, b.re, acc.im))};
+}
+template <typename T>  // acc - a b
+__device__ __forceinline__ cpx<T> cfms(cpx<T> acc, cpx<T> a, cpx<T> b) {
+    return {fmat(-a.re, b.re, fmat(a.im, b.im, acc.re)), fmat(-a.re, b.im, fmat(-a.im, b.re, acc.im))};
+}
+template <typename T>  // acc - a conj(b)
+__device__ __forceinline__ cpx<T> cfms_cb(cpx<T> acc, cpx<T> a, cpx<T> b) {
+    return {fmat(-a.re, b.re, fmat(-a.im, b.im, acc.re)), fmat(-a.im, b.re, fmat(a.re, b.im, acc.im))};
+}
+
 // One reflection: the reflector H = I - tau v v^H taking the first column of
 // B (rows 0..L-1) to (alpha, 0, ..., 0) is applied as B <- H B (B transposed
 // across lanes), D <- H D H and E <- E H.  vb indexes this wavefront's 32
-// scratch elements in the ring array, sink its lane's sink element.
+// scratch elements in the ring array, sink its lane's sink element.  Every
+// update is written as fused multiply-adds (two per real component of a
+// complex multiply-add).
 template <typename T>
 __device__ __forceinline__ void chase_reflect(cpx<T> *win, int vb, int sink, int L, Blk<T> &B, Blk<T> &D,
                                               Blk<T> &E) {
@@ -138,7 +166,7 @@ __device__ __forceinline__ void chase_reflect(cpx<T> *win, int vb, int sink, int
     // B were loaded as zero and stay zero
     T s = T(0);
 #pragma unroll
-    for (int tt = 0; tt < 4; ++tt) s += c_abs2(B.e[tt]);
+    for (int tt = 0; tt < 4; ++tt) s = fmat(B.e[tt].re, B.e[tt].re, fmat(B.e[tt].im, B.e[tt].im, s));
     const double nrm2 = (double)lane0(col_sum(s));
     const cpx<T> x0 = {lane0(B.e[0].re), lane0(B.e[0].im)};
     T tau;
@@ -157,35 +185,41 @@ __device__ __forceinline__ void chase_reflect(cpx<T> *win, int vb, int sink, int
     // B <- H B: sc[c] = sum_i conj(v_i) B[i][c]; lane (c = r, g) holds rows g + 4t
     cpx<T> sc = zero;
 #pragma unroll
-    for (int tt = 0; tt < 4; ++tt) sc = c_add(sc, c_cmul(vcol[tt], B.e[tt]));
-    sc = sum4g(sc);
+    for (int tt = 0; tt < 4; ++tt) sc = cfma_ca(sc, vcol[tt], B.e[tt]);
+    sc = c_scale(tau, sum4g(sc));
+    // The annihilated column (lanes r == 0) becomes exactly (alpha, 0, ..., 0):
+    // its lanes keep m = 0 of the old value and add alpha where it belongs.
+    const T m = r == 0 ? T(0) : T(1);
+    const T ma = (r == 0 && g == 0) ? T(1) : T(0);
 #pragma unroll
-    for (int tt = 0; tt < 4; ++tt) B.e[tt] = c_sub(B.e[tt], c_scale(tau, c_mul(vcol[tt], sc)));
-    // the annihilated column is exactly (alpha, 0, ..., 0)
-    B.e[0] = csel(r == 0, csel(g == 0, alpha, zero), B.e[0]);
-#pragma unroll
-    for (int tt = 1; tt < 4; ++tt) B.e[tt] = csel(r == 0, zero, B.e[tt]);
+    for (int tt = 0; tt < 4; ++tt) {
+        const cpx<T> x = cfms(B.e[tt], vcol[tt], sc);
+        if (tt == 0)
+            B.e[0] = {fmat(m, x.re, ma * alpha.re), fmat(m, x.im, ma * alpha.im)};
+        else
+            B.e[tt] = {m * x.re, m * x.im};
+    }
     // D <- H D H
     cpx<T> pr = zero;
 #pragma unroll
-    for (int tt = 0; tt < 4; ++tt) pr = c_add(pr, c_mul(D.e[tt], vcol[tt]));
+    for (int tt = 0; tt < 4; ++tt) pr = cfma(pr, D.e[tt], vcol[tt]);
     pr = c_scale(tau, sum4g(pr));
-    const cpx<T> vhp = sum16(c_cmul(vr, pr));
+    const cpx<T> vhp = sum16(cfma_ca(zero, vr, pr));
     const T K = (T)0.5 * tau * vhp.re;
-    const cpx<T> wr = c_sub(pr, c_scale(K, vr));
+    const cpx<T> wr = {fmat(-K, vr.re, pr.re), fmat(-K, vr.im, pr.im)};
     win[opaque(g == 0 ? vb + 16 + r : sink)] = wr;
 #pragma unroll
     for (int tt = 0; tt < 4; ++tt) {
         const cpx<T> wc = win[vb + 16 + g + 4 * tt];
-        D.e[tt] = c_sub(D.e[tt], c_add(c_mulc(vr, wc), c_mulc(wr, vcol[tt])));
+        D.e[tt] = cfms_cb(cfms_cb(D.e[tt], vr, wc), wr, vcol[tt]);
     }
-    // E <- E H (E is zero when there is no block below)
+    // E <- E H (E is zero when there is no block below): E - (tau q) v^H
     cpx<T> q = zero;
 #pragma unroll
-    for (int tt = 0; tt < 4; ++tt) q = c_add(q, c_mul(E.e[tt], vcol[tt]));
-    q = sum4g(q);
+    for (int tt = 0; tt < 4; ++tt) q = cfma(q, E.e[tt], vcol[tt]);
+    q = c_scale(tau, sum4g(q));
 #pragma unroll
-    for (int tt = 0; tt < 4; ++tt) E.e[tt] = c_sub(E.e[tt], c_scale(tau, c_mulc(q, vcol[tt])));
+    for (int tt = 0; tt < 4; ++tt) E.e[tt] = cfms_cb(E.e[tt], q, vcol[tt]);
 }
 
 // Number of steps of sweep j: step k works on rows j + 1 + kB k ..; the sweep
