@@ -241,14 +241,19 @@ mlmc_status mlmc_workspace_bytes(const mlmc_workspace_request *req, size_t *byte
  * memory), then Sturm-count bisection in double precision (Newton points
  * inside the certified brackets; each eigenvalue within 1e-12 eV, or a few
  * ulps of the spectral radius if that is larger).
- * d_H: [batch][ld][ld] column-major, only the lower triangle of the leading
- * n_b x n_b block is read; it is overwritten.  d_n: [batch] sides, each in
- * [0, ld] (a matrix with n_b outside that range gets NaN eigenvalues).
- * d_w: [batch][ldw], ascending, entries >= n_b untouched.
- * dtype/prec: (C128, FP64) or (C64, MIXED). */
+ * d_H: the matrices, column-major with leading dimension ld; only the lower
+ * triangle of the leading n_b x n_b block of matrix b is read, and it is
+ * overwritten.  d_offsets == NULL: matrix b starts at element b*ld*ld
+ * ([batch][ld][ld]).  Otherwise the layout is ragged: matrix b starts at
+ * element d_offsets[b] (device array [batch]) and occupies ld*n_b elements
+ * (its columns 0..n_b-1), so a batch of uneven sizes can be packed at
+ * offsets sum_{a<b} ld*n_a; the caller keeps the matrices inside its buffer
+ * and disjoint.  d_n: [batch] sides, each in [0, ld] (a matrix with n_b
+ * outside that range gets NaN eigenvalues).  d_w: [batch][ldw], ascending,
+ * entries >= n_b untouched.  dtype/prec: (C128, FP64) or (C64, MIXED). */
 mlmc_status mlmc_batched_eigvalsh(mlmc_dtype dtype, mlmc_precision prec, void *d_H, int64_t ld,
-                                  const int32_t *d_n, int64_t batch, double *d_w, int64_t ldw, void *d_work,
-                                  size_t work_bytes, mlmc_stream stream);
+                                  const int64_t *d_offsets, const int32_t *d_n, int64_t batch, double *d_w,
+                                  int64_t ldw, void *d_work, size_t work_bytes, mlmc_stream stream);
 
 /* mlmc_batched_eigvalsh for callers that cannot allocate device memory or
  * bring a workspace (code under HIP graph capture, tight serving loops,

@@ -86,7 +86,7 @@ SIGNATURES = {
     "mlmc_kgrid": (C.c_int, [C.c_int, I32, P, P, P]),
     "mlmc_build_hamiltonians": (C.c_int, [P, I32, P, I64, P, I32, C.c_int, P, I64, P, P]),
     "mlmc_workspace_bytes": (C.c_int, [P, P]),
-    "mlmc_batched_eigvalsh": (C.c_int, [C.c_int, C.c_int, P, I64, P, I64, P, I64, P, SZ, P]),
+    "mlmc_batched_eigvalsh": (C.c_int, [C.c_int, C.c_int, P, I64, P, P, I64, P, I64, P, SZ, P]),
     "mlmc_batched_eigvalsh_noalloc": (C.c_int, [C.c_int, C.c_int, P, I64, P, I64, P, I64, P]),
     "mlmc_build_overlaps": (C.c_int, [P, I32, P, I64, P, I32, C.c_int, P, I64, P, P]),
     "mlmc_batched_eigvalsh_generalized": (C.c_int, [C.c_int, C.c_int, P, P, I64, P, I64, P, I64, P, SZ, P]),
@@ -413,8 +413,10 @@ def mlmc_eigvalsh_workspace(dtype, prec, ld, batch) -> int:
     return mlmc_workspace_bytes(MLMC_OP_BATCHED_EIGVALSH, dtype, prec, ld, batch)
 
 
-def mlmc_batched_eigvalsh(H, n, prec=None, w=None, ldw=None, work=None, stream=None):
-    """H: [batch][ld][ld] column-major (torch stores [u][c][r]); overwritten."""
+def mlmc_batched_eigvalsh(H, n, prec=None, w=None, ldw=None, work=None, stream=None, offsets=None, ld=None):
+    """H: [batch][ld][ld] column-major (torch stores [u][c][r]); overwritten.
+    Ragged layout: `offsets` (int64 device tensor [batch]) gives each matrix's
+    first element in the flat buffer H, with leading dimension `ld`."""
     if H.dtype == torch.complex128:
         dtype = MLMC_C128
     elif H.dtype == torch.complex64:
@@ -425,7 +427,13 @@ def mlmc_batched_eigvalsh(H, n, prec=None, w=None, ldw=None, work=None, stream=N
         prec = MLMC_PREC_FP64 if dtype == MLMC_C128 else MLMC_PREC_MIXED
     _dev(H, None, "H")
     _dev(n, torch.int32, "n")
-    batch, ld = H.shape[0], H.shape[1]
+    if offsets is None:
+        batch, ld = H.shape[0], H.shape[1]
+    else:
+        _dev(offsets, torch.int64, "offsets")
+        if ld is None:
+            raise ValueError("a ragged layout needs ld")
+        batch = offsets.shape[0]
     ldw = ld if ldw is None else ldw
     if w is None:
         w = torch.zeros((batch, ldw), dtype=torch.float64, device=H.device)
@@ -434,8 +442,8 @@ def mlmc_batched_eigvalsh(H, n, prec=None, w=None, ldw=None, work=None, stream=N
     if work is None and need > 0:
         work = torch.empty((need,), dtype=torch.uint8, device=H.device)
     wb = 0 if work is None else work.numel() * work.element_size()
-    _check(lib().mlmc_batched_eigvalsh(dtype, prec, _ptr(H), ld, _ptr(n), batch, _ptr(w), ldw, _ptr(work), wb,
-                                       _stream(stream)), "mlmc_batched_eigvalsh")
+    _check(lib().mlmc_batched_eigvalsh(dtype, prec, _ptr(H), ld, _ptr(offsets), _ptr(n), batch, _ptr(w), ldw,
+                                       _ptr(work), wb, _stream(stream)), "mlmc_batched_eigvalsh")
     return w
 
 

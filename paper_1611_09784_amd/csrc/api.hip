@@ -194,28 +194,32 @@ mlmc_status run_bisect(const int32_t *n, int64_t ld, int64_t units, double *w, i
 // Band -> tridiagonal (b.d, b.e) of matrices that stage 1 left in H, on at
 // most max_blocks workgroups (0: one per matrix).
 mlmc_status run_chase(mlmc_precision prec, const void *H, int64_t ld, const int32_t *n, int64_t units,
-                      const EigBuffers &b, hipStream_t s, int64_t max_blocks = 0) {
+                      const EigBuffers &b, hipStream_t s, int64_t max_blocks = 0, const int64_t *offs = nullptr) {
     if (prec == MLMC_PREC_FP64)
         LAUNCH("chase", s, launch_band_chase<double>(static_cast<const cpx<double> *>(H), ld, n, units, b.d, b.e, ld,
-                                                     static_cast<cpx<double> *>(b.partial), s, max_blocks, b.stride));
+                                                     static_cast<cpx<double> *>(b.partial), s, max_blocks, b.stride,
+                                                     offs));
     else
         LAUNCH("chase", s, launch_band_chase<float>(static_cast<const cpx<float> *>(H), ld, n, units, b.d, b.e, ld,
-                                                    static_cast<cpx<float> *>(b.partial), s, max_blocks, b.stride));
+                                                    static_cast<cpx<float> *>(b.partial), s, max_blocks, b.stride,
+                                                    offs));
     return MLMC_OK;
 }
 
 // With defer_chase only stage 1 runs here (the caller runs run_chase and
-// run_bisect, possibly on other streams).
+// run_bisect, possibly on other streams).  offs: element offset of each
+// matrix in H (NULL: u ld^2).
 mlmc_status run_large(mlmc_precision prec, void *H, int64_t ld, const int32_t *n, int64_t units, double *w, int64_t ldw,
-                      const EigBuffers &b, hipStream_t s, bool defer_bisect = false, bool defer_chase = false) {
+                      const EigBuffers &b, hipStream_t s, bool defer_bisect = false, bool defer_chase = false,
+                      const int64_t *offs = nullptr) {
     if (prec == MLMC_PREC_FP64)
         LAUNCH("band_reduce", s, launch_band_reduce<double>(static_cast<cpx<double> *>(H), ld, n, units,
-                                                            static_cast<cpx<double> *>(b.partial), s, b.stride));
+                                                            static_cast<cpx<double> *>(b.partial), s, b.stride, offs));
     else
         LAUNCH("band_reduce", s, launch_band_reduce<float>(static_cast<cpx<float> *>(H), ld, n, units,
-                                                           static_cast<cpx<float> *>(b.partial), s, b.stride));
+                                                           static_cast<cpx<float> *>(b.partial), s, b.stride, offs));
     if (defer_chase) return MLMC_OK;
-    const mlmc_status st = run_chase(prec, H, ld, n, units, b, s);
+    const mlmc_status st = run_chase(prec, H, ld, n, units, b, s, 0, offs);
     if (st != MLMC_OK || defer_bisect) return st;
     return run_bisect(n, ld, units, w, ldw, b, s);
 }
@@ -648,9 +652,9 @@ static mlmc_status eigvalsh_workspace(mlmc_dtype dtype, mlmc_precision prec, int
     return MLMC_OK;
 }
 
-mlmc_status mlmc_batched_eigvalsh(mlmc_dtype dtype, mlmc_precision prec, void *d_H, int64_t ld, const int32_t *d_n,
-                                  int64_t batch, double *d_w, int64_t ldw, void *d_work, size_t work_bytes,
-                                  mlmc_stream stream) {
+mlmc_status mlmc_batched_eigvalsh(mlmc_dtype dtype, mlmc_precision prec, void *d_H, int64_t ld,
+                                  const int64_t *d_offsets, const int32_t *d_n, int64_t batch, double *d_w, int64_t ldw,
+                                  void *d_work, size_t work_bytes, mlmc_stream stream) {
     size_t need = 0;
     const mlmc_status st = eigvalsh_workspace(dtype, prec, ld, batch, &need);
     if (st != MLMC_OK) return st;
@@ -662,15 +666,17 @@ mlmc_status mlmc_batched_eigvalsh(mlmc_dtype dtype, mlmc_precision prec, void *d
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (ld <= small_cap(prec)) {
         if (prec == MLMC_PREC_FP64)
-            LAUNCH("small_fused", s, launch_small_from_matrix<double>(static_cast<const cpx<double> *>(d_H), ld, d_n, batch, d_w, ldw, s));
+            LAUNCH("small_fused", s, launch_small_from_matrix<double>(static_cast<const cpx<double> *>(d_H), ld, d_n,
+                                                                      batch, d_w, ldw, s, d_offsets));
         else
-            LAUNCH("small_fused", s, launch_small_from_matrix<float>(static_cast<const cpx<float> *>(d_H), ld, d_n, batch, d_w, ldw, s));
+            LAUNCH("small_fused", s, launch_small_from_matrix<float>(static_cast<const cpx<float> *>(d_H), ld, d_n,
+                                                                     batch, d_w, ldw, s, d_offsets));
         return MLMC_OK;
     }
     Carver cv{static_cast<char *>(d_work)};
     EigBuffers b;
     carve_large(cv, prec, ld, batch, false, b);
-    return run_large(prec, d_H, ld, d_n, batch, d_w, ldw, b, s);
+    return run_large(prec, d_H, ld, d_n, batch, d_w, ldw, b, s, false, false, d_offsets);
 }
 
 }  // extern "C"

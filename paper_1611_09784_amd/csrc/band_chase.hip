@@ -402,7 +402,8 @@ __device__ __forceinline__ void batch_phase(cpx<T> *win, cpx<T> *band, int64_t g
 // The whole chase of matrix u by one workgroup (ring and schedule in LDS).
 template <typename T, int S, int WC>
 __device__ __forceinline__ void chase_matrix(int64_t u, cpx<T> *win, int *sched, const cpx<T> *__restrict__ Hall,
-                                             int64_t ld, const int32_t *__restrict__ n_in, double *__restrict__ dall,
+                                             int64_t ld, const int64_t *__restrict__ offs,
+                                             const int32_t *__restrict__ n_in, double *__restrict__ dall,
                                              double *__restrict__ eall, int64_t lde, cpx<T> *__restrict__ wall,
                                              int64_t stride) {
     constexpr int NT = 64 * S;
@@ -418,7 +419,7 @@ __device__ __forceinline__ void chase_matrix(int64_t u, cpx<T> *win, int *sched,
     const TwoView<T> w(wall, stride, ld, u);
     cpx<T> *band = w.band;
     const int64_t gsink = ld * kBandLd;
-    const ColSource<T> from_h = {Hall + u * ld * ld, ld + 1, kB};
+    const ColSource<T> from_h = {Hall + mat_offset(offs, u, ld), ld + 1, kB};
     const ColSource<T> from_band = {band, kBandLd, kWinDiag - 1};
     if (threadIdx.x == 0) win[Ring<WC>::kZero] = {T(0), T(0)};
     const int nsw = max(n - 2, 0);  // sweeps j = 0 .. n - 3
@@ -490,13 +491,14 @@ __device__ __forceinline__ void chase_matrix(int64_t u, cpx<T> *win, int *sched,
 // leaves the other CUs to other work.
 template <typename T, int S, int WC>
 __global__ __launch_bounds__(64 * S) void chase_kernel(const cpx<T> *__restrict__ Hall, int64_t ld,
+                                                       const int64_t *__restrict__ offs,
                                                        const int32_t *__restrict__ n_in, int64_t batch,
                                                        double *__restrict__ dall, double *__restrict__ eall,
                                                        int64_t lde, cpx<T> *__restrict__ wall, int64_t stride) {
     __shared__ cpx<T> win[Ring<WC>::elems(S)];
     __shared__ int sched[WC + S + 1];  // resident phase: start phase per sweep, end phase per wavefront, length
     for (int64_t u = blockIdx.x; u < batch; u += gridDim.x) {
-        chase_matrix<T, S, WC>(u, win, sched, Hall, ld, n_in, dall, eall, lde, wall, stride);
+        chase_matrix<T, S, WC>(u, win, sched, Hall, ld, offs, n_in, dall, eall, lde, wall, stride);
         __syncthreads();  // every wavefront is done with the ring before the next matrix refills it
     }
 }
@@ -517,21 +519,24 @@ struct ChaseShape<float> {
 
 template <typename T>
 hipError_t launch_band_chase(const cpx<T> *H, int64_t ld, const int32_t *n_in, int64_t batch, double *d, double *e,
-                             int64_t lde, cpx<T> *work, hipStream_t s, int64_t max_blocks, int64_t stride) {
+                             int64_t lde, cpx<T> *work, hipStream_t s, int64_t max_blocks, int64_t stride,
+                             const int64_t *offs) {
     if (batch == 0) return hipSuccess;
     if (ld > 46340) return hipErrorInvalidValue;  // element offsets into H are 32-bit
     constexpr int S = ChaseShape<T>::S, WC = ChaseShape<T>::WC;
     if (stride == 0) stride = (int64_t)tridiag_twostage_work_elems<T>(ld);
     if (stride < (int64_t)tridiag_twostage_work_elems<T>(ld)) return hipErrorInvalidValue;
     const int64_t grid = (max_blocks > 0 && max_blocks < batch) ? max_blocks : batch;
-    hipLaunchKernelGGL((chase_kernel<T, S, WC>), dim3((unsigned)grid), dim3(64 * S), 0, s, H, ld, n_in, batch, d, e,
-                       lde, work, stride);
+    hipLaunchKernelGGL((chase_kernel<T, S, WC>), dim3((unsigned)grid), dim3(64 * S), 0, s, H, ld, offs, n_in, batch, d,
+                       e, lde, work, stride);
     return hipGetLastError();
 }
 
 template hipError_t launch_band_chase<double>(const cpx<double> *, int64_t, const int32_t *, int64_t, double *,
-                                              double *, int64_t, cpx<double> *, hipStream_t, int64_t, int64_t);
+                                              double *, int64_t, cpx<double> *, hipStream_t, int64_t, int64_t,
+                                              const int64_t *);
 template hipError_t launch_band_chase<float>(const cpx<float> *, int64_t, const int32_t *, int64_t, double *,
-                                             double *, int64_t, cpx<float> *, hipStream_t, int64_t, int64_t);
+                                             double *, int64_t, cpx<float> *, hipStream_t, int64_t, int64_t,
+                                             const int64_t *);
 
 }  // namespace mlmc

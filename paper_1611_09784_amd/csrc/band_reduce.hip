@@ -192,6 +192,7 @@ __device__ __noinline__ void store_vt(const TwoView<T> &w, int64_t ld, int s, in
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kQrThreads) void qr_panel_kernel(cpx<T> *__restrict__ Hall, int64_t ld,
+                                                              const int64_t *__restrict__ offs,
                                                               const int32_t *__restrict__ n_in,
                                                               cpx<T> *__restrict__ wall, int64_t stride, int p) {
     __shared__ cpx<T> part[kQrThreads / 64][kB];
@@ -204,7 +205,7 @@ __global__ __launch_bounds__(kQrThreads) void qr_panel_kernel(cpx<T> *__restrict
     if (n < 0 || n > ld || m < 2) return;
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
     const TwoView<T> w(wall, stride, ld, u);
-    cpx<T> *A = Hall + u * ld * ld;
+    cpx<T> *A = Hall + mat_offset(offs, u, ld);
     const int nr = min(m - 1, kB);
     for (int idx = t; idx < kB * kB; idx += kQrThreads) Ts[idx / kB][idx % kB] = {T(0), T(0)};
     for (int i = 0; i < kB; ++i) {
@@ -372,6 +373,7 @@ __device__ __forceinline__ void qr_reflect_all(QrShared<T, NT> &sh, cpx<T> (&P)[
 
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void qr_panel_reg_kernel(cpx<T> *__restrict__ Hall, int64_t ld,
+                                                          const int64_t *__restrict__ offs,
                                                           const int32_t *__restrict__ n_in,
                                                           cpx<T> *__restrict__ wall, int64_t stride, int p) {
     __shared__ QrShared<T, NT> sh;
@@ -384,7 +386,7 @@ __global__ __launch_bounds__(NT) void qr_panel_reg_kernel(cpx<T> *__restrict__ H
     const bool own = r < n;
     const int ldi = (int)ld;
     const TwoView<T> w(wall, stride, ld, u);
-    cpx<T> *A = Hall + u * ld * ld;
+    cpx<T> *A = Hall + mat_offset(offs, u, ld);
     const cpx<T> zero = {T(0), T(0)};
     cpx<T> P[kB];
 #pragma unroll
@@ -498,7 +500,8 @@ __device__ __forceinline__ void hemm_finish(const Acc (&acc)[4], const cpx<T> *V
 // (four 16-row tiles) x 16 columns; each step consumes 4 columns of A22.
 template <typename T>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void hemm_kernel(
-    const cpx<T> *__restrict__ Hall, int64_t ld, const int32_t *__restrict__ n_in, const cpx<T> *__restrict__ VTall,
+    const cpx<T> *__restrict__ Hall, int64_t ld, const int64_t *__restrict__ offs, const int32_t *__restrict__ n_in,
+    const cpx<T> *__restrict__ VTall,
     const cpx<T> *__restrict__ Vall, cpx<T> *__restrict__ Xall, cpx<T> *__restrict__ Zall, int64_t stride, int p,
     int64_t batch, int64_t tiles) {
     int64_t u, tile;
@@ -509,7 +512,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void he
     if (n < 0 || n > ld || m < 2) return;
     const int rb = s + (int)tile * kHemmRows;
     if (rb >= n) return;
-    const cpx<T> *A = Hall + u * ld * ld;
+    const cpx<T> *A = Hall + mat_offset(offs, u, ld);
     const cpx<T> *V = VTall + u * stride;
     CAcc3<T> acc[4];
 #pragma unroll
@@ -605,6 +608,7 @@ __global__ __launch_bounds__(kWThreads) void wfactor_kernel(const int32_t *__res
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void band_update_kernel(cpx<T> *__restrict__ Hall, int64_t ld,
+                                                          const int64_t *__restrict__ offs,
                                                           const int32_t *__restrict__ n_in, cpx<T> *__restrict__ wall,
                                                           int64_t stride, int p, int64_t batch, int64_t tiles,
                                                           int min_m) {
@@ -642,7 +646,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
     // This wave's part of the tile: rows rb + 16 tt + ii, columns cs + row(lane, v),
     // loaded now so that the loads are in flight during the products.
     const int cs = cb + wid * 16;
-    cpx<T> *A = Hall + u * ld * ld;
+    cpx<T> *A = Hall + mat_offset(offs, u, ld);
     cpx<T> x[4][4];
 #pragma unroll
     for (int tt = 0; tt < 4; ++tt) {
@@ -711,8 +715,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
 // 2a + 1 for a (a + 1) <= t < (a + 1) (a + 2).
 template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void band_update32_kernel(
-    cpx<T> *__restrict__ Hall, int64_t ld, const int32_t *__restrict__ n_in, cpx<T> *__restrict__ wall,
-    int64_t stride, int p, int64_t batch, int64_t tiles, int min_m) {
+    cpx<T> *__restrict__ Hall, int64_t ld, const int64_t *__restrict__ offs, const int32_t *__restrict__ n_in,
+    cpx<T> *__restrict__ wall, int64_t stride, int p, int64_t batch, int64_t tiles, int min_m) {
     constexpr int R = kUpdBlk / 2;  // rows per tile
     __shared__ cpx<T> sVr[kB][R], sWr[kB][R];
     int64_t u, tile;
@@ -751,7 +755,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
         const int k = 4 * q + kk;
         af[q] = (k < kB ? w.W : w.V)[c < n ? (k & (kB - 1)) * ldi + c : 0];
     }
-    cpx<T> *A = Hall + u * ld * ld;
+    cpx<T> *A = Hall + mat_offset(offs, u, ld);
     cpx<T> x[2][4];
 #pragma unroll
     for (int tt = 0; tt < 2; ++tt) {
@@ -805,7 +809,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
 
 template <typename T>
 hipError_t launch_band_reduce(cpx<T> *H, int64_t ld, const int32_t *n_in, int64_t batch, cpx<T> *work,
-                              hipStream_t s, int64_t stride) {
+                              hipStream_t s, int64_t stride, const int64_t *offs) {
     if (batch == 0) return hipSuccess;
     if (stride == 0) stride = (int64_t)tridiag_twostage_work_elems<T>(ld);
     if (stride < (int64_t)tridiag_twostage_work_elems<T>(ld)) return hipErrorInvalidValue;
@@ -813,17 +817,17 @@ hipError_t launch_band_reduce(cpx<T> *H, int64_t ld, const int32_t *n_in, int64_
     for (int p = 0; p + kB + 1 < ld; p += kB) {
         const int64_t mmax = ld - p - kB;
         if (mmax <= 64)
-            hipLaunchKernelGGL((qr_panel_reg_kernel<T, 64>), dim3(B), dim3(64), 0, s, H, ld, n_in, work, stride, p);
+            hipLaunchKernelGGL((qr_panel_reg_kernel<T, 64>), dim3(B), dim3(64), 0, s, H, ld, offs, n_in, work, stride, p);
         else if (mmax <= 128)
-            hipLaunchKernelGGL((qr_panel_reg_kernel<T, 128>), dim3(B), dim3(128), 0, s, H, ld, n_in, work, stride, p);
+            hipLaunchKernelGGL((qr_panel_reg_kernel<T, 128>), dim3(B), dim3(128), 0, s, H, ld, offs, n_in, work, stride, p);
         else if (mmax <= 256)
-            hipLaunchKernelGGL((qr_panel_reg_kernel<T, 256>), dim3(B), dim3(256), 0, s, H, ld, n_in, work, stride, p);
+            hipLaunchKernelGGL((qr_panel_reg_kernel<T, 256>), dim3(B), dim3(256), 0, s, H, ld, offs, n_in, work, stride, p);
         else if (mmax <= 512)
-            hipLaunchKernelGGL((qr_panel_reg_kernel<T, 512>), dim3(B), dim3(512), 0, s, H, ld, n_in, work, stride, p);
+            hipLaunchKernelGGL((qr_panel_reg_kernel<T, 512>), dim3(B), dim3(512), 0, s, H, ld, offs, n_in, work, stride, p);
         else
-            hipLaunchKernelGGL(qr_panel_kernel<T>, dim3(B), dim3(kQrThreads), 0, s, H, ld, n_in, work, stride, p);
+            hipLaunchKernelGGL(qr_panel_kernel<T>, dim3(B), dim3(kQrThreads), 0, s, H, ld, offs, n_in, work, stride, p);
         const int64_t hrows = (mmax + kHemmRows - 1) / kHemmRows;
-        hipLaunchKernelGGL(hemm_kernel<T>, dim3(xcd_grid(batch, hrows)), dim3(64), 0, s, H, ld, n_in,
+        hipLaunchKernelGGL(hemm_kernel<T>, dim3(xcd_grid(batch, hrows)), dim3(64), 0, s, H, ld, offs, n_in,
                            work + 2 * (int64_t)kB * ld, work, work + (int64_t)kB * ld,
                            work + hemm_partials_offset(ld), stride, p, batch, hrows);
         hipLaunchKernelGGL(wfactor_kernel<T>, dim3(B), dim3(kWThreads), 0, s, n_in, ld, work, stride, p);
@@ -832,7 +836,7 @@ hipError_t launch_band_reduce(cpx<T> *H, int64_t ld, const int32_t *n_in, int64_
         // row blocks (2a, 2a + 1) hold 2 (a + 1) tiles.
         const int64_t nb32 = (mmax + kUpdBlk / 2 - 1) / (kUpdBlk / 2), ha = (nb32 - 1) / 2;
         const int64_t ntile = (nb32 % 2 == 0) ? (ha + 1) * (ha + 2) : (ha + 1) * (ha + 1);
-        hipLaunchKernelGGL(band_update32_kernel<T>, dim3(xcd_grid(batch, ntile)), dim3(256), 0, s, H, ld, n_in, work,
+        hipLaunchKernelGGL(band_update32_kernel<T>, dim3(xcd_grid(batch, ntile)), dim3(256), 0, s, H, ld, offs, n_in, work,
                            stride, p, batch, ntile, 2);
         const hipError_t err = hipGetLastError();
         if (err != hipSuccess) return err;
@@ -850,7 +854,8 @@ hipError_t launch_rank2k_update(cpx<T> *H, int64_t ld, const int32_t *n_in, int6
     if (batch == 0 || p + kB >= ld) return hipSuccess;
     const int64_t mmax = ld - p - kB;
     const int64_t nblk = (mmax + kUpdBlk - 1) / kUpdBlk, ntile = nblk * (nblk + 1) / 2;
-    hipLaunchKernelGGL(band_update_kernel<T>, dim3(xcd_grid(batch, ntile)), dim3(256), 0, s, H, ld, n_in, work, stride,
+    hipLaunchKernelGGL(band_update_kernel<T>, dim3(xcd_grid(batch, ntile)), dim3(256), 0, s, H, ld,
+                       (const int64_t *)nullptr, n_in, work, stride,
                        p, batch, ntile, min_m);
     return hipGetLastError();
 }
@@ -862,8 +867,8 @@ template hipError_t launch_rank2k_update<float>(cpx<float> *, int64_t, const int
 template size_t tridiag_twostage_work_elems<double>(int64_t);
 template size_t tridiag_twostage_work_elems<float>(int64_t);
 template hipError_t launch_band_reduce<double>(cpx<double> *, int64_t, const int32_t *, int64_t, cpx<double> *,
-                                               hipStream_t, int64_t);
+                                               hipStream_t, int64_t, const int64_t *);
 template hipError_t launch_band_reduce<float>(cpx<float> *, int64_t, const int32_t *, int64_t, cpx<float> *,
-                                              hipStream_t, int64_t);
+                                              hipStream_t, int64_t, const int64_t *);
 
 }  // namespace mlmc

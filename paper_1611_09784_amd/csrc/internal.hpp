@@ -98,7 +98,7 @@ hipError_t launch_small_from_lattice(const DevLattice &lat, int N, const uint8_t
                                      hipStream_t s);
 template <typename T>
 hipError_t launch_small_from_matrix(const cpx<T> *H, int64_t ld, const int32_t *n_in, int64_t batch, double *w,
-                                    int64_t ldw, hipStream_t s);
+                                    int64_t ldw, hipStream_t s, const int64_t *offs = nullptr);
 
 // Two-stage reduction to tridiagonal form.  Stage 1 (launch_band_reduce):
 // dense -> band of half-width 16, in place in H (lower triangle).  Stage 2
@@ -107,16 +107,18 @@ hipError_t launch_small_from_matrix(const cpx<T> *H, int64_t ld, const int32_t *
 // in disjoint parts (stage 1: V, X, W, T and the Hermitian product's
 // partials; the chase: the band), so that the chase of one batch may run
 // beside stage 1 of another batch on the same workspace.  The chase runs on
-// at most max_blocks workgroups (one per CU; 0: one per matrix).  stride:
+// at most max_blocks workgroups (one per CU; 0: one per matrix).  offs:
+// element offset of each matrix in H (NULL: u ld^2).  stride:
 // elements between consecutive matrices' workspaces (0: the two-stage
 // layout's own size; a caller whose other kernels use a larger per-matrix
 // workspace passes that, so that their parts stay disjoint).
 template <typename T>
 hipError_t launch_band_reduce(cpx<T> *H, int64_t ld, const int32_t *n_in, int64_t batch, cpx<T> *work,
-                              hipStream_t s, int64_t stride = 0);
+                              hipStream_t s, int64_t stride = 0, const int64_t *offs = nullptr);
 template <typename T>
 hipError_t launch_band_chase(const cpx<T> *H, int64_t ld, const int32_t *n_in, int64_t batch, double *d, double *e,
-                             int64_t lde, cpx<T> *work, hipStream_t s, int64_t max_blocks = 0, int64_t stride = 0);
+                             int64_t lde, cpx<T> *work, hipStream_t s, int64_t max_blocks = 0, int64_t stride = 0,
+                             const int64_t *offs = nullptr);
 template <typename T>
 size_t tridiag_twostage_work_elems(int64_t ld);
 // Rank-2k update A22 -= V W^H + W V^H below panel p (see band_reduce.hip).

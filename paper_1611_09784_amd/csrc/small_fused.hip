@@ -37,6 +37,7 @@ template <typename T, bool FROM_LATTICE>
 __global__ __launch_bounds__(256) void small_eig_kernel(DevLattice lat, int N, const uint8_t *__restrict__ masks,
                                                         const double *__restrict__ kred, int n_k,
                                                         const cpx<T> *__restrict__ Hin, int64_t ld,
+                                                        const int64_t *__restrict__ offs,
                                                         const int32_t *__restrict__ n_in, double *__restrict__ w,
                                                         int64_t ldw, int32_t *__restrict__ n_out, int cap) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -90,7 +91,7 @@ __global__ __launch_bounds__(256) void small_eig_kernel(DevLattice lat, int N, c
             for (int64_t i = threadIdx.x; i < ldw && i < ld; i += blockDim.x) wu[i] = NAN;
             return;
         }
-        const cpx<T> *H = Hin + u * ld * ld;
+        const cpx<T> *H = Hin + (offs ? offs[u] : u * ld * ld);
         for (int c = 0; c < n; ++c) {
             const int base = packed_col(c, n) - c;
             for (int r = c + threadIdx.x; r < n; r += blockDim.x) L[base + r] = H[r + (int64_t)c * ld];
@@ -109,7 +110,7 @@ static int small_threads(int cap) {
 template <typename T, bool FROM_LATTICE>
 static hipError_t launch_small(int64_t units, int cap, hipStream_t s, DevLattice lat, int N, const uint8_t *masks,
                                const double *kred, int n_k, const cpx<T> *Hin, int64_t ld, const int32_t *n_in,
-                               double *w, int64_t ldw, int32_t *n_out) {
+                               double *w, int64_t ldw, int32_t *n_out, const int64_t *offs = nullptr) {
     if (units == 0) return hipSuccess;
     const int threads = small_threads<T>(cap);
     const SmallLayout lay = small_layout<T>(cap, threads);
@@ -118,7 +119,7 @@ static hipError_t launch_small(int64_t units, int cap, hipStream_t s, DevLattice
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lay.bytes);
     if (err != hipSuccess) return err;
     hipLaunchKernelGGL(kern, dim3((unsigned)units), dim3(threads), lay.bytes, s, lat, N, masks, kred, n_k, Hin, ld,
-                       n_in, w, ldw, n_out, cap);
+                       offs, n_in, w, ldw, n_out, cap);
     return hipGetLastError();
 }
 
@@ -133,9 +134,9 @@ hipError_t launch_small_from_lattice(const DevLattice &lat, int N, const uint8_t
 
 template <typename T>
 hipError_t launch_small_from_matrix(const cpx<T> *H, int64_t ld, const int32_t *n_in, int64_t batch, double *w,
-                                    int64_t ldw, hipStream_t s) {
+                                    int64_t ldw, hipStream_t s, const int64_t *offs) {
     DevLattice none{};
-    return launch_small<T, false>(batch, (int)ld, s, none, 0, nullptr, nullptr, 1, H, ld, n_in, w, ldw, nullptr);
+    return launch_small<T, false>(batch, (int)ld, s, none, 0, nullptr, nullptr, 1, H, ld, n_in, w, ldw, nullptr, offs);
 }
 
 template hipError_t launch_small_from_lattice<double>(const DevLattice &, int, const uint8_t *, int64_t,
@@ -144,8 +145,8 @@ template hipError_t launch_small_from_lattice<double>(const DevLattice &, int, c
 template hipError_t launch_small_from_lattice<float>(const DevLattice &, int, const uint8_t *, int64_t,
                                                      const double *, int, double *, int64_t, int32_t *, hipStream_t);
 template hipError_t launch_small_from_matrix<double>(const cpx<double> *, int64_t, const int32_t *, int64_t, double *,
-                                                     int64_t, hipStream_t);
+                                                     int64_t, hipStream_t, const int64_t *);
 template hipError_t launch_small_from_matrix<float>(const cpx<float> *, int64_t, const int32_t *, int64_t, double *,
-                                                    int64_t, hipStream_t);
+                                                    int64_t, hipStream_t, const int64_t *);
 
 }  // namespace mlmc

@@ -46,6 +46,12 @@ __device__ __forceinline__ cpx<T> *hemm_partials(const TwoView<T> &w, int64_t) {
     return w.zp;
 }
 
+// Element offset of matrix u of a batch: offs[u] in a ragged layout, else
+// u ld^2 (matrices ld x ld apart).
+__device__ __forceinline__ int64_t mat_offset(const int64_t *offs, int64_t u, int64_t ld) {
+    return offs ? offs[u] : u * ld * ld;
+}
+
 // Componentwise select (a select of whole structs can become a select of
 // their addresses, which forces register arrays into scratch memory).
 template <typename T>

@@ -609,3 +609,36 @@ def test_level_outcomes(B, gdev, mdev, name, N, coupled, K, Kc, kind, prec):
         ref = oracle.level_estimate(dl.lat, N, coupled, p, K, Kc, kind, seed, first + s, 1, eps, 0.1, 0, n_threads=8)
         assert np.abs(Y[s] - ref[0]).max() <= tol
         assert np.abs(Q[s] - ref[2]).max() <= tol
+
+
+@pytest.mark.parametrize("name,N,prec", [("graphene", 4, 0), ("graphene", 16, 0), ("graphene", 16, 1),
+                                         ("mos2", 4, 0)])
+def test_batched_eigvalsh_ragged(B, gdev, mdev, name, N, prec):
+    """Ragged layout of mlmc_batched_eigvalsh: the matrices of a batch of
+    uneven sizes packed in reverse order, each in its ld * n_b elements with a
+    gap between them, give the eigenvalues of the fixed-stride layout bit for
+    bit (fused path, two-stage path, mixed precision)."""
+    say(f"[eigvalsh ragged] {name} N={N} prec={prec}")
+    dl = pick(name, gdev, mdev)
+    dtype = B.MLMC_C128 if prec == 0 else B.MLMC_C64
+    mask = B.mlmc_sample_vacancies(dl, N, 0.2, 515, dl.tag(N), 0, 6)
+    kred = torch.as_tensor(np.array([[0.1, 0.3], [-0.25, 0.45]]), device=DEV)
+    H, n = B.mlmc_build_hamiltonians(dl, N, mask, kred, dtype)
+    batch, ld = H.shape[0], H.shape[1]
+    nn = n.cpu().numpy()
+    assert len(set(nn.tolist())) > 1   # uneven sizes
+    want = B.mlmc_batched_eigvalsh(H.clone(), n, prec=prec).cpu().numpy()
+    order = list(reversed(range(batch)))
+    offs, cur = [], 0
+    for b in order:
+        offs.append(cur)
+        cur += ld * int(nn[b]) + 7
+    flat = torch.zeros((cur,), dtype=H.dtype, device=DEV)
+    for pos, b in enumerate(order):
+        k = ld * int(nn[b])
+        flat[offs[pos]:offs[pos] + k] = H[b].reshape(-1)[:k]
+    offsets = torch.as_tensor(np.array(offs, dtype=np.int64), device=DEV)
+    n_r = n[torch.as_tensor(order, device=DEV)].contiguous()
+    got = B.mlmc_batched_eigvalsh(flat, n_r, prec=prec, offsets=offsets, ld=ld).cpu().numpy()
+    for pos, b in enumerate(order):
+        assert np.array_equal(got[pos, :nn[b]], want[b, :nn[b]]), f"matrix {b}"
