@@ -148,7 +148,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=250, help="samples per step")
-    ap.add_argument("--chunk", type=int, default=32, help="samples per internal pass (workspace size)")
+    ap.add_argument("--chunk", type=int, default=32, help="samples per internal pass (workspace size) without --tune")
+    ap.add_argument("--tune", dest="tune", action="store_true", default=True,
+                    help="take the chunk size, chase workgroups and update tile from the autotuner")
+    ap.add_argument("--no-tune", dest="tune", action="store_false")
     ap.add_argument("--streams", type=int, default=2, choices=[1, 2],
                     help="caller streams the steps alternate over (2: a step starts beside the previous "
                          "step's last chase and bisection)")
@@ -187,7 +190,10 @@ def time_to_tol(B, dev):
     (Gamma-centred K = 32 / N, p = 0.02, seed 303) run to TOL = 1e-3 relative
     with the FP64 path, the mixed path (FP32 reduction, FP64 bisection and
     sums), and the mixed path that solves each distinct outcome of the two
-    smallest supercells once (identical outcomes identified beforehand).
+    smallest supercells once (identical outcomes identified beforehand); each
+    also with launch choices from the autotuner (chunk size, chase
+    workgroups, update tile per level, measured before the runs and cached)
+    and graph-captured level calls on the LDS-resident levels.
     Beside each time: the per-level samples and the final statistical error;
     then each path's IDoS error against the FP64 oracle on the same coupled
     samples of every level (8, or 4 at N = 32)."""
@@ -202,10 +208,25 @@ def time_to_tol(B, dev):
     dlat = B.DeviceLattice(lat, 0)
     Ks = [wl.NK // N for N in wl.levels]
     out = {"workload": wl.name, "levels": list(wl.levels), "K": Ks, "tol_rel": wl.tol}
-    for name, prec, dedup in (("fp64", B.MLMC_PREC_FP64, 0), ("mixed", B.MLMC_PREC_MIXED, 0),
-                              ("mixed_reuse", B.MLMC_PREC_MIXED, 128)):
+    from paper_1611_09784_amd.autotune import Tuner
+    tuner = Tuner(min_seconds=0.3, max_call_seconds=0.4, chase_fractions=(0.625, 0.75, 0.875, 1.0),
+                  max_trial_seconds=1.5)
+    t_tune = time.perf_counter()
+    tunings = {}
+    for prec, pname in ((B.MLMC_PREC_FP64, "fp64"), (B.MLMC_PREC_MIXED, "mixed")):
+        d_eps = torch.as_tensor(eps, device=dev)
+        for st in D.make_levels(wl.levels, Ks):
+            t = tuner.tune_level(dlat, st.N, st.coupled, st.K, st.K_coarse, wl.kgrid, prec, d_eps, wl.delta, wl.p)
+            tunings.setdefault(pname, []).append({"N": st.N, "chunk": t.chunk, "chase_workgroups": t.chase_workgroups,
+                                                  "update_tile_rows": t.update_tile_rows, "trials": t.trials})
+    out["tuning"] = {"seconds": round(time.perf_counter() - t_tune, 2), "levels": tunings}
+    for name, prec, dedup, tuned in (("fp64", B.MLMC_PREC_FP64, 0, False), ("mixed", B.MLMC_PREC_MIXED, 0, False),
+                                     ("mixed_reuse", B.MLMC_PREC_MIXED, 128, False),
+                                     ("fp64_tuned", B.MLMC_PREC_FP64, 0, True),
+                                     ("mixed_tuned", B.MLMC_PREC_MIXED, 0, True),
+                                     ("mixed_tuned_reuse", B.MLMC_PREC_MIXED, 128, True)):
         est = D.Estimator(dlat, eps, wl.delta, wl.p, wl.kgrid, wl.seed, wl.smoother, prec, chunk_samples=32,
-                          dedup_max_orbitals=dedup)
+                          dedup_max_orbitals=dedup, tuner=tuner if tuned else None, graphs=tuned)
         for st in D.make_levels(wl.levels, Ks):  # warm-up: workspaces and first launches
             est.add_samples(st, 2)
         torch.cuda.synchronize(dev)
@@ -239,6 +260,7 @@ def time_to_tol(B, dev):
                                  "unit": "states/Angstrom^2, max over energies of mean Y and mean Q_f"}
     out["speedup_mixed_vs_fp64"] = round(out["fp64"]["seconds"] / out["mixed"]["seconds"], 3)
     out["speedup_mixed_reuse_vs_fp64"] = round(out["fp64"]["seconds"] / out["mixed_reuse"]["seconds"], 3)
+    out["speedup_mixed_tuned_vs_fp64"] = round(out["fp64"]["seconds"] / out["mixed_tuned"]["seconds"], 3)
     dlat.close()
     return out
 
@@ -290,21 +312,39 @@ KERNEL_NAMES = ("sample_vacancies", "kgrid", "assemble", "small_fused", "overlap
 def measure(B, wl, lat, eps, prec, args, dev):
     """Eigensolves/s of `args.steps` level calls of `args.batch` samples
     (after `args.warmup` untimed ones) with precision `prec`, the per-kernel
-    event times of the timed calls and the chase's roofline."""
+    event times of the timed calls and the chase's roofline.  With --tune the
+    chunk size, chase workgroups and update tile come from the autotuner
+    (measured before the timed calls)."""
     import torch
     dlat = B.DeviceLattice(lat, 0)
     d_eps = torch.as_tensor(eps, device=dev)
     N, K = wl.N, wl.K
     nk = B.mlmc_kgrid_points(wl.kgrid, K)
-    need = B.mlmc_level_workspace(dlat, N, False, K, K, wl.kgrid, args.chunk, prec, eps.size)
+    tuning = None
+    chunk = args.chunk
+    if args.tune:
+        from paper_1611_09784_amd.autotune import Tuner
+        t0 = time.perf_counter()
+        tuner = Tuner(min_seconds=1.0, chunks=(16, 32, 64), budget_bytes=64 << 30,
+                      chase_fractions=(0.625, 0.75, 0.875, 1.0), max_trial_seconds=30.0, verbose=True)
+        t = tuner.tune_level(dlat, N, False, K, K, wl.kgrid, prec, d_eps, wl.delta, wl.p, samples_per_call=args.batch)
+        chunk = t.chunk
+        tuning = {"chunk": t.chunk, "chase_workgroups": t.chase_workgroups, "update_tile_rows": t.update_tile_rows,
+                  "trials": t.trials, "seconds": round(time.perf_counter() - t0, 2)}
+        print(f"[bench] tuned: {tuning}", file=sys.stderr, flush=True)
+    need = B.mlmc_level_workspace(dlat, N, False, K, K, wl.kgrid, chunk, prec, eps.size)
     work = torch.empty((need,), dtype=torch.uint8, device=dev)
     stats = torch.zeros((4, eps.size), dtype=torch.float64, device=dev)
     ctx = B.Context(0)
+    if args.tune:
+        ctx.configure(chase_workgroups=t.chase_workgroups, update_tile_rows=t.update_tile_rows)
     # Consecutive steps are consecutive level-estimate calls of one context on
     # one workspace; on alternating streams a call's front part starts while
     # the previous call's last chunk is still chased and bisected (the sums
     # are still added in call order).
-    streams = [torch.cuda.current_stream()] + [torch.cuda.Stream(dev) for _ in range(args.streams - 1)]
+    streams = [ctx.stream(i) for i in range(args.streams)]  # created with the context's own streams
+    for st in streams:
+        st.wait_stream(torch.cuda.current_stream())  # workspace and sums are ready
     calls = [0]
 
     def step(first):
@@ -321,7 +361,7 @@ def measure(B, wl, lat, eps, prec, args, dev):
     torch.cuda.synchronize()
     stats.zero_()
     # event pairs for every launch of the timed calls, created before them
-    chunks = -(-args.batch // args.chunk)
+    chunks = -(-args.batch // chunk)
     ctx.timer(args.steps * chunks * 16 + 64)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -366,7 +406,7 @@ def measure(B, wl, lat, eps, prec, args, dev):
         # The level pipeline gives the chase part of the CUs (beside it the
         # next chunk's dense-to-band stage runs meanwhile): frac is against
         # the whole chip, frac_of_its_cus against the CUs it occupies.
-        cus = B.mlmc_chase_cus(prec)
+        cus = B.mlmc_chase_cus(prec) if not (tuning and tuning["chase_workgroups"]) else tuning["chase_workgroups"]
         cus_total = torch.cuda.get_device_properties(0).multi_processor_count
         roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                     "frac": round(achieved / peak, 4),
@@ -390,7 +430,8 @@ def measure(B, wl, lat, eps, prec, args, dev):
     return {"value": round(value, 3), "ms_per_step": round(1e3 * elapsed / args.steps, 3),
             "samples_per_s": round(args.steps * args.batch / elapsed, 3), "kernels_ms": kernels,
             "timer_dropped": dropped, "dominant_kernel": roofline["kernel"] if roofline else dom,
-            "roofline": roofline, "reduction_tflops_16_3_n3": round(flops / elapsed / 1e12, 3)}
+            "roofline": roofline, "reduction_tflops_16_3_n3": round(flops / elapsed / 1e12, 3),
+            "launch": {"chunk": chunk, "tuned": tuning}}
 
 
 def served(B, args, dev):
@@ -568,6 +609,7 @@ def main():
         "dominant_kernel": main_run["dominant_kernel"],
         "roofline": main_run["roofline"],
         "reduction_tflops_16_3_n3": main_run["reduction_tflops_16_3_n3"],
+        "launch": main_run["launch"],
     }
     if second is not None:
         out["mixed" if other == B.MLMC_PREC_MIXED else "fp64"] = second

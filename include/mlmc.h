@@ -316,6 +316,31 @@ mlmc_status mlmc_level_stats(const double *d_idos_fine, const double *d_idos_qua
  * calls with different contexts share nothing.  A context is bound to the
  * device current at creation. */
 mlmc_status mlmc_context_create(mlmc_context *out);
+/* One of two caller streams the context owns (index 0 or 1; default
+ * priority, non-blocking), created together with its back and chase streams
+ * so that the four are spread over the runtime's hardware queues; level calls
+ * alternating between them overlap as described at mlmc_level_estimate.
+ * The streams are destroyed with the context. */
+mlmc_status mlmc_context_stream(mlmc_context ctx, int32_t index, mlmc_stream *out);
+/* Launch choices of a context's level calls (the autotuner's knobs):
+ *   chase_workgroups: persistent workgroups of a chunk's band-to-tridiagonal
+ *     chase on the chase stream, beside the next chunk's dense-to-band stage
+ *     (0: 3/4 of the CUs); a call's last chunk is chased on one workgroup per
+ *     matrix;
+ *   bisect_workgroups: workgroups of a chunk's bisection on the back stream
+ *     (0: one per CU);
+ *   update_tile_rows: tiles of the dense-to-band stage's rank-2k update,
+ *     32 x 64 (32: 16 KiB of LDS, small enough to share a CU with a chase
+ *     workgroup) or 64 x 64 (64); 0 means 32.
+ * Results do not depend on the workgroup counts; the update tile changes the
+ * rounding of the reduction only (both within the accuracy stated for
+ * mlmc_batched_eigvalsh). */
+typedef struct {
+    int64_t chase_workgroups;
+    int64_t bisect_workgroups;
+    int32_t update_tile_rows;
+} mlmc_launch_config;
+mlmc_status mlmc_context_configure(mlmc_context ctx, const mlmc_launch_config *cfg);
 /* Waits for the context's streams, then destroys its events and streams.
  * NULL is accepted.  The caller must not use the context afterwards. */
 mlmc_status mlmc_context_destroy(mlmc_context ctx);
@@ -363,13 +388,18 @@ mlmc_status mlmc_context_timer_read(mlmc_context ctx, const char *name, double *
  * with any other layout a call waits for all of the context's earlier work.
  * Other work that uses the workspace is the caller's to order; two contexts
  * must not share a workspace while both have work in flight.
+ * d_first_sample (may be NULL): a device-resident int64 added to
+ * first_sample when the sampling kernels run, and advanced by M at the end
+ * of the call (on `stream`); with it, a HIP graph that captures the call
+ * (ctx == NULL) draws the next M samples on every replay.  The call records
+ * no memset and allocates nothing, so it can be captured.
  * Errors: N_fine < 1, coupled with odd N_fine, K < 1, p outside [0, 1],
  * delta <= 0, workspace too small for one sample. */
 mlmc_status mlmc_level_estimate(mlmc_lattice lat, int32_t N_fine, int32_t coupled, double p, int32_t K_fine,
                                 int32_t K_coarse, mlmc_kgrid_kind kind, uint64_t seed, int64_t first_sample,
                                 int64_t M, const double *d_eps, int32_t n_eps, double delta, mlmc_smoother smoother,
                                 mlmc_precision prec, double *d_stats, void *d_work, size_t work_bytes,
-                                mlmc_context ctx, mlmc_stream stream);
+                                int64_t *d_first_sample, mlmc_context ctx, mlmc_stream stream);
 
 /* The level of mlmc_level_estimate over M given outcomes instead of drawn
  * ones (d_mask: [M][N_fine][N_fine][n_groups], 1 = vacant, e.g. from

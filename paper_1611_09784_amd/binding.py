@@ -63,6 +63,10 @@ class _LatticeDesc(C.Structure):
                 ("n_overlap", C.c_int32), ("overlap", C.c_void_p)]
 
 
+class _LaunchConfig(C.Structure):
+    _fields_ = [("chase_workgroups", C.c_int64), ("bisect_workgroups", C.c_int64), ("update_tile_rows", C.c_int32)]
+
+
 class _WorkspaceRequest(C.Structure):
     _fields_ = [("op", C.c_int), ("dtype", C.c_int), ("prec", C.c_int), ("ld", C.c_int64), ("batch", C.c_int64),
                 ("lat", C.c_void_p), ("N_fine", C.c_int32), ("coupled", C.c_int32), ("K_fine", C.c_int32),
@@ -93,12 +97,14 @@ SIGNATURES = {
     "mlmc_idos": (C.c_int, [P, I64, P, I64, I32, P, DBL, P, I32, DBL, C.c_int, P, P]),
     "mlmc_level_stats": (C.c_int, [P, P, I64, I32, P, P]),
     "mlmc_level_estimate": (C.c_int, [P, I32, I32, DBL, I32, I32, C.c_int, U64, I64, I64, P, I32, DBL, C.c_int,
-                                      C.c_int, P, P, SZ, P, P]),
+                                      C.c_int, P, P, SZ, P, P, P]),
     "mlmc_level_outcomes": (C.c_int, [P, I32, I32, I32, I32, C.c_int, P, I64, P, I32, DBL, C.c_int, C.c_int,
                                       P, P, P, P, SZ, P, P]),
     "mlmc_context_create": (C.c_int, [P]),
     "mlmc_context_destroy": (C.c_int, [P]),
     "mlmc_context_timer": (C.c_int, [P, I64]),
+    "mlmc_context_configure": (C.c_int, [P, P]),
+    "mlmc_context_stream": (C.c_int, [P, I32, P]),
     "mlmc_context_timer_read": (C.c_int, [P, C.c_char_p, P, P, P]),
     "mlmc_optimal_samples": (C.c_int, [I32, P, P, DBL, DBL, DBL, P]),
     "mlmc_dos": (C.c_int, [I32, P, P, P]),
@@ -259,6 +265,17 @@ class Context:
         if self._h is None:
             raise RuntimeError("context already closed")
         return self._h
+
+    def stream(self, index: int):
+        """Caller stream `index` (0 or 1) owned by the context, as a torch stream."""
+        out = C.c_void_p()
+        _check(lib().mlmc_context_stream(self.handle, int(index), C.byref(out)), "mlmc_context_stream")
+        return torch.cuda.ExternalStream(out.value, device=self.device)
+
+    def configure(self, chase_workgroups: int = 0, bisect_workgroups: int = 0, update_tile_rows: int = 0):
+        """Launch choices of this context's level calls (0: the library's default)."""
+        cfg = _LaunchConfig(int(chase_workgroups), int(bisect_workgroups), int(update_tile_rows))
+        _check(lib().mlmc_context_configure(self.handle, C.byref(cfg)), "mlmc_context_configure")
 
     def timer(self, capacity: int):
         """Create `capacity` start/stop event pairs (0: destroy them); the
@@ -509,10 +526,13 @@ def mlmc_level_outcomes_workspace(dlat, N, coupled, K_fine, K_coarse, kind, n_ou
 
 def mlmc_level_estimate(dlat, N, coupled, p, K_fine, K_coarse, kind, seed, first_sample, M, eps, delta,
                         smoother=MLMC_SMOOTH_GAUSS, prec=MLMC_PREC_FP64, stats=None, work=None, chunk_samples=None,
-                        ctx=None, stream=None):
+                        ctx=None, stream=None, first_counter=None):
     """One level's sums ([4][n_eps]: sum Y, sum Y^2, sum Q, sum Q^2, accumulated
     into `stats`).  ctx: a Context (pipelined over its streams) or None (all on
-    `stream`)."""
+    `stream`).  first_counter: an int64 device tensor [1] added to first_sample
+    on the device and advanced by M (for graph capture)."""
+    if first_counter is not None:
+        _dev(first_counter, torch.int64, "first_counter")
     _dev(eps, torch.float64, "eps")
     ne = eps.shape[0]
     if stats is None:
@@ -524,8 +544,8 @@ def mlmc_level_estimate(dlat, N, coupled, p, K_fine, K_coarse, kind, seed, first
         work = torch.empty((need,), dtype=torch.uint8, device=eps.device)
     _check(lib().mlmc_level_estimate(dlat.handle, N, int(coupled), float(p), K_fine, K_coarse, kind,
                                      int(seed) & (2**64 - 1), first_sample, M, _ptr(eps), ne, float(delta), smoother,
-                                     prec, _ptr(stats), _ptr(work), work.numel(), _ctx(ctx), _stream(stream)),
-           "mlmc_level_estimate")
+                                     prec, _ptr(stats), _ptr(work), work.numel(), _ptr(first_counter), _ctx(ctx),
+                                     _stream(stream)), "mlmc_level_estimate")
     return stats
 
 

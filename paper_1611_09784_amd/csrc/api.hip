@@ -211,13 +211,15 @@ mlmc_status run_chase(mlmc_precision prec, const void *H, int64_t ld, const int3
 // matrix in H (NULL: u ld^2).
 mlmc_status run_large(mlmc_precision prec, void *H, int64_t ld, const int32_t *n, int64_t units, double *w, int64_t ldw,
                       const EigBuffers &b, hipStream_t s, bool defer_bisect = false, bool defer_chase = false,
-                      const int64_t *offs = nullptr) {
+                      const int64_t *offs = nullptr, int upd_rows = 32) {
     if (prec == MLMC_PREC_FP64)
         LAUNCH("band_reduce", s, launch_band_reduce<double>(static_cast<cpx<double> *>(H), ld, n, units,
-                                                            static_cast<cpx<double> *>(b.partial), s, b.stride, offs));
+                                                            static_cast<cpx<double> *>(b.partial), s, b.stride, offs,
+                                                            upd_rows));
     else
         LAUNCH("band_reduce", s, launch_band_reduce<float>(static_cast<cpx<float> *>(H), ld, n, units,
-                                                           static_cast<cpx<float> *>(b.partial), s, b.stride, offs));
+                                                           static_cast<cpx<float> *>(b.partial), s, b.stride, offs,
+                                                           upd_rows));
     if (defer_chase) return MLMC_OK;
     const mlmc_status st = run_chase(prec, H, ld, n, units, b, s, 0, offs);
     if (st != MLMC_OK || defer_bisect) return st;
@@ -291,7 +293,7 @@ LevelLayout level_layout(const mlmc_lattice_s *lat, int N, bool coupled, int Kf,
 // H L^{-H}, then the standard path on C).
 mlmc_status run_generalized(mlmc_precision prec, void *H, void *S, int64_t ld, const int32_t *n, int64_t units,
                             double *w, int64_t ldw, const EigBuffers &b, hipStream_t s, bool *bisect_pending = nullptr,
-                            bool *chase_pending = nullptr) {
+                            bool *chase_pending = nullptr, int upd_rows = 32) {
     if (prec == MLMC_PREC_FP64)
         LAUNCH("overlap_reduce", s, launch_cholesky_reduce<double>(static_cast<cpx<double> *>(H), static_cast<cpx<double> *>(S), ld, n, units,
                                                             static_cast<cpx<double> *>(b.partial), s));
@@ -308,7 +310,7 @@ mlmc_status run_generalized(mlmc_precision prec, void *H, void *S, int64_t ld, c
     if (bisect_pending) *bisect_pending = true;
     if (bisect_pending && chase_pending) *chase_pending = true;
     return run_large(prec, H, ld, n, units, w, ldw, b, s, bisect_pending != nullptr,
-                     bisect_pending != nullptr && chase_pending != nullptr);
+                     bisect_pending != nullptr && chase_pending != nullptr, nullptr, upd_rows);
 }
 
 // Eigenvalues of every (outcome, k) unit of `ns` outcomes of side N.  With
@@ -318,7 +320,8 @@ mlmc_status run_generalized(mlmc_precision prec, void *H, void *S, int64_t ld, c
 // run_chase first).
 mlmc_status outcome_spectra(const mlmc_lattice_s *lat, int N, const uint8_t *mask, int64_t ns, const double *kred,
                             int nk, mlmc_precision prec, double *w, int32_t *n_out, const EigBuffers &b,
-                            hipStream_t s, bool *bisect_pending = nullptr, bool *chase_pending = nullptr) {
+                            hipStream_t s, bool *bisect_pending = nullptr, bool *chase_pending = nullptr,
+                            int upd_rows = 32) {
     const int64_t ld = (int64_t)lat->dev.n_orb * N * N;
     const int64_t units = ns * nk;
     if (bisect_pending) *bisect_pending = false;
@@ -332,7 +335,7 @@ mlmc_status outcome_spectra(const mlmc_lattice_s *lat, int N, const uint8_t *mas
             LAUNCH("assemble", s, launch_assemble<float>(lat->dev, N, mask, ns, kred, nk, static_cast<cpx<float> *>(b.H), ld, n_out, s, false, true));
             LAUNCH("assemble", s, launch_assemble<float>(lat->dev, N, mask, ns, kred, nk, static_cast<cpx<float> *>(b.S), ld, n_out, s, true, true));
         }
-        return run_generalized(prec, b.H, b.S, ld, n_out, units, w, ld, b, s, bisect_pending, chase_pending);
+        return run_generalized(prec, b.H, b.S, ld, n_out, units, w, ld, b, s, bisect_pending, chase_pending, upd_rows);
     }
     if (ld <= small_cap(prec)) {
         if (prec == MLMC_PREC_FP64)
@@ -348,7 +351,7 @@ mlmc_status outcome_spectra(const mlmc_lattice_s *lat, int N, const uint8_t *mas
     if (bisect_pending) *bisect_pending = true;
     if (bisect_pending && chase_pending) *chase_pending = true;
     return run_large(prec, b.H, ld, n_out, units, w, ld, b, s, bisect_pending != nullptr,
-                     bisect_pending != nullptr && chase_pending != nullptr);
+                     bisect_pending != nullptr && chase_pending != nullptr, nullptr, upd_rows);
 }
 
 // Workgroups (one per CU) of a chase on a context's chase stream: the next
@@ -386,6 +389,7 @@ struct mlmc_context_s {
     int device = -1;
     hipStream_t s = nullptr;      // back stream
     hipStream_t sc = nullptr;     // chase stream
+    hipStream_t front[2] = {};    // two caller streams the context offers (mlmc_context_stream)
     int64_t bisect_blocks = 0;    // workgroups of a bisection on the back stream: one per CU
     int64_t chase_blocks = 0;     // workgroups of a chase on the chase stream
     hipEvent_t begin = nullptr;   // caller's stream -> back stream
@@ -402,6 +406,7 @@ struct mlmc_context_s {
     LayoutKey last;
     int next_set = 0;
     hipStream_t last_stream = nullptr;  // the previous call's stream
+    int upd_rows = 32;                  // rows of the stage-1 update tiles (32 or 64)
     std::mutex mu;                      // held while a call enqueues its work on this context
     LaunchTimer timer;
 
@@ -423,6 +428,13 @@ struct mlmc_context_s {
         if (sc) keep(hipStreamDestroy(sc));
         if (s) keep(hipStreamDestroy(s));
         sc = s = nullptr;
+        for (hipStream_t &f : front) {
+            if (f) {
+                keep(hipStreamSynchronize(f));
+                keep(hipStreamDestroy(f));
+            }
+            f = nullptr;
+        }
         return err;
     }
 };
@@ -892,7 +904,8 @@ struct TimerScope {
 // [M][N][N][G]).  Adds the level sums to d_stats (if not NULL) and writes the
 // per-outcome Y and Q_f rows to d_Y, d_Q (if not NULL).
 mlmc_status level_run(mlmc_context ctx, mlmc_lattice lat, int32_t N, bool cpl, double p, int32_t Kf, int32_t Kc,
-                      mlmc_kgrid_kind kind, uint64_t seed, int64_t first_sample, const uint8_t *d_mask_in,
+                      mlmc_kgrid_kind kind, uint64_t seed, int64_t first_sample, int64_t *d_first,
+                      const uint8_t *d_mask_in,
                       int64_t M, const double *d_eps, int32_t n_eps, double delta, mlmc_smoother smoother,
                       mlmc_precision prec, double *d_stats, double *d_Y, double *d_Q, void *d_work,
                       size_t work_bytes, hipStream_t s, bool single_pass_ok = false) {
@@ -1010,15 +1023,16 @@ mlmc_status level_run(mlmc_context ctx, mlmc_lattice lat, int32_t N, bool cpl, d
             mask = d_mask_in + done * mask_bytes;
         else
             LAUNCH("sample_vacancies", s,
-                   launch_sample_vacancies(lat->dev, N, thr, seed, tag, first_sample + done, ns, L.mask, s));
+                   launch_sample_vacancies(lat->dev, N, thr, seed, tag, first_sample + done, ns, L.mask, s, d_first));
         bool pend_f = false, pend_c = false, chase_f = false, chase_c = false;
         const EigBuffers bf = L.bf.set(q), bc = L.bc.set(q);
-        st = outcome_spectra(lat, N, mask, ns, L.kf[q], nkf, prec, L.wf[q], L.nf[q], bf, s, &pend_f, &chase_f);
+        const int upd = ctx ? ctx->upd_rows : 32;
+        st = outcome_spectra(lat, N, mask, ns, L.kf[q], nkf, prec, L.wf[q], L.nf[q], bf, s, &pend_f, &chase_f, upd);
         if (st != MLMC_OK) return st;
         if (cpl) {
             LAUNCH("partition", s, launch_partition(N, G, mask, ns, L.quarters, s));
             st = outcome_spectra(lat, h, L.quarters, ns * 4, L.kc[q], nkc, prec, L.wc[q], L.nc[q], bc, s, &pend_c,
-                                 &chase_c);
+                                 &chase_c, upd);
             if (st != MLMC_OK) return st;
         }
         hipStream_t sc = S.chase, sb = S.back;
@@ -1065,6 +1079,9 @@ mlmc_status level_run(mlmc_context ctx, mlmc_lattice lat, int32_t N, bool cpl, d
                                   d_Y ? d_Y + done * n_eps : nullptr, d_Q ? d_Q + done * n_eps : nullptr));
         if (ctx) HIP_TRY(hipEventRecord(ctx->freed[q], sb), "level: event");
     }
+    // the device-resident counter moves past this call's samples (after the
+    // last sampling kernel, which ran on this stream)
+    if (d_first) HIP_TRY(launch_advance_counter(d_first, M, s), "level: counter");
     guard.ok = true;
     if (ctx) {
         HIP_TRY(hipEventRecord(ctx->end, ctx->s), "level: event");
@@ -1096,14 +1113,15 @@ mlmc_status mlmc_level_estimate(mlmc_lattice lat, int32_t N, int32_t coupled, do
                                 mlmc_kgrid_kind kind, uint64_t seed, int64_t first_sample, int64_t M,
                                 const double *d_eps, int32_t n_eps, double delta, mlmc_smoother smoother,
                                 mlmc_precision prec, double *d_stats, void *d_work, size_t work_bytes,
-                                mlmc_context ctx, mlmc_stream stream) {
+                                int64_t *d_first_sample, mlmc_context ctx, mlmc_stream stream) {
     mlmc_status st = check_level_call(lat, N, coupled, p, Kf, Kc, kind, M, d_eps, n_eps, delta, smoother, prec);
     if (st != MLMC_OK) return st;
     if (first_sample < 0) return fail(MLMC_ERR_INVALID_ARG, "level: negative first sample");
     if (M == 0) return MLMC_OK;
     if (!d_stats) return fail(MLMC_ERR_INVALID_ARG, "level: NULL stats");
-    return level_run(ctx, lat, N, coupled != 0, p, Kf, Kc, kind, seed, first_sample, nullptr, M, d_eps, n_eps, delta,
-                     smoother, prec, d_stats, nullptr, nullptr, d_work, work_bytes, static_cast<hipStream_t>(stream));
+    return level_run(ctx, lat, N, coupled != 0, p, Kf, Kc, kind, seed, first_sample, d_first_sample, nullptr, M, d_eps,
+                     n_eps, delta, smoother, prec, d_stats, nullptr, nullptr, d_work, work_bytes,
+                     static_cast<hipStream_t>(stream));
 }
 
 mlmc_status mlmc_level_outcomes(mlmc_lattice lat, int32_t N, int32_t coupled, int32_t Kf, int32_t Kc,
@@ -1116,7 +1134,7 @@ mlmc_status mlmc_level_outcomes(mlmc_lattice lat, int32_t N, int32_t coupled, in
     if (M == 0) return MLMC_OK;
     if (!d_mask) return fail(MLMC_ERR_INVALID_ARG, "level_outcomes: NULL mask");
     if (!d_stats && !d_Y && !d_Q) return fail(MLMC_ERR_INVALID_ARG, "level_outcomes: no output");
-    return level_run(ctx, lat, N, coupled != 0, 0.0, Kf, Kc, kind, 0, 0, d_mask, M, d_eps, n_eps, delta, smoother,
+    return level_run(ctx, lat, N, coupled != 0, 0.0, Kf, Kc, kind, 0, 0, nullptr, d_mask, M, d_eps, n_eps, delta, smoother,
                      prec, d_stats, d_Y, d_Q, d_work, work_bytes, static_cast<hipStream_t>(stream), true);
 }
 
@@ -1132,7 +1150,14 @@ mlmc_status mlmc_context_create(mlmc_context *out) {
     // per CU on the graphene N = 16 workload).
     c->bisect_blocks = cus > 0 ? cus : 1;
     c->chase_blocks = chase_cus(cus);
-    // Default-priority streams that do not synchronise with the null stream.
+    // Default-priority streams that do not synchronise with the null stream,
+    // created one after another: the runtime spreads consecutively created
+    // streams over its hardware queues, so the two caller streams, the back
+    // stream and the chase stream do not share one (streams that share a
+    // hardware queue run their work in order, which would serialise the
+    // chase behind the next chunk's reduction).
+    if (err == hipSuccess) err = hipStreamCreateWithFlags(&c->front[0], hipStreamNonBlocking);
+    if (err == hipSuccess) err = hipStreamCreateWithFlags(&c->front[1], hipStreamNonBlocking);
     if (err == hipSuccess) err = hipStreamCreateWithFlags(&c->s, hipStreamNonBlocking);
     if (err == hipSuccess) err = hipStreamCreateWithFlags(&c->sc, hipStreamNonBlocking);
     hipEvent_t *evs[4 + kLevelSets] = {&c->begin, &c->ready, &c->chased, &c->end};
@@ -1165,6 +1190,28 @@ mlmc_status mlmc_context_destroy(mlmc_context ctx) {
     }
     delete ctx;
     if (err != hipSuccess) return hip_fail(err, "context_destroy");
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_context_stream(mlmc_context ctx, int32_t index, mlmc_stream *out) {
+    if (!ctx || !out || index < 0 || index > 1) return fail(MLMC_ERR_INVALID_ARG, "context_stream: bad argument");
+    *out = ctx->front[index];
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_context_configure(mlmc_context ctx, const mlmc_launch_config *cfg) {
+    if (!ctx || !cfg) return fail(MLMC_ERR_INVALID_ARG, "context_configure: NULL argument");
+    if (cfg->chase_workgroups < 0 || cfg->bisect_workgroups < 0)
+        return fail(MLMC_ERR_INVALID_ARG, "context_configure: negative workgroup count");
+    if (cfg->update_tile_rows != 0 && cfg->update_tile_rows != 32 && cfg->update_tile_rows != 64)
+        return fail(MLMC_ERR_INVALID_ARG, "context_configure: update_tile_rows %d (0, 32 or 64)",
+                    (int)cfg->update_tile_rows);
+    int cus = 0;
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device), "context_configure");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->chase_blocks = cfg->chase_workgroups > 0 ? cfg->chase_workgroups : chase_cus(cus);
+    ctx->bisect_blocks = cfg->bisect_workgroups > 0 ? cfg->bisect_workgroups : (cus > 0 ? cus : 1);
+    ctx->upd_rows = cfg->update_tile_rows > 0 ? cfg->update_tile_rows : 32;
     return MLMC_OK;
 }
 

@@ -809,7 +809,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
 
 template <typename T>
 hipError_t launch_band_reduce(cpx<T> *H, int64_t ld, const int32_t *n_in, int64_t batch, cpx<T> *work,
-                              hipStream_t s, int64_t stride, const int64_t *offs) {
+                              hipStream_t s, int64_t stride, const int64_t *offs, int upd_rows) {
+    if (upd_rows != 32 && upd_rows != 64) return hipErrorInvalidValue;
     if (batch == 0) return hipSuccess;
     if (stride == 0) stride = (int64_t)tridiag_twostage_work_elems<T>(ld);
     if (stride < (int64_t)tridiag_twostage_work_elems<T>(ld)) return hipErrorInvalidValue;
@@ -834,10 +835,16 @@ hipError_t launch_band_reduce(cpx<T> *H, int64_t ld, const int32_t *n_in, int64_
         // The rank-2k update in 32 x 64 tiles (small enough to share a CU with
         // a chase workgroup).  Lower tiles of row blocks 0 .. nb32 - 1: pairs of
         // row blocks (2a, 2a + 1) hold 2 (a + 1) tiles.
-        const int64_t nb32 = (mmax + kUpdBlk / 2 - 1) / (kUpdBlk / 2), ha = (nb32 - 1) / 2;
-        const int64_t ntile = (nb32 % 2 == 0) ? (ha + 1) * (ha + 2) : (ha + 1) * (ha + 1);
-        hipLaunchKernelGGL(band_update32_kernel<T>, dim3(xcd_grid(batch, ntile)), dim3(256), 0, s, H, ld, offs, n_in, work,
-                           stride, p, batch, ntile, 2);
+        if (upd_rows == 32) {
+            const int64_t nb32 = (mmax + kUpdBlk / 2 - 1) / (kUpdBlk / 2), ha = (nb32 - 1) / 2;
+            const int64_t ntile = (nb32 % 2 == 0) ? (ha + 1) * (ha + 2) : (ha + 1) * (ha + 1);
+            hipLaunchKernelGGL(band_update32_kernel<T>, dim3(xcd_grid(batch, ntile)), dim3(256), 0, s, H, ld, offs,
+                               n_in, work, stride, p, batch, ntile, 2);
+        } else {
+            const int64_t nblk = (mmax + kUpdBlk - 1) / kUpdBlk, ntile = nblk * (nblk + 1) / 2;
+            hipLaunchKernelGGL(band_update_kernel<T>, dim3(xcd_grid(batch, ntile)), dim3(256), 0, s, H, ld, offs,
+                               n_in, work, stride, p, batch, ntile, 2);
+        }
         const hipError_t err = hipGetLastError();
         if (err != hipSuccess) return err;
     }
@@ -867,8 +874,8 @@ template hipError_t launch_rank2k_update<float>(cpx<float> *, int64_t, const int
 template size_t tridiag_twostage_work_elems<double>(int64_t);
 template size_t tridiag_twostage_work_elems<float>(int64_t);
 template hipError_t launch_band_reduce<double>(cpx<double> *, int64_t, const int32_t *, int64_t, cpx<double> *,
-                                               hipStream_t, int64_t, const int64_t *);
+                                               hipStream_t, int64_t, const int64_t *, int);
 template hipError_t launch_band_reduce<float>(cpx<float> *, int64_t, const int32_t *, int64_t, cpx<float> *,
-                                              hipStream_t, int64_t, const int64_t *);
+                                              hipStream_t, int64_t, const int64_t *, int);
 
 }  // namespace mlmc

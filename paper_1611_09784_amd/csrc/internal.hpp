@@ -80,7 +80,10 @@ __host__ __device__ constexpr int64_t packed_size(int64_t n) { return n * (n + 1
 // Launchers (each returns hipGetLastError() of its launch).
 // ---------------------------------------------------------------------------
 hipError_t launch_sample_vacancies(const DevLattice &lat, int N, uint64_t threshold, uint64_t seed, uint64_t tag,
-                                   int64_t first, int64_t n_samples, uint8_t *mask, hipStream_t s);
+                                   int64_t first, int64_t n_samples, uint8_t *mask, hipStream_t s,
+                                   const int64_t *first_dev = nullptr);
+// *counter += delta on the device.
+hipError_t launch_advance_counter(int64_t *counter, int64_t delta, hipStream_t s);
 hipError_t launch_partition(int N, int G, const uint8_t *mask, int64_t n_samples, uint8_t *quarters, hipStream_t s);
 hipError_t launch_kgrid(int kind, int K, double *kred, double *kweight, hipStream_t s);
 // Number of points of a grid kind (K^2, or 3 K^2 for the three-rhombus lattice).
@@ -112,9 +115,12 @@ hipError_t launch_small_from_matrix(const cpx<T> *H, int64_t ld, const int32_t *
 // elements between consecutive matrices' workspaces (0: the two-stage
 // layout's own size; a caller whose other kernels use a larger per-matrix
 // workspace passes that, so that their parts stay disjoint).
+// upd_rows: row height of the rank-2k update's tiles, 32 (32 x 64 tiles with
+// 16 KiB of LDS, small enough to share a CU with a chase workgroup) or 64
+// (64 x 64 tiles, 64 KiB).
 template <typename T>
 hipError_t launch_band_reduce(cpx<T> *H, int64_t ld, const int32_t *n_in, int64_t batch, cpx<T> *work,
-                              hipStream_t s, int64_t stride = 0, const int64_t *offs = nullptr);
+                              hipStream_t s, int64_t stride = 0, const int64_t *offs = nullptr, int upd_rows = 32);
 template <typename T>
 hipError_t launch_band_chase(const cpx<T> *H, int64_t ld, const int32_t *n_in, int64_t batch, double *d, double *e,
                              int64_t lde, cpx<T> *work, hipStream_t s, int64_t max_blocks = 0, int64_t stride = 0,

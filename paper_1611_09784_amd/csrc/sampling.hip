@@ -24,12 +24,15 @@ __device__ __forceinline__ void philox4x64_10(uint64_t x[4], uint64_t k0, uint64
     }
 }
 
-// One thread per (sample, block of four groups).
+// One thread per (sample, block of four groups).  The first sample index is
+// `first`, plus *first_dev when that is given (a device-resident counter).
 __global__ void sample_vacancies_kernel(const uint8_t *__restrict__ removable, int G, int64_t groups,
                                         int64_t blocks_per_sample, uint64_t threshold, uint64_t seed, uint64_t tag,
-                                        int64_t first, int64_t n_samples, uint8_t *__restrict__ mask) {
+                                        int64_t first, const int64_t *__restrict__ first_dev, int64_t n_samples,
+                                        uint8_t *__restrict__ mask) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_samples * blocks_per_sample) return;
+    if (first_dev) first += *first_dev;
     const int64_t s = t / blocks_per_sample, blk = t % blocks_per_sample;
     uint64_t x[4] = {(uint64_t)(first + s), (uint64_t)blk, 0, 0};
     philox4x64_10(x, seed, tag);
@@ -44,7 +47,8 @@ __global__ void sample_vacancies_kernel(const uint8_t *__restrict__ removable, i
 }
 
 hipError_t launch_sample_vacancies(const DevLattice &lat, int N, uint64_t threshold, uint64_t seed, uint64_t tag,
-                                   int64_t first, int64_t n_samples, uint8_t *mask, hipStream_t s) {
+                                   int64_t first, int64_t n_samples, uint8_t *mask, hipStream_t s,
+                                   const int64_t *first_dev) {
     const int64_t groups = (int64_t)N * N * lat.n_groups;
     const int64_t bps = (groups + 3) / 4;
     const int64_t total = n_samples * bps;
@@ -52,7 +56,17 @@ hipError_t launch_sample_vacancies(const DevLattice &lat, int N, uint64_t thresh
     const int threads = 256;
     const int64_t blocks = (total + threads - 1) / threads;
     hipLaunchKernelGGL(sample_vacancies_kernel, dim3((unsigned)blocks), dim3(threads), 0, s, lat.removable,
-                       lat.n_groups, groups, bps, threshold, seed, tag, first, n_samples, mask);
+                       lat.n_groups, groups, bps, threshold, seed, tag, first, first_dev, n_samples, mask);
+    return hipGetLastError();
+}
+
+// *counter += delta (one thread).
+__global__ void advance_counter_kernel(int64_t *counter, int64_t delta) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *counter += delta;
+}
+
+hipError_t launch_advance_counter(int64_t *counter, int64_t delta, hipStream_t s) {
+    hipLaunchKernelGGL(advance_counter_kernel, dim3(1), dim3(64), 0, s, counter, delta);
     return hipGetLastError();
 }
 

@@ -60,7 +60,7 @@ class Estimator:
 
     def __init__(self, dlat: B.DeviceLattice, eps: np.ndarray, delta: float, p: float, kind: int, seed: int,
                  smoother: int = B.MLMC_SMOOTH_GAUSS, prec: int = B.MLMC_PREC_FP64, chunk_samples: int = 64,
-                 stream=None, dedup_max_orbitals: int = 0):
+                 stream=None, dedup_max_orbitals: int = 0, tuner=None, graphs: bool = False):
         self.dlat = dlat
         self.eps = torch.as_tensor(np.asarray(eps, dtype=np.float64), device=dlat.device)
         self.delta, self.p, self.kind, self.seed = float(delta), float(p), int(kind), int(seed)
@@ -68,18 +68,42 @@ class Estimator:
         self.stream = stream
         self.ctx = B.Context(dlat.device.index)
         self._work = {}
+        # tuner: an autotune.Tuner; each level then takes its measured chunk
+        # size and launch choices.  graphs: levels on the LDS-resident path
+        # replay a captured level call (see LevelGraph).
+        self.tuner = tuner
+        self.graphs = bool(graphs)
+        self._tuned = {}
+        self._graph = {}
         # levels whose matrices have at most this many orbitals solve each
         # distinct outcome once (0: off)
         self.dedup_max_orbitals = int(dedup_max_orbitals)
         self.unique_solved = 0
 
+    def _tuning(self, lvl: LevelState):
+        key = (lvl.N, lvl.coupled, lvl.K, lvl.K_coarse)
+        if self.tuner is None:
+            return None
+        if key not in self._tuned:
+            self._tuned[key] = self.tuner.tune_level(self.dlat, lvl.N, lvl.coupled, lvl.K, lvl.K_coarse, self.kind,
+                                                     self.prec, self.eps, self.delta, self.p)
+        return self._tuned[key]
+
+    def _chunk(self, lvl: LevelState) -> int:
+        t = self._tuning(lvl)
+        return self.chunk if t is None else t.chunk
+
     def _workspace(self, lvl: LevelState):
         key = (lvl.N, lvl.coupled, lvl.K, lvl.K_coarse)
         if key not in self._work:
-            need = B.mlmc_level_workspace(self.dlat, lvl.N, lvl.coupled, lvl.K, lvl.K_coarse, self.kind, self.chunk,
-                                          self.prec, self.eps.shape[0])
+            need = B.mlmc_level_workspace(self.dlat, lvl.N, lvl.coupled, lvl.K, lvl.K_coarse, self.kind,
+                                          self._chunk(lvl), self.prec, self.eps.shape[0])
             self._work[key] = torch.empty((need,), dtype=torch.uint8, device=self.dlat.device)
         return self._work[key]
+
+    def _use_graph(self, lvl: LevelState) -> bool:
+        return self.graphs and self.dlat.max_orbitals(lvl.N) <= B.SMALL_MAX[self.prec] and \
+            (not lvl.coupled or self.dlat.max_orbitals(lvl.N // 2) <= B.SMALL_MAX[self.prec])
 
     def add_samples(self, lvl: LevelState, count: int):
         if count <= 0:
@@ -90,19 +114,40 @@ class Estimator:
         if self.dedup_max_orbitals and self.dlat.max_orbitals(lvl.N) <= self.dedup_max_orbitals:
             self._add_deduplicated(lvl, count, stats)
         else:
-            B.mlmc_level_estimate(self.dlat, lvl.N, lvl.coupled, self.p, lvl.K, lvl.K_coarse, self.kind, self.seed,
-                                  lvl.M, count, self.eps, self.delta, self.smoother, self.prec, stats=stats,
-                                  work=self._workspace(lvl), ctx=self.ctx, stream=self.stream)
+            done = 0
+            if self._use_graph(lvl):
+                g = self._level_graph(lvl)
+                reps = count // g.M
+                if reps:
+                    g.run(lvl.M, reps, stats)
+                    done = reps * g.M
+            if count > done:
+                t = self._tuning(lvl)
+                if t is not None:
+                    t.configure(self.ctx)
+                B.mlmc_level_estimate(self.dlat, lvl.N, lvl.coupled, self.p, lvl.K, lvl.K_coarse, self.kind,
+                                      self.seed, lvl.M + done, count - done, self.eps, self.delta, self.smoother,
+                                      self.prec, stats=stats, work=self._workspace(lvl), ctx=self.ctx,
+                                      stream=self.stream)
         host = stats.cpu().numpy()
         lvl.seconds += time.perf_counter() - t0
         lvl.stats = host if lvl.stats is None else lvl.stats + host
         lvl.M += count
+
+    def _level_graph(self, lvl: LevelState):
+        key = (lvl.N, lvl.coupled, lvl.K, lvl.K_coarse)
+        if key not in self._graph:
+            c = self._chunk(lvl)
+            self._graph[key] = LevelGraph(self.dlat, lvl.N, lvl.coupled, self.p, lvl.K, lvl.K_coarse, self.kind,
+                                          self.seed, 4 * c, self.eps, self.delta, self.smoother, self.prec, c)
+        return self._graph[key]
 
     def close(self):
         if self.ctx is not None:
             self.ctx.close()
             self.ctx = None
         self._work.clear()
+        self._graph.clear()
 
     # -- explicit outcomes (steps a3-a7 through the C ABI) -------------------
     def outcome_idos(self, N: int, masks: torch.Tensor, K: int, budget_bytes: int = 1 << 30) -> torch.Tensor:
@@ -176,6 +221,44 @@ class Estimator:
         Q = self.outcome_idos(N, rep, K).cpu().numpy()
         self.unique_solved += int(first.size)
         return weight @ Q
+
+
+class LevelGraph:
+    """A level call of M samples captured once as a HIP graph (one stream, no
+    pipeline context) and replayed: the first sample index lives in a device
+    counter that the call reads when it draws outcomes and advances by M at
+    its end, so every replay draws the next M samples.  Replays add their
+    level sums into the graph's own sums, which run() adds to the caller's
+    (on the device, after the replays)."""
+
+    def __init__(self, dlat, N, coupled, p, K, Kc, kind, seed, M, eps, delta, smoother, prec, chunk):
+        dev = dlat.device
+        self.M = int(M)
+        ne = eps.shape[0]
+        self.stats = torch.zeros((4, ne), dtype=torch.float64, device=dev)
+        self.counter = torch.zeros((1,), dtype=torch.int64, device=dev)
+        need = B.mlmc_level_workspace(dlat, N, coupled, K, Kc, kind, chunk, prec, ne)
+        self.work = torch.empty((need,), dtype=torch.uint8, device=dev)
+        args = (dlat, N, coupled, p, K, Kc, kind, seed, 0, self.M, eps, delta, smoother, prec)
+        # one eager call first: the kernels' first launches happen outside the capture
+        side = torch.cuda.Stream(dev)
+        side.wait_stream(torch.cuda.current_stream(dev))
+        with torch.cuda.stream(side):
+            B.mlmc_level_estimate(*args, stats=self.stats, work=self.work, first_counter=self.counter)
+        torch.cuda.current_stream(dev).wait_stream(side)
+        torch.cuda.synchronize(dev)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            B.mlmc_level_estimate(*args, stats=self.stats, work=self.work, first_counter=self.counter)
+        torch.cuda.synchronize(dev)
+
+    def run(self, first: int, reps: int, stats: torch.Tensor):
+        """Samples first .. first + reps M - 1 added into stats."""
+        self.counter.fill_(int(first))
+        self.stats.zero_()
+        for _ in range(reps):
+            self.graph.replay()
+        stats += self.stats
 
 
 def outcome_keys(masks: np.ndarray, removable: np.ndarray, translations: bool) -> np.ndarray:

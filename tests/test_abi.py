@@ -84,7 +84,8 @@ def test_validation_without_device(B):
     assert lib.mlmc_idos(None, 8, None, 1, 1, None, -1.0, None, 5, 0.1, 0, None, None) == B.MLMC_ERR_INVALID_ARG
     assert lib.mlmc_sample_vacancies(None, 4, 0.1, 0, 0, 0, 1, None, None) == B.MLMC_ERR_INVALID_ARG
     assert lib.mlmc_level_estimate(None, 4, 0, 0.1, 1, 1, 0, 0, 0, 1, None, 1, 0.1, 0, 0, None, None, 0,
-                                   None, None) == B.MLMC_ERR_INVALID_ARG
+                                   None, None, None) == B.MLMC_ERR_INVALID_ARG
+    assert lib.mlmc_context_configure(None, None) == B.MLMC_ERR_INVALID_ARG
     assert lib.mlmc_level_outcomes(None, 4, 0, 1, 1, 0, None, 1, None, 1, 0.1, 0, 0, None, None, None, None, 0,
                                    None, None) == B.MLMC_ERR_INVALID_ARG
     assert lib.mlmc_context_create(None) == B.MLMC_ERR_INVALID_ARG
@@ -104,6 +105,7 @@ def test_lattice_descriptor_layout(B):
     assert C.sizeof(B._Hop) == 32
     assert C.sizeof(B._LatticeDesc) == 72
     assert C.sizeof(B._WorkspaceRequest) == 80
+    assert C.sizeof(B._LaunchConfig) == 24
 
 
 def test_kgrid_points_host_only(B):
