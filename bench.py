@@ -185,7 +185,7 @@ def copy_calibration():
     print(json.dumps({"copy_bytes": n, "copies": 3}), flush=True)
 
 
-def time_to_tol(B, dev):
+def time_to_tol(B, dev, wl_name="graphene_mlmc", variants=None, oracle_samples=None):
     """MLMC IDoS estimator of the graphene level hierarchy N = 4, 8, 16, 32
     (Gamma-centred K = 32 / N, p = 0.02, seed 303) run to TOL = 1e-3 relative
     with the FP64 path, the mixed path (FP32 reduction, FP64 bisection and
@@ -202,11 +202,11 @@ def time_to_tol(B, dev):
     from mlmc_inputs.configs import workload_eps
     from paper_1611_09784_amd import driver as D
 
-    wl = WORKLOADS["graphene_mlmc"]
+    wl = WORKLOADS[wl_name]
     lat = wl.make_lattice()
     eps = workload_eps(wl)
     dlat = B.DeviceLattice(lat, 0)
-    Ks = [wl.NK // N for N in wl.levels]
+    Ks = [wl.NK // N for N in wl.levels] if wl.NK else [wl.K] * len(wl.levels)
     out = {"workload": wl.name, "levels": list(wl.levels), "K": Ks, "tol_rel": wl.tol}
     from paper_1611_09784_amd.autotune import Tuner
     tuner = Tuner(min_seconds=0.3, max_call_seconds=0.4, chase_fractions=(0.625, 0.75, 0.875, 1.0),
@@ -220,11 +220,11 @@ def time_to_tol(B, dev):
             tunings.setdefault(pname, []).append({"N": st.N, "chunk": t.chunk, "chase_workgroups": t.chase_workgroups,
                                                   "update_tile_rows": t.update_tile_rows, "trials": t.trials})
     out["tuning"] = {"seconds": round(time.perf_counter() - t_tune, 2), "levels": tunings}
-    for name, prec, dedup, tuned in (("fp64", B.MLMC_PREC_FP64, 0, False), ("mixed", B.MLMC_PREC_MIXED, 0, False),
-                                     ("mixed_reuse", B.MLMC_PREC_MIXED, 128, False),
-                                     ("fp64_tuned", B.MLMC_PREC_FP64, 0, True),
-                                     ("mixed_tuned", B.MLMC_PREC_MIXED, 0, True),
-                                     ("mixed_tuned_reuse", B.MLMC_PREC_MIXED, 128, True)):
+    if variants is None:
+        variants = (("fp64", B.MLMC_PREC_FP64, 0, False), ("mixed", B.MLMC_PREC_MIXED, 0, False),
+                    ("mixed_reuse", B.MLMC_PREC_MIXED, 128, False), ("fp64_tuned", B.MLMC_PREC_FP64, 0, True),
+                    ("mixed_tuned", B.MLMC_PREC_MIXED, 0, True), ("mixed_tuned_reuse", B.MLMC_PREC_MIXED, 128, True))
+    for name, prec, dedup, tuned in variants:
         est = D.Estimator(dlat, eps, wl.delta, wl.p, wl.kgrid, wl.seed, wl.smoother, prec, chunk_samples=32,
                           dedup_max_orbitals=dedup, tuner=tuner if tuned else None, graphs=tuned)
         for st in D.make_levels(wl.levels, Ks):  # warm-up: workspaces and first launches
@@ -232,7 +232,10 @@ def time_to_tol(B, dev):
         torch.cuda.synchronize(dev)
         r = D.run_mlmc(est, wl.levels, Ks, wl.tol)
         est.close()
+        nks = [B.mlmc_kgrid_points(wl.kgrid, st.K) + (4 * B.mlmc_kgrid_points(wl.kgrid, st.K_coarse) if st.coupled
+                                                       else 0) for st in r.levels]
         out[name] = {"seconds": round(r.seconds, 3), "M": [st.M for st in r.levels], "error": r.error,
+                     "eigensolves": int(sum(m * k for m, k in zip([st.M for st in r.levels], nks))),
                      "tol_abs": r.tol_abs, "rounds": len(r.rounds),
                      "seconds_per_level": [round(st.seconds, 3) for st in r.levels]}
         if dedup:
@@ -245,8 +248,12 @@ def time_to_tol(B, dev):
     errs = {"fp64": [], "mixed": []}
     samples = []
     for l, st in enumerate(D.make_levels(wl.levels, Ks)):
-        ns = 4 if st.N >= 32 else 8
+        ns = (4 if st.N >= 32 else 8) if oracle_samples is None else oracle_samples[l]
         samples.append(ns)
+        if ns == 0:
+            errs["fp64"].append(None)
+            errs["mixed"].append(None)
+            continue
         want = oracle.level_estimate(lat, st.N, st.coupled, wl.p, st.K, st.K_coarse, wl.kgrid, wl.seed, 0, ns, eps,
                                      wl.delta, wl.smoother, n_threads=host_threads())
         for name, prec in (("fp64", B.MLMC_PREC_FP64), ("mixed", B.MLMC_PREC_MIXED)):
@@ -258,9 +265,9 @@ def time_to_tol(B, dev):
             errs[name].append(float(np.max(np.abs(lv.stats[[0, 2]] - want[[0, 2]]) / ns)))
     out["idos_err_vs_oracle"] = {"samples_per_level": samples, **errs,
                                  "unit": "states/Angstrom^2, max over energies of mean Y and mean Q_f"}
-    out["speedup_mixed_vs_fp64"] = round(out["fp64"]["seconds"] / out["mixed"]["seconds"], 3)
-    out["speedup_mixed_reuse_vs_fp64"] = round(out["fp64"]["seconds"] / out["mixed_reuse"]["seconds"], 3)
-    out["speedup_mixed_tuned_vs_fp64"] = round(out["fp64"]["seconds"] / out["mixed_tuned"]["seconds"], 3)
+    for other in ("mixed", "mixed_reuse", "mixed_tuned", "fp64_tuned"):
+        if other in out and "fp64" in out:
+            out[f"speedup_{other}_vs_fp64"] = round(out["fp64"]["seconds"] / out[other]["seconds"], 3)
     dlat.close()
     return out
 
@@ -515,6 +522,26 @@ def main():
     from mlmc_inputs import WORKLOADS
     from mlmc_inputs.configs import workload_eps
     from paper_1611_09784_amd import binding as B
+
+    if args.workload == "mos2_mlmc":
+        dev = torch.device("cuda", 0)
+        torch.cuda.set_device(dev)
+        # MLMC over the MoS2-shaped levels N = 4, 8, 16 (n up to 2816), K = 6 at every level; the oracle
+        # checks the two smaller levels (its N = 16 solves take about a minute each on one core)
+        ttt = time_to_tol(B, dev, "mos2_mlmc", variants=(("fp64", B.MLMC_PREC_FP64, 0, False),
+                                                          ("mixed", B.MLMC_PREC_MIXED, 0, False),
+                                                          ("fp64_tuned", B.MLMC_PREC_FP64, 0, True),
+                                                          ("mixed_tuned", B.MLMC_PREC_MIXED, 0, True)),
+                          oracle_samples=(8, 2, 0))
+        fp = ttt["fp64"]
+        print(json.dumps({
+            "metric": METRIC, "value": round(fp["eigensolves"] / fp["seconds"], 3), "unit": "eigensolves/s",
+            "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": round(1e3 * fp["seconds"], 3),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "mos2_mlmc", "lattice": "mos2_shaped", "levels": [4, 8, 16], "K": 6, "p": 0.02,
+                       "tol_rel": 1e-3, "step": "one MLMC run to TOL"},
+            "time_to_tol": ttt}), flush=True)
+        return
 
     if args.workload == "served":
         dev = torch.device("cuda", 0)

@@ -66,6 +66,7 @@ def lib():
         L.ora_tridiagonalize.argtypes = [C.c_int32, P, C.c_int64, P, P]
         L.ora_tridiag_eigvals.argtypes = [C.c_int32, P, P, P]
         L.ora_eigvalsh.argtypes = [C.c_int32, P, C.c_int64, P]
+        L.ora_eigh.argtypes = [C.c_int32, P, C.c_int64, P, P, C.c_int64]
         L.ora_smooth_step.argtypes = [C.c_int32, C.c_double]
         L.ora_smooth_step.restype = C.c_double
         L.ora_idos.argtypes = [P, C.c_int64, P, C.c_int32, P, C.c_double, P, C.c_int32, C.c_double,
@@ -242,6 +243,17 @@ def eigvalsh(A: np.ndarray) -> np.ndarray:
     w = np.zeros(n)
     _check(lib().ora_eigvalsh(n, _ptr(A), max(n, 1), _ptr(w)), "eigvalsh")
     return w
+
+
+def eigh(A: np.ndarray):
+    """(w ascending, V) with A V[:, i] = w[i] V[:, i], V unitary (column i the
+    unit eigenvector of w[i])."""
+    A = np.array(A, dtype=np.complex128, order="F")
+    n = A.shape[0]
+    w = np.zeros(n)
+    V = np.zeros((n, n), dtype=np.complex128, order="F")
+    _check(lib().ora_eigh(n, _ptr(A), max(n, 1), _ptr(w), _ptr(V), max(n, 1)), "eigh")
+    return w, V
 
 
 def smooth_step(smoother: int, x: float) -> float:

@@ -526,6 +526,158 @@ int ora_eigvalsh(int32_t n, cplx *A, int64_t ld, double *w)
     return st;
 }
 
+/* Eigenvalues and eigenvectors of a Hermitian matrix (eigenstates of H(k),  */
+/* the input of the conductivity the paper names as the next quantity of     */
+/* interest).  Textbook path (Golub & Van Loan Sections 8.3.1 and 8.3.5):    */
+/* Householder reduction A = Q T_c Q^H keeping the reflectors; the complex   */
+/* sub-diagonal alpha_j of T_c made real by D = diag(delta), delta_0 = 1,    */
+/* delta_{j+1} = delta_j alpha_j / |alpha_j|, so T_c = D T D^H with T real;  */
+/* the symmetric QR algorithm on T accumulating its rotations in Z (T = Z    */
+/* diag(w) Z^T); then V = Q D Z.  w ascending, V[:, i] (column-major, ldv)   */
+/* the unit eigenvector of w[i].  A is overwritten.                          */
+int ora_eigh(int32_t n, cplx *A, int64_t ld, double *w, cplx *V, int64_t ldv)
+{
+    if (n < 0 || ld < n || ldv < n) return ORA_ERR_ARG;
+    if (n == 0) return ORA_OK;
+    cplx *R = (cplx *)calloc((size_t)n * (size_t)n, sizeof(cplx));   /* reflector j in column j */
+    double *tau = (double *)calloc((size_t)n, sizeof(double));
+    cplx *delta = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+    cplx *p = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+    cplx *q = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+    double *a = (double *)malloc(sizeof(double) * (size_t)n);
+    double *b = (double *)calloc((size_t)n, sizeof(double));
+    double *Z = (double *)calloc((size_t)n * (size_t)n, sizeof(double));
+    int *order = (int *)malloc(sizeof(int) * (size_t)n);
+    int status = ORA_OK;
+    if (!R || !tau || !delta || !p || !q || !a || !b || !Z || !order) {
+        status = ORA_ERR_NOMEM;
+        goto done;
+    }
+    /* Householder reduction, the reflectors kept (as in ora_tridiagonalize) */
+    for (int j = 0; j + 2 < n; ++j) {
+        const int m = n - j - 1;
+        cplx *x = &A[(j + 1) + (int64_t)j * ld];
+        double nrm2 = 0.0;
+        for (int i = 0; i < m; ++i) nrm2 += creal(x[i]) * creal(x[i]) + cimag(x[i]) * cimag(x[i]);
+        const double xnorm = sqrt(nrm2);
+        if (xnorm == 0.0) continue;
+        const double ax0 = cabs(x[0]);
+        const cplx phase = ax0 > 0.0 ? x[0] / ax0 : 1.0;
+        const cplx alpha = -phase * xnorm;
+        cplx *v = &R[(int64_t)j * n];
+        for (int i = 0; i < m; ++i) v[i] = x[i];
+        v[0] -= alpha;
+        double vnorm2 = 0.0;
+        for (int i = 0; i < m; ++i) vnorm2 += creal(v[i]) * creal(v[i]) + cimag(v[i]) * cimag(v[i]);
+        tau[j] = 2.0 / vnorm2;
+        cplx *A22 = &A[(j + 1) + (int64_t)(j + 1) * ld];
+        for (int r = 0; r < m; ++r) {
+            cplx s = 0.0;
+            for (int c = 0; c < m; ++c) s += A22[r + (int64_t)c * ld] * v[c];
+            p[r] = tau[j] * s;
+        }
+        cplx vhp = 0.0;
+        for (int i = 0; i < m; ++i) vhp += conj(v[i]) * p[i];
+        const double K = 0.5 * tau[j] * creal(vhp);
+        for (int i = 0; i < m; ++i) q[i] = p[i] - K * v[i];
+        for (int c = 0; c < m; ++c)
+            for (int r = 0; r < m; ++r)
+                A22[r + (int64_t)c * ld] -= v[r] * conj(q[c]) + q[r] * conj(v[c]);
+        x[0] = alpha;
+        for (int i = 1; i < m; ++i) x[i] = 0.0;
+    }
+    /* real tridiagonal T = D^H T_c D */
+    delta[0] = 1.0;
+    for (int j = 0; j < n; ++j) a[j] = creal(A[j + (int64_t)j * ld]);
+    for (int j = 0; j + 1 < n; ++j) {
+        const cplx al = A[(j + 1) + (int64_t)j * ld];
+        const double m = cabs(al);
+        b[j] = m;
+        delta[j + 1] = m > 0.0 ? delta[j] * (al / m) : delta[j];
+    }
+    /* symmetric QR on (a, b) with the rotations accumulated in Z */
+    for (int i = 0; i < n; ++i) Z[i + (int64_t)i * n] = 1.0;
+    {
+        int hi = n - 1;
+        long iterations = 0;
+        const long max_iterations = 30L * n;
+        while (hi > 0) {
+            if (negligible(b[hi - 1], a[hi - 1], a[hi])) {
+                b[hi - 1] = 0.0;
+                --hi;
+                continue;
+            }
+            int lo = hi - 1;
+            while (lo > 0 && !negligible(b[lo - 1], a[lo - 1], a[lo])) --lo;
+            if (lo > 0) b[lo - 1] = 0.0;
+            if (++iterations > max_iterations) {
+                status = ORA_ERR_NOT_CONVERGED;
+                goto done;
+            }
+            /* the step of qr_step, each rotation also applied to Z's columns k, k+1 */
+            const double half_gap = 0.5 * (a[hi - 1] - a[hi]);
+            const double bt = b[hi - 1];
+            const double denom = half_gap + copysign(hypot(half_gap, bt), half_gap);
+            const double mu = a[hi] - bt * bt / denom;
+            double xx = a[lo] - mu, zz = b[lo];
+            for (int k = lo; k < hi; ++k) {
+                const double r = hypot(xx, zz);
+                double c = 1.0, s = 0.0;
+                if (r > 0.0) {
+                    c = xx / r;
+                    s = zz / r;
+                }
+                if (k > lo) b[k - 1] = r;
+                const double ak = a[k], ak1 = a[k + 1], bk = b[k];
+                a[k] = c * c * ak + 2.0 * c * s * bk + s * s * ak1;
+                a[k + 1] = s * s * ak - 2.0 * c * s * bk + c * c * ak1;
+                b[k] = c * s * (ak1 - ak) + (c * c - s * s) * bk;
+                if (k + 1 < hi) {
+                    const double bk1 = b[k + 1];
+                    zz = s * bk1;
+                    b[k + 1] = c * bk1;
+                    xx = b[k];
+                }
+                for (int i = 0; i < n; ++i) {
+                    const double zk = Z[i + (int64_t)k * n], zk1 = Z[i + (int64_t)(k + 1) * n];
+                    Z[i + (int64_t)k * n] = c * zk + s * zk1;
+                    Z[i + (int64_t)(k + 1) * n] = -s * zk + c * zk1;
+                }
+            }
+        }
+    }
+    /* ascending order */
+    for (int i = 0; i < n; ++i) order[i] = i;
+    for (int i = 1; i < n; ++i) {  /* insertion sort by eigenvalue (stable) */
+        const int o = order[i];
+        int k = i - 1;
+        while (k >= 0 && a[order[k]] > a[o]) {
+            order[k + 1] = order[k];
+            --k;
+        }
+        order[k + 1] = o;
+    }
+    /* V = Q D Z: column i starts as D z, then the reflectors in reverse order */
+    for (int i = 0; i < n; ++i) {
+        const int o = order[i];
+        w[i] = a[o];
+        cplx *vi = &V[(int64_t)i * ldv];
+        for (int r = 0; r < n; ++r) vi[r] = delta[r] * Z[r + (int64_t)o * n];
+        for (int j = n - 3; j >= 0; --j) {
+            if (tau[j] == 0.0) continue;
+            const int m = n - j - 1;
+            const cplx *v = &R[(int64_t)j * n];
+            cplx s = 0.0;
+            for (int r = 0; r < m; ++r) s += conj(v[r]) * vi[j + 1 + r];
+            s *= tau[j];
+            for (int r = 0; r < m; ++r) vi[j + 1 + r] -= v[r] * s;
+        }
+    }
+done:
+    free(R); free(tau); free(delta); free(p); free(q); free(a); free(b); free(Z); free(order);
+    return status;
+}
+
 /* Smoothed step of eq. (MLMC_smoothing).  smoother 0: Gaussian CDF           */
 /* erfc(x/sqrt 2)/2; smoother 1: the cubic 1/2 - 9x/8 + 5x^3/8 on [-1, 1]     */
 /* (1 below, 0 above), the polynomial of least degree meeting the endpoint   */

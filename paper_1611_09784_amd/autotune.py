@@ -67,7 +67,7 @@ class Tuner:
     """Measured launch choices per level configuration, cached on disk."""
 
     def __init__(self, cache_path: str = None, budget_bytes: int = 48 << 30, min_seconds: float = 0.25,
-                 chunks=(8, 16, 32, 64, 128, 256, 512, 1024, 2048), verbose: bool = False,
+                 chunks=(1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048), verbose: bool = False,
                  max_call_seconds: float = 1.0, chase_fractions=(0.5, 0.625, 0.75, 0.875, 1.0),
                  max_trial_seconds: float = 3.0):
         self.path = cache_path or _cache_path()
@@ -150,6 +150,8 @@ class Tuner:
                   B.mlmc_level_workspace(dlat, N, coupled, K, Kc, kind, c, prec, ne) <= self.budget]
         if not chunks:
             chunks = [1]
+        start = min(8, chunks[-1])  # small chunks only where larger ones do not fit
+        chunks = [c for c in chunks if c >= start]
         first = 1 << 40  # samples the tuner draws are never those of a run
         best = LevelTuning(chunk=chunks[0])
         trials = 0

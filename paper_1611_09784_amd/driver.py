@@ -60,7 +60,8 @@ class Estimator:
 
     def __init__(self, dlat: B.DeviceLattice, eps: np.ndarray, delta: float, p: float, kind: int, seed: int,
                  smoother: int = B.MLMC_SMOOTH_GAUSS, prec: int = B.MLMC_PREC_FP64, chunk_samples: int = 64,
-                 stream=None, dedup_max_orbitals: int = 0, tuner=None, graphs: bool = False):
+                 stream=None, dedup_max_orbitals: int = 0, tuner=None, graphs: bool = False,
+                 budget_bytes: int = 48 << 30):
         self.dlat = dlat
         self.eps = torch.as_tensor(np.asarray(eps, dtype=np.float64), device=dlat.device)
         self.delta, self.p, self.kind, self.seed = float(delta), float(p), int(kind), int(seed)
@@ -73,6 +74,7 @@ class Estimator:
         # replay a captured level call (see LevelGraph).
         self.tuner = tuner
         self.graphs = bool(graphs)
+        self.budget = int(budget_bytes)  # largest workspace of one level
         self._tuned = {}
         self._graph = {}
         # levels whose matrices have at most this many orbitals solve each
@@ -90,8 +92,14 @@ class Estimator:
         return self._tuned[key]
 
     def _chunk(self, lvl: LevelState) -> int:
+        """The tuned chunk, else the estimator's, halved until the level's
+        workspace fits the budget."""
         t = self._tuning(lvl)
-        return self.chunk if t is None else t.chunk
+        c = self.chunk if t is None else t.chunk
+        while c > 1 and B.mlmc_level_workspace(self.dlat, lvl.N, lvl.coupled, lvl.K, lvl.K_coarse, self.kind, c,
+                                               self.prec, self.eps.shape[0]) > self.budget:
+            c //= 2
+        return c
 
     def _workspace(self, lvl: LevelState):
         key = (lvl.N, lvl.coupled, lvl.K, lvl.K_coarse)
