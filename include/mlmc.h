@@ -124,8 +124,9 @@ typedef enum {
     MLMC_OP_LEVEL_ESTIMATE = 2,               /* mlmc_level_estimate and mlmc_level_outcomes: lat, N_fine,
                                                  coupled, K_fine, K_coarse, kgrid, chunk_samples, prec,
                                                  n_eps                                                   */
-    MLMC_OP_LEVEL_OUTCOMES_SINGLE_PASS = 3    /* mlmc_level_outcomes taking chunk_samples outcomes in one
+    MLMC_OP_LEVEL_OUTCOMES_SINGLE_PASS = 3,   /* mlmc_level_outcomes taking chunk_samples outcomes in one
                                                  pass (one buffer set): the fields of MLMC_OP_LEVEL_ESTIMATE */
+    MLMC_OP_BATCHED_EIGH = 4                  /* mlmc_batched_eigh: dtype, prec, ld, batch                */
 } mlmc_op;
 
 /* Arguments of a workspace query; fields an operation does not use are ignored. */
@@ -230,6 +231,8 @@ mlmc_status mlmc_build_overlaps(mlmc_lattice lat, int32_t N, const uint8_t *d_ma
  *   MLMC_OP_LEVEL_OUTCOMES_SINGLE_PASS: mlmc_level_outcomes on up to
  *     chunk_samples outcomes in a single pass with one buffer set (about a
  *     third of the matrix memory of the pipelined layout).
+ *   MLMC_OP_BATCHED_EIGH: `batch` matrices of side bound ld (7*ld*ld doubles
+ *     each: the tridiagonal eigenvectors and the inverse iteration's scratch).
  * Errors: NULL arguments, unknown op, the operation's own argument checks
  * (MLMC_ERR_UNSUPPORTED for sizes beyond the library's limits). */
 mlmc_status mlmc_workspace_bytes(const mlmc_workspace_request *req, size_t *bytes);
@@ -272,6 +275,33 @@ mlmc_status mlmc_batched_eigvalsh(mlmc_dtype dtype, mlmc_precision prec, void *d
 mlmc_status mlmc_batched_eigvalsh_noalloc(mlmc_dtype dtype, mlmc_precision prec, void *d_H, int64_t ld,
                                           const int32_t *d_n, int64_t batch, double *d_w, int64_t ldw,
                                           mlmc_stream stream);
+
+/* Eigenvalues and eigenvectors of a batch of Hermitian matrices: the
+ * eigenstates that the Kubo-Greenwood conductivity needs besides the band
+ * energies (Section 1; named as the next quantity of interest in Section 5).
+ * LDS-resident matrices only: ld <= 128 complex128 / 180 complex64.  One
+ * workgroup per matrix: Householder reduction H = Q T_c Q^H with the
+ * reflectors kept, T_c = D T D^H with a diagonal unitary D that makes the
+ * sub-diagonal real and non-negative, eigenvalues of T by the bisection of
+ * mlmc_batched_eigvalsh, eigenvectors Z of T by inverse iteration with
+ * partial pivoting (eigenvalues closer than 1e-3 ||T||_1 form a cluster
+ * whose vectors are orthogonalised against each other in every iteration),
+ * the eigenvalues refined to the Rayleigh quotients z^T T z (ascending),
+ * then V = Q D Z.
+ * d_H, d_offsets, d_n, d_w, ldw: as mlmc_batched_eigvalsh (the lower
+ * triangles are read; the matrices are left unchanged).  d_V: the
+ * eigenvectors, matrix b at element b*ldv*ldv, column-major with leading
+ * dimension ldv, column i (entries 0..n_b-1) the unit eigenvector of
+ * d_w[b][i]; entries outside the leading n_b x n_b block are untouched.
+ * Each vector is determined up to a phase (within a cluster, the cluster's
+ * columns up to a unitary mix).  Accuracy: ||H v - w v|| of a few ulps of
+ * ||H|| in the compute type (complex128 or complex64), columns orthonormal
+ * to the same order.  d_work: mlmc_workspace_bytes(MLMC_OP_BATCHED_EIGH).
+ * Errors: ld above the bound (MLMC_ERR_UNSUPPORTED), ldw or ldv < ld,
+ * NULL buffers, workspace too small. */
+mlmc_status mlmc_batched_eigh(mlmc_dtype dtype, mlmc_precision prec, void *d_H, int64_t ld, const int64_t *d_offsets,
+                              const int32_t *d_n, int64_t batch, double *d_w, int64_t ldw, void *d_V, int64_t ldv,
+                              void *d_work, size_t work_bytes, mlmc_stream stream);
 
 /* All eigenvalues of a batch of Hermitian-definite pencils (H, S) (the
  * generalised problem H c = E S c of a non-orthogonal basis, Section 3.1):

@@ -691,6 +691,42 @@ mlmc_status mlmc_batched_eigvalsh(mlmc_dtype dtype, mlmc_precision prec, void *d
     return run_large(prec, d_H, ld, d_n, batch, d_w, ldw, b, s, false, false, d_offsets);
 }
 
+static mlmc_status eigh_workspace(mlmc_dtype dtype, mlmc_precision prec, int64_t ld, int64_t batch, size_t *bytes) {
+    if (!bytes || ld < 0 || batch < 0) return fail(MLMC_ERR_INVALID_ARG, "eigh_workspace: bad argument");
+    const mlmc_status st = check_dtype_prec(dtype, prec);
+    if (st != MLMC_OK) return st;
+    if (ld > small_cap(prec))
+        return fail(MLMC_ERR_UNSUPPORTED, "batched_eigh: ld %lld exceeds the LDS-resident bound %d", (long long)ld,
+                    small_cap(prec));
+    *bytes = eigh_work_bytes(ld, batch);
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_batched_eigh(mlmc_dtype dtype, mlmc_precision prec, void *d_H, int64_t ld, const int64_t *d_offsets,
+                              const int32_t *d_n, int64_t batch, double *d_w, int64_t ldw, void *d_V, int64_t ldv,
+                              void *d_work, size_t work_bytes, mlmc_stream stream) {
+    size_t need = 0;
+    const mlmc_status st = eigh_workspace(dtype, prec, ld, batch, &need);
+    if (st != MLMC_OK) return st;
+    if (ldw < ld || ldv < ld)
+        return fail(MLMC_ERR_INVALID_ARG, "batched_eigh: ldw %lld, ldv %lld < ld %lld", (long long)ldw,
+                    (long long)ldv, (long long)ld);
+    if (batch > 0 && (!d_H || !d_n || !d_w || !d_V)) return fail(MLMC_ERR_INVALID_ARG, "batched_eigh: NULL buffer");
+    if (need > 0 && (!d_work || work_bytes < need))
+        return fail(MLMC_ERR_WORKSPACE, "batched_eigh: workspace %zu < %zu bytes", work_bytes, need);
+    if (batch == 0 || ld == 0) return MLMC_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (prec == MLMC_PREC_FP64)
+        LAUNCH("eigh_small", s, launch_eigh_small<double>(static_cast<const cpx<double> *>(d_H), ld, d_offsets, d_n,
+                                                          batch, d_w, ldw, static_cast<cpx<double> *>(d_V), ldv,
+                                                          static_cast<double *>(d_work), s));
+    else
+        LAUNCH("eigh_small", s, launch_eigh_small<float>(static_cast<const cpx<float> *>(d_H), ld, d_offsets, d_n,
+                                                         batch, d_w, ldw, static_cast<cpx<float> *>(d_V), ldv,
+                                                         static_cast<double *>(d_work), s));
+    return MLMC_OK;
+}
+
 }  // extern "C"
 
 namespace {
@@ -875,6 +911,7 @@ mlmc_status mlmc_workspace_bytes(const mlmc_workspace_request *req, size_t *byte
         case MLMC_OP_LEVEL_OUTCOMES_SINGLE_PASS:
             return level_workspace(req->lat, req->N_fine, req->coupled, req->K_fine, req->K_coarse, req->kgrid,
                                    req->chunk_samples, req->prec, req->n_eps, bytes, 1);
+        case MLMC_OP_BATCHED_EIGH: return eigh_workspace(req->dtype, req->prec, req->ld, req->batch, bytes);
         default: return fail(MLMC_ERR_INVALID_ARG, "workspace_bytes: unknown operation %d", (int)req->op);
     }
 }

@@ -89,9 +89,14 @@ __device__ __forceinline__ int packed_col(int c, int n) { return c * n - (c * (c
 // A <- A - v w^H - w v^H, w = p - (tau/2)(v^H p) v, p = tau A v.
 // O(n^2) work per column runs in T; scalar reductions run in double.
 // Requires blockDim.x even; v, pw hold >= n entries, part >= 2*cap.
+// With refl != NULL the reflectors are kept for a back-transformation:
+// refl[j] = (v_j[0], tau_j) as cpx with tau in .re of refl[cap + j] (v_j below
+// its first entry stays in L's column j, which the reduction does not touch
+// after step j), and alpha[j] = the reduced complex sub-diagonal entry
+// (alpha[n - 2] the last one, left unreflected).
 template <typename T>
 __device__ void tridiag_packed(cpx<T> *L, int n, int cap, cpx<T> *v, cpx<T> *pw, cpx<T> *part, double *d, double *e,
-                               double *red) {
+                               double *red, cpx<T> *refl = nullptr, cpx<T> *alpha_out = nullptr) {
     const int t = threadIdx.x, nt = blockDim.x, half = nt >> 1;
     const bool row_half = t < half;
     const int hl = row_half ? t : t - half;
@@ -119,6 +124,11 @@ __device__ void tridiag_packed(cpx<T> *L, int n, int cap, cpx<T> *v, cpx<T> *pw,
         if (t == 0) {
             d[j] = (double)L[packed_col(j, n)].re;
             e[j] = xnorm;
+            if (refl) {
+                refl[j] = v0;
+                refl[cap + j] = {tau, T(0)};
+                alpha_out[j] = alpha;
+            }
         }
         for (int i = t; i < m; i += nt) v[i] = (i == 0) ? v0 : x[i];
         __syncthreads();
@@ -165,6 +175,7 @@ __device__ void tridiag_packed(cpx<T> *L, int n, int cap, cpx<T> *v, cpx<T> *pw,
             const cpx<T> s = L[packed_col(n - 2, n) + 1];
             e[n - 2] = sqrt((double)s.re * (double)s.re + (double)s.im * (double)s.im);
             d[n - 1] = (double)L[packed_col(n - 1, n)].re;
+            if (alpha_out) alpha_out[n - 2] = s;
         } else if (n == 1) {
             d[0] = (double)L[0].re;
         }

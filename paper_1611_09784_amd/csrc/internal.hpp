@@ -103,6 +103,14 @@ template <typename T>
 hipError_t launch_small_from_matrix(const cpx<T> *H, int64_t ld, const int32_t *n_in, int64_t batch, double *w,
                                     int64_t ldw, hipStream_t s, const int64_t *offs = nullptr);
 
+// Eigenvalues and eigenvectors of LDS-resident matrices (ld <= the small
+// path's bound): one workgroup per matrix, the reflectors kept in LDS,
+// inverse iteration on the tridiagonal, V = Q D Z.  work: eigh_work_bytes.
+template <typename T>
+hipError_t launch_eigh_small(const cpx<T> *H, int64_t ld, const int64_t *offs, const int32_t *n_in, int64_t batch,
+                             double *w, int64_t ldw, cpx<T> *V, int64_t ldv, double *work, hipStream_t s);
+inline size_t eigh_work_bytes(int64_t ld, int64_t batch) { return sizeof(double) * 7 * (size_t)ld * ld * batch; }
+
 // Two-stage reduction to tridiagonal form.  Stage 1 (launch_band_reduce):
 // dense -> band of half-width 16, in place in H (lower triangle).  Stage 2
 // (launch_band_chase): band -> tridiagonal (d, e) by bulge chasing.  Both use

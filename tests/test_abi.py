@@ -132,3 +132,35 @@ def test_generalized_workspace_limits(B):
     assert gen_ws(B.MLMC_C128, B.MLMC_PREC_FP64, 64, 3) == B.MLMC_OK
     assert out.value > 0                    # the generalised path always needs its workspace
     assert gen_ws(B.MLMC_C64, B.MLMC_PREC_FP64, 64, 3) == B.MLMC_ERR_UNSUPPORTED
+
+
+def test_eigh_workspace_and_limits(B):
+    """The eigenstates call: LDS-resident sides only, workspace 7 ld^2
+    doubles per matrix, argument errors before any launch."""
+    out = C.c_size_t()
+    lib = B.lib()
+
+    def ws(dtype, prec, ld, batch):
+        req = B._WorkspaceRequest(B.MLMC_OP_BATCHED_EIGH, dtype, prec, ld, batch, None, 0, 0, 0, 0, 0, 0, 0)
+        return lib.mlmc_workspace_bytes(C.byref(req), C.byref(out))
+
+    assert ws(B.MLMC_C128, B.MLMC_PREC_FP64, 128, 3) == B.MLMC_OK
+    assert out.value == 3 * 7 * 128 * 128 * 8
+    assert ws(B.MLMC_C64, B.MLMC_PREC_MIXED, 180, 2) == B.MLMC_OK
+    assert out.value == 2 * 7 * 180 * 180 * 8
+    assert ws(B.MLMC_C128, B.MLMC_PREC_FP64, 129, 1) == B.MLMC_ERR_UNSUPPORTED
+    assert ws(B.MLMC_C64, B.MLMC_PREC_MIXED, 181, 1) == B.MLMC_ERR_UNSUPPORTED
+    assert ws(B.MLMC_C64, B.MLMC_PREC_FP64, 64, 1) == B.MLMC_ERR_UNSUPPORTED
+    assert B.mlmc_eigh_workspace(B.MLMC_C128, B.MLMC_PREC_FP64, 0, 5) == 0
+    # NULL buffers, short leading dimensions and short workspaces fail up front
+    assert lib.mlmc_batched_eigh(B.MLMC_C128, B.MLMC_PREC_FP64, None, 64, None, None, 2, None, 64, None, 64,
+                                 None, 0, None) == B.MLMC_ERR_INVALID_ARG
+    fake = C.c_void_p(16)  # never dereferenced: the checks fail first
+    assert lib.mlmc_batched_eigh(B.MLMC_C128, B.MLMC_PREC_FP64, fake, 64, None, fake, 2, fake, 63, fake, 64,
+                                 fake, 1 << 30, None) == B.MLMC_ERR_INVALID_ARG
+    assert lib.mlmc_batched_eigh(B.MLMC_C128, B.MLMC_PREC_FP64, fake, 64, None, fake, 2, fake, 64, fake, 32,
+                                 fake, 1 << 30, None) == B.MLMC_ERR_INVALID_ARG
+    assert lib.mlmc_batched_eigh(B.MLMC_C128, B.MLMC_PREC_FP64, fake, 64, None, fake, 2, fake, 64, fake, 64,
+                                 fake, 100, None) == B.MLMC_ERR_WORKSPACE
+    assert lib.mlmc_batched_eigh(B.MLMC_C128, B.MLMC_PREC_FP64, fake, 64, None, fake, 0, fake, 64, fake, 64,
+                                 None, 0, None) == B.MLMC_OK  # empty batch: nothing to do
