@@ -165,6 +165,9 @@ def parse():
     ap.add_argument("--mlmc", dest="mlmc", action="store_true", default=True,
                     help="also time the MLMC estimator to TOL (graphene levels N = 4..32), FP64 and mixed")
     ap.add_argument("--no-mlmc", dest="mlmc", action="store_false")
+    ap.add_argument("--stage1", dest="stage1", action="store_true", default=True,
+                    help="kernel-by-kernel roofline of the dense-to-band stage at n ~ 2000 (graphene N = 32)")
+    ap.add_argument("--no-stage1", dest="stage1", action="store_false")
     ap.add_argument("--serve-requests", type=int, default=160, help="requests per served run (--workload served)")
     ap.add_argument("--serve-slots", type=int, default=4, help="batches in flight at once (--workload served)")
     ap.add_argument("--serve-budget-gb", type=float, default=200.0, help="HBM budget of the server (GB)")
@@ -441,6 +444,100 @@ def measure(B, wl, lat, eps, prec, args, dev):
             "launch": {"chunk": chunk, "tuned": tuning}}
 
 
+def stage1_flops_bytes(n: int, ld: int, esize: int) -> dict:
+    """Algorithmic flops (8 per complex multiply-add) and HBM bytes of each
+    dense-to-band kernel over the panels of one matrix of side n (panel p
+    reduces columns p .. p + 15, leaving m = n - p - 16 trailing rows):
+      panel QR   ~2.5 * 16^2 m multiply-adds (reflectors and T); reads the
+                 m x 16 panel, writes V and V T;
+      Hermitian  X = A22 (V T): 16 m^2 multiply-adds (+ 256 m for V^H X T);
+      product    reads A22's lower triangle once, writes X;
+      W factor   256 m multiply-adds; reads X and V, writes W;
+      update     A22 -= V W^H + W V^H on the lower triangle: 16 m (m + 1)
+                 multiply-adds; reads and writes that triangle."""
+    out = {k: [0.0, 0.0] for k in ("s1_panel", "s1_hemm", "s1_wfactor", "s1_update")}
+    b = 16
+    for p in range(0, ld - b - 1, b):
+        m = n - p - b
+        if m <= 0:
+            continue
+        tri = m * (m + 1) / 2
+        out["s1_panel"][0] += 8 * 2.5 * b * b * m
+        out["s1_panel"][1] += 3 * b * m * esize
+        out["s1_hemm"][0] += 8 * (b * m * m + b * b * m)
+        out["s1_hemm"][1] += (tri + 2 * b * m) * esize
+        out["s1_wfactor"][0] += 8 * b * b * m
+        out["s1_wfactor"][1] += 3 * b * m * esize
+        out["s1_update"][0] += 8 * 2 * b * tri
+        out["s1_update"][1] += (2 * tri + 2 * b * m) * esize
+    return out
+
+
+def stage1_roofline(B, dev, prec, N=32, samples=32):
+    """Kernel-by-kernel roofline of the dense-to-band stage at n ~ 2000
+    (graphene N = 32, one k-point, p = 0.02): one level call of `samples`
+    samples in a single chunk, so that the stage runs alone on the chip
+    before its chase; every stage-1 kernel launch event-timed.  Per kernel:
+    algorithmic TFLOP/s against the matrix-core peak of the compute type
+    (FP64 78.6, FP32 157.3 TFLOP/s) and algorithmic GB/s against 8 TB/s."""
+    import torch
+    from mlmc_inputs import graphene
+    lat = graphene()
+    dlat = B.DeviceLattice(lat, 0)
+    K, kind, p, seed = 1, B.MLMC_KGRID_GAMMA, 0.02, 303
+    eps = torch.as_tensor(np.linspace(-9.0, 9.0, 401), device=dev)
+    need = B.mlmc_level_workspace(dlat, N, False, K, K, kind, samples, prec, 401)
+    work = torch.empty((need,), dtype=torch.uint8, device=dev)
+    stats = torch.zeros((4, 401), dtype=torch.float64, device=dev)
+    ld = lat.n_orb * N * N
+    panels = -(-(ld - 17) // 16)
+    with B.Context(0) as ctx:
+        def call(first):
+            B.mlmc_level_estimate(dlat, N, False, p, K, K, kind, seed, first, samples, eps, 0.05,
+                                  B.MLMC_SMOOTH_GAUSS, prec, stats=stats, work=work, ctx=ctx)
+        ctx.timer(8 * panels + 64, detail=True)
+        call(1 << 41)  # warm-up: first launches, first touch of the workspace
+        torch.cuda.synchronize()
+        ctx.timer(8 * panels + 64, detail=True)  # forget the warm-up's records
+        call(0)
+        torch.cuda.synchronize()
+        rec = {}
+        for name in ("band_reduce", "s1_panel", "s1_hemm", "s1_wfactor", "s1_update", "chase", "bisect"):
+            ms, cnt, dropped = ctx.timer_read(name)
+            rec[name] = (ms, cnt, dropped)
+    masks = B.mlmc_sample_vacancies(dlat, N, p, seed, dlat.tag(N), 0, samples).cpu().numpy()
+    orb_per_group = np.bincount(lat.orb_group, minlength=lat.n_groups)
+    vac = (masks.reshape(samples, -1, lat.n_groups) * orb_per_group).sum(axis=(1, 2))
+    sizes = (ld - vac).astype(np.int64)
+    dlat.close()
+    esize = 16 if prec == B.MLMC_PREC_FP64 else 8
+    peak = FP64_PEAK_TFLOPS if prec == B.MLMC_PREC_FP64 else FP32_PEAK_TFLOPS
+    tot = {k: [0.0, 0.0] for k in ("s1_panel", "s1_hemm", "s1_wfactor", "s1_update")}
+    for n in sizes:
+        for k, (f, b) in stage1_flops_bytes(int(n), ld, esize).items():
+            tot[k][0] += f
+            tot[k][1] += b
+    kernels = {}
+    for k, (f, b) in tot.items():
+        ms, cnt, _ = rec[k]
+        if not cnt:
+            continue
+        tf = f / (ms * 1e-3) / 1e12
+        gbs = b / (ms * 1e-3) / 1e9
+        kernels[k] = {"ms": round(ms, 3), "launches": cnt, "gflop": round(f / 1e9, 2), "gb": round(b / 1e9, 3),
+                      "tflops": round(tf, 3), "frac_mfma_peak": round(tf / peak, 4),
+                      "gbs": round(gbs, 1), "frac_hbm_peak": round(gbs / (HBM_PEAK_GBS), 4),
+                      "bound": "mfma" if f / (peak * 1e12) > b / (HBM_PEAK_GBS * 1e9) else "hbm"}
+    flops = float(np.sum(16.0 / 3.0 * sizes.astype(np.float64) ** 3))
+    s1_ms = rec["band_reduce"][0]
+    return {"workload": f"graphene N = {N}, K = 1 (Gamma), p = {p}, {samples} matrices in one chunk",
+            "precision": "fp64" if prec == B.MLMC_PREC_FP64 else "mixed", "n_mean": round(float(sizes.mean()), 1),
+            "ld": ld, "peak_tflops": peak, "peak_hbm_gbs": HBM_PEAK_GBS,
+            "stage1_ms": round(s1_ms, 3), "stage1_tflops_16_3_n3": round(flops / (s1_ms * 1e-3) / 1e12, 3),
+            "chase_ms": round(rec["chase"][0], 3), "bisect_ms": round(rec["bisect"][0], 3),
+            "timer_dropped": rec["band_reduce"][2], "kernels": kernels}
+
+
 def served(B, args, dev):
     """The served stream: Poisson arrivals (seed 5050) of single-sample MLMC
     requests, lattice uniform over {graphene, MoS2-shaped}, N in {4, 8, 16, 32}
@@ -576,6 +673,9 @@ def main():
     second = measure(B, wl, lat, eps, other, args, dev) if args.second else None
 
     ttt = time_to_tol(B, dev) if args.mlmc else None
+    s1 = None
+    if args.stage1:
+        s1 = [stage1_roofline(B, dev, q) for q in (B.MLMC_PREC_FP64, B.MLMC_PREC_MIXED)]
 
     cpu = None
     if args.cpu_baseline:
@@ -643,6 +743,7 @@ def main():
         if other == B.MLMC_PREC_MIXED:
             out["speedup_mixed_vs_fp64_eigensolves"] = round(second["value"] / main_run["value"], 3)
     out["time_to_tol"] = ttt
+    out["roofline_stage1"] = s1
     out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 

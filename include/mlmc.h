@@ -379,14 +379,18 @@ mlmc_status mlmc_context_destroy(mlmc_context ctx);
  * and each kernel launch of those calls then records one pair on the stream
  * it is launched on, until all pairs are used (later launches are counted as
  * dropped).  Calling again with the same capacity forgets the records and
- * keeps the events; 0 destroys them. */
-mlmc_status mlmc_context_timer(mlmc_context ctx, int64_t capacity);
+ * keeps the events; 0 destroys them.  detail != 0: the kernels of the
+ * dense-to-band stage are also timed one by one (a pair each, inside the
+ * "band_reduce" pair of their launch). */
+mlmc_status mlmc_context_timer(mlmc_context ctx, int64_t capacity, int32_t detail);
 /* Total event-measured duration (ms) and count of the recorded launches of
  * kernel `name` since the timer was last (re)set: "sample_vacancies",
  * "partition", "kgrid", "assemble", "small_fused", "band_reduce" (dense to
  * band, several kernels per launch), "chase" (band to tridiagonal, one
  * kernel), "overlap_reduce" (Cholesky and reduction of a generalised
- * problem, several kernels), "bisect", "idos" or "level_stats"; `dropped`
+ * problem, several kernels), "bisect", "idos" or "level_stats"; with detail
+ * also "s1_panel" (panel QR), "s1_hemm" (Hermitian product), "s1_wfactor"
+ * and "s1_update" (rank-2k update), one launch per panel each; `dropped`
  * (may be NULL) receives the launches not timed.  Blocks until the recorded
  * launches have completed. */
 mlmc_status mlmc_context_timer_read(mlmc_context ctx, const char *name, double *total_ms, int64_t *launches,

@@ -104,7 +104,7 @@ SIGNATURES = {
                                       P, P, P, P, SZ, P, P]),
     "mlmc_context_create": (C.c_int, [P]),
     "mlmc_context_destroy": (C.c_int, [P]),
-    "mlmc_context_timer": (C.c_int, [P, I64]),
+    "mlmc_context_timer": (C.c_int, [P, I64, C.c_int32]),
     "mlmc_context_configure": (C.c_int, [P, P]),
     "mlmc_context_stream": (C.c_int, [P, I32, P]),
     "mlmc_context_timer_read": (C.c_int, [P, C.c_char_p, P, P, P]),
@@ -279,10 +279,11 @@ class Context:
         cfg = _LaunchConfig(int(chase_workgroups), int(bisect_workgroups), int(update_tile_rows))
         _check(lib().mlmc_context_configure(self.handle, C.byref(cfg)), "mlmc_context_configure")
 
-    def timer(self, capacity: int):
+    def timer(self, capacity: int, detail: bool = False):
         """Create `capacity` start/stop event pairs (0: destroy them); the
-        level calls of this context then time their kernel launches."""
-        _check(lib().mlmc_context_timer(self.handle, int(capacity)), "mlmc_context_timer")
+        level calls of this context then time their kernel launches (with
+        `detail` also the dense-to-band stage's kernels one by one)."""
+        _check(lib().mlmc_context_timer(self.handle, int(capacity), int(bool(detail))), "mlmc_context_timer")
 
     def timer_read(self, name: str):
         """(total milliseconds, launches, dropped) of kernel `name` since the timer was (re)set."""

@@ -62,6 +62,7 @@ struct LaunchTimer {
     std::vector<const char *> names;  // name of record r (pair 2r, 2r + 1)
     size_t used = 0;
     int64_t dropped = 0;  // launches not timed because every pair was in use
+    bool detail = false;  // also time the kernels inside multi-kernel launchers
 
     void release() {
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
@@ -81,17 +82,30 @@ hipError_t timed(const char *name, hipStream_t s, F &&launch) {
         ++tm->dropped;
         return launch();
     }
+    // The record is taken before the launch, so that launches timed inside
+    // it (the kernels of a multi-kernel launcher) take the records after it;
+    // it gets its name only once both of its events are recorded.
     const size_t r = tm->used;
+    tm->names[r] = nullptr;
+    tm->used = r + 1;
     hipError_t err = hipEventRecord(tm->ev[2 * r], s);
     if (err != hipSuccess) return err;
     err = launch();
     const hipError_t e2 = hipEventRecord(tm->ev[2 * r + 1], s);
-    tm->names[r] = name;
-    tm->used = r + 1;
+    if (err == hipSuccess && e2 == hipSuccess) tm->names[r] = name;
     return err != hipSuccess ? err : e2;
 }
 
 #define LAUNCH(name, stream, expr) HIP_TRY(timed(name, stream, [&]() { return (expr); }), name)
+
+}  // namespace
+
+hipError_t mlmc::timed_sub(const char *name, hipStream_t s, hipError_t (*launch)(void *), void *arg) {
+    if (!t_timer || !t_timer->detail) return launch(arg);
+    return timed(name, s, [&]() { return launch(arg); });
+}
+
+namespace {
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -1252,11 +1266,12 @@ mlmc_status mlmc_context_configure(mlmc_context ctx, const mlmc_launch_config *c
     return MLMC_OK;
 }
 
-mlmc_status mlmc_context_timer(mlmc_context ctx, int64_t capacity) {
+mlmc_status mlmc_context_timer(mlmc_context ctx, int64_t capacity, int32_t detail) {
     if (!ctx || capacity < 0 || capacity > (int64_t)1 << 20)
         return fail(MLMC_ERR_INVALID_ARG, "context_timer: bad argument");
     std::lock_guard<std::mutex> lk(ctx->mu);
     LaunchTimer &t = ctx->timer;
+    t.detail = detail != 0;
     if ((int64_t)t.names.size() == capacity) {  // same capacity: keep the events, forget the records
         t.used = 0;
         t.dropped = 0;
@@ -1284,7 +1299,7 @@ mlmc_status mlmc_context_timer_read(mlmc_context ctx, const char *name, double *
     double total = 0.0;
     int64_t count = 0;
     for (size_t r = 0; r < t.used; ++r) {
-        if (std::strcmp(t.names[r], name) != 0) continue;
+        if (!t.names[r] || std::strcmp(t.names[r], name) != 0) continue;
         HIP_TRY(hipEventSynchronize(t.ev[2 * r + 1]), "timer_read");
         float ms = 0.0f;
         HIP_TRY(hipEventElapsedTime(&ms, t.ev[2 * r], t.ev[2 * r + 1]), "timer_read");

@@ -18,6 +18,8 @@
 // Complex products on the matrix cores take three real products each.  Per
 // panel the trailing matrix is read about three times, instead of once per
 // column as in a one-stage reduction.
+#include <algorithm>
+
 #include "twostage_common.hpp"
 
 namespace mlmc {
@@ -296,7 +298,7 @@ __global__ __launch_bounds__(kQrThreads) void qr_panel_kernel(cpx<T> *__restrict
 template <typename T, int NT>
 struct QrShared {
     double part[NT / 64][32];
-    double dotf[2 * kB];
+    double dotw[NT / 64][2 * kB];  // each wavefront's copy of the summed products
     double nred[NT / 64];
     cpx<T> x0s;
     cpx<T> Ts[kB][kB];
@@ -338,17 +340,20 @@ __device__ __forceinline__ void qr_reflect(QrShared<T, NT> &sh, cpx<T> (&P)[kB],
     const T red = wave_reduce_scatter32(x);
     if ((lane & 1) == 0) sh.part[wid][scatter_elem(lane)] = (double)red;
     __syncthreads();
-    if (t < 2 * kB) {
+    // Every wavefront sums the parts into its own copy and reads it back: a
+    // wavefront's LDS operations complete in order, so no second barrier.
+    if (lane < 2 * kB) {
         double sum = 0.0;
 #pragma unroll
-        for (int q = 0; q < NW; ++q) sum += sh.part[q][t];
-        sh.dotf[t] = sum;
+        for (int q = 0; q < NW; ++q) sum += sh.part[q][lane];
+        sh.dotw[wid][lane] = sum;
     }
-    __syncthreads();
+    __builtin_amdgcn_wave_barrier();
+    const double *dotf = sh.dotw[wid];
     // apply the reflector to the columns right of I
 #pragma unroll
     for (int c = I + 1; c < kB; ++c) {
-        const cpx<T> dc = {(T)sh.dotf[2 * c], (T)sh.dotf[2 * c + 1]};
+        const cpx<T> dc = {(T)dotf[2 * c], (T)dotf[2 * c + 1]};
         P[c] = c_sub(P[c], c_scale(tau, c_mul(v, dc)));
     }
     P[I] = csel(r == r0, v0, P[I]);
@@ -356,7 +361,7 @@ __device__ __forceinline__ void qr_reflect(QrShared<T, NT> &sh, cpx<T> (&P)[kB],
     if (t < I) {
         cpx<T> sum = zero;
         for (int q = t; q < I; ++q)
-            sum = c_add(sum, c_mul(sh.Ts[t][q], cpx<T>{(T)sh.dotf[2 * q], (T)sh.dotf[2 * q + 1]}));
+            sum = c_add(sum, c_mul(sh.Ts[t][q], cpx<T>{(T)dotf[2 * q], (T)dotf[2 * q + 1]}));
         sh.Ts[t][I] = c_scale(-tau, sum);
     }
     if (t == I) {
@@ -416,6 +421,300 @@ __global__ __launch_bounds__(NT) void qr_panel_reg_kernel(cpx<T> *__restrict__ H
 #pragma unroll
         for (int l = 0; l < kB; ++l) w.W[l * ldi + r] = vt[l];
     }
+    for (int idx = t; idx < kB * kB; idx += NT) w.Tm[idx] = sh.Ts[idx / kB][idx % kB];
+}
+
+// Panel QR for panels taller than a workgroup: thread t holds rows
+// s + t + NT k (k < R) of W of the panel's columns at a time (R W complex
+// values per thread).  The W-column sub-panels are factored left to right.
+// Each is first brought up to date by the reflectors of the sub-panels before
+// it in compact WY form, A_g <- (I - V T V^H)^H A_g = A_g - V T^H (V^H A_g),
+// and after it the triangular factor grows by a block column,
+// T = [[T0, -T0 (V0^H V1) T1], [0, T1]] (V1 the new reflectors, T1 their own
+// factor).  A thread needs V only on its own rows, which it wrote itself, so
+// V is read back without synchronisation.  Per reflector two workgroup
+// reductions as in the one-row-per-thread kernel; per later sub-panel two
+// more (V^H A_g and V0^H V1).  The panel is read and written once.
+// Sub-panel width for R rows per thread: 256 bytes of panel per thread
+// (64 registers).
+template <typename T>
+constexpr int kBlkW(int R) {
+    return (int)(256 / (2 * sizeof(T))) / R;
+}
+
+// Eight rows per thread for complex64 (four, never launched, for complex128).
+template <typename T>
+constexpr int kBlkR8 = sizeof(T) == 4 ? 8 : 4;
+
+template <typename T, int NT>
+struct QrBlkShared {
+    double part[2][NT / 64][128];  // per-wavefront reduce-scattered sums, two buffers in turn
+    double dotw[NT / 64][128];     // each wavefront's copy of the summed products
+    double nred[NT / 64];
+    cpx<T> x0s;
+    cpx<T> Ts[kB][kB];
+    cpx<T> Zs[kB][kB];  // T^H (V^H A_g), then (V0^H V1) T1
+    cpx<T> alphas[kB];
+};
+
+// One chunk of 32 values of a workgroup sum: this wavefront's reduce-scatter
+// into slots 32 chunk .. 32 chunk + 31 of `part`.
+template <typename T, int NT>
+__device__ __forceinline__ void blk_red_chunk(double (&part)[NT / 64][128], int chunk, const T (&x)[32]) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const T r = wave_reduce_scatter32(x);
+    if ((lane & 1) == 0) part[wid][32 * chunk + scatter_elem(lane)] = (double)r;
+}
+// After the chunks: one barrier, then every wavefront sums the NV values
+// into its own copy and reads it back (a wavefront's LDS operations complete
+// in order).  Consecutive sums alternate between the two buffers of `part`,
+// so that a sum's writes never meet a slower wavefront's reads of the sum
+// before the previous one (a barrier separates them).
+template <int NT, int NV>
+__device__ __forceinline__ const double *blk_red_finish(double (&part)[NT / 64][128],
+                                                        double (&dotw)[NT / 64][128]) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+#pragma unroll
+    for (int e = lane; e < NV; e += 64) {
+        double sum = 0.0;
+#pragma unroll
+        for (int q = 0; q < NT / 64; ++q) sum += part[q][e];
+        dotw[wid][e] = sum;
+    }
+    __builtin_amdgcn_wave_barrier();
+    return dotw[wid];
+}
+
+template <typename T, int NT, int R>
+__device__ __forceinline__ void blk_load_v(const TwoView<T> &w, int ldi, int s, int n, int q, cpx<T> (&vq)[R]) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int r = s + t + NT * k;
+        const cpx<T> a = w.V[r < n ? q * ldi + r : 0];
+        vq[k] = csel(r < n, a, cpx<T>{T(0), T(0)});
+    }
+}
+
+// X[q][c] = sum over the thread's rows of conj(V[q][r]) B[r][c] for the
+// reflectors q < Q of earlier sub-panels (16 products per chunk), summed over
+// the workgroup: X at 2 (q W + c) (re, im) of the returned copy.
+template <typename T, int NT, int R, int W, int Q>
+__device__ __forceinline__ const double *blk_vh_times(QrBlkShared<T, NT> &sh, const TwoView<T> &w, int ldi, int s,
+                                                      int n, const cpx<T> (&Bm)[R][W], int &pb) {
+    constexpr int QB = 16 / W, NCH = (Q + QB - 1) / QB;
+    static_assert(NCH * 32 <= 128, "at most four chunks");
+#pragma unroll 1
+    for (int ch = 0; ch < NCH; ++ch) {
+        T x[32];
+#pragma unroll
+        for (int j = 0; j < 32; ++j) x[j] = T(0);
+#pragma unroll
+        for (int qq = 0; qq < QB; ++qq) {
+            if (ch * QB + qq >= Q) break;  // static: the last chunk's padding stays zero
+            cpx<T> vq[R];
+            blk_load_v<T, NT, R>(w, ldi, s, n, ch * QB + qq, vq);
+#pragma unroll
+            for (int c = 0; c < W; ++c) {
+                cpx<T> acc = {T(0), T(0)};
+#pragma unroll
+                for (int k = 0; k < R; ++k) acc = c_add(acc, c_cmul(vq[k], Bm[k][c]));
+                x[2 * (qq * W + c)] = acc.re;
+                x[2 * (qq * W + c) + 1] = acc.im;
+            }
+        }
+        blk_red_chunk<T, NT>(sh.part[pb], ch, x);
+    }
+    const double *out = blk_red_finish<NT, 2 * Q * W>(sh.part[pb], sh.dotw);
+    pb ^= 1;
+    return out;
+}
+
+// Reflector I = c0 + C of the panel (column C of the sub-panel in P).
+template <typename T, int NT, int R, int W, int C>
+__device__ __forceinline__ void qr_blk_reflect(QrBlkShared<T, NT> &sh, cpx<T> (&P)[R][W], int c0, int s, int n,
+                                               int nr, int &pb) {
+    constexpr int NW = NT / 64;
+    const int I = c0 + C;
+    if (I >= nr) return;  // uniform over the workgroup
+    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+    const int r0 = s + I;
+    const cpx<T> zero = {T(0), T(0)};
+    // norm of column I from the pivot row down; the pivot is row s + I, which
+    // thread I holds first
+    double ws = 0.0;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int r = s + t + NT * k;
+        ws += (r < n && r >= r0) ? (double)c_abs2(P[k][C]) : 0.0;
+    }
+    ws = col_sum(row_sum(ws));
+    if (lane == 0) sh.nred[wid] = ws;
+    if (t == I) sh.x0s = P[0][C];
+    __syncthreads();
+    double nrm2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) nrm2 += sh.nred[q];
+    T tau;
+    cpx<T> v0, alpha;
+    make_reflector<T>(nrm2, sh.x0s, tau, v0, alpha);
+    cpx<T> v[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int r = s + t + NT * k;
+        v[k] = csel(r == r0, v0, csel(r < n && r > r0, P[k][C], zero));
+    }
+    // v^H P[:, c] for the sub-panel's columns c > C, V[:, c]^H v for c < C
+    T x[32];
+#pragma unroll
+    for (int j = 0; j < 32; ++j) x[j] = T(0);
+#pragma unroll
+    for (int c = 0; c < W; ++c) {
+        cpx<T> acc = zero;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            if (c > C) acc = c_add(acc, c_cmul(v[k], P[k][c]));
+            else if (c < C) acc = c_add(acc, c_cmul(P[k][c], v[k]));
+        }
+        x[2 * c] = acc.re;
+        x[2 * c + 1] = acc.im;
+    }
+    blk_red_chunk<T, NT>(sh.part[pb], 0, x);
+    const double *d = blk_red_finish<NT, 2 * W>(sh.part[pb], sh.dotw);
+    pb ^= 1;
+#pragma unroll
+    for (int c = C + 1; c < W; ++c) {
+        const cpx<T> dc = {(T)d[2 * c], (T)d[2 * c + 1]};
+#pragma unroll
+        for (int k = 0; k < R; ++k) P[k][c] = c_sub(P[k][c], c_scale(tau, c_mul(v[k], dc)));
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) P[k][C] = csel(s + t + NT * k == r0, v0, P[k][C]);
+    // T[c0:I, I] = -tau T[c0:I, c0:I] (V^H v_I)[c0:I], T[I, I] = tau
+    if (t >= c0 && t < I) {
+        cpx<T> sum = zero;
+        for (int q = t; q < I; ++q)
+            sum = c_add(sum, c_mul(sh.Ts[t][q], cpx<T>{(T)d[2 * (q - c0)], (T)d[2 * (q - c0) + 1]}));
+        sh.Ts[t][I] = c_scale(-tau, sum);
+    }
+    if (t == I) {
+        sh.Ts[I][I] = {tau, T(0)};
+        sh.alphas[I] = alpha;
+    }
+}
+template <typename T, int NT, int R, int W, int... Cs>
+__device__ __forceinline__ void qr_blk_reflect_all(QrBlkShared<T, NT> &sh, cpx<T> (&P)[R][W], int c0, int s, int n,
+                                                   int nr, int &pb, std::integer_sequence<int, Cs...>) {
+    (qr_blk_reflect<T, NT, R, W, Cs>(sh, P, c0, s, n, nr, pb), ...);
+}
+
+// Sub-panel G (panel columns G W .. G W + W - 1).
+template <typename T, int NT, int R, int W, int G>
+__device__ __forceinline__ void qr_blk_subpanel(QrBlkShared<T, NT> &sh, cpx<T> *A, const TwoView<T> &w, int ldi,
+                                                int p, int s, int n, int nr, int &pb) {
+    constexpr int c0 = G * W;
+    const int t = threadIdx.x;
+    const cpx<T> zero = {T(0), T(0)};
+    cpx<T> P[R][W];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int r = s + t + NT * k;
+#pragma unroll
+        for (int c = 0; c < W; ++c) {
+            const cpx<T> a = A[r < n ? r + (p + c0 + c) * ldi : 0];
+            P[k][c] = csel(r < n, a, zero);
+        }
+    }
+    if constexpr (G > 0) {
+        // A_g <- A_g - V Z, Z = T^H (V^H A_g), over the reflectors q < c0
+        const double *Y = blk_vh_times<T, NT, R, W, c0>(sh, w, ldi, s, n, P, pb);
+        if (t < c0 * W) {
+            const int q = t / W, c = t % W;
+            cpx<T> z = zero;
+            for (int q2 = 0; q2 <= q; ++q2)
+                z = c_add(z, c_cmul(sh.Ts[q2][q], cpx<T>{(T)Y[2 * (q2 * W + c)], (T)Y[2 * (q2 * W + c) + 1]}));
+            sh.Zs[q][c] = z;
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int q = 0; q < c0; ++q) {
+            cpx<T> vq[R];
+            blk_load_v<T, NT, R>(w, ldi, s, n, q, vq);
+#pragma unroll
+            for (int c = 0; c < W; ++c) {
+                const cpx<T> zc = sh.Zs[q][c];
+#pragma unroll
+                for (int k = 0; k < R; ++k) P[k][c] = c_sub(P[k][c], c_mul(vq[k], zc));
+            }
+        }
+    }
+    qr_blk_reflect_all<T, NT, R, W>(sh, P, c0, s, n, nr, pb, std::make_integer_sequence<int, W>{});
+    // V columns (zero above each pivot) and the band part of the panel
+    // columns: rows s .. s + I of column p + I (R above the pivot, alpha at
+    // it); the zeros below lie outside the band and are never read again.
+#pragma unroll
+    for (int c = 0; c < W; ++c) {
+        const int I = c0 + c, r0c = s + I;
+        const bool refl = I < nr;
+        const cpx<T> al = sh.alphas[I];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int r = s + t + NT * k;
+            const cpx<T> vk = csel(refl && r >= r0c, P[k][c], zero);
+            if (r < n) w.V[I * ldi + r] = vk;
+            if (k == 0 && t <= I) A[r + (p + I) * ldi] = csel(!refl || r < r0c, P[k][c], csel(r == r0c, al, zero));
+            P[k][c] = vk;
+        }
+    }
+    if constexpr (G > 0) {
+        // T[0:c0, c0:c0+W] = -T[0:c0, 0:c0] (V0^H V1) T[c0:c0+W, c0:c0+W]
+        const double *X = blk_vh_times<T, NT, R, W, c0>(sh, w, ldi, s, n, P, pb);
+        if (t < c0 * W) {
+            const int q = t / W, c = t % W;
+            cpx<T> m1 = zero;
+            for (int c2 = 0; c2 <= c; ++c2)
+                m1 = c_add(m1, c_mul(cpx<T>{(T)X[2 * (q * W + c2)], (T)X[2 * (q * W + c2) + 1]}, sh.Ts[c0 + c2][c0 + c]));
+            sh.Zs[q][c] = m1;
+        }
+        __syncthreads();
+        if (t < c0 * W) {
+            const int q = t / W, c = t % W;
+            cpx<T> tq = zero;
+            for (int q2 = q; q2 < c0; ++q2) tq = c_add(tq, c_mul(sh.Ts[q][q2], sh.Zs[q2][c]));
+            sh.Ts[q][c0 + c] = {-tq.re, -tq.im};
+        }
+    }
+}
+template <typename T, int NT, int R, int W, int... Gs>
+__device__ __forceinline__ void qr_blk_all(QrBlkShared<T, NT> &sh, cpx<T> *A, const TwoView<T> &w, int ldi, int p,
+                                           int s, int n, int nr, int &pb, std::integer_sequence<int, Gs...>) {
+    (qr_blk_subpanel<T, NT, R, W, Gs>(sh, A, w, ldi, p, s, n, nr, pb), ...);
+}
+
+template <typename T, int NT, int R, int W>
+__global__ __launch_bounds__(NT) void qr_panel_blk_kernel(cpx<T> *__restrict__ Hall, int64_t ld,
+                                                          const int64_t *__restrict__ offs,
+                                                          const int32_t *__restrict__ n_in,
+                                                          cpx<T> *__restrict__ wall, int64_t stride, int p) {
+    static_assert(kB % W == 0 && W * R * 2 * sizeof(T) == 256, "sub-panel of 256 bytes per thread");
+    __shared__ QrBlkShared<T, NT> sh;
+    const int64_t u = blockIdx.x;
+    const int n = n_in[u];
+    const int s = p + kB, m = n - s;
+    if (n < 0 || n > ld || m < 2 || m > NT * R) return;
+    const int t = threadIdx.x;
+    const int ldi = (int)ld;
+    const TwoView<T> w(wall, stride, ld, u);
+    cpx<T> *A = Hall + mat_offset(offs, u, ld);
+    const cpx<T> zero = {T(0), T(0)};
+    for (int idx = t; idx < kB * kB; idx += NT) sh.Ts[idx / kB][idx % kB] = zero;
+    const int nr = min(m - 1, kB);
+    int pb = 0;
+    // (the first reduction's barrier orders the zeroing of T before its writes)
+    qr_blk_all<T, NT, R, W>(sh, A, w, ldi, p, s, n, nr, pb, std::make_integer_sequence<int, kB / W>{});
+    __syncthreads();
+    store_vt<T>(w, ld, s, n, t, NT, sh.Ts);  // V T for the Hermitian product (own rows of V)
     for (int idx = t; idx < kB * kB; idx += NT) w.Tm[idx] = sh.Ts[idx / kB][idx % kB];
 }
 
@@ -562,14 +861,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void he
 
 // ---------------------------------------------------------------------------
 // Stage 1: W = X T - 1/2 V Y, Y = T^H Z, Z = sum over the Hermitian product's
-// row blocks of V_rows^H (X T)_rows.  One workgroup per matrix.
+// row blocks of V_rows^H (X T)_rows.  `rblocks` workgroups per matrix, each
+// forming Y and taking every rblocks-th block of 256 rows (several when the
+// batch is too small to fill the chip).
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kWThreads) void wfactor_kernel(const int32_t *__restrict__ n_in, int64_t ld,
-                                                            cpx<T> *__restrict__ wall, int64_t stride, int p) {
+                                                            cpx<T> *__restrict__ wall, int64_t stride, int p,
+                                                            int rblocks) {
     __shared__ cpx<T> Ts[kB][kB], Zs[kB][kB], Y[kB][kB];
     static_assert(kWThreads == kB * kB, "one thread per entry of the 16 x 16 factors");
-    const int64_t u = blockIdx.x;
+    const int64_t u = blockIdx.x / rblocks;
+    const int rb = (int)(blockIdx.x % rblocks);
     const int n = n_in[u];
     const int s = p + kB, m = n - s;
     if (n < 0 || n > ld || m < 2) return;
@@ -587,7 +890,7 @@ __global__ __launch_bounds__(kWThreads) void wfactor_kernel(const int32_t *__res
     Y[k][l] = y;
     __syncthreads();
 #pragma unroll 1
-    for (int r = s + t; r < n; r += kWThreads) {
+    for (int r = s + kWThreads * rb + t; r < n; r += kWThreads * rblocks) {
         cpx<T> v[kB];
 #pragma unroll
         for (int q = 0; q < kB; ++q) v[q] = w.V[(int64_t)q * ld + r];
@@ -817,35 +1120,66 @@ hipError_t launch_band_reduce(cpx<T> *H, int64_t ld, const int32_t *n_in, int64_
     const unsigned B = (unsigned)batch;
     for (int p = 0; p + kB + 1 < ld; p += kB) {
         const int64_t mmax = ld - p - kB;
-        if (mmax <= 64)
-            hipLaunchKernelGGL((qr_panel_reg_kernel<T, 64>), dim3(B), dim3(64), 0, s, H, ld, offs, n_in, work, stride, p);
-        else if (mmax <= 128)
-            hipLaunchKernelGGL((qr_panel_reg_kernel<T, 128>), dim3(B), dim3(128), 0, s, H, ld, offs, n_in, work, stride, p);
-        else if (mmax <= 256)
-            hipLaunchKernelGGL((qr_panel_reg_kernel<T, 256>), dim3(B), dim3(256), 0, s, H, ld, offs, n_in, work, stride, p);
-        else if (mmax <= 512)
-            hipLaunchKernelGGL((qr_panel_reg_kernel<T, 512>), dim3(B), dim3(512), 0, s, H, ld, offs, n_in, work, stride, p);
-        else
-            hipLaunchKernelGGL(qr_panel_kernel<T>, dim3(B), dim3(kQrThreads), 0, s, H, ld, offs, n_in, work, stride, p);
+        hipError_t err = timed_call("s1_panel", s, [&]() {
+            if (mmax <= 64)
+                hipLaunchKernelGGL((qr_panel_reg_kernel<T, 64>), dim3(B), dim3(64), 0, s, H, ld, offs, n_in, work,
+                                   stride, p);
+            else if (mmax <= 128)
+                hipLaunchKernelGGL((qr_panel_reg_kernel<T, 128>), dim3(B), dim3(128), 0, s, H, ld, offs, n_in, work,
+                                   stride, p);
+            else if (mmax <= 256)
+                hipLaunchKernelGGL((qr_panel_reg_kernel<T, 256>), dim3(B), dim3(256), 0, s, H, ld, offs, n_in, work,
+                                   stride, p);
+            else if (mmax <= 512)
+                hipLaunchKernelGGL((qr_panel_reg_kernel<T, 512>), dim3(B), dim3(512), 0, s, H, ld, offs, n_in, work,
+                                   stride, p);
+            else if (mmax <= 1024)
+                hipLaunchKernelGGL((qr_panel_blk_kernel<T, 512, 2, kBlkW<T>(2)>), dim3(B), dim3(512), 0, s, H, ld,
+                                   offs, n_in, work, stride, p);
+            else if (mmax <= 2048)
+                hipLaunchKernelGGL((qr_panel_blk_kernel<T, 512, 4, kBlkW<T>(4)>), dim3(B), dim3(512), 0, s, H, ld,
+                                   offs, n_in, work, stride, p);
+            else if (sizeof(T) == 4 && mmax <= 4096)  // (eight complex128 rows per thread would spill)
+                hipLaunchKernelGGL((qr_panel_blk_kernel<T, 512, kBlkR8<T>, kBlkW<T>(kBlkR8<T>)>), dim3(B), dim3(512),
+                                   0, s, H, ld, offs, n_in, work, stride, p);
+            else
+                hipLaunchKernelGGL(qr_panel_kernel<T>, dim3(B), dim3(kQrThreads), 0, s, H, ld, offs, n_in, work,
+                                   stride, p);
+            return hipGetLastError();
+        });
+        if (err != hipSuccess) return err;
         const int64_t hrows = (mmax + kHemmRows - 1) / kHemmRows;
-        hipLaunchKernelGGL(hemm_kernel<T>, dim3(xcd_grid(batch, hrows)), dim3(64), 0, s, H, ld, offs, n_in,
-                           work + 2 * (int64_t)kB * ld, work, work + (int64_t)kB * ld,
-                           work + hemm_partials_offset(ld), stride, p, batch, hrows);
-        hipLaunchKernelGGL(wfactor_kernel<T>, dim3(B), dim3(kWThreads), 0, s, n_in, ld, work, stride, p);
+        err = timed_call("s1_hemm", s, [&]() {
+            hipLaunchKernelGGL(hemm_kernel<T>, dim3(xcd_grid(batch, hrows)), dim3(64), 0, s, H, ld, offs, n_in,
+                               work + 2 * (int64_t)kB * ld, work, work + (int64_t)kB * ld,
+                               work + hemm_partials_offset(ld), stride, p, batch, hrows);
+            return hipGetLastError();
+        });
+        if (err != hipSuccess) return err;
+        err = timed_call("s1_wfactor", s, [&]() {
+            const int64_t rmax = (mmax + kWThreads - 1) / kWThreads;
+            const int rblocks = (int)std::max<int64_t>(1, std::min<int64_t>(rmax, (512 + batch - 1) / batch));
+            hipLaunchKernelGGL(wfactor_kernel<T>, dim3(B * rblocks), dim3(kWThreads), 0, s, n_in, ld, work, stride,
+                               p, rblocks);
+            return hipGetLastError();
+        });
+        if (err != hipSuccess) return err;
         // The rank-2k update in 32 x 64 tiles (small enough to share a CU with
         // a chase workgroup).  Lower tiles of row blocks 0 .. nb32 - 1: pairs of
         // row blocks (2a, 2a + 1) hold 2 (a + 1) tiles.
-        if (upd_rows == 32) {
-            const int64_t nb32 = (mmax + kUpdBlk / 2 - 1) / (kUpdBlk / 2), ha = (nb32 - 1) / 2;
-            const int64_t ntile = (nb32 % 2 == 0) ? (ha + 1) * (ha + 2) : (ha + 1) * (ha + 1);
-            hipLaunchKernelGGL(band_update32_kernel<T>, dim3(xcd_grid(batch, ntile)), dim3(256), 0, s, H, ld, offs,
-                               n_in, work, stride, p, batch, ntile, 2);
-        } else {
-            const int64_t nblk = (mmax + kUpdBlk - 1) / kUpdBlk, ntile = nblk * (nblk + 1) / 2;
-            hipLaunchKernelGGL(band_update_kernel<T>, dim3(xcd_grid(batch, ntile)), dim3(256), 0, s, H, ld, offs,
-                               n_in, work, stride, p, batch, ntile, 2);
-        }
-        const hipError_t err = hipGetLastError();
+        err = timed_call("s1_update", s, [&]() {
+            if (upd_rows == 32) {
+                const int64_t nb32 = (mmax + kUpdBlk / 2 - 1) / (kUpdBlk / 2), ha = (nb32 - 1) / 2;
+                const int64_t ntile = (nb32 % 2 == 0) ? (ha + 1) * (ha + 2) : (ha + 1) * (ha + 1);
+                hipLaunchKernelGGL(band_update32_kernel<T>, dim3(xcd_grid(batch, ntile)), dim3(256), 0, s, H, ld,
+                                   offs, n_in, work, stride, p, batch, ntile, 2);
+            } else {
+                const int64_t nblk = (mmax + kUpdBlk - 1) / kUpdBlk, ntile = nblk * (nblk + 1) / 2;
+                hipLaunchKernelGGL(band_update_kernel<T>, dim3(xcd_grid(batch, ntile)), dim3(256), 0, s, H, ld,
+                                   offs, n_in, work, stride, p, batch, ntile, 2);
+            }
+            return hipGetLastError();
+        });
         if (err != hipSuccess) return err;
     }
     return hipSuccess;

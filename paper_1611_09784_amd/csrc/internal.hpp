@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <type_traits>
 
 #include "mlmc.h"
 
@@ -110,6 +111,17 @@ template <typename T>
 hipError_t launch_eigh_small(const cpx<T> *H, int64_t ld, const int64_t *offs, const int32_t *n_in, int64_t batch,
                              double *w, int64_t ldw, cpx<T> *V, int64_t ldv, double *work, hipStream_t s);
 inline size_t eigh_work_bytes(int64_t ld, int64_t batch) { return sizeof(double) * 7 * (size_t)ld * ld * batch; }
+
+// Per-kernel timing inside launchers that issue several kernels: when the
+// calling thread enqueues work for a context whose launch timer is on, an
+// event pair brackets `launch` on stream s under `name`; otherwise `launch`
+// just runs.  `launch` enqueues one kernel and returns its launch status.
+hipError_t timed_sub(const char *name, hipStream_t s, hipError_t (*launch)(void *), void *arg);
+template <typename F>
+inline hipError_t timed_call(const char *name, hipStream_t s, F &&f) {
+    using Fn = typename std::remove_reference<F>::type;
+    return timed_sub(name, s, [](void *p) { return (*static_cast<Fn *>(p))(); }, static_cast<void *>(&f));
+}
 
 // Two-stage reduction to tridiagonal form.  Stage 1 (launch_band_reduce):
 // dense -> band of half-width 16, in place in H (lower triangle).  Stage 2

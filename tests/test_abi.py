@@ -90,7 +90,7 @@ def test_validation_without_device(B):
                                    None, None) == B.MLMC_ERR_INVALID_ARG
     assert lib.mlmc_context_create(None) == B.MLMC_ERR_INVALID_ARG
     assert lib.mlmc_context_destroy(None) == B.MLMC_OK
-    assert lib.mlmc_context_timer(None, 4) == B.MLMC_ERR_INVALID_ARG
+    assert lib.mlmc_context_timer(None, 4, 0) == B.MLMC_ERR_INVALID_ARG
     assert lib.mlmc_lattice_create(None, None) == B.MLMC_ERR_INVALID_ARG
     assert b"NULL" in lib.mlmc_last_error()
     assert lib.mlmc_lattice_destroy(None) == B.MLMC_OK
