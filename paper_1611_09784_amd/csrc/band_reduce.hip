@@ -25,7 +25,6 @@
 namespace mlmc {
 
 constexpr int kQrThreads = 256;
-constexpr int kHemmRows = 64;
 constexpr int kHemmDepth = 2;  // Hermitian product: register sets of its load pipeline
 constexpr int kWThreads = 256;
 constexpr int kUpdBlk = 64;
@@ -721,25 +720,25 @@ __global__ __launch_bounds__(NT) void qr_panel_blk_kernel(cpx<T> *__restrict__ H
 // Raw operand loads of one hemm step (columns c0 .. c0 + 3) and their fix-up.
 // Offsets are 32-bit (ld * ld fits) and selects are per real component, so
 // that the loads are straight-line code.
-template <typename T>
+template <typename T, int NTL>
 __device__ __forceinline__ void hemm_fetch(const cpx<T> *A, const cpx<T> *V, int ld, int n, int rb, int c0,
-                                           cpx<T> (&a)[4], cpx<T> &vb) {
+                                           cpx<T> (&a)[NTL], cpx<T> &vb) {
     const int lane = threadIdx.x, ii = lane & 15, c = c0 + (lane >> 4);
     vb = V[c < n ? ii * ld + c : 0];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < NTL; ++t) {
         const int r = rb + 16 * t + ii;
         const int hi = r > c ? r : c, lo = r > c ? c : r;
         a[t] = A[(r < n && c < n) ? hi + lo * ld : 0];
     }
 }
-template <typename T>
-__device__ __forceinline__ void hemm_fix(int n, int rb, int c0, cpx<T> (&a)[4], cpx<T> &vb) {
+template <typename T, int NTL>
+__device__ __forceinline__ void hemm_fix(int n, int rb, int c0, cpx<T> (&a)[NTL], cpx<T> &vb) {
     const int lane = threadIdx.x, ii = lane & 15, c = c0 + (lane >> 4);
     vb.re = c < n ? vb.re : T(0);
     vb.im = c < n ? vb.im : T(0);
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < NTL; ++t) {
         const int r = rb + 16 * t + ii;
         const bool ok = r < n && c < n;
         const T re = a[t].re, im = a[t].im;
@@ -748,31 +747,31 @@ __device__ __forceinline__ void hemm_fix(int n, int rb, int c0, cpx<T> (&a)[4], 
     }
 }
 
-// After the Hermitian product of a wavefront's 64-row block (rows rb ..):
-// its rows of X T, and Z_b = V_rows^H (X T)_rows for the block b, on the
-// matrix cores (the accumulators are already laid out as the B operand of a
-// 4-row step), into Zall[b][16][16] for the W factor.
-template <typename T, typename Acc>
-__device__ __forceinline__ void hemm_finish(const Acc (&acc)[4], const cpx<T> *Vo, cpx<T> *X, cpx<T> *Z,
+// After the Hermitian product of a wavefront's row block (rows rb ..,
+// NTL tiles of 16): its rows of X T, and Z_b = V_rows^H (X T)_rows for each
+// 16-row tile b, on the matrix cores (the accumulators are already laid out
+// as the B operand of a 4-row step), into Zall[b][16][16] for the W factor.
+template <typename T, int NTL, typename Acc>
+__device__ __forceinline__ void hemm_finish(const Acc (&acc)[NTL], const cpx<T> *Vo, cpx<T> *X, cpx<T> *Z,
                                             int ldi, int n, int rb) {
     using v4 = typename Mfma<T>::v4;
     const int lane = (int)threadIdx.x & 63, ii = lane & 15;
-    cpx<T> vz[4][4];
+    cpx<T> vz[NTL][4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < NTL; ++t)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int r = rb + 16 * t + Mfma<T>::row(lane, v);
             vz[t][v] = Vo[r < n ? ii * ldi + r : 0];
         }
-    v4 dre[4], dim[4];
+    v4 dre[NTL], dim[NTL];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < NTL; ++t) {
         dre[t] = acc[t].re();
         dim[t] = acc[t].im();
     }
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < NTL; ++t)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int r = rb + 16 * t + Mfma<T>::row(lane, v);
@@ -781,9 +780,11 @@ __device__ __forceinline__ void hemm_finish(const Acc (&acc)[4], const cpx<T> *V
     // Z_b[i][l] = sum_r conj(V[r][i]) (X T)[r][l]: step (t, v) takes the rows
     // rb + 16 t + row(lane, v), lane supplying A[ii][kk] = conj(V[r][ii]) and
     // B[kk][ii] = (X T)[r][ii] (its own accumulator entry).
-    v4 zre = v4{T(0), T(0), T(0), T(0)}, zim = v4{T(0), T(0), T(0), T(0)};
+    // One partial per 16-row tile, so that the sums do not depend on how
+    // many tiles a wavefront takes.
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < NTL; ++t) {
+        v4 zre = v4{T(0), T(0), T(0), T(0)}, zim = v4{T(0), T(0), T(0), T(0)};
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int r = rb + 16 * t + Mfma<T>::row(lane, v);
@@ -792,12 +793,15 @@ __device__ __forceinline__ void hemm_finish(const Acc (&acc)[4], const cpx<T> *V
             cmma<T>(a, cpx<T>{dre[t][v], dim[t][v]}, zre, zim);
         }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) Z[Mfma<T>::row(lane, v) * kB + ii] = {zre[v], zim[v]};
+        for (int v = 0; v < 4; ++v) Z[t * kB * kB + Mfma<T>::row(lane, v) * kB + ii] = {zre[v], zim[v]};
+    }
 }
 
-// X T = A22 (V T) on the matrix cores: one wavefront per 64 output rows
-// (four 16-row tiles) x 16 columns; each step consumes 4 columns of A22.
-template <typename T>
+// X T = A22 (V T) on the matrix cores: one wavefront per 16 NTL output rows
+// (NTL 16-row tiles: four, or fewer when the batch is too small to give
+// every SIMD two wavefronts) x 16 columns; each step consumes 4 columns of
+// A22.
+template <typename T, int NTL>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void hemm_kernel(
     const cpx<T> *__restrict__ Hall, int64_t ld, const int64_t *__restrict__ offs, const int32_t *__restrict__ n_in,
     const cpx<T> *__restrict__ VTall,
@@ -809,13 +813,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void he
     const int n = n_in[u];
     const int s = p + kB, m = n - s;
     if (n < 0 || n > ld || m < 2) return;
-    const int rb = s + (int)tile * kHemmRows;
+    constexpr int kRows = 16 * NTL;
+    const int rb = s + (int)tile * kRows;
     if (rb >= n) return;
     const cpx<T> *A = Hall + mat_offset(offs, u, ld);
     const cpx<T> *V = VTall + u * stride;
-    CAcc3<T> acc[4];
+    CAcc3<T> acc[NTL];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t].zero();
+    for (int t = 0; t < NTL; ++t) acc[t].zero();
     // Raw loads (every lane loads from a valid address: the stored lower
     // element of its position, element 0 when outside the matrix) are issued
     // kHemmDepth - 1 steps ahead into a ring of register sets; the fix-up
@@ -825,21 +830,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void he
     // loop-carried loaded values into loop-carried addresses (which would
     // move the loads down to their use).
     //
-    // Column order: the wavefront of row block I starts at column offset
+    // Column order: the wavefront of 64-row block I starts at column offset
     // -64 I (mod m, in steps of 4 columns) and wraps around, so that the
     // wavefronts of a matrix do not all stream the same columns at the same
     // time (about 9 % faster than all starting at column s).  Steps past
     // the last one (the step count is padded to a multiple of kHemmDepth)
     // read column n, which is masked to zero.
     constexpr int D = kHemmDepth;
-    cpx<T> a[D][4], b[D];
+    cpx<T> a[D][NTL], b[D];
     int cs[D];
     const int ldi = (int)ld;
     const int m4 = (m + 3) & ~3, nst = m4 / 4;
-    int of = (m4 - (kHemmRows * (int)tile) % m4) % m4, fetched = 0;
+    // (the offset follows the 64-row block, so that every row sums its
+    // columns in the same order whatever NTL is)
+    int of = (m4 - ((kRows * (int)tile) & ~63) % m4) % m4, fetched = 0;
     auto fetch_next = [&](int slot) {
         cs[slot] = fetched < nst ? s + of : n;
-        hemm_fetch(A, V, ldi, n, rb, cs[slot], a[slot], b[slot]);
+        hemm_fetch<T, NTL>(A, V, ldi, n, rb, cs[slot], a[slot], b[slot]);
         of = of + 4 >= m4 ? 0 : of + 4;
         ++fetched;
     };
@@ -850,18 +857,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void he
         for (int i = 0; i < D; ++i) {
             fetch_next((i + D - 1) % D);
             asm volatile("" ::: "memory");
-            hemm_fix(n, rb, cs[i], a[i], b[i]);
+            hemm_fix<T, NTL>(n, rb, cs[i], a[i], b[i]);
 #pragma unroll
-            for (int t = 0; t < 4; ++t) acc[t].mma(a[i][t], a[i][t].re + a[i][t].im, b[i], b[i].re + b[i].im);
+            for (int t = 0; t < NTL; ++t) acc[t].mma(a[i][t], a[i][t].re + a[i][t].im, b[i], b[i].re + b[i].im);
         }
     }
-    hemm_finish<T>(acc, Vall + u * stride, Xall + u * stride, Zall + u * stride + (int64_t)tile * kB * kB, ldi, n,
-                   rb);
+    hemm_finish<T, NTL>(acc, Vall + u * stride, Xall + u * stride, Zall + u * stride + (int64_t)tile * NTL * kB * kB,
+                        ldi, n, rb);
 }
 
 // ---------------------------------------------------------------------------
 // Stage 1: W = X T - 1/2 V Y, Y = T^H Z, Z = sum over the Hermitian product's
-// row blocks of V_rows^H (X T)_rows.  `rblocks` workgroups per matrix, each
+// 16-row tiles of V_rows^H (X T)_rows.  `rblocks` workgroups per matrix, each
 // forming Y and taking every rblocks-th block of 256 rows (several when the
 // batch is too small to fill the chip).
 // ---------------------------------------------------------------------------
@@ -879,7 +886,7 @@ __global__ __launch_bounds__(kWThreads) void wfactor_kernel(const int32_t *__res
     const int t = threadIdx.x, k = t / kB, l = t % kB;
     const TwoView<T> w(wall, stride, ld, u);
     const cpx<T> *Zp = hemm_partials(w, ld);
-    const int blocks = (m + kHemmRows - 1) / kHemmRows;
+    const int blocks = (m + 15) / 16;  // the Hermitian product's 16-row tiles
     Ts[k][l] = w.Tm[t];
     cpx<T> z = {T(0), T(0)};
     for (int b = 0; b < blocks; ++b) z = c_add(z, Zp[(int64_t)b * kB * kB + t]);
@@ -1148,11 +1155,24 @@ hipError_t launch_band_reduce(cpx<T> *H, int64_t ld, const int32_t *n_in, int64_
             return hipGetLastError();
         });
         if (err != hipSuccess) return err;
-        const int64_t hrows = (mmax + kHemmRows - 1) / kHemmRows;
+        // Row tiles per wavefront: four, unless the batch gives fewer than
+        // four wavefronts per SIMD that way (a small batch of large matrices).
+        const int64_t waves4 = (int64_t)kXcds * ((batch + kXcds - 1) / kXcds) * ((mmax + 63) / 64);
+        const int ntl = waves4 >= 4096 ? 4 : (2 * waves4 >= 4096 ? 2 : 1);
+        const int hemm_rows = 16 * ntl;
+        const int64_t hrows = (mmax + hemm_rows - 1) / hemm_rows;
         err = timed_call("s1_hemm", s, [&]() {
-            hipLaunchKernelGGL(hemm_kernel<T>, dim3(xcd_grid(batch, hrows)), dim3(64), 0, s, H, ld, offs, n_in,
-                               work + 2 * (int64_t)kB * ld, work, work + (int64_t)kB * ld,
-                               work + hemm_partials_offset(ld), stride, p, batch, hrows);
+            const cpx<T> *vt = work + 2 * (int64_t)kB * ld;
+            cpx<T> *xo = work + (int64_t)kB * ld, *zo = work + hemm_partials_offset(ld);
+            if (ntl == 4)
+                hipLaunchKernelGGL((hemm_kernel<T, 4>), dim3(xcd_grid(batch, hrows)), dim3(64), 0, s, H, ld, offs,
+                                   n_in, vt, work, xo, zo, stride, p, batch, hrows);
+            else if (ntl == 2)
+                hipLaunchKernelGGL((hemm_kernel<T, 2>), dim3(xcd_grid(batch, hrows)), dim3(64), 0, s, H, ld, offs,
+                                   n_in, vt, work, xo, zo, stride, p, batch, hrows);
+            else
+                hipLaunchKernelGGL((hemm_kernel<T, 1>), dim3(xcd_grid(batch, hrows)), dim3(64), 0, s, H, ld, offs,
+                                   n_in, vt, work, xo, zo, stride, p, batch, hrows);
             return hipGetLastError();
         });
         if (err != hipSuccess) return err;
@@ -1164,9 +1184,6 @@ hipError_t launch_band_reduce(cpx<T> *H, int64_t ld, const int32_t *n_in, int64_
             return hipGetLastError();
         });
         if (err != hipSuccess) return err;
-        // The rank-2k update in 32 x 64 tiles (small enough to share a CU with
-        // a chase workgroup).  Lower tiles of row blocks 0 .. nb32 - 1: pairs of
-        // row blocks (2a, 2a + 1) hold 2 (a + 1) tiles.
         err = timed_call("s1_update", s, [&]() {
             if (upd_rows == 32) {
                 const int64_t nb32 = (mmax + kUpdBlk / 2 - 1) / (kUpdBlk / 2), ha = (nb32 - 1) / 2;

@@ -15,14 +15,15 @@ constexpr int kBandLd = 2 * kB + 1;    // stored sub-diagonals per column (incl.
 
 // Per-matrix workspace (complex elements): V [kB][ld], X [kB][ld], W [kB][ld],
 // T [kB][kB], band [ld + 1][kBandLd], then the Hermitian product's
-// per-row-block partial products [ceil(ld / 64)][kB][kB].  The band's last
+// per-row-block partial products [ceil(ld / 16)][kB][kB] (row blocks of 16,
+// 32 or 64 rows).  The band's last
 // column is a discard slot: lanes with nothing to store write there, so that
 // every store of a block is issued unconditionally.  Stage 1 never touches
 // the band and the chase touches nothing else.
 template <typename T>
 size_t tridiag_twostage_work_elems(int64_t ld) {
     return (size_t)(3 * kB) * (size_t)ld + (size_t)kB * kB + (size_t)kBandLd * (size_t)(ld + 1) +
-           (size_t)((ld + 63) / 64) * kB * kB;
+           (size_t)((ld + 15) / 16) * kB * kB;
 }
 // Offset of the partial products within a matrix's workspace.
 inline int64_t hemm_partials_offset(int64_t ld) { return 3 * kB * ld + kB * kB + kBandLd * (ld + 1); }
