@@ -13,17 +13,20 @@ workspace already resident.  The default 8 steps x 250 samples cover exactly
 the 2000 samples of the workload.  Consecutive steps alternate between two
 caller streams (``--streams 1``: one), so that a step's first chunk is reduced
 while the previous step's last chunk is chased and bisected; every step's work
-is inside the timed region.
+is inside the timed region.  The steps are timed in ``--repeats`` windows
+(default 5) of exactly ``--steps`` steps each, over the same samples, with
+nothing recorded inside them; ``value`` is the median window's rate.
 
 Prints one JSON line.  ``value`` is eigensolves per second of the whole job
 on the FP64 path; ``mixed`` holds the same measurement of the mixed path
 (complex64 reduction and chase, FP64 bisection, IDoS and sums), run in the
-same process after it.  Kernel durations come from HIP event pairs that the
-level calls' pipeline context creates before the timed region and records
-around each launch inside it (``mlmc_context_timer``).
+same process after it.  Kernel durations come from a separate instrumented
+pass over the same steps, after the timed windows: HIP event pairs that the
+level calls' pipeline context creates before the pass and records around
+each launch inside it (``mlmc_context_timer``).
 ``roofline`` reports the single kernel with the largest share, the
 band-to-tridiagonal chase, timed with HIP events on the stream it runs on
-during the timed region, against the vector ALU peak: algorithmic flops per
+during the instrumented pass, against the vector ALU peak: algorithmic flops per
 launch (``chase_flops``) over the average launch duration, with its
 algorithmic HBM bytes (``chase_bytes``) alongside.  The chase runs on 3/4 of
 the CUs beside the next chunk's dense-to-band stage (``cus``,
@@ -38,7 +41,9 @@ error per level against the FP64 oracle on the same coupled samples.
 samples of the same workload on the host cores (``nproc`` and the CPU model
 recorded), with two context lines: the oracle on one core and one sample,
 and LAPACK's Hermitian eigenvalues (scipy, threaded BLAS) on the 64 matrices
-of sample 0.
+of sample 0.  ``roofline_stage1`` times the dense-to-band stage kernel by
+kernel at n ~ 2000 (graphene N = 32, one chunk) in both precisions;
+``eigenstates`` the eigenvalue-and-eigenvector call at graphene N = 8.
 """
 
 from __future__ import annotations
@@ -147,6 +152,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="timed windows of --steps steps each; value = the median window's rate")
     ap.add_argument("--batch", type=int, default=250, help="samples per step")
     ap.add_argument("--chunk", type=int, default=32, help="samples per internal pass (workspace size) without --tune")
     ap.add_argument("--tune", dest="tune", action="store_true", default=True,
@@ -168,6 +175,9 @@ def parse():
     ap.add_argument("--stage1", dest="stage1", action="store_true", default=True,
                     help="kernel-by-kernel roofline of the dense-to-band stage at n ~ 2000 (graphene N = 32)")
     ap.add_argument("--no-stage1", dest="stage1", action="store_false")
+    ap.add_argument("--eigh", dest="eigh", action="store_true", default=True,
+                    help="eigenstates per second of mlmc_batched_eigh (graphene N = 8)")
+    ap.add_argument("--no-eigh", dest="eigh", action="store_false")
     ap.add_argument("--serve-requests", type=int, default=160, help="requests per served run (--workload served)")
     ap.add_argument("--serve-slots", type=int, default=4, help="batches in flight at once (--workload served)")
     ap.add_argument("--serve-budget-gb", type=float, default=200.0, help="HBM budget of the server (GB)")
@@ -240,7 +250,8 @@ def time_to_tol(B, dev, wl_name="graphene_mlmc", variants=None, oracle_samples=N
         out[name] = {"seconds": round(r.seconds, 3), "M": [st.M for st in r.levels], "error": r.error,
                      "eigensolves": int(sum(m * k for m, k in zip([st.M for st in r.levels], nks))),
                      "tol_abs": r.tol_abs, "rounds": len(r.rounds),
-                     "seconds_per_level": [round(st.seconds, 3) for st in r.levels]}
+                     "seconds_per_level": [round(st.seconds, 3) for st in r.levels],
+                     "cost_per_sample_s_by_round": [[float(f"{w:.3g}") for w in rd["W"]] for rd in r.rounds]}
         if dedup:
             out[name]["distinct_outcomes_solved"] = est.unique_solved
         print(f"[bench] time-to-TOL {name}: {r.seconds:.2f} s, M = {[st.M for st in r.levels]}", file=sys.stderr,
@@ -370,16 +381,30 @@ def measure(B, wl, lat, eps, prec, args, dev):
         step((args.steps + w) * args.batch)
     torch.cuda.synchronize()
     stats.zero_()
-    # event pairs for every launch of the timed calls, created before them
+    # Timed windows of exactly args.steps steps each, with no event records
+    # inside them; the value is the median over args.repeats windows (the
+    # same samples each time).
+    windows = []
+    for rep in range(args.repeats):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            step(i * args.batch)
+        torch.cuda.synchronize()
+        windows.append(time.perf_counter() - t0)
+        print(f"[bench] {pname} window {rep + 1}/{args.repeats}: {windows[-1]:.3f} s", file=sys.stderr, flush=True)
+    elapsed = float(np.median(windows))
+    # A separate instrumented pass over the same steps: an event pair around
+    # every launch (pairs created before the pass), for the per-kernel times
+    # and the roofline.
     chunks = -(-args.batch // chunk)
     ctx.timer(args.steps * chunks * 16 + 64)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         step(i * args.batch)
-        print(f"[bench] {pname} step {i + 1}/{args.steps} queued", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    instrumented = time.perf_counter() - t0
     kernels = {}
     dropped = 0
     for name in KERNEL_NAMES:
@@ -438,6 +463,7 @@ def measure(B, wl, lat, eps, prec, args, dev):
                     "flops_per_launch": flops / kernels["small_fused"]["launches"]}
     dlat.close()
     return {"value": round(value, 3), "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+            "windows_s": [round(w, 4) for w in windows], "instrumented_pass_s": round(instrumented, 4),
             "samples_per_s": round(args.steps * args.batch / elapsed, 3), "kernels_ms": kernels,
             "timer_dropped": dropped, "dominant_kernel": roofline["kernel"] if roofline else dom,
             "roofline": roofline, "reduction_tflops_16_3_n3": round(flops / elapsed / 1e12, 3),
@@ -536,6 +562,47 @@ def stage1_roofline(B, dev, prec, N=32, samples=32):
             "stage1_ms": round(s1_ms, 3), "stage1_tflops_16_3_n3": round(flops / (s1_ms * 1e-3) / 1e12, 3),
             "chase_ms": round(rec["chase"][0], 3), "bisect_ms": round(rec["bisect"][0], 3),
             "timer_dropped": rec["band_reduce"][2], "kernels": kernels}
+
+
+def eigh_throughput(B, dev, prec, N=8, K=4, samples=256, repeats=5):
+    """Eigenstates (eigenvalues and eigenvectors) of the LDS-resident H(k):
+    graphene N = 8 (n <= 128), p = 0.05, K x K Monkhorst-Pack k-points,
+    `samples` samples in one mlmc_batched_eigh call, median of `repeats`
+    event-timed calls.  Algorithmic flops per matrix: 16/3 n^3 for the
+    reduction and 8 n^3 for V = Q D Z (n reflectors applied to n vectors),
+    against the vector peak of the compute type."""
+    import torch
+    from mlmc_inputs import graphene
+    lat = graphene()
+    dlat = B.DeviceLattice(lat, 0)
+    mask = B.mlmc_sample_vacancies(dlat, N, 0.05, 808, dlat.tag(N), 0, samples)
+    kred, _ = B.mlmc_kgrid(B.MLMC_KGRID_MP, K)
+    dtype = B.MLMC_C128 if prec == B.MLMC_PREC_FP64 else B.MLMC_C64
+    H, n = B.mlmc_build_hamiltonians(dlat, N, mask, kred, dtype)
+    dlat.close()
+    batch, ld = H.shape[0], H.shape[1]
+    w = torch.zeros((batch, ld), dtype=torch.float64, device=dev)
+    V = torch.zeros((batch, ld, ld), dtype=H.dtype, device=dev)
+    work = torch.empty((B.mlmc_eigh_workspace(dtype, prec, ld, batch),), dtype=torch.uint8, device=dev)
+    B.mlmc_batched_eigh(H, n, prec=prec, w=w, V=V, work=work)  # warm-up
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * repeats)]
+    for r in range(repeats):
+        ev[2 * r].record()
+        B.mlmc_batched_eigh(H, n, prec=prec, w=w, V=V, work=work)
+        ev[2 * r + 1].record()
+    torch.cuda.synchronize()
+    ms = float(np.median([ev[2 * r].elapsed_time(ev[2 * r + 1]) for r in range(repeats)]))
+    sizes = n.cpu().numpy().astype(np.float64)
+    flops = float(np.sum(16.0 / 3.0 * sizes ** 3 + 8.0 * sizes ** 3))
+    peak = FP64_PEAK_TFLOPS if prec == B.MLMC_PREC_FP64 else FP32_PEAK_TFLOPS
+    tf = flops / (ms * 1e-3) / 1e12
+    return {"workload": f"graphene N = {N}, p = 0.05, {K}x{K} Monkhorst-Pack, {samples} samples",
+            "precision": "fp64" if prec == B.MLMC_PREC_FP64 else "mixed", "matrices": batch,
+            "n_mean": round(float(sizes.mean()), 1), "ms_per_call": round(ms, 3),
+            "eigenstates_per_s": round(batch / (ms * 1e-3), 1),
+            "roofline": {"bound": "alu", "kernel": "eigh_small_kernel", "achieved": round(tf, 3), "peak": peak,
+                         "unit": "TFLOP/s", "frac": round(tf / peak, 4),
+                         "flops_per_launch": round(flops)}}
 
 
 def served(B, args, dev):
@@ -676,6 +743,9 @@ def main():
     s1 = None
     if args.stage1:
         s1 = [stage1_roofline(B, dev, q) for q in (B.MLMC_PREC_FP64, B.MLMC_PREC_MIXED)]
+    eigh = None
+    if args.eigh:
+        eigh = [eigh_throughput(B, dev, q) for q in (B.MLMC_PREC_FP64, B.MLMC_PREC_MIXED)]
 
     cpu = None
     if args.cpu_baseline:
@@ -722,6 +792,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": main_run["ms_per_step"],
+        "windows_s": main_run["windows_s"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -744,6 +815,7 @@ def main():
             out["speedup_mixed_vs_fp64_eigensolves"] = round(second["value"] / main_run["value"], 3)
     out["time_to_tol"] = ttt
     out["roofline_stage1"] = s1
+    out["eigenstates"] = eigh
     out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 

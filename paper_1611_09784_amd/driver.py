@@ -81,6 +81,9 @@ class Estimator:
         # distinct outcome once (0: off)
         self.dedup_max_orbitals = int(dedup_max_orbitals)
         self.unique_solved = 0
+        # per level: the distinct outcomes solved so far (key -> row of the
+        # cached per-outcome IDoS), kept across rounds
+        self._outcomes = {}
 
     def _tuning(self, lvl: LevelState):
         key = (lvl.N, lvl.coupled, lvl.K, lvl.K_coarse)
@@ -156,6 +159,7 @@ class Estimator:
             self.ctx = None
         self._work.clear()
         self._graph.clear()
+        self._outcomes.clear()
 
     # -- explicit outcomes (steps a3-a7 through the C ABI) -------------------
     def outcome_idos(self, N: int, masks: torch.Tensor, K: int, budget_bytes: int = 1 << 30) -> torch.Tensor:
@@ -182,7 +186,9 @@ class Estimator:
     def _add_deduplicated(self, lvl: LevelState, count: int, stats: torch.Tensor):
         """Samples lvl.M .. lvl.M + count - 1 with each distinct outcome solved
         once (Section 4.4: identical outcomes are identified beforehand and not
-        recomputed).  Uncoupled levels identify outcomes up to a translation of
+        recomputed), also across calls: the per-outcome IDoS of every outcome
+        solved on this level is kept, so a later round solves only outcomes not
+        seen before.  Uncoupled levels identify outcomes up to a translation of
         the supercell (which leaves every H(k) spectrum unchanged); coupled
         levels identify equal outcomes only, since the quarters depend on the
         position of the vacancies."""
@@ -190,19 +196,37 @@ class Estimator:
         masks = B.mlmc_sample_vacancies(self.dlat, N, self.p, self.seed, self.dlat.tag(N), lvl.M, count,
                                         stream=self.stream)
         keys = outcome_keys(masks.cpu().numpy(), self.dlat.lat.group_removable, translations=not lvl.coupled)
-        _, first, inverse = np.unique(keys, return_index=True, return_inverse=True)
-        rep = masks[torch.as_tensor(first, device=masks.device)]
-        inv = torch.as_tensor(inverse.reshape(-1), device=masks.device)
-        Qf = self.outcome_idos(N, rep, lvl.K)[inv].contiguous()
-        Qq = None
-        if lvl.coupled:
-            h = N // 2
-            quarters = B.mlmc_partition_masks(self.dlat, N, rep, stream=self.stream)
-            G = self.dlat.lat.n_groups
-            Qq_rep = self.outcome_idos(h, quarters.reshape(-1, h, h, G), lvl.K_coarse)
-            Qq = Qq_rep.reshape(rep.shape[0], 4, -1)[inv].contiguous()
+        uniq, first, inverse = np.unique(keys, return_index=True, return_inverse=True)
+        cache = self._outcomes.setdefault((N, lvl.coupled, lvl.K, lvl.K_coarse),
+                                          {"index": {}, "Qf": None, "Qq": None})
+        hkeys = [k.tobytes() if isinstance(k, np.void) else int(k) for k in uniq]
+        rows = np.empty(len(hkeys), dtype=np.int64)
+        new = []
+        for i, h in enumerate(hkeys):
+            r = cache["index"].get(h)
+            if r is None:
+                new.append(i)
+            else:
+                rows[i] = r
+        if new:
+            rep = masks[torch.as_tensor(first[new], device=masks.device)]
+            Qf_new = self.outcome_idos(N, rep, lvl.K)
+            base = 0 if cache["Qf"] is None else cache["Qf"].shape[0]
+            cache["Qf"] = Qf_new if cache["Qf"] is None else torch.cat([cache["Qf"], Qf_new])
+            if lvl.coupled:
+                h = N // 2
+                quarters = B.mlmc_partition_masks(self.dlat, N, rep, stream=self.stream)
+                G = self.dlat.lat.n_groups
+                Qq_new = self.outcome_idos(h, quarters.reshape(-1, h, h, G), lvl.K_coarse).reshape(len(new), 4, -1)
+                cache["Qq"] = Qq_new if cache["Qq"] is None else torch.cat([cache["Qq"], Qq_new])
+            for j, i in enumerate(new):
+                cache["index"][hkeys[i]] = base + j
+                rows[i] = base + j
+        sel = torch.as_tensor(rows[inverse.reshape(-1)], device=masks.device)
+        Qf = cache["Qf"][sel].contiguous()
+        Qq = cache["Qq"][sel].contiguous() if lvl.coupled else None
         B.mlmc_level_stats(Qf, Qq, stats=stats, stream=self.stream)
-        self.unique_solved += int(first.size)
+        self.unique_solved += len(new)
 
     def exhaustive_expectation(self, N: int, K: int) -> np.ndarray:
         """E[Q_N] over every vacancy outcome of the N x N supercell, each with
@@ -286,7 +310,21 @@ def outcome_keys(masks: np.ndarray, removable: np.ndarray, translations: bool) -
                 best = code if best is None else np.minimum(best, code)
         return best
     if translations:
-        raise ValueError("translation classes need at most 62 removable sites")
+        # more removable sites than an int64 holds: the lexicographically
+        # smallest packed bit string over the cyclic shifts
+        best = None
+        rows = np.arange(n)
+        for a in range(N):
+            for b in range(N):
+                code = np.packbits(np.roll(bits, (a, b), axis=(1, 2)).reshape(n, -1), axis=1)
+                if best is None:
+                    best = code.copy()
+                    continue
+                diff = code != best
+                at = diff.argmax(axis=1)
+                less = diff.any(axis=1) & (code[rows, at] < best[rows, at])
+                best[less] = code[less]
+        return np.ascontiguousarray(best).view(np.dtype((np.void, best.shape[1]))).reshape(-1)
     packed = np.packbits(bits.reshape(n, -1), axis=1)
     return np.ascontiguousarray(packed).view(np.dtype((np.void, packed.shape[1]))).reshape(-1)
 

@@ -17,7 +17,8 @@ def translates(m):
     return [np.roll(m, (a, b), axis=(0, 1)) for a in range(N) for b in range(N)]
 
 
-@pytest.mark.parametrize("N,G,removable", [(3, 2, [1, 1]), (2, 3, [0, 1, 1]), (4, 2, [1, 1])])
+@pytest.mark.parametrize("N,G,removable", [(3, 2, [1, 1]), (2, 3, [0, 1, 1]), (4, 2, [1, 1]),
+                                           (6, 2, [1, 1]), (8, 2, [1, 1])])   # 72 and 128 removable sites
 def test_translation_keys_identify_exactly_the_translates(N, G, removable):
     rng = np.random.default_rng(N * 10 + G)
     masks = (rng.random((60, N, N, G)) < 0.3).astype(np.uint8)

@@ -69,9 +69,13 @@ def test_duplicate_reuse_equals_plain_level_call(B, N, coupled, K, Kc, M, prec):
         for count in (M // 2, M - M // 2):
             plain.add_samples(a, count)
             dedup.add_samples(b, count)
+        masks = B.mlmc_sample_vacancies(dl, N, 0.05, 303, dl.tag(N), 0, M).cpu().numpy()
     finally:
         dl.close()
-    assert dedup.unique_solved < M                  # duplicates were solved once
+    # every distinct outcome solved exactly once over both rounds (the second
+    # round reuses the first round's outcomes)
+    keys = D.outcome_keys(masks, lat.group_removable, translations=not coupled)
+    assert dedup.unique_solved == np.unique(keys).size < M
     tol = 1e-10 if prec == 0 else 1e-6
     assert np.abs(a.stats[0] - b.stats[0]).max() <= M * tol
     assert np.abs(a.stats[2] - b.stats[2]).max() <= M * tol
