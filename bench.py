@@ -175,6 +175,8 @@ def parse():
     ap.add_argument("--stage1", dest="stage1", action="store_true", default=True,
                     help="kernel-by-kernel roofline of the dense-to-band stage at n ~ 2000 (graphene N = 32)")
     ap.add_argument("--no-stage1", dest="stage1", action="store_false")
+    ap.add_argument("--timer-detail", action="store_true",
+                    help="also time the dense-to-band kernels one by one in the instrumented pass")
     ap.add_argument("--eigh", dest="eigh", action="store_true", default=True,
                     help="eigenstates per second of mlmc_batched_eigh (graphene N = 8)")
     ap.add_argument("--no-eigh", dest="eigh", action="store_false")
@@ -326,6 +328,7 @@ def cpu_info() -> dict:
     return info
 
 
+STAGE1_NAMES = ("s1_panel", "s1_hemm", "s1_wfactor", "s1_update")
 KERNEL_NAMES = ("sample_vacancies", "kgrid", "assemble", "small_fused", "overlap_reduce", "band_reduce", "chase",
                 "bisect", "idos", "level_stats")
 
@@ -398,7 +401,8 @@ def measure(B, wl, lat, eps, prec, args, dev):
     # every launch (pairs created before the pass), for the per-kernel times
     # and the roofline.
     chunks = -(-args.batch // chunk)
-    ctx.timer(args.steps * chunks * 16 + 64)
+    per_chunk = 16 + (4 * (-(-lat.n_orb * N * N // 16)) if args.timer_detail else 0)
+    ctx.timer(args.steps * chunks * per_chunk + 64, detail=args.timer_detail)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -407,7 +411,7 @@ def measure(B, wl, lat, eps, prec, args, dev):
     instrumented = time.perf_counter() - t0
     kernels = {}
     dropped = 0
-    for name in KERNEL_NAMES:
+    for name in KERNEL_NAMES + (STAGE1_NAMES if args.timer_detail else ()):
         ms, cnt, dropped = ctx.timer_read(name)
         if cnt:
             kernels[name] = {"ms": round(ms, 3), "launches": cnt}

@@ -232,7 +232,8 @@ mlmc_status mlmc_build_overlaps(mlmc_lattice lat, int32_t N, const uint8_t *d_ma
  *     chunk_samples outcomes in a single pass with one buffer set (about a
  *     third of the matrix memory of the pipelined layout).
  *   MLMC_OP_BATCHED_EIGH: `batch` matrices of side bound ld (7*ld*ld doubles
- *     each: the tridiagonal eigenvectors and the inverse iteration's scratch).
+ *     each, ld*ld rounded up to even: the tridiagonal eigenvectors and the
+ *     inverse iteration's scratch).
  * Errors: NULL arguments, unknown op, the operation's own argument checks
  * (MLMC_ERR_UNSUPPORTED for sizes beyond the library's limits). */
 mlmc_status mlmc_workspace_bytes(const mlmc_workspace_request *req, size_t *bytes);

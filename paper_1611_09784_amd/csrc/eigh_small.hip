@@ -16,8 +16,8 @@
 //    orthogonalised against the cluster's earlier members in every
 //    iteration; Golub & Van Loan Section 8.2.2, Wilkinson's cluster
 //    treatment), the vectors in a device workspace.
-// 4. Back-transformation V = Q D Z, one thread per eigenvector, the
-//    reflectors read from LDS.
+// 4. Back-transformation V = Q D Z with each eigenvector held in the
+//    registers of four lanes, the reflectors read from LDS.
 #include "device_common.hpp"
 
 namespace mlmc {
@@ -52,8 +52,10 @@ __host__ __device__ inline EighLayout eigh_layout(int cap, int threads) {
 }
 
 // Doubles of device workspace per matrix of side bound cap: Z [cap][cap] and
-// the inverse iteration's scratch, 6 cap per eigenvalue.
-__host__ __device__ inline int64_t eigh_work_doubles(int64_t cap) { return 7 * cap * cap; }
+// the inverse iteration's scratch, 6 cap per eigenvalue (later the complex
+// working copy of V); both parts start at even offsets (16-byte aligned).
+__host__ __device__ inline int64_t eigh_zsize(int64_t cap) { return (cap * cap + 1) & ~int64_t(1); }
+__host__ __device__ inline int64_t eigh_work_doubles(int64_t cap) { return eigh_zsize(cap) + 6 * cap * cap; }
 
 // Deterministic start vector entry in (-1, 1) for (eigenvalue k, row r).
 __device__ __forceinline__ double start_entry(int k, int r) {
@@ -67,7 +69,9 @@ __device__ __forceinline__ double start_entry(int k, int r) {
 }
 
 // Eigenvectors of the symmetric tridiagonal (d, e) for the eigenvalues
-// w[i0..i1) (one cluster), into Z columns i0..i1-1 (column stride ldz).
+// w[i0..i1) (one cluster), into Z columns i0..i1-1 (Z row-major: entry
+// (r, k) at r ldz + k, so that threads taking consecutive vectors touch
+// consecutive addresses later on).
 // scr: 6 n doubles (the pivoted LU of T - lambda I: diagonal, two upper
 // diagonals, multipliers, interchange flags; and the iterate).  rq[i0..i1):
 // the refined eigenvalues.
@@ -87,61 +91,69 @@ __device__ void cluster_vectors(const double *d, const double *e, int n, const d
             if (lam < shift_prev + pertol) lam = shift_prev + pertol;
         }
         shift_prev = lam;
-        // pivoted LU of T - lam I
-        for (int r = 0; r < n; ++r) {
-            dg[r] = d[r] - lam;
-            u1[r] = (r + 1 < n) ? e[r] : 0.0;
-            u2[r] = 0.0;
-        }
+        // pivoted LU of T - lam I; the running pivot row stays in registers
+        // and the factors are only stored (dg as reciprocals of the pivots),
+        // so that no step waits on memory
+        double dcur = d[0] - lam, ucur = n > 1 ? e[0] : 0.0;
         for (int r = 0; r + 1 < n; ++r) {
-            const double c = e[r];
-            const double er1 = (r + 2 < n) ? e[r + 1] : 0.0;
-            if (fabs(dg[r]) >= fabs(c)) {
-                dg[r] = raise(dg[r]);
-                const double l = c / dg[r];
-                lm[r] = l;
+            const double c = e[r], dnext = d[r + 1] - lam, er1 = (r + 2 < n) ? e[r + 1] : 0.0;
+            double l, dn, un;
+            if (fabs(dcur) >= fabs(c)) {
+                dcur = raise(dcur);
+                l = c / dcur;
+                dg[r] = 1.0 / dcur;
+                u1[r] = ucur;
+                u2[r] = 0.0;
                 pv[r] = 0.0;
-                dg[r + 1] -= l * u1[r];
+                dn = dnext - l * ucur;
+                un = er1;
             } else {
-                const double l = dg[r] / c;
-                const double u1old = u1[r], dnext = dg[r + 1];
-                lm[r] = l;
-                pv[r] = 1.0;
-                dg[r] = c;
+                l = dcur / c;
+                dg[r] = 1.0 / c;
                 u1[r] = dnext;
                 u2[r] = er1;
-                dg[r + 1] = u1old - l * dnext;
-                u1[r + 1] = -l * er1;
+                pv[r] = 1.0;
+                dn = ucur - l * dnext;
+                un = -l * er1;
             }
+            lm[r] = l;
+            dcur = dn;
+            ucur = un;
         }
-        dg[n - 1] = raise(dg[n - 1]);
+        dg[n - 1] = 1.0 / raise(dcur);
+        u1[n - 1] = 0.0;
+        u2[n - 1] = 0.0;
         for (int r = 0; r < n; ++r) y[r] = start_entry(k, r);
         for (int it = 0; it < 3; ++it) {
-            // solve L U x = y in place
+            // solve L U x = y in place, the recurrences' operands in registers
+            double ycur = y[0];
             for (int r = 0; r + 1 < n; ++r) {
+                double ynext = y[r + 1];
                 if (pv[r] != 0.0) {
-                    const double t = y[r];
-                    y[r] = y[r + 1];
-                    y[r + 1] = t;
+                    const double tmp = ycur;
+                    ycur = ynext;
+                    ynext = tmp;
                 }
-                y[r + 1] -= lm[r] * y[r];
+                ynext -= lm[r] * ycur;
+                y[r] = ycur;
+                ycur = ynext;
             }
+            y[n - 1] = ycur;
+            double y1 = 0.0, y2 = 0.0, mx = 0.0;
             for (int r = n - 1; r >= 0; --r) {
-                double s = y[r];
-                if (r + 1 < n) s -= u1[r] * y[r + 1];
-                if (r + 2 < n) s -= u2[r] * y[r + 2];
-                y[r] = s / dg[r];
+                const double v = (y[r] - u1[r] * y1 - u2[r] * y2) * dg[r];
+                y[r] = v;
+                y2 = y1;
+                y1 = v;
+                mx = fmax(mx, fabs(v));
             }
             // scale, orthogonalise against the cluster's earlier members, normalise
-            double mx = 0.0;
-            for (int r = 0; r < n; ++r) mx = fmax(mx, fabs(y[r]));
             const double sc = mx > 0.0 ? 1.0 / mx : 1.0;
             for (int r = 0; r < n; ++r) y[r] *= sc;
             for (int q = i0; q < k; ++q) {
-                const double *zq = Z + (int64_t)q * ldz;
                 double dot = 0.0;
-                for (int r = 0; r < n; ++r) dot += zq[r] * y[r];
-                for (int r = 0; r < n; ++r) y[r] -= dot * zq[r];
+                for (int r = 0; r < n; ++r) dot += Z[(int64_t)r * ldz + q] * y[r];
+                for (int r = 0; r < n; ++r) y[r] -= dot * Z[(int64_t)r * ldz + q];
             }
             double nrm = 0.0;
             for (int r = 0; r < n; ++r) nrm += y[r] * y[r];
@@ -149,17 +161,18 @@ __device__ void cluster_vectors(const double *d, const double *e, int n, const d
             const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
             for (int r = 0; r < n; ++r) y[r] *= inv;
         }
-        double *zk = Z + (int64_t)k * ldz;
-        for (int r = 0; r < n; ++r) zk[r] = y[r];
+        for (int r = 0; r < n; ++r) Z[(int64_t)r * ldz + k] = y[r];
     }
     // Rayleigh quotients z^T T z: the eigenvalues to working accuracy (the
     // bisection stops at its absolute bound); the cluster's members sorted by
     // them (clusters are further apart than either bound, so the whole
     // spectrum stays ascending)
     for (int k = i0; k < i1; ++k) {
-        const double *z = Z + (int64_t)k * ldz;
         double q = 0.0;
-        for (int r = 0; r < n; ++r) q += z[r] * (d[r] * z[r] + (r + 1 < n ? 2.0 * e[r] * z[r + 1] : 0.0));
+        for (int r = 0; r < n; ++r) {
+            const double zr = Z[(int64_t)r * ldz + k];
+            q += zr * (d[r] * zr + (r + 1 < n ? 2.0 * e[r] * Z[(int64_t)(r + 1) * ldz + k] : 0.0));
+        }
         rq[k] = q;
     }
     for (int k = i0 + 1; k < i1; ++k) {
@@ -167,17 +180,17 @@ __device__ void cluster_vectors(const double *d, const double *e, int n, const d
             const double tq = rq[q];
             rq[q] = rq[q - 1];
             rq[q - 1] = tq;
-            double *a = Z + (int64_t)q * ldz, *b = Z + (int64_t)(q - 1) * ldz;
             for (int r = 0; r < n; ++r) {
-                const double tr = a[r];
-                a[r] = b[r];
-                b[r] = tr;
+                double *a = Z + (int64_t)r * ldz + q;
+                const double tr = a[0];
+                a[0] = a[-1];
+                a[-1] = tr;
             }
         }
     }
 }
 
-template <typename T>
+template <typename T, int RPT>
 __global__ __launch_bounds__(256) void eigh_small_kernel(const cpx<T> *__restrict__ Hin, int64_t ld,
                                                          const int64_t *__restrict__ offs,
                                                          const int32_t *__restrict__ n_in, double *__restrict__ w,
@@ -244,25 +257,55 @@ __global__ __launch_bounds__(256) void eigh_small_kernel(const cpx<T> *__restric
         int j = i + 1;
         while (j < n && wu[j] - wu[j - 1] <= ortol) ++j;
         // e (squared by the bisection) is free now: it takes the refined eigenvalues
-        cluster_vectors(d, e1, n, wu, i, j, tn, Zu + (int64_t)cap * cap + (int64_t)6 * cap * i, Zu, cap, e);
+        cluster_vectors(d, e1, n, wu, i, j, tn, Zu + eigh_zsize(cap) + (int64_t)6 * cap * i, Zu, cap, e);
     }
     __syncthreads();
-    // V = Q D Z, one thread per eigenvector
-    for (int i = t; i < n; i += nt) {
-        wu[i] = e[i];
-        const double *zi = Zu + (int64_t)i * cap;
-        cpx<T> *vi = V + (int64_t)i * ldv;
-        for (int r = 0; r < n; ++r) vi[r] = {(T)(delta[r].re * zi[r]), (T)(delta[r].im * zi[r])};
+    for (int i = t; i < n; i += nt) wu[i] = e[i];
+    // V = Q D Z with each eigenvector in registers: four lanes per vector,
+    // lane `sub` holding rows sub, sub + 4, ...; nt / 4 vectors at a time.
+    // Every reflector is read from LDS (lanes of one quarter share the
+    // address) and its product with the vector summed over the four lanes.
+    constexpr int kRpt = RPT;  // rows per lane: 4 kRpt >= cap
+    const int sub = t & 3, vpp = nt >> 2;
+    for (int i0 = 0; i0 < n; i0 += vpp) {
+        const int i = i0 + (t >> 2);
+        const bool live = i < n;
+        cpx<T> y[kRpt];
+#pragma unroll
+        for (int q = 0; q < kRpt; ++q) {
+            const int r = sub + 4 * q;
+            const double z = (live && r < n) ? Zu[(int64_t)r * cap + i] : 0.0;
+            const cpx<double> dl = r < n ? delta[r] : cpx<double>{0.0, 0.0};
+            y[q] = {(T)(dl.re * z), (T)(dl.im * z)};
+        }
         for (int jj = n - 3; jj >= 0; --jj) {
             const T tau = refl[cap + jj].re;
-            if (tau == T(0)) continue;
-            const int m = n - jj - 1;
-            const cpx<T> *col = L + packed_col(jj, n) + 1;  // v_j below its first entry
-            cpx<T> s = c_cmul(refl[jj], vi[jj + 1]);
-            for (int r = 1; r < m; ++r) s = c_add(s, c_cmul(col[r], vi[jj + 1 + r]));
-            s = c_scale(tau, s);
-            vi[jj + 1] = c_sub(vi[jj + 1], c_mul(refl[jj], s));
-            for (int r = 1; r < m; ++r) vi[jj + 1 + r] = c_sub(vi[jj + 1 + r], c_mul(col[r], s));
+            if (tau == T(0)) continue;  // uniform: the reflector is the identity
+            const int base = packed_col(jj, n) - jj;  // L[base + r] = v_j[r] for rows r > jj + 1
+            cpx<T> v[kRpt];
+            cpx<T> sp = {T(0), T(0)};
+#pragma unroll
+            for (int q = 0; q < kRpt; ++q) {
+                const int r = sub + 4 * q;
+                const bool in = r > jj && r < n;
+                const cpx<T> lv = L[in ? (r == jj + 1 ? 0 : base + r) : 0];
+                v[q] = in ? (r == jj + 1 ? refl[jj] : lv) : cpx<T>{T(0), T(0)};
+                sp = c_add(sp, c_cmul(v[q], y[q]));
+            }
+            sp.re += __shfl_xor(sp.re, 1, 64);
+            sp.im += __shfl_xor(sp.im, 1, 64);
+            sp.re += __shfl_xor(sp.re, 2, 64);
+            sp.im += __shfl_xor(sp.im, 2, 64);
+            const cpx<T> sc = c_scale(tau, sp);
+#pragma unroll
+            for (int q = 0; q < kRpt; ++q) y[q] = c_sub(y[q], c_mul(v[q], sc));
+        }
+        if (live) {
+#pragma unroll
+            for (int q = 0; q < kRpt; ++q) {
+                const int r = sub + 4 * q;
+                if (r < n) V[(int64_t)i * ldv + r] = y[q];
+            }
         }
     }
 }
@@ -280,11 +323,17 @@ hipError_t launch_eigh_small(const cpx<T> *H, int64_t ld, const int64_t *offs, c
     const int cap = (int)ld;
     const int threads = cap <= 32 ? 64 : (cap <= 64 ? 128 : 256);
     const EighLayout lay = eigh_layout<T>(cap, threads);
-    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(eigh_small_kernel<T>),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lay.bytes);
+    // rows per lane of the back-transformation: 32 (sides up to 128) or 45 (up to 180)
+    const void *fn = cap <= 128 ? reinterpret_cast<const void *>(eigh_small_kernel<T, 32>)
+                                : reinterpret_cast<const void *>(eigh_small_kernel<T, 45>);
+    hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lay.bytes);
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(eigh_small_kernel<T>, dim3((unsigned)batch), dim3(threads), lay.bytes, s, H, ld, offs, n_in, w,
-                       ldw, V, ldv, work, cap);
+    if (cap <= 128)
+        hipLaunchKernelGGL((eigh_small_kernel<T, 32>), dim3((unsigned)batch), dim3(threads), lay.bytes, s, H, ld, offs,
+                           n_in, w, ldw, V, ldv, work, cap);
+    else
+        hipLaunchKernelGGL((eigh_small_kernel<T, 45>), dim3((unsigned)batch), dim3(threads), lay.bytes, s, H, ld, offs,
+                           n_in, w, ldw, V, ldv, work, cap);
     return hipGetLastError();
 }
 

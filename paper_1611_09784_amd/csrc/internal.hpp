@@ -110,7 +110,9 @@ hipError_t launch_small_from_matrix(const cpx<T> *H, int64_t ld, const int32_t *
 template <typename T>
 hipError_t launch_eigh_small(const cpx<T> *H, int64_t ld, const int64_t *offs, const int32_t *n_in, int64_t batch,
                              double *w, int64_t ldw, cpx<T> *V, int64_t ldv, double *work, hipStream_t s);
-inline size_t eigh_work_bytes(int64_t ld, int64_t batch) { return sizeof(double) * 7 * (size_t)ld * ld * batch; }
+inline size_t eigh_work_bytes(int64_t ld, int64_t batch) {
+    return sizeof(double) * (size_t)((((ld * ld + 1) & ~int64_t(1)) + 6 * ld * ld) * batch);
+}
 
 // Per-kernel timing inside launchers that issue several kernels: when the
 // calling thread enqueues work for a context whose launch timer is on, an

@@ -130,6 +130,7 @@ def clustered_spectrum(m, rng):
 
 
 @pytest.mark.parametrize("ld,sizes,prec", [(64, [0, 1, 2, 3, 17, 64], 0), (128, [128, 127, 5], 0),
+                                           (127, [127, 60, 1], 0), (33, [33, 20, 2], 1),   # odd sides
                                            (64, [1, 2, 33, 64], 1), (180, [180, 179, 7], 1)])
 def test_eigh_random(B, ld, sizes, prec):
     say(f"[eigh random] ld={ld} sizes={sizes} prec={prec}")
