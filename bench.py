@@ -290,7 +290,7 @@ def time_to_tol(B, dev, wl_name="graphene_mlmc", variants=None, oracle_samples=N
 
 def host_threads() -> int:
     """Threads for the oracle: every core this process may run on, at most 16
-    (the host share of one GPU on the GPU machines)."""
+    (the host cores that serve one GPU of a multi-GPU node)."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:  # pragma: no cover
@@ -765,8 +765,8 @@ def main():
         cpu = {"value": round(ns * nk / ct, 3), "unit": "eigensolves/s", "cores": threads, "kind": "oracle",
                "sample": f"{ns} samples x {nk} k-points of {wl.name} (samples 0..{ns - 1}), {ct:.1f} s",
                "cpu_model": info["model"], "host": info,
-               "threads_note": "one oracle thread per core this process may use, at most 16 (the host share of "
-                               "one GPU on the GPU boxes)"}
+               "threads_note": "one oracle thread per core this process may use, at most 16 (the host cores "
+                               "that serve one GPU of a multi-GPU node)"}
         # Context: the oracle on one core (the paper's one-sample-per-core
         # regime), and LAPACK's Hermitian eigenvalues (scipy, threaded BLAS)
         # on the oracle-built matrices of sample 0, eigenvalues only.
