@@ -441,10 +441,6 @@ constexpr int kBlkW(int R) {
     return (int)(256 / (2 * sizeof(T))) / R;
 }
 
-// Eight rows per thread for complex64 (four, never launched, for complex128).
-template <typename T>
-constexpr int kBlkR8 = sizeof(T) == 4 ? 8 : 4;
-
 template <typename T, int NT>
 struct QrBlkShared {
     double part[2][NT / 64][128];  // per-wavefront reduce-scattered sums, two buffers in turn
@@ -499,11 +495,23 @@ __device__ __forceinline__ void blk_load_v(const TwoView<T> &w, int ldi, int s, 
 // X[q][c] = sum over the thread's rows of conj(V[q][r]) B[r][c] for the
 // reflectors q < Q of earlier sub-panels (16 products per chunk), summed over
 // the workgroup: X at 2 (q W + c) (re, im) of the returned copy.
+// Reflectors per chunk of a V^H product: 16 products, or fewer when R rows of
+// them would not stay in registers (at most 32 complex values of V per chunk).
+template <int R, int W>
+constexpr int kBlkQB = (16 / W) < (32 / R) ? (16 / W) : (32 / R);
+// Slot of X[q][c] (re; im at +1) in the summed copy: chunk q / QB holds
+// 32 slots, of which it fills 2 QB W.
+template <int R, int W>
+__device__ __forceinline__ int blk_slot(int q, int c) {
+    constexpr int QB = kBlkQB<R, W>;
+    return 32 * (q / QB) + 2 * ((q % QB) * W + c);
+}
+
 template <typename T, int NT, int R, int W, int Q>
 __device__ __forceinline__ const double *blk_vh_times(QrBlkShared<T, NT> &sh, const TwoView<T> &w, int ldi, int s,
                                                       int n, const cpx<T> (&Bm)[R][W], int &pb) {
-    constexpr int QB = 16 / W, NCH = (Q + QB - 1) / QB;
-    static_assert(NCH * 32 <= 128, "at most four chunks");
+    constexpr int QB = kBlkQB<R, W>, NCH = (Q + QB - 1) / QB;
+    static_assert(QB >= 1 && NCH * 32 <= 128, "at most four chunks");
 #pragma unroll 1
     for (int ch = 0; ch < NCH; ++ch) {
         T x[32];
@@ -525,7 +533,7 @@ __device__ __forceinline__ const double *blk_vh_times(QrBlkShared<T, NT> &sh, co
         }
         blk_red_chunk<T, NT>(sh.part[pb], ch, x);
     }
-    const double *out = blk_red_finish<NT, 2 * Q * W>(sh.part[pb], sh.dotw);
+    const double *out = blk_red_finish<NT, 32 * NCH>(sh.part[pb], sh.dotw);
     pb ^= 1;
     return out;
 }
@@ -632,7 +640,7 @@ __device__ __forceinline__ void qr_blk_subpanel(QrBlkShared<T, NT> &sh, cpx<T> *
             const int q = t / W, c = t % W;
             cpx<T> z = zero;
             for (int q2 = 0; q2 <= q; ++q2)
-                z = c_add(z, c_cmul(sh.Ts[q2][q], cpx<T>{(T)Y[2 * (q2 * W + c)], (T)Y[2 * (q2 * W + c) + 1]}));
+                z = c_add(z, c_cmul(sh.Ts[q2][q], cpx<T>{(T)Y[blk_slot<R, W>(q2, c)], (T)Y[blk_slot<R, W>(q2, c) + 1]}));
             sh.Zs[q][c] = z;
         }
         __syncthreads();
@@ -673,7 +681,8 @@ __device__ __forceinline__ void qr_blk_subpanel(QrBlkShared<T, NT> &sh, cpx<T> *
             const int q = t / W, c = t % W;
             cpx<T> m1 = zero;
             for (int c2 = 0; c2 <= c; ++c2)
-                m1 = c_add(m1, c_mul(cpx<T>{(T)X[2 * (q * W + c2)], (T)X[2 * (q * W + c2) + 1]}, sh.Ts[c0 + c2][c0 + c]));
+                m1 = c_add(m1, c_mul(cpx<T>{(T)X[blk_slot<R, W>(q, c2)], (T)X[blk_slot<R, W>(q, c2) + 1]},
+                                     sh.Ts[c0 + c2][c0 + c]));
             sh.Zs[q][c] = m1;
         }
         __syncthreads();
@@ -1146,9 +1155,9 @@ hipError_t launch_band_reduce(cpx<T> *H, int64_t ld, const int32_t *n_in, int64_
             else if (mmax <= 2048)
                 hipLaunchKernelGGL((qr_panel_blk_kernel<T, 512, 4, kBlkW<T>(4)>), dim3(B), dim3(512), 0, s, H, ld,
                                    offs, n_in, work, stride, p);
-            else if (sizeof(T) == 4 && mmax <= 4096)  // (eight complex128 rows per thread would spill)
-                hipLaunchKernelGGL((qr_panel_blk_kernel<T, 512, kBlkR8<T>, kBlkW<T>(kBlkR8<T>)>), dim3(B), dim3(512),
-                                   0, s, H, ld, offs, n_in, work, stride, p);
+            else if (mmax <= 4096)
+                hipLaunchKernelGGL((qr_panel_blk_kernel<T, 512, 8, kBlkW<T>(8)>), dim3(B), dim3(512), 0, s, H, ld,
+                                   offs, n_in, work, stride, p);
             else
                 hipLaunchKernelGGL(qr_panel_kernel<T>, dim3(B), dim3(kQrThreads), 0, s, H, ld, offs, n_in, work,
                                    stride, p);
