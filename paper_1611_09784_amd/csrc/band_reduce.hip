@@ -441,12 +441,16 @@ constexpr int kBlkW(int R) {
     return (int)(256 / (2 * sizeof(T))) / R;
 }
 
-template <typename T, int NT>
+// 32 rows per thread for complex64 (16, a variant launched above, for complex128).
+template <typename T>
+constexpr int kBlkR32 = sizeof(T) == 4 ? 32 : 16;
+
+template <typename T, int NT, int SL>
 struct QrBlkShared {
-    double part[2][NT / 64][128];  // per-wavefront reduce-scattered sums, two buffers in turn
-    double dotw[NT / 64][128];     // each wavefront's copy of the summed products
-    double nred[NT / 64];
-    cpx<T> x0s;
+    double part[2][NT / 64][SL];  // per-wavefront reduce-scattered sums, two buffers in turn
+    double dotw[NT / 64][SL];     // each wavefront's copy of the summed products
+    double nred[2][NT / 64];  // column norms and pivots of consecutive reflectors alternate, so
+    cpx<T> x0s[2];            // that no barrier is needed between a read and the next write
     cpx<T> Ts[kB][kB];
     cpx<T> Zs[kB][kB];  // T^H (V^H A_g), then (V0^H V1) T1
     cpx<T> alphas[kB];
@@ -454,8 +458,8 @@ struct QrBlkShared {
 
 // One chunk of 32 values of a workgroup sum: this wavefront's reduce-scatter
 // into slots 32 chunk .. 32 chunk + 31 of `part`.
-template <typename T, int NT>
-__device__ __forceinline__ void blk_red_chunk(double (&part)[NT / 64][128], int chunk, const T (&x)[32]) {
+template <typename T, int NT, int SL>
+__device__ __forceinline__ void blk_red_chunk(double (&part)[NT / 64][SL], int chunk, const T (&x)[32]) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const T r = wave_reduce_scatter32(x);
     if ((lane & 1) == 0) part[wid][32 * chunk + scatter_elem(lane)] = (double)r;
@@ -465,9 +469,8 @@ __device__ __forceinline__ void blk_red_chunk(double (&part)[NT / 64][128], int 
 // in order).  Consecutive sums alternate between the two buffers of `part`,
 // so that a sum's writes never meet a slower wavefront's reads of the sum
 // before the previous one (a barrier separates them).
-template <int NT, int NV>
-__device__ __forceinline__ const double *blk_red_finish(double (&part)[NT / 64][128],
-                                                        double (&dotw)[NT / 64][128]) {
+template <int NT, int SL, int NV>
+__device__ __forceinline__ const double *blk_red_finish(double (&part)[NT / 64][SL], double (&dotw)[NT / 64][SL]) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     __syncthreads();
 #pragma unroll
@@ -499,6 +502,11 @@ __device__ __forceinline__ void blk_load_v(const TwoView<T> &w, int ldi, int s, 
 // them would not stay in registers (at most 32 complex values of V per chunk).
 template <int R, int W>
 constexpr int kBlkQB = (16 / W) < (32 / R) ? (16 / W) : (32 / R);
+// LDS slots of a workgroup sum: the largest V^H product (reflectors of all
+// sub-panels but the last) in chunks of 32, at least one chunk.
+template <int R, int W>
+constexpr int kBlkSlots = 32 * ((kB - W + kBlkQB<R, W> - 1) / kBlkQB<R, W> > 1
+                                    ? (kB - W + kBlkQB<R, W> - 1) / kBlkQB<R, W> : 1);
 // Slot of X[q][c] (re; im at +1) in the summed copy: chunk q / QB holds
 // 32 slots, of which it fills 2 QB W.
 template <int R, int W>
@@ -508,10 +516,10 @@ __device__ __forceinline__ int blk_slot(int q, int c) {
 }
 
 template <typename T, int NT, int R, int W, int Q>
-__device__ __forceinline__ const double *blk_vh_times(QrBlkShared<T, NT> &sh, const TwoView<T> &w, int ldi, int s,
+__device__ __forceinline__ const double *blk_vh_times(QrBlkShared<T, NT, kBlkSlots<R, W>> &sh, const TwoView<T> &w, int ldi, int s,
                                                       int n, const cpx<T> (&Bm)[R][W], int &pb) {
     constexpr int QB = kBlkQB<R, W>, NCH = (Q + QB - 1) / QB;
-    static_assert(QB >= 1 && NCH * 32 <= 128, "at most four chunks");
+    static_assert(QB >= 1 && NCH * 32 <= kBlkSlots<R, W>, "chunks within the LDS slots");
 #pragma unroll 1
     for (int ch = 0; ch < NCH; ++ch) {
         T x[32];
@@ -531,16 +539,16 @@ __device__ __forceinline__ const double *blk_vh_times(QrBlkShared<T, NT> &sh, co
                 x[2 * (qq * W + c) + 1] = acc.im;
             }
         }
-        blk_red_chunk<T, NT>(sh.part[pb], ch, x);
+        blk_red_chunk<T, NT, kBlkSlots<R, W>>(sh.part[pb], ch, x);
     }
-    const double *out = blk_red_finish<NT, 32 * NCH>(sh.part[pb], sh.dotw);
+    const double *out = blk_red_finish<NT, kBlkSlots<R, W>, 32 * NCH>(sh.part[pb], sh.dotw);
     pb ^= 1;
     return out;
 }
 
 // Reflector I = c0 + C of the panel (column C of the sub-panel in P).
 template <typename T, int NT, int R, int W, int C>
-__device__ __forceinline__ void qr_blk_reflect(QrBlkShared<T, NT> &sh, cpx<T> (&P)[R][W], int c0, int s, int n,
+__device__ __forceinline__ void qr_blk_reflect(QrBlkShared<T, NT, kBlkSlots<R, W>> &sh, cpx<T> (&P)[R][W], int c0, int s, int n,
                                                int nr, int &pb) {
     constexpr int NW = NT / 64;
     const int I = c0 + C;
@@ -557,68 +565,72 @@ __device__ __forceinline__ void qr_blk_reflect(QrBlkShared<T, NT> &sh, cpx<T> (&
         ws += (r < n && r >= r0) ? (double)c_abs2(P[k][C]) : 0.0;
     }
     ws = col_sum(row_sum(ws));
-    if (lane == 0) sh.nred[wid] = ws;
-    if (t == I) sh.x0s = P[0][C];
+    const int nb = I & 1;
+    if (lane == 0) sh.nred[nb][wid] = ws;
+    if (t == I) sh.x0s[nb] = P[0][C];
     __syncthreads();
     double nrm2 = 0.0;
 #pragma unroll
-    for (int q = 0; q < NW; ++q) nrm2 += sh.nred[q];
+    for (int q = 0; q < NW; ++q) nrm2 += sh.nred[nb][q];
     T tau;
     cpx<T> v0, alpha;
-    make_reflector<T>(nrm2, sh.x0s, tau, v0, alpha);
+    make_reflector<T>(nrm2, sh.x0s[nb], tau, v0, alpha);
     cpx<T> v[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         const int r = s + t + NT * k;
         v[k] = csel(r == r0, v0, csel(r < n && r > r0, P[k][C], zero));
     }
-    // v^H P[:, c] for the sub-panel's columns c > C, V[:, c]^H v for c < C
-    T x[32];
+    // (a one-column sub-panel has no other columns: no second reduction)
+    if constexpr (W > 1) {
+        // v^H P[:, c] for the sub-panel's columns c > C, V[:, c]^H v for c < C
+        T x[32];
 #pragma unroll
-    for (int j = 0; j < 32; ++j) x[j] = T(0);
+        for (int j = 0; j < 32; ++j) x[j] = T(0);
 #pragma unroll
-    for (int c = 0; c < W; ++c) {
-        cpx<T> acc = zero;
+        for (int c = 0; c < W; ++c) {
+            cpx<T> acc = zero;
 #pragma unroll
-        for (int k = 0; k < R; ++k) {
-            if (c > C) acc = c_add(acc, c_cmul(v[k], P[k][c]));
-            else if (c < C) acc = c_add(acc, c_cmul(P[k][c], v[k]));
+            for (int k = 0; k < R; ++k) {
+                if (c > C) acc = c_add(acc, c_cmul(v[k], P[k][c]));
+                else if (c < C) acc = c_add(acc, c_cmul(P[k][c], v[k]));
+            }
+            x[2 * c] = acc.re;
+            x[2 * c + 1] = acc.im;
         }
-        x[2 * c] = acc.re;
-        x[2 * c + 1] = acc.im;
-    }
-    blk_red_chunk<T, NT>(sh.part[pb], 0, x);
-    const double *d = blk_red_finish<NT, 2 * W>(sh.part[pb], sh.dotw);
-    pb ^= 1;
+        blk_red_chunk<T, NT, kBlkSlots<R, W>>(sh.part[pb], 0, x);
+        const double *d = blk_red_finish<NT, kBlkSlots<R, W>, 2 * W>(sh.part[pb], sh.dotw);
+        pb ^= 1;
 #pragma unroll
-    for (int c = C + 1; c < W; ++c) {
-        const cpx<T> dc = {(T)d[2 * c], (T)d[2 * c + 1]};
+        for (int c = C + 1; c < W; ++c) {
+            const cpx<T> dc = {(T)d[2 * c], (T)d[2 * c + 1]};
 #pragma unroll
-        for (int k = 0; k < R; ++k) P[k][c] = c_sub(P[k][c], c_scale(tau, c_mul(v[k], dc)));
+            for (int k = 0; k < R; ++k) P[k][c] = c_sub(P[k][c], c_scale(tau, c_mul(v[k], dc)));
+        }
+        // T[c0:I, I] = -tau T[c0:I, c0:I] (V^H v_I)[c0:I], T[I, I] = tau
+        if (t >= c0 && t < I) {
+            cpx<T> sum = zero;
+            for (int q = t; q < I; ++q)
+                sum = c_add(sum, c_mul(sh.Ts[t][q], cpx<T>{(T)d[2 * (q - c0)], (T)d[2 * (q - c0) + 1]}));
+            sh.Ts[t][I] = c_scale(-tau, sum);
+        }
     }
 #pragma unroll
     for (int k = 0; k < R; ++k) P[k][C] = csel(s + t + NT * k == r0, v0, P[k][C]);
-    // T[c0:I, I] = -tau T[c0:I, c0:I] (V^H v_I)[c0:I], T[I, I] = tau
-    if (t >= c0 && t < I) {
-        cpx<T> sum = zero;
-        for (int q = t; q < I; ++q)
-            sum = c_add(sum, c_mul(sh.Ts[t][q], cpx<T>{(T)d[2 * (q - c0)], (T)d[2 * (q - c0) + 1]}));
-        sh.Ts[t][I] = c_scale(-tau, sum);
-    }
     if (t == I) {
         sh.Ts[I][I] = {tau, T(0)};
         sh.alphas[I] = alpha;
     }
 }
 template <typename T, int NT, int R, int W, int... Cs>
-__device__ __forceinline__ void qr_blk_reflect_all(QrBlkShared<T, NT> &sh, cpx<T> (&P)[R][W], int c0, int s, int n,
+__device__ __forceinline__ void qr_blk_reflect_all(QrBlkShared<T, NT, kBlkSlots<R, W>> &sh, cpx<T> (&P)[R][W], int c0, int s, int n,
                                                    int nr, int &pb, std::integer_sequence<int, Cs...>) {
     (qr_blk_reflect<T, NT, R, W, Cs>(sh, P, c0, s, n, nr, pb), ...);
 }
 
 // Sub-panel G (panel columns G W .. G W + W - 1).
 template <typename T, int NT, int R, int W, int G>
-__device__ __forceinline__ void qr_blk_subpanel(QrBlkShared<T, NT> &sh, cpx<T> *A, const TwoView<T> &w, int ldi,
+__device__ __forceinline__ void qr_blk_subpanel(QrBlkShared<T, NT, kBlkSlots<R, W>> &sh, cpx<T> *A, const TwoView<T> &w, int ldi,
                                                 int p, int s, int n, int nr, int &pb) {
     constexpr int c0 = G * W;
     const int t = threadIdx.x;
@@ -695,7 +707,7 @@ __device__ __forceinline__ void qr_blk_subpanel(QrBlkShared<T, NT> &sh, cpx<T> *
     }
 }
 template <typename T, int NT, int R, int W, int... Gs>
-__device__ __forceinline__ void qr_blk_all(QrBlkShared<T, NT> &sh, cpx<T> *A, const TwoView<T> &w, int ldi, int p,
+__device__ __forceinline__ void qr_blk_all(QrBlkShared<T, NT, kBlkSlots<R, W>> &sh, cpx<T> *A, const TwoView<T> &w, int ldi, int p,
                                            int s, int n, int nr, int &pb, std::integer_sequence<int, Gs...>) {
     (qr_blk_subpanel<T, NT, R, W, Gs>(sh, A, w, ldi, p, s, n, nr, pb), ...);
 }
@@ -706,7 +718,7 @@ __global__ __launch_bounds__(NT) void qr_panel_blk_kernel(cpx<T> *__restrict__ H
                                                           const int32_t *__restrict__ n_in,
                                                           cpx<T> *__restrict__ wall, int64_t stride, int p) {
     static_assert(kB % W == 0 && W * R * 2 * sizeof(T) == 256, "sub-panel of 256 bytes per thread");
-    __shared__ QrBlkShared<T, NT> sh;
+    __shared__ QrBlkShared<T, NT, kBlkSlots<R, W>> sh;
     const int64_t u = blockIdx.x;
     const int n = n_in[u];
     const int s = p + kB, m = n - s;
@@ -1158,6 +1170,12 @@ hipError_t launch_band_reduce(cpx<T> *H, int64_t ld, const int32_t *n_in, int64_
             else if (mmax <= 4096)
                 hipLaunchKernelGGL((qr_panel_blk_kernel<T, 512, 8, kBlkW<T>(8)>), dim3(B), dim3(512), 0, s, H, ld,
                                    offs, n_in, work, stride, p);
+            else if (mmax <= 8192)
+                hipLaunchKernelGGL((qr_panel_blk_kernel<T, 512, 16, kBlkW<T>(16)>), dim3(B), dim3(512), 0, s, H, ld,
+                                   offs, n_in, work, stride, p);
+            else if (sizeof(T) == 4 && mmax <= 16384)  // (32 complex128 rows per thread would not fit)
+                hipLaunchKernelGGL((qr_panel_blk_kernel<T, 512, kBlkR32<T>, kBlkW<T>(kBlkR32<T>)>), dim3(B),
+                                   dim3(512), 0, s, H, ld, offs, n_in, work, stride, p);
             else
                 hipLaunchKernelGGL(qr_panel_kernel<T>, dim3(B), dim3(kQrThreads), 0, s, H, ld, offs, n_in, work,
                                    stride, p);

@@ -213,3 +213,42 @@ def test_eigvalsh_mos2_n32_with_vacancies_trace_identities(B, mdev, mlat):
     # each eigenvalue within 1e-9 max|E| gives these bounds on the sums
     assert abs(E.sum() - tr) <= nb * 1e-9 * emax
     assert abs((E * E).sum() - fro2) <= 2.0 * nb * 1e-9 * emax * emax
+
+
+def known_spectrum_matrix(n, seed):
+    """Dense Hermitian H = P3 P2 P1 diag(lam) P1 P2 P3 with random Householder
+    reflectors P = I - 2 v v^H (every entry of H nonzero) and a spectrum lam
+    known by construction: random values, a three-fold zero, a three-fold
+    1.5 and a pair 1e-9 apart."""
+    rng = np.random.default_rng(seed)
+    lam = np.sort(np.concatenate([rng.uniform(-6.0, 6.0, n - 8), [0.0] * 3, [1.5] * 3, [2.0, 2.0 + 1e-9]]))
+    A = np.diag(lam).astype(np.complex128)
+    for _ in range(3):
+        v = rng.normal(size=n) + 1j * rng.normal(size=n)
+        v /= np.linalg.norm(v)
+        w = A @ v
+        A -= 2.0 * np.outer(v, w.conj())
+        A -= 2.0 * np.outer(w, v.conj())
+        A += (4.0 * np.vdot(v, w).real) * np.outer(v, v.conj())
+    return A, lam
+
+
+@pytest.mark.parametrize("n,prec", [(5200, 0), (9000, 0), (9000, 1)])
+def test_eigvalsh_tall_panels_known_spectrum(B, n, prec):
+    """Dense matrices whose dense-to-band panels are taller than 4096 rows
+    (the register-blocked panel QR with 16 rows per thread, and 32 in
+    complex64; above 8192 rows in complex128 the global-memory panel QR):
+    every eigenvalue against the spectrum known by construction, within
+    1e-9 max|E| (FP64) and 5e-5 max|E| (mixed, a single-precision reduction of
+    side 9000)."""
+    say(f"[eigvalsh known spectrum] n={n} prec={prec}")
+    A, lam = known_spectrum_matrix(n, 1000 + n)
+    dt = torch.complex128 if prec == 0 else torch.complex64
+    H = torch.as_tensor(np.ascontiguousarray(A.T)[None], device=DEV).to(dt)  # column-major storage
+    del A
+    nn = torch.full((1,), n, dtype=torch.int32, device=DEV)
+    w = B.mlmc_batched_eigvalsh(H, nn, prec=prec).cpu().numpy()[0]
+    err = np.abs(w - lam).max()
+    tol = (1e-9 if prec == 0 else 5e-5) * np.abs(lam).max()
+    say(f"  max error {err:.3e} (bound {tol:.3e})")
+    assert err <= tol
