@@ -642,3 +642,31 @@ def test_batched_eigvalsh_ragged(B, gdev, mdev, name, N, prec):
     got = B.mlmc_batched_eigvalsh(flat, n_r, prec=prec, offsets=offsets, ld=ld).cpu().numpy()
     for pos, b in enumerate(order):
         assert np.array_equal(got[pos, :nn[b]], want[b, :nn[b]]), f"matrix {b}"
+
+
+def test_context_timer_detail(B, gdev):
+    """The context timer's detail mode times the dense-to-band kernels one by
+    one (one launch each per panel, inside the stage's own record); without it
+    only the whole stage is recorded.  Timing never changes the results."""
+    say("[context timer detail]")
+    N, K, M = 16, 1, 4
+    eps = torch.as_tensor(energy_grid(-9.0, 9.0, 41), device=DEV)
+    need = B.mlmc_level_workspace(gdev, N, False, K, K, 0, M, 0, 41)
+    work = torch.empty((need,), dtype=torch.uint8, device=DEV)
+    sums = []
+    for detail in (False, True):
+        stats = torch.zeros((4, 41), dtype=torch.float64, device=DEV)
+        with B.Context(0) as ctx:
+            ctx.timer(4096, detail=detail)
+            B.mlmc_level_estimate(gdev, N, False, 0.05, K, K, 0, 11, 0, M, eps, 0.1, 0, 0, stats=stats, work=work,
+                                  ctx=ctx)
+            torch.cuda.synchronize()
+            _, stage, _ = ctx.timer_read("band_reduce")
+            counts = [ctx.timer_read(k)[1] for k in ("s1_panel", "s1_hemm", "s1_wfactor", "s1_update")]
+        assert stage >= 1
+        if detail:
+            assert counts[0] > 0 and len(set(counts)) == 1, counts   # one of each per panel
+        else:
+            assert counts == [0, 0, 0, 0]
+        sums.append(stats.cpu().numpy())
+    assert np.array_equal(sums[0], sums[1])
