@@ -909,9 +909,16 @@ __global__ __launch_bounds__(kWThreads) void wfactor_kernel(const int32_t *__res
     const cpx<T> *Zp = hemm_partials(w, ld);
     const int blocks = (m + 15) / 16;  // the Hermitian product's 16-row tiles
     Ts[k][l] = w.Tm[t];
-    cpx<T> z = {T(0), T(0)};
-    for (int b = 0; b < blocks; ++b) z = c_add(z, Zp[(int64_t)b * kB * kB + t]);
-    Zs[k][l] = z;
+    // four partial sums over the tiles b = i (mod 4), then their sum in
+    // order: a fixed order, with four independent chains of loads and adds
+    cpx<T> z4[4] = {{T(0), T(0)}, {T(0), T(0)}, {T(0), T(0)}, {T(0), T(0)}};
+    int b = 0;
+    for (; b + 4 <= blocks; b += 4) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) z4[i] = c_add(z4[i], Zp[(int64_t)(b + i) * kB * kB + t]);
+    }
+    for (int i = 0; b + i < blocks; ++i) z4[i] = c_add(z4[i], Zp[(int64_t)(b + i) * kB * kB + t]);
+    Zs[k][l] = c_add(c_add(z4[0], z4[1]), c_add(z4[2], z4[3]));
     __syncthreads();
     cpx<T> y = {T(0), T(0)};  // Y = T^H Z, T upper triangular
     for (int q = 0; q <= k; ++q) y = c_add(y, c_cmul(Ts[q][k], Zs[q][l]));
