@@ -231,9 +231,12 @@ mlmc_status mlmc_build_overlaps(mlmc_lattice lat, int32_t N, const uint8_t *d_ma
  *   MLMC_OP_LEVEL_OUTCOMES_SINGLE_PASS: mlmc_level_outcomes on up to
  *     chunk_samples outcomes in a single pass with one buffer set (about a
  *     third of the matrix memory of the pipelined layout).
- *   MLMC_OP_BATCHED_EIGH: `batch` matrices of side bound ld (7*ld*ld doubles
- *     each, ld*ld rounded up to even: the tridiagonal eigenvectors and the
- *     inverse iteration's scratch).
+ *   MLMC_OP_BATCHED_EIGH: `batch` matrices of side bound ld.  LDS-resident
+ *     sides: 7*ld*ld doubles each, ld*ld rounded up to even (the tridiagonal
+ *     eigenvectors and the inverse iteration's scratch).  Larger complex128
+ *     sides: a copy of each matrix, the two-stage buffers, every panel's
+ *     block reflector (16*ld + 256 complex per 16 columns) and the band
+ *     inverse iteration's LU factors (about 788*ld bytes per wavefront).
  * Errors: NULL arguments, unknown op, the operation's own argument checks
  * (MLMC_ERR_UNSUPPORTED for sizes beyond the library's limits). */
 mlmc_status mlmc_workspace_bytes(const mlmc_workspace_request *req, size_t *bytes);
@@ -280,25 +283,37 @@ mlmc_status mlmc_batched_eigvalsh_noalloc(mlmc_dtype dtype, mlmc_precision prec,
 /* Eigenvalues and eigenvectors of a batch of Hermitian matrices: the
  * eigenstates that the Kubo-Greenwood conductivity needs besides the band
  * energies (Section 1; named as the next quantity of interest in Section 5).
- * LDS-resident matrices only: ld <= 128 complex128 / 180 complex64.  One
+ * LDS-resident matrices (ld <= 128 complex128 / 180 complex64): one
  * workgroup per matrix: Householder reduction H = Q T_c Q^H with the
  * reflectors kept, T_c = D T D^H with a diagonal unitary D that makes the
  * sub-diagonal real and non-negative, eigenvalues of T by the bisection of
  * mlmc_batched_eigvalsh, eigenvectors Z of T by inverse iteration with
- * partial pivoting (eigenvalues closer than 1e-3 ||T||_1 form a cluster
- * whose vectors are orthogonalised against each other in every iteration),
- * the eigenvalues refined to the Rayleigh quotients z^T T z (ascending),
- * then V = Q D Z.
- * d_H, d_offsets, d_n, d_w, ldw: as mlmc_batched_eigvalsh (the lower
- * triangles are read; the matrices are left unchanged).  d_V: the
+ * partial pivoting, then V = Q D Z.
+ * Larger matrices (complex128 only, ld <= 4096): a copy of the matrices is
+ * reduced to a band of half-width 16 (stage 1 of mlmc_batched_eigvalsh, each
+ * panel's block reflector I - V_p T_p V_p^H kept), the band is chased to
+ * tridiagonal form and bisected for the eigenvalues, eigenvectors of the band
+ * matrix B come from inverse iteration with a pivoted band LU of B - lam I
+ * (one wavefront per cluster), and the block reflectors take them back,
+ * last panel first.
+ * Both paths: eigenvalues closer than 1e-3 of the spectral radius form a
+ * cluster whose vectors are orthogonalised against each other after every
+ * solve; the eigenvalues are refined to the vectors' Rayleigh quotients
+ * (ascending, a cluster's columns sorted with them).
+ * d_H, d_offsets, d_n, d_w, ldw: as mlmc_batched_eigvalsh, except that the
+ * matrices are left unchanged (only the lower triangles are read).  d_V: the
  * eigenvectors, matrix b at element b*ldv*ldv, column-major with leading
  * dimension ldv, column i (entries 0..n_b-1) the unit eigenvector of
  * d_w[b][i]; entries outside the leading n_b x n_b block are untouched.
  * Each vector is determined up to a phase (within a cluster, the cluster's
  * columns up to a unitary mix).  Accuracy: ||H v - w v|| of a few ulps of
  * ||H|| in the compute type (complex128 or complex64), columns orthonormal
- * to the same order.  d_work: mlmc_workspace_bytes(MLMC_OP_BATCHED_EIGH).
- * Errors: ld above the bound (MLMC_ERR_UNSUPPORTED), ldw or ldv < ld,
+ * to the same order.  d_work: mlmc_workspace_bytes(MLMC_OP_BATCHED_EIGH)
+ * (7 ld^2 doubles per LDS-resident matrix; above that about 2 ld^2 complex
+ * per matrix and the inverse iteration's factors, ld * 788 bytes per
+ * wavefront in flight).
+ * Errors: ld above 4096, or above the LDS bound in complex64, or a batch
+ * above 65535 beyond the LDS bound (MLMC_ERR_UNSUPPORTED); ldw or ldv < ld,
  * NULL buffers, workspace too small. */
 mlmc_status mlmc_batched_eigh(mlmc_dtype dtype, mlmc_precision prec, void *d_H, int64_t ld, const int64_t *d_offsets,
                               const int32_t *d_n, int64_t batch, double *d_w, int64_t ldw, void *d_V, int64_t ldv,

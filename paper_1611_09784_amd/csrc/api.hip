@@ -9,6 +9,7 @@
 #include <string>
 #include <vector>
 
+#include "eigh_large.hpp"
 #include "internal.hpp"
 
 using namespace mlmc;
@@ -705,14 +706,41 @@ mlmc_status mlmc_batched_eigvalsh(mlmc_dtype dtype, mlmc_precision prec, void *d
     return run_large(prec, d_H, ld, d_n, batch, d_w, ldw, b, s, false, false, d_offsets);
 }
 
+// Workspace of the banded eigenvector path (ld above the LDS-resident
+// bound): a copy of the matrices for stage 1, the two-stage buffers, every
+// panel's block reflector, the inverse iteration's LU factors.
+struct EighLargeBuffers {
+    EigBuffers b;
+    double *w = nullptr;  // the bisection's eigenvalues [batch][ld]
+    cpx<double> *keep = nullptr;
+    void *ii = nullptr;
+};
+static void carve_eigh_large(Carver &cv, int64_t ld, int64_t batch, EighLargeBuffers &L) {
+    carve_large(cv, MLMC_PREC_FP64, ld, batch, true, L.b);
+    L.w = cv.take<double>(sizeof(double) * (size_t)ld * (size_t)batch);
+    L.keep = cv.take<cpx<double>>(sizeof(cpx<double>) * (size_t)eigh_keep_elems(ld) * (size_t)batch);
+    L.ii = cv.take<void>(band_ii_scratch_bytes(ld, batch));
+}
+
 static mlmc_status eigh_workspace(mlmc_dtype dtype, mlmc_precision prec, int64_t ld, int64_t batch, size_t *bytes) {
     if (!bytes || ld < 0 || batch < 0) return fail(MLMC_ERR_INVALID_ARG, "eigh_workspace: bad argument");
     const mlmc_status st = check_dtype_prec(dtype, prec);
     if (st != MLMC_OK) return st;
-    if (ld > small_cap(prec))
-        return fail(MLMC_ERR_UNSUPPORTED, "batched_eigh: ld %lld exceeds the LDS-resident bound %d", (long long)ld,
-                    small_cap(prec));
-    *bytes = eigh_work_bytes(ld, batch);
+    if (ld <= small_cap(prec)) {
+        *bytes = eigh_work_bytes(ld, batch);
+        return MLMC_OK;
+    }
+    if (prec != MLMC_PREC_FP64)
+        return fail(MLMC_ERR_UNSUPPORTED, "batched_eigh: ld %lld above the LDS-resident bound %d needs complex128",
+                    (long long)ld, small_cap(prec));
+    if (ld > kEighLargeMax)
+        return fail(MLMC_ERR_UNSUPPORTED, "batched_eigh: ld %lld exceeds %d", (long long)ld, kEighLargeMax);
+    if (batch > 65535) return fail(MLMC_ERR_UNSUPPORTED, "batched_eigh: batch %lld above 65535 for ld > %d",
+                                   (long long)batch, small_cap(prec));
+    Carver cv{nullptr};
+    EighLargeBuffers L;
+    carve_eigh_large(cv, ld, batch, L);
+    *bytes = cv.used;
     return MLMC_OK;
 }
 
@@ -730,14 +758,34 @@ mlmc_status mlmc_batched_eigh(mlmc_dtype dtype, mlmc_precision prec, void *d_H, 
         return fail(MLMC_ERR_WORKSPACE, "batched_eigh: workspace %zu < %zu bytes", work_bytes, need);
     if (batch == 0 || ld == 0) return MLMC_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (prec == MLMC_PREC_FP64)
-        LAUNCH("eigh_small", s, launch_eigh_small<double>(static_cast<const cpx<double> *>(d_H), ld, d_offsets, d_n,
-                                                          batch, d_w, ldw, static_cast<cpx<double> *>(d_V), ldv,
-                                                          static_cast<double *>(d_work), s));
-    else
-        LAUNCH("eigh_small", s, launch_eigh_small<float>(static_cast<const cpx<float> *>(d_H), ld, d_offsets, d_n,
-                                                         batch, d_w, ldw, static_cast<cpx<float> *>(d_V), ldv,
-                                                         static_cast<double *>(d_work), s));
+    if (ld <= small_cap(prec)) {
+        if (prec == MLMC_PREC_FP64)
+            LAUNCH("eigh_small", s, launch_eigh_small<double>(static_cast<const cpx<double> *>(d_H), ld, d_offsets,
+                                                              d_n, batch, d_w, ldw, static_cast<cpx<double> *>(d_V),
+                                                              ldv, static_cast<double *>(d_work), s));
+        else
+            LAUNCH("eigh_small", s, launch_eigh_small<float>(static_cast<const cpx<float> *>(d_H), ld, d_offsets,
+                                                             d_n, batch, d_w, ldw, static_cast<cpx<float> *>(d_V),
+                                                             ldv, static_cast<double *>(d_work), s));
+        return MLMC_OK;
+    }
+    Carver cv{static_cast<char *>(d_work)};
+    EighLargeBuffers L;
+    carve_eigh_large(cv, ld, batch, L);
+    cpx<double> *Hc = static_cast<cpx<double> *>(L.b.H);
+    const int64_t keep_stride = eigh_keep_elems(ld);
+    LAUNCH("eigh_gather", s,
+           launch_gather_matrices(static_cast<const cpx<double> *>(d_H), ld, d_offsets, d_n, batch, Hc, s));
+    LAUNCH("band_reduce", s, launch_band_reduce_keep<double>(Hc, ld, d_n, batch, static_cast<cpx<double> *>(L.b.partial),
+                                                             s, L.b.stride, nullptr, L.keep, keep_stride));
+    mlmc_status rs = run_chase(prec, Hc, ld, d_n, batch, L.b, s);
+    if (rs != MLMC_OK) return rs;
+    rs = run_bisect(d_n, ld, batch, L.w, ld, L.b, s);
+    if (rs != MLMC_OK) return rs;
+    LAUNCH("eigh_band_ii", s, launch_band_inverse_iteration(Hc, ld, d_n, batch, L.w, d_w, ldw,
+                                                            static_cast<cpx<double> *>(d_V), ldv, L.ii, s));
+    LAUNCH("eigh_backtransform", s, launch_panel_backtransform(L.keep, keep_stride, ld, d_n, batch,
+                                                               static_cast<cpx<double> *>(d_V), ldv, s));
     return MLMC_OK;
 }
 

@@ -20,6 +20,7 @@
 // column as in a one-stage reduction.
 #include <algorithm>
 
+#include "eigh_large.hpp"
 #include "twostage_common.hpp"
 
 namespace mlmc {
@@ -1145,9 +1146,47 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
     }
 }
 
+// Panel p's V [16][ld] and T [16][16] of every matrix into its reflector
+// store (slot p / 16); matrices whose panel has no reflectors (fewer than two
+// rows below the band) are skipped, as the panel kernels skip them.
+template <typename T>
+__global__ __launch_bounds__(256) void keep_panel_kernel(const int32_t *__restrict__ n_in, int64_t ld,
+                                                         const cpx<T> *__restrict__ wall, int64_t stride, int p,
+                                                         cpx<T> *__restrict__ keep, int64_t keep_stride) {
+    const int64_t u = blockIdx.x;
+    const int n = n_in[u];
+    const int s = p + kB, m = n - s;
+    if (n < 0 || n > ld || m < 2) return;
+    const TwoView<T> w(const_cast<cpx<T> *>(wall), stride, ld, u);
+    cpx<T> *kp = keep + u * keep_stride + (int64_t)(p / kB) * (kB * ld + kB * kB);
+    for (int64_t idx = threadIdx.x; idx < (int64_t)kB * m; idx += 256) {
+        const int c = (int)(idx / m), r = s + (int)(idx % m);
+        kp[(int64_t)c * ld + r] = w.V[(int64_t)c * ld + r];
+    }
+    for (int idx = threadIdx.x; idx < kB * kB; idx += 256) kp[(int64_t)kB * ld + idx] = w.Tm[idx];
+}
+
+template <typename T>
+hipError_t band_reduce_impl(cpx<T> *H, int64_t ld, const int32_t *n_in, int64_t batch, cpx<T> *work, hipStream_t s,
+                            int64_t stride, const int64_t *offs, int upd_rows, cpx<T> *keep, int64_t keep_stride);
+
 template <typename T>
 hipError_t launch_band_reduce(cpx<T> *H, int64_t ld, const int32_t *n_in, int64_t batch, cpx<T> *work,
                               hipStream_t s, int64_t stride, const int64_t *offs, int upd_rows) {
+    return band_reduce_impl<T>(H, ld, n_in, batch, work, s, stride, offs, upd_rows, nullptr, 0);
+}
+
+template <typename T>
+hipError_t launch_band_reduce_keep(cpx<T> *H, int64_t ld, const int32_t *n_in, int64_t batch, cpx<T> *work,
+                                   hipStream_t s, int64_t stride, const int64_t *offs, cpx<T> *keep,
+                                   int64_t keep_stride) {
+    if (!keep || keep_stride < eigh_keep_elems(ld)) return hipErrorInvalidValue;
+    return band_reduce_impl<T>(H, ld, n_in, batch, work, s, stride, offs, 32, keep, keep_stride);
+}
+
+template <typename T>
+hipError_t band_reduce_impl(cpx<T> *H, int64_t ld, const int32_t *n_in, int64_t batch, cpx<T> *work, hipStream_t s,
+                            int64_t stride, const int64_t *offs, int upd_rows, cpx<T> *keep, int64_t keep_stride) {
     if (upd_rows != 32 && upd_rows != 64) return hipErrorInvalidValue;
     if (batch == 0) return hipSuccess;
     if (stride == 0) stride = (int64_t)tridiag_twostage_work_elems<T>(ld);
@@ -1189,6 +1228,12 @@ hipError_t launch_band_reduce(cpx<T> *H, int64_t ld, const int32_t *n_in, int64_
             return hipGetLastError();
         });
         if (err != hipSuccess) return err;
+        if (keep) {
+            hipLaunchKernelGGL(keep_panel_kernel<T>, dim3(B), dim3(256), 0, s, n_in, ld, work, stride, p, keep,
+                               keep_stride);
+            err = hipGetLastError();
+            if (err != hipSuccess) return err;
+        }
         // Row tiles per wavefront: four, unless the batch gives fewer than
         // four wavefronts per SIMD that way (a small batch of large matrices).
         const int64_t waves4 = (int64_t)kXcds * ((batch + kXcds - 1) / kXcds) * ((mmax + 63) / 64);
@@ -1258,6 +1303,9 @@ template hipError_t launch_rank2k_update<float>(cpx<float> *, int64_t, const int
                                                 int64_t, int, int, hipStream_t);
 template size_t tridiag_twostage_work_elems<double>(int64_t);
 template size_t tridiag_twostage_work_elems<float>(int64_t);
+template hipError_t launch_band_reduce_keep<double>(cpx<double> *, int64_t, const int32_t *, int64_t,
+                                                    cpx<double> *, hipStream_t, int64_t, const int64_t *,
+                                                    cpx<double> *, int64_t);
 template hipError_t launch_band_reduce<double>(cpx<double> *, int64_t, const int32_t *, int64_t, cpx<double> *,
                                                hipStream_t, int64_t, const int64_t *, int);
 template hipError_t launch_band_reduce<float>(cpx<float> *, int64_t, const int32_t *, int64_t, cpx<float> *,

@@ -1,0 +1,66 @@
+// Eigenvectors of matrices above the LDS-resident size (complex128): stage 1
+// keeps each panel's block reflector (V_p, T_p), inverse iteration runs on
+// the band matrix of half-width kB that stage 1 leaves in the lower triangle
+// of H, and the band's eigenvectors go back through the kept reflectors.
+#pragma once
+#include <algorithm>
+
+#include "twostage_common.hpp"
+
+namespace mlmc {
+
+// Largest side of the banded eigenvector path.
+constexpr int kEighLargeMax = 4096;
+
+// Elements of one matrix's reflector store: per panel V_p [kB][ld] (rows
+// below the panel's band; the rest untouched) and T_p [kB][kB] row-major.
+inline int64_t eigh_keep_elems(int64_t ld) { return ((ld + kB - 1) / kB) * (kB * ld + kB * kB); }
+
+// Stage 1 as launch_band_reduce (32-row update tiles) that also copies every
+// panel's V_p, T_p into keep + u * keep_stride (keep_stride >= eigh_keep_elems(ld)).
+template <typename T>
+hipError_t launch_band_reduce_keep(cpx<T> *H, int64_t ld, const int32_t *n_in, int64_t batch, cpx<T> *work,
+                                   hipStream_t s, int64_t stride, const int64_t *offs, cpx<T> *keep, int64_t keep_stride);
+
+// Inverse iteration: one wavefront per cluster, its LU factors in a slice of
+// device scratch of band_ii_wave_bytes(ld).
+// Scratch: U rows of 2 kB + 1 entries, kB multipliers and a pivot index per
+// elimination step, for ld + kIIStep steps (whole blocks of kIIStep).  LDS:
+// the (kB + 1) x (2 kB + 1) elimination window, kB multipliers, kIIStep
+// steps of incoming band rows and of outgoing factors, the iterated vector.
+constexpr int kIIStep = 8;
+inline int64_t band_ii_wave_bytes(int64_t ld) {
+    return ((ld + kIIStep) * ((3 * kB + 1) * 16 + 4) + 255) / 256 * 256;
+}
+inline int64_t band_ii_lds_bytes(int64_t ld) {
+    return 16 * ((kB + 1) * (2 * kB + 1) + kB + kIIStep * (2 * (2 * kB + 1) + kB) + ld) + 4 * kIIStep;
+}
+// Wavefronts of one launch: what the CUs hold at once (LDS-bound, at most
+// four per SIMD), and no more than the eigenvalues of the batch.
+inline int64_t band_ii_waves(int64_t ld, int64_t batch) {
+    const int64_t per_cu = std::min<int64_t>(16, (160 * 1024) / band_ii_lds_bytes(ld));
+    return std::max<int64_t>(1, std::min<int64_t>(256 * per_cu, batch * ld));
+}
+inline size_t band_ii_scratch_bytes(int64_t ld, int64_t batch) {
+    return (size_t)band_ii_waves(ld, batch) * (size_t)band_ii_wave_bytes(ld);
+}
+
+// Matrix u's leading ld x n_u block (offs: element offsets, NULL: u ld^2) to
+// dst + u ld^2.
+hipError_t launch_gather_matrices(const cpx<double> *H, int64_t ld, const int64_t *offs, const int32_t *n_in,
+                                  int64_t batch, cpx<double> *dst, hipStream_t s);
+
+// Columns 0..n_u-1 of V_u (column-major, ldv, matrix u at u ldv^2): unit
+// eigenvectors of the band matrix in H (matrix u at u ld^2) for the ascending
+// eigenvalues w_in[u ld + i]; w_out[u ldw + i]: their Rayleigh quotients,
+// ascending (NaN for i < ld when n_u is outside [0, ld]).
+hipError_t launch_band_inverse_iteration(const cpx<double> *H, int64_t ld, const int32_t *n_in, int64_t batch,
+                                         const double *w_in, double *w_out, int64_t ldw, cpx<double> *V, int64_t ldv,
+                                         void *scratch, hipStream_t s);
+
+// V_u <- Q_u V_u, Q_u = (I - V_0 T_0 V_0^H) ... (I - V_P T_P V_P^H) from the
+// reflector store.
+hipError_t launch_panel_backtransform(const cpx<double> *keep, int64_t keep_stride, int64_t ld, const int32_t *n_in,
+                                      int64_t batch, cpx<double> *V, int64_t ldv, hipStream_t s);
+
+}  // namespace mlmc

@@ -135,8 +135,9 @@ def test_generalized_workspace_limits(B):
 
 
 def test_eigh_workspace_and_limits(B):
-    """The eigenstates call: LDS-resident sides only, workspace 7 ld^2
-    doubles per matrix, argument errors before any launch."""
+    """The eigenstates call: workspace 7 ld^2 doubles per LDS-resident
+    matrix, the banded path's sizes and bounds above that, argument errors
+    before any launch."""
     out = C.c_size_t()
     lib = B.lib()
 
@@ -148,7 +149,15 @@ def test_eigh_workspace_and_limits(B):
     assert out.value == 3 * 7 * 128 * 128 * 8
     assert ws(B.MLMC_C64, B.MLMC_PREC_MIXED, 180, 2) == B.MLMC_OK
     assert out.value == 2 * 7 * 180 * 180 * 8
-    assert ws(B.MLMC_C128, B.MLMC_PREC_FP64, 129, 1) == B.MLMC_ERR_UNSUPPORTED
+    # above the LDS bound: complex128 only, up to 4096, with a copy of the
+    # matrices and every panel's block reflector (16 ld + 256 elements per
+    # 16 columns) in the workspace
+    for ld, batch in ((129, 1), (2048, 3), (4096, 1)):
+        assert ws(B.MLMC_C128, B.MLMC_PREC_FP64, ld, batch) == B.MLMC_OK
+        keep = -(-ld // 16) * (16 * ld + 256)
+        assert out.value >= batch * 16 * (ld * ld + keep)
+    assert ws(B.MLMC_C128, B.MLMC_PREC_FP64, 4097, 1) == B.MLMC_ERR_UNSUPPORTED
+    assert ws(B.MLMC_C128, B.MLMC_PREC_FP64, 129, 65536) == B.MLMC_ERR_UNSUPPORTED
     assert ws(B.MLMC_C64, B.MLMC_PREC_MIXED, 181, 1) == B.MLMC_ERR_UNSUPPORTED
     assert ws(B.MLMC_C64, B.MLMC_PREC_FP64, 64, 1) == B.MLMC_ERR_UNSUPPORTED
     assert B.mlmc_eigh_workspace(B.MLMC_C128, B.MLMC_PREC_FP64, 0, 5) == 0

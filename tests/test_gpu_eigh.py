@@ -70,8 +70,9 @@ def groups(w, tol):
     return out
 
 
-def check_eigh(A, w, V, prec, label):
-    """One matrix: eigenvalues, residuals, orthonormality, projectors."""
+def check_eigh(A, w, V, prec, label, projectors=True):
+    """One matrix: eigenvalues, residuals, orthonormality, projectors (those
+    only with `projectors`: they cost n^3 per group)."""
     m = A.shape[0]
     if m == 0:
         return
@@ -87,6 +88,8 @@ def check_eigh(A, w, V, prec, label):
     say(f"  {label}: n={m} res/(n eps |H|)={res / (m * eps * hn):.3f} orth/(n eps)={orth / (m * eps):.3f}")
     assert res <= 16 * m * eps * hn, f"{label}: residual {res:.3e}"
     assert orth <= 16 * m * eps, f"{label}: orthonormality {orth:.3e}"
+    if not projectors:
+        return
     worst = 0.0
     for a, b in groups(wo, 1e-6 * hn):
         if b - a == m:
@@ -101,7 +104,7 @@ def check_eigh(A, w, V, prec, label):
     say(f"  {label}: worst projector error / bound = {worst:.3f}")
 
 
-def run_and_check(B, Hs, sizes, prec, label):
+def run_and_check(B, Hs, sizes, prec, label, projectors=True):
     """Hs: [batch][ld][ld] column-major complex128 (lower triangles used)."""
     n = torch.as_tensor(np.array(sizes, np.int32), device=DEV)
     dt = torch.complex128 if prec == 0 else torch.complex64
@@ -115,7 +118,7 @@ def run_and_check(B, Hs, sizes, prec, label):
     for u, m in enumerate(sizes):
         A = full_from_lower(Hin[u], m)
         Vu = Vc[u][:m, :m].T.astype(np.complex128)  # column i = eigenvector i
-        check_eigh(A, wc[u, :m], Vu, prec, f"{label}[{u}]")
+        check_eigh(A, wc[u, :m], Vu, prec, f"{label}[{u}]", projectors)
     return w, V
 
 
@@ -231,10 +234,96 @@ def test_eigh_ragged_offsets_bit_exact(B):
 
 
 def test_eigh_errors(B):
+    """Above the LDS bound only complex128 runs (banded path), up to 4096."""
     say("[eigh errors]")
-    for prec, cap in ((0, 128), (1, 180)):
+    for prec, cap in ((0, 4096), (1, 180)):
         dt = torch.complex128 if prec == 0 else torch.complex64
         H = torch.zeros((1, cap + 1, cap + 1), dtype=dt, device=DEV)
         n = torch.ones((1,), dtype=torch.int32, device=DEV)
         with pytest.raises(RuntimeError):
             B.mlmc_batched_eigh(H, n)
+
+
+# Above 128 (complex128) the banded path runs: stage 1 to half-bandwidth 16
+# with each panel's reflector kept, chase + bisection for the eigenvalues,
+# inverse iteration on the band, back-transformation through the panels.
+# Sides 17 and 18 give no panel and a panel of one reflector.
+
+@pytest.mark.parametrize("ld,sizes", [(300, [300, 257, 129, 1, 0]), (160, [160, 17, 18, 33, 2])])
+def test_eigh_large_random(B, ld, sizes):
+    say(f"[eigh large random] ld={ld} sizes={sizes}")
+    rng = np.random.default_rng(5000 + ld)
+    Hs = np.zeros((len(sizes), ld, ld), np.complex128)
+    for u, m in enumerate(sizes):
+        A = rng.normal(size=(m, m)) + 1j * rng.normal(size=(m, m))
+        Hs[u, :m, :m] = (A + A.conj().T).T
+    run_and_check(B, Hs, sizes, 0, "large-random")
+
+
+def test_eigh_large_clustered(B):
+    say("[eigh large clustered]")
+    rng = np.random.default_rng(91)
+    ld, sizes = 256, [256, 200]
+    Hs = np.zeros((len(sizes), ld, ld), np.complex128)
+    for u, m in enumerate(sizes):
+        lam = clustered_spectrum(m, rng)
+        Q, _ = np.linalg.qr(rng.normal(size=(m, m)) + 1j * rng.normal(size=(m, m)))
+        A = (Q * lam) @ Q.conj().T
+        Hs[u, :m, :m] = (0.5 * (A + A.conj().T)).T
+    run_and_check(B, Hs, sizes, 0, "large-clustered")
+
+
+@pytest.mark.parametrize("name,N,p,K", [("graphene", 16, 0.05, 1), ("graphene", 12, 0.1, 2), ("mos2", 5, 0.1, 1)])
+def test_eigh_large_hamiltonians(B, devs, name, N, p, K):
+    """H(k) with vacancies above the LDS bound: zero modes, the degeneracies
+    of the Gamma point (K = 1) and of a 2 x 2 grid."""
+    say(f"[eigh large H(k)] {name} N={N} p={p} K={K}")
+    dl = devs[name]
+    mask = B.mlmc_sample_vacancies(dl, N, p, 57, dl.tag(N), 0, 1)
+    kred, _ = B.mlmc_kgrid(1, K)
+    H, n = B.mlmc_build_hamiltonians(dl, N, mask, kred, B.MLMC_C128)
+    run_and_check(B, H.cpu().numpy(), [int(x) for x in n.cpu().numpy()], 0, f"{name}N{N}")
+
+
+def test_eigh_large_n2000(B, devs):
+    """Graphene N = 32 at Gamma (n ~ 2000, the blocked panel kernels of stage 1):
+    eigenvalues, residuals and orthonormality against the oracle."""
+    say("[eigh large n~2000] graphene N=32")
+    dl = devs["graphene"]
+    mask = B.mlmc_sample_vacancies(dl, 32, 0.05, 58, dl.tag(32), 0, 1)
+    kred, _ = B.mlmc_kgrid(1, 1)
+    H, n = B.mlmc_build_hamiltonians(dl, 32, mask, kred, B.MLMC_C128)
+    run_and_check(B, H.cpu().numpy(), [int(x) for x in n.cpu().numpy()], 0, "grapheneN32", projectors=False)
+
+
+def test_eigh_large_ragged_offsets_bit_exact(B):
+    """The banded path at caller offsets gives the fixed-stride results bit for
+    bit, and two calls agree bit for bit."""
+    say("[eigh large ragged offsets]")
+    rng = np.random.default_rng(4343)
+    ld, sizes = 200, [200, 150, 0, 170]
+    Hs = np.zeros((len(sizes), ld, ld), np.complex128)
+    for u, m in enumerate(sizes):
+        A = rng.normal(size=(m, m)) + 1j * rng.normal(size=(m, m))
+        Hs[u, :m, :m] = (A + A.conj().T).T
+    n = torch.as_tensor(np.array(sizes, np.int32), device=DEV)
+    H = torch.as_tensor(Hs, device=DEV)
+    w1, V1 = B.mlmc_batched_eigh(H, n)
+    w2, V2 = B.mlmc_batched_eigh(H, n)
+    assert torch.equal(w1, w2) and torch.equal(V1, V2)
+    offs, at = [0] * len(sizes), 0
+    for u in reversed(range(len(sizes))):
+        at += 5 * ld
+        offs[u] = at
+        at += ld * sizes[u]
+    buf = torch.zeros((at + ld,), dtype=torch.complex128, device=DEV)
+    for u, m in enumerate(sizes):
+        buf[offs[u]:offs[u] + ld * m] = H[u, :m, :].reshape(-1)
+    off_t = torch.as_tensor(np.array(offs, np.int64), device=DEV)
+    w3, V3 = B.mlmc_batched_eigh(buf, n, offsets=off_t, ld=ld)
+    for u, m in enumerate(sizes):
+        assert torch.equal(w3[u, :m], w1[u, :m])
+        assert torch.equal(V3[u, :m, :m], V1[u, :m, :m])
+    bad = torch.as_tensor(np.array([3, ld + 1], np.int32), device=DEV)
+    w4, _ = B.mlmc_batched_eigh(H[:2].clone(), bad)
+    assert torch.isnan(w4[1]).all() and not torch.isnan(w4[0, :3]).any()
