@@ -236,7 +236,8 @@ mlmc_status mlmc_build_overlaps(mlmc_lattice lat, int32_t N, const uint8_t *d_ma
  *     eigenvectors and the inverse iteration's scratch).  Larger complex128
  *     sides: a copy of each matrix, the two-stage buffers, every panel's
  *     block reflector (16*ld + 256 complex per 16 columns) and the band
- *     inverse iteration's LU factors (about 788*ld bytes per wavefront).
+ *     inverse iteration's LU factors and vector (about 804*ld bytes per
+ *     wavefront).
  * Errors: NULL arguments, unknown op, the operation's own argument checks
  * (MLMC_ERR_UNSUPPORTED for sizes beyond the library's limits). */
 mlmc_status mlmc_workspace_bytes(const mlmc_workspace_request *req, size_t *bytes);
@@ -294,11 +295,12 @@ mlmc_status mlmc_batched_eigvalsh_noalloc(mlmc_dtype dtype, mlmc_precision prec,
  * panel's block reflector I - V_p T_p V_p^H kept), the band is chased to
  * tridiagonal form and bisected for the eigenvalues, eigenvectors of the band
  * matrix B come from inverse iteration with a pivoted band LU of B - lam I
- * (one wavefront per cluster), and the block reflectors take them back,
+ * (one wavefront per eigenvalue), and the block reflectors take them back,
  * last panel first.
  * Both paths: eigenvalues closer than 1e-3 of the spectral radius form a
- * cluster whose vectors are orthogonalised against each other after every
- * solve; the eigenvalues are refined to the vectors' Rayleigh quotients
+ * cluster whose vectors are orthogonalised against each other (after every
+ * solve on the LDS path; once, by Gram-Schmidt applied twice, on the banded
+ * path); the eigenvalues are refined to the vectors' Rayleigh quotients
  * (ascending, a cluster's columns sorted with them).
  * d_H, d_offsets, d_n, d_w, ldw: as mlmc_batched_eigvalsh, except that the
  * matrices are left unchanged (only the lower triangles are read).  d_V: the
@@ -310,8 +312,8 @@ mlmc_status mlmc_batched_eigvalsh_noalloc(mlmc_dtype dtype, mlmc_precision prec,
  * ||H|| in the compute type (complex128 or complex64), columns orthonormal
  * to the same order.  d_work: mlmc_workspace_bytes(MLMC_OP_BATCHED_EIGH)
  * (7 ld^2 doubles per LDS-resident matrix; above that about 2 ld^2 complex
- * per matrix and the inverse iteration's factors, ld * 788 bytes per
- * wavefront in flight).
+ * per matrix and the inverse iteration's factors and vector, about
+ * ld * 804 bytes per wavefront in flight).
  * Errors: ld above 4096, or above the LDS bound in complex64, or a batch
  * above 65535 beyond the LDS bound (MLMC_ERR_UNSUPPORTED); ldw or ldv < ld,
  * NULL buffers, workspace too small. */

@@ -2,10 +2,10 @@
 // stage 1 (dense -> band of half-width kB, each panel's block reflector kept)
 // and the eigenvalues (chase + bisection), the eigenvectors are
 //   band_ii_kernel   inverse iteration on the band matrix B, one wavefront
-//                    per cluster of close eigenvalues: pivoted band LU of
-//                    B - lam I, three solves from a hashed start vector,
-//                    each followed by orthogonalisation against the
-//                    cluster's earlier vectors
+//                    per eigenvalue: pivoted band LU of B - lam I, two
+//                    solves from a hashed start vector
+//   cluster_orth_kernel  the vectors of each cluster of close eigenvalues
+//                    orthonormalised, their Rayleigh quotients, sorted
 //   panel_bt_kernel  X <- (I - V_p T_p V_p^H) X for the panels from last to
 //                    first, which takes B's eigenvectors to H's
 // The chase's rotations are not needed: B's own eigenvectors are computed.
@@ -22,6 +22,10 @@ constexpr int kWC = 2 * kB + 1;      // its columns (U has 2 kB superdiagonals a
 constexpr int kSt = kIIStep;         // steps per staged block
 constexpr int kRowPer = (kSt * kWC + 63) / 64;
 constexpr int kLPer = (kSt * kB + 63) / 64;
+// Solves per eigenvalue: the shift is within the bisection's 1e-12 of the
+// eigenvalue, so each solve shrinks the other eigenvectors' share by their
+// distance over 1e-12 (the members of a cluster mix, and are orthogonalised).
+constexpr int kIISolves = 2;
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
 
@@ -76,33 +80,40 @@ __device__ __forceinline__ double start_value(int k, int r, int part) {
 //   U[k kWC + j] = U(k, k + j) for 1 <= j <= 2 kB, U[k kWC] = 1 / U(k, k)
 //   L[k kB + i]  = multiplier of row k + 1 + i at elimination step k
 //   piv[k]       = the row swapped with row k at step k
+//   y[r]         = the iterated vector
 struct IIFactors {
-    cpx<double> *U, *L;
+    cpx<double> *U, *L, *y;
     int *piv;
     __device__ IIFactors(char *base, int64_t ld) {
         U = reinterpret_cast<cpx<double> *>(base);
         L = U + (ld + kSt) * kWC;
-        piv = reinterpret_cast<int *>(L + (ld + kSt) * kB);
+        y = L + (ld + kSt) * kB;
+        piv = reinterpret_cast<int *>(y + ld);
     }
 };
 
+// LDS of a wavefront: the elimination window, kSt steps of incoming band rows
+// (or of U's columns in the backward solve), of outgoing U rows and
+// multipliers (or of the forward solve's multipliers), the pivots, and a ring
+// of kIIYRing entries of the iterated vector around the solves' current row.
+constexpr int kYR = kIIYRing;
 struct IILds {
-    cpx<double> *win, *lbuf, *rows, *outU, *outL, *y;
+    cpx<double> *win, *rows, *outU, *outL, *yr;
     int *outP;
-    __device__ IILds(unsigned char *base, int64_t ld) {
+    __device__ IILds(unsigned char *base) {
         win = reinterpret_cast<cpx<double> *>(base);
-        lbuf = win + kWR * kWC;
-        rows = lbuf + kB;
+        rows = win + kWR * kWC;
         outU = rows + kSt * kWC;
         outL = outU + kSt * kWC;
-        y = outL + kSt * kB;
-        outP = reinterpret_cast<int *>(y + ld);
+        yr = outL + kSt * kB;
+        outP = reinterpret_cast<int *>(yr + kYR);
     }
 };
 
-// Window slot of (row r, column c): the window holds rows k .. k + kB and
-// columns k .. k + 2 kB at elimination step k.
-__device__ __forceinline__ int wat(int r, int c) { return (r % kWR) * kWC + (c % kWC); }
+// The elimination window is a ring: at step k it holds rows k .. k + kB
+// (row r in slot r mod (kB + 1)) and columns k .. k + 2 kB (column c in slot
+// c mod (2 kB + 1)), the rows' slots in that order except that the pivot
+// search reorders them (see band_lu).
 
 // B[r][c] - lam delta_rc of the band matrix of half-width kB whose lower
 // triangle stage 1 left in H (column-major, ld); zero outside the band and
@@ -158,18 +169,23 @@ __device__ __forceinline__ void flush_factors(const IILds &sm, const IIFactors &
 // Step k takes the largest entry of column k in rows k .. k + kB as the pivot
 // (its magnitude compared in single precision; equals go to the upper row),
 // records U's row k and the multipliers, eliminates, and slides the window
-// down and right by one.  The steps touch LDS only: the band rows they slide
-// in are fetched a block ahead, and their factors go out a block behind.
+// down and right by one.  The swap of rows k and p is implicit: row k's slot
+// leaves the window, and p's slot takes row k's eliminated entries.  A step
+// reads everything that does not depend on the pivot at once, then the pivot
+// row, and touches LDS only: the band rows it slides in are fetched a block
+// ahead, and its factors go out a block behind.
 __device__ __forceinline__ void band_lu(const cpx<double> *H, int64_t ld, int n, double lam, double tiny, const IILds &sm,
-                        const IIFactors &f) {
+                                        const IIFactors &f) {
     static_assert(kSt * kB == 64 * kLPer, "whole multiplier blocks");
     const int lane = lane_id();
+    const int cc = 1 + (lane & 31), rh = lane >> 5;  // this lane: column k + cc, rows k + 1 + rh + 2q
     for (int idx = lane; idx < kWR * kWC; idx += 64) {
         const int r = idx / kWC, c = idx % kWC;
-        sm.win[wat(r, c)] = band_ld(H, ld, n, r, c, lam);
+        st2(sm.win + r * kWC + c, band_ld(H, ld, n, r, c, lam));
     }
     cpx<double> pre[kRowPer];
     fetch_rows(H, ld, n, lam, 0, pre);
+    int ks = 0, kc = 0;  // window slots of row k and column k
     for (int k0 = 0; k0 < n; k0 += kSt) {
         wave_lds_sync();
         if (k0 > 0) flush_factors(sm, f, k0 - kSt);
@@ -181,49 +197,66 @@ __device__ __forceinline__ void band_lu(const cpx<double> *H, int64_t ld, int n,
         const int k1 = min(k0 + kSt, n);
         for (int k = k0; k < k1; ++k) {
             const int i = k - k0;
-            int key = 0;
-            if (lane < kWR && k + lane < n)
-                key = (int)((__float_as_uint((float)c_abs2(sm.win[wat(k + lane, k)])) & ~31u) | (uint32_t)(31 - lane));
-            const int p = k + 31 - (max_key32(key) & 31);
-            if (p != k && lane < kWC) {
-                const int c = k + lane;
-                const cpx<double> a = ld2(sm.win + wat(k, c)), b = ld2(sm.win + wat(p, c));
-                st2(sm.win + wat(k, c), b);
-                st2(sm.win + wat(p, c), a);
+            const int csl = kc + cc >= kWC ? kc + cc - kWC : kc + cc;
+            cpx<double> colk[kB / 2], xr[kB / 2];
+            int rsl[kB / 2];
+#pragma unroll
+            for (int q = 0; q < kB / 2; ++q) {
+                const int rr = 1 + rh + 2 * q;
+                rsl[q] = ks + rr >= kWR ? ks + rr - kWR : ks + rr;
+                colk[q] = ld2(sm.win + rsl[q] * kWC + kc);
+                xr[q] = ld2(sm.win + rsl[q] * kWC + csl);
             }
-            wave_lds_sync();
-            cpx<double> piv = sm.win[wat(k, k)];
+            const cpx<double> rowk = ld2(sm.win + ks * kWC + csl), dkk = ld2(sm.win + ks * kWC + kc);
+            const cpx<double> inrow = ld2(sm.rows + i * kWC + (lane < kWC ? lane : 0));
+            const int ml = lane & (kB - 1);  // lane < kB: the multiplier of row k + 1 + ml
+            const int mls = ks + 1 + ml >= kWR ? ks + 1 + ml - kWR : ks + 1 + ml;
+            const cpx<double> colm = ld2(sm.win + mls * kWC + kc);
+            int key = 0;
+            if (lane < kWR && k + lane < n) {
+                const int sl = ks + lane >= kWR ? ks + lane - kWR : ks + lane;
+                key = (int)((__float_as_uint((float)c_abs2(ld2(sm.win + sl * kWC + kc))) & ~31u) |
+                            (uint32_t)(31 - lane));
+            }
+            const int pr = 31 - (max_key32(key) & 31);  // the pivot row is k + pr
+            const int psl = ks + pr >= kWR ? ks + pr - kWR : ks + pr;
+            cpx<double> piv = ld2(sm.win + psl * kWC + kc);
+            const cpx<double> rowp = ld2(sm.win + psl * kWC + csl);
             double a2 = c_abs2(piv);
             if (!(a2 >= tiny * tiny)) {  // singular to working precision: lam is an eigenvalue
                 piv = {tiny, 0.0};
                 a2 = tiny * tiny;
             }
             const cpx<double> rp = {piv.re / a2, -piv.im / a2};
-            if (lane < kB) {
-                const int r = k + 1 + lane;
-                const cpx<double> l = csel(r < n, c_mul(sm.win[wat(r, k)], rp), cpx<double>{0.0, 0.0});
-                sm.lbuf[lane] = l;
-                sm.outL[i * kB + lane] = l;
-            }
-            if (lane == 0) sm.outP[i] = p;
-            if (lane < kWC) sm.outU[i * kWC + lane] = csel(lane == 0, rp, sm.win[wat(k, k + lane)]);
-            wave_lds_sync();
-            {  // rows k + 1 .. k + kB -= l * row k over columns k + 1 .. k + 2 kB
-                const int cc = 1 + (lane & 31);
-                const cpx<double> urow = sm.win[wat(k, k + cc)];
+            // rows k + 1 .. k + kB -= l * (pivot row) over columns k + 1 .. k + 2 kB; the
+            // row in p's slot stands for row k from here on, so its entries are
+            // rewritten from row k's after the loop (the loop leaves zeros there)
 #pragma unroll
-                for (int q = 0; q < kB / 2; ++q) {
-                    const int rr = 1 + (lane >> 5) + 2 * q;
-                    const cpx<double> l = sm.lbuf[rr - 1];
-                    const int at = wat(k + rr, k + cc);
-                    sm.win[at] = c_sub(sm.win[at], c_mul(l, urow));
-                }
+            for (int q = 0; q < kB / 2; ++q) {
+                const cpx<double> l = c_mul(colk[q], rp);
+                st2(sm.win + rsl[q] * kWC + csl, c_sub(xr[q], c_mul(l, rowp)));
             }
-            wave_lds_sync();
+            const cpx<double> lk = c_mul(dkk, rp);
+            if (pr > 0 && rh == ((pr - 1) & 1)) st2(sm.win + psl * kWC + csl, c_sub(rowk, c_mul(lk, rowp)));
+            if (lane < kB) st2(sm.outL + i * kB + ml, c_mul(csel(ml + 1 == pr, dkk, colm), rp));
+            if (lane < 2 * kB) st2(sm.outU + i * kWC + 1 + lane, rowp);
+            if (lane == 0) {
+                st2(sm.outU + i * kWC, rp);
+                sm.outP[i] = k + pr;
+            }
             // row k's slot takes row k + kB + 1 (columns k + 1 .. k + 2 kB + 1); column
             // k's slot becomes column k + 2 kB + 1, zero in rows k + 1 .. k + kB
-            if (lane < kWC) sm.win[wat(k + kWR, k + 1 + lane)] = sm.rows[i * kWC + lane];
-            if (lane < kB) sm.win[wat(k + 1 + lane, k + kWC)] = {0.0, 0.0};
+            if (lane < kWC) {
+                const int c = kc + 1 + lane;
+                st2(sm.win + ks * kWC + (c >= kWC ? c - kWC : c), inrow);
+            }
+            if (lane < kB) {
+                const int sl = ks + 1 + lane;
+                st2(sm.win + (sl >= kWR ? sl - kWR : sl) * kWC + kc, cpx<double>{0.0, 0.0});
+            }
+            ks = ks + 1 == kWR ? 0 : ks + 1;
+            kc = kc + 1 == kWC ? 0 : kc + 1;
+            __builtin_amdgcn_wave_barrier();  // the wavefront's LDS operations complete in order
         }
     }
     wave_lds_sync();
@@ -251,60 +284,119 @@ __device__ __forceinline__ void fetch_u(const IIFactors &f, int n, int lo, cpx<d
     }
 }
 
-// y <- (B - lam I)^{-1} y from the factors (y in LDS); the factors of a block
-// of kSt steps are fetched while the previous block is applied.
-__device__ __forceinline__ void band_solve(int n, const IILds &sm, const IIFactors &f) {
-    const int lane = lane_id();
-    // forward: y <- L^{-1} P y; step k swaps y[k] with y[piv[k]] and updates rows k + 1 .. k + kB
+// Entry j of the vector entering a forward solve, times `scale` (zero at and
+// beyond n; the load is unconditional, from entry 0 there).
+__device__ __forceinline__ cpx<double> y_in(const cpx<double> *yb, int n, int j, double scale) {
+    const cpx<double> v = ld2(yb + (j < n ? j : 0));
+    const double g = j < n ? scale : 0.0;
+    return {v.re * g, v.im * g};
+}
+
+// y <- L^{-1} P (scale y), in place in the scratch vector.  Step k swaps y[k]
+// with y[piv[k]] and updates rows k + 1 .. k + kB, in an LDS ring that holds
+// y[k0 .. k0 + kSt + kB - 1] at the start of block k0: each block's entering
+// entries are fetched a block ahead, its finished entries written a block
+// behind, and its multipliers and pivots fetched a block ahead.
+__device__ __forceinline__ void solve_forward(int n, const IILds &sm, const IIFactors &f, double scale) {
+    const int lane = lane_id(), l8 = lane & (kSt - 1);
+    cpx<double> *yr = sm.yr;
+    if (lane < kSt + kB) st2(yr + lane, y_in(f.y, n, lane, scale));
+    cpx<double> pre = y_in(f.y, n, kSt + kB + l8, scale);
     cpx<double> pl[kLPer];
     int pp;
     fetch_l(f, 0, pl, pp);
-    for (int k0 = 0; k0 < n - 1; k0 += kSt) {
+    int k0 = 0;
+    for (; k0 < n - 1; k0 += kSt) {
         wave_lds_sync();
 #pragma unroll
         for (int q = 0; q < kLPer; ++q) st2(sm.outL + lane + 64 * q, pl[q]);
-        if (lane < kSt) sm.outP[lane] = pp;
+        const int pblk = pp;  // lane i: the pivot of step k0 + i
         if (k0 + kSt < n - 1) fetch_l(f, k0 + kSt, pl, pp);
+        if (k0 > 0 && lane < kSt) {
+            st2(f.y + k0 - kSt + lane, ld2(yr + ((k0 - kSt + lane) & (kYR - 1))));
+            st2(yr + ((k0 + kB + lane) & (kYR - 1)), pre);
+            pre = y_in(f.y, n, k0 + kSt + kB + lane, scale);
+        }
         wave_lds_sync();
         const int k1 = min(k0 + kSt, n - 1);
         for (int k = k0; k < k1; ++k) {
-            const int p = sm.outP[k - k0];
-            const cpx<double> yk = sm.y[k], yp = sm.y[p];
+            const int p = __builtin_amdgcn_readlane(pblk, k - k0);
+            const cpx<double> yk = ld2(yr + (k & (kYR - 1))), yp = ld2(yr + (p & (kYR - 1)));
             if (lane < kB && k + 1 + lane < n) {
-                const int r = k + 1 + lane;
-                const cpx<double> x = csel(r == p, yk, sm.y[r]);
-                sm.y[r] = c_sub(x, c_mul(sm.outL[(k - k0) * kB + lane], yp));
+                const int r = (k + 1 + lane) & (kYR - 1);
+                const cpx<double> x = csel(k + 1 + lane == p, yk, ld2(yr + r));
+                st2(yr + r, c_sub(x, c_mul(ld2(sm.outL + (k - k0) * kB + lane), yp)));
             }
-            if (lane == 0) sm.y[k] = yp;
-            wave_lds_sync();
+            if (lane == 0) st2(yr + (k & (kYR - 1)), yp);
+            __builtin_amdgcn_wave_barrier();
         }
     }
-    // backward, by columns: y[c] <- y[c] / U(c, c), then rows c - 2 kB .. c - 1 -= U(., c) y[c];
-    // a block holds columns lo .. lo + kSt - 1, entry (c, j) = U(c - j, c)
+    wave_lds_sync();
+    for (int j = max(k0 - kSt, 0) + lane; j < n; j += 64) st2(f.y + j, ld2(yr + (j & (kYR - 1))));
+}
+
+// y <- U^{-1} y, in place in the scratch vector, by columns: y[c] <- y[c] /
+// U(c, c), then rows c - 2 kB .. c - 1 -= U(., c) y[c].  A block holds
+// columns lo .. lo + kSt - 1 (entry (c, j) = U(c - j, c) staged in LDS); the
+// ring holds y[lo - 2 kB .. lo + kSt - 1] at its start.  Returns the sum and
+// the largest of |y_r|^2 over the result.
+__device__ __forceinline__ void solve_backward(int n, const IILds &sm, const IIFactors &f, double &nrm2,
+                                               double &mx2) {
+    const int lane = lane_id();
+    cpx<double> *yr = sm.yr;
+    const int lo0 = (n - 1) / kSt * kSt;
+    if (lane < 2 * kB + kSt) {
+        const int j = lo0 - 2 * kB + lane;
+        const cpx<double> v = ld2(f.y + (j >= 0 && j < n ? j : 0));
+        if (j >= 0 && j < n) st2(yr + (j & (kYR - 1)), v);
+    }
+    cpx<double> pre = ld2(f.y + max(lo0 - kSt - 2 * kB + (lane & (kSt - 1)), 0));
     cpx<double> pu[kRowPer];
-    int lo = (n - 1) / kSt * kSt;
-    fetch_u(f, n, lo, pu);
-    for (; lo >= 0; lo -= kSt) {
+    fetch_u(f, n, lo0, pu);
+    double s2 = 0.0, m2 = 0.0;
+    for (int lo = lo0; lo >= 0; lo -= kSt) {
         wave_lds_sync();
 #pragma unroll
         for (int q = 0; q < kRowPer; ++q)
             if (lane + 64 * q < kSt * kWC) st2(sm.rows + lane + 64 * q, pu[q]);
         if (lo > 0) fetch_u(f, n, lo - kSt, pu);
+        if (lo != lo0 && lane < kSt) {
+            const int j = lo + kSt + lane;  // the previous block's results out
+            if (j < n) {
+                const cpx<double> x = ld2(yr + (j & (kYR - 1)));
+                st2(f.y + j, x);
+                s2 += c_abs2(x);
+                m2 = fmax(m2, c_abs2(x));
+            }
+            const int ji = lo - 2 * kB + lane;  // this block's lowest rows in
+            if (ji >= 0) st2(yr + (ji & (kYR - 1)), pre);
+            pre = ld2(f.y + max(ji - kSt, 0));
+        }
         wave_lds_sync();
         for (int c = min(lo + kSt, n) - 1; c >= lo; --c) {
             const cpx<double> *uc = sm.rows + (c - lo) * kWC;
-            const cpx<double> yc = c_mul(sm.y[c], uc[0]);
+            const cpx<double> yc = c_mul(ld2(yr + (c & (kYR - 1))), ld2(uc));
             if (lane < 2 * kB && c - 1 - lane >= 0) {
-                const int r = c - 1 - lane;
-                sm.y[r] = c_sub(sm.y[r], c_mul(uc[1 + lane], yc));
+                const int r = (c - 1 - lane) & (kYR - 1);
+                st2(yr + r, c_sub(ld2(yr + r), c_mul(ld2(uc + 1 + lane), yc)));
             }
-            if (lane == 0) sm.y[c] = yc;
-            wave_lds_sync();
+            if (lane == 0) st2(yr + (c & (kYR - 1)), yc);
+            __builtin_amdgcn_wave_barrier();
         }
     }
+    wave_lds_sync();
+    if (lane < kSt && lane < n) {  // the last block (columns 0 .. kSt - 1)
+        const cpx<double> x = ld2(yr + lane);
+        st2(f.y + lane, x);
+        s2 += c_abs2(x);
+        m2 = fmax(m2, c_abs2(x));
+    }
+    nrm2 = wave_sum(s2);
+    mx2 = wave_max(m2);
+    wave_global_sync();
 }
 
-// Rayleigh quotient y^H B y of a unit vector y (in LDS) from B's lower
+// Rayleigh quotient y^H B y of a unit vector y from B's lower
 // triangle: sum_r B_rr |y_r|^2 + 2 Re sum_{r > c} conj(y_r) B_rc y_c.
 __device__ __forceinline__ double band_rayleigh(const cpx<double> *H, int64_t ld, int n, const cpx<double> *y) {
     const int lane = lane_id();
@@ -318,100 +410,157 @@ __device__ __forceinline__ double band_rayleigh(const cpx<double> *H, int64_t ld
     return wave_sum(acc);
 }
 
-// One wavefront per cluster of eigenvalues (neighbours closer than 1e-3 of
-// the spectral radius): each member's shift is kept at least a few ulps above
-// the previous member's, and its vector is orthogonalised against the
-// cluster's earlier vectors after every solve.  The eigenvalues go out as the
-// vectors' Rayleigh quotients, the cluster's members sorted ascending with
-// their columns.  Jobs (matrix, first eigenvalue of a cluster) are taken in a
-// fixed stride over the grid; w_in (from the bisection) is only read, so
-// every wavefront finds the same clusters.
+// Eigenvalues closer than 1e-3 of the spectral radius (or 4e-12) form a
+// cluster; its vectors are orthogonalised against each other.
+__device__ __forceinline__ double cluster_tol(const double *w, int n) {
+    return fmax(1e-3 * fmax(fabs(w[0]), fabs(w[n - 1])), 4e-12);
+}
+
+// One wavefront per eigenvalue: inverse iteration (LU of B - lam I,
+// kIISolves solves from a hashed start vector, each rescaled) with lam = w_in[k],
+// kept at least a few ulps above the shift of the previous member of its
+// cluster (the shifts of a cluster are w_i0, then max(w_j, previous + 10 eps
+// max(|w_j|, ||B||))).  Writes column k of V and its Rayleigh quotient.  The
+// members of a cluster run in parallel; cluster_orth_kernel orthogonalises
+// them afterwards.  Jobs (matrix, eigenvalue) are taken in a fixed stride
+// over the grid.
 __global__ __launch_bounds__(64) void band_ii_kernel(const cpx<double> *__restrict__ Hall, int64_t ld,
                                                      const int32_t *__restrict__ n_in, int64_t batch,
                                                      const double *__restrict__ w_in, double *__restrict__ w_out,
                                                      int64_t ldw, cpx<double> *__restrict__ Vall, int64_t ldv,
                                                      char *scratch, int64_t wave_bytes) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const IILds sm(smem, ld);
+    const IILds sm(smem);
     const IIFactors f(scratch + (int64_t)blockIdx.x * wave_bytes, ld);
     const int lane = lane_id();
     for (int64_t job = blockIdx.x; job < batch * ld; job += gridDim.x) {
         const int64_t u = job / ld;
-        const int i0 = (int)(job % ld);
+        const int k = (int)(job % ld);
         const int n = n_in[u];
         if (n < 0 || n > ld) {  // a side outside [0, ld]: NaN eigenvalues
-            if (lane == 0) w_out[u * ldw + i0] = NAN;
+            if (lane == 0) w_out[u * ldw + k] = NAN;
             continue;
         }
-        if (i0 >= n) continue;
+        if (k >= n) continue;
         const double *w = w_in + u * ld;
-        double *wo = w_out + u * ldw;
         const double tn = fmax(fabs(w[0]), fabs(w[n - 1]));
-        const double ortol = fmax(1e-3 * tn, 4e-12);
+        const double ortol = cluster_tol(w, n);
+        int i0 = k;
+        while (i0 > 0 && w[i0] - w[i0 - 1] <= ortol) --i0;
+        double lam = w[i0];
+        for (int j = i0 + 1; j <= k; ++j) lam = fmax(w[j], lam + 10.0 * DBL_EPSILON * fmax(fabs(w[j]), tn));
+        const cpx<double> *H = Hall + u * ld * ld;
+        band_lu(H, ld, n, lam, fmax(DBL_EPSILON * tn, 1e-280), sm, f);
+        for (int r = lane; r < n; r += 64) st2(f.y + r, cpx<double>{start_value(k, r, 0), start_value(k, r, 1)});
+        wave_global_sync();
+        double scale = 1.0, inv = 0.0;
+        for (int it = 0; it < kIISolves; ++it) {
+            solve_forward(n, sm, f, scale);
+            wave_global_sync();
+            double nrm2, mx2;
+            solve_backward(n, sm, f, nrm2, mx2);
+            scale = mx2 > 0.0 ? 1.0 / sqrt(mx2) : 1.0;  // the next solve starts from entries of at most 1
+            inv = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
+        }
+        cpx<double> *vk = Vall + u * ldv * ldv + (int64_t)k * ldv;
+        for (int r = lane; r < n; r += 64) st2(vk + r, c_scale(inv, ld2(f.y + r)));
+        wave_global_sync();
+        const double rq = band_rayleigh(H, ld, n, vk);
+        if (lane == 0) w_out[u * ldw + k] = rq;
+        wave_lds_sync();
+    }
+}
+
+// One workgroup per cluster of two or more eigenvalues: the members' vectors
+// orthonormalised in order by classical Gram-Schmidt applied twice (the dots
+// with the earlier members by the four wavefronts in turn, then one update),
+// their Rayleigh quotients recomputed, and the members sorted by them with
+// their columns.
+constexpr int kOrthThreads = 256;
+__global__ __launch_bounds__(kOrthThreads) void cluster_orth_kernel(const cpx<double> *__restrict__ Hall,
+                                                                    int64_t ld, const int32_t *__restrict__ n_in,
+                                                                    int64_t batch, const double *__restrict__ w_in,
+                                                                    double *__restrict__ w_out, int64_t ldw,
+                                                                    cpx<double> *__restrict__ Vall, int64_t ldv) {
+    constexpr int NW = kOrthThreads / 64;
+    __shared__ cpx<double> dots[kOrthThreads];
+    __shared__ double red[NW];
+    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+    for (int64_t job = blockIdx.x; job < batch * ld; job += gridDim.x) {
+        const int64_t u = job / ld;
+        const int i0 = (int)(job % ld);
+        const int n = n_in[u];
+        if (n < 1 || n > ld || i0 >= n) continue;
+        const double *w = w_in + u * ld;
+        const double ortol = cluster_tol(w, n);
         if (i0 > 0 && w[i0] - w[i0 - 1] <= ortol) continue;  // not the first of its cluster
         int i1 = i0 + 1;
         while (i1 < n && w[i1] - w[i1 - 1] <= ortol) ++i1;
-        const cpx<double> *H = Hall + u * ld * ld;
+        if (i1 - i0 < 2) continue;
         cpx<double> *V = Vall + u * ldv * ldv;
-        const double tiny = fmax(DBL_EPSILON * tn, 1e-280);
-        double shift_prev = 0.0;
-        for (int k = i0; k < i1; ++k) {
-            double lam = w[k];
-            if (k > i0) lam = fmax(lam, shift_prev + 10.0 * DBL_EPSILON * fmax(fabs(lam), tn));
-            shift_prev = lam;
-            band_lu(H, ld, n, lam, tiny, sm, f);
-            for (int r = lane; r < n; r += 64) sm.y[r] = {start_value(k, r, 0), start_value(k, r, 1)};
-            for (int it = 0; it < 3; ++it) {
-                wave_lds_sync();
-                band_solve(n, sm, f);
-                double mx = 0.0;
-                for (int r = lane; r < n; r += 64) mx = fmax(mx, c_abs2(sm.y[r]));
-                mx = wave_max(mx);
-                const double sc = mx > 0.0 ? 1.0 / sqrt(mx) : 1.0;
-                for (int r = lane; r < n; r += 64) sm.y[r] = c_scale(sc, sm.y[r]);
-                for (int q = i0; q < k; ++q) {  // against the cluster's earlier vectors
-                    const cpx<double> *vq = V + (int64_t)q * ldv;
-                    double dre = 0.0, dim = 0.0;
-                    for (int r = lane; r < n; r += 64) {
-                        const cpx<double> d = c_cmul(vq[r], sm.y[r]);
-                        dre += d.re;
-                        dim += d.im;
+        double *wo = w_out + u * ldw;
+        for (int j = i0 + 1; j < i1; ++j) {
+            cpx<double> *vj = V + (int64_t)j * ldv;
+            for (int pass = 0; pass < 2; ++pass) {
+                for (int c0 = i0; c0 < j; c0 += kOrthThreads) {
+                    const int c1 = min(c0 + kOrthThreads, j);
+                    for (int i = c0 + wid; i < c1; i += NW) {
+                        const cpx<double> *vi = V + (int64_t)i * ldv;
+                        double re = 0.0, im = 0.0;
+                        for (int r = lane; r < n; r += 64) {
+                            const cpx<double> d = c_cmul(ld2(vi + r), ld2(vj + r));
+                            re += d.re;
+                            im += d.im;
+                        }
+                        re = wave_sum(re);
+                        im = wave_sum(im);
+                        if (lane == 0) dots[i - c0] = {re, im};
                     }
-                    const cpx<double> dot = {wave_sum(dre), wave_sum(dim)};
-                    for (int r = lane; r < n; r += 64) sm.y[r] = c_sub(sm.y[r], c_mul(vq[r], dot));
+                    __syncthreads();
+                    for (int r = t; r < n; r += kOrthThreads) {
+                        cpx<double> x = ld2(vj + r);
+                        for (int i = c0; i < c1; ++i) x = c_sub(x, c_mul(ld2(V + (int64_t)i * ldv + r), dots[i - c0]));
+                        st2(vj + r, x);
+                    }
+                    __syncthreads();
                 }
-                double nrm = 0.0;
-                for (int r = lane; r < n; r += 64) nrm += c_abs2(sm.y[r]);
-                nrm = wave_sum(nrm);
-                const double inv = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
-                for (int r = lane; r < n; r += 64) sm.y[r] = c_scale(inv, sm.y[r]);
             }
-            wave_lds_sync();
-            const double rq = band_rayleigh(H, ld, n, sm.y);
-            cpx<double> *vk = V + (int64_t)k * ldv;
-            for (int r = lane; r < n; r += 64) vk[r] = sm.y[r];
-            if (lane == 0) wo[k] = rq;
-            wave_lds_sync();
-            wave_global_sync();  // the cluster's next member reads this column
+            double nrm = 0.0;
+            for (int r = t; r < n; r += kOrthThreads) nrm += c_abs2(ld2(vj + r));
+            nrm = wave_sum(nrm);
+            if (lane == 0) red[wid] = nrm;
+            __syncthreads();
+            nrm = 0.0;
+            for (int q = 0; q < NW; ++q) nrm += red[q];
+            const double inv = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
+            for (int r = t; r < n; r += kOrthThreads) st2(vj + r, c_scale(inv, ld2(vj + r)));
+            __syncthreads();
         }
-        // insertion sort of the cluster's Rayleigh quotients, columns along
-        for (int k = i0 + 1; k < i1; ++k) {
+        const cpx<double> *H = Hall + u * ld * ld;
+        for (int i = i0 + wid; i < i1; i += NW) {
+            const double rq = band_rayleigh(H, ld, n, V + (int64_t)i * ldv);
+            if (lane == 0) wo[i] = rq;
+        }
+        __syncthreads();
+        for (int k = i0 + 1; k < i1; ++k) {  // insertion sort, columns along
             for (int j = k; j > i0; --j) {
                 const double a = wo[j - 1], b = wo[j];
+                __syncthreads();  // every thread has read the pair before it changes
                 if (!(b < a)) break;
                 cpx<double> *va = V + (int64_t)(j - 1) * ldv, *vb = V + (int64_t)j * ldv;
-                for (int r = lane; r < n; r += 64) {
-                    const cpx<double> t = ld2(va + r);
+                for (int r = t; r < n; r += kOrthThreads) {
+                    const cpx<double> x = ld2(va + r);
                     st2(va + r, ld2(vb + r));
-                    st2(vb + r, t);
+                    st2(vb + r, x);
                 }
-                if (lane == 0) {
+                if (t == 0) {
                     wo[j - 1] = b;
                     wo[j] = a;
                 }
-                wave_global_sync();
+                __syncthreads();
             }
         }
+        __syncthreads();
     }
 }
 
@@ -509,6 +658,11 @@ hipError_t launch_band_inverse_iteration(const cpx<double> *H, int64_t ld, const
     if (err != hipSuccess) return err;
     hipLaunchKernelGGL(band_ii_kernel, dim3((unsigned)band_ii_waves(ld, batch)), dim3(64), (size_t)lds, s, H, ld,
                        n_in, batch, w_in, w_out, ldw, V, ldv, static_cast<char *>(scratch), band_ii_wave_bytes(ld));
+    err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    const int64_t groups = std::min<int64_t>(batch * ld, 2048);
+    hipLaunchKernelGGL(cluster_orth_kernel, dim3((unsigned)groups), dim3(kOrthThreads), 0, s, H, ld, n_in, batch,
+                       w_in, w_out, ldw, V, ldv);
     return hipGetLastError();
 }
 

@@ -25,15 +25,17 @@ hipError_t launch_band_reduce_keep(cpx<T> *H, int64_t ld, const int32_t *n_in, i
 // Inverse iteration: one wavefront per cluster, its LU factors in a slice of
 // device scratch of band_ii_wave_bytes(ld).
 // Scratch: U rows of 2 kB + 1 entries, kB multipliers and a pivot index per
-// elimination step, for ld + kIIStep steps (whole blocks of kIIStep).  LDS:
-// the (kB + 1) x (2 kB + 1) elimination window, kB multipliers, kIIStep
-// steps of incoming band rows and of outgoing factors, the iterated vector.
+// elimination step, for ld + kIIStep steps (whole blocks of kIIStep), and the
+// iterated vector.  LDS: the (kB + 1) x (2 kB + 1) elimination window,
+// kIIStep steps of incoming band rows and of outgoing factors, a ring of
+// kIIYRing entries of the iterated vector.
 constexpr int kIIStep = 8;
+constexpr int kIIYRing = 64;
 inline int64_t band_ii_wave_bytes(int64_t ld) {
-    return ((ld + kIIStep) * ((3 * kB + 1) * 16 + 4) + 255) / 256 * 256;
+    return ((ld + kIIStep) * ((3 * kB + 1) * 16 + 4) + ld * 16 + 255) / 256 * 256;
 }
-inline int64_t band_ii_lds_bytes(int64_t ld) {
-    return 16 * ((kB + 1) * (2 * kB + 1) + kB + kIIStep * (2 * (2 * kB + 1) + kB) + ld) + 4 * kIIStep;
+inline int64_t band_ii_lds_bytes(int64_t) {
+    return 16 * ((kB + 1) * (2 * kB + 1) + kIIStep * (2 * (2 * kB + 1) + kB) + kIIYRing) + 4 * kIIStep;
 }
 // Wavefronts of one launch: what the CUs hold at once (LDS-bound, at most
 // four per SIMD), and no more than the eigenvalues of the batch.
