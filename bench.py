@@ -43,7 +43,8 @@ recorded), with two context lines: the oracle on one core and one sample,
 and LAPACK's Hermitian eigenvalues (scipy, threaded BLAS) on the 64 matrices
 of sample 0.  ``roofline_stage1`` times the dense-to-band stage kernel by
 kernel at n ~ 2000 (graphene N = 32, one chunk) in both precisions;
-``eigenstates`` the eigenvalue-and-eigenvector call at graphene N = 8.
+``eigenstates`` the eigenvalue-and-eigenvector call at graphene N = 8 (LDS-resident) and N = 16
+(the banded path).
 """
 
 from __future__ import annotations
@@ -178,7 +179,7 @@ def parse():
     ap.add_argument("--timer-detail", action="store_true",
                     help="also time the dense-to-band kernels one by one in the instrumented pass")
     ap.add_argument("--eigh", dest="eigh", action="store_true", default=True,
-                    help="eigenstates per second of mlmc_batched_eigh (graphene N = 8)")
+                    help="eigenstates per second of mlmc_batched_eigh (graphene N = 8 and 16)")
     ap.add_argument("--no-eigh", dest="eigh", action="store_false")
     ap.add_argument("--serve-requests", type=int, default=160, help="requests per served run (--workload served)")
     ap.add_argument("--serve-slots", type=int, default=4, help="batches in flight at once (--workload served)")
@@ -569,12 +570,15 @@ def stage1_roofline(B, dev, prec, N=32, samples=32):
 
 
 def eigh_throughput(B, dev, prec, N=8, K=4, samples=256, repeats=5):
-    """Eigenstates (eigenvalues and eigenvectors) of the LDS-resident H(k):
-    graphene N = 8 (n <= 128), p = 0.05, K x K Monkhorst-Pack k-points,
-    `samples` samples in one mlmc_batched_eigh call, median of `repeats`
-    event-timed calls.  Algorithmic flops per matrix: 16/3 n^3 for the
-    reduction and 8 n^3 for V = Q D Z (n reflectors applied to n vectors),
-    against the vector peak of the compute type."""
+    """Eigenstates (eigenvalues and eigenvectors) of H(k): graphene N = 8
+    (n <= 128, LDS-resident) or N = 16 (n ~ 490, the banded path), p = 0.05,
+    K x K Monkhorst-Pack k-points, `samples` samples in one mlmc_batched_eigh
+    call, median of `repeats` event-timed calls.  Algorithmic flops per
+    matrix: 16/3 n^3 for the reduction and 8 n^3 for the back-transformation
+    (n reflectors applied to n vectors); the banded path adds its inverse
+    iteration, per eigenvalue a band LU (16 x 32 complex multiply-adds per
+    row) and two solves (16 + 32 per row each): 4864 n^2.  Against the vector
+    peak of the compute type."""
     import torch
     from mlmc_inputs import graphene
     lat = graphene()
@@ -597,15 +601,17 @@ def eigh_throughput(B, dev, prec, N=8, K=4, samples=256, repeats=5):
     torch.cuda.synchronize()
     ms = float(np.median([ev[2 * r].elapsed_time(ev[2 * r + 1]) for r in range(repeats)]))
     sizes = n.cpu().numpy().astype(np.float64)
-    flops = float(np.sum(16.0 / 3.0 * sizes ** 3 + 8.0 * sizes ** 3))
+    banded = ld > (128 if prec == B.MLMC_PREC_FP64 else 180)
+    flops = float(np.sum(16.0 / 3.0 * sizes ** 3 + 8.0 * sizes ** 3 + (4864.0 * sizes ** 2 if banded else 0.0)))
     peak = FP64_PEAK_TFLOPS if prec == B.MLMC_PREC_FP64 else FP32_PEAK_TFLOPS
     tf = flops / (ms * 1e-3) / 1e12
     return {"workload": f"graphene N = {N}, p = 0.05, {K}x{K} Monkhorst-Pack, {samples} samples",
             "precision": "fp64" if prec == B.MLMC_PREC_FP64 else "mixed", "matrices": batch,
+            "path": "banded (stage 1, chase, band inverse iteration)" if banded else "LDS-resident",
             "n_mean": round(float(sizes.mean()), 1), "ms_per_call": round(ms, 3),
             "eigenstates_per_s": round(batch / (ms * 1e-3), 1),
-            "roofline": {"bound": "alu", "kernel": "eigh_small_kernel", "achieved": round(tf, 3), "peak": peak,
-                         "unit": "TFLOP/s", "frac": round(tf / peak, 4),
+            "roofline": {"bound": "alu", "kernel": "all kernels of the call" if banded else "eigh_small_kernel",
+                         "achieved": round(tf, 3), "peak": peak, "unit": "TFLOP/s", "frac": round(tf / peak, 4),
                          "flops_per_launch": round(flops)}}
 
 
@@ -750,6 +756,7 @@ def main():
     eigh = None
     if args.eigh:
         eigh = [eigh_throughput(B, dev, q) for q in (B.MLMC_PREC_FP64, B.MLMC_PREC_MIXED)]
+        eigh.append(eigh_throughput(B, dev, B.MLMC_PREC_FP64, N=16, K=2, samples=32))
 
     cpu = None
     if args.cpu_baseline:
