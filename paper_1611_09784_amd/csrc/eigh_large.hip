@@ -473,10 +473,10 @@ __global__ __launch_bounds__(64) void band_ii_kernel(const cpx<double> *__restri
 
 // One workgroup per cluster of two or more eigenvalues: the members' vectors
 // orthonormalised in order by classical Gram-Schmidt applied twice (the dots
-// with the earlier members by the four wavefronts in turn, then one update),
-// their Rayleigh quotients recomputed, and the members sorted by them with
-// their columns.
-constexpr int kOrthThreads = 256;
+// with the earlier members by the sixteen wavefronts in turn, then one
+// update), their Rayleigh quotients recomputed, and the members sorted by
+// them with their columns.
+constexpr int kOrthThreads = 1024;
 __global__ __launch_bounds__(kOrthThreads) void cluster_orth_kernel(const cpx<double> *__restrict__ Hall,
                                                                     int64_t ld, const int32_t *__restrict__ n_in,
                                                                     int64_t batch, const double *__restrict__ w_in,
