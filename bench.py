@@ -43,8 +43,8 @@ recorded), with two context lines: the oracle on one core and one sample,
 and LAPACK's Hermitian eigenvalues (scipy, threaded BLAS) on the 64 matrices
 of sample 0.  ``roofline_stage1`` times the dense-to-band stage kernel by
 kernel at n ~ 2000 (graphene N = 32, one chunk) in both precisions;
-``eigenstates`` the eigenvalue-and-eigenvector call at graphene N = 8 (LDS-resident) and N = 16
-(the banded path).
+``eigenstates`` the eigenvalue-and-eigenvector call at graphene N = 8 (LDS-resident) and N = 16,
+32 (the banded path).
 """
 
 from __future__ import annotations
@@ -179,7 +179,7 @@ def parse():
     ap.add_argument("--timer-detail", action="store_true",
                     help="also time the dense-to-band kernels one by one in the instrumented pass")
     ap.add_argument("--eigh", dest="eigh", action="store_true", default=True,
-                    help="eigenstates per second of mlmc_batched_eigh (graphene N = 8 and 16)")
+                    help="eigenstates per second of mlmc_batched_eigh (graphene N = 8, 16, 32)")
     ap.add_argument("--no-eigh", dest="eigh", action="store_false")
     ap.add_argument("--serve-requests", type=int, default=160, help="requests per served run (--workload served)")
     ap.add_argument("--serve-slots", type=int, default=4, help="batches in flight at once (--workload served)")
@@ -571,7 +571,7 @@ def stage1_roofline(B, dev, prec, N=32, samples=32):
 
 def eigh_throughput(B, dev, prec, N=8, K=4, samples=256, repeats=5):
     """Eigenstates (eigenvalues and eigenvectors) of H(k): graphene N = 8
-    (n <= 128, LDS-resident) or N = 16 (n ~ 490, the banded path), p = 0.05,
+    (n <= 128, LDS-resident) or N = 16, 32 (n ~ 490, 1950: the banded path), p = 0.05,
     K x K Monkhorst-Pack k-points, `samples` samples in one mlmc_batched_eigh
     call, median of `repeats` event-timed calls.  Algorithmic flops per
     matrix: 16/3 n^3 for the reduction and 8 n^3 for the back-transformation
@@ -757,6 +757,7 @@ def main():
     if args.eigh:
         eigh = [eigh_throughput(B, dev, q) for q in (B.MLMC_PREC_FP64, B.MLMC_PREC_MIXED)]
         eigh.append(eigh_throughput(B, dev, B.MLMC_PREC_FP64, N=16, K=2, samples=32))
+        eigh.append(eigh_throughput(B, dev, B.MLMC_PREC_FP64, N=32, K=2, samples=2))
 
     cpu = None
     if args.cpu_baseline:
