@@ -265,9 +265,12 @@ constexpr int kNewtonCounts = 48;
 // each thread chose, keeps the threads of a wavefront in step; a thread
 // moves on to its next eigenvalue as soon as one is done.
 // e is squared in place.  w[i] = i-th smallest eigenvalue.
-// cnt holds blockDim.x + 1 ints of LDS.
-__device__ inline void bisect_block(const double *d, double *e, int n, double *w, double *red, int *cnt) {
-    const int t = threadIdx.x, nt = blockDim.x;
+// cnt holds blockDim.x + 1 ints of LDS.  With parts > 1 the workgroup takes
+// only the eigenvalues i = part nt + t + q parts nt of the matrix (the other
+// parts go to other workgroups, each with its own copy of d and e).
+__device__ inline void bisect_block(const double *d, double *e, int n, double *w, double *red, int *cnt,
+                                    int part = 0, int parts = 1) {
+    const int t = threadIdx.x, nt = blockDim.x, stride = parts * nt;
     if (n <= 0) return;
     double lo_p = INFINITY, hi_p = -INFINITY, e2max = 0.0;
     for (int i = t; i < n; i += nt) {
@@ -291,7 +294,7 @@ __device__ inline void bisect_block(const double *d, double *e, int n, double *w
     cnt[t + 1] = (t + 1 == nt) ? n : sturm_count(d, e, n, gl + step * (t + 1), pivmin);
     if (t == 0) cnt[0] = 0;
     __syncthreads();
-    int i = t;
+    int i = part * nt + t;
     double lo = 0.0, hi = 0.0, xn = NAN, dxprev = INFINITY, xc = 0.0, h = 0.0;
     int clo = 0, chi = 0, mode = 0, its = 0;  // mode 1 / 2: count at xc - h / xc + h next
     auto start = [&]() {
@@ -333,7 +336,7 @@ __device__ inline void bisect_block(const double *d, double *e, int n, double *w
         }
         if (done) {
             w[i] = lo + 0.5 * (hi - lo);
-            i += nt;
+            i += stride;
             if (i < n) start();
             continue;
         }

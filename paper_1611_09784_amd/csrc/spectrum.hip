@@ -1,10 +1,13 @@
 // Sturm bisection of tridiagonal matrices, smoothed IDoS and level sums.
+#include <algorithm>
+
 #include "device_common.hpp"
 
 namespace mlmc {
 
 // ---------------------------------------------------------------------------
-// Bisection: one workgroup per tridiagonal (d, e) at a time; d and e are
+// Bisection: one workgroup per tridiagonal (d, e) at a time, or per part of
+// its eigenvalues when the batch is too small to fill the chip; d and e are
 // staged in LDS (e squared there), so the serial Sturm recurrences read
 // broadcast LDS.  A grid smaller than the batch walks it with a stride
 // (a bisection running beside other kernels keeps to a few workgroups per CU).
@@ -19,13 +22,16 @@ template <bool GLOBAL>
 __global__ __launch_bounds__(kBisectThreads) void bisect_kernel(const double *__restrict__ dall,
                                                                 double *__restrict__ eall, int64_t lde,
                                                                 const int32_t *__restrict__ n_in, int64_t batch,
-                                                                int64_t ld_max, double *__restrict__ w, int64_t ldw) {
+                                                                int64_t ld_max, double *__restrict__ w, int64_t ldw,
+                                                                int parts) {
     extern __shared__ __align__(16) unsigned char smem[];
     double *red = reinterpret_cast<double *>(smem);
     int *cnt = reinterpret_cast<int *>(red + 32);
     double *dl = reinterpret_cast<double *>(cnt + kBisectThreads + 8);
     double *el = dl + ld_max;
-    for (int64_t u = blockIdx.x; u < batch; u += gridDim.x) {
+    for (int64_t job = blockIdx.x; job < batch * parts; job += gridDim.x) {
+        const int64_t u = job / parts;
+        const int part = (int)(job % parts);
         const int n = n_in[u];
         double *wu = w + u * ldw;
         if (n < 0 || n > ld_max) {
@@ -44,7 +50,7 @@ __global__ __launch_bounds__(kBisectThreads) void bisect_kernel(const double *__
             }
         }
         __syncthreads();
-        bisect_block(d, e, n, wu, red, cnt);
+        bisect_block(d, e, n, wu, red, cnt, part, parts);
         __syncthreads();  // d, e are read to the end before the next matrix replaces them
     }
 }
@@ -59,13 +65,20 @@ hipError_t launch_bisect(const double *d, double *e, int64_t lde, const int32_t 
                             : reinterpret_cast<const void *>(bisect_kernel<false>);
     hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (err != hipSuccess) return err;
-    const int64_t blocks = (max_blocks > 0 && max_blocks < batch) ? max_blocks : batch;
+    // A batch of fewer than 512 matrices (with no cap on the grid) splits each
+    // matrix's eigenvalues over up to ld_max / 256 workgroups, so that about
+    // 512 run; the global-memory variant squares e in place and keeps one.
+    int parts = 1;
+    if (!global && max_blocks <= 0 && batch < 512)
+        parts = (int)std::max<int64_t>(1, std::min<int64_t>(512 / batch, (ld_max + kBisectThreads - 1) / kBisectThreads));
+    const int64_t jobs = batch * parts;
+    const int64_t blocks = (max_blocks > 0 && max_blocks < jobs) ? max_blocks : jobs;
     if (global)
         hipLaunchKernelGGL(bisect_kernel<true>, dim3((unsigned)blocks), dim3(kBisectThreads), lds, s, d, e, lde, n_in,
-                           batch, ld_max, w, ldw);
+                           batch, ld_max, w, ldw, parts);
     else
         hipLaunchKernelGGL(bisect_kernel<false>, dim3((unsigned)blocks), dim3(kBisectThreads), lds, s, d, e, lde, n_in,
-                           batch, ld_max, w, ldw);
+                           batch, ld_max, w, ldw, parts);
     return hipGetLastError();
 }
 
