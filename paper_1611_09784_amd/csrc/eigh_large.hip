@@ -110,6 +110,9 @@ struct IILds {
     }
 };
 
+// Offset of row slot r in the window (a 24-bit multiply: slots are small).
+__device__ __forceinline__ int wrow(int r) { return (int)__umul24((unsigned)r, (unsigned)kWC); }
+
 // The elimination window is a ring: at step k it holds rows k .. k + kB
 // (row r in slot r mod (kB + 1)) and columns k .. k + 2 kB (column c in slot
 // c mod (2 kB + 1)), the rows' slots in that order except that the pivot
@@ -197,47 +200,48 @@ __device__ __forceinline__ void band_lu(const cpx<double> *H, int64_t ld, int n,
         const int k1 = min(k0 + kSt, n);
         for (int k = k0; k < k1; ++k) {
             const int i = k - k0;
+            // the pivot search's candidates are read first, so that it waits for them only
+            const int ksl = ks + lane >= kWR ? ks + lane - kWR : ks + lane;
+            const cpx<double> cand = ld2(sm.win + wrow(lane < kWR ? ksl : ks) + kc);
             const int csl = kc + cc >= kWC ? kc + cc - kWC : kc + cc;
             cpx<double> colk[kB / 2], xr[kB / 2];
             int rsl[kB / 2];
 #pragma unroll
             for (int q = 0; q < kB / 2; ++q) {
                 const int rr = 1 + rh + 2 * q;
-                rsl[q] = ks + rr >= kWR ? ks + rr - kWR : ks + rr;
-                colk[q] = ld2(sm.win + rsl[q] * kWC + kc);
-                xr[q] = ld2(sm.win + rsl[q] * kWC + csl);
+                rsl[q] = wrow(ks + rr >= kWR ? ks + rr - kWR : ks + rr);
+                colk[q] = ld2(sm.win + rsl[q] + kc);
+                xr[q] = ld2(sm.win + rsl[q] + csl);
             }
-            const cpx<double> rowk = ld2(sm.win + ks * kWC + csl), dkk = ld2(sm.win + ks * kWC + kc);
+            const cpx<double> rowk = ld2(sm.win + wrow(ks) + csl), dkk = ld2(sm.win + wrow(ks) + kc);
             const cpx<double> inrow = ld2(sm.rows + i * kWC + (lane < kWC ? lane : 0));
             const int ml = lane & (kB - 1);  // lane < kB: the multiplier of row k + 1 + ml
             const int mls = ks + 1 + ml >= kWR ? ks + 1 + ml - kWR : ks + 1 + ml;
-            const cpx<double> colm = ld2(sm.win + mls * kWC + kc);
-            int key = 0;
-            if (lane < kWR && k + lane < n) {
-                const int sl = ks + lane >= kWR ? ks + lane - kWR : ks + lane;
-                key = (int)((__float_as_uint((float)c_abs2(ld2(sm.win + sl * kWC + kc))) & ~31u) |
-                            (uint32_t)(31 - lane));
-            }
+            const cpx<double> colm = ld2(sm.win + wrow(mls) + kc);
+            const int key = lane < kWR && k + lane < n
+                                ? (int)((__float_as_uint((float)c_abs2(cand)) & ~31u) | (uint32_t)(31 - lane))
+                                : 0;
             const int pr = 31 - (max_key32(key) & 31);  // the pivot row is k + pr
-            const int psl = ks + pr >= kWR ? ks + pr - kWR : ks + pr;
-            cpx<double> piv = ld2(sm.win + psl * kWC + kc);
-            const cpx<double> rowp = ld2(sm.win + psl * kWC + csl);
+            const int psl = wrow(ks + pr >= kWR ? ks + pr - kWR : ks + pr);
+            cpx<double> piv = ld2(sm.win + psl + kc);
+            const cpx<double> rowp = ld2(sm.win + psl + csl);
             double a2 = c_abs2(piv);
             if (!(a2 >= tiny * tiny)) {  // singular to working precision: lam is an eigenvalue
                 piv = {tiny, 0.0};
                 a2 = tiny * tiny;
             }
-            const cpx<double> rp = {piv.re / a2, -piv.im / a2};
+            const double ia2 = 1.0 / a2;
+            const cpx<double> rp = {piv.re * ia2, -piv.im * ia2};
             // rows k + 1 .. k + kB -= l * (pivot row) over columns k + 1 .. k + 2 kB; the
             // row in p's slot stands for row k from here on, so its entries are
             // rewritten from row k's after the loop (the loop leaves zeros there)
 #pragma unroll
             for (int q = 0; q < kB / 2; ++q) {
                 const cpx<double> l = c_mul(colk[q], rp);
-                st2(sm.win + rsl[q] * kWC + csl, c_sub(xr[q], c_mul(l, rowp)));
+                st2(sm.win + rsl[q] + csl, c_sub(xr[q], c_mul(l, rowp)));
             }
             const cpx<double> lk = c_mul(dkk, rp);
-            if (pr > 0 && rh == ((pr - 1) & 1)) st2(sm.win + psl * kWC + csl, c_sub(rowk, c_mul(lk, rowp)));
+            if (pr > 0 && rh == ((pr - 1) & 1)) st2(sm.win + psl + csl, c_sub(rowk, c_mul(lk, rowp)));
             if (lane < kB) st2(sm.outL + i * kB + ml, c_mul(csel(ml + 1 == pr, dkk, colm), rp));
             if (lane < 2 * kB) st2(sm.outU + i * kWC + 1 + lane, rowp);
             if (lane == 0) {
@@ -248,11 +252,11 @@ __device__ __forceinline__ void band_lu(const cpx<double> *H, int64_t ld, int n,
             // k's slot becomes column k + 2 kB + 1, zero in rows k + 1 .. k + kB
             if (lane < kWC) {
                 const int c = kc + 1 + lane;
-                st2(sm.win + ks * kWC + (c >= kWC ? c - kWC : c), inrow);
+                st2(sm.win + wrow(ks) + (c >= kWC ? c - kWC : c), inrow);
             }
             if (lane < kB) {
                 const int sl = ks + 1 + lane;
-                st2(sm.win + (sl >= kWR ? sl - kWR : sl) * kWC + kc, cpx<double>{0.0, 0.0});
+                st2(sm.win + wrow(sl >= kWR ? sl - kWR : sl) + kc, cpx<double>{0.0, 0.0});
             }
             ks = ks + 1 == kWR ? 0 : ks + 1;
             kc = kc + 1 == kWC ? 0 : kc + 1;
