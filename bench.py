@@ -757,6 +757,7 @@ def main():
     if args.eigh:
         eigh = [eigh_throughput(B, dev, q) for q in (B.MLMC_PREC_FP64, B.MLMC_PREC_MIXED)]
         eigh.append(eigh_throughput(B, dev, B.MLMC_PREC_FP64, N=16, K=2, samples=32))
+        eigh.append(eigh_throughput(B, dev, B.MLMC_PREC_MIXED, N=16, K=2, samples=32))
         eigh.append(eigh_throughput(B, dev, B.MLMC_PREC_FP64, N=32, K=2, samples=2))
 
     cpu = None

@@ -233,11 +233,11 @@ mlmc_status mlmc_build_overlaps(mlmc_lattice lat, int32_t N, const uint8_t *d_ma
  *     third of the matrix memory of the pipelined layout).
  *   MLMC_OP_BATCHED_EIGH: `batch` matrices of side bound ld.  LDS-resident
  *     sides: 7*ld*ld doubles each, ld*ld rounded up to even (the tridiagonal
- *     eigenvectors and the inverse iteration's scratch).  Larger complex128
- *     sides: a copy of each matrix, the two-stage buffers, every panel's
- *     block reflector (16*ld + 256 complex per 16 columns) and the band
- *     inverse iteration's LU factors and vector (about 804*ld bytes per
- *     wavefront).
+ *     eigenvectors and the inverse iteration's scratch).  Larger sides: a
+ *     copy of each matrix, the two-stage buffers, every panel's block
+ *     reflector (16*ld + 256 complex per 16 columns), for complex64 the
+ *     vectors in complex128, and the band inverse iteration's LU factors and
+ *     vector (about 804*ld bytes per wavefront).
  * Errors: NULL arguments, unknown op, the operation's own argument checks
  * (MLMC_ERR_UNSUPPORTED for sizes beyond the library's limits). */
 mlmc_status mlmc_workspace_bytes(const mlmc_workspace_request *req, size_t *bytes);
@@ -290,13 +290,14 @@ mlmc_status mlmc_batched_eigvalsh_noalloc(mlmc_dtype dtype, mlmc_precision prec,
  * sub-diagonal real and non-negative, eigenvalues of T by the bisection of
  * mlmc_batched_eigvalsh, eigenvectors Z of T by inverse iteration with
  * partial pivoting, then V = Q D Z.
- * Larger matrices (complex128 only, ld <= 4096): a copy of the matrices is
- * reduced to a band of half-width 16 (stage 1 of mlmc_batched_eigvalsh, each
- * panel's block reflector I - V_p T_p V_p^H kept), the band is chased to
+ * Larger matrices (ld <= 4096): a copy of the matrices is reduced to a band
+ * of half-width 16 (stage 1 of mlmc_batched_eigvalsh in the compute type,
+ * each panel's block reflector I - V_p T_p V_p^H kept), the band is chased to
  * tridiagonal form and bisected for the eigenvalues, eigenvectors of the band
  * matrix B come from inverse iteration with a pivoted band LU of B - lam I
  * (one wavefront per eigenvalue), and the block reflectors take them back,
- * last panel first.
+ * last panel first; the band and the reflectors are widened to double for
+ * these steps, and complex64 vectors are rounded at the end.
  * Both paths: eigenvalues closer than 1e-3 of the spectral radius form a
  * cluster whose vectors are orthogonalised against each other (after every
  * solve on the LDS path; once, by Gram-Schmidt applied twice, on the banded
@@ -312,11 +313,12 @@ mlmc_status mlmc_batched_eigvalsh_noalloc(mlmc_dtype dtype, mlmc_precision prec,
  * ||H|| in the compute type (complex128 or complex64), columns orthonormal
  * to the same order.  d_work: mlmc_workspace_bytes(MLMC_OP_BATCHED_EIGH)
  * (7 ld^2 doubles per LDS-resident matrix; above that about 2 ld^2 complex
- * per matrix and the inverse iteration's factors and vector, about
- * ld * 804 bytes per wavefront in flight).
- * Errors: ld above 4096, or above the LDS bound in complex64, or a batch
- * above 65535 beyond the LDS bound (MLMC_ERR_UNSUPPORTED); ldw or ldv < ld,
- * NULL buffers, workspace too small. */
+ * per matrix, plus ld^2 complex128 for complex64 input, and the inverse
+ * iteration's factors and vector, about ld * 804 bytes per wavefront in
+ * flight).
+ * Errors: ld above 4096, or a batch above 65535 beyond the LDS bound
+ * (MLMC_ERR_UNSUPPORTED); ldw or ldv < ld, NULL buffers, workspace too
+ * small. */
 mlmc_status mlmc_batched_eigh(mlmc_dtype dtype, mlmc_precision prec, void *d_H, int64_t ld, const int64_t *d_offsets,
                               const int32_t *d_n, int64_t batch, double *d_w, int64_t ldw, void *d_V, int64_t ldv,
                               void *d_work, size_t work_bytes, mlmc_stream stream);

@@ -472,8 +472,7 @@ def mlmc_eigh_workspace(dtype, prec, ld, batch) -> int:
 
 
 def mlmc_batched_eigh(H, n, prec=None, w=None, V=None, work=None, stream=None, offsets=None, ld=None):
-    """Eigenvalues and eigenvectors of Hermitian matrices (complex64 up to
-    side 180, complex128 up to 4096).
+    """Eigenvalues and eigenvectors of Hermitian matrices (up to side 4096).
     H: [batch][ld][ld] column-major (torch [u][c][r]), read only; or a flat
     buffer with `offsets` and `ld` as in mlmc_batched_eigvalsh.  Returns
     (w [batch][ld], V [batch][ld][ld]) with V[b, i, :n_b] the unit

@@ -708,18 +708,21 @@ mlmc_status mlmc_batched_eigvalsh(mlmc_dtype dtype, mlmc_precision prec, void *d
 
 // Workspace of the banded eigenvector path (ld above the LDS-resident
 // bound): a copy of the matrices for stage 1, the two-stage buffers, every
-// panel's block reflector, the inverse iteration's LU factors.
+// panel's block reflector, the inverse iteration's LU factors and, for
+// complex64 input, the vectors in complex128 until they are rounded.
 struct EighLargeBuffers {
     EigBuffers b;
     double *w = nullptr;  // the bisection's eigenvalues [batch][ld]
-    cpx<double> *keep = nullptr;
+    void *keep = nullptr;
     void *ii = nullptr;
+    cpx<double> *vd = nullptr;  // complex64 input: the vectors [batch][ld][ld] in complex128
 };
-static void carve_eigh_large(Carver &cv, int64_t ld, int64_t batch, EighLargeBuffers &L) {
-    carve_large(cv, MLMC_PREC_FP64, ld, batch, true, L.b);
+static void carve_eigh_large(Carver &cv, mlmc_precision prec, int64_t ld, int64_t batch, EighLargeBuffers &L) {
+    carve_large(cv, prec, ld, batch, true, L.b);
     L.w = cv.take<double>(sizeof(double) * (size_t)ld * (size_t)batch);
-    L.keep = cv.take<cpx<double>>(sizeof(cpx<double>) * (size_t)eigh_keep_elems(ld) * (size_t)batch);
+    L.keep = cv.take<void>(cplx_bytes(prec) * (size_t)eigh_keep_elems(ld) * (size_t)batch);
     L.ii = cv.take<void>(band_ii_scratch_bytes(ld, batch));
+    if (prec != MLMC_PREC_FP64) L.vd = cv.take<cpx<double>>(sizeof(cpx<double>) * (size_t)ld * (size_t)ld * (size_t)batch);
 }
 
 static mlmc_status eigh_workspace(mlmc_dtype dtype, mlmc_precision prec, int64_t ld, int64_t batch, size_t *bytes) {
@@ -730,19 +733,45 @@ static mlmc_status eigh_workspace(mlmc_dtype dtype, mlmc_precision prec, int64_t
         *bytes = eigh_work_bytes(ld, batch);
         return MLMC_OK;
     }
-    if (prec != MLMC_PREC_FP64)
-        return fail(MLMC_ERR_UNSUPPORTED, "batched_eigh: ld %lld above the LDS-resident bound %d needs complex128",
-                    (long long)ld, small_cap(prec));
     if (ld > kEighLargeMax)
         return fail(MLMC_ERR_UNSUPPORTED, "batched_eigh: ld %lld exceeds %d", (long long)ld, kEighLargeMax);
     if (batch > 65535) return fail(MLMC_ERR_UNSUPPORTED, "batched_eigh: batch %lld above 65535 for ld > %d",
                                    (long long)batch, small_cap(prec));
     Carver cv{nullptr};
     EighLargeBuffers L;
-    carve_eigh_large(cv, ld, batch, L);
+    carve_eigh_large(cv, prec, ld, batch, L);
     *bytes = cv.used;
     return MLMC_OK;
 }
+
+extern "C++" {  // (a template, inside the C-linkage block of the entry points)
+template <typename T>
+static mlmc_status eigh_large(mlmc_precision prec, const void *d_H, int64_t ld, const int64_t *d_offsets,
+                              const int32_t *d_n, int64_t batch, double *d_w, int64_t ldw, void *d_V, int64_t ldv,
+                              void *d_work, hipStream_t s) {
+    Carver cv{static_cast<char *>(d_work)};
+    EighLargeBuffers L;
+    carve_eigh_large(cv, prec, ld, batch, L);
+    cpx<T> *Hc = static_cast<cpx<T> *>(L.b.H);
+    cpx<T> *keep = static_cast<cpx<T> *>(L.keep);
+    const int64_t keep_stride = eigh_keep_elems(ld);
+    // complex128 vectors: the caller's buffer, or the workspace's copy for complex64 input
+    cpx<double> *V = L.vd ? L.vd : static_cast<cpx<double> *>(d_V);
+    const int64_t vld = L.vd ? ld : ldv;
+    LAUNCH("eigh_gather", s, launch_gather_matrices<T>(static_cast<const cpx<T> *>(d_H), ld, d_offsets, d_n, batch, Hc, s));
+    LAUNCH("band_reduce", s, launch_band_reduce_keep<T>(Hc, ld, d_n, batch, static_cast<cpx<T> *>(L.b.partial), s,
+                                                        L.b.stride, nullptr, keep, keep_stride));
+    mlmc_status rs = run_chase(prec, Hc, ld, d_n, batch, L.b, s);
+    if (rs != MLMC_OK) return rs;
+    rs = run_bisect(d_n, ld, batch, L.w, ld, L.b, s);
+    if (rs != MLMC_OK) return rs;
+    LAUNCH("eigh_band_ii", s, launch_band_inverse_iteration<T>(Hc, ld, d_n, batch, L.w, d_w, ldw, V, vld, L.ii, s));
+    LAUNCH("eigh_backtransform", s, launch_panel_backtransform<T>(keep, keep_stride, ld, d_n, batch, V, vld, s));
+    if (L.vd)
+        LAUNCH("eigh_narrow", s, launch_narrow_vectors(L.vd, ld, d_n, batch, static_cast<cpx<float> *>(d_V), ldv, s));
+    return MLMC_OK;
+}
+}  // extern "C++"
 
 mlmc_status mlmc_batched_eigh(mlmc_dtype dtype, mlmc_precision prec, void *d_H, int64_t ld, const int64_t *d_offsets,
                               const int32_t *d_n, int64_t batch, double *d_w, int64_t ldw, void *d_V, int64_t ldv,
@@ -769,24 +798,9 @@ mlmc_status mlmc_batched_eigh(mlmc_dtype dtype, mlmc_precision prec, void *d_H, 
                                                              ldv, static_cast<double *>(d_work), s));
         return MLMC_OK;
     }
-    Carver cv{static_cast<char *>(d_work)};
-    EighLargeBuffers L;
-    carve_eigh_large(cv, ld, batch, L);
-    cpx<double> *Hc = static_cast<cpx<double> *>(L.b.H);
-    const int64_t keep_stride = eigh_keep_elems(ld);
-    LAUNCH("eigh_gather", s,
-           launch_gather_matrices(static_cast<const cpx<double> *>(d_H), ld, d_offsets, d_n, batch, Hc, s));
-    LAUNCH("band_reduce", s, launch_band_reduce_keep<double>(Hc, ld, d_n, batch, static_cast<cpx<double> *>(L.b.partial),
-                                                             s, L.b.stride, nullptr, L.keep, keep_stride));
-    mlmc_status rs = run_chase(prec, Hc, ld, d_n, batch, L.b, s);
-    if (rs != MLMC_OK) return rs;
-    rs = run_bisect(d_n, ld, batch, L.w, ld, L.b, s);
-    if (rs != MLMC_OK) return rs;
-    LAUNCH("eigh_band_ii", s, launch_band_inverse_iteration(Hc, ld, d_n, batch, L.w, d_w, ldw,
-                                                            static_cast<cpx<double> *>(d_V), ldv, L.ii, s));
-    LAUNCH("eigh_backtransform", s, launch_panel_backtransform(L.keep, keep_stride, ld, d_n, batch,
-                                                               static_cast<cpx<double> *>(d_V), ldv, s));
-    return MLMC_OK;
+    if (prec == MLMC_PREC_FP64)
+        return eigh_large<double>(prec, d_H, ld, d_offsets, d_n, batch, d_w, ldw, d_V, ldv, d_work, s);
+    return eigh_large<float>(prec, d_H, ld, d_offsets, d_n, batch, d_w, ldw, d_V, ldv, d_work, s);
 }
 
 }  // extern "C"

@@ -1306,6 +1306,8 @@ template size_t tridiag_twostage_work_elems<float>(int64_t);
 template hipError_t launch_band_reduce_keep<double>(cpx<double> *, int64_t, const int32_t *, int64_t,
                                                     cpx<double> *, hipStream_t, int64_t, const int64_t *,
                                                     cpx<double> *, int64_t);
+template hipError_t launch_band_reduce_keep<float>(cpx<float> *, int64_t, const int32_t *, int64_t, cpx<float> *,
+                                                   hipStream_t, int64_t, const int64_t *, cpx<float> *, int64_t);
 template hipError_t launch_band_reduce<double>(cpx<double> *, int64_t, const int32_t *, int64_t, cpx<double> *,
                                                hipStream_t, int64_t, const int64_t *, int);
 template hipError_t launch_band_reduce<float>(cpx<float> *, int64_t, const int32_t *, int64_t, cpx<float> *,

@@ -1,4 +1,5 @@
-// Eigenvectors of matrices above the LDS-resident size (complex128).  After
+// Eigenvectors of matrices above the LDS-resident size (complex128 or complex64
+// storage, computed in double).  After
 // stage 1 (dense -> band of half-width kB, each panel's block reflector kept)
 // and the eigenvalues (chase + bisection), the eigenvectors are
 //   band_ii_kernel   inverse iteration on the band matrix B, one wavefront
@@ -37,6 +38,14 @@ __device__ __forceinline__ cpx<double> ld2(const cpx<double> *p) {
     return {v.x, v.y};
 }
 __device__ __forceinline__ void st2(cpx<double> *p, cpx<double> x) { *reinterpret_cast<d2v *>(p) = d2v{x.re, x.im}; }
+// An entry of the matrices or of the reflector store, complex128 or complex64,
+// widened to complex128 (the banded path computes in double either way).
+typedef float f2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ cpx<double> ldc(const cpx<double> *p) { return ld2(p); }
+__device__ __forceinline__ cpx<double> ldc(const cpx<float> *p) {
+    const f2v v = *reinterpret_cast<const f2v *>(p);
+    return {(double)v.x, (double)v.y};
+}
 
 // Orders this wavefront's LDS traffic (the workgroup is one wavefront; its
 // LDS operations complete in order, so only the compiler is held back).
@@ -123,12 +132,13 @@ __device__ __forceinline__ int wrow(int r) { return (int)__umul24((unsigned)r, (
 // outside the n x n matrix (n >= 1); the diagonal is taken real.  The load is
 // unconditional (from H[0] for an entry outside), so that a block of such
 // loads stays in flight together.
-__device__ __forceinline__ cpx<double> band_ld(const cpx<double> *H, int64_t ld, int n, int r, int c, double lam) {
+template <typename T>
+__device__ __forceinline__ cpx<double> band_ld(const cpx<T> *H, int64_t ld, int n, int r, int c, double lam) {
     const int d = r - c;
     const bool in = r >= 0 && c >= 0 && r < n && c < n && d <= kB && d >= -kB;
     const bool up = d < 0;
     const int64_t at = in ? (up ? (int64_t)c + (int64_t)r * ld : (int64_t)r + (int64_t)c * ld) : 0;
-    const cpx<double> x = ld2(H + at);
+    const cpx<double> x = ldc(H + at);
     // factors instead of selects, so that both halves are always used
     const double keep = in ? 1.0 : 0.0, sgn = d == 0 ? 0.0 : (up ? -keep : keep);
     return {(x.re - (d == 0 ? lam : 0.0)) * keep, x.im * sgn};
@@ -136,7 +146,8 @@ __device__ __forceinline__ cpx<double> band_ld(const cpx<double> *H, int64_t ld,
 
 // Band rows k0 + kWR + i, columns k0 + i + 1 .. k0 + i + 2 kB + 1 (i < kSt):
 // what the steps k0 .. k0 + kSt - 1 slide into the window.
-__device__ __forceinline__ void fetch_rows(const cpx<double> *H, int64_t ld, int n, double lam, int k0,
+template <typename T>
+__device__ __forceinline__ void fetch_rows(const cpx<T> *H, int64_t ld, int n, double lam, int k0,
                                            cpx<double> (&pre)[kRowPer]) {
     const int lane = lane_id();
 #pragma unroll
@@ -177,7 +188,8 @@ __device__ __forceinline__ void flush_factors(const IILds &sm, const IIFactors &
 // reads everything that does not depend on the pivot at once, then the pivot
 // row, and touches LDS only: the band rows it slides in are fetched a block
 // ahead, and its factors go out a block behind.
-__device__ __forceinline__ void band_lu(const cpx<double> *H, int64_t ld, int n, double lam, double tiny, const IILds &sm,
+template <typename T>
+__device__ __forceinline__ void band_lu(const cpx<T> *H, int64_t ld, int n, double lam, double tiny, const IILds &sm,
                                         const IIFactors &f) {
     static_assert(kSt * kB == 64 * kLPer, "whole multiplier blocks");
     const int lane = lane_id();
@@ -402,14 +414,15 @@ __device__ __forceinline__ void solve_backward(int n, const IILds &sm, const IIF
 
 // Rayleigh quotient y^H B y of a unit vector y from B's lower
 // triangle: sum_r B_rr |y_r|^2 + 2 Re sum_{r > c} conj(y_r) B_rc y_c.
-__device__ __forceinline__ double band_rayleigh(const cpx<double> *H, int64_t ld, int n, const cpx<double> *y) {
+template <typename T>
+__device__ __forceinline__ double band_rayleigh(const cpx<T> *H, int64_t ld, int n, const cpx<double> *y) {
     const int lane = lane_id();
     double acc = 0.0;
     for (int r = lane; r < n; r += 64) {
-        const cpx<double> yr = y[r];
+        const cpx<double> yr = ld2(y + r);
         cpx<double> off = {0.0, 0.0};
-        for (int c = max(r - kB, 0); c < r; ++c) off = c_add(off, c_mul(H[(int64_t)r + (int64_t)c * ld], y[c]));
-        acc += H[(int64_t)r + (int64_t)r * ld].re * c_abs2(yr) + 2.0 * c_cmul(yr, off).re;
+        for (int c = max(r - kB, 0); c < r; ++c) off = c_add(off, c_mul(ldc(H + (int64_t)r + (int64_t)c * ld), ld2(y + c)));
+        acc += ldc(H + (int64_t)r + (int64_t)r * ld).re * c_abs2(yr) + 2.0 * c_cmul(yr, off).re;
     }
     return wave_sum(acc);
 }
@@ -428,7 +441,8 @@ __device__ __forceinline__ double cluster_tol(const double *w, int n) {
 // members of a cluster run in parallel; cluster_orth_kernel orthogonalises
 // them afterwards.  Jobs (matrix, eigenvalue) are taken in a fixed stride
 // over the grid.
-__global__ __launch_bounds__(64) void band_ii_kernel(const cpx<double> *__restrict__ Hall, int64_t ld,
+template <typename T>
+__global__ __launch_bounds__(64) void band_ii_kernel(const cpx<T> *__restrict__ Hall, int64_t ld,
                                                      const int32_t *__restrict__ n_in, int64_t batch,
                                                      const double *__restrict__ w_in, double *__restrict__ w_out,
                                                      int64_t ldw, cpx<double> *__restrict__ Vall, int64_t ldv,
@@ -453,7 +467,7 @@ __global__ __launch_bounds__(64) void band_ii_kernel(const cpx<double> *__restri
         while (i0 > 0 && w[i0] - w[i0 - 1] <= ortol) --i0;
         double lam = w[i0];
         for (int j = i0 + 1; j <= k; ++j) lam = fmax(w[j], lam + 10.0 * DBL_EPSILON * fmax(fabs(w[j]), tn));
-        const cpx<double> *H = Hall + u * ld * ld;
+        const cpx<T> *H = Hall + u * ld * ld;
         band_lu(H, ld, n, lam, fmax(DBL_EPSILON * tn, 1e-280), sm, f);
         for (int r = lane; r < n; r += 64) st2(f.y + r, cpx<double>{start_value(k, r, 0), start_value(k, r, 1)});
         wave_global_sync();
@@ -481,7 +495,8 @@ __global__ __launch_bounds__(64) void band_ii_kernel(const cpx<double> *__restri
 // update), their Rayleigh quotients recomputed, and the members sorted by
 // them with their columns.
 constexpr int kOrthThreads = 1024;
-__global__ __launch_bounds__(kOrthThreads) void cluster_orth_kernel(const cpx<double> *__restrict__ Hall,
+template <typename T>
+__global__ __launch_bounds__(kOrthThreads) void cluster_orth_kernel(const cpx<T> *__restrict__ Hall,
                                                                     int64_t ld, const int32_t *__restrict__ n_in,
                                                                     int64_t batch, const double *__restrict__ w_in,
                                                                     double *__restrict__ w_out, int64_t ldw,
@@ -540,7 +555,7 @@ __global__ __launch_bounds__(kOrthThreads) void cluster_orth_kernel(const cpx<do
             for (int r = t; r < n; r += kOrthThreads) st2(vj + r, c_scale(inv, ld2(vj + r)));
             __syncthreads();
         }
-        const cpx<double> *H = Hall + u * ld * ld;
+        const cpx<T> *H = Hall + u * ld * ld;
         for (int i = i0 + wid; i < i1; i += NW) {
             const double rq = band_rayleigh(H, ld, n, V + (int64_t)i * ldv);
             if (lane == 0) wo[i] = rq;
@@ -571,7 +586,8 @@ __global__ __launch_bounds__(kOrthThreads) void cluster_orth_kernel(const cpx<do
 // Panel p's block reflector applied to 16 columns of X: X <- X - V_p (T_p (V_p^H X))
 // over the rows s = p + kB .. n - 1.  Thread (rr, j) takes column j of the
 // tile and rows s + rr + 16 q.
-__global__ __launch_bounds__(256) void panel_bt_kernel(const cpx<double> *__restrict__ keep, int64_t keep_stride,
+template <typename T>
+__global__ __launch_bounds__(256) void panel_bt_kernel(const cpx<T> *__restrict__ keep, int64_t keep_stride,
                                                        int64_t ld, const int32_t *__restrict__ n_in, int64_t batch,
                                                        cpx<double> *__restrict__ Vall, int64_t ldv, int p,
                                                        int64_t tiles) {
@@ -584,8 +600,8 @@ __global__ __launch_bounds__(256) void panel_bt_kernel(const cpx<double> *__rest
     if (n < 1 || n > ld || m < 2) return;  // the panel had no reflectors
     const int col0 = tile * kB;
     if (col0 >= n) return;
-    const cpx<double> *Vp = keep + u * keep_stride + (int64_t)(p / kB) * (kB * ld + kB * kB);
-    const cpx<double> *Tp = Vp + kB * ld;
+    const cpx<T> *Vp = keep + u * keep_stride + (int64_t)(p / kB) * (kB * ld + kB * kB);
+    const cpx<T> *Tp = Vp + kB * ld;
     cpx<double> *X = Vall + u * ldv * ldv;
     const int t = threadIdx.x, rr = t & 15, j = t >> 4, col = col0 + j;
     const bool live = col < n;
@@ -596,7 +612,7 @@ __global__ __launch_bounds__(256) void panel_bt_kernel(const cpx<double> *__rest
         for (int r = s + rr; r < n; r += kB) {
             const cpx<double> x = X[(int64_t)col * ldv + r];
 #pragma unroll
-            for (int i = 0; i < kB; ++i) acc[i] = c_add(acc[i], c_cmul(Vp[(int64_t)i * ld + r], x));
+            for (int i = 0; i < kB; ++i) acc[i] = c_add(acc[i], c_cmul(ldc(Vp + (int64_t)i * ld + r), x));
         }
     }
 #pragma unroll
@@ -614,7 +630,7 @@ __global__ __launch_bounds__(256) void panel_bt_kernel(const cpx<double> *__rest
     __syncthreads();
     {  // Y = T W, T upper triangular: entry (rr, j)
         cpx<double> yv = {0.0, 0.0};
-        for (int l = rr; l < kB; ++l) yv = c_add(yv, c_mul(Tp[rr * kB + l], Ws[l][j]));
+        for (int l = rr; l < kB; ++l) yv = c_add(yv, c_mul(ldc(Tp + rr * kB + l), Ws[l][j]));
         Ys[rr][j] = yv;
     }
     __syncthreads();
@@ -622,67 +638,107 @@ __global__ __launch_bounds__(256) void panel_bt_kernel(const cpx<double> *__rest
         for (int r = s + rr; r < n; r += kB) {
             cpx<double> sum = {0.0, 0.0};
 #pragma unroll
-            for (int i = 0; i < kB; ++i) sum = c_add(sum, c_mul(Vp[(int64_t)i * ld + r], Ys[i][j]));
+            for (int i = 0; i < kB; ++i) sum = c_add(sum, c_mul(ldc(Vp + (int64_t)i * ld + r), Ys[i][j]));
             cpx<double> &x = X[(int64_t)col * ldv + r];
             x = c_sub(x, sum);
         }
     }
 }
 
-__global__ __launch_bounds__(256) void gather_kernel(const cpx<double> *__restrict__ H, int64_t ld,
+template <typename T>
+__global__ __launch_bounds__(256) void gather_kernel(const cpx<T> *__restrict__ H, int64_t ld,
                                                      const int64_t *__restrict__ offs, const int32_t *__restrict__ n_in,
-                                                     cpx<double> *__restrict__ dst) {
+                                                     cpx<T> *__restrict__ dst) {
     const int64_t u = blockIdx.y;
     const int n = n_in[u];
     if (n < 1 || n > ld) return;
-    const cpx<double> *src = H + (offs ? offs[u] : u * ld * ld);
-    cpx<double> *out = dst + u * ld * ld;
+    const cpx<T> *src = H + (offs ? offs[u] : u * ld * ld);
+    cpx<T> *out = dst + u * ld * ld;
     const int64_t total = ld * (int64_t)n;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) out[i] = src[i];
 }
 
+// The leading n_u x n_u block of each complex128 matrix (ld apart) rounded
+// to complex64 into dst (ldv apart).
+__global__ __launch_bounds__(256) void narrow_kernel(const cpx<double> *__restrict__ src, int64_t ld,
+                                                     const int32_t *__restrict__ n_in, cpx<float> *__restrict__ dst,
+                                                     int64_t ldv) {
+    const int64_t u = blockIdx.y;
+    const int n = n_in[u];
+    if (n < 1 || n > ld) return;
+    const int64_t total = (int64_t)n * n;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
+        const int64_t c = i / n, r = i % n;
+        const cpx<double> x = ld2(src + u * ld * ld + c * ld + r);
+        dst[u * ldv * ldv + c * ldv + r] = {(float)x.re, (float)x.im};
+    }
+}
+
 }  // namespace
 
-hipError_t launch_gather_matrices(const cpx<double> *H, int64_t ld, const int64_t *offs, const int32_t *n_in,
-                                  int64_t batch, cpx<double> *dst, hipStream_t s) {
+template <typename T>
+hipError_t launch_gather_matrices(const cpx<T> *H, int64_t ld, const int64_t *offs, const int32_t *n_in,
+                                  int64_t batch, cpx<T> *dst, hipStream_t s) {
     if (batch == 0) return hipSuccess;
     if (batch > 65535) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(gather_kernel, dim3(64, (unsigned)batch), dim3(256), 0, s, H, ld, offs, n_in, dst);
+    hipLaunchKernelGGL(gather_kernel<T>, dim3(64, (unsigned)batch), dim3(256), 0, s, H, ld, offs, n_in, dst);
     return hipGetLastError();
 }
 
-hipError_t launch_band_inverse_iteration(const cpx<double> *H, int64_t ld, const int32_t *n_in, int64_t batch,
+hipError_t launch_narrow_vectors(const cpx<double> *src, int64_t ld, const int32_t *n_in, int64_t batch,
+                                 cpx<float> *dst, int64_t ldv, hipStream_t s) {
+    if (batch == 0) return hipSuccess;
+    if (batch > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(narrow_kernel, dim3(64, (unsigned)batch), dim3(256), 0, s, src, ld, n_in, dst, ldv);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_band_inverse_iteration(const cpx<T> *H, int64_t ld, const int32_t *n_in, int64_t batch,
                                          const double *w_in, double *w_out, int64_t ldw, cpx<double> *V, int64_t ldv,
                                          void *scratch, hipStream_t s) {
     if (batch == 0) return hipSuccess;
     if (ld > kEighLargeMax) return hipErrorInvalidValue;
     const int64_t lds = band_ii_lds_bytes(ld);
-    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(band_ii_kernel),
+    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(band_ii_kernel<T>),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(band_ii_kernel, dim3((unsigned)band_ii_waves(ld, batch)), dim3(64), (size_t)lds, s, H, ld,
+    hipLaunchKernelGGL(band_ii_kernel<T>, dim3((unsigned)band_ii_waves(ld, batch)), dim3(64), (size_t)lds, s, H, ld,
                        n_in, batch, w_in, w_out, ldw, V, ldv, static_cast<char *>(scratch), band_ii_wave_bytes(ld));
     err = hipGetLastError();
     if (err != hipSuccess) return err;
     const int64_t groups = std::min<int64_t>(batch * ld, 2048);
-    hipLaunchKernelGGL(cluster_orth_kernel, dim3((unsigned)groups), dim3(kOrthThreads), 0, s, H, ld, n_in, batch,
+    hipLaunchKernelGGL(cluster_orth_kernel<T>, dim3((unsigned)groups), dim3(kOrthThreads), 0, s, H, ld, n_in, batch,
                        w_in, w_out, ldw, V, ldv);
     return hipGetLastError();
 }
 
-hipError_t launch_panel_backtransform(const cpx<double> *keep, int64_t keep_stride, int64_t ld, const int32_t *n_in,
+template <typename T>
+hipError_t launch_panel_backtransform(const cpx<T> *keep, int64_t keep_stride, int64_t ld, const int32_t *n_in,
                                       int64_t batch, cpx<double> *V, int64_t ldv, hipStream_t s) {
     if (batch == 0) return hipSuccess;
     const int64_t tiles = (ld + kB - 1) / kB;
     int last = -1;
     for (int p = 0; p + kB + 1 < ld; p += kB) last = p;  // the panels stage 1 ran
     for (int p = last; p >= 0; p -= kB) {
-        hipLaunchKernelGGL(panel_bt_kernel, dim3((unsigned)(batch * tiles)), dim3(256), 0, s, keep, keep_stride, ld,
-                           n_in, batch, V, ldv, p, tiles);
+        hipLaunchKernelGGL(panel_bt_kernel<T>, dim3((unsigned)(batch * tiles)), dim3(256), 0, s, keep, keep_stride,
+                           ld, n_in, batch, V, ldv, p, tiles);
         const hipError_t err = hipGetLastError();
         if (err != hipSuccess) return err;
     }
     return hipSuccess;
 }
+
+#define MLMC_EIGH_LARGE(T)                                                                                           \
+    template hipError_t launch_gather_matrices<T>(const cpx<T> *, int64_t, const int64_t *, const int32_t *, int64_t, \
+                                                  cpx<T> *, hipStream_t);                                           \
+    template hipError_t launch_band_inverse_iteration<T>(const cpx<T> *, int64_t, const int32_t *, int64_t,          \
+                                                         const double *, double *, int64_t, cpx<double> *, int64_t,  \
+                                                         void *, hipStream_t);                                       \
+    template hipError_t launch_panel_backtransform<T>(const cpx<T> *, int64_t, int64_t, const int32_t *, int64_t,     \
+                                                      cpx<double> *, int64_t, hipStream_t);
+MLMC_EIGH_LARGE(double)
+MLMC_EIGH_LARGE(float)
+#undef MLMC_EIGH_LARGE
 
 }  // namespace mlmc

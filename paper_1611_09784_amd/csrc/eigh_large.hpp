@@ -1,4 +1,4 @@
-// Eigenvectors of matrices above the LDS-resident size (complex128): stage 1
+// Eigenvectors of matrices above the LDS-resident size: stage 1
 // keeps each panel's block reflector (V_p, T_p), inverse iteration runs on
 // the band matrix of half-width kB that stage 1 leaves in the lower triangle
 // of H, and the band's eigenvectors go back through the kept reflectors.
@@ -49,20 +49,29 @@ inline size_t band_ii_scratch_bytes(int64_t ld, int64_t batch) {
 
 // Matrix u's leading ld x n_u block (offs: element offsets, NULL: u ld^2) to
 // dst + u ld^2.
-hipError_t launch_gather_matrices(const cpx<double> *H, int64_t ld, const int64_t *offs, const int32_t *n_in,
-                                  int64_t batch, cpx<double> *dst, hipStream_t s);
+template <typename T>
+hipError_t launch_gather_matrices(const cpx<T> *H, int64_t ld, const int64_t *offs, const int32_t *n_in,
+                                  int64_t batch, cpx<T> *dst, hipStream_t s);
 
-// Columns 0..n_u-1 of V_u (column-major, ldv, matrix u at u ldv^2): unit
-// eigenvectors of the band matrix in H (matrix u at u ld^2) for the ascending
-// eigenvalues w_in[u ld + i]; w_out[u ldw + i]: their Rayleigh quotients,
-// ascending (NaN for i < ld when n_u is outside [0, ld]).
-hipError_t launch_band_inverse_iteration(const cpx<double> *H, int64_t ld, const int32_t *n_in, int64_t batch,
+// Columns 0..n_u-1 of V_u (complex128, column-major, ldv, matrix u at u ldv^2):
+// unit eigenvectors of the band matrix in H (matrix u at u ld^2, complex128 or
+// complex64, widened) for the ascending eigenvalues w_in[u ld + i];
+// w_out[u ldw + i]: their Rayleigh quotients, ascending (NaN for i < ld when
+// n_u is outside [0, ld]).
+template <typename T>
+hipError_t launch_band_inverse_iteration(const cpx<T> *H, int64_t ld, const int32_t *n_in, int64_t batch,
                                          const double *w_in, double *w_out, int64_t ldw, cpx<double> *V, int64_t ldv,
                                          void *scratch, hipStream_t s);
 
 // V_u <- Q_u V_u, Q_u = (I - V_0 T_0 V_0^H) ... (I - V_P T_P V_P^H) from the
-// reflector store.
-hipError_t launch_panel_backtransform(const cpx<double> *keep, int64_t keep_stride, int64_t ld, const int32_t *n_in,
+// reflector store (complex128 or complex64, widened).
+template <typename T>
+hipError_t launch_panel_backtransform(const cpx<T> *keep, int64_t keep_stride, int64_t ld, const int32_t *n_in,
                                       int64_t batch, cpx<double> *V, int64_t ldv, hipStream_t s);
+
+// The leading n_u x n_u block of each complex128 matrix of src (ld apart),
+// rounded to complex64, into dst (ldv apart).
+hipError_t launch_narrow_vectors(const cpx<double> *src, int64_t ld, const int32_t *n_in, int64_t batch,
+                                 cpx<float> *dst, int64_t ldv, hipStream_t s);
 
 }  // namespace mlmc

@@ -149,16 +149,20 @@ def test_eigh_workspace_and_limits(B):
     assert out.value == 3 * 7 * 128 * 128 * 8
     assert ws(B.MLMC_C64, B.MLMC_PREC_MIXED, 180, 2) == B.MLMC_OK
     assert out.value == 2 * 7 * 180 * 180 * 8
-    # above the LDS bound: complex128 only, up to 4096, with a copy of the
-    # matrices and every panel's block reflector (16 ld + 256 elements per
-    # 16 columns) in the workspace
+    # above the LDS bound, up to 4096: a copy of the matrices and every panel's
+    # block reflector (16 ld + 256 elements per 16 columns) in the workspace,
+    # and for complex64 input the vectors in complex128 as well
     for ld, batch in ((129, 1), (2048, 3), (4096, 1)):
         assert ws(B.MLMC_C128, B.MLMC_PREC_FP64, ld, batch) == B.MLMC_OK
         keep = -(-ld // 16) * (16 * ld + 256)
         assert out.value >= batch * 16 * (ld * ld + keep)
+    for ld, batch in ((181, 1), (2048, 3)):
+        assert ws(B.MLMC_C64, B.MLMC_PREC_MIXED, ld, batch) == B.MLMC_OK
+        keep = -(-ld // 16) * (16 * ld + 256)
+        assert out.value >= batch * (8 * (ld * ld + keep) + 16 * ld * ld)
     assert ws(B.MLMC_C128, B.MLMC_PREC_FP64, 4097, 1) == B.MLMC_ERR_UNSUPPORTED
+    assert ws(B.MLMC_C64, B.MLMC_PREC_MIXED, 4097, 1) == B.MLMC_ERR_UNSUPPORTED
     assert ws(B.MLMC_C128, B.MLMC_PREC_FP64, 129, 65536) == B.MLMC_ERR_UNSUPPORTED
-    assert ws(B.MLMC_C64, B.MLMC_PREC_MIXED, 181, 1) == B.MLMC_ERR_UNSUPPORTED
     assert ws(B.MLMC_C64, B.MLMC_PREC_FP64, 64, 1) == B.MLMC_ERR_UNSUPPORTED
     assert B.mlmc_eigh_workspace(B.MLMC_C128, B.MLMC_PREC_FP64, 0, 5) == 0
     # NULL buffers, short leading dimensions and short workspaces fail up front

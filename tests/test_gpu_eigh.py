@@ -234,9 +234,9 @@ def test_eigh_ragged_offsets_bit_exact(B):
 
 
 def test_eigh_errors(B):
-    """Above the LDS bound only complex128 runs (banded path), up to 4096."""
+    """The banded path runs up to side 4096 in both precisions."""
     say("[eigh errors]")
-    for prec, cap in ((0, 4096), (1, 180)):
+    for prec, cap in ((0, 4096), (1, 4096)):
         dt = torch.complex128 if prec == 0 else torch.complex64
         H = torch.zeros((1, cap + 1, cap + 1), dtype=dt, device=DEV)
         n = torch.ones((1,), dtype=torch.int32, device=DEV)
@@ -244,24 +244,27 @@ def test_eigh_errors(B):
             B.mlmc_batched_eigh(H, n)
 
 
-# Above 128 (complex128) the banded path runs: stage 1 to half-bandwidth 16
-# with each panel's reflector kept, chase + bisection for the eigenvalues,
-# inverse iteration on the band, back-transformation through the panels.
+# Above 128 (complex128) or 180 (complex64) the banded path runs: stage 1 to
+# half-bandwidth 16 with each panel's reflector kept, chase + bisection for
+# the eigenvalues, inverse iteration on the band, back-transformation through
+# the panels (in double; complex64 input is widened, the vectors rounded).
 # Sides 17 and 18 give no panel and a panel of one reflector.
 
-@pytest.mark.parametrize("ld,sizes", [(300, [300, 257, 129, 1, 0]), (160, [160, 17, 18, 33, 2])])
-def test_eigh_large_random(B, ld, sizes):
-    say(f"[eigh large random] ld={ld} sizes={sizes}")
-    rng = np.random.default_rng(5000 + ld)
+@pytest.mark.parametrize("ld,sizes,prec", [(300, [300, 257, 129, 1, 0], 0), (160, [160, 17, 18, 33, 2], 0),
+                                           (300, [300, 181, 17, 1], 1)])
+def test_eigh_large_random(B, ld, sizes, prec):
+    say(f"[eigh large random] ld={ld} sizes={sizes} prec={prec}")
+    rng = np.random.default_rng(5000 + ld + prec)
     Hs = np.zeros((len(sizes), ld, ld), np.complex128)
     for u, m in enumerate(sizes):
         A = rng.normal(size=(m, m)) + 1j * rng.normal(size=(m, m))
         Hs[u, :m, :m] = (A + A.conj().T).T
-    run_and_check(B, Hs, sizes, 0, "large-random")
+    run_and_check(B, Hs, sizes, prec, "large-random")
 
 
-def test_eigh_large_clustered(B):
-    say("[eigh large clustered]")
+@pytest.mark.parametrize("prec", [0, 1])
+def test_eigh_large_clustered(B, prec):
+    say(f"[eigh large clustered] prec={prec}")
     rng = np.random.default_rng(91)
     ld, sizes = 256, [256, 200]
     Hs = np.zeros((len(sizes), ld, ld), np.complex128)
@@ -270,19 +273,21 @@ def test_eigh_large_clustered(B):
         Q, _ = np.linalg.qr(rng.normal(size=(m, m)) + 1j * rng.normal(size=(m, m)))
         A = (Q * lam) @ Q.conj().T
         Hs[u, :m, :m] = (0.5 * (A + A.conj().T)).T
-    run_and_check(B, Hs, sizes, 0, "large-clustered")
+    run_and_check(B, Hs, sizes, prec, "large-clustered")
 
 
-@pytest.mark.parametrize("name,N,p,K", [("graphene", 16, 0.05, 1), ("graphene", 12, 0.1, 2), ("mos2", 5, 0.1, 1)])
-def test_eigh_large_hamiltonians(B, devs, name, N, p, K):
+@pytest.mark.parametrize("name,N,p,K,prec", [("graphene", 16, 0.05, 1, 0), ("graphene", 12, 0.1, 2, 0),
+                                             ("mos2", 5, 0.1, 1, 0), ("graphene", 16, 0.05, 1, 1),
+                                             ("mos2", 5, 0.1, 1, 1)])
+def test_eigh_large_hamiltonians(B, devs, name, N, p, K, prec):
     """H(k) with vacancies above the LDS bound: zero modes, the degeneracies
     of the Gamma point (K = 1) and of a 2 x 2 grid."""
-    say(f"[eigh large H(k)] {name} N={N} p={p} K={K}")
+    say(f"[eigh large H(k)] {name} N={N} p={p} K={K} prec={prec}")
     dl = devs[name]
     mask = B.mlmc_sample_vacancies(dl, N, p, 57, dl.tag(N), 0, 1)
     kred, _ = B.mlmc_kgrid(1, K)
     H, n = B.mlmc_build_hamiltonians(dl, N, mask, kred, B.MLMC_C128)
-    run_and_check(B, H.cpu().numpy(), [int(x) for x in n.cpu().numpy()], 0, f"{name}N{N}")
+    run_and_check(B, H.cpu().numpy(), [int(x) for x in n.cpu().numpy()], prec, f"{name}N{N}")
 
 
 def test_eigh_large_n2000(B, devs):
