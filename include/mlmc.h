@@ -126,7 +126,8 @@ typedef enum {
                                                  n_eps                                                   */
     MLMC_OP_LEVEL_OUTCOMES_SINGLE_PASS = 3,   /* mlmc_level_outcomes taking chunk_samples outcomes in one
                                                  pass (one buffer set): the fields of MLMC_OP_LEVEL_ESTIMATE */
-    MLMC_OP_BATCHED_EIGH = 4                  /* mlmc_batched_eigh: dtype, prec, ld, batch                */
+    MLMC_OP_BATCHED_EIGH = 4,                 /* mlmc_batched_eigh: dtype, prec, ld, batch                */
+    MLMC_OP_BATCHED_EIGH_GENERALIZED = 5      /* mlmc_batched_eigh_generalized: dtype, prec, ld, batch    */
 } mlmc_op;
 
 /* Arguments of a workspace query; fields an operation does not use are ignored. */
@@ -322,6 +323,23 @@ mlmc_status mlmc_batched_eigvalsh_noalloc(mlmc_dtype dtype, mlmc_precision prec,
 mlmc_status mlmc_batched_eigh(mlmc_dtype dtype, mlmc_precision prec, void *d_H, int64_t ld, const int64_t *d_offsets,
                               const int32_t *d_n, int64_t batch, double *d_w, int64_t ldw, void *d_V, int64_t ldv,
                               void *d_work, size_t work_bytes, mlmc_stream stream);
+
+/* Eigenvalues and eigenvectors of a batch of Hermitian pencils (H, S), S
+ * positive definite: H c = E S c, the non-orthogonal basis of Section 3.1,
+ * for the eigenstates of Sections 1 and 5.  S = L L^H and C = L^{-1} H
+ * L^{-H} as in mlmc_batched_eigvalsh_generalized, the eigenstates y of C as
+ * in mlmc_batched_eigh, then c = L^{-H} y (a blocked back-substitution in
+ * double), so that the columns are S-orthonormal: c_i^H S c_j = delta_ij.
+ * d_H, d_S: [batch][ld][ld] column-major, lower triangles read, both
+ * overwritten (C and L).  d_n, d_w, ldw, d_V, ldv: as mlmc_batched_eigh.
+ * d_work: mlmc_workspace_bytes(MLMC_OP_BATCHED_EIGH_GENERALIZED) (the
+ * Cholesky reduction's workspace plus mlmc_batched_eigh's).  Accuracy:
+ * ||H c - E S c|| of a few ulps of ||H|| + |E| ||S|| in the compute type,
+ * times the condition of S.  Errors: ld above 2048 (MLMC_ERR_UNSUPPORTED),
+ * otherwise as mlmc_batched_eigh. */
+mlmc_status mlmc_batched_eigh_generalized(mlmc_dtype dtype, mlmc_precision prec, void *d_H, void *d_S, int64_t ld,
+                                          const int32_t *d_n, int64_t batch, double *d_w, int64_t ldw, void *d_V,
+                                          int64_t ldv, void *d_work, size_t work_bytes, mlmc_stream stream);
 
 /* All eigenvalues of a batch of Hermitian-definite pencils (H, S) (the
  * generalised problem H c = E S c of a non-orthogonal basis, Section 3.1):

@@ -40,6 +40,7 @@ MLMC_OP_BATCHED_EIGVALSH_GENERALIZED = 1
 MLMC_OP_LEVEL_ESTIMATE = 2
 MLMC_OP_LEVEL_OUTCOMES_SINGLE_PASS = 3
 MLMC_OP_BATCHED_EIGH = 4
+MLMC_OP_BATCHED_EIGH_GENERALIZED = 5
 
 # Largest matrix side of the LDS-resident fused path / of the device-memory path.
 SMALL_MAX = {MLMC_PREC_FP64: 128, MLMC_PREC_MIXED: 180}
@@ -94,6 +95,7 @@ SIGNATURES = {
     "mlmc_batched_eigvalsh": (C.c_int, [C.c_int, C.c_int, P, I64, P, P, I64, P, I64, P, SZ, P]),
     "mlmc_batched_eigvalsh_noalloc": (C.c_int, [C.c_int, C.c_int, P, I64, P, I64, P, I64, P]),
     "mlmc_batched_eigh": (C.c_int, [C.c_int, C.c_int, P, I64, P, P, I64, P, I64, P, I64, P, SZ, P]),
+    "mlmc_batched_eigh_generalized": (C.c_int, [C.c_int, C.c_int, P, P, I64, P, I64, P, I64, P, I64, P, SZ, P]),
     "mlmc_build_overlaps": (C.c_int, [P, I32, P, I64, P, I32, C.c_int, P, I64, P, P]),
     "mlmc_batched_eigvalsh_generalized": (C.c_int, [C.c_int, C.c_int, P, P, I64, P, I64, P, I64, P, SZ, P]),
     "mlmc_idos": (C.c_int, [P, I64, P, I64, I32, P, DBL, P, I32, DBL, C.c_int, P, P]),
@@ -508,6 +510,47 @@ def mlmc_batched_eigh(H, n, prec=None, w=None, V=None, work=None, stream=None, o
     wb = 0 if work is None else work.numel() * work.element_size()
     _check(lib().mlmc_batched_eigh(dtype, prec, _ptr(H), ld, _ptr(offsets), _ptr(n), batch, _ptr(w), w.shape[1],
                                    _ptr(V), V.shape[1], _ptr(work), wb, _stream(stream)), "mlmc_batched_eigh")
+    return w, V
+
+
+def mlmc_eigh_generalized_workspace(dtype, prec, ld, batch) -> int:
+    return mlmc_workspace_bytes(MLMC_OP_BATCHED_EIGH_GENERALIZED, dtype, prec, ld, batch)
+
+
+def mlmc_batched_eigh_generalized(H, S, n, prec=None, w=None, V=None, work=None, stream=None):
+    """Eigenvalues and S-orthonormal eigenvectors of the pencils (H, S) (up to
+    side 2048).  H, S: [batch][ld][ld] column-major (torch [u][c][r]), both
+    overwritten.  Returns (w [batch][ld], V [batch][ld][ld]) with V[b, i, :n_b]
+    the eigenvector of w[b, i]."""
+    if H.dtype == torch.complex128:
+        dtype = MLMC_C128
+    elif H.dtype == torch.complex64:
+        dtype = MLMC_C64
+    else:
+        raise ValueError("H must be complex64 or complex128")
+    if prec is None:
+        prec = MLMC_PREC_FP64 if dtype == MLMC_C128 else MLMC_PREC_MIXED
+    _dev(H, None, "H")
+    _dev(S, H.dtype, "S")
+    _dev(n, torch.int32, "n")
+    if S.shape != H.shape or H.dim() != 3:
+        raise ValueError("H and S must be [batch][ld][ld] of one shape")
+    batch, ld = H.shape[0], H.shape[1]
+    if w is None:
+        w = torch.zeros((batch, ld), dtype=torch.float64, device=H.device)
+    _dev(w, torch.float64, "w")
+    if V is None:
+        V = torch.zeros((batch, ld, ld), dtype=H.dtype, device=H.device)
+    _dev(V, H.dtype, "V")
+    if V.dim() != 3 or V.shape[0] != batch or V.shape[1] != V.shape[2] or not V.is_contiguous():
+        raise ValueError("V must be a contiguous [batch][ldv][ldv] tensor")
+    need = mlmc_eigh_generalized_workspace(dtype, prec, ld, batch)
+    if work is None and need > 0:
+        work = torch.empty((need,), dtype=torch.uint8, device=H.device)
+    wb = 0 if work is None else work.numel() * work.element_size()
+    _check(lib().mlmc_batched_eigh_generalized(dtype, prec, _ptr(H), _ptr(S), ld, _ptr(n), batch, _ptr(w), w.shape[1],
+                                               _ptr(V), V.shape[1], _ptr(work), wb, _stream(stream)),
+           "mlmc_batched_eigh_generalized")
     return w, V
 
 

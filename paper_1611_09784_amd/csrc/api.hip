@@ -773,20 +773,10 @@ static mlmc_status eigh_large(mlmc_precision prec, const void *d_H, int64_t ld, 
 }
 }  // extern "C++"
 
-mlmc_status mlmc_batched_eigh(mlmc_dtype dtype, mlmc_precision prec, void *d_H, int64_t ld, const int64_t *d_offsets,
-                              const int32_t *d_n, int64_t batch, double *d_w, int64_t ldw, void *d_V, int64_t ldv,
-                              void *d_work, size_t work_bytes, mlmc_stream stream) {
-    size_t need = 0;
-    const mlmc_status st = eigh_workspace(dtype, prec, ld, batch, &need);
-    if (st != MLMC_OK) return st;
-    if (ldw < ld || ldv < ld)
-        return fail(MLMC_ERR_INVALID_ARG, "batched_eigh: ldw %lld, ldv %lld < ld %lld", (long long)ldw,
-                    (long long)ldv, (long long)ld);
-    if (batch > 0 && (!d_H || !d_n || !d_w || !d_V)) return fail(MLMC_ERR_INVALID_ARG, "batched_eigh: NULL buffer");
-    if (need > 0 && (!d_work || work_bytes < need))
-        return fail(MLMC_ERR_WORKSPACE, "batched_eigh: workspace %zu < %zu bytes", work_bytes, need);
-    if (batch == 0 || ld == 0) return MLMC_OK;
-    hipStream_t s = static_cast<hipStream_t>(stream);
+// The eigenstates of validated arguments (d_work: eigh_workspace bytes).
+static mlmc_status eigh_run(mlmc_precision prec, void *d_H, int64_t ld, const int64_t *d_offsets, const int32_t *d_n,
+                            int64_t batch, double *d_w, int64_t ldw, void *d_V, int64_t ldv, void *d_work,
+                            hipStream_t s) {
     if (ld <= small_cap(prec)) {
         if (prec == MLMC_PREC_FP64)
             LAUNCH("eigh_small", s, launch_eigh_small<double>(static_cast<const cpx<double> *>(d_H), ld, d_offsets,
@@ -801,6 +791,76 @@ mlmc_status mlmc_batched_eigh(mlmc_dtype dtype, mlmc_precision prec, void *d_H, 
     if (prec == MLMC_PREC_FP64)
         return eigh_large<double>(prec, d_H, ld, d_offsets, d_n, batch, d_w, ldw, d_V, ldv, d_work, s);
     return eigh_large<float>(prec, d_H, ld, d_offsets, d_n, batch, d_w, ldw, d_V, ldv, d_work, s);
+}
+
+mlmc_status mlmc_batched_eigh(mlmc_dtype dtype, mlmc_precision prec, void *d_H, int64_t ld, const int64_t *d_offsets,
+                              const int32_t *d_n, int64_t batch, double *d_w, int64_t ldw, void *d_V, int64_t ldv,
+                              void *d_work, size_t work_bytes, mlmc_stream stream) {
+    size_t need = 0;
+    const mlmc_status st = eigh_workspace(dtype, prec, ld, batch, &need);
+    if (st != MLMC_OK) return st;
+    if (ldw < ld || ldv < ld)
+        return fail(MLMC_ERR_INVALID_ARG, "batched_eigh: ldw %lld, ldv %lld < ld %lld", (long long)ldw,
+                    (long long)ldv, (long long)ld);
+    if (batch > 0 && (!d_H || !d_n || !d_w || !d_V)) return fail(MLMC_ERR_INVALID_ARG, "batched_eigh: NULL buffer");
+    if (need > 0 && (!d_work || work_bytes < need))
+        return fail(MLMC_ERR_WORKSPACE, "batched_eigh: workspace %zu < %zu bytes", work_bytes, need);
+    if (batch == 0 || ld == 0) return MLMC_OK;
+    return eigh_run(prec, d_H, ld, d_offsets, d_n, batch, d_w, ldw, d_V, ldv, d_work, static_cast<hipStream_t>(stream));
+}
+
+// Generalised eigenstates: the Cholesky reduction's workspace, then the
+// eigenstates' (both aligned).
+static mlmc_status eigh_generalized_workspace(mlmc_dtype dtype, mlmc_precision prec, int64_t ld, int64_t batch,
+                                              size_t *bytes, size_t *gen_bytes) {
+    if (!bytes || ld < 0 || batch < 0) return fail(MLMC_ERR_INVALID_ARG, "eigh_generalized_workspace: bad argument");
+    const mlmc_status st = check_dtype_prec(dtype, prec);
+    if (st != MLMC_OK) return st;
+    if (ld > kGenMax)
+        return fail(MLMC_ERR_UNSUPPORTED, "batched_eigh_generalized: ld %lld exceeds %d", (long long)ld, kGenMax);
+    size_t eb = 0;
+    const mlmc_status se = eigh_workspace(dtype, prec, ld, batch, &eb);
+    if (se != MLMC_OK) return se;
+    const size_t ge = prec == MLMC_PREC_FP64 ? generalized_work_elems<double>(ld) : generalized_work_elems<float>(ld);
+    const size_t gb = align_up(cplx_bytes(prec) * ge * (size_t)batch);
+    if (gen_bytes) *gen_bytes = gb;
+    *bytes = gb + eb;
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_batched_eigh_generalized(mlmc_dtype dtype, mlmc_precision prec, void *d_H, void *d_S, int64_t ld,
+                                          const int32_t *d_n, int64_t batch, double *d_w, int64_t ldw, void *d_V,
+                                          int64_t ldv, void *d_work, size_t work_bytes, mlmc_stream stream) {
+    size_t need = 0, gen = 0;
+    const mlmc_status st = eigh_generalized_workspace(dtype, prec, ld, batch, &need, &gen);
+    if (st != MLMC_OK) return st;
+    if (ldw < ld || ldv < ld)
+        return fail(MLMC_ERR_INVALID_ARG, "batched_eigh_generalized: ldw %lld, ldv %lld < ld %lld", (long long)ldw,
+                    (long long)ldv, (long long)ld);
+    if (batch > 0 && (!d_H || !d_S || !d_n || !d_w || !d_V))
+        return fail(MLMC_ERR_INVALID_ARG, "batched_eigh_generalized: NULL buffer");
+    if (need > 0 && (!d_work || work_bytes < need))
+        return fail(MLMC_ERR_WORKSPACE, "batched_eigh_generalized: workspace %zu < %zu bytes", work_bytes, need);
+    if (batch == 0 || ld == 0) return MLMC_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char *work = static_cast<char *>(d_work);
+    if (prec == MLMC_PREC_FP64)
+        LAUNCH("overlap_reduce", s, launch_cholesky_reduce<double>(static_cast<cpx<double> *>(d_H),
+                                                                   static_cast<cpx<double> *>(d_S), ld, d_n, batch,
+                                                                   reinterpret_cast<cpx<double> *>(work), s));
+    else
+        LAUNCH("overlap_reduce", s, launch_cholesky_reduce<float>(static_cast<cpx<float> *>(d_H),
+                                                                  static_cast<cpx<float> *>(d_S), ld, d_n, batch,
+                                                                  reinterpret_cast<cpx<float> *>(work), s));
+    const mlmc_status se = eigh_run(prec, d_H, ld, nullptr, d_n, batch, d_w, ldw, d_V, ldv, work + gen, s);
+    if (se != MLMC_OK) return se;
+    if (prec == MLMC_PREC_FP64)
+        LAUNCH("eigh_backsolve", s, launch_trsm_lh<double>(static_cast<const cpx<double> *>(d_S), ld, d_n, batch,
+                                                           static_cast<cpx<double> *>(d_V), ldv, s));
+    else
+        LAUNCH("eigh_backsolve", s, launch_trsm_lh<float>(static_cast<const cpx<float> *>(d_S), ld, d_n, batch,
+                                                          static_cast<cpx<float> *>(d_V), ldv, s));
+    return MLMC_OK;
 }
 
 }  // extern "C"
@@ -988,6 +1048,8 @@ mlmc_status mlmc_workspace_bytes(const mlmc_workspace_request *req, size_t *byte
             return level_workspace(req->lat, req->N_fine, req->coupled, req->K_fine, req->K_coarse, req->kgrid,
                                    req->chunk_samples, req->prec, req->n_eps, bytes, 1);
         case MLMC_OP_BATCHED_EIGH: return eigh_workspace(req->dtype, req->prec, req->ld, req->batch, bytes);
+        case MLMC_OP_BATCHED_EIGH_GENERALIZED:
+            return eigh_generalized_workspace(req->dtype, req->prec, req->ld, req->batch, bytes, nullptr);
         default: return fail(MLMC_ERR_INVALID_ARG, "workspace_bytes: unknown operation %d", (int)req->op);
     }
 }

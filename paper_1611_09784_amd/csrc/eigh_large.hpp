@@ -69,6 +69,13 @@ template <typename T>
 hipError_t launch_panel_backtransform(const cpx<T> *keep, int64_t keep_stride, int64_t ld, const int32_t *n_in,
                                       int64_t batch, cpx<double> *V, int64_t ldv, hipStream_t s);
 
+// X_u <- L_u^{-H} X_u for the columns and rows 0..n_u-1 (L_u lower
+// triangular with a real positive diagonal, column-major, ld; X_u
+// column-major, ldx), computed in double.
+template <typename T>
+hipError_t launch_trsm_lh(const cpx<T> *L, int64_t ld, const int32_t *n_in, int64_t batch, cpx<T> *X, int64_t ldx,
+                          hipStream_t s);
+
 // The leading n_u x n_u block of each complex128 matrix of src (ld apart),
 // rounded to complex64, into dst (ldv apart).
 hipError_t launch_narrow_vectors(const cpx<double> *src, int64_t ld, const int32_t *n_in, int64_t batch,

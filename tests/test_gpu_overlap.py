@@ -199,3 +199,46 @@ def test_generalized_eigvalsh_random_pencils_two_segments(B, prec):
     n = torch.as_tensor(np.array(sizes, np.int32), device=DEV)
     w = B.mlmc_batched_eigvalsh_generalized(H, S, n).cpu().numpy()
     check_eigs(w, want, sizes, 1e-9 if prec == 0 else 5e-5)
+
+
+def _full_from_lower(Hcm_u, m):
+    """The Hermitian matrix whose lower triangle the column-major block holds."""
+    A = np.array(Hcm_u[:m, :m].T)
+    return np.tril(A) + np.tril(A, -1).conj().T
+
+
+@pytest.mark.parametrize("N,p,K,prec", [(4, 0.2, 2, 0), (8, 0.05, 1, 0), (12, 0.1, 1, 0), (8, 0.05, 1, 1),
+                                        (12, 0.1, 1, 1)])
+def test_eigh_generalized(B, odev, N, p, K, prec):
+    """Eigenstates of the overlap model's pencils (H(k), S(k)) with vacancies:
+    eigenvalues against the oracle's generalised eigenvalues, residuals
+    ||H c - E S c|| and S-orthonormality c^H S c = I within bounds scaled by
+    the condition of S; sides 32 and 128 (LDS-resident) and 288 (banded)."""
+    say(f"[eigh generalized] N={N} p={p} K={K} prec={prec}")
+    mask = B.mlmc_sample_vacancies(odev, N, p, 77, odev.tag(N), 0, 1)
+    kred, _ = B.mlmc_kgrid(0, K)
+    H, n = B.mlmc_build_hamiltonians(odev, N, mask, kred, B.MLMC_C128)
+    S, _ = B.mlmc_build_overlaps(odev, N, mask, kred)
+    dt = torch.complex128 if prec == 0 else torch.complex64
+    Hd, Sd = H.to(dt), S.to(dt)
+    Hin, Sin = Hd.cpu().numpy().astype(np.complex128), Sd.cpu().numpy().astype(np.complex128)  # what the GPU saw
+    w, V = B.mlmc_batched_eigh_generalized(Hd.clone(), Sd.clone(), n)
+    torch.cuda.synchronize()
+    wc, Vc, nc = w.cpu().numpy(), V.cpu().numpy().astype(np.complex128), n.cpu().numpy()
+    eps = np.finfo(np.float64 if prec == 0 else np.float32).eps
+    for u in range(Hin.shape[0]):
+        m = int(nc[u])
+        A, Sm = _full_from_lower(Hin[u], m), _full_from_lower(Sin[u], m)
+        wo = oracle.eigvalsh_generalized(A, Sm)
+        scale = max(1.0, np.abs(wo).max())
+        err = np.abs(wc[u, :m] - wo).max()
+        assert err <= (1e-9 if prec == 0 else 2e-5) * scale, f"unit {u}: eigenvalue error {err:.3e}"
+        X = Vc[u][:m, :m].T  # column i: the eigenvector of w[u, i]
+        kappa = np.linalg.cond(Sm)
+        hn = np.abs(A).sum(axis=0).max() + np.abs(wc[u, :m]).max() * np.abs(Sm).sum(axis=0).max()
+        res = np.linalg.norm(A @ X - (Sm @ X) * wc[u, :m][None, :], axis=0).max()
+        orth = np.abs(X.conj().T @ Sm @ X - np.eye(m)).max()
+        say(f"  unit {u}: n={m} kappa(S)={kappa:.2f} res/(n eps (|H|+|E||S|))={res / (m * eps * hn):.3f} "
+            f"orth/(n eps kappa)={orth / (m * eps * kappa):.3f}")
+        assert res <= 16 * m * eps * hn * kappa, f"unit {u}: residual {res:.3e}"
+        assert orth <= 16 * m * eps * kappa, f"unit {u}: S-orthonormality {orth:.3e}"
