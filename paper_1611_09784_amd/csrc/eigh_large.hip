@@ -1,7 +1,7 @@
-// Eigenvectors of matrices above the LDS-resident size (complex128 or complex64
-// storage, computed in double).  After
-// stage 1 (dense -> band of half-width kB, each panel's block reflector kept)
-// and the eigenvalues (chase + bisection), the eigenvectors are
+// Eigenvectors of matrices above the LDS-resident size (complex128 or
+// complex64 storage, computed in double).  After stage 1 (dense -> band of
+// half-width kB, each panel's block reflector kept) and the eigenvalues
+// (chase + bisection), the eigenvectors are
 //   band_ii_kernel   inverse iteration on the band matrix B, one wavefront
 //                    per eigenvalue: pivoted band LU of B - lam I, two
 //                    solves from a hashed start vector
@@ -122,10 +122,10 @@ struct IILds {
 // Offset of row slot r in the window (a 24-bit multiply: slots are small).
 __device__ __forceinline__ int wrow(int r) { return (int)__umul24((unsigned)r, (unsigned)kWC); }
 
-// The elimination window is a ring: at step k it holds rows k .. k + kB
-// (row r in slot r mod (kB + 1)) and columns k .. k + 2 kB (column c in slot
-// c mod (2 kB + 1)), the rows' slots in that order except that the pivot
-// search reorders them (see band_lu).
+// The elimination window is a ring: at step k it holds row positions
+// k .. k + kB (position r in slot r mod (kB + 1), holding what an explicit
+// row interchange would have put there) and columns k .. k + 2 kB (column c
+// in slot c mod (2 kB + 1)).
 
 // B[r][c] - lam delta_rc of the band matrix of half-width kB whose lower
 // triangle stage 1 left in H (column-major, ld); zero outside the band and
