@@ -505,9 +505,12 @@ __global__ __launch_bounds__(kOrthThreads) void cluster_orth_kernel(const cpx<T>
     __shared__ cpx<double> dots[kOrthThreads];
     __shared__ double red[NW];
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+    // jobs (eigenvalue index, matrix) with the matrix fastest: the matrices of a
+    // batch often have their large clusters at the same indices, which would
+    // otherwise all fall to one workgroup
     for (int64_t job = blockIdx.x; job < batch * ld; job += gridDim.x) {
-        const int64_t u = job / ld;
-        const int i0 = (int)(job % ld);
+        const int64_t u = job % batch;
+        const int i0 = (int)(job / batch);
         const int n = n_in[u];
         if (n < 1 || n > ld || i0 >= n) continue;
         const double *w = w_in + u * ld;
