@@ -714,6 +714,7 @@ struct EighLargeBuffers {
     EigBuffers b;
     double *w = nullptr;  // the bisection's eigenvalues [batch][ld]
     void *keep = nullptr;
+    cpx<double> *tg = nullptr;  // the back-transformation's compound T factors
     void *ii = nullptr;
     cpx<double> *vd = nullptr;  // complex64 input: the vectors [batch][ld][ld] in complex128
 };
@@ -721,6 +722,7 @@ static void carve_eigh_large(Carver &cv, mlmc_precision prec, int64_t ld, int64_
     carve_large(cv, prec, ld, batch, true, L.b);
     L.w = cv.take<double>(sizeof(double) * (size_t)ld * (size_t)batch);
     L.keep = cv.take<void>(cplx_bytes(prec) * (size_t)eigh_keep_elems(ld) * (size_t)batch);
+    L.tg = cv.take<cpx<double>>(sizeof(cpx<double>) * (size_t)eigh_group_t_elems(ld) * (size_t)batch);
     L.ii = cv.take<void>(band_ii_scratch_bytes(ld, batch));
     if (prec != MLMC_PREC_FP64) L.vd = cv.take<cpx<double>>(sizeof(cpx<double>) * (size_t)ld * (size_t)ld * (size_t)batch);
 }
@@ -766,7 +768,7 @@ static mlmc_status eigh_large(mlmc_precision prec, const void *d_H, int64_t ld, 
     rs = run_bisect(d_n, ld, batch, L.w, ld, L.b, s);
     if (rs != MLMC_OK) return rs;
     LAUNCH("eigh_band_ii", s, launch_band_inverse_iteration<T>(Hc, ld, d_n, batch, L.w, d_w, ldw, V, vld, L.ii, s));
-    LAUNCH("eigh_backtransform", s, launch_panel_backtransform<T>(keep, keep_stride, ld, d_n, batch, V, vld, s));
+    LAUNCH("eigh_backtransform", s, launch_panel_backtransform<T>(keep, keep_stride, ld, d_n, batch, V, vld, L.tg, s));
     if (L.vd)
         LAUNCH("eigh_narrow", s, launch_narrow_vectors(L.vd, ld, d_n, batch, static_cast<cpx<float> *>(d_V), ldv, s));
     return MLMC_OK;

@@ -7,8 +7,9 @@
 //                    solves from a hashed start vector
 //   cluster_orth_kernel  the vectors of each cluster of close eigenvalues
 //                    orthonormalised, their Rayleigh quotients, sorted
-//   panel_bt_kernel  X <- (I - V_p T_p V_p^H) X for the panels from last to
-//                    first, which takes B's eigenvectors to H's
+//   group_t_kernel, group_bt_kernel  X <- (I - V T V^H) X for groups of four
+//                    panels from last to first, which takes B's eigenvectors
+//                    to H's
 // The chase's rotations are not needed: B's own eigenvectors are computed.
 #include <cfloat>
 
@@ -586,64 +587,172 @@ __global__ __launch_bounds__(kOrthThreads) void cluster_orth_kernel(const cpx<T>
     }
 }
 
-// Panel p's block reflector applied to 16 columns of X: X <- X - V_p (T_p (V_p^H X))
-// over the rows s = p + kB .. n - 1.  Thread (rr, j) takes column j of the
-// tile and rows s + rr + 16 q.
+// The back-transformation takes the panels four at a time: with V = [V_a]
+// (the four panels' reflectors side by side, zero above each panel's rows)
+// Q_a Q_a+1 Q_a+2 Q_a+3 = I - V T V^H, T upper triangular 64 x 64 with the
+// panels' T_a on its diagonal and, column block by column block,
+// T[0:b, b] = -T[0:b, 0:b] (V[0:b]^H V_b) T_b.  A panel that ran no
+// reflectors (fewer than two rows below its band, or past the last panel)
+// counts as zero.  X is then read twice and written once per four panels.
+constexpr int kGP = 4;         // panels per group
+constexpr int kGR = kGP * kB;  // reflectors per group
+
+__device__ __forceinline__ bool panel_ran(int pi, int npan, int n) { return pi < npan && n - (pi + 1) * kB >= 2; }
+
+// Thread (rr, j): sum over rows r = s + rr + 16 q < n of conj(A[r][i]) B[r][j]
+// for i < 16 (A, B column-major with leading dimensions lda, ldb), summed
+// over the 16 consecutive lanes rr, into dst[i * kB] (LDS, a complex128
+// array) from lane rr = 0; eight i at a time, to bound the registers in flight.
+template <typename TA, typename TB>
+__device__ __forceinline__ void gram16(const cpx<TA> *A, int64_t lda, const cpx<TB> *B, int64_t ldb, int s, int n,
+                                       int rr, int j, cpx<double> *dst) {
+#pragma unroll
+    for (int h = 0; h < kB; h += kB / 2) {
+        cpx<double> part[kB / 2];
+#pragma unroll
+        for (int i = 0; i < kB / 2; ++i) part[i] = {0.0, 0.0};
+        for (int r = s + rr; r < n; r += kB) {
+            const cpx<double> x = ldc(B + (int64_t)j * ldb + r);
+#pragma unroll
+            for (int i = 0; i < kB / 2; ++i) part[i] = c_add(part[i], c_cmul(ldc(A + (int64_t)(h + i) * lda + r), x));
+        }
+#pragma unroll
+        for (int i = 0; i < kB / 2; ++i) {
+#pragma unroll
+            for (int o = 1; o < kB; o <<= 1) {
+                part[i].re += __shfl_xor(part[i].re, o, 64);
+                part[i].im += __shfl_xor(part[i].im, o, 64);
+            }
+            if (rr == 0) dst[(h + i) * kB] = part[i];
+        }
+    }
+}
+
+// One workgroup per (matrix, group of four panels): the group's T into
+// tg + (u G + g) kGR^2, row-major, complex128.
 template <typename T>
-__global__ __launch_bounds__(256) void panel_bt_kernel(const cpx<T> *__restrict__ keep, int64_t keep_stride,
-                                                       int64_t ld, const int32_t *__restrict__ n_in, int64_t batch,
-                                                       cpx<double> *__restrict__ Vall, int64_t ldv, int p,
-                                                       int64_t tiles) {
-    __shared__ cpx<double> Ws[kB][kB], Ys[kB][kB];
+__global__ __launch_bounds__(256) void group_t_kernel(const cpx<T> *__restrict__ keep, int64_t keep_stride,
+                                                      int64_t ld, const int32_t *__restrict__ n_in, int64_t batch,
+                                                      int npan, int groups, cpx<double> *__restrict__ tg) {
+    __shared__ cpx<double> Tp[kGP * (kGP + 1) / 2][kB][kB];  // block (a, b), a <= b, packed by rows
+    __shared__ cpx<double> M[kGP - 1][kB][kB];                // G[c][b] T_b of the current column block b
+    auto Tb = [&](int a, int b) -> cpx<double>(&)[kB][kB] { return Tp[a * kGP - a * (a - 1) / 2 + (b - a)]; };
+    const int64_t u = blockIdx.x / groups;
+    const int g = (int)(blockIdx.x % groups);
+    if (u >= batch) return;
+    const int n = n_in[u];
+    if (n < 1 || n > ld) return;
+    const int t = threadIdx.x, rr = t & (kB - 1), j = t >> 4;
+    const cpx<T> *kp = keep + u * keep_stride;
+    auto vpan = [&](int pi) { return kp + (int64_t)pi * (kB * ld + kB * kB); };
+    for (int a = 0; a < kGP; ++a)
+        for (int b = a; b < kGP; ++b) Tb(a, b)[j][rr] = {0.0, 0.0};
+    __syncthreads();
+    for (int b = 0; b < kGP; ++b) {
+        const int pb = kGP * g + b;
+        if (!panel_ran(pb, npan, n)) continue;  // T_b and its column block stay zero
+        Tb(b, b)[j][rr] = ldc(vpan(pb) + kB * ld + j * kB + rr);
+        __syncthreads();
+        if (b == 0) continue;
+        for (int c = 0; c < b; ++c) {  // M[c] = G[c][b] first, entry (i, j); then G[c][b] T_b
+            const int pc = kGP * g + c;
+            if (panel_ran(pc, npan, n)) gram16(vpan(pc), ld, vpan(pb), ld, (pb + 1) * kB, n, rr, j, &M[c][0][j]);
+            else if (rr == 0)
+                for (int i = 0; i < kB; ++i) M[c][i][j] = {0.0, 0.0};
+            __syncthreads();
+            cpx<double> m = {0.0, 0.0};  // entry (j, rr) of G T_b
+            for (int l = 0; l <= rr; ++l) m = c_add(m, c_mul(M[c][j][l], Tb(b, b)[l][rr]));
+            __syncthreads();
+            M[c][j][rr] = m;
+            __syncthreads();
+        }
+        for (int a = 0; a < b; ++a) {  // T[a][b] = -sum_{c = a}^{b - 1} T[a][c] M[c]
+            cpx<double> x = {0.0, 0.0};
+            for (int c = a; c < b; ++c)
+                for (int l = 0; l < kB; ++l) x = c_add(x, c_mul(Tb(a, c)[j][l], M[c][l][rr]));
+            Tb(a, b)[j][rr] = {-x.re, -x.im};
+        }
+        __syncthreads();
+    }
+    cpx<double> *out = tg + ((int64_t)u * groups + g) * kGR * kGR;
+    for (int idx = t; idx < kGR * kGR; idx += 256) {
+        const int r = idx / kGR, c = idx % kGR, a = r / kB, b = c / kB;
+        st2(out + idx, a <= b ? Tb(a, b)[r % kB][c % kB] : cpx<double>{0.0, 0.0});
+    }
+}
+
+// Group g of four panels applied to 16 columns of X: X <- X - V (T (V^H X))
+// over the rows below the group's first panel.  V^H X: thread (b, j, rr) of
+// 1024 takes panel b, column j and rows p_b + kB + rr + 16 q; T (V^H X): one
+// entry per thread; the update: wavefront w takes the 16-row blocks w, w + 16,
+// ..., lane (row l, column group cg) the row's four columns 4 cg .. 4 cg + 3,
+// so that every reflector row is read once per workgroup.
+template <typename T>
+__global__ __launch_bounds__(1024) void group_bt_kernel(const cpx<T> *__restrict__ keep, int64_t keep_stride,
+                                                        int64_t ld, const int32_t *__restrict__ n_in, int64_t batch,
+                                                        int npan, int groups, const cpx<double> *__restrict__ tg,
+                                                        int g, cpx<double> *__restrict__ Vall, int64_t ldv,
+                                                        int64_t tiles) {
+    __shared__ cpx<double> Ws[kGR][kB], Ys[kGR][kB];
     const int64_t u = blockIdx.x / tiles;
     const int tile = (int)(blockIdx.x % tiles);
     if (u >= batch) return;
     const int n = n_in[u];
-    const int s = p + kB, m = n - s;
-    if (n < 1 || n > ld || m < 2) return;  // the panel had no reflectors
+    if (n < 1 || n > ld || !panel_ran(kGP * g, npan, n)) return;  // no reflectors in the group
     const int col0 = tile * kB;
     if (col0 >= n) return;
-    const cpx<T> *Vp = keep + u * keep_stride + (int64_t)(p / kB) * (kB * ld + kB * kB);
-    const cpx<T> *Tp = Vp + kB * ld;
+    const int t = threadIdx.x, s0 = (kGP * g + 1) * kB;
+    const cpx<T> *kp = keep + u * keep_stride;
     cpx<double> *X = Vall + u * ldv * ldv;
-    const int t = threadIdx.x, rr = t & 15, j = t >> 4, col = col0 + j;
-    const bool live = col < n;
-    cpx<double> acc[kB];
-#pragma unroll
-    for (int i = 0; i < kB; ++i) acc[i] = {0.0, 0.0};
-    if (live) {
-        for (int r = s + rr; r < n; r += kB) {
-            const cpx<double> x = X[(int64_t)col * ldv + r];
-#pragma unroll
-            for (int i = 0; i < kB; ++i) acc[i] = c_add(acc[i], c_cmul(ldc(Vp + (int64_t)i * ld + r), x));
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < kB; ++i) {  // over the 16 consecutive lanes of a column
-#pragma unroll
-        for (int o = 1; o < 16; o <<= 1) {
-            acc[i].re += __shfl_xor(acc[i].re, o, 64);
-            acc[i].im += __shfl_xor(acc[i].im, o, 64);
-        }
-    }
-    if (rr == 0) {
-#pragma unroll
-        for (int i = 0; i < kB; ++i) Ws[i][j] = acc[i];
+    {
+        const int rr = t & (kB - 1), j = (t >> 4) & (kB - 1), b = t >> 8, pb = kGP * g + b;
+        const int col = min(col0 + j, n - 1);
+        if (panel_ran(pb, npan, n))
+            gram16(kp + (int64_t)pb * (kB * ld + kB * kB), ld, X + (int64_t)col * ldv, ldv, (pb + 1) * kB,
+                   col0 + j < n ? n : 0, rr, 0, &Ws[b * kB][j]);
+        else if (rr == 0)
+            for (int i = 0; i < kB; ++i) Ws[b * kB + i][j] = {0.0, 0.0};
     }
     __syncthreads();
-    {  // Y = T W, T upper triangular: entry (rr, j)
-        cpx<double> yv = {0.0, 0.0};
-        for (int l = rr; l < kB; ++l) yv = c_add(yv, c_mul(ldc(Tp + rr * kB + l), Ws[l][j]));
-        Ys[rr][j] = yv;
+    {
+        const int i = t >> 4, j = t & (kB - 1);
+        const cpx<double> *trow = tg + ((int64_t)u * groups + g) * kGR * kGR + (int64_t)i * kGR;
+        cpx<double> y = {0.0, 0.0};
+        for (int l = i; l < kGR; ++l) y = c_add(y, c_mul(ld2(trow + l), Ws[l][j]));
+        Ys[i][j] = y;
     }
     __syncthreads();
-    if (live) {
-        for (int r = s + rr; r < n; r += kB) {
-            cpx<double> sum = {0.0, 0.0};
+    const int wv = t >> 6, l = t & (kB - 1), cg = (t >> 4) & 3;
+    for (int r0 = s0 + kB * wv; r0 < n; r0 += kB * (1024 / 64)) {
+        const int r = r0 + l;
+        cpx<double> acc[4] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+        if (r < n) {
+#pragma unroll 1
+            for (int b = 0; b < kGP; ++b) {
+                const int pb = kGP * g + b;
+                if (!panel_ran(pb, npan, n) || r < (pb + 1) * kB) continue;
+                const cpx<T> *vb = kp + (int64_t)pb * (kB * ld + kB * kB) + r;
 #pragma unroll
-            for (int i = 0; i < kB; ++i) sum = c_add(sum, c_mul(ldc(Vp + (int64_t)i * ld + r), Ys[i][j]));
-            cpx<double> &x = X[(int64_t)col * ldv + r];
-            x = c_sub(x, sum);
+                for (int h = 0; h < kB; h += kB / 2) {
+                    cpx<double> v8[kB / 2];  // eight of the row's reflector entries in flight together
+#pragma unroll
+                    for (int i = 0; i < kB / 2; ++i) v8[i] = ldc(vb + (int64_t)(h + i) * ld);
+#pragma unroll
+                    for (int i = 0; i < kB / 2; ++i) {
+                        const cpx<double> *yrow = &Ys[b * kB + h + i][4 * cg];
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) acc[c] = c_add(acc[c], c_mul(v8[i], yrow[c]));
+                    }
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int col = col0 + 4 * cg + c;
+                if (col < n) {
+                    cpx<double> *x = X + (int64_t)col * ldv + r;
+                    st2(x, c_sub(ld2(x), acc[c]));
+                }
+            }
         }
     }
 }
@@ -718,15 +827,19 @@ hipError_t launch_band_inverse_iteration(const cpx<T> *H, int64_t ld, const int3
 
 template <typename T>
 hipError_t launch_panel_backtransform(const cpx<T> *keep, int64_t keep_stride, int64_t ld, const int32_t *n_in,
-                                      int64_t batch, cpx<double> *V, int64_t ldv, hipStream_t s) {
+                                      int64_t batch, cpx<double> *V, int64_t ldv, cpx<double> *tg, hipStream_t s) {
     if (batch == 0) return hipSuccess;
+    const int npan = eigh_panels(ld), groups = eigh_panel_groups(ld);
+    if (groups == 0) return hipSuccess;
+    hipLaunchKernelGGL(group_t_kernel<T>, dim3((unsigned)(batch * groups)), dim3(256), 0, s, keep, keep_stride, ld,
+                       n_in, batch, npan, groups, tg);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
     const int64_t tiles = (ld + kB - 1) / kB;
-    int last = -1;
-    for (int p = 0; p + kB + 1 < ld; p += kB) last = p;  // the panels stage 1 ran
-    for (int p = last; p >= 0; p -= kB) {
-        hipLaunchKernelGGL(panel_bt_kernel<T>, dim3((unsigned)(batch * tiles)), dim3(256), 0, s, keep, keep_stride,
-                           ld, n_in, batch, V, ldv, p, tiles);
-        const hipError_t err = hipGetLastError();
+    for (int g = groups - 1; g >= 0; --g) {
+        hipLaunchKernelGGL(group_bt_kernel<T>, dim3((unsigned)(batch * tiles)), dim3(1024), 0, s, keep, keep_stride,
+                           ld, n_in, batch, npan, groups, tg, g, V, ldv, tiles);
+        err = hipGetLastError();
         if (err != hipSuccess) return err;
     }
     return hipSuccess;
@@ -739,7 +852,7 @@ hipError_t launch_panel_backtransform(const cpx<T> *keep, int64_t keep_stride, i
                                                          const double *, double *, int64_t, cpx<double> *, int64_t,  \
                                                          void *, hipStream_t);                                       \
     template hipError_t launch_panel_backtransform<T>(const cpx<T> *, int64_t, int64_t, const int32_t *, int64_t,     \
-                                                      cpx<double> *, int64_t, hipStream_t);
+                                                      cpx<double> *, int64_t, cpx<double> *, hipStream_t);
 MLMC_EIGH_LARGE(double)
 MLMC_EIGH_LARGE(float)
 #undef MLMC_EIGH_LARGE

@@ -63,11 +63,19 @@ hipError_t launch_band_inverse_iteration(const cpx<T> *H, int64_t ld, const int3
                                          const double *w_in, double *w_out, int64_t ldw, cpx<double> *V, int64_t ldv,
                                          void *scratch, hipStream_t s);
 
+// Panels stage 1 runs for side bound ld (p = 0, 16, ... while p + kB + 1 < ld),
+// and groups of four of them.
+inline int eigh_panels(int64_t ld) { return ld > kB + 1 ? (int)((ld - kB - 2) / kB + 1) : 0; }
+inline int eigh_panel_groups(int64_t ld) { return (eigh_panels(ld) + 3) / 4; }
+// Complex128 elements of one matrix's compound T factors (64 x 64 per group).
+inline int64_t eigh_group_t_elems(int64_t ld) { return (int64_t)eigh_panel_groups(ld) * 64 * 64; }
+
 // V_u <- Q_u V_u, Q_u = (I - V_0 T_0 V_0^H) ... (I - V_P T_P V_P^H) from the
-// reflector store (complex128 or complex64, widened).
+// reflector store (complex128 or complex64, widened), four panels at a time
+// (tg: batch * eigh_group_t_elems(ld) complex128 elements of scratch).
 template <typename T>
 hipError_t launch_panel_backtransform(const cpx<T> *keep, int64_t keep_stride, int64_t ld, const int32_t *n_in,
-                                      int64_t batch, cpx<double> *V, int64_t ldv, hipStream_t s);
+                                      int64_t batch, cpx<double> *V, int64_t ldv, cpx<double> *tg, hipStream_t s);
 
 // X_u <- L_u^{-H} X_u for the columns and rows 0..n_u-1 (L_u lower
 // triangular with a real positive diagonal, column-major, ld; X_u
