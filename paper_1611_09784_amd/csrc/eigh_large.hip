@@ -442,8 +442,11 @@ __device__ __forceinline__ double cluster_tol(const double *w, int n) {
 // members of a cluster run in parallel; cluster_orth_kernel orthogonalises
 // them afterwards.  Jobs (matrix, eigenvalue) are taken in a fixed stride
 // over the grid.
+// (Three wavefronts per SIMD: a few registers go to scratch, and the ten
+// wavefronts per CU that the LDS then allows hide more of each step's latency
+// than the eight that fit without spilling.)
 template <typename T>
-__global__ __launch_bounds__(64) void band_ii_kernel(const cpx<T> *__restrict__ Hall, int64_t ld,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void band_ii_kernel(const cpx<T> *__restrict__ Hall, int64_t ld,
                                                      const int32_t *__restrict__ n_in, int64_t batch,
                                                      const double *__restrict__ w_in, double *__restrict__ w_out,
                                                      int64_t ldw, cpx<double> *__restrict__ Vall, int64_t ldv,
@@ -815,8 +818,19 @@ hipError_t launch_band_inverse_iteration(const cpx<T> *H, int64_t ld, const int3
     hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(band_ii_kernel<T>),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(band_ii_kernel<T>, dim3((unsigned)band_ii_waves(ld, batch)), dim3(64), (size_t)lds, s, H, ld,
-                       n_in, batch, w_in, w_out, ldw, V, ldv, static_cast<char *>(scratch), band_ii_wave_bytes(ld));
+    // as many wavefronts as the CUs hold at once (registers and LDS), within the
+    // workspace's slices
+    int per_cu = 0, dev = 0, cus = 0;
+    err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(band_ii_kernel<T>), 64,
+                                                       (size_t)lds);
+    if (err != hipSuccess) return err;
+    err = hipGetDevice(&dev);
+    if (err != hipSuccess) return err;
+    err = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (err != hipSuccess) return err;
+    const int64_t waves = std::max<int64_t>(1, std::min<int64_t>(band_ii_waves(ld, batch), (int64_t)per_cu * cus));
+    hipLaunchKernelGGL(band_ii_kernel<T>, dim3((unsigned)waves), dim3(64), (size_t)lds, s, H, ld, n_in, batch, w_in,
+                       w_out, ldw, V, ldv, static_cast<char *>(scratch), band_ii_wave_bytes(ld));
     err = hipGetLastError();
     if (err != hipSuccess) return err;
     const int64_t groups = std::min<int64_t>(batch * ld, 2048);

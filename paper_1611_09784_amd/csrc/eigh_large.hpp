@@ -29,7 +29,7 @@ hipError_t launch_band_reduce_keep(cpx<T> *H, int64_t ld, const int32_t *n_in, i
 // iterated vector.  LDS: the (kB + 1) x (2 kB + 1) elimination window,
 // kIIStep steps of incoming band rows and of outgoing factors, a ring of
 // kIIYRing entries of the iterated vector.
-constexpr int kIIStep = 8;
+constexpr int kIIStep = 4;
 constexpr int kIIYRing = 64;
 inline int64_t band_ii_wave_bytes(int64_t ld) {
     return ((ld + kIIStep) * ((3 * kB + 1) * 16 + 4) + ld * 16 + 255) / 256 * 256;
@@ -37,8 +37,9 @@ inline int64_t band_ii_wave_bytes(int64_t ld) {
 inline int64_t band_ii_lds_bytes(int64_t) {
     return 16 * ((kB + 1) * (2 * kB + 1) + kIIStep * (2 * (2 * kB + 1) + kB) + kIIYRing) + 4 * kIIStep;
 }
-// Wavefronts of one launch: what the CUs hold at once (LDS-bound, at most
-// four per SIMD), and no more than the eigenvalues of the batch.
+// Wavefronts (scratch slices) of one launch: what the CUs' LDS holds at once
+// (at most four per SIMD), and no more than the eigenvalues of the batch; the
+// launch takes fewer when registers allow fewer per CU.
 inline int64_t band_ii_waves(int64_t ld, int64_t batch) {
     const int64_t per_cu = std::min<int64_t>(16, (160 * 1024) / band_ii_lds_bytes(ld));
     return std::max<int64_t>(1, std::min<int64_t>(256 * per_cu, batch * ld));
