@@ -201,7 +201,7 @@ def copy_calibration():
     print(json.dumps({"copy_bytes": n, "copies": 3}), flush=True)
 
 
-def time_to_tol(B, dev, wl_name="graphene_mlmc", variants=None, oracle_samples=None):
+def time_to_tol(B, dev, wl_name="graphene_mlmc", variants=None, oracle_samples=None, ctx=None):
     """MLMC IDoS estimator of the graphene level hierarchy N = 4, 8, 16, 32
     (Gamma-centred K = 32 / N, p = 0.02, seed 303) run to TOL = 1e-3 relative
     with the FP64 path, the mixed path (FP32 reduction, FP64 bisection and
@@ -212,7 +212,9 @@ def time_to_tol(B, dev, wl_name="graphene_mlmc", variants=None, oracle_samples=N
     and graph-captured level calls on the LDS-resident levels.
     Beside each time: the per-level samples and the final statistical error;
     then each path's IDoS error against the FP64 oracle on the same coupled
-    samples of every level (8, or 4 at N = 32)."""
+    samples of every level (8, or 4 at N = 32).  The tuner's trials and every
+    estimator run on one pipeline context (the caller's, else one made
+    here)."""
     import torch
     from mlmc_inputs import WORKLOADS
     from mlmc_inputs.configs import workload_eps
@@ -222,6 +224,9 @@ def time_to_tol(B, dev, wl_name="graphene_mlmc", variants=None, oracle_samples=N
     lat = wl.make_lattice()
     eps = workload_eps(wl)
     dlat = B.DeviceLattice(lat, 0)
+    own_ctx = ctx is None
+    if own_ctx:
+        ctx = B.Context(0)
     Ks = [wl.NK // N for N in wl.levels] if wl.NK else [wl.K] * len(wl.levels)
     out = {"workload": wl.name, "levels": list(wl.levels), "K": Ks, "tol_rel": wl.tol}
     from paper_1611_09784_amd.autotune import Tuner
@@ -232,7 +237,8 @@ def time_to_tol(B, dev, wl_name="graphene_mlmc", variants=None, oracle_samples=N
     for prec, pname in ((B.MLMC_PREC_FP64, "fp64"), (B.MLMC_PREC_MIXED, "mixed")):
         d_eps = torch.as_tensor(eps, device=dev)
         for st in D.make_levels(wl.levels, Ks):
-            t = tuner.tune_level(dlat, st.N, st.coupled, st.K, st.K_coarse, wl.kgrid, prec, d_eps, wl.delta, wl.p)
+            t = tuner.tune_level(dlat, st.N, st.coupled, st.K, st.K_coarse, wl.kgrid, prec, d_eps, wl.delta, wl.p,
+                                 ctx=ctx)
             tunings.setdefault(pname, []).append({"N": st.N, "chunk": t.chunk, "chase_workgroups": t.chase_workgroups,
                                                   "update_tile_rows": t.update_tile_rows, "trials": t.trials})
     out["tuning"] = {"seconds": round(time.perf_counter() - t_tune, 2), "levels": tunings}
@@ -242,7 +248,7 @@ def time_to_tol(B, dev, wl_name="graphene_mlmc", variants=None, oracle_samples=N
                     ("mixed_tuned", B.MLMC_PREC_MIXED, 0, True), ("mixed_tuned_reuse", B.MLMC_PREC_MIXED, 128, True))
     for name, prec, dedup, tuned in variants:
         est = D.Estimator(dlat, eps, wl.delta, wl.p, wl.kgrid, wl.seed, wl.smoother, prec, chunk_samples=32,
-                          dedup_max_orbitals=dedup, tuner=tuner if tuned else None, graphs=tuned)
+                          dedup_max_orbitals=dedup, tuner=tuner if tuned else None, graphs=tuned, ctx=ctx)
         for st in D.make_levels(wl.levels, Ks):  # warm-up: workspaces and first launches
             est.add_samples(st, 2)
         torch.cuda.synchronize(dev)
@@ -274,7 +280,8 @@ def time_to_tol(B, dev, wl_name="graphene_mlmc", variants=None, oracle_samples=N
         want = oracle.level_estimate(lat, st.N, st.coupled, wl.p, st.K, st.K_coarse, wl.kgrid, wl.seed, 0, ns, eps,
                                      wl.delta, wl.smoother, n_threads=host_threads())
         for name, prec in (("fp64", B.MLMC_PREC_FP64), ("mixed", B.MLMC_PREC_MIXED)):
-            est = D.Estimator(dlat, eps, wl.delta, wl.p, wl.kgrid, wl.seed, wl.smoother, prec, chunk_samples=8)
+            est = D.Estimator(dlat, eps, wl.delta, wl.p, wl.kgrid, wl.seed, wl.smoother, prec, chunk_samples=8,
+                              ctx=ctx)
             lv = D.make_levels(wl.levels, Ks)[l]
             est.add_samples(lv, ns)
             est.close()
@@ -285,6 +292,8 @@ def time_to_tol(B, dev, wl_name="graphene_mlmc", variants=None, oracle_samples=N
     for other in ("mixed", "mixed_reuse", "mixed_tuned", "fp64_tuned"):
         if other in out and "fp64" in out:
             out[f"speedup_{other}_vs_fp64"] = round(out["fp64"]["seconds"] / out[other]["seconds"], 3)
+    if own_ctx:
+        ctx.close()
     dlat.close()
     return out
 
@@ -334,12 +343,13 @@ KERNEL_NAMES = ("sample_vacancies", "kgrid", "assemble", "small_fused", "overlap
                 "bisect", "idos", "level_stats")
 
 
-def measure(B, wl, lat, eps, prec, args, dev):
+def measure(B, wl, lat, eps, prec, args, dev, ctx):
     """Eigensolves/s of `args.steps` level calls of `args.batch` samples
-    (after `args.warmup` untimed ones) with precision `prec`, the per-kernel
-    event times of the timed calls and the chase's roofline.  With --tune the
-    chunk size, chase workgroups and update tile come from the autotuner
-    (measured before the timed calls)."""
+    (after `args.warmup` untimed ones) with precision `prec` on the pipeline
+    context `ctx`, the per-kernel event times of the timed calls and the
+    chase's roofline.  With --tune the chunk size, chase workgroups and
+    update tile come from the autotuner (measured before the timed calls, on
+    the same context and streams)."""
     import torch
     dlat = B.DeviceLattice(lat, 0)
     d_eps = torch.as_tensor(eps, device=dev)
@@ -352,7 +362,8 @@ def measure(B, wl, lat, eps, prec, args, dev):
         t0 = time.perf_counter()
         tuner = Tuner(min_seconds=1.0, chunks=(16, 32, 64), budget_bytes=64 << 30,
                       chase_fractions=(0.625, 0.75, 0.875, 1.0), max_trial_seconds=30.0, verbose=True)
-        t = tuner.tune_level(dlat, N, False, K, K, wl.kgrid, prec, d_eps, wl.delta, wl.p, samples_per_call=args.batch)
+        t = tuner.tune_level(dlat, N, False, K, K, wl.kgrid, prec, d_eps, wl.delta, wl.p, samples_per_call=args.batch,
+                             ctx=ctx)
         chunk = t.chunk
         tuning = {"chunk": t.chunk, "chase_workgroups": t.chase_workgroups, "update_tile_rows": t.update_tile_rows,
                   "trials": t.trials, "seconds": round(time.perf_counter() - t0, 2)}
@@ -360,9 +371,10 @@ def measure(B, wl, lat, eps, prec, args, dev):
     need = B.mlmc_level_workspace(dlat, N, False, K, K, wl.kgrid, chunk, prec, eps.size)
     work = torch.empty((need,), dtype=torch.uint8, device=dev)
     stats = torch.zeros((4, eps.size), dtype=torch.float64, device=dev)
-    ctx = B.Context(0)
     if args.tune:
         ctx.configure(chase_workgroups=t.chase_workgroups, update_tile_rows=t.update_tile_rows)
+    else:
+        ctx.configure()
     # Consecutive steps are consecutive level-estimate calls of one context on
     # one workspace; on alternating streams a call's front part starts while
     # the previous call's last chunk is still chased and bisected (the sums
@@ -416,7 +428,8 @@ def measure(B, wl, lat, eps, prec, args, dev):
         ms, cnt, dropped = ctx.timer_read(name)
         if cnt:
             kernels[name] = {"ms": round(ms, 3), "launches": cnt}
-    ctx.close()
+    ctx.timer(0)  # no event records in the later calls on this context
+    ctx.configure()
     solves = args.steps * args.batch * nk
     value = solves / elapsed
 
@@ -504,7 +517,7 @@ def stage1_flops_bytes(n: int, ld: int, esize: int) -> dict:
     return out
 
 
-def stage1_roofline(B, dev, prec, N=32, samples=32):
+def stage1_roofline(B, dev, prec, ctx, N=32, samples=32):
     """Kernel-by-kernel roofline of the dense-to-band stage at n ~ 2000
     (graphene N = 32, one k-point, p = 0.02): one level call of `samples`
     samples in a single chunk, so that the stage runs alone on the chip
@@ -522,20 +535,21 @@ def stage1_roofline(B, dev, prec, N=32, samples=32):
     stats = torch.zeros((4, 401), dtype=torch.float64, device=dev)
     ld = lat.n_orb * N * N
     panels = -(-(ld - 17) // 16)
-    with B.Context(0) as ctx:
-        def call(first):
-            B.mlmc_level_estimate(dlat, N, False, p, K, K, kind, seed, first, samples, eps, 0.05,
-                                  B.MLMC_SMOOTH_GAUSS, prec, stats=stats, work=work, ctx=ctx)
-        ctx.timer(8 * panels + 64, detail=True)
-        call(1 << 41)  # warm-up: first launches, first touch of the workspace
-        torch.cuda.synchronize()
-        ctx.timer(8 * panels + 64, detail=True)  # forget the warm-up's records
-        call(0)
-        torch.cuda.synchronize()
-        rec = {}
-        for name in ("band_reduce", "s1_panel", "s1_hemm", "s1_wfactor", "s1_update", "chase", "bisect"):
-            ms, cnt, dropped = ctx.timer_read(name)
-            rec[name] = (ms, cnt, dropped)
+
+    def call(first):
+        B.mlmc_level_estimate(dlat, N, False, p, K, K, kind, seed, first, samples, eps, 0.05,
+                              B.MLMC_SMOOTH_GAUSS, prec, stats=stats, work=work, ctx=ctx)
+    ctx.timer(8 * panels + 64, detail=True)
+    call(1 << 41)  # warm-up: first launches, first touch of the workspace
+    torch.cuda.synchronize()
+    ctx.timer(8 * panels + 64, detail=True)  # forget the warm-up's records
+    call(0)
+    torch.cuda.synchronize()
+    rec = {}
+    for name in ("band_reduce", "s1_panel", "s1_hemm", "s1_wfactor", "s1_update", "chase", "bisect"):
+        ms, cnt, dropped = ctx.timer_read(name)
+        rec[name] = (ms, cnt, dropped)
+    ctx.timer(0)
     masks = B.mlmc_sample_vacancies(dlat, N, p, seed, dlat.tag(N), 0, samples).cpu().numpy()
     orb_per_group = np.bincount(lat.orb_group, minlength=lat.n_groups)
     vac = (masks.reshape(samples, -1, lat.n_groups) * orb_per_group).sum(axis=(1, 2))
@@ -746,13 +760,21 @@ def main():
     N, K = wl.N, wl.K
     nk = B.mlmc_kgrid_points(wl.kgrid, K)
 
-    main_run = measure(B, wl, lat, eps, prec, args, dev)
-    second = measure(B, wl, lat, eps, other, args, dev) if args.second else None
+    # One pipeline context for every level call of the run (tuning trials,
+    # both precisions, the stage-1 roofline, the MLMC estimators): contexts
+    # made and destroyed on the way would change which of the runtime's few
+    # hardware queues the next context's streams share (streams on one queue
+    # run in order; measured: 25.9k FP64 eigensolves/s on a fresh context,
+    # 23.0k on one made after the tuner's per-trial contexts).
+    ctx = B.Context(0)
+    main_run = measure(B, wl, lat, eps, prec, args, dev, ctx)
+    second = measure(B, wl, lat, eps, other, args, dev, ctx) if args.second else None
 
-    ttt = time_to_tol(B, dev) if args.mlmc else None
+    ttt = time_to_tol(B, dev, ctx=ctx) if args.mlmc else None
     s1 = None
     if args.stage1:
-        s1 = [stage1_roofline(B, dev, q) for q in (B.MLMC_PREC_FP64, B.MLMC_PREC_MIXED)]
+        s1 = [stage1_roofline(B, dev, q, ctx) for q in (B.MLMC_PREC_FP64, B.MLMC_PREC_MIXED)]
+    ctx.close()
     eigh = None
     if args.eigh:
         eigh = [eigh_throughput(B, dev, q) for q in (B.MLMC_PREC_FP64, B.MLMC_PREC_MIXED)]

@@ -97,8 +97,9 @@ class Tuner:
 
     # -- one measurement ----------------------------------------------------
     def _measure(self, dlat, N, coupled, K, Kc, kind, prec, eps, delta, p, seed, chunk, cfg, first,
-                 samples_per_call=None):
-        """Samples/s of consecutive level calls with the given choices."""
+                 samples_per_call=None, ctx=None):
+        """Samples/s of consecutive level calls with the given choices, on
+        the caller's context if one is given (else on a context of its own)."""
         dev = dlat.device
         need = B.mlmc_level_workspace(dlat, N, coupled, K, Kc, kind, chunk, prec, eps.shape[0])
         work = torch.empty((need,), dtype=torch.uint8, device=dev)
@@ -109,7 +110,10 @@ class Tuner:
         # so that every chunk but the last of the window runs in the pipelined
         # shape being measured.
         per_call = 4 * chunk if samples_per_call is None else int(samples_per_call)
-        with B.Context(dev.index) as ctx:
+        own = ctx is None
+        if own:
+            ctx = B.Context(dev.index)
+        try:
             ctx.configure(chase_workgroups=cfg.chase_workgroups, update_tile_rows=cfg.update_tile_rows)
             streams = [ctx.stream(0), ctx.stream(1)]
             streams[0].wait_stream(torch.cuda.current_stream(dev))  # the workspace is ready
@@ -131,14 +135,28 @@ class Tuner:
             torch.cuda.synchronize(dev)
             el = time.perf_counter() - t0
             first += (calls + 2) * per_call
+        finally:
+            if own:
+                ctx.close()
+            else:
+                ctx.configure()  # back to the library's defaults
         del work
         return calls * per_call / el, first, el / calls
 
     # -- coordinate descent -------------------------------------------------
     def tune_level(self, dlat, N, coupled, K, Kc, kind, prec, eps, delta, p, seed=987654321, retune=False,
-                   max_chunk=None, samples_per_call=None) -> LevelTuning:
+                   max_chunk=None, samples_per_call=None, ctx=None) -> LevelTuning:
         """Launch choices for one level configuration.  samples_per_call:
-        the size of the calls the caller makes (default four chunks)."""
+        the size of the calls the caller makes (default four chunks).  ctx:
+        the pipeline context the caller will run the level on; the trials
+        then run on its streams (left configured with the library's defaults
+        afterwards), which is what they should measure.  A context made and
+        destroyed per trial is not the same thing: the runtime hands out a
+        few hardware queues per process and gives each new stream the least
+        used one, so after streams have come and gone a new context's chase
+        stream can share a queue with one of its caller streams, and work on
+        one queue runs in order (the chase then no longer overlaps the next
+        chunk's reduction)."""
         eps = eps if isinstance(eps, torch.Tensor) else torch.as_tensor(np.asarray(eps, dtype=np.float64),
                                                                         device=dlat.device)
         key = level_key(dlat, N, coupled, K, Kc, kind, prec, eps.shape[0]) + \
@@ -161,7 +179,7 @@ class Tuner:
             cfg = LevelTuning(chunk=c)
             t0 = time.perf_counter()
             r, first, per_call = self._measure(dlat, N, coupled, K, Kc, kind, prec, eps, delta, p, seed, c, cfg,
-                                               first, samples_per_call)
+                                               first, samples_per_call, ctx)
             slow = time.perf_counter() - t0 > self.max_trial_seconds
             trials += 1
             rates[c] = r
@@ -185,7 +203,7 @@ class Tuner:
                     if (g, tile) == (int(cus * 0.75), 32) and best.chase_workgroups == 0:
                         continue  # the default, measured above
                     r, first, _ = self._measure(dlat, N, coupled, K, Kc, kind, prec, eps, delta, p, seed,
-                                                best.chunk, cfg, first, samples_per_call)
+                                                best.chunk, cfg, first, samples_per_call, ctx)
                     trials += 1
                     if self.verbose:
                         print(f"[tune] {key} chase {g} tile {tile}: {r:.1f} samples/s", file=sys.stderr, flush=True)

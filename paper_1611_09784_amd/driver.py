@@ -54,20 +54,25 @@ class MLMCResult:
 
 
 class Estimator:
-    """Runs level calls on one device with a reusable workspace and its own
-    pipeline context (the chase and back streams of the level calls);
-    ``close()`` releases the context."""
+    """Runs level calls on one device with a reusable workspace and a
+    pipeline context (the chase and back streams of the level calls): the
+    caller's ``ctx``, which it keeps, or one of its own that ``close()``
+    releases.  A process that runs several estimators one after another
+    does best to give them one long-lived context: streams that come and go
+    change which of the runtime's few hardware queues a new context's
+    streams share, and streams on one queue run their work in order."""
 
     def __init__(self, dlat: B.DeviceLattice, eps: np.ndarray, delta: float, p: float, kind: int, seed: int,
                  smoother: int = B.MLMC_SMOOTH_GAUSS, prec: int = B.MLMC_PREC_FP64, chunk_samples: int = 64,
                  stream=None, dedup_max_orbitals: int = 0, tuner=None, graphs: bool = False,
-                 budget_bytes: int = 48 << 30):
+                 budget_bytes: int = 48 << 30, ctx: B.Context = None):
         self.dlat = dlat
         self.eps = torch.as_tensor(np.asarray(eps, dtype=np.float64), device=dlat.device)
         self.delta, self.p, self.kind, self.seed = float(delta), float(p), int(kind), int(seed)
         self.smoother, self.prec, self.chunk = int(smoother), int(prec), int(chunk_samples)
         self.stream = stream
-        self.ctx = B.Context(dlat.device.index)
+        self._own_ctx = ctx is None
+        self.ctx = B.Context(dlat.device.index) if ctx is None else ctx
         self._work = {}
         # tuner: an autotune.Tuner; each level then takes its measured chunk
         # size and launch choices.  graphs: levels on the LDS-resident path
@@ -91,7 +96,7 @@ class Estimator:
             return None
         if key not in self._tuned:
             self._tuned[key] = self.tuner.tune_level(self.dlat, lvl.N, lvl.coupled, lvl.K, lvl.K_coarse, self.kind,
-                                                     self.prec, self.eps, self.delta, self.p)
+                                                     self.prec, self.eps, self.delta, self.p, ctx=self.ctx)
         return self._tuned[key]
 
     def _chunk(self, lvl: LevelState) -> int:
@@ -136,6 +141,8 @@ class Estimator:
                 t = self._tuning(lvl)
                 if t is not None:
                     t.configure(self.ctx)
+                else:
+                    self.ctx.configure()  # the library's defaults (a shared context may hold other choices)
                 B.mlmc_level_estimate(self.dlat, lvl.N, lvl.coupled, self.p, lvl.K, lvl.K_coarse, self.kind,
                                       self.seed, lvl.M + done, count - done, self.eps, self.delta, self.smoother,
                                       self.prec, stats=stats, work=self._workspace(lvl), ctx=self.ctx,
@@ -154,9 +161,9 @@ class Estimator:
         return self._graph[key]
 
     def close(self):
-        if self.ctx is not None:
+        if self.ctx is not None and self._own_ctx:
             self.ctx.close()
-            self.ctx = None
+        self.ctx = None
         self._work.clear()
         self._graph.clear()
         self._outcomes.clear()
