@@ -6,6 +6,8 @@
   samples bit for bit (fused path, coupled fused path, two-stage path).
 * The autotuner returns launch choices from measured runs, caches them, and a
   tuned estimator's level sums equal the untuned ones to rounding.
+* The tuner's trials and several estimators on one caller-owned context give
+  the level sums of estimators with contexts of their own.
 """
 
 import os
@@ -92,3 +94,34 @@ def test_autotuner_choices_cached_and_results_unchanged(B, gdev, tmp_path):
     plain.close()
     tuned.close()
     assert np.allclose(lv_a.stats, lv_b.stats, rtol=1e-12, atol=1e-14)
+
+
+def test_estimators_and_tuner_on_a_shared_context(B, gdev, tmp_path):
+    """The tuner's trials and several estimators on one caller-owned context:
+    closing an estimator leaves the context open, a plain estimator resets
+    launch choices a tuned one left on it (its level sums equal those of an
+    estimator with a context of its own bit for bit), and a tuned one equals
+    them to rounding."""
+    import paper_1611_09784_amd.driver as D
+    from paper_1611_09784_amd.autotune import Tuner
+    eps = energy_grid(-9.0, 9.0, 101)
+    say("[shared ctx] tuning graphene N = 16, K = 1 on the caller's context")
+    with B.Context(0) as ctx:
+        tuner = Tuner(cache_path=str(tmp_path / "tune.json"), min_seconds=0.05, chunks=(4, 8))
+        t = tuner.tune_level(gdev, 16, False, 1, 1, B.MLMC_KGRID_GAMMA, 0, eps, 0.05, 0.02, ctx=ctx)
+        assert t.chunk in (4, 8) and t.trials >= 2
+        levels = [D.make_levels((16,), [1])[0] for _ in range(3)]
+        tuned = D.Estimator(gdev, eps, 0.05, 0.02, B.MLMC_KGRID_GAMMA, 303, tuner=tuner, ctx=ctx)
+        tuned.add_samples(levels[0], 12)
+        tuned.close()
+        ctx.configure(chase_workgroups=64, update_tile_rows=64)  # choices a plain estimator must not inherit
+        shared = D.Estimator(gdev, eps, 0.05, 0.02, B.MLMC_KGRID_GAMMA, 303, chunk_samples=8, ctx=ctx)
+        shared.add_samples(levels[1], 12)
+        shared.close()
+        assert ctx.handle is not None  # still open after both estimators closed
+        say("[shared ctx] estimator with a context of its own")
+        own = D.Estimator(gdev, eps, 0.05, 0.02, B.MLMC_KGRID_GAMMA, 303, chunk_samples=8)
+        own.add_samples(levels[2], 12)
+        own.close()
+    assert np.array_equal(levels[1].stats, levels[2].stats)
+    assert np.allclose(levels[0].stats, levels[2].stats, rtol=1e-12, atol=1e-14)
