@@ -5,7 +5,9 @@
   (fine K = 1, quarters on the K = 2 grid) against the oracle's level sums.
 * Graphene N = 32 (n ~ 2007), the finest level of the graphene hierarchy,
   coupled (fine K = 1, quarters N = 16 on K = 2), FP64 and mixed against the
-  oracle's level sums.
+  oracle's level sums.  Both coupled levels also run on a pipeline context
+  (reductions on the caller's stream, chases on the chase stream, bisections
+  on the back stream), equal to the single-stream call bit for bit.
 * MoS2-shaped N = 32 (ld 11264, 2 GB per complex128 matrix, the largest
   matrix of the served stream): the pristine supercell's spectrum is the
   union of the primitive 11 x 11 spectra at the N^2 folded wave vectors, an
@@ -132,6 +134,12 @@ def test_level_mos2_n16_coupled(B, mdev, mos2_n16_level, prec):
     got = B.mlmc_level_estimate(mdev, 16, True, 0.02, 1, 2, 1, 404, 3, 1, torch.as_tensor(eps, device=DEV), 0.1,
                                 prec=prec).cpu().numpy()
     compare_stats(got, want, 1, 1e-10 if prec == 0 else 1e-5)
+    # on a pipeline context: reductions on the caller's stream, chases on the
+    # chase stream, bisections and sums on the back stream
+    with B.Context() as ctx:
+        piped = B.mlmc_level_estimate(mdev, 16, True, 0.02, 1, 2, 1, 404, 3, 1, torch.as_tensor(eps, device=DEV), 0.1,
+                                      prec=prec, ctx=ctx).cpu().numpy()
+    assert np.array_equal(piped, got)
 
 
 @pytest.fixture(scope="module")
@@ -153,6 +161,18 @@ def test_level_graphene_n32_coupled(B, gdev, graphene_n32_level, prec):
     got = B.mlmc_level_estimate(gdev, 32, True, 0.02, 1, 2, 1, 303, 11, 2, torch.as_tensor(eps, device=DEV), 0.05,
                                 prec=prec).cpu().numpy()
     compare_stats(got, want, 2, 1e-10 if prec == 0 else 1e-5)
+    # One sample per chunk on a pipeline context (the first chunk chased on
+    # the chase stream's share of the CUs beside the second chunk's reduction,
+    # the last chunk on the whole device) against the same chunks on one
+    # stream, bit for bit.
+    d_eps = torch.as_tensor(eps, device=DEV)
+    one = B.mlmc_level_estimate(gdev, 32, True, 0.02, 1, 2, 1, 303, 11, 2, d_eps, 0.05, prec=prec,
+                                chunk_samples=1).cpu().numpy()
+    with B.Context() as ctx:
+        piped = B.mlmc_level_estimate(gdev, 32, True, 0.02, 1, 2, 1, 303, 11, 2, d_eps, 0.05, prec=prec,
+                                      chunk_samples=1, ctx=ctx).cpu().numpy()
+    assert np.array_equal(piped, one)
+    compare_stats(piped, want, 2, 1e-10 if prec == 0 else 1e-5)
 
 
 def folded_primitive_bands(lat, N, kappa):
