@@ -360,7 +360,10 @@ def measure(B, wl, lat, eps, prec, args, dev, ctx):
     if args.tune:
         from paper_1611_09784_amd.autotune import Tuner
         t0 = time.perf_counter()
-        tuner = Tuner(min_seconds=1.0, chunks=(16, 32, 64), budget_bytes=64 << 30,
+        # Trials of about 3 s (five or more calls of the benchmark's size): with
+        # two calls the pipeline's fill and drain favour small chunks, which
+        # run slower over the consecutive calls of the timed windows.
+        tuner = Tuner(min_seconds=3.0, chunks=(16, 32, 64), budget_bytes=64 << 30,
                       chase_fractions=(0.625, 0.75, 0.875, 1.0), max_trial_seconds=30.0, verbose=True)
         t = tuner.tune_level(dlat, N, False, K, K, wl.kgrid, prec, d_eps, wl.delta, wl.p, samples_per_call=args.batch,
                              ctx=ctx)
