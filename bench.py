@@ -249,8 +249,13 @@ def time_to_tol(B, dev, wl_name="graphene_mlmc", variants=None, oracle_samples=N
     for name, prec, dedup, tuned in variants:
         est = D.Estimator(dlat, eps, wl.delta, wl.p, wl.kgrid, wl.seed, wl.smoother, prec, chunk_samples=32,
                           dedup_max_orbitals=dedup, tuner=tuner if tuned else None, graphs=tuned, ctx=ctx)
-        for st in D.make_levels(wl.levels, Ks):  # warm-up: workspaces and first launches
-            est.add_samples(st, 2)
+        # Warm-up: workspaces, first launches and buffers of the pilot rounds'
+        # size, on samples far from those of the run; outcomes it solved are
+        # then forgotten, so that the run's first round pays for its own.
+        for st in D.make_levels(wl.levels, Ks):
+            st.M = 1 << 40
+            est.add_samples(st, 16)
+        est.forget_outcomes()
         torch.cuda.synchronize(dev)
         r = D.run_mlmc(est, wl.levels, Ks, wl.tol)
         est.close()

@@ -160,6 +160,12 @@ class Estimator:
                                           self.seed, 4 * c, self.eps, self.delta, self.smoother, self.prec, c)
         return self._graph[key]
 
+    def forget_outcomes(self):
+        """Drop the per-outcome results kept for duplicate reuse (after a
+        warm-up, so that a run starts with none solved)."""
+        self._outcomes.clear()
+        self.unique_solved = 0
+
     def close(self):
         if self.ctx is not None and self._own_ctx:
             self.ctx.close()
